@@ -1,0 +1,206 @@
+// C-ABI layer of libqsvm.so: argument validation, defaults and dispatch to the
+// HIP kernels.  Every check runs on the host before any HIP call, so a
+// rejected call enqueues nothing and touches no device state.
+
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <string>
+
+#include "../../include/qsvm.h"
+#include "qsvm_internal.h"
+#include "sweep_common.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+constexpr int64_t kMaxN = (int64_t(1) << 31) - 1;
+constexpr int32_t kMaxQubits = 65535;
+constexpr int32_t kDefaultRenorm = 4;
+constexpr int32_t kMaxRenorm = 16;
+
+qsvm_status fail(qsvm_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+
+qsvm_status fail(qsvm_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+qsvm_status ok() {
+  g_last_error.clear();
+  return QSVM_OK;
+}
+
+qsvm_status check_shape(int64_t N, int32_t n, int32_t reps, const char* what) {
+  if (N < 1 || N > kMaxN) return fail(QSVM_ERR_INVALID_ARG, "%s: N = %lld outside [1, 2^31-1]", what, (long long)N);
+  if (n < 1 || n > kMaxQubits) return fail(QSVM_ERR_INVALID_ARG, "%s: n_qubits = %d outside [1, 65535]", what, n);
+  if (reps < 1) return fail(QSVM_ERR_INVALID_ARG, "%s: reps = %d must be >= 1", what, reps);
+  if (reps > 3) return fail(QSVM_ERR_UNSUPPORTED, "%s: reps = %d > 3 (bond dimension above 8) is not supported", what, reps);
+  return QSVM_OK;
+}
+
+// Host-forced failure for tests of the error path: QSVM_FAULT_INJECT=launch
+// makes every call that passed validation return QSVM_ERR_HIP instead of
+// launching.
+bool injected_launch_failure() {
+  const char* v = getenv("QSVM_FAULT_INJECT");
+  return v && strcmp(v, "launch") == 0;
+}
+
+qsvm_status hip_status(hipError_t e, const char* what) {
+  if (e == hipSuccess) return ok();
+  return fail(QSVM_ERR_HIP, "%s: HIP error %d (%s)", what, int(e), hipGetErrorString(e));
+}
+
+struct Opts {
+  int32_t renorm_every = kDefaultRenorm;
+  int32_t sweep = QSVM_SWEEP_BUTTERFLY;
+  int32_t diag_mode = 0;
+  int64_t row_begin = 0, row_end = 0;
+  double* log_k = nullptr;
+};
+
+qsvm_status read_opts(const qsvm_gram_opts* o, int64_t rows, Opts& out, const char* what) {
+  out = Opts{};
+  out.row_end = rows;
+  if (!o) return QSVM_OK;
+  if (o->renorm_every < 0 || o->renorm_every > kMaxRenorm)
+    return fail(QSVM_ERR_INVALID_ARG, "%s: renorm_every = %d outside [0, %d]", what, o->renorm_every, kMaxRenorm);
+  if (o->renorm_every) out.renorm_every = o->renorm_every;
+  if (o->sweep < QSVM_SWEEP_AUTO || o->sweep > QSVM_SWEEP_DENSE)
+    return fail(QSVM_ERR_INVALID_ARG, "%s: unknown sweep kind %d", what, o->sweep);
+  out.sweep = (o->sweep == QSVM_SWEEP_DENSE) ? QSVM_SWEEP_DENSE : QSVM_SWEEP_BUTTERFLY;
+  if (o->diag_mode != 0 && o->diag_mode != 1)
+    return fail(QSVM_ERR_INVALID_ARG, "%s: diag_mode = %d must be 0 or 1", what, o->diag_mode);
+  out.diag_mode = o->diag_mode;
+  if (o->reserved0 != 0) return fail(QSVM_ERR_INVALID_ARG, "%s: reserved0 must be 0", what);
+  if (o->row_begin != 0 || o->row_end != 0) {
+    if (o->row_begin < 0 || o->row_end < o->row_begin || o->row_end > rows)
+      return fail(QSVM_ERR_INVALID_ARG, "%s: row range [%lld, %lld) outside [0, %lld]", what,
+                  (long long)o->row_begin, (long long)o->row_end, (long long)rows);
+    out.row_begin = o->row_begin;
+    out.row_end = o->row_end;
+  }
+  out.log_k = o->log_k;
+  return QSVM_OK;
+}
+
+qsvm_status run_gram(const void* mps_a, int64_t Na, const void* mps_b, int64_t Nb, int32_t n,
+                     int32_t reps, double* K, int64_t ldk, const Opts& o, bool sym, void* stream,
+                     const char* what) {
+  using qsvm::kTile;
+  if (o.row_end <= o.row_begin) return ok();  // empty row range: nothing to do
+  qsvm::SweepArgs a{};
+  a.gen_a = reinterpret_cast<const float4*>(static_cast<const char*>(mps_a) + qsvm::dense_bytes(Na, n, reps));
+  a.gen_b = reinterpret_cast<const float4*>(static_cast<const char*>(mps_b) + qsvm::dense_bytes(Nb, n, reps));
+  a.dense_a = static_cast<const float2*>(mps_a);
+  a.dense_b = static_cast<const float2*>(mps_b);
+  a.K = K;
+  a.log_k = o.log_k;
+  a.Na = Na;
+  a.Nb = Nb;
+  a.ldk = ldk;
+  a.row_begin = o.row_begin;
+  a.row_end = o.row_end;
+  a.n = n;
+  a.renorm_every = o.renorm_every;
+  a.sym = sym ? 1 : 0;
+  a.diag_mode = o.diag_mode;
+  a.tile_row0 = int32_t(o.row_begin / kTile);
+  a.tile_rows = int32_t((o.row_end - 1) / kTile) - a.tile_row0 + 1;
+  a.tiles_b = int32_t((Nb + kTile - 1) / kTile);
+  // launch-size limit: at most 16 blocks per tile, < 2^31 blocks
+  const int64_t tiles = int64_t(a.tile_rows) * a.tiles_b;
+  if (tiles * 16 > (int64_t(1) << 31) - 8)
+    return fail(QSVM_ERR_UNSUPPORTED, "%s: %lld tiles exceed one launch", what, (long long)tiles);
+  if (injected_launch_failure()) return fail(QSVM_ERR_HIP, "%s: injected launch failure (QSVM_FAULT_INJECT=launch)", what);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = (o.sweep == QSVM_SWEEP_DENSE) ? qsvm::launch_sweep_dense_args(a, reps, s)
+                                                : qsvm::launch_sweep_butterfly_args(a, reps, s);
+  return hip_status(e, what);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t qsvm_mps_bytes(int64_t N, int32_t n_qubits, int32_t reps) {
+  if (N < 1 || N > kMaxN || n_qubits < 1 || n_qubits > kMaxQubits || reps < 1 || reps > 3) return 0;
+  const int64_t chi = int64_t(1) << reps;
+  return size_t(int64_t(n_qubits) * N * (chi * chi * 8 + 16));
+}
+
+qsvm_status qsvm_encode_mps(const double* X, int64_t N, int32_t n_qubits, int32_t reps, void* mps,
+                            size_t mps_bytes, void* stream) {
+  const char* what = "qsvm_encode_mps";
+  qsvm_status s = check_shape(N, n_qubits, reps, what);
+  if (s != QSVM_OK) return s;
+  if (!X) return fail(QSVM_ERR_INVALID_ARG, "%s: X is NULL", what);
+  if (!mps) return fail(QSVM_ERR_INVALID_ARG, "%s: mps is NULL", what);
+  if (reinterpret_cast<uintptr_t>(mps) % 16 != 0) return fail(QSVM_ERR_INVALID_ARG, "%s: mps is not 16-byte aligned", what);
+  if (reinterpret_cast<uintptr_t>(X) % 8 != 0) return fail(QSVM_ERR_INVALID_ARG, "%s: X is not 8-byte aligned", what);
+  const size_t need = qsvm_mps_bytes(N, n_qubits, reps);
+  if (mps_bytes < need)
+    return fail(QSVM_ERR_SIZE, "%s: mps_bytes = %zu < %zu needed", what, mps_bytes, need);
+  if (injected_launch_failure()) return fail(QSVM_ERR_HIP, "%s: injected launch failure (QSVM_FAULT_INJECT=launch)", what);
+  return hip_status(qsvm::launch_encode(X, N, n_qubits, reps, mps, static_cast<hipStream_t>(stream)), what);
+}
+
+qsvm_status qsvm_gram(const void* mps_a, int64_t Na, const void* mps_b, int64_t Nb, int32_t n_qubits,
+                      int32_t reps, double* K, int64_t ldk, const qsvm_gram_opts* opts, void* stream) {
+  const char* what = "qsvm_gram";
+  if (!mps_a || !mps_b) return fail(QSVM_ERR_INVALID_ARG, "%s: MPS buffer is NULL", what);
+  if (!K) return fail(QSVM_ERR_INVALID_ARG, "%s: K is NULL", what);
+  qsvm_status s = check_shape(Na, n_qubits, reps, what);
+  if (s != QSVM_OK) return s;
+  s = check_shape(Nb, n_qubits, reps, what);
+  if (s != QSVM_OK) return s;
+  if (ldk < Nb) return fail(QSVM_ERR_INVALID_ARG, "%s: ldk = %lld < Nb = %lld", what, (long long)ldk, (long long)Nb);
+  if ((reinterpret_cast<uintptr_t>(mps_a) | reinterpret_cast<uintptr_t>(mps_b)) % 16 != 0)
+    return fail(QSVM_ERR_INVALID_ARG, "%s: MPS buffer is not 16-byte aligned", what);
+  Opts o;
+  s = read_opts(opts, Na, o, what);
+  if (s != QSVM_OK) return s;
+  o.diag_mode = 0;
+  return run_gram(mps_a, Na, mps_b, Nb, n_qubits, reps, K, ldk, o, false, stream, what);
+}
+
+qsvm_status qsvm_gram_sym(const void* mps, int64_t N, int32_t n_qubits, int32_t reps, double* K,
+                          int64_t ldk, const qsvm_gram_opts* opts, void* stream) {
+  const char* what = "qsvm_gram_sym";
+  if (!mps) return fail(QSVM_ERR_INVALID_ARG, "%s: mps is NULL", what);
+  if (!K) return fail(QSVM_ERR_INVALID_ARG, "%s: K is NULL", what);
+  qsvm_status s = check_shape(N, n_qubits, reps, what);
+  if (s != QSVM_OK) return s;
+  if (ldk < N) return fail(QSVM_ERR_INVALID_ARG, "%s: ldk = %lld < N = %lld", what, (long long)ldk, (long long)N);
+  if (reinterpret_cast<uintptr_t>(mps) % 16 != 0) return fail(QSVM_ERR_INVALID_ARG, "%s: mps is not 16-byte aligned", what);
+  Opts o;
+  s = read_opts(opts, N, o, what);
+  if (s != QSVM_OK) return s;
+  return run_gram(mps, N, mps, N, n_qubits, reps, K, ldk, o, true, stream, what);
+}
+
+const char* qsvm_status_string(qsvm_status s) {
+  switch (s) {
+    case QSVM_OK: return "QSVM_OK";
+    case QSVM_ERR_INVALID_ARG: return "QSVM_ERR_INVALID_ARG: invalid argument";
+    case QSVM_ERR_UNSUPPORTED: return "QSVM_ERR_UNSUPPORTED: request outside the supported range";
+    case QSVM_ERR_HIP: return "QSVM_ERR_HIP: HIP runtime or launch failure";
+    case QSVM_ERR_SIZE: return "QSVM_ERR_SIZE: caller buffer too small";
+  }
+  return "unknown qsvm_status";
+}
+
+const char* qsvm_last_error(void) { return g_last_error.c_str(); }
+
+int32_t qsvm_abi_version(void) { return 1; }
+
+}  // extern "C"

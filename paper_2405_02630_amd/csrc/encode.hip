@@ -1,0 +1,119 @@
+// MPS encode kernel: writes the exact closed-form MPS of every data point.
+//
+// The paper converts each pair's circuit into an einsum expression plus
+// operands and updates the operands in place for the next pair (§3.4.2,
+// §4.1).  Here the operands are built once per point.  For the ZZ feature
+// map every repetition is H^n followed by a diagonal phase
+// exp(i[sum_k 2 x_k b_k + sum_k theta_k (b_k XOR b_{k+1})]); inserting the
+// computational basis between repetitions gives each qubit an r-bit "column"
+// c = (value after rep 1, ..., value after rep r) and
+//     psi(s) = sum_{c : c_{k,r} = s_k} prod_k w_k(c_k) prod_k J_k(c_k, c_{k+1}),
+//     w_k(c) = 2^{-r/2} (-1)^{sum_l c_l c_{l-1}} exp(2 i x_k |c|),
+//     J_k(c, c') = exp(i theta_k |c XOR c'|),
+// i.e. an MPS with bond dimension exactly 2^r and site tensor
+// A_k[alpha][beta] = J_{k-1}(alpha, beta) w_k(beta).  Section D stores these
+// tensors; Section G stores the generators (a_k, b_k, g_{n-1}) of the same
+// MPS in the diagonal gauge D_k = diag(1, g_k) per bond bit, where
+// J_{k-1} w_k factorises into 2x2 blocks [[1, a_k], [1, b_k]] (layout and
+// formulas in include/qsvm.h).
+//
+// One thread per (site k, point i).  All phases are formed in FP64 (the
+// largest angle is below 3 * (2 pi + 2 pi^2) ~ 78 rad) and each tensor entry
+// is rounded to FP32 once.
+
+#include "qsvm_internal.h"
+
+namespace qsvm {
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+__device__ __forceinline__ double zz_theta(double a, double b) {
+  return 2.0 * (kPi - a) * (kPi - b);
+}
+
+template <int R>
+__global__ void __launch_bounds__(256)
+encode_kernel(const double* __restrict__ X, int64_t N, int32_t n,
+              float2* __restrict__ dense, float4* __restrict__ gen) {
+  constexpr int CHI = 1 << R;
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int32_t k = blockIdx.y;
+  if (i >= N) return;
+  const double* x = X + i * n;
+
+  const double xk = x[k];
+  const double th_prev = (k >= 1) ? zz_theta(x[k - 1], xk) : 0.0;  // theta_{k-1}
+
+  // ---- Section D: dense tensor A_k[alpha][beta] ----
+  // powers p^m = exp(2 i x_k m) and t^m = exp(i theta_{k-1} m), m = 0..R, in FP64
+  double pr[R + 1], pi_[R + 1], tr[R + 1], ti[R + 1];
+  double sp, cp, st, ct;
+  sincos(2.0 * xk, &sp, &cp);
+  sincos(th_prev, &st, &ct);
+  pr[0] = 1.0; pi_[0] = 0.0; tr[0] = 1.0; ti[0] = 0.0;
+#pragma unroll
+  for (int m = 1; m <= R; ++m) {
+    pr[m] = pr[m - 1] * cp - pi_[m - 1] * sp;
+    pi_[m] = pr[m - 1] * sp + pi_[m - 1] * cp;
+    tr[m] = tr[m - 1] * ct - ti[m - 1] * st;
+    ti[m] = tr[m - 1] * st + ti[m - 1] * ct;
+  }
+  // 2^{-R/2}
+  const double scale = (R == 1) ? 0.70710678118654752440 : (R == 2) ? 0.5 : 0.35355339059327376220;
+  float2* out = dense + (int64_t(k) * N + i) * (CHI * CHI);
+#pragma unroll
+  for (int a = 0; a < CHI; ++a) {
+#pragma unroll
+    for (int b = 0; b < CHI; ++b) {
+      const int pb = __builtin_popcount(b);
+      const int pab = __builtin_popcount(a ^ b);
+      const int sgn_bits = __builtin_popcount(b & (b >> 1)) & 1;  // sum_l b_l b_{l-1} mod 2
+      double re = pr[pb] * tr[pab] - pi_[pb] * ti[pab];
+      double im = pr[pb] * ti[pab] + pi_[pb] * tr[pab];
+      const double s = sgn_bits ? -scale : scale;
+      out[a * CHI + b] = make_float2(float(re * s), float(im * s));
+    }
+  }
+
+  // ---- Section G: gauge generators ----
+  float4 rec;
+  if (k >= 1) {
+    // G_{k-1} = 2 x_{k-1} + theta_{k-2};  a_k = e^{i(theta_{k-1} + G_{k-1})},
+    // b_k = e^{i(G_{k-1} - theta_{k-1})}
+    const double xm = x[k - 1];
+    const double th_pp = (k >= 2) ? zz_theta(x[k - 2], xm) : 0.0;
+    const double G = 2.0 * xm + th_pp;
+    double sa, ca, sb, cb;
+    sincos(G + th_prev, &sa, &ca);
+    sincos(G - th_prev, &sb, &cb);
+    rec = make_float4(float(ca), float(sa), float(cb), float(sb));
+  } else {
+    // closure phase g_{n-1} = e^{i(2 x_{n-1} + theta_{n-2})}
+    const double xl = x[n - 1];
+    const double th_l = (n >= 2) ? zz_theta(x[n - 2], xl) : 0.0;
+    double sg, cg;
+    sincos(2.0 * xl + th_l, &sg, &cg);
+    rec = make_float4(float(cg), float(sg), 0.0f, 0.0f);
+  }
+  gen[int64_t(k) * N + i] = rec;
+}
+
+}  // namespace
+
+hipError_t launch_encode(const double* X, int64_t N, int32_t n, int32_t reps, void* mps,
+                         hipStream_t stream) {
+  const dim3 block(256);
+  const dim3 grid(unsigned((N + 255) / 256), unsigned(n));
+  float2* dense = static_cast<float2*>(mps);
+  float4* gen = reinterpret_cast<float4*>(static_cast<char*>(mps) + dense_bytes(N, n, reps));
+  switch (reps) {
+    case 1: hipLaunchKernelGGL(encode_kernel<1>, grid, block, 0, stream, X, N, n, dense, gen); break;
+    case 2: hipLaunchKernelGGL(encode_kernel<2>, grid, block, 0, stream, X, N, n, dense, gen); break;
+    case 3: hipLaunchKernelGGL(encode_kernel<3>, grid, block, 0, stream, X, N, n, dense, gen); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace qsvm

@@ -1,0 +1,196 @@
+"""Python binding of libqsvm.so (argument marshalling only).
+
+The functions ``qsvm_mps_bytes``, ``qsvm_encode_mps``, ``qsvm_gram`` and
+``qsvm_gram_sym`` have the names and meaning of the C entry points declared
+in include/qsvm.h; they take PyTorch CUDA tensors for device memory and launch
+on the current PyTorch stream.  Every step of the computation runs in the HIP
+kernels of the library: if the library cannot be loaded these functions raise
+and there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqsvm.so")
+
+QSVM_OK = 0
+QSVM_ERR_INVALID_ARG = -1
+QSVM_ERR_UNSUPPORTED = -2
+QSVM_ERR_HIP = -3
+QSVM_ERR_SIZE = -4
+
+SWEEP_AUTO = 0
+SWEEP_BUTTERFLY = 1
+SWEEP_DENSE = 2
+
+
+class GramOpts(ctypes.Structure):
+    """Mirror of qsvm_gram_opts."""
+
+    _fields_ = [
+        ("renorm_every", ctypes.c_int32),
+        ("sweep", ctypes.c_int32),
+        ("diag_mode", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32),
+        ("row_begin", ctypes.c_int64),
+        ("row_end", ctypes.c_int64),
+        ("log_k", ctypes.c_void_p),
+    ]
+
+
+class QsvmError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{message} (status {status})")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libqsvm.so once; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"{path} not found: build it with `python -m paper_2405_02630_amd.build` "
+            "(there is no fallback implementation)"
+        )
+    lib = ctypes.CDLL(path)
+    i32, i64, vp, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t
+    lib.qsvm_mps_bytes.argtypes = [i64, i32, i32]
+    lib.qsvm_mps_bytes.restype = sz
+    lib.qsvm_encode_mps.argtypes = [vp, i64, i32, i32, vp, sz, vp]
+    lib.qsvm_encode_mps.restype = i32
+    lib.qsvm_gram.argtypes = [vp, i64, vp, i64, i32, i32, vp, i64, ctypes.POINTER(GramOpts), vp]
+    lib.qsvm_gram.restype = i32
+    lib.qsvm_gram_sym.argtypes = [vp, i64, i32, i32, vp, i64, ctypes.POINTER(GramOpts), vp]
+    lib.qsvm_gram_sym.restype = i32
+    lib.qsvm_status_string.argtypes = [i32]
+    lib.qsvm_status_string.restype = ctypes.c_char_p
+    lib.qsvm_last_error.argtypes = []
+    lib.qsvm_last_error.restype = ctypes.c_char_p
+    lib.qsvm_abi_version.argtypes = []
+    lib.qsvm_abi_version.restype = i32
+    _lib = lib
+    return lib
+
+
+def _check(status: int) -> None:
+    if status != QSVM_OK:
+        lib = load_library()
+        msg = lib.qsvm_last_error().decode() or lib.qsvm_status_string(status).decode()
+        raise QsvmError(status, msg)
+
+
+def _stream_ptr(stream):
+    import torch
+
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _device_ptr(t, name, dtype=None):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+@dataclass
+class MPS:
+    """Device MPS buffer written by qsvm_encode_mps (layout in include/qsvm.h)."""
+
+    buf: "object"  # torch.uint8 CUDA tensor
+    N: int
+    n: int
+    reps: int
+
+
+def qsvm_mps_bytes(N: int, n_qubits: int, reps: int) -> int:
+    return int(load_library().qsvm_mps_bytes(N, n_qubits, reps))
+
+
+def qsvm_encode_mps(X, reps: int, out=None, stream=None) -> MPS:
+    """Encode the rows of X (CUDA float64, N x n) as exact MPS."""
+    import torch
+
+    lib = load_library()
+    if X.dim() != 2:
+        raise ValueError("X must be 2-D (N x n_qubits)")
+    N, n = int(X.shape[0]), int(X.shape[1])
+    need = lib.qsvm_mps_bytes(N, n, reps)
+    if out is None:
+        if need == 0:
+            # let the library produce the precise error
+            _check(lib.qsvm_encode_mps(_device_ptr(X, "X", torch.float64), N, n, reps, None, 0, _stream_ptr(stream)))
+        out = torch.empty(need, dtype=torch.uint8, device=X.device)
+    st = lib.qsvm_encode_mps(
+        _device_ptr(X, "X", torch.float64), N, n, reps, _device_ptr(out, "out"), out.numel(), _stream_ptr(stream)
+    )
+    _check(st)
+    return MPS(out, N, n, reps)
+
+
+def _opts(renorm_every, sweep, diag_mode, rows, log_k):
+    o = GramOpts()
+    o.renorm_every = renorm_every
+    o.sweep = sweep
+    o.diag_mode = diag_mode
+    if rows is not None:
+        o.row_begin, o.row_end = int(rows[0]), int(rows[1])
+    o.log_k = None if log_k is None else log_k.data_ptr()
+    return o
+
+
+def qsvm_gram(mps_a: MPS, mps_b: MPS, K=None, *, log_k=None, renorm_every: int = 0,
+              sweep: int = SWEEP_AUTO, rows=None, stream=None):
+    """K[i, j] = |<psi(b_j)|psi(a_i)>|^2 (CUDA float64, Na x Nb).  Returns K."""
+    import torch
+
+    lib = load_library()
+    if mps_a.n != mps_b.n or mps_a.reps != mps_b.reps:
+        raise ValueError("both MPS sets need the same n_qubits and reps")
+    if K is None:
+        K = torch.empty((mps_a.N, mps_b.N), dtype=torch.float64, device=mps_a.buf.device)
+    if K.dim() != 2 or K.shape[0] < mps_a.N or K.stride(1) != 1:
+        raise ValueError("K must be 2-D with unit column stride and at least Na rows")
+    if log_k is not None and (log_k.shape != K.shape or log_k.stride() != K.stride() or log_k.dtype != torch.float64):
+        raise ValueError("log_k must match K's shape, strides and dtype")
+    o = _opts(renorm_every, sweep, 0, rows, log_k)
+    st = lib.qsvm_gram(
+        _device_ptr(mps_a.buf, "mps_a"), mps_a.N, _device_ptr(mps_b.buf, "mps_b"), mps_b.N, mps_a.n, mps_a.reps,
+        ctypes.c_void_p(K.data_ptr()), K.stride(0), ctypes.byref(o), _stream_ptr(stream),
+    )
+    _check(st)
+    return K
+
+
+def qsvm_gram_sym(mps: MPS, K=None, *, log_k=None, renorm_every: int = 0, sweep: int = SWEEP_AUTO,
+                  diag_mode: int = 0, rows=None, stream=None):
+    """Symmetric Gram of one set: pairs i < j contracted, mirrored, K[i, i] = 1
+    (diag_mode 0) or computed (diag_mode 1).  Returns K."""
+    import torch
+
+    lib = load_library()
+    if K is None:
+        K = torch.empty((mps.N, mps.N), dtype=torch.float64, device=mps.buf.device)
+    if K.dim() != 2 or K.shape[0] < mps.N or K.stride(1) != 1:
+        raise ValueError("K must be 2-D with unit column stride and at least N rows")
+    if log_k is not None and (log_k.shape != K.shape or log_k.stride() != K.stride() or log_k.dtype != torch.float64):
+        raise ValueError("log_k must match K's shape, strides and dtype")
+    o = _opts(renorm_every, sweep, diag_mode, rows, log_k)
+    st = lib.qsvm_gram_sym(
+        _device_ptr(mps.buf, "mps"), mps.N, mps.n, mps.reps, ctypes.c_void_p(K.data_ptr()), K.stride(0),
+        ctypes.byref(o), _stream_ptr(stream),
+    )
+    _check(st)
+    return K

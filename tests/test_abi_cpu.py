@@ -1,0 +1,178 @@
+"""The C-ABI library on a machine without a GPU: it loads, exports every
+symbol include/qsvm.h declares, and rejects bad arguments on the host before
+any HIP call (so every branch here runs with fake, never-dereferenced
+pointers).  The injected launch failure shows the error path that a real
+launch failure takes."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2405_02630_amd import qsvm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qsvm.h")
+
+FAKE = ctypes.c_void_p(0x100000)  # 16-byte aligned, never dereferenced on these paths
+FAKE2 = ctypes.c_void_p(0x200000)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return qsvm.load_library()
+
+
+@pytest.fixture
+def no_inject(monkeypatch):
+    monkeypatch.delenv("QSVM_FAULT_INJECT", raising=False)
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qsvm_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_three_paper_calls():
+    names = declared_functions()
+    for f in ("qsvm_encode_mps", "qsvm_gram", "qsvm_gram_sym", "qsvm_mps_bytes"):
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_abi_version(lib):
+    assert lib.qsvm_abi_version() == 1
+
+
+def test_opts_struct_layout():
+    # int32 x4, int64 x2, pointer: 40 bytes, log_k at offset 32
+    assert ctypes.sizeof(qsvm.GramOpts) == 40
+    assert qsvm.GramOpts.log_k.offset == 32
+
+
+@pytest.mark.parametrize("N,n,reps", [(1, 1, 1), (32, 8, 2), (4096, 784, 2), (1024, 784, 3), (7, 3, 1)])
+def test_mps_bytes_formula(N, n, reps):
+    chi = 2**reps
+    assert qsvm.qsvm_mps_bytes(N, n, reps) == n * N * (chi * chi * 8 + 16)
+
+
+@pytest.mark.parametrize("N,n,reps", [(0, 8, 2), (8, 0, 2), (8, 8, 0), (8, 8, 4), (-1, 8, 2), (8, 65536, 2), (2**31, 8, 2)])
+def test_mps_bytes_rejects(N, n, reps):
+    assert qsvm.qsvm_mps_bytes(N, n, reps) == 0
+
+
+def test_status_strings(lib):
+    for s in (0, -1, -2, -3, -4):
+        assert lib.qsvm_status_string(s).startswith(b"QSVM_")
+    assert lib.qsvm_status_string(17) == b"unknown qsvm_status"
+
+
+def _enc(lib, X=FAKE, N=8, n=4, reps=2, mps=FAKE2, nbytes=None):
+    if nbytes is None:
+        nbytes = max(qsvm.qsvm_mps_bytes(N, n, reps), 1)
+    return lib.qsvm_encode_mps(X, N, n, reps, mps, nbytes, None)
+
+
+def test_encode_validation(lib, no_inject):
+    assert _enc(lib, X=None) == qsvm.QSVM_ERR_INVALID_ARG
+    assert _enc(lib, mps=None) == qsvm.QSVM_ERR_INVALID_ARG
+    assert _enc(lib, N=0) == qsvm.QSVM_ERR_INVALID_ARG
+    assert _enc(lib, n=0) == qsvm.QSVM_ERR_INVALID_ARG
+    assert _enc(lib, n=70000) == qsvm.QSVM_ERR_INVALID_ARG
+    assert _enc(lib, reps=0) == qsvm.QSVM_ERR_INVALID_ARG
+    assert _enc(lib, reps=4) == qsvm.QSVM_ERR_UNSUPPORTED
+    assert b"reps = 4" in lib.qsvm_last_error()
+    assert _enc(lib, mps=ctypes.c_void_p(0x100008)) == qsvm.QSVM_ERR_INVALID_ARG  # misaligned
+    assert _enc(lib, X=ctypes.c_void_p(0x100004)) == qsvm.QSVM_ERR_INVALID_ARG
+    need = qsvm.qsvm_mps_bytes(8, 4, 2)
+    assert _enc(lib, nbytes=need - 1) == qsvm.QSVM_ERR_SIZE
+
+
+def _sym(lib, mps=FAKE, N=100, n=8, reps=2, K=FAKE2, ldk=None, opts=None):
+    ldk = N if ldk is None else ldk
+    return lib.qsvm_gram_sym(mps, N, n, reps, K, ldk, ctypes.byref(opts) if opts is not None else None, None)
+
+
+def _rect(lib, a=FAKE, Na=50, b=FAKE2, Nb=70, n=8, reps=2, K=FAKE2, ldk=None, opts=None):
+    ldk = Nb if ldk is None else ldk
+    return lib.qsvm_gram(a, Na, b, Nb, n, reps, K, ldk, ctypes.byref(opts) if opts is not None else None, None)
+
+
+def test_gram_sym_validation(lib, no_inject):
+    assert _sym(lib, mps=None) == qsvm.QSVM_ERR_INVALID_ARG
+    assert _sym(lib, K=None) == qsvm.QSVM_ERR_INVALID_ARG
+    assert _sym(lib, N=0) == qsvm.QSVM_ERR_INVALID_ARG
+    assert _sym(lib, n=0) == qsvm.QSVM_ERR_INVALID_ARG
+    assert _sym(lib, reps=5) == qsvm.QSVM_ERR_UNSUPPORTED
+    assert _sym(lib, ldk=99) == qsvm.QSVM_ERR_INVALID_ARG
+    assert _sym(lib, mps=ctypes.c_void_p(0x100004)) == qsvm.QSVM_ERR_INVALID_ARG
+
+
+def test_gram_rect_validation(lib, no_inject):
+    assert _rect(lib, a=None) == qsvm.QSVM_ERR_INVALID_ARG
+    assert _rect(lib, b=None) == qsvm.QSVM_ERR_INVALID_ARG
+    assert _rect(lib, K=None) == qsvm.QSVM_ERR_INVALID_ARG
+    assert _rect(lib, Na=0) == qsvm.QSVM_ERR_INVALID_ARG
+    assert _rect(lib, Nb=-3) == qsvm.QSVM_ERR_INVALID_ARG
+    assert _rect(lib, ldk=69) == qsvm.QSVM_ERR_INVALID_ARG
+    assert _rect(lib, reps=4) == qsvm.QSVM_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize(
+    "field,value",
+    [("renorm_every", -1), ("renorm_every", 17), ("sweep", 3), ("sweep", -1), ("diag_mode", 2), ("reserved0", 1)],
+)
+def test_gram_opts_validation(lib, no_inject, field, value):
+    o = qsvm.GramOpts()
+    setattr(o, field, value)
+    assert _sym(lib, opts=o) == qsvm.QSVM_ERR_INVALID_ARG
+    assert _rect(lib, opts=o) == qsvm.QSVM_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("rb,re_", [(-1, 5), (5, 4), (0, 101), (10, 200)])
+def test_gram_row_range_validation(lib, no_inject, rb, re_):
+    o = qsvm.GramOpts()
+    o.row_begin, o.row_end = rb, re_
+    assert _sym(lib, N=100, opts=o) == qsvm.QSVM_ERR_INVALID_ARG
+
+
+def test_empty_row_range_is_a_no_op(lib, no_inject):
+    # an empty range returns OK without launching (pointers are fake)
+    o = qsvm.GramOpts()
+    o.row_begin, o.row_end = 7, 7
+    assert _sym(lib, N=100, opts=o) == qsvm.QSVM_OK
+    assert _rect(lib, Na=50, opts=o) == qsvm.QSVM_OK
+
+
+def test_injected_launch_failure(lib, monkeypatch):
+    monkeypatch.setenv("QSVM_FAULT_INJECT", "launch")
+    assert _enc(lib) == qsvm.QSVM_ERR_HIP
+    assert b"injected" in lib.qsvm_last_error()
+    assert _sym(lib) == qsvm.QSVM_ERR_HIP
+    assert _rect(lib) == qsvm.QSVM_ERR_HIP
+    # validation still comes first
+    assert _sym(lib, N=0) == qsvm.QSVM_ERR_INVALID_ARG
+
+
+def test_python_binding_raises_with_the_library_message(monkeypatch):
+    monkeypatch.setenv("QSVM_FAULT_INJECT", "launch")
+    with pytest.raises(qsvm.QsvmError) as ei:
+        qsvm._check(qsvm.load_library().qsvm_gram_sym(FAKE, 8, 8, 2, FAKE2, 8, None, None))
+    assert ei.value.status == qsvm.QSVM_ERR_HIP
+    assert "injected" in str(ei.value)
+
+
+def test_missing_library_raises(tmp_path):
+    saved = qsvm._lib
+    try:
+        qsvm._lib = None
+        with pytest.raises(RuntimeError, match="no fallback"):
+            qsvm.load_library(str(tmp_path / "libqsvm.so"))
+    finally:
+        qsvm._lib = saved

@@ -1,0 +1,309 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU oracle.
+
+Bars (derivation in tests/gpu_helpers.py): |K_gpu - K_oracle| <= 1e-5 on every
+compared entry, and for the log-domain error |ln K_gpu - ln K_oracle| a max of
+LOG_TOL_MAX and a median of LOG_TOL_MEDIAN, since most off-diagonal kernels of
+64 or 784 qubits are 1e-30..1e-500, far below the absolute bar.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import closed_forms, mps, statevector
+from paper_2405_02630_amd import qsvm, synth
+
+from gpu_helpers import (
+    K_ABS_TOL,
+    LOG_TOL_MAX,
+    log_close,
+    contract_dense,
+    encode,
+    gauge_tensors,
+    gram_rect,
+    gram_sym,
+    mps_sections,
+    require_gpu,
+)
+
+pytestmark = pytest.mark.gpu
+
+SWEEPS = [qsvm.SWEEP_BUTTERFLY, qsvm.SWEEP_DENSE]
+SWEEP_IDS = ["butterfly", "dense"]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    return require_gpu()
+
+
+def _log_err(lk_gpu, lk_ref):
+    return oracle.log_k_errors(lk_gpu, lk_ref)
+
+
+def _oracle_pairs_log(Xa, Xb, reps, ia, jb):
+    Sa = mps.mps_states(Xa, reps)
+    Sb = Sa if Xb is Xa else mps.mps_states(Xb, reps)
+    return mps.mps_gram_pairs(Sa, Sb, ia, jb)
+
+
+# --------------------------------------------------------------------------
+# Encode: the MPS the GPU writes is the state (both sections)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [1, 2, 5, 10])
+@pytest.mark.parametrize("reps", [1, 2, 3])
+def test_encode_dense_section_is_the_state(n, reps):
+    X = synth.uniform_features(3, n, seed=10 * n + reps)
+    m = encode(X, reps)
+    dense, _ = mps_sections(m)
+    for i in range(X.shape[0]):
+        psi = contract_dense(dense[:, i], reps)
+        ref = statevector.sv_state(X[i], reps)
+        assert np.max(np.abs(psi - ref)) < 2e-6
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 10])
+@pytest.mark.parametrize("reps", [1, 2, 3])
+def test_encode_gauge_section_is_the_state(n, reps):
+    X = synth.uniform_features(3, n, seed=20 * n + reps)
+    m = encode(X, reps)
+    _, gen = mps_sections(m)
+    for i in range(X.shape[0]):
+        T, right = gauge_tensors(gen[:, i], reps)
+        psi = contract_dense(T, reps, right)
+        ref = statevector.sv_state(X[i], reps)
+        assert np.max(np.abs(psi - ref)) < 2e-6
+
+
+def test_encode_dense_entries_closed_form():
+    # spot-check entries of Section D against the closed form of include/qsvm.h
+    X = synth.uniform_features(5, 7, seed=3)
+    reps = 3
+    m = encode(X, reps)
+    dense, _ = mps_sections(m)
+    for (k, i, a, b) in [(0, 0, 0, 5), (3, 2, 6, 1), (6, 4, 7, 7), (5, 1, 2, 4)]:
+        th = 2 * (math.pi - X[i, k - 1]) * (math.pi - X[i, k]) if k else 0.0
+        sg = -1.0 if bin(b & (b >> 1)).count("1") % 2 else 1.0
+        ref = 2 ** (-1.5) * sg * np.exp(1j * (2 * X[i, k] * bin(b).count("1") + th * bin(a ^ b).count("1")))
+        assert abs(dense[k, i, a, b] - ref) < 1e-6
+
+
+# --------------------------------------------------------------------------
+# Small exact Grams against the state vector (several tiles + ragged tails)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("sweep", SWEEPS, ids=SWEEP_IDS)
+def test_tiny_workload_full_gram(sweep):
+    wl = synth.tiny_uniform(seed=0)
+    ref = statevector.sv_gram(wl.X, wl.reps)
+    K, L = gram_sym(wl.X, wl.reps, sweep=sweep)
+    assert np.max(np.abs(K - ref)) <= K_ABS_TOL
+    assert np.all(np.diag(K) == 1.0)
+    assert np.array_equal(K, K.T)
+    assert oracle.check_gram(K, tol=K_ABS_TOL) == {}
+    off = ~np.eye(K.shape[0], dtype=bool)
+    assert log_close(_log_err(L[off], np.log(ref[off])))
+
+
+@pytest.mark.parametrize("sweep", SWEEPS, ids=SWEEP_IDS)
+@pytest.mark.parametrize("reps", [1, 2, 3])
+@pytest.mark.parametrize("n,N", [(1, 5), (2, 66), (7, 130), (11, 67)])
+def test_sym_gram_vs_state_vector(sweep, reps, n, N):
+    X = synth.uniform_features(N, n, seed=1000 + 10 * n + reps)
+    ref = statevector.sv_gram(X, reps)
+    K, L = gram_sym(X, reps, sweep=sweep, diag_mode=1)
+    assert np.max(np.abs(K - ref)) <= K_ABS_TOL
+    assert np.array_equal(K, K.T)
+    pos = ref > 1e-200
+    assert log_close(_log_err(L[pos], np.log(ref[pos])))
+
+
+@pytest.mark.parametrize("sweep", SWEEPS, ids=SWEEP_IDS)
+@pytest.mark.parametrize("reps", [1, 2, 3])
+def test_rect_gram_vs_state_vector(sweep, reps):
+    Xa = synth.uniform_features(70, 9, seed=5 + reps)
+    Xb = synth.uniform_features(131, 9, seed=6 + reps)
+    ref = statevector.sv_gram_rect(Xa, Xb, reps)
+    K, L = gram_rect(Xa, Xb, reps, sweep=sweep)
+    assert np.max(np.abs(K - ref)) <= K_ABS_TOL
+    assert log_close(_log_err(L, np.log(ref)))
+
+
+def test_single_point_and_single_qubit():
+    X = np.array([[0.3]])
+    K, L = gram_sym(X, 2)
+    assert K.shape == (1, 1) and K[0, 0] == 1.0 and L[0, 0] == 0.0
+    K, _ = gram_sym(X, 2, diag_mode=1)
+    assert abs(K[0, 0] - 1.0) <= K_ABS_TOL
+    Xa, Xb = np.array([[0.25 * math.pi]]), np.array([[0.0], [0.5 * math.pi]])
+    K, _ = gram_rect(Xa, Xb, 1)
+    assert abs(K[0, 0] - 0.5) <= K_ABS_TOL and abs(K[0, 1] - 0.5) <= K_ABS_TOL
+
+
+# --------------------------------------------------------------------------
+# 64 qubits: the 10-class mixture workload, sampled pairs against exact MPS
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("sweep", SWEEPS, ids=SWEEP_IDS)
+def test_mixture64_full_gram_sampled_pairs(sweep):
+    wl = synth.mixture64(seed=0)
+    K, L = gram_sym(wl.X, wl.reps, sweep=sweep)
+    assert np.array_equal(K, K.T) and np.all(np.diag(K) == 1.0)
+    assert K.min() >= 0.0 and K.max() <= 1.0
+    rng = np.random.default_rng(0)
+    pts = np.sort(rng.choice(wl.X.shape[0], 192, replace=False))
+    S = mps.mps_states(wl.X[pts], wl.reps)
+    ia, jb = np.triu_indices(len(pts), 1)
+    lk_ref, k_ref = mps.mps_gram_pairs(S, S, ia, jb)
+    gi, gj = pts[ia], pts[jb]
+    assert np.max(np.abs(K[gi, gj] - k_ref)) <= K_ABS_TOL
+    assert log_close(_log_err(L[gi, gj], lk_ref))
+
+
+# --------------------------------------------------------------------------
+# 784 qubits
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("reps", [2, 3])
+def test_images784_sym_and_rect_vs_mps(reps):
+    wl = synth.images784(seed=4, n_train=130, n_test=70, reps=reps)
+    K, L = gram_sym(wl.X, reps)
+    Kr, Lr = gram_rect(wl.X_test, wl.X, reps)
+    pts = np.array([0, 1, 2, 17, 63, 64, 65, 101, 128, 129])
+    tst = np.array([0, 5, 69])
+    S = mps.mps_states(wl.X[pts], reps)
+    St = mps.mps_states(wl.X_test[tst], reps)
+    ia, jb = np.triu_indices(len(pts), 1)
+    lk_ref, k_ref = mps.mps_gram_pairs(S, S, ia, jb)
+    assert log_close(_log_err(L[pts[ia], pts[jb]], lk_ref))
+    assert np.max(np.abs(K[pts[ia], pts[jb]] - k_ref)) <= K_ABS_TOL
+    ti, tj = np.meshgrid(np.arange(len(tst)), np.arange(len(pts)), indexing="ij")
+    lk_ref, _ = mps.mps_gram_pairs(St, S, ti.ravel(), tj.ravel())
+    assert log_close(_log_err(Lr[tst[ti.ravel()], pts[tj.ravel()]], lk_ref))
+
+
+@pytest.mark.parametrize("sweep", SWEEPS, ids=SWEEP_IDS)
+@pytest.mark.parametrize("reps", [1, 2, 3])
+def test_entanglement_free_784_closed_form(sweep, reps):
+    X = synth.pin_even_features(synth.images784(seed=7, n_train=66, n_test=0).X)
+    _, L = gram_sym(X, reps, sweep=sweep)
+    for (i, j) in [(0, 1), (3, 40), (10, 65), (64, 65)]:
+        ref = closed_forms.k_product_log(X[i], X[j], reps)
+        assert abs(L[i, j] - ref) <= LOG_TOL_MAX, (i, j, L[i, j], ref)
+
+
+def test_one_rep_784_transfer_closed_form():
+    X = synth.uniform_features(20, 784, seed=8)
+    _, L = gram_sym(X, 1)
+    for (i, j) in [(0, 1), (2, 19), (7, 8)]:
+        ref, _ = closed_forms.k_reps1_transfer(X[i], X[j])
+        assert abs(L[i, j] - ref) <= LOG_TOL_MAX
+
+
+@pytest.mark.parametrize("reps", [2, 3])
+def test_near_duplicates_784_absolute_bar(reps):
+    base, Xp, idx, eps = synth.image_near_duplicates(seed=3, n_base=6)
+    K, L = gram_rect(base, Xp, reps)
+    S = mps.mps_states(base, reps)
+    Sp = mps.mps_states(Xp, reps)
+    ii, jj = np.meshgrid(np.arange(base.shape[0]), np.arange(Xp.shape[0]), indexing="ij")
+    lk_ref, k_ref = mps.mps_gram_pairs(S, Sp, ii.ravel(), jj.ravel())
+    assert k_ref.max() > 0.9  # the set reaches K ~ 1, where the absolute bar bites
+    assert np.max(np.abs(K.ravel() - k_ref)) <= K_ABS_TOL
+    pos = k_ref > 0
+    assert log_close(_log_err(L.ravel()[pos], lk_ref[pos]))
+
+
+def test_self_overlap_784_diag_mode_1():
+    X = synth.images784(seed=9, n_train=70, n_test=0).X
+    K, _ = gram_sym(X, 2, diag_mode=1)
+    assert np.max(np.abs(np.diag(K) - 1.0)) <= K_ABS_TOL
+
+
+# --------------------------------------------------------------------------
+# Paths and options that must agree
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("reps", [1, 2, 3])
+def test_dense_and_butterfly_agree(reps):
+    X = synth.images784(seed=11, n_train=100, n_test=0).X[:, :200]
+    _, L1 = gram_sym(X, reps, sweep=qsvm.SWEEP_BUTTERFLY)
+    _, L2 = gram_sym(X, reps, sweep=qsvm.SWEEP_DENSE)
+    off = ~np.eye(100, dtype=bool)
+    assert log_close(_log_err(L1[off], L2[off]))
+
+
+@pytest.mark.parametrize("sweep", SWEEPS, ids=SWEEP_IDS)
+def test_renorm_interval_changes_rounding_only(sweep):
+    X = synth.images784(seed=12, n_train=70, n_test=0).X
+    _, L1 = gram_sym(X, 2, sweep=sweep, renorm_every=1)
+    _, L4 = gram_sym(X, 2, sweep=sweep, renorm_every=4)
+    _, L16 = gram_sym(X, 2, sweep=sweep, renorm_every=16)
+    off = ~np.eye(70, dtype=bool)
+    assert log_close(_log_err(L1[off], L4[off]))
+    assert log_close(_log_err(L1[off], L16[off]))
+
+
+@pytest.mark.parametrize("sweep", SWEEPS, ids=SWEEP_IDS)
+def test_bitwise_deterministic(sweep):
+    X = synth.images784(seed=13, n_train=130, n_test=0).X
+    K1, L1 = gram_sym(X, 2, sweep=sweep)
+    K2, L2 = gram_sym(X, 2, sweep=sweep)
+    assert np.array_equal(K1, K2) and np.array_equal(L1, L2)
+
+
+def test_row_blocks_reassemble_bitwise():
+    import torch
+
+    X = synth.images784(seed=14, n_train=150, n_test=0).X
+    m = encode(X, 2)
+    full = torch.full((150, 150), -7.0, dtype=torch.float64, device="cuda:0")
+    qsvm.qsvm_gram_sym(m, full)
+    parts = torch.full((150, 150), -7.0, dtype=torch.float64, device="cuda:0")
+    for rb, re_ in [(0, 37), (37, 64), (64, 149), (149, 150)]:
+        qsvm.qsvm_gram_sym(m, parts, rows=(rb, re_))
+    assert torch.equal(full, parts)
+    # rows (i, j > i) of one block touch only those rows and their mirror columns
+    one = torch.full((150, 150), -7.0, dtype=torch.float64, device="cuda:0")
+    qsvm.qsvm_gram_sym(m, one, rows=(40, 50))
+    o = one.cpu().numpy()
+    f = full.cpu().numpy()
+    assert np.array_equal(o[40:50, 40:], f[40:50, 40:])
+    assert np.all(o[:40, :40] == -7.0) and np.all(o[50:, 50:] == -7.0)
+    # rectangular
+    Xb = synth.images784(seed=15, n_train=90, n_test=0).X
+    mb = encode(Xb, 2)
+    r_full = qsvm.qsvm_gram(m, mb)
+    r_parts = torch.full((150, 90), -7.0, dtype=torch.float64, device="cuda:0")
+    for rb, re_ in [(0, 70), (70, 150)]:
+        qsvm.qsvm_gram(m, mb, r_parts, rows=(rb, re_))
+    assert torch.equal(r_full, r_parts)
+
+
+def test_ldk_padding_untouched():
+    import torch
+
+    X = synth.uniform_features(70, 10, seed=16)
+    m = encode(X, 2)
+    big = torch.full((70, 100), -3.0, dtype=torch.float64, device="cuda:0")
+    view = big[:, :70]
+    qsvm.qsvm_gram_sym(m, view)
+    b = big.cpu().numpy()
+    assert np.all(b[:, 70:] == -3.0)
+    assert np.max(np.abs(b[:, :70] - statevector.sv_gram(X, 2))) <= K_ABS_TOL
+
+
+def test_unsupported_and_invalid_raise_before_launch():
+    import torch
+
+    X = torch.zeros((4, 5), dtype=torch.float64, device="cuda:0")
+    with pytest.raises(qsvm.QsvmError) as ei:
+        qsvm.qsvm_encode_mps(X, 4)
+    assert ei.value.status == qsvm.QSVM_ERR_UNSUPPORTED
+    m = qsvm.qsvm_encode_mps(X, 2)
+    K = torch.empty((4, 3), dtype=torch.float64, device="cuda:0")
+    with pytest.raises(ValueError):
+        qsvm.qsvm_gram_sym(m, K[:3])
