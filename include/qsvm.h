@@ -72,11 +72,14 @@ typedef enum {
 typedef struct {
   int32_t renorm_every; /* sites between power-of-two renormalisations of the
                            environment (exact rescaling, exponent kept in an
-                           integer log2 accumulator); 0 = default (4), else 1..64 */
+                           integer log2 accumulator); 0 = default (4), else 1..16 */
   int32_t sweep;        /* qsvm_sweep_kind */
   int32_t diag_mode;    /* qsvm_gram_sym only: 0 = K[i][i] := 1 exactly (Alg. 1-3);
                            1 = compute the self-overlaps like any other pair */
-  int32_t reserved0;    /* must be 0 */
+  int32_t variant;      /* butterfly kernel variant: 0 = the tuned choice for this
+                           reps and size (qsvm_autotune) or the built-in default;
+                           1..4 = force variant 0..3 (ket points per lane and
+                           register budget); the dense sweep ignores it */
   int64_t row_begin;    /* compute only rows i in [row_begin, row_end) of K;   */
   int64_t row_end;      /* 0,0 = all rows.  For qsvm_gram_sym a row i covers the
                            pairs (i, j > i) and writes K[i][j], K[j][i], and
@@ -161,6 +164,78 @@ qsvm_status qsvm_gram(const void* mps_a, int64_t Na, const void* mps_b, int64_t 
  */
 qsvm_status qsvm_gram_sym(const void* mps, int64_t N, int32_t n_qubits, int32_t reps,
                           double* K, int64_t ldk, const qsvm_gram_opts* opts, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Batched jobs: many independent symmetric Grams in one persistent launch.
+ * Every job is cut into the work items of the single-Gram sweep, the items of
+ * all jobs are queued by decreasing cost (longest processing time first), and
+ * one persistent kernel -- one block per resident slot of every compute unit
+ * -- pops items with an atomic counter until the queue is empty (the
+ * concurrent, host-free contraction stream of §4.1, batched over jobs).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  const void* mps;   /* device MPS buffer of the job (qsvm_encode_mps with N, n_qubits, reps) */
+  int64_t N;         /* points */
+  int32_t n_qubits;
+  int32_t reps;      /* 1..3; jobs may mix reps and sizes */
+  double* K;         /* device N x N output, row stride ldk >= N; written as by qsvm_gram_sym */
+  int64_t ldk;
+  double* log_k;     /* optional device N x N output (same stride), or NULL */
+} qsvm_job;
+
+typedef struct {
+  int32_t renorm_every; /* as in qsvm_gram_opts; 0 = default */
+  int32_t diag_mode;    /* as in qsvm_gram_opts, for every job */
+  int32_t use_graph;    /* 1: capture the launch (counter reset + persistent kernel)
+                           into a hipGraph at plan creation and replay it */
+  int32_t grid_blocks;  /* persistent blocks; 0 = compute units x resident blocks per unit */
+} qsvm_batch_opts;
+
+typedef struct qsvm_batch_plan qsvm_batch_plan; /* opaque */
+
+/*
+ * Build a plan for n_jobs jobs on the current device: validates every job
+ * (errors name the job), orders the work queue, allocates and uploads the
+ * job table and the queue counter (hipMalloc + a synchronous copy: call this
+ * at set-up, not in a timed loop), and captures the graph if asked.  The
+ * jobs' buffers must stay valid for every later launch.  *plan = NULL on error.
+ */
+qsvm_status qsvm_batch_plan_create(const qsvm_job* jobs, int32_t n_jobs, const qsvm_batch_opts* opts,
+                                   qsvm_batch_plan** plan);
+
+/* Enqueue one execution of the plan on `stream` (graph launch or the two
+ * kernels).  Launches of one plan share its queue counter: keep them ordered
+ * on one stream. */
+qsvm_status qsvm_batch_plan_launch(qsvm_batch_plan* plan, void* stream);
+
+/* Wait for the plan's last launch, then free it (NULL is a no-op). */
+qsvm_status qsvm_batch_plan_destroy(qsvm_batch_plan* plan);
+
+/* Work items in the queue, persistent grid size, and whether a graph is used. */
+qsvm_status qsvm_batch_plan_info(const qsvm_batch_plan* plan, int64_t* total_items, int32_t* grid_blocks,
+                                 int32_t* uses_graph);
+
+/*
+ * Autotune the butterfly sweep for (reps, n_qubits, N) on the current device:
+ * every kernel variant (ket points per lane x register budget) is timed on a
+ * synthetic symmetric Gram of that shape (features from a fixed hash, uniform
+ * in [0, pi)), and the fastest is recorded in the per-process table that
+ * launches with opts.variant == 0 consult, keyed by reps and floor(log2 n).
+ * Allocates and frees its own device scratch (N x N doubles plus the MPS)
+ * and synchronises `stream`; N <= 65536.
+ *   best_variant  optional output: the chosen variant (0..3).
+ *   variant_ms    optional output of n_variant_ms >= 4 floats: mean launch
+ *                 time of each variant in milliseconds.
+ */
+qsvm_status qsvm_autotune(int32_t reps, int32_t n_qubits, int64_t N, void* stream, int32_t* best_variant,
+                          float* variant_ms, int32_t n_variant_ms);
+
+/* The variant (0..3) a launch with opts.variant == 0 uses for (reps, n_qubits). */
+int32_t qsvm_get_tuned_variant(int32_t reps, int32_t n_qubits);
+
+/* Record a variant for (reps, n_qubits) in the per-process table (e.g. from a
+ * saved tuning cache).  No HIP call. */
+qsvm_status qsvm_set_tuned_variant(int32_t reps, int32_t n_qubits, int32_t variant);
 
 /* Static description of a status code (never NULL). */
 const char* qsvm_status_string(qsvm_status s);

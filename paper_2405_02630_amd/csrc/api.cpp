@@ -64,6 +64,7 @@ struct Opts {
   int32_t renorm_every = kDefaultRenorm;
   int32_t sweep = QSVM_SWEEP_BUTTERFLY;
   int32_t diag_mode = 0;
+  int32_t variant = 0;
   int64_t row_begin = 0, row_end = 0;
   double* log_k = nullptr;
 };
@@ -81,7 +82,9 @@ qsvm_status read_opts(const qsvm_gram_opts* o, int64_t rows, Opts& out, const ch
   if (o->diag_mode != 0 && o->diag_mode != 1)
     return fail(QSVM_ERR_INVALID_ARG, "%s: diag_mode = %d must be 0 or 1", what, o->diag_mode);
   out.diag_mode = o->diag_mode;
-  if (o->reserved0 != 0) return fail(QSVM_ERR_INVALID_ARG, "%s: reserved0 must be 0", what);
+  if (o->variant < 0 || o->variant > qsvm::kButterflyVariants)
+    return fail(QSVM_ERR_INVALID_ARG, "%s: variant = %d outside [0, %d]", what, o->variant, qsvm::kButterflyVariants);
+  out.variant = o->variant;
   if (o->row_begin != 0 || o->row_end != 0) {
     if (o->row_begin < 0 || o->row_end < o->row_begin || o->row_end > rows)
       return fail(QSVM_ERR_INVALID_ARG, "%s: row range [%lld, %lld) outside [0, %lld]", what,
@@ -91,6 +94,11 @@ qsvm_status read_opts(const qsvm_gram_opts* o, int64_t rows, Opts& out, const ch
   }
   out.log_k = o->log_k;
   return QSVM_OK;
+}
+
+// Variant for a launch: forced by opts, else the tuned table (default 0).
+int32_t pick_variant(const Opts& o, int32_t reps, int32_t n) {
+  return o.variant > 0 ? o.variant - 1 : qsvm::tuned_variant(reps, n);
 }
 
 qsvm_status run_gram(const void* mps_a, int64_t Na, const void* mps_b, int64_t Nb, int32_t n,
@@ -124,11 +132,19 @@ qsvm_status run_gram(const void* mps_a, int64_t Na, const void* mps_b, int64_t N
   if (injected_launch_failure()) return fail(QSVM_ERR_HIP, "%s: injected launch failure (QSVM_FAULT_INJECT=launch)", what);
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = (o.sweep == QSVM_SWEEP_DENSE) ? qsvm::launch_sweep_dense_args(a, reps, s)
-                                                : qsvm::launch_sweep_butterfly_args(a, reps, s);
+                                                : qsvm::launch_sweep_butterfly_args(a, reps, pick_variant(o, reps, n), s);
   return hip_status(e, what);
 }
 
 }  // namespace
+
+namespace qsvm {
+// Status helpers shared with the batch-plan translation unit.
+qsvm_status api_fail(qsvm_status s, const char* msg) { return fail(s, "%s", msg); }
+qsvm_status api_ok() { return ok(); }
+qsvm_status api_hip(hipError_t e, const char* what) { return hip_status(e, what); }
+bool api_injected_failure() { return injected_launch_failure(); }
+}  // namespace qsvm
 
 extern "C" {
 
@@ -186,6 +202,34 @@ qsvm_status qsvm_gram_sym(const void* mps, int64_t N, int32_t n_qubits, int32_t 
   s = read_opts(opts, N, o, what);
   if (s != QSVM_OK) return s;
   return run_gram(mps, N, mps, N, n_qubits, reps, K, ldk, o, true, stream, what);
+}
+
+qsvm_status qsvm_autotune(int32_t reps, int32_t n_qubits, int64_t N, void* stream, int32_t* best_variant,
+                          float* variant_ms, int32_t n_variant_ms) {
+  const char* what = "qsvm_autotune";
+  qsvm_status s = check_shape(N, n_qubits, reps, what);
+  if (s != QSVM_OK) return s;
+  if (N > 65536) return fail(QSVM_ERR_INVALID_ARG, "%s: N = %lld above the 65536 tuning limit", what, (long long)N);
+  if (variant_ms && n_variant_ms < qsvm::kButterflyVariants)
+    return fail(QSVM_ERR_SIZE, "%s: variant_ms holds %d < %d entries", what, n_variant_ms, qsvm::kButterflyVariants);
+  if (injected_launch_failure()) return fail(QSVM_ERR_HIP, "%s: injected launch failure (QSVM_FAULT_INJECT=launch)", what);
+  int32_t best = 0;
+  hipError_t e = qsvm::autotune_run(reps, n_qubits, N, static_cast<hipStream_t>(stream), &best, variant_ms);
+  if (e != hipSuccess) return hip_status(e, what);
+  if (best_variant) *best_variant = best;
+  return ok();
+}
+
+int32_t qsvm_get_tuned_variant(int32_t reps, int32_t n_qubits) { return qsvm::tuned_variant(reps, n_qubits); }
+
+qsvm_status qsvm_set_tuned_variant(int32_t reps, int32_t n_qubits, int32_t variant) {
+  const char* what = "qsvm_set_tuned_variant";
+  qsvm_status s = check_shape(1, n_qubits, reps, what);
+  if (s != QSVM_OK) return s;
+  if (variant < 0 || variant >= qsvm::kButterflyVariants)
+    return fail(QSVM_ERR_INVALID_ARG, "%s: variant = %d outside [0, %d)", what, variant, qsvm::kButterflyVariants);
+  qsvm::set_tuned_variant(reps, n_qubits, variant);
+  return ok();
 }
 
 const char* qsvm_status_string(qsvm_status s) {

@@ -1,263 +1,29 @@
-// Butterfly sweep: <psi(y)|psi(x)> for every pair of a tile, from the
-// gauge generators of Section G (layout in include/qsvm.h).
-//
-// The overlap of two MPS is the left-to-right environment recursion
-// E <- sum_s B_s^dagger E A_s (the contraction Alg. 2 repeats per pair, in
-// the one fixed order that is optimal for a chain).  E is indexed by the
-// bond states (c, c') of ket and bra; the physical index forces the top bit
-// of c and c' to agree, so E has 2^(2r-1) entries.  In the diagonal gauge of
-// Section G each site tensor is sgn(new) * prod_l C[new_l][old_l] with
-// C = [[1, a], [1, b]] (times 2^(-r/2), kept in the exponent), so one site
-// step is a sequence of 2x2 butterflies, one per bit axis:
-//   ket bit axes l < r : (u0, u1) -> (u0 + a_x u1, u0 + b_x u1)
-//   bra bit axes l < r : (u0, u1) -> (u0 + conj(a_y) u1, u0 + conj(b_y) u1)
-//   shared top bit     : (u0, u1) -> (u0 + a_x conj(a_y) u1, u0 + b_x conj(b_y) u1)
-// followed by the sign pattern (-1)^(sum_l c_l c_{l-1} + same for c'), folded
-// into the second output of each butterfly.  That is (2r-1) 2^(2r-2) * 2
-// complex multiply-adds per site instead of the chi^3 of the dense update.
-//
-// Work layout: a tile is 64 ket points x 64 bra points.  A wave owns PI ket
-// points (wave-uniform, their generators come through scalar loads) and 64
-// bra points (one per lane), and keeps the PI environments of its lane in
-// VGPRs for the whole chain.  A block is 4 waves on consecutive ket groups of
-// one tile.  Every `renorm_every` sites the environment is divided by the
-// power of two nearest its largest component (exact) and the exponent added
-// to an integer log2 accumulator.  The final closure with the right boundary
-// g^|c| conj(g')^|c'| and |amp|^2 are formed in FP64.
+// Single-Gram launch of the butterfly sweep (device code of one work item in
+// sweep_butterfly_item.h): one grid over the tiles of one Gram, blocks mapped
+// XCD-aware, with the kernel variants the autotuner chooses among.
 
-#include "sweep_common.h"
+#include "sweep_butterfly_item.h"
 
 namespace qsvm {
 namespace {
 
-// t0 = u0 + (ar + i ai) u1 ; t1 = u0 + (br + i bi) u1 ; u1 <- NEG ? -t1 : t1
-template <bool NEG>
-__device__ __forceinline__ void bfly(float2& u0, float2& u1, float ar, float ai, float br, float bi) {
-  const float x0 = u0.x, y0 = u0.y, x1 = u1.x, y1 = u1.y;
-  float t0r = fmaf(ar, x1, x0);
-  t0r = fmaf(-ai, y1, t0r);
-  float t0i = fmaf(ar, y1, y0);
-  t0i = fmaf(ai, x1, t0i);
-  float t1r, t1i;
-  if (NEG) {
-    t1r = fmaf(-br, x1, -x0);
-    t1r = fmaf(bi, y1, t1r);
-    t1i = fmaf(-br, y1, -y0);
-    t1i = fmaf(-bi, x1, t1i);
-  } else {
-    t1r = fmaf(br, x1, x0);
-    t1r = fmaf(-bi, y1, t1r);
-    t1i = fmaf(br, y1, y0);
-    t1i = fmaf(bi, x1, t1i);
-  }
-  u0 = make_float2(t0r, t0i);
-  u1 = make_float2(t1r, t1i);
-}
-
-template <int R>
-struct Layout {
-  static constexpr int NB = 2 * R - 1;      // index bits of the environment
-  static constexpr int M = 1 << NB;         // environment entries
-  static constexpr int S = NB - 1;          // shared top (physical) bit
-  __host__ __device__ static constexpr int ket_bit(int l) { return l - 1; }          // l = 1..R-1
-  __host__ __device__ static constexpr int bra_bit(int l) { return R - 1 + l - 1; }  // l = 1..R-1
-};
-
-template <int R, int AXBIT, int SIGNBIT, int SIGNBIT2>
-__device__ __forceinline__ void axis(float2 (&v)[Layout<R>::M], float ar, float ai, float br, float bi) {
-  constexpr int M = Layout<R>::M;
-#pragma unroll
-  for (int i0 = 0; i0 < M; ++i0) {
-    if (i0 & (1 << AXBIT)) continue;
-    const int i1 = i0 | (1 << AXBIT);
-    bool neg = false;
-    if constexpr (SIGNBIT >= 0) neg ^= ((i0 >> SIGNBIT) & 1) != 0;
-    if constexpr (SIGNBIT2 >= 0) neg ^= ((i0 >> SIGNBIT2) & 1) != 0;
-    if (neg)
-      bfly<true>(v[i0], v[i1], ar, ai, br, bi);
-    else
-      bfly<false>(v[i0], v[i1], ar, ai, br, bi);
-  }
-}
-
-// Ket axes and bra axes for l = 1..R-1 (compile-time recursion).
-template <int R, int L>
-struct Axes {
-  __device__ __forceinline__ static void ket(float2 (&v)[Layout<R>::M], const float4& c) {
-    if constexpr (L <= R - 1) {
-      axis<R, Layout<R>::ket_bit(L), (L >= 2 ? Layout<R>::ket_bit(L - 1) : -1), -1>(v, c.x, c.y, c.z, c.w);
-      Axes<R, L + 1>::ket(v, c);
-    }
-  }
-  __device__ __forceinline__ static void bra(float2 (&v)[Layout<R>::M], const float4& c) {
-    if constexpr (L <= R - 1) {
-      axis<R, Layout<R>::bra_bit(L), (L >= 2 ? Layout<R>::bra_bit(L - 1) : -1), -1>(v, c.x, -c.y, c.z, -c.w);
-      Axes<R, L + 1>::bra(v, c);
-    }
-  }
-};
-
-template <int R>
-__device__ __forceinline__ void site_step(float2 (&v)[Layout<R>::M], const float4& cx, const float4& cy) {
-  Axes<R, 1>::ket(v, cx);
-  Axes<R, 1>::bra(v, cy);
-  // shared top bit: coefficients a_x conj(a_y), b_x conj(b_y)
-  const float asr = fmaf(cx.x, cy.x, cx.y * cy.y);
-  const float asi = fmaf(cx.y, cy.x, -(cx.x * cy.y));
-  const float bsr = fmaf(cx.z, cy.z, cx.w * cy.w);
-  const float bsi = fmaf(cx.w, cy.z, -(cx.z * cy.w));
-  constexpr int SB1 = (R >= 2) ? Layout<R>::ket_bit(R - 1) : -1;
-  constexpr int SB2 = (R >= 2) ? Layout<R>::bra_bit(R - 1) : -1;
-  axis<R, Layout<R>::S, SB1, SB2>(v, asr, asi, bsr, bsi);
-}
-
-template <int R>
-__device__ __forceinline__ int renorm(float2 (&v)[Layout<R>::M]) {
-  constexpr int M = Layout<R>::M;
-  float m = 0.0f;
-#pragma unroll
-  for (int q = 0; q < M; ++q) m = fmaxf(m, fmaxf(fabsf(v[q].x), fabsf(v[q].y)));
-  const int e = __builtin_amdgcn_frexp_expf(m);  // m = f 2^e, f in [0.5, 1); 0 for m = 0
-  // v * 2^-e, exact; ldexp per component stays correct even where 2^-e alone
-  // would not be representable
-#pragma unroll
-  for (int q = 0; q < M; ++q) {
-    v[q].x = __builtin_amdgcn_ldexpf(v[q].x, -e);
-    v[q].y = __builtin_amdgcn_ldexpf(v[q].y, -e);
-  }
-  return e;
-}
-
-// Sign of a bond column: (-1)^(sum_{l=1}^{r-1} c_l c_{l-1}) over the bits
-// (c_0 .. c_{r-2} from `low`, c_{r-1} = s).
-template <int R>
-__device__ __forceinline__ constexpr int col_sign_parity(int low, int s) {
-  const int c = low | (s << (R - 1));
-  return __builtin_popcount(c & (c >> 1)) & 1;
-}
-
-template <int R>
-__device__ __forceinline__ void init_env(float2 (&v)[Layout<R>::M]) {
-  constexpr int M = Layout<R>::M;
-  constexpr int LOWMASK = (1 << (R - 1)) - 1;
-#pragma unroll
-  for (int q = 0; q < M; ++q) {
-    const int ket = q & LOWMASK;
-    const int bra = (q >> (R - 1)) & LOWMASK;
-    const int s = (q >> Layout<R>::S) & 1;
-    const int par = col_sign_parity<R>(ket, s) ^ col_sign_parity<R>(bra, s);
-    v[q] = make_float2(par ? -1.0f : 1.0f, 0.0f);
-  }
-}
-
-// |sum_q g_x^|c| conj(g_y)^|c'| v[q]|^2 in FP64.
-template <int R>
-__device__ __forceinline__ double closure(const float2 (&v)[Layout<R>::M], float4 gx4, float4 gy4) {
-  constexpr int M = Layout<R>::M;
-  constexpr int LOWMASK = (1 << (R - 1)) - 1;
-  double pxr[R + 1], pxi[R + 1], pyr[R + 1], pyi[R + 1];
-  pxr[0] = 1.0; pxi[0] = 0.0; pyr[0] = 1.0; pyi[0] = 0.0;
-  const double gxr = gx4.x, gxi = gx4.y, gyr = gy4.x, gyi = -double(gy4.y);  // conj(g_y)
-#pragma unroll
-  for (int m = 1; m <= R; ++m) {
-    pxr[m] = pxr[m - 1] * gxr - pxi[m - 1] * gxi;
-    pxi[m] = pxr[m - 1] * gxi + pxi[m - 1] * gxr;
-    pyr[m] = pyr[m - 1] * gyr - pyi[m - 1] * gyi;
-    pyi[m] = pyr[m - 1] * gyi + pyi[m - 1] * gyr;
-  }
-  double sr = 0.0, si = 0.0;
-#pragma unroll
-  for (int q = 0; q < M; ++q) {
-    const int s = (q >> Layout<R>::S) & 1;
-    const int hk = __builtin_popcount(q & LOWMASK) + s;
-    const int hb = __builtin_popcount((q >> (R - 1)) & LOWMASK) + s;
-    const double wr = pxr[hk] * pyr[hb] - pxi[hk] * pyi[hb];
-    const double wi = pxr[hk] * pyi[hb] + pxi[hk] * pyr[hb];
-    sr += wr * double(v[q].x) - wi * double(v[q].y);
-    si += wr * double(v[q].y) + wi * double(v[q].x);
-  }
-  return sr * sr + si * si;
-}
-
-template <int R, int PI>
-__global__ void __launch_bounds__(256)
+// One launch over the tiles of one Gram.  W = target waves per SIMD (the
+// register budget the compiler must fit: 512 / W VGPRs).
+template <int R, int PI, int W>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8)))
 sweep_butterfly_kernel(SweepArgs a) {
-  constexpr int M = Layout<R>::M;
   const uint32_t L = xcd_logical_block();
   if (L >= a.num_blocks) return;
   const uint32_t tile = L / uint32_t(a.blocks_per_tile);
   const uint32_t sub = L % uint32_t(a.blocks_per_tile);
   int32_t ti, tj;
   decode_tile(a, tile, ti, tj);
-
-  const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t j = int64_t(tj) * kTile + lane;
   const int64_t i0 = int64_t(ti) * kTile + (int64_t(sub) * 4 + wave) * PI;  // wave-uniform
-
-  bool comp[PI];
-  bool any_comp = false, any_active = false;
-#pragma unroll
-  for (int p = 0; p < PI; ++p) {
-    comp[p] = pair_computed(a, i0 + p, j);
-    any_comp |= comp[p];
-    any_active |= pair_active(a, i0 + p, j);
-  }
-  if (!__builtin_amdgcn_ballot_w64(any_active)) return;  // wave has nothing to write
-
-  const int64_t jc = (j < a.Nb) ? j : a.Nb - 1;  // clamp loads of idle lanes in bounds
-  int64_t ic[PI];
-#pragma unroll
-  for (int p = 0; p < PI; ++p) ic[p] = (i0 + p < a.Na) ? i0 + p : a.Na - 1;
-
-  float2 v[PI][M];
-  int32_t acc[PI];
-#pragma unroll
-  for (int p = 0; p < PI; ++p) {
-    init_env<R>(v[p]);
-    acc[p] = 0;
-  }
-
-  const float4* __restrict__ gA = a.gen_a;
-  const float4* __restrict__ gB = a.gen_b;
-  if (__builtin_amdgcn_ballot_w64(any_comp)) {
-    int countdown = a.renorm_every;
-    float4 cy = gB[a.Nb + jc];  // site 1
-    float4 cx[PI];
-#pragma unroll
-    for (int p = 0; p < PI; ++p) cx[p] = gA[a.Na + ic[p]];
-    for (int k = 1; k < a.n; ++k) {
-      // prefetch the next site's generators (clamped to the last site)
-      const int kn = (k + 1 < a.n) ? k + 1 : k;
-      const float4 cy_next = gB[int64_t(kn) * a.Nb + jc];
-      float4 cx_next[PI];
-#pragma unroll
-      for (int p = 0; p < PI; ++p) cx_next[p] = gA[int64_t(kn) * a.Na + ic[p]];
-#pragma unroll
-      for (int p = 0; p < PI; ++p) site_step<R>(v[p], cx[p], cy);
-      if (--countdown == 0) {
-#pragma unroll
-        for (int p = 0; p < PI; ++p) acc[p] += renorm<R>(v[p]);
-        countdown = a.renorm_every;
-      }
-      cy = cy_next;
-#pragma unroll
-      for (int p = 0; p < PI; ++p) cx[p] = cx_next[p];
-    }
-  }
-
-  const float4 gy = gB[jc];
-#pragma unroll
-  for (int p = 0; p < PI; ++p) {
-    if (!pair_active(a, i0 + p, j)) continue;
-    const double s2 = comp[p] ? closure<R>(v[p], gA[ic[p]], gy) : 1.0;
-    // amp = closure * 2^(acc - R n)  =>  K = s2 * 2^(2 (acc - R n))
-    const int32_t e2 = 2 * (acc[p] - R * a.n);
-    store_entry(a, i0 + p, j, s2, e2);
-  }
+  butterfly_item<R, PI>(a, i0, int64_t(tj) * kTile);
 }
 
-template <int R, int PI>
+template <int R, int PI, int W>
 hipError_t launch_pi(const SweepArgs& a0, hipStream_t stream) {
   SweepArgs a = a0;
   a.blocks_per_tile = kTile / (4 * PI);
@@ -270,17 +36,28 @@ hipError_t launch_pi(const SweepArgs& a0, hipStream_t stream) {
   if (blocks > (int64_t(1) << 31) - 8) return hipErrorInvalidValue;
   a.num_blocks = uint32_t(blocks);
   const uint32_t padded = uint32_t((blocks + 7) / 8 * 8);
-  hipLaunchKernelGGL((sweep_butterfly_kernel<R, PI>), dim3(padded), dim3(256), 0, stream, a);
+  hipLaunchKernelGGL((sweep_butterfly_kernel<R, PI, W>), dim3(padded), dim3(256), 0, stream, a);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_sweep_butterfly_args(const SweepArgs& a, int32_t reps, hipStream_t stream) {
-  switch (reps) {
-    case 1: return launch_pi<1, 4>(a, stream);
-    case 2: return launch_pi<2, 4>(a, stream);
-    case 3: return launch_pi<3, 2>(a, stream);
+// Kernel variants (ket points per lane PI, target waves per SIMD W); the
+// autotuner picks among them, variant 0 of each reps is the default.
+hipError_t launch_sweep_butterfly_args(const SweepArgs& a, int32_t reps, int32_t variant, hipStream_t stream) {
+  switch (reps * 16 + variant) {
+    case 16 + 0: return launch_pi<1, 8, 4>(a, stream);
+    case 16 + 1: return launch_pi<1, 4, 4>(a, stream);
+    case 16 + 2: return launch_pi<1, 8, 2>(a, stream);
+    case 16 + 3: return launch_pi<1, 4, 8>(a, stream);
+    case 32 + 0: return launch_pi<2, 4, 4>(a, stream);
+    case 32 + 1: return launch_pi<2, 2, 4>(a, stream);
+    case 32 + 2: return launch_pi<2, 4, 2>(a, stream);
+    case 32 + 3: return launch_pi<2, 2, 8>(a, stream);
+    case 48 + 0: return launch_pi<3, 1, 3>(a, stream);
+    case 48 + 1: return launch_pi<3, 2, 2>(a, stream);
+    case 48 + 2: return launch_pi<3, 1, 2>(a, stream);
+    case 48 + 3: return launch_pi<3, 1, 4>(a, stream);
     default: return hipErrorInvalidValue;
   }
 }

@@ -35,10 +35,35 @@ class GramOpts(ctypes.Structure):
         ("renorm_every", ctypes.c_int32),
         ("sweep", ctypes.c_int32),
         ("diag_mode", ctypes.c_int32),
-        ("reserved0", ctypes.c_int32),
+        ("variant", ctypes.c_int32),
         ("row_begin", ctypes.c_int64),
         ("row_end", ctypes.c_int64),
         ("log_k", ctypes.c_void_p),
+    ]
+
+
+class Job(ctypes.Structure):
+    """Mirror of qsvm_job."""
+
+    _fields_ = [
+        ("mps", ctypes.c_void_p),
+        ("N", ctypes.c_int64),
+        ("n_qubits", ctypes.c_int32),
+        ("reps", ctypes.c_int32),
+        ("K", ctypes.c_void_p),
+        ("ldk", ctypes.c_int64),
+        ("log_k", ctypes.c_void_p),
+    ]
+
+
+class BatchOpts(ctypes.Structure):
+    """Mirror of qsvm_batch_opts."""
+
+    _fields_ = [
+        ("renorm_every", ctypes.c_int32),
+        ("diag_mode", ctypes.c_int32),
+        ("use_graph", ctypes.c_int32),
+        ("grid_blocks", ctypes.c_int32),
     ]
 
 
@@ -77,6 +102,20 @@ def load_library(path: str = LIB_PATH):
     lib.qsvm_last_error.restype = ctypes.c_char_p
     lib.qsvm_abi_version.argtypes = []
     lib.qsvm_abi_version.restype = i32
+    lib.qsvm_batch_plan_create.argtypes = [ctypes.POINTER(Job), i32, ctypes.POINTER(BatchOpts), ctypes.POINTER(vp)]
+    lib.qsvm_batch_plan_create.restype = i32
+    lib.qsvm_batch_plan_launch.argtypes = [vp, vp]
+    lib.qsvm_batch_plan_launch.restype = i32
+    lib.qsvm_batch_plan_destroy.argtypes = [vp]
+    lib.qsvm_batch_plan_destroy.restype = i32
+    lib.qsvm_batch_plan_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.qsvm_batch_plan_info.restype = i32
+    lib.qsvm_autotune.argtypes = [i32, i32, i64, vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float), i32]
+    lib.qsvm_autotune.restype = i32
+    lib.qsvm_get_tuned_variant.argtypes = [i32, i32]
+    lib.qsvm_get_tuned_variant.restype = i32
+    lib.qsvm_set_tuned_variant.argtypes = [i32, i32, i32]
+    lib.qsvm_set_tuned_variant.restype = i32
     _lib = lib
     return lib
 
@@ -140,8 +179,30 @@ def qsvm_encode_mps(X, reps: int, out=None, stream=None) -> MPS:
     return MPS(out, N, n, reps)
 
 
-def _opts(renorm_every, sweep, diag_mode, rows, log_k):
+N_VARIANTS = 4
+
+
+def qsvm_autotune(reps: int, n_qubits: int, N: int, stream=None):
+    """Time every butterfly variant on a synthetic (N, n_qubits, reps) Gram and
+    record the fastest for later launches.  Returns (best, [ms per variant])."""
+    lib = load_library()
+    best = ctypes.c_int32(0)
+    ms = (ctypes.c_float * N_VARIANTS)()
+    _check(lib.qsvm_autotune(reps, n_qubits, N, _stream_ptr(stream), ctypes.byref(best), ms, N_VARIANTS))
+    return int(best.value), [float(x) for x in ms]
+
+
+def qsvm_get_tuned_variant(reps: int, n_qubits: int) -> int:
+    return int(load_library().qsvm_get_tuned_variant(reps, n_qubits))
+
+
+def qsvm_set_tuned_variant(reps: int, n_qubits: int, variant: int) -> None:
+    _check(load_library().qsvm_set_tuned_variant(reps, n_qubits, variant))
+
+
+def _opts(renorm_every, sweep, diag_mode, rows, log_k, variant=0):
     o = GramOpts()
+    o.variant = variant
     o.renorm_every = renorm_every
     o.sweep = sweep
     o.diag_mode = diag_mode
@@ -152,7 +213,7 @@ def _opts(renorm_every, sweep, diag_mode, rows, log_k):
 
 
 def qsvm_gram(mps_a: MPS, mps_b: MPS, K=None, *, log_k=None, renorm_every: int = 0,
-              sweep: int = SWEEP_AUTO, rows=None, stream=None):
+              sweep: int = SWEEP_AUTO, rows=None, variant: int = 0, stream=None):
     """K[i, j] = |<psi(b_j)|psi(a_i)>|^2 (CUDA float64, Na x Nb).  Returns K."""
     import torch
 
@@ -165,7 +226,7 @@ def qsvm_gram(mps_a: MPS, mps_b: MPS, K=None, *, log_k=None, renorm_every: int =
         raise ValueError("K must be 2-D with unit column stride and at least Na rows")
     if log_k is not None and (log_k.shape != K.shape or log_k.stride() != K.stride() or log_k.dtype != torch.float64):
         raise ValueError("log_k must match K's shape, strides and dtype")
-    o = _opts(renorm_every, sweep, 0, rows, log_k)
+    o = _opts(renorm_every, sweep, 0, rows, log_k, variant)
     st = lib.qsvm_gram(
         _device_ptr(mps_a.buf, "mps_a"), mps_a.N, _device_ptr(mps_b.buf, "mps_b"), mps_b.N, mps_a.n, mps_a.reps,
         ctypes.c_void_p(K.data_ptr()), K.stride(0), ctypes.byref(o), _stream_ptr(stream),
@@ -175,7 +236,7 @@ def qsvm_gram(mps_a: MPS, mps_b: MPS, K=None, *, log_k=None, renorm_every: int =
 
 
 def qsvm_gram_sym(mps: MPS, K=None, *, log_k=None, renorm_every: int = 0, sweep: int = SWEEP_AUTO,
-                  diag_mode: int = 0, rows=None, stream=None):
+                  diag_mode: int = 0, rows=None, variant: int = 0, stream=None):
     """Symmetric Gram of one set: pairs i < j contracted, mirrored, K[i, i] = 1
     (diag_mode 0) or computed (diag_mode 1).  Returns K."""
     import torch
@@ -187,10 +248,58 @@ def qsvm_gram_sym(mps: MPS, K=None, *, log_k=None, renorm_every: int = 0, sweep:
         raise ValueError("K must be 2-D with unit column stride and at least N rows")
     if log_k is not None and (log_k.shape != K.shape or log_k.stride() != K.stride() or log_k.dtype != torch.float64):
         raise ValueError("log_k must match K's shape, strides and dtype")
-    o = _opts(renorm_every, sweep, diag_mode, rows, log_k)
+    o = _opts(renorm_every, sweep, diag_mode, rows, log_k, variant)
     st = lib.qsvm_gram_sym(
         _device_ptr(mps.buf, "mps"), mps.N, mps.n, mps.reps, ctypes.c_void_p(K.data_ptr()), K.stride(0),
         ctypes.byref(o), _stream_ptr(stream),
     )
     _check(st)
     return K
+
+
+class BatchPlan:
+    """A qsvm_batch_plan over symmetric Gram jobs [(MPS, K, log_k or None), ...].
+
+    Holds references to every job buffer for its lifetime; ``launch`` enqueues
+    one execution on the current PyTorch stream."""
+
+    def __init__(self, jobs, *, renorm_every: int = 0, diag_mode: int = 0, use_graph: bool = True,
+                 grid_blocks: int = 0):
+        lib = load_library()
+        self._keep = list(jobs)
+        arr = (Job * len(jobs))()
+        for q, (m, K, L) in enumerate(jobs):
+            if K.dim() != 2 or K.shape[0] < m.N or K.shape[1] < m.N or K.stride(1) != 1:
+                raise ValueError(f"job {q}: K must be at least N x N with unit column stride")
+            arr[q].mps = _device_ptr(m.buf, f"job {q} mps").value
+            arr[q].N = m.N
+            arr[q].n_qubits = m.n
+            arr[q].reps = m.reps
+            arr[q].K = K.data_ptr()
+            arr[q].ldk = K.stride(0)
+            arr[q].log_k = None if L is None else L.data_ptr()
+        o = BatchOpts(renorm_every, diag_mode, 1 if use_graph else 0, grid_blocks)
+        h = ctypes.c_void_p()
+        _check(lib.qsvm_batch_plan_create(arr, len(jobs), ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(load_library().qsvm_batch_plan_launch(self._h, _stream_ptr(stream)))
+
+    def info(self):
+        t = ctypes.c_int64()
+        g = ctypes.c_int32()
+        u = ctypes.c_int32()
+        _check(load_library().qsvm_batch_plan_info(self._h, ctypes.byref(t), ctypes.byref(g), ctypes.byref(u)))
+        return int(t.value), int(g.value), bool(u.value)
+
+    def close(self):
+        if self._h:
+            load_library().qsvm_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -126,7 +126,7 @@ def test_gram_rect_validation(lib, no_inject):
 
 @pytest.mark.parametrize(
     "field,value",
-    [("renorm_every", -1), ("renorm_every", 17), ("sweep", 3), ("sweep", -1), ("diag_mode", 2), ("reserved0", 1)],
+    [("renorm_every", -1), ("renorm_every", 17), ("sweep", 3), ("sweep", -1), ("diag_mode", 2), ("variant", 5), ("variant", -1)],
 )
 def test_gram_opts_validation(lib, no_inject, field, value):
     o = qsvm.GramOpts()
@@ -176,3 +176,75 @@ def test_missing_library_raises(tmp_path):
             qsvm.load_library(str(tmp_path / "libqsvm.so"))
     finally:
         qsvm._lib = saved
+
+
+# --------------------------------------------------------------------------
+# Batched plans: validation happens before any HIP call
+# --------------------------------------------------------------------------
+
+def _job(mps=0x100000, N=100, n=8, reps=2, K=0x200000, ldk=100, log_k=None):
+    j = qsvm.Job()
+    j.mps, j.N, j.n_qubits, j.reps, j.K, j.ldk, j.log_k = mps, N, n, reps, K, ldk, log_k
+    return j
+
+
+def _plan(lib, jobs, opts=None):
+    arr = (qsvm.Job * len(jobs))(*jobs)
+    h = ctypes.c_void_p()
+    st = lib.qsvm_batch_plan_create(arr, len(jobs), ctypes.byref(opts) if opts else None, ctypes.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize(
+    "kw",
+    [dict(mps=None), dict(K=None), dict(N=0), dict(n=0), dict(reps=0), dict(ldk=99), dict(mps=0x100008)],
+)
+def test_batch_plan_rejects_bad_job(lib, no_inject, kw):
+    st, h = _plan(lib, [_job(), _job(**kw)])
+    assert st == qsvm.QSVM_ERR_INVALID_ARG and not h.value
+    assert b"job 1" in lib.qsvm_last_error()
+
+
+def test_batch_plan_unsupported_reps(lib, no_inject):
+    st, h = _plan(lib, [_job(reps=4)])
+    assert st == qsvm.QSVM_ERR_UNSUPPORTED and not h.value
+
+
+@pytest.mark.parametrize("field,value", [("renorm_every", 17), ("diag_mode", 3), ("use_graph", 2), ("grid_blocks", -1)])
+def test_batch_plan_rejects_bad_opts(lib, no_inject, field, value):
+    o = qsvm.BatchOpts()
+    setattr(o, field, value)
+    st, _ = _plan(lib, [_job()], o)
+    assert st == qsvm.QSVM_ERR_INVALID_ARG
+
+
+def test_batch_plan_null_arguments(lib, no_inject):
+    assert lib.qsvm_batch_plan_create(None, 0, None, None) == qsvm.QSVM_ERR_INVALID_ARG
+    h = ctypes.c_void_p()
+    assert lib.qsvm_batch_plan_create(None, 3, None, ctypes.byref(h)) == qsvm.QSVM_ERR_INVALID_ARG
+    assert lib.qsvm_batch_plan_launch(None, None) == qsvm.QSVM_ERR_INVALID_ARG
+    assert lib.qsvm_batch_plan_info(None, None, None, None) == qsvm.QSVM_ERR_INVALID_ARG
+    assert lib.qsvm_batch_plan_destroy(None) == qsvm.QSVM_OK
+
+
+def test_batch_plan_injected_failure(lib, monkeypatch):
+    monkeypatch.setenv("QSVM_FAULT_INJECT", "launch")
+    st, h = _plan(lib, [_job(), _job(reps=3, n=5)])
+    assert st == qsvm.QSVM_ERR_HIP and not h.value
+
+
+def test_tuned_variant_table(lib, no_inject):
+    assert lib.qsvm_set_tuned_variant(2, 300, 4) == qsvm.QSVM_ERR_INVALID_ARG
+    assert lib.qsvm_set_tuned_variant(5, 300, 1) == qsvm.QSVM_ERR_UNSUPPORTED
+    assert lib.qsvm_set_tuned_variant(2, 300, 3) == qsvm.QSVM_OK
+    assert lib.qsvm_get_tuned_variant(2, 300) == 3
+    assert lib.qsvm_get_tuned_variant(2, 511) == 3  # same log2 bucket
+    assert lib.qsvm_get_tuned_variant(2, 512) == 0  # untuned bucket -> default
+    assert lib.qsvm_set_tuned_variant(2, 300, 0) == qsvm.QSVM_OK
+
+
+def test_autotune_validation(lib, no_inject):
+    ms = (ctypes.c_float * 2)()
+    assert lib.qsvm_autotune(4, 10, 100, None, None, None, 0) == qsvm.QSVM_ERR_UNSUPPORTED
+    assert lib.qsvm_autotune(2, 10, 70000, None, None, None, 0) == qsvm.QSVM_ERR_INVALID_ARG
+    assert lib.qsvm_autotune(2, 10, 100, None, None, ms, 2) == qsvm.QSVM_ERR_SIZE
