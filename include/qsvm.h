@@ -165,6 +165,18 @@ qsvm_status qsvm_gram(const void* mps_a, int64_t Na, const void* mps_b, int64_t 
 qsvm_status qsvm_gram_sym(const void* mps, int64_t N, int32_t n_qubits, int32_t reps,
                           double* K, int64_t ldk, const qsvm_gram_opts* opts, void* stream);
 
+/*
+ * Symmetric Gram restricted to a list of 64 x 64 tiles: for every (ti, tj) in
+ * `tiles` (device int32 pairs, 0 <= ti <= tj < ceil(N/64)) the pairs
+ * i < j with i in tile row ti and j in tile column tj are contracted and
+ * written to K[i][j] and K[j][i], and diagonal tiles apply the diag_mode rule
+ * -- exactly what qsvm_gram_sym writes for those tiles, bit for bit.  List
+ * entries outside that range are skipped on the device.  Used as the exact
+ * fallback of the surrogate.  opts row ranges must be 0,0.
+ */
+qsvm_status qsvm_gram_sym_tiles(const void* mps, int64_t N, int32_t n_qubits, int32_t reps, const int32_t* tiles,
+                                int64_t n_tiles, double* K, int64_t ldk, const qsvm_gram_opts* opts, void* stream);
+
 /* ------------------------------------------------------------------------
  * Batched jobs: many independent symmetric Grams in one persistent launch.
  * Every job is cut into the work items of the single-Gram sweep, the items of
@@ -236,6 +248,80 @@ int32_t qsvm_get_tuned_variant(int32_t reps, int32_t n_qubits);
 /* Record a variant for (reps, n_qubits) in the per-process table (e.g. from a
  * saved tuning cache).  No HIP call. */
 qsvm_status qsvm_set_tuned_variant(int32_t reps, int32_t n_qubits, int32_t variant);
+
+/* ------------------------------------------------------------------------
+ * Learned surrogate: an MLP embedding f: R^n -> R^d_out (layers
+ * d_in -> d_h1 -> d_h2 -> d_out, GELU after the two hidden layers, BF16
+ * weights and activations, FP32 accumulation on the matrix cores) with
+ * K_hat(x, y) = sigmoid(alpha <f(x), f(y)> + beta), trained on exact kernel
+ * entries; tiles where K_hat could exceed a threshold fall back to the exact
+ * sweep (qsvm_gram_sym_tiles).  All widths and row counts are multiples of
+ * 64 (pad features with zeros up to d_in; pad rows with zero rows).
+ * Matrices are row-major; bf16 buffers are passed as void*.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t d_in, d_h1, d_h2, d_out;
+  const void* W1; const float* b1; /* W1: d_in x d_h1 (bf16), b1: d_h1 (f32); layer: x W1 + b1 */
+  const void* W2; const float* b2; /* W2: d_h1 x d_h2 */
+  const void* W3; const float* b3; /* W3: d_h2 x d_out */
+} qsvm_mlp;
+
+typedef struct {   /* activations of `rows` inputs */
+  float* H1; void* A1; /* rows x d_h1: pre-activation (f32), GELU output (bf16) */
+  float* H2; void* A2; /* rows x d_h2 */
+  float* E;  void* E16; /* rows x d_out embedding, f32 and bf16 */
+} qsvm_mlp_acts;
+
+typedef struct {   /* gradients (f32, shaped like the parameters) and bf16 scratch */
+  float* dW1; float* db1; float* dW2; float* db2; float* dW3; float* db3;
+  void* dH1; void* dH2; /* rows x d_h1, rows x d_h2 */
+} qsvm_mlp_grads;
+
+/* out[r][c] = bf16(X[idx[r]][c]) for c < n_qubits; 0 for n_qubits <= c < d_pad
+ * and for rows whose idx[r] is outside [0, N) (padding rows; checked on the
+ * device).  X: N x n_qubits float64; idx: rows int32; out: rows x d_pad. */
+qsvm_status qsvm_gather_features(const double* X, int64_t N, int32_t n_qubits, const int32_t* idx, int64_t rows,
+                                 int32_t d_pad, void* out, void* stream);
+
+/* Forward pass of `rows` inputs X16 (rows x d_in bf16) into acts. */
+qsvm_status qsvm_mlp_forward(const qsvm_mlp* net, const void* X16, int64_t rows, const qsvm_mlp_acts* acts,
+                             void* stream);
+
+/* Pair head over E (2*pairs x d, f32): rows p and pairs + p are the two points
+ * of pair p with exact kernel target[p].  K_hat = sigmoid(ab[0] <e, e'> + ab[1]);
+ * loss_kind 0: loss = mean (K_hat - target)^2; 1: loss = mean soft-target
+ * cross-entropy -t log K_hat - (1 - t) log(1 - K_hat) (its logit gradient
+ * K_hat - t does not vanish for tiny kernels).  Writes dE16 (2*pairs x d,
+ * bf16 gradient of the loss w.r.t. E), per-pair partials (3*pairs floats) and
+ * out3 = (loss, dloss/dalpha, dloss/dbeta), reduced in a fixed order. */
+qsvm_status qsvm_pair_head(const float* E, int64_t pairs, int32_t d, const float* target, const float* alpha_beta,
+                           int32_t loss_kind, void* dE16, float* partial, float* out3, void* stream);
+
+/* Backward pass given dE16 (rows x d_out bf16): parameter gradients into grads
+ * (overwritten, not accumulated). */
+qsvm_status qsvm_mlp_backward(const qsvm_mlp* net, const void* X16, const qsvm_mlp_acts* acts, const void* dE16,
+                              int64_t rows, const qsvm_mlp_grads* grads, void* stream);
+
+/* AdamW step (decoupled weight decay, bias-corrected moments) on f32 master
+ * weights w with moments m, v; step counts from 1; writes a bf16 copy to w16
+ * when it is not NULL. */
+qsvm_status qsvm_adamw(float* w, const float* grad, float* m, float* v, void* w16, int64_t count, float lr,
+                       float beta1, float beta2, float eps, float weight_decay, int32_t step, void* stream);
+
+/* Surrogate Gram: K[i][j] = sigmoid(ab[0] <e_i, e_j> + ab[1]) for i, j < N,
+ * K[i][i] = 1 (the diagonal rule of Alg. 1-3), from E16 (N_pad x d bf16,
+ * N_pad = N rounded up to 64, padding rows anything).  tile_max receives, per
+ * 64 x 64 tile (row-major, (N_pad/64)^2 floats), the largest off-diagonal
+ * K_hat (-inf for none). */
+qsvm_status qsvm_surrogate_gram(const void* E16, int64_t N, int64_t N_pad, int32_t d, const float* alpha_beta,
+                                double* K, int64_t ldk, float* tile_max, void* stream);
+
+/* Append every upper-triangular tile (ti <= tj) of a T x T tile_max array whose
+ * value is >= tau to tile_list (int32 pairs, room for T(T+1)/2) and its count
+ * to *count (device int32; cleared first).  The order of the list is not
+ * specified. */
+qsvm_status qsvm_flag_tiles(const float* tile_max, int32_t T, float tau, int32_t* tile_list, int32_t* count,
+                            void* stream);
 
 /* Static description of a status code (never NULL). */
 const char* qsvm_status_string(qsvm_status s);

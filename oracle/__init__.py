@@ -14,7 +14,9 @@ double-precision NumPy code that computes
   pairwise overlap swept site by site with a log-scale (the tensor-network
   method of §3.4.2 / Alg. 3, contracted in a fixed left-to-right order);
 * ``closed_forms`` (O3) -- entanglement-free product states, the one-rep
-  transfer-matrix sum and the one-qubit case.
+  transfer-matrix sum and the one-qubit case;
+* ``mlp`` -- FP64 forward, pair loss, backward and AdamW of the learned
+  surrogate that stands in for K at large N.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import this package.  The product path (the HIP library and

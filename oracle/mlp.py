@@ -1,0 +1,109 @@
+"""FP64 reference of the learned surrogate's arithmetic (test infrastructure only).
+
+The surrogate embeds a feature vector with a three-layer perceptron
+f(x) = ((gelu(gelu(x W1 + b1) W2 + b2)) W3 + b3) and predicts a kernel entry
+as K_hat(x, y) = sigmoid(alpha <f(x), f(y)> + beta); it is trained by mean
+squared error against exact kernel entries (the kernel of §2, Eq. 3) with
+AdamW.  This module writes those definitions out in float64 NumPy so the GPU
+kernels (BF16 operands, FP32 accumulation) can be compared with them.  GELU
+is the exact form x Phi(x).  Nothing here is shared with the GPU path.
+"""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from scipy.special import erf
+
+SQRT_HALF = math.sqrt(0.5)
+INV_SQRT_2PI = 1.0 / math.sqrt(2.0 * math.pi)
+
+
+def gelu(x):
+    return 0.5 * x * (1.0 + erf(x * SQRT_HALF))
+
+
+def gelu_grad(x):
+    return 0.5 * (1.0 + erf(x * SQRT_HALF)) + x * INV_SQRT_2PI * np.exp(-0.5 * x * x)
+
+
+def sigmoid(z):
+    return 1.0 / (1.0 + np.exp(-z))
+
+
+def forward(params, X):
+    """params = (W1, b1, W2, b2, W3, b3); returns dict of H1, A1, H2, A2, E."""
+    W1, b1, W2, b2, W3, b3 = params
+    H1 = X @ W1 + b1
+    A1 = gelu(H1)
+    H2 = A1 @ W2 + b2
+    A2 = gelu(H2)
+    E = A2 @ W3 + b3
+    return {"H1": H1, "A1": A1, "H2": H2, "A2": A2, "E": E}
+
+
+def softplus(z):
+    return np.logaddexp(0.0, z)
+
+
+def pair_loss(E, target, alpha, beta, kind="mse"):
+    """Rows p and P + p of E are the two points of pair p.
+
+    Returns (loss, dE, dalpha, dbeta) for loss = mean_p l_p with
+    l_p = (K_hat_p - t_p)^2 ("mse") or the soft-target cross-entropy
+    -t_p log K_hat_p - (1 - t_p) log(1 - K_hat_p) ("bce").
+    """
+    P = target.shape[0]
+    ei, ej = E[:P], E[P:]
+    dot = np.sum(ei * ej, axis=1)
+    z = alpha * dot + beta
+    kh = sigmoid(z)
+    if kind == "bce":
+        loss = float(np.mean(target * softplus(-z) + (1.0 - target) * softplus(z)))
+        ds = (kh - target) / P
+    else:
+        err = kh - target
+        loss = float(np.mean(err * err))
+        ds = (2.0 * err / P) * kh * (1.0 - kh)
+    dE = np.concatenate([(ds * alpha)[:, None] * ej, (ds * alpha)[:, None] * ei])
+    return loss, dE, float(np.sum(ds * dot)), float(np.sum(ds))
+
+
+def backward(params, X, acts, dE):
+    """Gradients (dW1, db1, dW2, db2, dW3, db3) of a loss with dloss/dE = dE."""
+    W1, b1, W2, b2, W3, b3 = params
+    dW3 = acts["A2"].T @ dE
+    db3 = dE.sum(axis=0)
+    dH2 = (dE @ W3.T) * gelu_grad(acts["H2"])
+    dW2 = acts["A1"].T @ dH2
+    db2 = dH2.sum(axis=0)
+    dH1 = (dH2 @ W2.T) * gelu_grad(acts["H1"])
+    dW1 = X.T @ dH1
+    db1 = dH1.sum(axis=0)
+    return dW1, db1, dW2, db2, dW3, db3
+
+
+def adamw_step(w, g, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0):
+    """One AdamW update (decoupled weight decay, bias-corrected moments)."""
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    mhat = m / (1.0 - beta1**step)
+    vhat = v / (1.0 - beta2**step)
+    w = w * (1.0 - lr * weight_decay) - lr * mhat / (np.sqrt(vhat) + eps)
+    return w, m, v
+
+
+def surrogate_gram(E, alpha, beta):
+    """K_hat = sigmoid(alpha E E^T + beta) with the diagonal set to 1."""
+    K = sigmoid(alpha * (E @ E.T) + beta)
+    np.fill_diagonal(K, 1.0)
+    return K
+
+
+def bf16_round(a):
+    """Round float64/float32 values to the nearest bfloat16 (ties to even)."""
+    a32 = np.asarray(a, dtype=np.float32)
+    u = a32.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)

@@ -204,6 +204,46 @@ qsvm_status qsvm_gram_sym(const void* mps, int64_t N, int32_t n_qubits, int32_t 
   return run_gram(mps, N, mps, N, n_qubits, reps, K, ldk, o, true, stream, what);
 }
 
+qsvm_status qsvm_gram_sym_tiles(const void* mps, int64_t N, int32_t n_qubits, int32_t reps, const int32_t* tiles,
+                                int64_t n_tiles, double* K, int64_t ldk, const qsvm_gram_opts* opts, void* stream) {
+  const char* what = "qsvm_gram_sym_tiles";
+  qsvm_status s = check_shape(N, n_qubits, reps, what);
+  if (s != QSVM_OK) return s;
+  if (!mps || !K || !tiles) return fail(QSVM_ERR_INVALID_ARG, "%s: mps, tiles or K is NULL", what);
+  if (ldk < N) return fail(QSVM_ERR_INVALID_ARG, "%s: ldk = %lld < N = %lld", what, (long long)ldk, (long long)N);
+  if (reinterpret_cast<uintptr_t>(mps) % 16 != 0) return fail(QSVM_ERR_INVALID_ARG, "%s: mps is not 16-byte aligned", what);
+  const int64_t T = (N + qsvm::kTile - 1) / qsvm::kTile;
+  if (n_tiles < 0 || n_tiles > T * (T + 1) / 2)
+    return fail(QSVM_ERR_INVALID_ARG, "%s: n_tiles = %lld outside [0, %lld]", what, (long long)n_tiles, (long long)(T * (T + 1) / 2));
+  Opts o;
+  s = read_opts(opts, N, o, what);
+  if (s != QSVM_OK) return s;
+  if (o.row_begin != 0 || o.row_end != N) return fail(QSVM_ERR_INVALID_ARG, "%s: row ranges do not apply to tile lists", what);
+  if (n_tiles == 0) return ok();
+  if (injected_launch_failure()) return fail(QSVM_ERR_HIP, "%s: injected launch failure (QSVM_FAULT_INJECT=launch)", what);
+  qsvm::SweepArgs a{};
+  a.gen_a = a.gen_b = reinterpret_cast<const float4*>(static_cast<const char*>(mps) + qsvm::dense_bytes(N, n_qubits, reps));
+  a.dense_a = a.dense_b = static_cast<const float2*>(mps);
+  a.K = K;
+  a.log_k = o.log_k;
+  a.Na = a.Nb = N;
+  a.ldk = ldk;
+  a.row_begin = 0;
+  a.row_end = N;
+  a.n = n_qubits;
+  a.renorm_every = o.renorm_every;
+  a.sym = 1;
+  a.diag_mode = o.diag_mode;
+  a.tile_row0 = 0;
+  a.tile_rows = int32_t(n_tiles);  // list length
+  a.tiles_b = int32_t(T);
+  a.tile_list = tiles;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = (o.sweep == QSVM_SWEEP_DENSE) ? qsvm::launch_sweep_dense_args(a, reps, st)
+                                                : qsvm::launch_sweep_butterfly_args(a, reps, pick_variant(o, reps, n_qubits), st);
+  return hip_status(e, what);
+}
+
 qsvm_status qsvm_autotune(int32_t reps, int32_t n_qubits, int64_t N, void* stream, int32_t* best_variant,
                           float* variant_ms, int32_t n_variant_ms) {
   const char* what = "qsvm_autotune";

@@ -54,7 +54,7 @@ batched_kernel(const BatchJob* __restrict__ jobs, int32_t n_jobs, int64_t total_
     const uint32_t tile = uint32_t(local / bpt);
     const uint32_t sub = uint32_t(local % bpt);
     int32_t ti, tj;
-    decode_tile(a, tile, ti, tj);
+    decode_tile(a, tile, ti, tj);  // the job table holds no tile lists
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t j0 = int64_t(tj) * kTile;
     if (reps == 2) {

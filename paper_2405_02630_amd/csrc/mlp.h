@@ -1,0 +1,49 @@
+// Launch interface of the surrogate kernels (mlp.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qsvm {
+
+enum GemmEpilogue {
+  EPI_F32 = 0,           // C (float) = acc
+  EPI_BIAS_GELU = 1,     // C (float) = acc + bias (pre-activation); C2 (bf16) = gelu(C)
+  EPI_BIAS = 2,          // C (float) = acc + bias; C2 (bf16) = C
+  EPI_GELU_BWD = 3,      // C2 (bf16) = acc * gelu'(aux)
+  EPI_SIGMOID_GRAM = 4,  // C (double) = sigmoid(ab[0] acc + ab[1]), diagonal 1; tile_max per block
+};
+
+struct GemmArgs {
+  int64_t M, N, K;    // multiples of 64, 64, 32
+  const void* A;      // bf16
+  int64_t lda;
+  const void* B;      // bf16
+  int64_t ldb;
+  void* C;            // float or double (see epilogue)
+  void* C2;           // bf16 output of some epilogues
+  int64_t ldc;        // row stride of C, C2 and aux
+  const float* bias;  // [N]
+  const float* aux;   // pre-activation for EPI_GELU_BWD
+  const float* ab;    // device (alpha, beta) for EPI_SIGMOID_GRAM
+  float* tile_max;    // [M/64][N/64] for EPI_SIGMOID_GRAM
+  int64_t valid;      // rows/cols < valid are real points (EPI_SIGMOID_GRAM)
+};
+
+struct AdamArgs {
+  float lr, beta1, beta2, eps, weight_decay;
+  float bc1, bc2;  // 1 - beta1^t, 1 - beta2^t
+};
+
+hipError_t launch_gemm(int ta, int tb, int epi, const GemmArgs& g, hipStream_t s);
+hipError_t launch_gather(const double* X, int64_t N, int32_t n, const int32_t* idx, int64_t rows, int32_t d_pad,
+                         uint16_t* out, hipStream_t s);
+hipError_t launch_colsum(const uint16_t* A, int64_t rows, int32_t cols, float* out, hipStream_t s);
+hipError_t launch_pair_head(const float* E, int64_t P, int32_t d, const float* target, const float* ab,
+                            int32_t loss_kind, uint16_t* dE16, float* partial, float* out3, hipStream_t s);
+hipError_t launch_adamw(float* w, const float* grad, float* m, float* v, uint16_t* w16, int64_t count,
+                        const AdamArgs& o, hipStream_t s);
+hipError_t launch_flag_tiles(const float* tile_max, int32_t T, float tau, int32_t* list, int32_t* count,
+                             hipStream_t s);
+
+}  // namespace qsvm

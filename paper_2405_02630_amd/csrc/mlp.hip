@@ -1,0 +1,338 @@
+// Kernels of the learned surrogate: an MLP embedding f (BF16 weights and
+// activations, FP32 accumulation on the matrix cores) whose scaled inner
+// products stand in for kernel entries, K_hat(x, y) = sigmoid(alpha <f(x), f(y)> + beta).
+//
+// * bf16_gemm<TA, TB, EPI>: C = op(A) op(B) on v_mfma_f32_32x32x16_bf16.
+//   A 64 x 64 output tile per block of 4 waves (each wave one 32 x 32
+//   accumulator), K in steps of 32 staged through LDS with both operands
+//   stored k-contiguous so every lane reads its 8 k-values as one 16-byte
+//   LDS load.  Dimensions are multiples of the tile (the host pads), so no
+//   bounds checks are needed.  Fused epilogues: FP32 store; bias + GELU
+//   (keeps the pre-activation for the backward pass); bias + FP32/BF16 store;
+//   multiply by GELU'(pre-activation) (backward through the activation);
+//   sigmoid-scaled Gram with per-tile maxima of the off-diagonal entries.
+// * gather_features: FP64 feature rows -> zero-padded BF16 rows.
+// * colsum_bf16: bias gradients (column sums, fixed order).
+// * pair_head: per pair, K_hat, the loss (squared error or soft-target
+//   cross-entropy) and its gradient w.r.t. both embeddings, alpha and beta;
+//   per-pair partial sums reduced in a fixed order.
+// * adamw: decoupled-weight-decay Adam on FP32 master weights, BF16 copy.
+// * flag_tiles: compacts the tiles whose largest off-diagonal K_hat reaches
+//   the fallback threshold.
+//
+// GELU is the exact form x Phi(x) = x (1 + erf(x / sqrt 2)) / 2.
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "mlp.h"
+
+namespace qsvm {
+namespace {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+
+constexpr int BM = 64, BN = 64, BK = 32;
+constexpr int LDS_STRIDE = BK + 8;  // bf16 elements per LDS row (16-byte pad)
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
+
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {  // round to nearest even
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+
+__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+
+__device__ __forceinline__ float gelu_grad(float x) {
+  const float cdf = 0.5f * (1.0f + erff(x * 0.70710678118654752f));
+  const float pdf = 0.39894228040143268f * __expf(-0.5f * x * x);
+  return cdf + x * pdf;
+}
+
+__device__ __forceinline__ float sigmoidf(float z) { return 1.0f / (1.0f + __expf(-z)); }
+
+// op(A)[m][k]: TA = 0 -> A[m*lda + k]; TA = 1 -> A[k*lda + m].
+// op(B)[k][n]: TB = 0 -> B[k*ldb + n]; TB = 1 -> B[n*ldb + k].
+template <int TA, int TB, int EPI>
+__global__ void __launch_bounds__(256) bf16_gemm(GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[BM * LDS_STRIDE];  // [m][k]
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[BN * LDS_STRIDE];  // [n][k]
+  __shared__ float red[4];
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int wave = t >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int64_t m0 = int64_t(blockIdx.y) * BM;
+  const int64_t n0 = int64_t(blockIdx.x) * BN;
+  const uint16_t* __restrict__ A = static_cast<const uint16_t*>(g.A);
+  const uint16_t* __restrict__ B = static_cast<const uint16_t*>(g.B);
+
+  f32x16_t acc;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+
+  for (int64_t k0 = 0; k0 < g.K; k0 += BK) {
+    // ---- global -> LDS (each thread moves 8 bf16 of A and 8 of B) ----
+    if (TA == 0) {
+      const int m = t >> 2, kk = (t & 3) * 8;
+      const uint4 val = *reinterpret_cast<const uint4*>(A + (m0 + m) * g.lda + k0 + kk);
+      *reinterpret_cast<uint4*>(&As[m * LDS_STRIDE + kk]) = val;
+    } else {
+      const int kk = t >> 3, m = (t & 7) * 8;
+      const uint4 val = *reinterpret_cast<const uint4*>(A + (k0 + kk) * g.lda + m0 + m);
+      const uint16_t* e = reinterpret_cast<const uint16_t*>(&val);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) As[(m + q) * LDS_STRIDE + kk] = e[q];
+    }
+    if (TB == 1) {
+      const int n = t >> 2, kk = (t & 3) * 8;
+      const uint4 val = *reinterpret_cast<const uint4*>(B + (n0 + n) * g.ldb + k0 + kk);
+      *reinterpret_cast<uint4*>(&Bs[n * LDS_STRIDE + kk]) = val;
+    } else {
+      const int kk = t >> 3, n = (t & 7) * 8;
+      const uint4 val = *reinterpret_cast<const uint4*>(B + (k0 + kk) * g.ldb + n0 + n);
+      const uint16_t* e = reinterpret_cast<const uint16_t*>(&val);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) Bs[(n + q) * LDS_STRIDE + kk] = e[q];
+    }
+    __syncthreads();
+    // ---- two 32x32x16 MFMAs per wave ----
+    const int i = lane & 31, kh = lane >> 5;
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 16) {
+      const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(&As[(wm * 32 + i) * LDS_STRIDE + ks + kh * 8]);
+      const bf16x8_t b = *reinterpret_cast<const bf16x8_t*>(&Bs[(wn * 32 + i) * LDS_STRIDE + ks + kh * 8]);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+
+  // ---- epilogue: element v of the accumulator is row i, column j ----
+  const int j = lane & 31;
+  float tmax = -INFINITY;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int i = (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+    const int64_t r = m0 + wm * 32 + i;
+    const int64_t c = n0 + wn * 32 + j;
+    const float x = acc[v];
+    if (EPI == EPI_F32) {
+      static_cast<float*>(g.C)[r * g.ldc + c] = x;
+    } else if (EPI == EPI_BIAS_GELU) {
+      const float h = x + g.bias[c];
+      static_cast<float*>(g.C)[r * g.ldc + c] = h;
+      static_cast<uint16_t*>(g.C2)[r * g.ldc + c] = f32_to_bf16(gelu(h));
+    } else if (EPI == EPI_BIAS) {
+      const float h = x + g.bias[c];
+      static_cast<float*>(g.C)[r * g.ldc + c] = h;
+      static_cast<uint16_t*>(g.C2)[r * g.ldc + c] = f32_to_bf16(h);
+    } else if (EPI == EPI_GELU_BWD) {
+      const float d = x * gelu_grad(g.aux[r * g.ldc + c]);
+      static_cast<uint16_t*>(g.C2)[r * g.ldc + c] = f32_to_bf16(d);
+    } else if (EPI == EPI_SIGMOID_GRAM) {
+      if (r < g.valid && c < g.valid) {
+        const float s = sigmoidf(g.ab[0] * x + g.ab[1]);
+        static_cast<double*>(g.C)[r * g.ldc + c] = (r == c) ? 1.0 : double(s);
+        if (r != c) tmax = fmaxf(tmax, s);
+      }
+    }
+  }
+  if (EPI == EPI_SIGMOID_GRAM) {
+    for (int off = 32; off > 0; off >>= 1) tmax = fmaxf(tmax, __shfl_xor(tmax, off, 64));
+    if (lane == 0) red[wave] = tmax;
+    __syncthreads();
+    if (t == 0) {
+      const float mx = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+      g.tile_max[int64_t(blockIdx.y) * gridDim.x + blockIdx.x] = mx;
+    }
+  }
+}
+
+// Indices outside [0, N) (padding rows) give zero rows.
+__global__ void gather_features(const double* __restrict__ X, int64_t N, int32_t n, const int32_t* __restrict__ idx,
+                                int64_t rows, int32_t d_pad, uint16_t* __restrict__ out) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= rows * d_pad) return;
+  const int64_t r = t / d_pad;
+  const int32_t c = int32_t(t % d_pad);
+  const int32_t p = idx[r];
+  out[t] = (c < n && p >= 0 && p < N) ? f32_to_bf16(float(X[int64_t(p) * n + c])) : uint16_t(0);
+}
+
+__global__ void colsum_bf16(const uint16_t* __restrict__ A, int64_t rows, int32_t cols, float* __restrict__ out) {
+  const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  float s = 0.0f;
+  for (int64_t r = 0; r < rows; ++r) s += bf16_to_f32(A[r * cols + c]);
+  out[c] = s;
+}
+
+__device__ __forceinline__ float softplusf(float z) {  // log(1 + e^z), no overflow
+  return fmaxf(z, 0.0f) + log1pf(__expf(-fabsf(z)));
+}
+
+// One wave per pair p: rows p (point i) and P + p (point j) of E.  loss_kind
+// 0: squared error (K_hat - t)^2; 1: cross-entropy with the soft target t,
+// -t log K_hat - (1 - t) log(1 - K_hat), whose gradient in the logit s is
+// K_hat - t (it does not vanish as K_hat -> 0).
+__global__ void __launch_bounds__(256) pair_head(const float* __restrict__ E, int64_t P, int32_t d,
+                                                 const float* __restrict__ target, const float* __restrict__ ab,
+                                                 int32_t loss_kind, uint16_t* __restrict__ dE16,
+                                                 float* __restrict__ partial) {
+  const int64_t p = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (p >= P) return;
+  const float* ei = E + p * d;
+  const float* ej = E + (P + p) * d;
+  float dot = 0.0f;
+  for (int c = lane; c < d; c += 64) dot = fmaf(ei[c], ej[c], dot);
+  for (int off = 32; off > 0; off >>= 1) dot += __shfl_xor(dot, off, 64);
+  const float alpha = ab[0], beta = ab[1];
+  const float z = alpha * dot + beta;
+  const float kh = sigmoidf(z);
+  const float t = target[p];
+  float lp, ds;
+  if (loss_kind == 1) {
+    lp = t * softplusf(-z) + (1.0f - t) * softplusf(z);
+    ds = (kh - t) / float(P);
+  } else {
+    const float err = kh - t;
+    lp = err * err;
+    ds = (2.0f * err / float(P)) * kh * (1.0f - kh);
+  }
+  for (int c = lane; c < d; c += 64) {
+    dE16[p * d + c] = f32_to_bf16(ds * alpha * ej[c]);
+    dE16[(P + p) * d + c] = f32_to_bf16(ds * alpha * ei[c]);
+  }
+  if (lane == 0) {
+    partial[3 * p + 0] = lp;
+    partial[3 * p + 1] = ds * dot;
+    partial[3 * p + 2] = ds;
+  }
+}
+
+// out[0] = mean per-pair loss, out[1] = d loss / d alpha, out[2] = d loss / d beta.
+__global__ void __launch_bounds__(256) reduce_partials(const float* __restrict__ partial, int64_t P, float* __restrict__ out) {
+  __shared__ double s[3][256];
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  for (int64_t p = threadIdx.x; p < P; p += blockDim.x) {
+    a0 += partial[3 * p];
+    a1 += partial[3 * p + 1];
+    a2 += partial[3 * p + 2];
+  }
+  s[0][threadIdx.x] = a0;
+  s[1][threadIdx.x] = a1;
+  s[2][threadIdx.x] = a2;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w)
+      for (int q = 0; q < 3; ++q) s[q][threadIdx.x] += s[q][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = float(s[0][0] / double(P));
+    out[1] = float(s[1][0]);
+    out[2] = float(s[2][0]);
+  }
+}
+
+__global__ void adamw(float* __restrict__ w, const float* __restrict__ grad, float* __restrict__ m,
+                      float* __restrict__ v, uint16_t* __restrict__ w16, int64_t count, AdamArgs o) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  const float gr = grad[t];
+  const float mt = o.beta1 * m[t] + (1.0f - o.beta1) * gr;
+  const float vt = o.beta2 * v[t] + (1.0f - o.beta2) * gr * gr;
+  m[t] = mt;
+  v[t] = vt;
+  const float mhat = mt / o.bc1;
+  const float vhat = vt / o.bc2;
+  float wt = w[t] * (1.0f - o.lr * o.weight_decay);
+  wt -= o.lr * mhat / (sqrtf(vhat) + o.eps);
+  w[t] = wt;
+  if (w16) w16[t] = f32_to_bf16(wt);
+}
+
+__global__ void flag_tiles(const float* __restrict__ tile_max, int32_t T, float tau, int32_t* __restrict__ list,
+                           int32_t* __restrict__ count) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= int64_t(T) * T) return;
+  const int32_t ti = int32_t(t / T), tj = int32_t(t % T);
+  if (ti > tj) return;
+  if (tile_max[t] >= tau) {
+    const int32_t slot = atomicAdd(count, 1);
+    list[2 * slot] = ti;
+    list[2 * slot + 1] = tj;
+  }
+}
+
+__global__ void zero_int(int32_t* p) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
+}
+
+template <int TA, int TB, int EPI>
+hipError_t launch_gemm_t(const GemmArgs& g, hipStream_t s) {
+  const dim3 grid(unsigned(g.N / BN), unsigned(g.M / BM));
+  hipLaunchKernelGGL((bf16_gemm<TA, TB, EPI>), grid, dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_gemm(int ta, int tb, int epi, const GemmArgs& g, hipStream_t s) {
+  switch (ta * 100 + tb * 10 + epi) {
+    case 0 * 100 + 0 * 10 + EPI_BIAS_GELU: return launch_gemm_t<0, 0, EPI_BIAS_GELU>(g, s);
+    case 0 * 100 + 0 * 10 + EPI_BIAS: return launch_gemm_t<0, 0, EPI_BIAS>(g, s);
+    case 0 * 100 + 0 * 10 + EPI_F32: return launch_gemm_t<0, 0, EPI_F32>(g, s);
+    case 1 * 100 + 0 * 10 + EPI_F32: return launch_gemm_t<1, 0, EPI_F32>(g, s);
+    case 0 * 100 + 1 * 10 + EPI_GELU_BWD: return launch_gemm_t<0, 1, EPI_GELU_BWD>(g, s);
+    case 0 * 100 + 1 * 10 + EPI_F32: return launch_gemm_t<0, 1, EPI_F32>(g, s);
+    case 0 * 100 + 1 * 10 + EPI_SIGMOID_GRAM: return launch_gemm_t<0, 1, EPI_SIGMOID_GRAM>(g, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_gather(const double* X, int64_t N, int32_t n, const int32_t* idx, int64_t rows, int32_t d_pad,
+                         uint16_t* out, hipStream_t s) {
+  const int64_t total = rows * d_pad;
+  hipLaunchKernelGGL(gather_features, dim3(unsigned((total + 255) / 256)), dim3(256), 0, s, X, N, n, idx, rows, d_pad, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_colsum(const uint16_t* A, int64_t rows, int32_t cols, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(colsum_bf16, dim3(unsigned((cols + 255) / 256)), dim3(256), 0, s, A, rows, cols, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_head(const float* E, int64_t P, int32_t d, const float* target, const float* ab,
+                            int32_t loss_kind, uint16_t* dE16, float* partial, float* out3, hipStream_t s) {
+  const int64_t threads = P * 64;
+  hipLaunchKernelGGL(pair_head, dim3(unsigned((threads + 255) / 256)), dim3(256), 0, s, E, P, d, target, ab,
+                     loss_kind, dE16, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, s, partial, P, out3);
+  return hipGetLastError();
+}
+
+hipError_t launch_adamw(float* w, const float* grad, float* m, float* v, uint16_t* w16, int64_t count,
+                        const AdamArgs& o, hipStream_t s) {
+  hipLaunchKernelGGL(adamw, dim3(unsigned((count + 255) / 256)), dim3(256), 0, s, w, grad, m, v, w16, count, o);
+  return hipGetLastError();
+}
+
+hipError_t launch_flag_tiles(const float* tile_max, int32_t T, float tau, int32_t* list, int32_t* count,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(zero_int, dim3(1), dim3(64), 0, s, count);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t total = int64_t(T) * T;
+  hipLaunchKernelGGL(flag_tiles, dim3(unsigned((total + 255) / 256)), dim3(256), 0, s, tile_max, T, tau, list, count);
+  return hipGetLastError();
+}
+
+}  // namespace qsvm

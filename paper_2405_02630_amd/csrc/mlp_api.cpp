@@ -1,0 +1,207 @@
+// C-ABI entry points of the learned surrogate and of the tile-list exact
+// fallback.  Shapes are validated on the host before any launch; the MLP's
+// matrix dimensions must be multiples of the GEMM tile (64 for rows and all
+// widths, the padded input width included), which the caller ensures by zero
+// padding.
+
+#include <stdio.h>
+
+#include "../../include/qsvm.h"
+#include "mlp.h"
+#include "qsvm_internal.h"
+#include "sweep_common.h"
+
+namespace qsvm {
+qsvm_status api_fail(qsvm_status s, const char* msg);
+qsvm_status api_ok();
+qsvm_status api_hip(hipError_t e, const char* what);
+bool api_injected_failure();
+}  // namespace qsvm
+
+namespace {
+
+using qsvm::api_fail;
+using qsvm::api_hip;
+using qsvm::api_ok;
+
+qsvm_status check_net(const qsvm_mlp* net, const char* what) {
+  char msg[256];
+  if (!net || !net->W1 || !net->W2 || !net->W3 || !net->b1 || !net->b2 || !net->b3) {
+    snprintf(msg, sizeof msg, "%s: network or one of its weights is NULL", what);
+    return api_fail(QSVM_ERR_INVALID_ARG, msg);
+  }
+  if (net->d_in < 64 || net->d_in % 64 || net->d_h1 < 64 || net->d_h1 % 64 || net->d_h2 < 64 ||
+      net->d_h2 % 64 || net->d_out < 64 || net->d_out % 64) {
+    snprintf(msg, sizeof msg, "%s: widths (%d, %d, %d, %d) must all be positive multiples of 64", what,
+             net->d_in, net->d_h1, net->d_h2, net->d_out);
+    return api_fail(QSVM_ERR_INVALID_ARG, msg);
+  }
+  return QSVM_OK;
+}
+
+qsvm_status check_rows(int64_t rows, const char* what) {
+  char msg[160];
+  if (rows < 64 || rows % 64 || rows > (int64_t(1) << 26)) {
+    snprintf(msg, sizeof msg, "%s: rows = %lld must be a positive multiple of 64 (<= 2^26)", what, (long long)rows);
+    return api_fail(QSVM_ERR_INVALID_ARG, msg);
+  }
+  return QSVM_OK;
+}
+
+qsvm_status injected(const char* what) {
+  char msg[160];
+  snprintf(msg, sizeof msg, "%s: injected launch failure (QSVM_FAULT_INJECT=launch)", what);
+  return api_fail(QSVM_ERR_HIP, msg);
+}
+
+qsvm::GemmArgs gemm(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, const void* B, int64_t ldb,
+                    void* C, void* C2, int64_t ldc, const float* bias = nullptr, const float* aux = nullptr) {
+  qsvm::GemmArgs g{};
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.A = A;
+  g.lda = lda;
+  g.B = B;
+  g.ldb = ldb;
+  g.C = C;
+  g.C2 = C2;
+  g.ldc = ldc;
+  g.bias = bias;
+  g.aux = aux;
+  return g;
+}
+
+}  // namespace
+
+extern "C" {
+
+qsvm_status qsvm_gather_features(const double* X, int64_t N, int32_t n_qubits, const int32_t* idx, int64_t rows,
+                                 int32_t d_pad, void* out, void* stream) {
+  const char* what = "qsvm_gather_features";
+  if (!X || !idx || !out) return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_gather_features: NULL pointer");
+  if (N < 1 || n_qubits < 1 || rows < 1 || d_pad < n_qubits)
+    return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_gather_features: need N, n_qubits, rows >= 1 and d_pad >= n_qubits");
+  if (qsvm::api_injected_failure()) return injected(what);
+  return api_hip(qsvm::launch_gather(X, N, n_qubits, idx, rows, d_pad, static_cast<uint16_t*>(out),
+                                     static_cast<hipStream_t>(stream)),
+                 what);
+}
+
+qsvm_status qsvm_mlp_forward(const qsvm_mlp* net, const void* X16, int64_t rows, const qsvm_mlp_acts* acts,
+                             void* stream) {
+  const char* what = "qsvm_mlp_forward";
+  qsvm_status s = check_net(net, what);
+  if (s != QSVM_OK) return s;
+  if ((s = check_rows(rows, what)) != QSVM_OK) return s;
+  if (!X16 || !acts || !acts->H1 || !acts->A1 || !acts->H2 || !acts->A2 || !acts->E || !acts->E16)
+    return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_mlp_forward: input or an activation buffer is NULL");
+  if (qsvm::api_injected_failure()) return injected(what);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = qsvm::launch_gemm(0, 0, qsvm::EPI_BIAS_GELU,
+                                   gemm(rows, net->d_h1, net->d_in, X16, net->d_in, net->W1, net->d_h1, acts->H1,
+                                        acts->A1, net->d_h1, net->b1),
+                                   st);
+  if (e == hipSuccess)
+    e = qsvm::launch_gemm(0, 0, qsvm::EPI_BIAS_GELU,
+                          gemm(rows, net->d_h2, net->d_h1, acts->A1, net->d_h1, net->W2, net->d_h2, acts->H2, acts->A2,
+                               net->d_h2, net->b2),
+                          st);
+  if (e == hipSuccess)
+    e = qsvm::launch_gemm(0, 0, qsvm::EPI_BIAS,
+                          gemm(rows, net->d_out, net->d_h2, acts->A2, net->d_h2, net->W3, net->d_out, acts->E,
+                               acts->E16, net->d_out, net->b3),
+                          st);
+  return api_hip(e, what);
+}
+
+qsvm_status qsvm_pair_head(const float* E, int64_t pairs, int32_t d, const float* target, const float* alpha_beta,
+                           int32_t loss_kind, void* dE16, float* partial, float* out3, void* stream) {
+  const char* what = "qsvm_pair_head";
+  if (!E || !target || !alpha_beta || !dE16 || !partial || !out3)
+    return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_pair_head: NULL pointer");
+  if (pairs < 1 || d < 1) return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_pair_head: pairs and d must be >= 1");
+  if (loss_kind != 0 && loss_kind != 1) return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_pair_head: loss_kind must be 0 or 1");
+  if (qsvm::api_injected_failure()) return injected(what);
+  return api_hip(qsvm::launch_pair_head(E, pairs, d, target, alpha_beta, loss_kind, static_cast<uint16_t*>(dE16), partial,
+                                        out3, static_cast<hipStream_t>(stream)),
+                 what);
+}
+
+qsvm_status qsvm_mlp_backward(const qsvm_mlp* net, const void* X16, const qsvm_mlp_acts* acts, const void* dE16,
+                              int64_t rows, const qsvm_mlp_grads* g, void* stream) {
+  const char* what = "qsvm_mlp_backward";
+  qsvm_status s = check_net(net, what);
+  if (s != QSVM_OK) return s;
+  if ((s = check_rows(rows, what)) != QSVM_OK) return s;
+  if (!X16 || !acts || !acts->H1 || !acts->A1 || !acts->H2 || !acts->A2 || !dE16 || !g || !g->dW1 || !g->db1 ||
+      !g->dW2 || !g->db2 || !g->dW3 || !g->db3 || !g->dH1 || !g->dH2)
+    return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_mlp_backward: NULL pointer");
+  if (qsvm::api_injected_failure()) return injected(what);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t din = net->d_in, h1 = net->d_h1, h2 = net->d_h2, dout = net->d_out;
+  // dW3 = A2^T dE ; db3 = colsum(dE)
+  hipError_t e = qsvm::launch_gemm(1, 0, qsvm::EPI_F32, gemm(h2, dout, rows, acts->A2, h2, dE16, dout, g->dW3, nullptr, dout), st);
+  if (e == hipSuccess) e = qsvm::launch_colsum(static_cast<const uint16_t*>(dE16), rows, int32_t(dout), g->db3, st);
+  // dH2 = (dE W3^T) * gelu'(H2)
+  if (e == hipSuccess)
+    e = qsvm::launch_gemm(0, 1, qsvm::EPI_GELU_BWD,
+                          gemm(rows, h2, dout, dE16, dout, net->W3, dout, nullptr, g->dH2, h2, nullptr, acts->H2), st);
+  // dW2 = A1^T dH2 ; db2 = colsum(dH2)
+  if (e == hipSuccess) e = qsvm::launch_gemm(1, 0, qsvm::EPI_F32, gemm(h1, h2, rows, acts->A1, h1, g->dH2, h2, g->dW2, nullptr, h2), st);
+  if (e == hipSuccess) e = qsvm::launch_colsum(static_cast<const uint16_t*>(g->dH2), rows, int32_t(h2), g->db2, st);
+  // dH1 = (dH2 W2^T) * gelu'(H1)
+  if (e == hipSuccess)
+    e = qsvm::launch_gemm(0, 1, qsvm::EPI_GELU_BWD,
+                          gemm(rows, h1, h2, g->dH2, h2, net->W2, h2, nullptr, g->dH1, h1, nullptr, acts->H1), st);
+  // dW1 = X^T dH1 ; db1 = colsum(dH1)
+  if (e == hipSuccess) e = qsvm::launch_gemm(1, 0, qsvm::EPI_F32, gemm(din, h1, rows, X16, din, g->dH1, h1, g->dW1, nullptr, h1), st);
+  if (e == hipSuccess) e = qsvm::launch_colsum(static_cast<const uint16_t*>(g->dH1), rows, int32_t(h1), g->db1, st);
+  return api_hip(e, what);
+}
+
+qsvm_status qsvm_adamw(float* w, const float* grad, float* m, float* v, void* w16, int64_t count, float lr,
+                       float beta1, float beta2, float eps, float weight_decay, int32_t step, void* stream) {
+  const char* what = "qsvm_adamw";
+  if (!w || !grad || !m || !v) return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_adamw: NULL pointer");
+  if (count < 1 || step < 1 || !(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) ||
+      !(eps > 0.0f))
+    return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_adamw: need count, step >= 1, lr >= 0, betas in [0, 1), eps > 0");
+  if (qsvm::api_injected_failure()) return injected(what);
+  qsvm::AdamArgs o{};
+  o.lr = lr;
+  o.beta1 = beta1;
+  o.beta2 = beta2;
+  o.eps = eps;
+  o.weight_decay = weight_decay;
+  o.bc1 = 1.0f - powf(beta1, float(step));
+  o.bc2 = 1.0f - powf(beta2, float(step));
+  return api_hip(qsvm::launch_adamw(w, grad, m, v, static_cast<uint16_t*>(w16), count, o, static_cast<hipStream_t>(stream)),
+                 what);
+}
+
+qsvm_status qsvm_surrogate_gram(const void* E16, int64_t N, int64_t N_pad, int32_t d, const float* alpha_beta,
+                                double* K, int64_t ldk, float* tile_max, void* stream) {
+  const char* what = "qsvm_surrogate_gram";
+  if (!E16 || !alpha_beta || !K || !tile_max) return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_surrogate_gram: NULL pointer");
+  if (N < 1 || N_pad < N || N_pad % 64 || N_pad - N >= 64 || d < 32 || d % 32 || ldk < N)
+    return api_fail(QSVM_ERR_INVALID_ARG,
+                    "qsvm_surrogate_gram: need 1 <= N <= N_pad < N + 64, N_pad % 64 == 0, d % 32 == 0, ldk >= N");
+  if (qsvm::api_injected_failure()) return injected(what);
+  qsvm::GemmArgs g = gemm(N_pad, N_pad, d, E16, d, E16, d, K, nullptr, ldk);
+  g.ab = alpha_beta;
+  g.tile_max = tile_max;
+  g.valid = N;
+  return api_hip(qsvm::launch_gemm(0, 1, qsvm::EPI_SIGMOID_GRAM, g, static_cast<hipStream_t>(stream)), what);
+}
+
+qsvm_status qsvm_flag_tiles(const float* tile_max, int32_t T, float tau, int32_t* tile_list, int32_t* count,
+                            void* stream) {
+  const char* what = "qsvm_flag_tiles";
+  if (!tile_max || !tile_list || !count) return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_flag_tiles: NULL pointer");
+  if (T < 1 || T > 65536) return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_flag_tiles: T outside [1, 65536]");
+  if (qsvm::api_injected_failure()) return injected(what);
+  return api_hip(qsvm::launch_flag_tiles(tile_max, T, tau, tile_list, count, static_cast<hipStream_t>(stream)), what);
+}
+
+}  // extern "C"

@@ -17,7 +17,7 @@ sweep_butterfly_kernel(SweepArgs a) {
   const uint32_t tile = L / uint32_t(a.blocks_per_tile);
   const uint32_t sub = L % uint32_t(a.blocks_per_tile);
   int32_t ti, tj;
-  decode_tile(a, tile, ti, tj);
+  if (!decode_tile(a, tile, ti, tj)) return;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t i0 = int64_t(ti) * kTile + (int64_t(sub) * 4 + wave) * PI;  // wave-uniform
   butterfly_item<R, PI>(a, i0, int64_t(tj) * kTile);
@@ -27,10 +27,11 @@ template <int R, int PI, int W>
 hipError_t launch_pi(const SweepArgs& a0, hipStream_t stream) {
   SweepArgs a = a0;
   a.blocks_per_tile = kTile / (4 * PI);
-  const int64_t tiles = a.sym ? (int64_t(a.tile_rows) * a.tiles_b -
-                                 (int64_t(a.tile_rows) * (a.tile_rows - 1)) / 2 -
-                                 int64_t(a.tile_rows) * a.tile_row0)
-                              : int64_t(a.tile_rows) * a.tiles_b;
+  const int64_t tiles = a.tile_list ? int64_t(a.tile_rows)  // list length
+                        : a.sym ? (int64_t(a.tile_rows) * a.tiles_b -
+                                   (int64_t(a.tile_rows) * (a.tile_rows - 1)) / 2 -
+                                   int64_t(a.tile_rows) * a.tile_row0)
+                                : int64_t(a.tile_rows) * a.tiles_b;
   const int64_t blocks = tiles * a.blocks_per_tile;
   if (blocks <= 0) return hipSuccess;
   if (blocks > (int64_t(1) << 31) - 8) return hipErrorInvalidValue;

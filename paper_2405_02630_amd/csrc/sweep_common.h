@@ -30,6 +30,7 @@ struct SweepArgs {
   int32_t tiles_b;       // tile columns (ceil(Nb / 64))
   int32_t blocks_per_tile;
   uint32_t num_blocks;   // logical blocks (before padding to a multiple of 8)
+  const int32_t* tile_list;  // optional device list of (ti, tj) tiles (symmetric only)
 };
 
 // Map the hardware block index to a logical block so that the blocks of one
@@ -43,12 +44,19 @@ __device__ __forceinline__ uint32_t xcd_logical_block() {
 }
 
 // Tile (row, column) of logical tile u.  Symmetric: upper triangle
-// (row <= column) of tile rows [tile_row0, tile_row0 + tile_rows), row-major.
-__device__ __forceinline__ void decode_tile(const SweepArgs& a, uint32_t u, int32_t& ti, int32_t& tj) {
+// (row <= column) of tile rows [tile_row0, tile_row0 + tile_rows), row-major;
+// or entry u of the tile list, when one is given.  Returns false for a list
+// entry outside 0 <= ti <= tj < tiles_b (the work item is then skipped).
+__device__ __forceinline__ bool decode_tile(const SweepArgs& a, uint32_t u, int32_t& ti, int32_t& tj) {
+  if (a.tile_list) {
+    ti = a.tile_list[2 * int64_t(u)];
+    tj = a.tile_list[2 * int64_t(u) + 1];
+    return ti >= 0 && ti <= tj && tj < a.tiles_b;
+  }
   if (!a.sym) {
     ti = a.tile_row0 + int32_t(u / uint32_t(a.tiles_b));
     tj = int32_t(u % uint32_t(a.tiles_b));
-    return;
+    return true;
   }
   const int64_t T = a.tiles_b;
   // offset(t) = t*T - t*(t-1)/2 tiles precede tile row t
@@ -61,6 +69,7 @@ __device__ __forceinline__ void decode_tile(const SweepArgs& a, uint32_t u, int3
   while (t > 0 && offset(t) > U) --t;
   ti = int32_t(t);
   tj = int32_t(t + (U - offset(t)));
+  return true;
 }
 
 // Finalize one pair: amp = s * 2^(e2/2) where |s|^2 = s2 and e2 = 2*(log2

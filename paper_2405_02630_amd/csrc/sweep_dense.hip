@@ -49,7 +49,7 @@ sweep_dense_kernel(SweepArgs a) {
   const uint32_t tile = L / uint32_t(a.blocks_per_tile);
   const uint32_t sub = L % uint32_t(a.blocks_per_tile);
   int32_t ti, tj;
-  decode_tile(a, tile, ti, tj);
+  if (!decode_tile(a, tile, ti, tj)) return;
 
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -157,10 +157,11 @@ template <int R>
 hipError_t launch_r(const SweepArgs& a0, hipStream_t stream) {
   SweepArgs a = a0;
   a.blocks_per_tile = kTile / 4;
-  const int64_t tiles = a.sym ? (int64_t(a.tile_rows) * a.tiles_b -
-                                 (int64_t(a.tile_rows) * (a.tile_rows - 1)) / 2 -
-                                 int64_t(a.tile_rows) * a.tile_row0)
-                              : int64_t(a.tile_rows) * a.tiles_b;
+  const int64_t tiles = a.tile_list ? int64_t(a.tile_rows)  // list length
+                        : a.sym ? (int64_t(a.tile_rows) * a.tiles_b -
+                                   (int64_t(a.tile_rows) * (a.tile_rows - 1)) / 2 -
+                                   int64_t(a.tile_rows) * a.tile_row0)
+                                : int64_t(a.tile_rows) * a.tiles_b;
   const int64_t blocks = tiles * a.blocks_per_tile;
   if (blocks <= 0) return hipSuccess;
   if (blocks > (int64_t(1) << 31) - 8) return hipErrorInvalidValue;

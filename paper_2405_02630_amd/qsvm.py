@@ -67,6 +67,32 @@ class BatchOpts(ctypes.Structure):
     ]
 
 
+class Mlp(ctypes.Structure):
+    """Mirror of qsvm_mlp."""
+
+    _fields_ = [
+        ("d_in", ctypes.c_int32), ("d_h1", ctypes.c_int32), ("d_h2", ctypes.c_int32), ("d_out", ctypes.c_int32),
+        ("W1", ctypes.c_void_p), ("b1", ctypes.c_void_p),
+        ("W2", ctypes.c_void_p), ("b2", ctypes.c_void_p),
+        ("W3", ctypes.c_void_p), ("b3", ctypes.c_void_p),
+    ]
+
+
+class MlpActs(ctypes.Structure):
+    """Mirror of qsvm_mlp_acts."""
+
+    _fields_ = [("H1", ctypes.c_void_p), ("A1", ctypes.c_void_p), ("H2", ctypes.c_void_p),
+                ("A2", ctypes.c_void_p), ("E", ctypes.c_void_p), ("E16", ctypes.c_void_p)]
+
+
+class MlpGrads(ctypes.Structure):
+    """Mirror of qsvm_mlp_grads."""
+
+    _fields_ = [("dW1", ctypes.c_void_p), ("db1", ctypes.c_void_p), ("dW2", ctypes.c_void_p),
+                ("db2", ctypes.c_void_p), ("dW3", ctypes.c_void_p), ("db3", ctypes.c_void_p),
+                ("dH1", ctypes.c_void_p), ("dH2", ctypes.c_void_p)]
+
+
 class QsvmError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"{message} (status {status})")
@@ -110,6 +136,24 @@ def load_library(path: str = LIB_PATH):
     lib.qsvm_batch_plan_destroy.restype = i32
     lib.qsvm_batch_plan_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.qsvm_batch_plan_info.restype = i32
+    P = ctypes.POINTER
+    f32 = ctypes.c_float
+    lib.qsvm_gram_sym_tiles.argtypes = [vp, i64, i32, i32, vp, i64, vp, i64, P(GramOpts), vp]
+    lib.qsvm_gram_sym_tiles.restype = i32
+    lib.qsvm_gather_features.argtypes = [vp, i64, i32, vp, i64, i32, vp, vp]
+    lib.qsvm_gather_features.restype = i32
+    lib.qsvm_mlp_forward.argtypes = [P(Mlp), vp, i64, P(MlpActs), vp]
+    lib.qsvm_mlp_forward.restype = i32
+    lib.qsvm_pair_head.argtypes = [vp, i64, i32, vp, vp, i32, vp, vp, vp, vp]
+    lib.qsvm_pair_head.restype = i32
+    lib.qsvm_mlp_backward.argtypes = [P(Mlp), vp, P(MlpActs), vp, i64, P(MlpGrads), vp]
+    lib.qsvm_mlp_backward.restype = i32
+    lib.qsvm_adamw.argtypes = [vp, vp, vp, vp, vp, i64, f32, f32, f32, f32, f32, i32, vp]
+    lib.qsvm_adamw.restype = i32
+    lib.qsvm_surrogate_gram.argtypes = [vp, i64, i64, i32, vp, vp, i64, vp, vp]
+    lib.qsvm_surrogate_gram.restype = i32
+    lib.qsvm_flag_tiles.argtypes = [vp, i32, f32, vp, vp, vp]
+    lib.qsvm_flag_tiles.restype = i32
     lib.qsvm_autotune.argtypes = [i32, i32, i64, vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float), i32]
     lib.qsvm_autotune.restype = i32
     lib.qsvm_get_tuned_variant.argtypes = [i32, i32]
@@ -303,3 +347,61 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+
+
+# --------------------------------------------------------------------------
+# Surrogate building blocks (tensors are CUDA; bf16 buffers are torch.bfloat16)
+# --------------------------------------------------------------------------
+
+def _p(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def qsvm_gram_sym_tiles(mps: MPS, tiles, n_tiles: int, K, *, log_k=None, renorm_every: int = 0,
+                        sweep: int = SWEEP_AUTO, diag_mode: int = 0, variant: int = 0, stream=None):
+    """Exact symmetric Gram on a device list of (ti, tj) tiles (int32 tensor)."""
+    o = _opts(renorm_every, sweep, diag_mode, None, log_k, variant)
+    _check(load_library().qsvm_gram_sym_tiles(
+        _device_ptr(mps.buf, "mps"), mps.N, mps.n, mps.reps, _p(tiles), n_tiles, _p(K), K.stride(0),
+        ctypes.byref(o), _stream_ptr(stream)))
+    return K
+
+
+def qsvm_gather_features(X, idx, d_pad: int, out, stream=None):
+    _check(load_library().qsvm_gather_features(
+        _p(X), X.shape[0], X.shape[1], _p(idx), idx.shape[0], d_pad, _p(out), _stream_ptr(stream)))
+    return out
+
+
+def qsvm_mlp_forward(net: Mlp, X16, rows: int, acts: MlpActs, stream=None):
+    _check(load_library().qsvm_mlp_forward(ctypes.byref(net), _p(X16), rows, ctypes.byref(acts), _stream_ptr(stream)))
+
+
+LOSS_MSE = 0
+LOSS_BCE = 1
+
+
+def qsvm_pair_head(E, pairs: int, d: int, target, alpha_beta, dE16, partial, out3, loss_kind: int = LOSS_BCE,
+                   stream=None):
+    _check(load_library().qsvm_pair_head(_p(E), pairs, d, _p(target), _p(alpha_beta), loss_kind, _p(dE16),
+                                         _p(partial), _p(out3), _stream_ptr(stream)))
+
+
+def qsvm_mlp_backward(net: Mlp, X16, acts: MlpActs, dE16, rows: int, grads: MlpGrads, stream=None):
+    _check(load_library().qsvm_mlp_backward(ctypes.byref(net), _p(X16), ctypes.byref(acts), _p(dE16), rows,
+                                            ctypes.byref(grads), _stream_ptr(stream)))
+
+
+def qsvm_adamw(w, grad, m, v, w16, lr, beta1, beta2, eps, weight_decay, step, stream=None):
+    _check(load_library().qsvm_adamw(_p(w), _p(grad), _p(m), _p(v), _p(w16), w.numel(), lr, beta1, beta2, eps,
+                                     weight_decay, step, _stream_ptr(stream)))
+
+
+def qsvm_surrogate_gram(E16, N: int, alpha_beta, K, tile_max, stream=None):
+    _check(load_library().qsvm_surrogate_gram(_p(E16), N, E16.shape[0], E16.shape[1], _p(alpha_beta), _p(K),
+                                              K.stride(0), _p(tile_max), _stream_ptr(stream)))
+    return K
+
+
+def qsvm_flag_tiles(tile_max, T: int, tau: float, tile_list, count, stream=None):
+    _check(load_library().qsvm_flag_tiles(_p(tile_max), T, tau, _p(tile_list), _p(count), _stream_ptr(stream)))

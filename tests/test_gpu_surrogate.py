@@ -1,0 +1,283 @@
+"""GPU: the surrogate's kernels against the FP64 reference (oracle/mlp.py).
+
+The kernels round to BF16 where the design says (inputs, weights, hidden
+activations, back-propagated gradients) and accumulate in FP32.  Each check
+compares with the FP64 reference evaluated on the same BF16-rounded operands,
+with the kernels' intermediate BF16 roundings emulated (tight bar), and where
+noted with the unrounded FP64 reference (loose bar, set by BF16's 2^-9 unit
+roundoff compounded over three layers).
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mlp as ref
+from oracle import statevector
+from paper_2405_02630_amd import qsvm, synth
+
+from gpu_helpers import K_ABS_TOL, encode, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+DIMS = (128, 64, 128, 64)  # d_in, d_h1, d_h2, d_out (multiples of 64)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    return require_gpu()
+
+
+def _nrel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _bf16_dev(x):
+    import torch
+
+    return torch.as_tensor(np.asarray(x, np.float32)).to(torch.bfloat16).to("cuda:0")
+
+
+def _f32_dev(x):
+    import torch
+
+    return torch.as_tensor(np.asarray(x, np.float32), device="cuda:0")
+
+
+def _host(t):
+    import torch
+
+    return t.to(torch.float64).cpu().numpy()
+
+
+def _setup(seed=0, rows=128):
+    import torch
+
+    rng = np.random.default_rng(seed)
+    d0, d1, d2, d3 = DIMS
+    W = [ref.bf16_round(rng.normal(0, math.sqrt(2 / d0), (d0, d1))), rng.normal(0, 0.1, d1),
+         ref.bf16_round(rng.normal(0, math.sqrt(2 / d1), (d1, d2))), rng.normal(0, 0.1, d2),
+         ref.bf16_round(rng.normal(0, math.sqrt(1 / d2), (d2, d3))), rng.normal(0, 0.1, d3)]
+    W[1], W[3], W[5] = (np.float32(w).astype(np.float64) for w in (W[1], W[3], W[5]))
+    X = ref.bf16_round(rng.normal(0, 1, (rows, d0)))
+    dev = {k: v for k, v in zip(["W1", "b1", "W2", "b2", "W3", "b3"],
+                                [_bf16_dev(W[0]), _f32_dev(W[1]), _bf16_dev(W[2]), _f32_dev(W[3]),
+                                 _bf16_dev(W[4]), _f32_dev(W[5])])}
+    net = qsvm.Mlp(d0, d1, d2, d3, dev["W1"].data_ptr(), dev["b1"].data_ptr(), dev["W2"].data_ptr(),
+                   dev["b2"].data_ptr(), dev["W3"].data_ptr(), dev["b3"].data_ptr())
+    f32, b16 = torch.float32, torch.bfloat16
+    bufs = {
+        "X16": _bf16_dev(X),
+        "H1": torch.empty((rows, d1), dtype=f32, device="cuda:0"),
+        "A1": torch.empty((rows, d1), dtype=b16, device="cuda:0"),
+        "H2": torch.empty((rows, d2), dtype=f32, device="cuda:0"),
+        "A2": torch.empty((rows, d2), dtype=b16, device="cuda:0"),
+        "E": torch.empty((rows, d3), dtype=f32, device="cuda:0"),
+        "E16": torch.empty((rows, d3), dtype=b16, device="cuda:0"),
+    }
+    acts = qsvm.MlpActs(*(bufs[k].data_ptr() for k in ("H1", "A1", "H2", "A2", "E", "E16")))
+    return W, X, dev, net, bufs, acts
+
+
+def _emulated_forward(W, X):
+    H1 = X @ W[0] + W[1]
+    A1 = ref.bf16_round(ref.gelu(H1))
+    H2 = A1 @ W[2] + W[3]
+    A2 = ref.bf16_round(ref.gelu(H2))
+    E = A2 @ W[4] + W[5]
+    return H1, A1, H2, A2, E
+
+
+def test_mlp_forward_matches_reference():
+    import torch
+
+    W, X, dev, net, bufs, acts = _setup(0)
+    qsvm.qsvm_mlp_forward(net, bufs["X16"], X.shape[0], acts)
+    torch.cuda.synchronize()
+    H1, A1, H2, A2, E = _emulated_forward(W, X)
+    assert _nrel(_host(bufs["H1"]), H1) < 1e-5  # first layer: exact BF16 products, FP32 sums
+    assert _nrel(_host(bufs["A1"]), A1) < 4e-3  # one BF16 rounding of the activation
+    assert _nrel(_host(bufs["H2"]), H2) < 5e-3
+    assert _nrel(_host(bufs["E"]), E) < 1e-2
+    full = ref.forward(W, X)["E"]  # no intermediate rounding at all
+    assert _nrel(_host(bufs["E"]), full) < 2e-2
+    assert np.array_equal(_host(bufs["E16"]), ref.bf16_round(_host(bufs["E"])))
+
+
+@pytest.mark.parametrize("kind", [qsvm.LOSS_MSE, qsvm.LOSS_BCE], ids=["mse", "bce"])
+def test_pair_head_and_backward_match_reference(kind):
+    import torch
+
+    W, X, dev, net, bufs, acts = _setup(1)
+    rows = X.shape[0]
+    P = rows // 2
+    rng = np.random.default_rng(7)
+    target = rng.uniform(0, 1, P).astype(np.float32).astype(np.float64)
+    ab = _f32_dev([0.05, -0.3])
+    qsvm.qsvm_mlp_forward(net, bufs["X16"], rows, acts)
+    dE16 = torch.empty((rows, DIMS[3]), dtype=torch.bfloat16, device="cuda:0")
+    partial = torch.empty(3 * P, dtype=torch.float32, device="cuda:0")
+    out3 = torch.empty(3, dtype=torch.float32, device="cuda:0")
+    qsvm.qsvm_pair_head(bufs["E"], P, DIMS[3], _f32_dev(target), ab, dE16, partial, out3, loss_kind=kind)
+    torch.cuda.synchronize()
+    E = _host(bufs["E"])
+    loss, dE, da, db = ref.pair_loss(E, target, float(np.float32(0.05)), float(np.float32(-0.3)),
+                                     "bce" if kind == qsvm.LOSS_BCE else "mse")
+    o = out3.cpu().numpy()
+    assert abs(o[0] - loss) <= 1e-5 * max(1.0, abs(loss))
+    assert abs(o[1] - da) <= 1e-4 * max(1e-3, abs(da)) + 1e-7
+    assert abs(o[2] - db) <= 1e-4 * max(1e-3, abs(db)) + 1e-7
+    assert _nrel(_host(dE16), dE) < 4e-3
+
+    grads = {k: torch.empty_like(dev[w], dtype=torch.float32) for k, w in
+             zip(["dW1", "db1", "dW2", "db2", "dW3", "db3"], ["W1", "b1", "W2", "b2", "W3", "b3"])}
+    dH1 = torch.empty((rows, DIMS[1]), dtype=torch.bfloat16, device="cuda:0")
+    dH2 = torch.empty((rows, DIMS[2]), dtype=torch.bfloat16, device="cuda:0")
+    g = qsvm.MlpGrads(*(grads[k].data_ptr() for k in ("dW1", "db1", "dW2", "db2", "dW3", "db3")),
+                      dH1.data_ptr(), dH2.data_ptr())
+    qsvm.qsvm_mlp_backward(net, bufs["X16"], acts, dE16, rows, g)
+    torch.cuda.synchronize()
+    # reference backward on the kernel's own forward activations and dE16,
+    # with the BF16 rounding of dH2 and dH1 emulated
+    H1, A1, H2, A2 = _host(bufs["H1"]), _host(bufs["A1"]), _host(bufs["H2"]), _host(bufs["A2"])
+    dEk = _host(dE16)
+    dW3 = A2.T @ dEk
+    dH2r = ref.bf16_round((dEk @ W[4].T) * ref.gelu_grad(H2))
+    dW2 = A1.T @ dH2r
+    dH1r = ref.bf16_round((dH2r @ W[2].T) * ref.gelu_grad(H1))
+    dW1 = X.T @ dH1r
+    assert _nrel(_host(grads["dW3"]), dW3) < 1e-5
+    assert _nrel(_host(grads["db3"]), dEk.sum(0)) < 1e-5
+    assert _nrel(_host(dH2), dH2r) < 4e-3
+    assert _nrel(_host(grads["dW2"]), dW2) < 5e-3
+    assert _nrel(_host(grads["dW1"]), dW1) < 1e-2
+    # and against the unrounded FP64 backward of the FP64 forward
+    full = ref.forward(W, X)
+    _, dEf, _, _ = ref.pair_loss(full["E"], target, 0.05, -0.3, "bce" if kind == qsvm.LOSS_BCE else "mse")
+    gf = ref.backward(W, X, full, dEf)
+    assert _nrel(_host(grads["dW1"]), gf[0]) < 5e-2
+    assert _nrel(_host(grads["dW3"]), gf[4]) < 5e-2
+
+
+def test_adamw_matches_reference():
+    import torch
+
+    rng = np.random.default_rng(3)
+    w0 = rng.normal(0, 1, 1000).astype(np.float32)
+    w = _f32_dev(w0)
+    m = torch.zeros_like(w)
+    v = torch.zeros_like(w)
+    w16 = torch.empty(1000, dtype=torch.bfloat16, device="cuda:0")
+    rw, rm, rv = w0.astype(np.float64), np.zeros(1000), np.zeros(1000)
+    for step in range(1, 4):
+        gr = rng.normal(0, 1, 1000).astype(np.float32)
+        qsvm.qsvm_adamw(w, _f32_dev(gr), m, v, w16, 1e-2, 0.9, 0.999, 1e-8, 0.01, step)
+        rw, rm, rv = ref.adamw_step(rw, gr.astype(np.float64), rm, rv, step, 1e-2, 0.9, 0.999, 1e-8, 0.01)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(w.cpu().numpy() - rw)) < 1e-5
+    assert np.array_equal(_host(w16), ref.bf16_round(w.cpu().numpy()))
+
+
+def test_surrogate_gram_tile_max_and_flags():
+    import torch
+
+    rng = np.random.default_rng(4)
+    N, d = 150, 64
+    Np = 192
+    E = ref.bf16_round(rng.normal(0, 0.3, (Np, d)))
+    E16 = _bf16_dev(E)
+    ab = _f32_dev([0.5, -3.0])
+    K = torch.full((N, N), -1.0, dtype=torch.float64, device="cuda:0")
+    T = Np // 64
+    tmax = torch.empty(T * T, dtype=torch.float32, device="cuda:0")
+    qsvm.qsvm_surrogate_gram(E16, N, ab, K, tmax)
+    torch.cuda.synchronize()
+    Kh = K.cpu().numpy()
+    Kr = ref.surrogate_gram(E[:N], 0.5, -3.0)
+    assert np.max(np.abs(Kh - Kr)) < 1e-6
+    tm = tmax.cpu().numpy().reshape(T, T)
+    for ti in range(T):
+        for tj in range(T):
+            blk = Kh[ti * 64:min(N, ti * 64 + 64), tj * 64:min(N, tj * 64 + 64)].copy()
+            if ti == tj:
+                np.fill_diagonal(blk, -np.inf)
+            assert tm[ti, tj] == np.float32(blk.max())
+    tau = float(np.median(tm[np.triu_indices(T)]))
+    tiles = torch.empty(T * (T + 1), dtype=torch.int32, device="cuda:0")
+    count = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+    qsvm.qsvm_flag_tiles(tmax, T, tau, tiles, count)
+    torch.cuda.synchronize()
+    c = int(count.item())
+    got = {tuple(x) for x in tiles.cpu().numpy()[: 2 * c].reshape(-1, 2)}
+    want = {(ti, tj) for ti in range(T) for tj in range(ti, T) if tm[ti, tj] >= np.float32(tau)}
+    assert got == want and c == len(want)
+
+
+def test_gram_sym_tiles_equals_full_gram_on_those_tiles():
+    import torch
+
+    X = synth.uniform_features(200, 20, seed=5)
+    m = encode(X, 2)
+    full = qsvm.qsvm_gram_sym(m)
+    K = torch.full((200, 200), -2.0, dtype=torch.float64, device="cuda:0")
+    lst = [(0, 0), (0, 2), (1, 3), (2, 2), (3, 1), (5, 5), (-1, 0)]  # last three are invalid, skipped
+    tiles = torch.tensor(lst, dtype=torch.int32, device="cuda:0").reshape(-1)
+    qsvm.qsvm_gram_sym_tiles(m, tiles, len(lst), K)
+    torch.cuda.synchronize()
+    Kh, F = K.cpu().numpy(), full.cpu().numpy()
+    mask = np.zeros((200, 200), dtype=bool)
+    for ti, tj in lst[:4]:
+        mask[ti * 64:(ti + 1) * 64, tj * 64:(tj + 1) * 64] = True
+        mask[tj * 64:(tj + 1) * 64, ti * 64:(ti + 1) * 64] = True
+    assert np.array_equal(Kh[mask], F[mask])
+    assert np.all(Kh[~mask] == -2.0)
+
+
+def test_surrogate_training_reduces_held_out_error():
+    """A small problem with sizeable kernels (n = 8): training lowers the loss
+    and the held-out error against exact entries, versus the same network
+    before training."""
+    import torch
+
+    from paper_2405_02630_amd.surrogate import Surrogate, SurrogateConfig
+
+    n, reps = 8, 2
+    Xh = synth.uniform_features(640, n, seed=11)
+    X = torch.as_tensor(Xh, device="cuda:0")
+    train = np.arange(0, 384)
+    hold = np.arange(384, 640)
+    Kfull = qsvm.qsvm_gram_sym(encode(Xh, reps)).cpu().numpy()
+    assert np.max(np.abs(Kfull[:40, :40] - statevector.sv_gram(Xh[:40], reps))) <= K_ABS_TOL
+    cfg = SurrogateConfig(d_h1=128, d_h2=128, d_out=64, pairs_per_step=2048, lr=2e-3, lr_head=2e-2, seed=3)
+    sur = Surrogate(n, cfg)
+    iu = np.triu_indices(len(hold), 1)
+
+    def held_out_mse():
+        Kh, _ = sur.gram(X, None, tau=2.0)  # tau > 1: no tile is flagged, pure surrogate
+        Ks = Kh.cpu().numpy()[np.ix_(hold, hold)]
+        return float(np.mean((Ks[iu] - Kfull[np.ix_(hold, hold)][iu]) ** 2))
+
+    sur.init_head_from_targets(float(np.mean(Kfull[np.ix_(train, train)][np.triu_indices(len(train), 1)])))
+    before = held_out_mse()
+    rep = sur.fit(X, train, Kfull[np.ix_(train, train)], steps=400, log_every=100)
+    after = held_out_mse()
+    assert rep.loss_history[-1][1] < rep.loss_history[0][1]
+    assert after < 0.7 * before, (before, after)
+
+
+def test_surrogate_gram_with_full_fallback_is_exact():
+    """tau = 0 flags every tile: the result must equal the exact Gram bit for bit."""
+    import torch
+
+    from paper_2405_02630_amd.surrogate import Surrogate, SurrogateConfig
+
+    Xh = synth.uniform_features(150, 12, seed=12)
+    X = torch.as_tensor(Xh, device="cuda:0")
+    m = encode(Xh, 2)
+    exact = qsvm.qsvm_gram_sym(m)
+    sur = Surrogate(12, SurrogateConfig(d_h1=64, d_h2=64, d_out=64))
+    K, flagged = sur.gram(X, m, tau=0.0)
+    torch.cuda.synchronize()
+    assert flagged == 3 * 4 // 2
+    assert torch.equal(K, exact)

@@ -1,0 +1,134 @@
+"""Pins of the surrogate's FP64 reference (oracle/mlp.py), no GPU.
+
+The reference is checked against finite differences of its own loss (the
+backward must be the derivative of the forward) and against PyTorch's CPU
+float64 autograd, GELU and AdamW, and bfloat16 conversion -- library routines
+that the reference does not use.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp
+
+
+def _params(rng, dims=(6, 5, 4, 3), scale=0.5):
+    d0, d1, d2, d3 = dims
+    return (
+        rng.normal(0, scale, (d0, d1)), rng.normal(0, 0.1, d1),
+        rng.normal(0, scale, (d1, d2)), rng.normal(0, 0.1, d2),
+        rng.normal(0, scale, (d2, d3)), rng.normal(0, 0.1, d3),
+    )
+
+
+def _loss(params, X, target, alpha, beta, kind="mse"):
+    acts = mlp.forward(params, X)
+    return mlp.pair_loss(acts["E"], target, alpha, beta, kind)[0]
+
+
+def test_gelu_matches_torch():
+    x = np.linspace(-6, 6, 101)
+    ref = torch.nn.functional.gelu(torch.tensor(x, dtype=torch.float64), approximate="none").numpy()
+    assert np.max(np.abs(mlp.gelu(x) - ref)) < 1e-14
+
+
+def test_gelu_grad_matches_finite_difference():
+    x = np.linspace(-5, 5, 41)
+    h = 1e-6
+    fd = (mlp.gelu(x + h) - mlp.gelu(x - h)) / (2 * h)
+    assert np.max(np.abs(mlp.gelu_grad(x) - fd)) < 1e-8
+
+
+@pytest.mark.parametrize("kind", ["mse", "bce"])
+def test_backward_matches_finite_differences(kind):
+    rng = np.random.default_rng(0)
+    params = list(_params(rng))
+    X = rng.normal(0, 1, (8, 6))
+    target = rng.uniform(0, 1, 4)
+    alpha, beta = 0.7, -0.2
+    acts = mlp.forward(params, X)
+    _, dE, da, db = mlp.pair_loss(acts["E"], target, alpha, beta, kind)
+    grads = mlp.backward(params, X, acts, dE)
+    h = 1e-6
+    for pi, (p, g) in enumerate(zip(params, grads)):
+        flat = p.reshape(-1)
+        for q in range(0, flat.size, max(1, flat.size // 7)):
+            old = flat[q]
+            flat[q] = old + h
+            lp = _loss(params, X, target, alpha, beta, kind)
+            flat[q] = old - h
+            lm = _loss(params, X, target, alpha, beta, kind)
+            flat[q] = old
+            assert abs((lp - lm) / (2 * h) - g.reshape(-1)[q]) < 1e-7, (pi, q)
+    fa = (_loss(params, X, target, alpha + h, beta, kind) - _loss(params, X, target, alpha - h, beta, kind)) / (2 * h)
+    fb = (_loss(params, X, target, alpha, beta + h, kind) - _loss(params, X, target, alpha, beta - h, kind)) / (2 * h)
+    assert abs(fa - da) < 1e-7 and abs(fb - db) < 1e-7
+
+
+def test_bce_loss_matches_torch():
+    rng = np.random.default_rng(5)
+    E = rng.normal(0, 1, (8, 3))
+    t = rng.uniform(0, 1, 4)
+    loss, *_ = mlp.pair_loss(E, t, 0.9, -0.3, "bce")
+    z = 0.9 * np.sum(E[:4] * E[4:], axis=1) - 0.3
+    ref = torch.nn.functional.binary_cross_entropy_with_logits(torch.tensor(z), torch.tensor(t)).item()
+    assert abs(loss - ref) < 1e-14
+
+
+def test_forward_and_gradients_match_torch_autograd():
+    rng = np.random.default_rng(1)
+    params = _params(rng, dims=(10, 8, 7, 5))
+    X = rng.normal(0, 1, (12, 10))
+    target = rng.uniform(0, 1, 6)
+    alpha, beta = 1.3, 0.4
+    acts = mlp.forward(params, X)
+    loss, dE, da, db = mlp.pair_loss(acts["E"], target, alpha, beta)
+    grads = mlp.backward(params, X, acts, dE)
+
+    tp = [torch.tensor(p, dtype=torch.float64, requires_grad=True) for p in params]
+    ta = torch.tensor(alpha, dtype=torch.float64, requires_grad=True)
+    tb = torch.tensor(beta, dtype=torch.float64, requires_grad=True)
+    tX = torch.tensor(X)
+    g = torch.nn.functional.gelu
+    E = g(g(tX @ tp[0] + tp[1]) @ tp[2] + tp[3]) @ tp[4] + tp[5]
+    P = 6
+    kh = torch.sigmoid(ta * (E[:P] * E[P:]).sum(1) + tb)
+    tl = ((kh - torch.tensor(target)) ** 2).mean()
+    tl.backward()
+    assert abs(tl.item() - loss) < 1e-14
+    assert np.max(np.abs(E.detach().numpy() - acts["E"])) < 1e-13
+    for p, gr in zip(tp, grads):
+        assert np.max(np.abs(p.grad.numpy() - gr)) < 1e-13
+    assert abs(ta.grad.item() - da) < 1e-13 and abs(tb.grad.item() - db) < 1e-13
+
+
+def test_adamw_matches_torch():
+    rng = np.random.default_rng(2)
+    w0 = rng.normal(0, 1, 17)
+    grads = [rng.normal(0, 1, 17) for _ in range(3)]
+    lr, b1, b2, eps, wd = 1e-2, 0.9, 0.99, 1e-8, 0.05
+    tw = torch.tensor(w0, requires_grad=True)
+    opt = torch.optim.AdamW([tw], lr=lr, betas=(b1, b2), eps=eps, weight_decay=wd)
+    w, m, v = w0.copy(), np.zeros(17), np.zeros(17)
+    for step, gr in enumerate(grads, start=1):
+        tw.grad = torch.tensor(gr)
+        opt.step()
+        w, m, v = mlp.adamw_step(w, gr, m, v, step, lr, b1, b2, eps, wd)
+    assert np.max(np.abs(tw.detach().numpy() - w)) < 1e-13
+
+
+def test_bf16_round_matches_torch():
+    rng = np.random.default_rng(3)
+    x = np.concatenate([rng.normal(0, 1, 1000), rng.normal(0, 1e-3, 100), [0.0, 1.0, -2.5, 1.00390625, 1.01171875]])
+    ref = torch.tensor(x, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(mlp.bf16_round(x), ref)
+
+
+def test_surrogate_gram_definition():
+    rng = np.random.default_rng(4)
+    E = rng.normal(0, 1, (5, 3))
+    K = mlp.surrogate_gram(E, 0.5, -1.0)
+    assert np.all(np.diag(K) == 1.0)
+    assert abs(K[1, 3] - 1 / (1 + np.exp(-(0.5 * E[1] @ E[3] - 1.0)))) < 1e-15
+    assert np.allclose(K, K.T)
