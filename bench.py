@@ -8,11 +8,21 @@ features already resident in HBM.  value = contracted pairs per second.
 Prints one JSON line with the timing, a roofline entry for the dominant
 kernel (the overlap sweep; launch durations from HIP events on the launch
 stream) and, on rank 0, a CPU baseline: the FP64 oracle timed on the host
-cores on a bounded sample of the same workload.
+cores on a bounded sample of the same workload.  Two more legs add their own
+objects to the line:
+  surrogate -- 32768 synthetic 784-pixel images, reps = 2: the MLP surrogate
+               trained on 2 % of the exact entries (the complete Gram of a
+               random 4634-point subset), judged on 1 % held out (the Gram of
+               a disjoint 3277-point subset), its whole-set Gram with exact
+               fallback timed against the exact whole-set Gram, and
+               one-vs-rest SVM accuracy on a 4096-point subset with the exact
+               and the surrogate Gram;
+  batched   -- 64 independent Gram jobs of uneven n, N and reps in one
+               persistent hipGraph launch, against one launch per job.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--reps 2|3]
-                       [--sweep butterfly|dense] [--no-cpu-baseline]
-                       [--cpu-sample P] [--copy-calibration MiB]
+                       [--sweep butterfly|dense] [--legs exact,surrogate,batched]
+                       [--no-cpu-baseline] [--cpu-sample P] [--copy-calibration MiB]
 """
 
 from __future__ import annotations
@@ -28,8 +38,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_FP32_VECTOR_TFLOPS = 157.3  # 256 CU x 2.4 GHz x 256 flop/clk (packed dual-issue FMA)
-ISSUE_PEAK_NONPACKED_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 4 SIMD x 16 lanes x 2 (one FMA per lane per clock)
+PEAK_FP32_VECTOR_TFLOPS = 157.3  # MI355X FP32 vector: 256 CU x 2.4 GHz x 256 flop/clk
+
+# HBM bytes per sweep launch from two rocprofv3 counter passes (FETCH_SIZE,
+# WRITE_SIZE), each scaled by what the counter reads for a 1 GiB copy; valid
+# only for the kernel and configuration they were taken on (sweep, reps,
+# points, qubits) -- any other configuration reports null.
+MEASURED_TRAFFIC = {
+    ("butterfly", 2, 4096, 784): (2.1867e9, "profiles/sweep_butterfly_images784_r2_hbm_counters.md"),
+}
 
 
 def log(*a):
@@ -102,6 +119,200 @@ def _pair_chunk(args):
     return omps.mps_gram_pairs(_BENCH_STATES, _BENCH_STATES, ia, jb)
 
 
+def _events(n):
+    import torch
+
+    return [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+
+
+def surrogate_leg(args, exact_rate):
+    """Train, time and judge the learned surrogate on the 32768-image workload."""
+    import numpy as np
+    import torch
+
+    from paper_2405_02630_amd import qsvm, synth
+    from paper_2405_02630_amd.surrogate import Surrogate, SurrogateConfig
+
+    dev = torch.device("cuda:0")
+    N = args.sur_points
+    reps = 2
+    wl = synth.images784(seed=5, n_train=N, n_test=0, reps=reps)
+    X = torch.as_tensor(wl.X, dtype=torch.float64, device=dev)
+    n = wl.X.shape[1]
+    rng = np.random.default_rng(17)
+    perm = rng.permutation(N)
+    s_train = int(round(math.sqrt(0.02 * N * (N - 1))))  # S(S-1)/2 = 2 % of N(N-1)/2
+    s_hold = int(round(math.sqrt(0.01 * N * (N - 1))))
+    s_svm = min(4096, N - s_train - s_hold)
+    train_pts = np.sort(perm[:s_train])
+    hold_pts = np.sort(perm[s_train:s_train + s_hold])
+    svm_pts = np.sort(perm[s_train + s_hold:s_train + s_hold + s_svm])
+    log(f"surrogate: N={N}, train {s_train} pts ({s_train*(s_train-1)//2} pairs), "
+        f"held out {s_hold} pts ({s_hold*(s_hold-1)//2} pairs)")
+
+    def exact_sub(pts):
+        m = qsvm.qsvm_encode_mps(X[torch.as_tensor(pts, device=dev)].contiguous(), reps)
+        return qsvm.qsvm_gram_sym(m)
+
+    t0 = time.perf_counter()
+    K_train = exact_sub(train_pts).cpu().numpy()
+    t_targets = time.perf_counter() - t0
+    cfg = SurrogateConfig()
+    sur = Surrogate(n, cfg)
+    # the untrained network with the same initial head, judged like the trained one
+    hp = torch.as_tensor(hold_pts, device=dev)
+    iu = np.triu_indices(s_hold, 1)
+    Kh_hold = exact_sub(hold_pts).cpu().numpy()
+    sur.init_head_from_targets(float(np.mean(K_train[np.triu_indices(s_train, 1)])))
+    K0, _ = sur.gram(X[hp].contiguous(), None, tau=2.0)
+    dk0 = np.abs(K0.cpu().numpy()[iu] - Kh_hold[iu])
+    del K0
+    rep = sur.fit(X, train_pts, K_train, steps=args.sur_steps, log_every=max(1, args.sur_steps // 5))
+    log(f"surrogate: trained {rep.steps} steps in {rep.seconds:.2f} s, loss {rep.loss_history}")
+
+    mps_all = qsvm.qsvm_encode_mps(X, reps)
+    Kall = torch.empty((N, N), dtype=torch.float64, device=dev)
+    # surrogate Gram with fallback, timed end to end (embedding + GEMM + flags + fallback)
+    sur.gram(X, mps_all, K=Kall)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        _, flagged = sur.gram(X, mps_all, K=Kall)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    sur_s = float(np.median(times))
+    T = (N + 63) // 64
+    # judge on the held-out pairs against their exact Gram
+    Ks_hold = Kall[hp][:, hp].cpu().numpy()
+    dk = np.abs(Ks_hold[iu] - Kh_hold[iu])
+    # SVM on a disjoint subset with the exact and the surrogate Gram
+    sp = torch.as_tensor(svm_pts, device=dev)
+    Ks_svm = Kall[sp][:, sp].cpu().numpy()
+    Ke_svm = exact_sub(svm_pts).cpu().numpy()
+    acc_exact, acc_sur = svm_accuracies(Ke_svm, Ks_svm, wl.labels[svm_pts])
+    # exact whole-set Gram for the speedup (same N, same buffer)
+    ev = _events(2)
+    ev[0].record()
+    qsvm.qsvm_gram_sym(mps_all, Kall)
+    ev[1].record()
+    torch.cuda.synchronize()
+    exact_s = ev[0].elapsed_time(ev[1]) / 1e3
+    pairs = N * (N - 1) // 2
+    res = {
+        "workload": f"images-n{n}-r{reps}-N{N}-sym",
+        "value": pairs / sur_s,
+        "unit": "entries/s",
+        "seconds": sur_s,
+        "exact_seconds": exact_s,
+        "exact_value": pairs / exact_s,
+        "speedup_vs_exact": exact_s / sur_s,
+        "flagged_tiles": flagged,
+        "tiles": T * (T + 1) // 2,
+        "held_out_pairs": int(dk.size),
+        "held_out_max_abs_dK": float(dk.max()),
+        "held_out_mean_abs_dK": float(dk.mean()),
+        "held_out_exact_K_max": float(Kh_hold[iu].max()),
+        "untrained_held_out_max_abs_dK": float(dk0.max()),
+        "untrained_held_out_mean_abs_dK": float(dk0.mean()),
+        "train_pairs": s_train * (s_train - 1) // 2,
+        "train_steps": rep.steps,
+        "train_seconds": rep.seconds,
+        "target_seconds": t_targets,
+        "final_loss": rep.loss_history[-1][1] if rep.loss_history else None,
+        "svm_subset": int(s_svm),
+        "svm_accuracy_exact": acc_exact,
+        "svm_accuracy_surrogate": acc_sur,
+        "model": f"MLP {n}->{cfg.d_h1}->{cfg.d_h2}->{cfg.d_out} GELU, bf16 weights, fp32 accumulate",
+    }
+    log(f"surrogate: {res['value']:.3e} entries/s ({sur_s*1e3:.1f} ms) vs exact {exact_s*1e3:.1f} ms; "
+        f"held-out max|dK| {res['held_out_max_abs_dK']:.2e}; flagged {flagged}; "
+        f"SVM exact {acc_exact:.3f} surrogate {acc_sur:.3f}")
+    del Kall
+    torch.cuda.empty_cache()
+    return res
+
+
+def svm_accuracies(K_exact, K_sur, labels, n_train_frac=0.75):
+    """One-vs-rest SVM on a precomputed Gram: train on the first 75 %, test on the rest."""
+    import numpy as np
+    from sklearn.multiclass import OneVsRestClassifier
+    from sklearn.svm import SVC
+
+    M = K_exact.shape[0]
+    tr = np.arange(int(M * n_train_frac))
+    te = np.arange(int(M * n_train_frac), M)
+    accs = []
+    for K in (K_exact, K_sur):
+        clf = OneVsRestClassifier(SVC(kernel="precomputed", C=1.0))
+        clf.fit(K[np.ix_(tr, tr)], labels[tr])
+        accs.append(float(np.mean(clf.predict(K[np.ix_(te, tr)]) == labels[te])))
+    return accs[0], accs[1]
+
+
+def batched_leg():
+    """64 uneven jobs: one persistent hipGraph launch vs one launch per job."""
+    import numpy as np
+    import torch
+
+    from paper_2405_02630_amd import qsvm, synth
+
+    dev = torch.device("cuda:0")
+    wl = synth.uneven_jobs(seed=0)
+    jobs = []
+    for w in wl:
+        m = qsvm.qsvm_encode_mps(torch.as_tensor(w.X, device=dev), w.reps)
+        K = torch.empty((m.N, m.N), dtype=torch.float64, device=dev)
+        jobs.append((m, K, None))
+    plan = qsvm.BatchPlan(jobs, use_graph=True)
+    total_items, grid, _ = plan.info()
+    pairs = [m.N * (m.N - 1) // 2 for m, _, _ in jobs]
+    # warm-up both paths
+    plan.launch()
+    for m, K, _ in jobs:
+        qsvm.qsvm_gram_sym(m, K)
+    torch.cuda.synchronize()
+    ev = _events(2)
+    ev[0].record()
+    for _ in range(3):
+        plan.launch()
+    ev[1].record()
+    torch.cuda.synchronize()
+    batched_s = ev[0].elapsed_time(ev[1]) / 3e3
+    per_job = []
+    ev_all = _events(2)
+    ev_all[0].record()
+    for m, K, _ in jobs:
+        e = _events(2)
+        e[0].record()
+        qsvm.qsvm_gram_sym(m, K)
+        e[1].record()
+        per_job.append(e)
+    ev_all[1].record()
+    torch.cuda.synchronize()
+    serial_s = ev_all[0].elapsed_time(ev_all[1]) / 1e3
+    job_rates = [p / (e[0].elapsed_time(e[1]) / 1e3) for p, e in zip(pairs, per_job)]
+    plan.close()
+    res = {
+        "workload": "64 jobs, n in {16,64,196,400,784}, N in [64,2048], reps in {2,3}, uniform features",
+        "jobs": len(jobs),
+        "pairs": int(sum(pairs)),
+        "work_items": total_items,
+        "persistent_blocks": grid,
+        "value": sum(pairs) / batched_s,
+        "unit": "entries/s",
+        "seconds": batched_s,
+        "one_launch_per_job_value": sum(pairs) / serial_s,
+        "one_launch_per_job_seconds": serial_s,
+        "speedup": serial_s / batched_s,
+        "per_job_entries_per_s": {"min": float(np.min(job_rates)), "median": float(np.median(job_rates)),
+                                  "max": float(np.max(job_rates))},
+    }
+    log(f"batched: {res['value']:.3e} entries/s ({batched_s*1e3:.1f} ms) vs one launch per job "
+        f"{res['one_launch_per_job_value']:.3e} ({serial_s*1e3:.1f} ms)")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,7 +323,10 @@ def main():
     ap.add_argument("--sweep", choices=["butterfly", "dense"], default="butterfly")
     ap.add_argument("--renorm-every", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=256)
+    ap.add_argument("--cpu-sample", type=int, default=512)
+    ap.add_argument("--legs", default="exact,surrogate,batched")
+    ap.add_argument("--sur-points", type=int, default=32768)
+    ap.add_argument("--sur-steps", type=int, default=300)
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="run only a plain device copy of this many MiB (for HBM counter scaling)")
     args = ap.parse_args()
@@ -185,12 +399,11 @@ def main():
         "peak": PEAK_FP32_VECTOR_TFLOPS,
         "unit": "TFLOP/s",
         "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
-        "traffic": None,
+        "traffic": MEASURED_TRAFFIC.get((args.sweep, reps, N, n), (None, None))[0],
+        "traffic_source": MEASURED_TRAFFIC.get((args.sweep, reps, N, n), (None, None))[1],
         "kernel": f"sweep_{args.sweep}_kernel<{reps},*>",
         "flops_per_launch": flops,
         "avg_launch_ms": round(sweep_ms, 4),
-        "issue_peak_nonpacked": ISSUE_PEAK_NONPACKED_TFLOPS,
-        "frac_of_issue_peak_nonpacked": round(achieved / ISSUE_PEAK_NONPACKED_TFLOPS, 4),
     }
 
     out = {
@@ -218,7 +431,19 @@ def main():
         "roofline": roofline,
     }
 
+    legs = set(args.legs.split(","))
+    if "surrogate" in legs:
+        del K  # release the exact leg's buffers first
+        torch.cuda.empty_cache()
+        out["surrogate"] = surrogate_leg(args, exact_rate=value)
+        K = None
+    if "batched" in legs:
+        out["batched"] = batched_leg()
+
     if not args.no_cpu_baseline:
+        if K is None:
+            K = torch.empty((N, N), dtype=torch.float64, device=dev)
+            qsvm.qsvm_gram_sym(qsvm.qsvm_encode_mps(X, reps, out=mps_buf), K, sweep=sweep)
         Kh = K.cpu().numpy()
         cores = max(1, min(16, os.cpu_count() or 1))
         log(f"cpu baseline: oracle on {args.cpu_sample} points with {cores} processes")

@@ -272,10 +272,18 @@ typedef struct {   /* activations of `rows` inputs */
   float* E;  void* E16; /* rows x d_out embedding, f32 and bf16 */
 } qsvm_mlp_acts;
 
-typedef struct {   /* gradients (f32, shaped like the parameters) and bf16 scratch */
+typedef struct {   /* gradients (f32, shaped like the parameters) and scratch */
   float* dW1; float* db1; float* dW2; float* db2; float* dW3; float* db3;
-  void* dH1; void* dH2; /* rows x d_h1, rows x d_h2 */
+  void* dH1; void* dH2; /* bf16, rows x d_h1 and rows x d_h2 */
+  float* ws;            /* f32 workspace of ws_floats >= qsvm_mlp_workspace_floats(net, rows):
+                           split-K partial products of the weight gradients and
+                           partial column sums, reduced in a fixed order */
+  int64_t ws_floats;
 } qsvm_mlp_grads;
+
+/* Workspace (floats) qsvm_mlp_backward needs for `rows` inputs; -1 for an
+ * invalid network or row count.  No HIP call. */
+int64_t qsvm_mlp_workspace_floats(const qsvm_mlp* net, int64_t rows);
 
 /* out[r][c] = bf16(X[idx[r]][c]) for c < n_qubits; 0 for n_qubits <= c < d_pad
  * and for rows whose idx[r] is outside [0, N) (padding rows; checked on the
@@ -298,7 +306,9 @@ qsvm_status qsvm_pair_head(const float* E, int64_t pairs, int32_t d, const float
                            int32_t loss_kind, void* dE16, float* partial, float* out3, void* stream);
 
 /* Backward pass given dE16 (rows x d_out bf16): parameter gradients into grads
- * (overwritten, not accumulated). */
+ * (overwritten, not accumulated).  Weight gradients (K = rows) are split along
+ * the rows into partial products in grads->ws and summed in a fixed order;
+ * a too-small workspace returns QSVM_ERR_SIZE. */
 qsvm_status qsvm_mlp_backward(const qsvm_mlp* net, const void* X16, const qsvm_mlp_acts* acts, const void* dE16,
                               int64_t rows, const qsvm_mlp_grads* grads, void* stream);
 

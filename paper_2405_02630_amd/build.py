@@ -3,7 +3,9 @@
 Usage: python -m paper_2405_02630_amd.build [--verbose]
 
 Every source under csrc/ is compiled as HIP for gfx950 only, with packed
-FP32 instructions disabled (-packed-fp32-ops), then linked into
+FP32 instructions disabled (-packed-fp32-ops) and floating-point contraction
+off (the kernels write every fused multiply-add explicitly, so a result does
+not depend on how one kernel variant was scheduled), then linked into
 paper_2405_02630_amd/libqsvm.so next to this file.  Objects go to _build/ at
 the repository root.
 """
@@ -31,6 +33,7 @@ FLAGS = [
     "-Wall",
     "-Wno-unused-function",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-ffp-contract=off",  # every FMA is written out: results do not depend on instruction selection
     "-I" + os.path.join(ROOT, "include"),
 ]
 

@@ -28,6 +28,7 @@ struct GemmArgs {
   const float* ab;    // device (alpha, beta) for EPI_SIGMOID_GRAM
   float* tile_max;    // [M/64][N/64] for EPI_SIGMOID_GRAM
   int64_t valid;      // rows/cols < valid are real points (EPI_SIGMOID_GRAM)
+  int32_t splits;     // split-K factor (>= 1; > 1 only with EPI_F32: C holds `splits` slabs of M x ldc)
 };
 
 struct AdamArgs {
@@ -38,7 +39,9 @@ struct AdamArgs {
 hipError_t launch_gemm(int ta, int tb, int epi, const GemmArgs& g, hipStream_t s);
 hipError_t launch_gather(const double* X, int64_t N, int32_t n, const int32_t* idx, int64_t rows, int32_t d_pad,
                          uint16_t* out, hipStream_t s);
-hipError_t launch_colsum(const uint16_t* A, int64_t rows, int32_t cols, float* out, hipStream_t s);
+int colsum_chunks(int64_t rows);
+hipError_t launch_colsum(const uint16_t* A, int64_t rows, int32_t cols, float* partial, float* out, hipStream_t s);
+hipError_t launch_sum_slabs(const float* slabs, int32_t n_slabs, int64_t count, float* out, hipStream_t s);
 hipError_t launch_pair_head(const float* E, int64_t P, int32_t d, const float* target, const float* ab,
                             int32_t loss_kind, uint16_t* dE16, float* partial, float* out3, hipStream_t s);
 hipError_t launch_adamw(float* w, const float* grad, float* m, float* v, uint16_t* w16, int64_t count,

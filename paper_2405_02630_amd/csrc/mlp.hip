@@ -12,7 +12,8 @@
 //   multiply by GELU'(pre-activation) (backward through the activation);
 //   sigmoid-scaled Gram with per-tile maxima of the off-diagonal entries.
 // * gather_features: FP64 feature rows -> zero-padded BF16 rows.
-// * colsum_bf16: bias gradients (column sums, fixed order).
+// * colsum_partial + sum_slabs: bias gradients (column sums in two fixed-order
+//   stages) and the reduction of split-K partial products.
 // * pair_head: per pair, K_hat, the loss (squared error or soft-target
 //   cross-entropy) and its gradient w.r.t. both embeddings, alpha and beta;
 //   per-pair partial sums reduced in a fixed order.
@@ -75,7 +76,10 @@ __global__ void __launch_bounds__(256) bf16_gemm(GemmArgs g) {
 #pragma unroll
   for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
 
-  for (int64_t k0 = 0; k0 < g.K; k0 += BK) {
+  // split-K: block z covers K range [z K / splits, (z + 1) K / splits)
+  const int64_t kspan = g.K / g.splits;
+  const int64_t kbeg = int64_t(blockIdx.z) * kspan;
+  for (int64_t k0 = kbeg; k0 < kbeg + kspan; k0 += BK) {
     // ---- global -> LDS (each thread moves 8 bf16 of A and 8 of B) ----
     if (TA == 0) {
       const int m = t >> 2, kk = (t & 3) * 8;
@@ -121,7 +125,7 @@ __global__ void __launch_bounds__(256) bf16_gemm(GemmArgs g) {
     const int64_t c = n0 + wn * 32 + j;
     const float x = acc[v];
     if (EPI == EPI_F32) {
-      static_cast<float*>(g.C)[r * g.ldc + c] = x;
+      static_cast<float*>(g.C)[int64_t(blockIdx.z) * g.M * g.ldc + r * g.ldc + c] = x;
     } else if (EPI == EPI_BIAS_GELU) {
       const float h = x + g.bias[c];
       static_cast<float*>(g.C)[r * g.ldc + c] = h;
@@ -163,12 +167,26 @@ __global__ void gather_features(const double* __restrict__ X, int64_t N, int32_t
   out[t] = (c < n && p >= 0 && p < N) ? f32_to_bf16(float(X[int64_t(p) * n + c])) : uint16_t(0);
 }
 
-__global__ void colsum_bf16(const uint16_t* __restrict__ A, int64_t rows, int32_t cols, float* __restrict__ out) {
+// Column sums in two fixed-order stages: partial[chunk][c] over 256-row
+// chunks (consecutive threads read consecutive columns), then the chunks.
+constexpr int kColChunk = 256;
+
+__global__ void colsum_partial(const uint16_t* __restrict__ A, int64_t rows, int32_t cols, float* __restrict__ partial) {
   const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= cols) return;
+  const int64_t r0 = int64_t(blockIdx.y) * kColChunk;
+  const int64_t r1 = (r0 + kColChunk < rows) ? r0 + kColChunk : rows;
   float s = 0.0f;
-  for (int64_t r = 0; r < rows; ++r) s += bf16_to_f32(A[r * cols + c]);
-  out[c] = s;
+  for (int64_t r = r0; r < r1; ++r) s += bf16_to_f32(A[r * cols + c]);
+  partial[int64_t(blockIdx.y) * cols + c] = s;
+}
+
+__global__ void sum_slabs(const float* __restrict__ slabs, int32_t n_slabs, int64_t count, float* __restrict__ out) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  float s = 0.0f;
+  for (int32_t z = 0; z < n_slabs; ++z) s += slabs[int64_t(z) * count + t];
+  out[t] = s;
 }
 
 __device__ __forceinline__ float softplusf(float z) {  // log(1 + e^z), no overflow
@@ -276,7 +294,7 @@ __global__ void zero_int(int32_t* p) {
 
 template <int TA, int TB, int EPI>
 hipError_t launch_gemm_t(const GemmArgs& g, hipStream_t s) {
-  const dim3 grid(unsigned(g.N / BN), unsigned(g.M / BM));
+  const dim3 grid(unsigned(g.N / BN), unsigned(g.M / BM), unsigned(g.splits));
   hipLaunchKernelGGL((bf16_gemm<TA, TB, EPI>), grid, dim3(256), 0, s, g);
   return hipGetLastError();
 }
@@ -303,8 +321,19 @@ hipError_t launch_gather(const double* X, int64_t N, int32_t n, const int32_t* i
   return hipGetLastError();
 }
 
-hipError_t launch_colsum(const uint16_t* A, int64_t rows, int32_t cols, float* out, hipStream_t s) {
-  hipLaunchKernelGGL(colsum_bf16, dim3(unsigned((cols + 255) / 256)), dim3(256), 0, s, A, rows, cols, out);
+int colsum_chunks(int64_t rows) { return int((rows + kColChunk - 1) / kColChunk); }
+
+hipError_t launch_colsum(const uint16_t* A, int64_t rows, int32_t cols, float* partial, float* out, hipStream_t s) {
+  const int chunks = colsum_chunks(rows);
+  hipLaunchKernelGGL(colsum_partial, dim3(unsigned((cols + 255) / 256), unsigned(chunks)), dim3(256), 0, s, A, rows,
+                     cols, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_sum_slabs(partial, chunks, cols, out, s);
+}
+
+hipError_t launch_sum_slabs(const float* slabs, int32_t n_slabs, int64_t count, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(sum_slabs, dim3(unsigned((count + 255) / 256)), dim3(256), 0, s, slabs, n_slabs, count, out);
   return hipGetLastError();
 }
 

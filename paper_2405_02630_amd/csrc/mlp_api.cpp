@@ -69,7 +69,39 @@ qsvm::GemmArgs gemm(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda,
   g.ldc = ldc;
   g.bias = bias;
   g.aux = aux;
+  g.splits = 1;
   return g;
+}
+
+// Split-K factor of a weight-gradient GEMM with K = rows.
+int32_t grad_splits(int64_t rows) {
+  for (int32_t s = 8; s > 1; s >>= 1)
+    if (rows % (int64_t(s) * 32) == 0 && rows / s >= 256) return s;
+  return 1;
+}
+
+int64_t workspace_floats(const qsvm_mlp* net, int64_t rows) {
+  const int64_t din = net->d_in, h1 = net->d_h1, h2 = net->d_h2, dout = net->d_out;
+  int64_t mn = din * h1;
+  if (h1 * h2 > mn) mn = h1 * h2;
+  if (h2 * dout > mn) mn = h2 * dout;
+  int64_t cols = h1 > h2 ? h1 : h2;
+  if (dout > cols) cols = dout;
+  const int64_t a = int64_t(grad_splits(rows)) * mn;
+  const int64_t b = int64_t(qsvm::colsum_chunks(rows)) * cols;
+  return a > b ? a : b;
+}
+
+// dW (M x N) = op(A)^T B over K = rows, split along K into workspace slabs
+// that are then summed in a fixed order.
+hipError_t grad_gemm(int64_t M, int64_t N, int64_t rows, const void* A, int64_t lda, const void* B, int64_t ldb,
+                     float* dW, float* ws, hipStream_t st) {
+  qsvm::GemmArgs g = gemm(M, N, rows, A, lda, B, ldb, ws, nullptr, N);
+  g.splits = grad_splits(rows);
+  if (g.splits == 1) g.C = dW;
+  hipError_t e = qsvm::launch_gemm(1, 0, qsvm::EPI_F32, g, st);
+  if (e == hipSuccess && g.splits > 1) e = qsvm::launch_sum_slabs(ws, g.splits, M * N, dW, st);
+  return e;
 }
 
 }  // namespace
@@ -137,27 +169,40 @@ qsvm_status qsvm_mlp_backward(const qsvm_mlp* net, const void* X16, const qsvm_m
   if (!X16 || !acts || !acts->H1 || !acts->A1 || !acts->H2 || !acts->A2 || !dE16 || !g || !g->dW1 || !g->db1 ||
       !g->dW2 || !g->db2 || !g->dW3 || !g->db3 || !g->dH1 || !g->dH2)
     return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_mlp_backward: NULL pointer");
+  if (!g->ws || g->ws_floats < workspace_floats(net, rows)) {
+    char msg[200];
+    snprintf(msg, sizeof msg, "%s: workspace of %lld floats < %lld needed (qsvm_mlp_workspace_floats)", what,
+             (long long)g->ws_floats, (long long)workspace_floats(net, rows));
+    return api_fail(QSVM_ERR_SIZE, msg);
+  }
   if (qsvm::api_injected_failure()) return injected(what);
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int64_t din = net->d_in, h1 = net->d_h1, h2 = net->d_h2, dout = net->d_out;
+  float* ws = g->ws;
   // dW3 = A2^T dE ; db3 = colsum(dE)
-  hipError_t e = qsvm::launch_gemm(1, 0, qsvm::EPI_F32, gemm(h2, dout, rows, acts->A2, h2, dE16, dout, g->dW3, nullptr, dout), st);
-  if (e == hipSuccess) e = qsvm::launch_colsum(static_cast<const uint16_t*>(dE16), rows, int32_t(dout), g->db3, st);
+  hipError_t e = grad_gemm(h2, dout, rows, acts->A2, h2, dE16, dout, g->dW3, ws, st);
+  if (e == hipSuccess) e = qsvm::launch_colsum(static_cast<const uint16_t*>(dE16), rows, int32_t(dout), ws, g->db3, st);
   // dH2 = (dE W3^T) * gelu'(H2)
   if (e == hipSuccess)
     e = qsvm::launch_gemm(0, 1, qsvm::EPI_GELU_BWD,
                           gemm(rows, h2, dout, dE16, dout, net->W3, dout, nullptr, g->dH2, h2, nullptr, acts->H2), st);
   // dW2 = A1^T dH2 ; db2 = colsum(dH2)
-  if (e == hipSuccess) e = qsvm::launch_gemm(1, 0, qsvm::EPI_F32, gemm(h1, h2, rows, acts->A1, h1, g->dH2, h2, g->dW2, nullptr, h2), st);
-  if (e == hipSuccess) e = qsvm::launch_colsum(static_cast<const uint16_t*>(g->dH2), rows, int32_t(h2), g->db2, st);
+  if (e == hipSuccess) e = grad_gemm(h1, h2, rows, acts->A1, h1, g->dH2, h2, g->dW2, ws, st);
+  if (e == hipSuccess) e = qsvm::launch_colsum(static_cast<const uint16_t*>(g->dH2), rows, int32_t(h2), ws, g->db2, st);
   // dH1 = (dH2 W2^T) * gelu'(H1)
   if (e == hipSuccess)
     e = qsvm::launch_gemm(0, 1, qsvm::EPI_GELU_BWD,
                           gemm(rows, h1, h2, g->dH2, h2, net->W2, h2, nullptr, g->dH1, h1, nullptr, acts->H1), st);
   // dW1 = X^T dH1 ; db1 = colsum(dH1)
-  if (e == hipSuccess) e = qsvm::launch_gemm(1, 0, qsvm::EPI_F32, gemm(din, h1, rows, X16, din, g->dH1, h1, g->dW1, nullptr, h1), st);
-  if (e == hipSuccess) e = qsvm::launch_colsum(static_cast<const uint16_t*>(g->dH1), rows, int32_t(h1), g->db1, st);
+  if (e == hipSuccess) e = grad_gemm(din, h1, rows, X16, din, g->dH1, h1, g->dW1, ws, st);
+  if (e == hipSuccess) e = qsvm::launch_colsum(static_cast<const uint16_t*>(g->dH1), rows, int32_t(h1), ws, g->db1, st);
   return api_hip(e, what);
+}
+
+int64_t qsvm_mlp_workspace_floats(const qsvm_mlp* net, int64_t rows) {
+  if (check_net(net, "qsvm_mlp_workspace_floats") != QSVM_OK || check_rows(rows, "qsvm_mlp_workspace_floats") != QSVM_OK)
+    return -1;
+  return workspace_floats(net, rows);
 }
 
 qsvm_status qsvm_adamw(float* w, const float* grad, float* m, float* v, void* w16, int64_t count, float lr,

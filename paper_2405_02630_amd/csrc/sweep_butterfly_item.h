@@ -152,7 +152,8 @@ __device__ __forceinline__ void init_env(float2 (&v)[Layout<R>::M]) {
   }
 }
 
-// |sum_q g_x^|c| conj(g_y)^|c'| v[q]|^2 in FP64.
+// |sum_q g_x^|c| conj(g_y)^|c'| v[q]|^2 in FP64 (every product-sum written as
+// an explicit fma, so the result is the same in every kernel variant).
 template <int R>
 __device__ __forceinline__ double closure(const float2 (&v)[Layout<R>::M], float4 gx4, float4 gy4) {
   constexpr int M = Layout<R>::M;
@@ -162,10 +163,10 @@ __device__ __forceinline__ double closure(const float2 (&v)[Layout<R>::M], float
   const double gxr = gx4.x, gxi = gx4.y, gyr = gy4.x, gyi = -double(gy4.y);  // conj(g_y)
 #pragma unroll
   for (int m = 1; m <= R; ++m) {
-    pxr[m] = pxr[m - 1] * gxr - pxi[m - 1] * gxi;
-    pxi[m] = pxr[m - 1] * gxi + pxi[m - 1] * gxr;
-    pyr[m] = pyr[m - 1] * gyr - pyi[m - 1] * gyi;
-    pyi[m] = pyr[m - 1] * gyi + pyi[m - 1] * gyr;
+    pxr[m] = fma(pxr[m - 1], gxr, -(pxi[m - 1] * gxi));
+    pxi[m] = fma(pxr[m - 1], gxi, pxi[m - 1] * gxr);
+    pyr[m] = fma(pyr[m - 1], gyr, -(pyi[m - 1] * gyi));
+    pyi[m] = fma(pyr[m - 1], gyi, pyi[m - 1] * gyr);
   }
   double sr = 0.0, si = 0.0;
 #pragma unroll
@@ -173,12 +174,13 @@ __device__ __forceinline__ double closure(const float2 (&v)[Layout<R>::M], float
     const int s = (q >> Layout<R>::S) & 1;
     const int hk = __builtin_popcount(q & LOWMASK) + s;
     const int hb = __builtin_popcount((q >> (R - 1)) & LOWMASK) + s;
-    const double wr = pxr[hk] * pyr[hb] - pxi[hk] * pyi[hb];
-    const double wi = pxr[hk] * pyi[hb] + pxi[hk] * pyr[hb];
-    sr += wr * double(v[q].x) - wi * double(v[q].y);
-    si += wr * double(v[q].y) + wi * double(v[q].x);
+    const double wr = fma(pxr[hk], pyr[hb], -(pxi[hk] * pyi[hb]));
+    const double wi = fma(pxr[hk], pyi[hb], pxi[hk] * pyr[hb]);
+    const double vx = v[q].x, vy = v[q].y;
+    sr = fma(wr, vx, fma(-wi, vy, sr));
+    si = fma(wr, vy, fma(wi, vx, si));
   }
-  return sr * sr + si * si;
+  return fma(sr, sr, si * si);
 }
 
 // One work item: the PI wave-uniform ket points i0 .. i0+PI-1 against the 64

@@ -148,7 +148,7 @@ sweep_dense_kernel(SweepArgs a) {
           sr += double(e[t][p][q].x);
           si += double(e[t][p][q].y);
         }
-    s2 = sr * sr + si * si;
+    s2 = fma(sr, sr, si * si);
   }
   store_entry(a, i, j, s2, 2 * acc);
 }

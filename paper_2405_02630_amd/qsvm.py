@@ -90,7 +90,8 @@ class MlpGrads(ctypes.Structure):
 
     _fields_ = [("dW1", ctypes.c_void_p), ("db1", ctypes.c_void_p), ("dW2", ctypes.c_void_p),
                 ("db2", ctypes.c_void_p), ("dW3", ctypes.c_void_p), ("db3", ctypes.c_void_p),
-                ("dH1", ctypes.c_void_p), ("dH2", ctypes.c_void_p)]
+                ("dH1", ctypes.c_void_p), ("dH2", ctypes.c_void_p), ("ws", ctypes.c_void_p),
+                ("ws_floats", ctypes.c_int64)]
 
 
 class QsvmError(RuntimeError):
@@ -148,6 +149,8 @@ def load_library(path: str = LIB_PATH):
     lib.qsvm_pair_head.restype = i32
     lib.qsvm_mlp_backward.argtypes = [P(Mlp), vp, P(MlpActs), vp, i64, P(MlpGrads), vp]
     lib.qsvm_mlp_backward.restype = i32
+    lib.qsvm_mlp_workspace_floats.argtypes = [P(Mlp), i64]
+    lib.qsvm_mlp_workspace_floats.restype = i64
     lib.qsvm_adamw.argtypes = [vp, vp, vp, vp, vp, i64, f32, f32, f32, f32, f32, i32, vp]
     lib.qsvm_adamw.restype = i32
     lib.qsvm_surrogate_gram.argtypes = [vp, i64, i64, i32, vp, vp, i64, vp, vp]
@@ -390,6 +393,10 @@ def qsvm_pair_head(E, pairs: int, d: int, target, alpha_beta, dE16, partial, out
 def qsvm_mlp_backward(net: Mlp, X16, acts: MlpActs, dE16, rows: int, grads: MlpGrads, stream=None):
     _check(load_library().qsvm_mlp_backward(ctypes.byref(net), _p(X16), ctypes.byref(acts), _p(dE16), rows,
                                             ctypes.byref(grads), _stream_ptr(stream)))
+
+
+def qsvm_mlp_workspace_floats(net: Mlp, rows: int) -> int:
+    return int(load_library().qsvm_mlp_workspace_floats(ctypes.byref(net), rows))
 
 
 def qsvm_adamw(w, grad, m, v, w16, lr, beta1, beta2, eps, weight_decay, step, stream=None):

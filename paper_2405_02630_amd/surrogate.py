@@ -127,6 +127,7 @@ class Surrogate:
             "idx": torch.empty(rows, dtype=torch.int32, device=self.dev),
             "target": torch.empty(rows // 2, dtype=f32, device=self.dev),
         }
+        b["ws"] = torch.empty(max(1, qsvm.qsvm_mlp_workspace_floats(self.net(), rows)), dtype=f32, device=self.dev)
         self._bufs[rows] = b
         return b
 
@@ -137,7 +138,8 @@ class Surrogate:
     def _grads(self, b) -> qsvm.MlpGrads:
         p = self.params
         return qsvm.MlpGrads(p[0].g.data_ptr(), p[1].g.data_ptr(), p[2].g.data_ptr(), p[3].g.data_ptr(),
-                             p[4].g.data_ptr(), p[5].g.data_ptr(), b["dH1"].data_ptr(), b["dH2"].data_ptr())
+                             p[4].g.data_ptr(), p[5].g.data_ptr(), b["dH1"].data_ptr(), b["dH2"].data_ptr(),
+                             b["ws"].data_ptr(), b["ws"].numel())
 
     # ------------------------------------------------------------------
     def init_head_from_targets(self, mean_target: float) -> None:
