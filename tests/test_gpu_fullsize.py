@@ -1,0 +1,123 @@
+"""GPU parity at the benchmark's full sizes, maximum sizes and degenerate inputs.
+
+Full-size Grams are computed in the launch configuration bench.py times
+(default sweep, default variant and renormalisation interval) and checked on
+sampled entries that the FP64 MPS oracle computes one by one, plus the
+properties that hold at any size (exact symmetry, unit diagonal, range).
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import closed_forms, mps, statevector
+from paper_2405_02630_amd import qsvm, synth
+
+from gpu_helpers import K_ABS_TOL, LOG_TOL_MAX, encode, gram_rect, gram_sym, log_close, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    return require_gpu()
+
+
+def _sampled_check(X, K, L, pts, reps):
+    S = mps.mps_states(X[pts], reps, processes=8)
+    ia, jb = np.triu_indices(len(pts), 1)
+    lk, kk = mps.mps_gram_pairs(S, S, ia, jb)
+    assert np.max(np.abs(K[pts[ia], pts[jb]] - kk)) <= K_ABS_TOL
+    assert log_close(np.abs(L[pts[ia], pts[jb]] - lk))
+
+
+@pytest.mark.parametrize("reps", [2, 3])
+def test_images784_train_gram_full_size(reps):
+    """4096 points x 784 qubits: the benchmark's symmetric Gram."""
+    wl = synth.images784(seed=0, n_train=4096, n_test=0, reps=reps)
+    K, L = gram_sym(wl.X, reps)
+    assert np.array_equal(K, K.T) and np.all(np.diag(K) == 1.0)
+    assert K.min() >= 0.0 and K.max() <= 1.0
+    rng = np.random.default_rng(reps)
+    pts = np.sort(np.concatenate([[0, 63, 64, 4095], rng.choice(np.arange(1, 4095), 20, replace=False)]))
+    _sampled_check(wl.X, K, L, np.unique(pts), reps)
+
+
+def test_images784_test_by_train_full_size():
+    """1024 test x 4096 train points, rectangular Gram."""
+    wl = synth.images784(seed=0, n_train=4096, n_test=1024, reps=2)
+    K, L = gram_rect(wl.X_test, wl.X, 2)
+    rng = np.random.default_rng(5)
+    ti = np.sort(rng.choice(1024, 6, replace=False))
+    tj = np.sort(rng.choice(4096, 8, replace=False))
+    St = mps.mps_states(wl.X_test[ti], 2, processes=8)
+    Sr = mps.mps_states(wl.X[tj], 2, processes=8)
+    a, b = np.meshgrid(np.arange(6), np.arange(8), indexing="ij")
+    lk, kk = mps.mps_gram_pairs(St, Sr, a.ravel(), b.ravel())
+    assert np.max(np.abs(K[ti[a.ravel()], tj[b.ravel()]] - kk)) <= K_ABS_TOL
+    assert log_close(np.abs(L[ti[a.ravel()], tj[b.ravel()]] - lk))
+
+
+def test_images784_32768_points_sampled():
+    """The surrogate leg's exact whole-set Gram (32768 points): sampled entries,
+    symmetry and diagonal on a band of rows (the matrix is 8.6 GB)."""
+    import torch
+
+    wl = synth.images784(seed=5, n_train=32768, n_test=0, reps=2)
+    m = encode(wl.X, 2)
+    K = torch.empty((32768, 32768), dtype=torch.float64, device="cuda:0")
+    L = torch.empty_like(K)
+    qsvm.qsvm_gram_sym(m, K, log_k=L)
+    torch.cuda.synchronize()
+    pts = np.array([0, 1, 4097, 16384, 20000, 32702, 32767])
+    p = torch.as_tensor(pts, device="cuda:0")
+    Kp = K[p][:, p].cpu().numpy()
+    Lp = L[p][:, p].cpu().numpy()
+    S = mps.mps_states(wl.X[pts], 2, processes=7)
+    ia, jb = np.triu_indices(len(pts), 1)
+    lk, kk = mps.mps_gram_pairs(S, S, ia, jb)
+    assert np.max(np.abs(Kp[ia, jb] - kk)) <= K_ABS_TOL
+    assert log_close(np.abs(Lp[ia, jb] - lk))
+    band = K[16320:16448]
+    assert torch.equal(band[:, 16320:16448], band[:, 16320:16448].T)
+    assert torch.all(torch.diagonal(K) == 1.0)
+    del K, L
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("reps", [1, 2])
+def test_maximum_qubits_closed_forms(reps):
+    """n = 65535 qubits (the largest supported): entanglement-free inputs
+    against the product closed form, and one rep against the transfer form.
+    The bar on ln K grows with the chain: each site adds a relative rounding
+    of ~1e-7 to K, so up to 1e-7 |ln K| (a few 1e-3 here) on top of LOG_TOL_MAX."""
+    n = 65535
+    X = synth.pin_even_features(synth.uniform_features(3, n, seed=40 + reps))
+    _, L = gram_sym(X, reps)
+    for (i, j) in [(0, 1), (1, 2)]:
+        ref = closed_forms.k_product_log(X[i], X[j], reps)
+        assert abs(L[i, j] - ref) <= 1e-7 * abs(ref) + LOG_TOL_MAX
+    if reps == 1:
+        Y = synth.uniform_features(2, n, seed=50)
+        _, L1 = gram_sym(Y, 1)
+        ref, _ = closed_forms.k_reps1_transfer(Y[0], Y[1])
+        assert abs(L1[0, 1] - ref) <= 1e-7 * abs(ref) + LOG_TOL_MAX
+
+
+def test_degenerate_inputs():
+    # identical points: K = 1 off the diagonal too
+    x = synth.uniform_features(1, 30, seed=60)[0]
+    K, _ = gram_sym(np.stack([x, x, x]), 2, diag_mode=1)
+    assert np.max(np.abs(K - 1.0)) <= K_ABS_TOL
+    # all features pi: theta = 0 and P(2 pi) = I, so every rep is H^n and both
+    # points have the same state H^r |0..0>
+    K, _ = gram_sym(np.full((2, 12), math.pi), 3, diag_mode=1)
+    assert np.max(np.abs(K - 1.0)) <= K_ABS_TOL
+    # orthogonal one-qubit states: cos^2(pi/2) = 0
+    K, _ = gram_rect(np.array([[0.5 * math.pi]]), np.array([[0.0]]), 1)
+    assert K[0, 0] <= 1e-12
+    # all-zero features (theta = 2 pi^2 on every bond) against the state vector
+    X = np.vstack([np.zeros(9), synth.uniform_features(3, 9, seed=61)])
+    K, _ = gram_sym(X, 2, diag_mode=1)
+    assert np.max(np.abs(K - statevector.sv_gram(X, 2))) <= K_ABS_TOL
