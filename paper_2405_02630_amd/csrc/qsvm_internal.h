@@ -16,7 +16,7 @@ inline int64_t dense_bytes(int64_t N, int32_t n, int32_t reps) {
 hipError_t launch_encode(const double* X, int64_t N, int32_t n, int32_t reps, void* mps,
                          hipStream_t stream);
 struct SweepArgs;
-constexpr int kButterflyVariants = 4;  // per reps, see launch_sweep_butterfly_args
+constexpr int kButterflyVariants = 8;  // per reps, see launch_sweep_butterfly_args
 hipError_t launch_sweep_butterfly_args(const SweepArgs& a, int32_t reps, int32_t variant, hipStream_t stream);
 // Autotuned variant table (autotune.cpp).
 int32_t tuned_variant(int32_t reps, int32_t n);

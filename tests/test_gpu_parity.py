@@ -132,6 +132,31 @@ def test_rect_gram_vs_state_vector(sweep, reps):
     assert log_close(_log_err(L, np.log(ref)))
 
 
+@pytest.mark.parametrize("reps", [1, 2, 3])
+@pytest.mark.parametrize("n,N", [(1, 5), (7, 130), (11, 67)])
+def test_sign_tracked_form_vs_state_vector(reps, n, N):
+    """The sign-tracked butterfly form (variants 5..8) against the oracle."""
+    X = synth.uniform_features(N, n, seed=2000 + 10 * n + reps)
+    ref = statevector.sv_gram(X, reps)
+    for v in (5, 8):
+        K, L = gram_sym(X, reps, diag_mode=1, variant=v)
+        assert np.max(np.abs(K - ref)) <= K_ABS_TOL
+        pos = ref > 1e-200
+        assert log_close(_log_err(L[pos], np.log(ref[pos])))
+
+
+@pytest.mark.parametrize("reps", [2, 3])
+def test_sign_tracked_form_784_vs_mps(reps):
+    wl = synth.images784(seed=12, n_train=130, n_test=0, reps=reps)
+    pts = np.array([0, 3, 63, 64, 100, 129])
+    S = mps.mps_states(wl.X[pts], reps)
+    ia, jb = np.triu_indices(len(pts), 1)
+    lk_ref, k_ref = mps.mps_gram_pairs(S, S, ia, jb)
+    K, L = gram_sym(wl.X, reps, variant=6)
+    assert log_close(_log_err(L[pts[ia], pts[jb]], lk_ref))
+    assert np.max(np.abs(K[pts[ia], pts[jb]] - k_ref)) <= K_ABS_TOL
+
+
 def test_single_point_and_single_qubit():
     X = np.array([[0.3]])
     K, L = gram_sym(X, 2)
