@@ -72,17 +72,15 @@ typedef enum {
 typedef struct {
   int32_t renorm_every; /* sites between power-of-two renormalisations of the
                            environment (exact rescaling, exponent kept in an
-                           integer log2 accumulator); 0 = default (4), else 1..16 */
+                           integer log2 accumulator); 0 = default (8), else 1..16 */
   int32_t sweep;        /* qsvm_sweep_kind */
   int32_t diag_mode;    /* qsvm_gram_sym only: 0 = K[i][i] := 1 exactly (Alg. 1-3);
                            1 = compute the self-overlaps like any other pair */
   int32_t variant;      /* butterfly kernel variant: 0 = the tuned choice for this
                            reps and size (qsvm_autotune) or the built-in default;
-                           1..8 = force variant 0..7: ket points per lane and
-                           register budget (variant mod 4) x butterfly form
-                           (0..3 sign-folded, 4..7 sign-tracked; the two forms
-                           round differently, variants of one form agree
-                           bitwise); the dense sweep ignores it */
+                           1..4 = force variant 0..3 (ket points per lane and
+                           register budget; all agree bitwise); the dense
+                           sweep ignores it */
   int64_t row_begin;    /* compute only rows i in [row_begin, row_end) of K;   */
   int64_t row_end;      /* 0,0 = all rows.  For qsvm_gram_sym a row i covers the
                            pairs (i, j > i) and writes K[i][j], K[j][i], and
@@ -232,15 +230,14 @@ qsvm_status qsvm_batch_plan_info(const qsvm_batch_plan* plan, int64_t* total_ite
 
 /*
  * Autotune the butterfly sweep for (reps, n_qubits, N) on the current device:
- * every kernel variant (ket points per lane x register budget x butterfly
- * form) is timed on a
+ * every kernel variant (ket points per lane x register budget) is timed on a
  * synthetic symmetric Gram of that shape (features from a fixed hash, uniform
  * in [0, pi)), and the fastest is recorded in the per-process table that
  * launches with opts.variant == 0 consult, keyed by reps and floor(log2 n).
  * Allocates and frees its own device scratch (N x N doubles plus the MPS)
  * and synchronises `stream`; N <= 65536.
- *   best_variant  optional output: the chosen variant (0..7).
- *   variant_ms    optional output of n_variant_ms >= 8 floats: mean launch
+ *   best_variant  optional output: the chosen variant (0..3).
+ *   variant_ms    optional output of n_variant_ms >= 4 floats: mean launch
  *                 time of each variant in milliseconds.
  */
 qsvm_status qsvm_autotune(int32_t reps, int32_t n_qubits, int64_t N, void* stream, int32_t* best_variant,

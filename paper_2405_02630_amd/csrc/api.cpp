@@ -19,8 +19,6 @@ thread_local std::string g_last_error;
 
 constexpr int64_t kMaxN = (int64_t(1) << 31) - 1;
 constexpr int32_t kMaxQubits = 65535;
-constexpr int32_t kDefaultRenorm = 4;
-constexpr int32_t kMaxRenorm = 16;
 
 qsvm_status fail(qsvm_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 
@@ -61,7 +59,7 @@ qsvm_status hip_status(hipError_t e, const char* what) {
 }
 
 struct Opts {
-  int32_t renorm_every = kDefaultRenorm;
+  int32_t renorm_every = qsvm::kDefaultRenorm;
   int32_t sweep = QSVM_SWEEP_BUTTERFLY;
   int32_t diag_mode = 0;
   int32_t variant = 0;
@@ -73,8 +71,8 @@ qsvm_status read_opts(const qsvm_gram_opts* o, int64_t rows, Opts& out, const ch
   out = Opts{};
   out.row_end = rows;
   if (!o) return QSVM_OK;
-  if (o->renorm_every < 0 || o->renorm_every > kMaxRenorm)
-    return fail(QSVM_ERR_INVALID_ARG, "%s: renorm_every = %d outside [0, %d]", what, o->renorm_every, kMaxRenorm);
+  if (o->renorm_every < 0 || o->renorm_every > qsvm::kMaxRenorm)
+    return fail(QSVM_ERR_INVALID_ARG, "%s: renorm_every = %d outside [0, %d]", what, o->renorm_every, qsvm::kMaxRenorm);
   if (o->renorm_every) out.renorm_every = o->renorm_every;
   if (o->sweep < QSVM_SWEEP_AUTO || o->sweep > QSVM_SWEEP_DENSE)
     return fail(QSVM_ERR_INVALID_ARG, "%s: unknown sweep kind %d", what, o->sweep);

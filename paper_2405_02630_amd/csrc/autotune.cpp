@@ -96,7 +96,7 @@ hipError_t autotune_run(int32_t reps, int32_t n, int64_t N, hipStream_t stream, 
     a.row_begin = 0;
     a.row_end = N;
     a.n = n;
-    a.renorm_every = 4;
+    a.renorm_every = kDefaultRenorm;
     a.sym = 1;
     a.tile_row0 = 0;
     a.tiles_b = a.tile_rows = int32_t((N + kTile - 1) / kTile);

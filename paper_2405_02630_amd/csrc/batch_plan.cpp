@@ -129,7 +129,7 @@ extern "C" qsvm_status qsvm_batch_plan_create(const qsvm_job* jobs, int32_t n_jo
   if (!jobs || n_jobs < 1) return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_batch_plan_create: no jobs");
   qsvm_batch_opts o{};
   if (opts) o = *opts;
-  if (o.renorm_every < 0 || o.renorm_every > 16)
+  if (o.renorm_every < 0 || o.renorm_every > kMaxRenorm)
     return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_batch_plan_create: renorm_every outside [0, 16]");
   if (o.diag_mode != 0 && o.diag_mode != 1)
     return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_batch_plan_create: diag_mode must be 0 or 1");
@@ -144,7 +144,7 @@ extern "C" qsvm_status qsvm_batch_plan_create(const qsvm_job* jobs, int32_t n_jo
   }
   std::vector<BatchJob> table;
   int64_t total = 0;
-  if (!build_jobs(jobs, n_jobs, o.renorm_every ? o.renorm_every : 4, o.diag_mode, table, total, msg, sizeof msg))
+  if (!build_jobs(jobs, n_jobs, o.renorm_every ? o.renorm_every : kDefaultRenorm, o.diag_mode, table, total, msg, sizeof msg))
     return api_fail(QSVM_ERR_INVALID_ARG, msg);
   if (api_injected_failure()) return api_fail(QSVM_ERR_HIP, "qsvm_batch_plan_create: injected launch failure (QSVM_FAULT_INJECT=launch)");
 

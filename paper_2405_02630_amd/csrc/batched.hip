@@ -22,8 +22,9 @@ namespace {
 
 constexpr int kBatchWaves = 4;  // target waves per SIMD of the persistent kernel
 
-// Pairs of ket points per lane of each reps in the batched kernel.
-__host__ __device__ constexpr int batch_pi(int reps) { return reps == 1 ? 8 : (reps == 2 ? 4 : 1); }
+// Ket points per lane of each reps in the batched kernel (those of the default
+// single-launch variants).
+__host__ __device__ constexpr int batch_pi(int reps) { return reps == 1 ? 4 : (reps == 2 ? 2 : 1); }
 
 __global__ void reset_counter(unsigned int* counter) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;

@@ -16,7 +16,16 @@ inline int64_t dense_bytes(int64_t N, int32_t n, int32_t reps) {
 hipError_t launch_encode(const double* X, int64_t N, int32_t n, int32_t reps, void* mps,
                          hipStream_t stream);
 struct SweepArgs;
-constexpr int kButterflyVariants = 8;  // per reps, see launch_sweep_butterfly_args
+constexpr int kButterflyVariants = 4;  // per reps, see launch_sweep_butterfly_args
+// Sites between power-of-two renormalisations of the FP32 environment: the
+// default and the largest accepted interval.  Within one interval the
+// largest entry can grow by at most 2^(2r-1) per site (each butterfly axis at
+// most doubles it), 2^80 over 16 sites at r = 3, far from FP32 overflow; it
+// underflows the FP32 normal range only if it shrinks by more than 2^-125
+// within one interval, i.e. by a factor below 2^-15.6 per site on average
+// over 8 sites.
+constexpr int32_t kDefaultRenorm = 8;
+constexpr int32_t kMaxRenorm = 16;
 hipError_t launch_sweep_butterfly_args(const SweepArgs& a, int32_t reps, int32_t variant, hipStream_t stream);
 // Autotuned variant table (autotune.cpp).
 int32_t tuned_variant(int32_t reps, int32_t n);

@@ -56,49 +56,6 @@ __device__ __forceinline__ void bfly(float2& u0, float2& u1, float ar, float ai,
   u1 = make_float2(t1r, t1i);
 }
 
-// Complex coefficient with its negations in registers, so that products can be
-// accumulated with plain (modifier-free) fused multiply-adds.
-struct Coef {
-  float re, nre, im, nim;  // re, -re, im, -im
-};
-
-// The empty asm statements hide that the four values are negations of each
-// other, so the compiler keeps them as operands of accumulating fmac (VOP2)
-// instead of folding the signs into source modifiers of three-operand fma
-// (VOP3).  UNIFORM: the value is the same in every lane (kept in SGPRs).
-template <bool UNIFORM>
-__device__ __forceinline__ float opaque(float x) {
-  if constexpr (UNIFORM) {
-    x = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
-    asm volatile("" : "+s"(x));
-  } else
-    asm volatile("" : "+v"(x));
-  return x;
-}
-
-template <bool UNIFORM>
-__device__ __forceinline__ Coef make_coef(float re, float im) {
-  return Coef{opaque<UNIFORM>(re), opaque<UNIFORM>(-re), opaque<UNIFORM>(im), opaque<UNIFORM>(-im)};
-}
-
-// Sign-tracked form: (u0, u1) -> (u0 + k0 u1, u0 + k1 u1) with k = SIGN * c and
-// the result of the second output written over u0 (accumulate in place).
-template <int SIGN>
-__device__ __forceinline__ void bfly_acc(float2& u0, float2& u1, const Coef& c0, const Coef& c1) {
-  const float k0r = SIGN > 0 ? c0.re : c0.nre, k0i = SIGN > 0 ? c0.im : c0.nim, k0n = SIGN > 0 ? c0.nim : c0.im;
-  const float k1r = SIGN > 0 ? c1.re : c1.nre, k1i = SIGN > 0 ? c1.im : c1.nim, k1n = SIGN > 0 ? c1.nim : c1.im;
-  float t0r = fmaf(k0r, u1.x, u0.x);
-  t0r = fmaf(k0n, u1.y, t0r);
-  float t0i = fmaf(k0r, u1.y, u0.y);
-  t0i = fmaf(k0i, u1.x, t0i);
-  float t1r = fmaf(k1r, u1.x, u0.x);
-  t1r = fmaf(k1n, u1.y, t1r);
-  float t1i = fmaf(k1r, u1.y, u0.y);
-  t1i = fmaf(k1i, u1.x, t1i);
-  u0 = make_float2(t0r, t0i);
-  u1 = make_float2(t1r, t1i);
-}
-
 template <int R>
 struct Layout {
   static constexpr int NB = 2 * R - 1;      // index bits of the environment
@@ -142,59 +99,6 @@ struct Axes {
   }
 };
 
-// One ket or bra bit axis in the sign-tracked form.  The tracked signs start
-// each site in the pattern (-1)^(sum of products of neighbouring column bits),
-// and the coefficient sign of butterfly (i0, i1) on axis l is then the next
-// bit along the same column chain (bit l+1 of that side, or the shared bit s
-// after the last one); the shared-bit axis needs no negation.
-template <int R, int AXBIT, int SIGNBIT>
-__device__ __forceinline__ void axis_tracked(float2 (&v)[Layout<R>::M], const Coef& c0, const Coef& c1) {
-  constexpr int M = Layout<R>::M;
-#pragma unroll
-  for (int i0 = 0; i0 < M; ++i0) {
-    if (i0 & (1 << AXBIT)) continue;
-    const int i1 = i0 | (1 << AXBIT);
-    if ((i0 >> SIGNBIT) & 1)
-      bfly_acc<-1>(v[i0], v[i1], c0, c1);
-    else
-      bfly_acc<+1>(v[i0], v[i1], c0, c1);
-  }
-}
-
-template <int R, int L>
-struct AxesTracked {
-  __device__ __forceinline__ static void ket(float2 (&v)[Layout<R>::M], const Coef& a, const Coef& b) {
-    if constexpr (L <= R - 1) {
-      axis_tracked<R, Layout<R>::ket_bit(L), (L < R - 1 ? Layout<R>::ket_bit(L + 1) : Layout<R>::S)>(v, a, b);
-      AxesTracked<R, L + 1>::ket(v, a, b);
-    }
-  }
-  __device__ __forceinline__ static void bra(float2 (&v)[Layout<R>::M], const Coef& a, const Coef& b) {
-    if constexpr (L <= R - 1) {
-      axis_tracked<R, Layout<R>::bra_bit(L), (L < R - 1 ? Layout<R>::bra_bit(L + 1) : Layout<R>::S)>(v, a, b);
-      AxesTracked<R, L + 1>::bra(v, a, b);
-    }
-  }
-};
-
-template <int R>
-__device__ __forceinline__ void site_step_tracked(float2 (&v)[Layout<R>::M], const float4& cx, const float4& cy) {
-  AxesTracked<R, 1>::ket(v, make_coef<true>(cx.x, cx.y), make_coef<true>(cx.z, cx.w));
-  AxesTracked<R, 1>::bra(v, make_coef<false>(cy.x, -cy.y), make_coef<false>(cy.z, -cy.w));
-  // shared top bit: all coefficient signs are + in the tracked pattern
-  const float asr = fmaf(cx.x, cy.x, cx.y * cy.y);
-  const float asi = fmaf(cx.y, cy.x, -(cx.x * cy.y));
-  const float bsr = fmaf(cx.z, cy.z, cx.w * cy.w);
-  const float bsi = fmaf(cx.w, cy.z, -(cx.z * cy.w));
-  constexpr int M = Layout<R>::M;
-  const Coef as = make_coef<false>(asr, asi), bs = make_coef<false>(bsr, bsi);
-#pragma unroll
-  for (int i0 = 0; i0 < M; ++i0) {
-    if (i0 & (1 << Layout<R>::S)) continue;
-    bfly_acc<+1>(v[i0], v[i0 | (1 << Layout<R>::S)], as, bs);
-  }
-}
-
 template <int R>
 __device__ __forceinline__ void site_step(float2 (&v)[Layout<R>::M], const float4& cx, const float4& cy) {
   Axes<R, 1>::ket(v, cx);
@@ -209,12 +113,33 @@ __device__ __forceinline__ void site_step(float2 (&v)[Layout<R>::M], const float
   axis<R, Layout<R>::S, SB1, SB2>(v, asr, asi, bsr, bsi);
 }
 
+// max(|a|, |b|, |c|) in one instruction (source modifiers take the absolute
+// values; the inputs are finite, so no NaN handling is needed).
+__device__ __forceinline__ float absmax3(float a, float b, float c) {
+  float r;
+  asm("v_max3_f32 %0, |%1|, |%2|, |%3|" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+
 template <int R>
 __device__ __forceinline__ int renorm(float2 (&v)[Layout<R>::M]) {
   constexpr int M = Layout<R>::M;
-  float m = 0.0f;
+  constexpr int F = 2 * M;  // real components
+  float f[F];
 #pragma unroll
-  for (int q = 0; q < M; ++q) m = fmaxf(m, fmaxf(fabsf(v[q].x), fabsf(v[q].y)));
+  for (int q = 0; q < M; ++q) {
+    f[2 * q] = v[q].x;
+    f[2 * q + 1] = v[q].y;
+  }
+  // largest |component|: a tree of three-input maxima
+  constexpr int P = (F + 2) / 3;
+  float part[P];
+#pragma unroll
+  for (int t = 0; t < P; ++t)
+    part[t] = absmax3(f[3 * t], f[3 * t + 1 < F ? 3 * t + 1 : F - 1], f[3 * t + 2 < F ? 3 * t + 2 : F - 1]);
+  float m = part[0];
+#pragma unroll
+  for (int t = 1; t < P; t += 2) m = absmax3(m, part[t], part[t + 1 < P ? t + 1 : P - 1]);
   const int e = __builtin_amdgcn_frexp_expf(m);  // m = f 2^e, f in [0.5, 1); 0 for m = 0
   // v * 2^-e, exact; ldexp per component stays correct even where 2^-e alone
   // would not be representable
@@ -234,18 +159,6 @@ __device__ __forceinline__ constexpr int col_sign_parity(int low, int s) {
   return __builtin_popcount(c & (c >> 1)) & 1;
 }
 
-// Static sign of entry q under sign tracking (stored value = sign * value):
-// the pattern (-1)^(s (sum of the lower ket bits' top + lower bra bits' top))
-// that the plain form starts from, which one site maps back onto itself.
-template <int R>
-__device__ __forceinline__ constexpr int tracked_sign_parity(int q) {
-  constexpr int LOWMASK = (1 << (R - 1)) - 1;
-  const int ket = q & LOWMASK;
-  const int bra = (q >> (R - 1)) & LOWMASK;
-  const int s = (q >> Layout<R>::S) & 1;
-  return col_sign_parity<R>(ket, s) ^ col_sign_parity<R>(bra, s);
-}
-
 template <int R>
 __device__ __forceinline__ void init_env(float2 (&v)[Layout<R>::M]) {
   constexpr int M = Layout<R>::M;
@@ -261,9 +174,8 @@ __device__ __forceinline__ void init_env(float2 (&v)[Layout<R>::M]) {
 }
 
 // |sum_q g_x^|c| conj(g_y)^|c'| v[q]|^2 in FP64 (every product-sum written as
-// an explicit fma, so the result is the same in every kernel variant).  In
-// the sign-tracked form (TRACKED) entry q holds sign(q) times its value.
-template <int R, bool TRACKED = false>
+// an explicit fma, so the result is the same in every kernel variant).
+template <int R>
 __device__ __forceinline__ double closure(const float2 (&v)[Layout<R>::M], float4 gx4, float4 gy4) {
   constexpr int M = Layout<R>::M;
   constexpr int LOWMASK = (1 << (R - 1)) - 1;
@@ -285,8 +197,7 @@ __device__ __forceinline__ double closure(const float2 (&v)[Layout<R>::M], float
     const int hb = __builtin_popcount((q >> (R - 1)) & LOWMASK) + s;
     const double wr = fma(pxr[hk], pyr[hb], -(pxi[hk] * pyi[hb]));
     const double wi = fma(pxr[hk], pyi[hb], pxi[hk] * pyr[hb]);
-    const double sg = (TRACKED && tracked_sign_parity<R>(q)) ? -1.0 : 1.0;
-    const double vx = sg * double(v[q].x), vy = sg * double(v[q].y);
+    const double vx = v[q].x, vy = v[q].y;
     sr = fma(wr, vx, fma(-wi, vy, sr));
     si = fma(wr, vy, fma(wi, vx, si));
   }
@@ -295,10 +206,7 @@ __device__ __forceinline__ double closure(const float2 (&v)[Layout<R>::M], float
 
 // One work item: the PI wave-uniform ket points i0 .. i0+PI-1 against the 64
 // bra points j0 + lane, over all sites; writes their entries.
-// FORM 0: butterflies with the sign pattern folded into FMA negations;
-// FORM 1: sign-tracked butterflies with register coefficients (modifier-free
-// accumulating FMAs).  Both compute the same values; their roundings differ.
-template <int R, int PI, int FORM = 0>
+template <int R, int PI>
 __device__ __forceinline__ void butterfly_item(const SweepArgs& a, int64_t i0, int64_t j0) {
   constexpr int M = Layout<R>::M;
   const int lane = threadIdx.x & 63;
@@ -323,12 +231,7 @@ __device__ __forceinline__ void butterfly_item(const SweepArgs& a, int64_t i0, i
   int32_t acc[PI];
 #pragma unroll
   for (int p = 0; p < PI; ++p) {
-    if (FORM == 1) {
-#pragma unroll
-      for (int q = 0; q < M; ++q) v[p][q] = make_float2(1.0f, 0.0f);  // sign * sign
-    } else {
-      init_env<R>(v[p]);
-    }
+    init_env<R>(v[p]);
     acc[p] = 0;
   }
 
@@ -349,10 +252,7 @@ __device__ __forceinline__ void butterfly_item(const SweepArgs& a, int64_t i0, i
       for (int p = 0; p < PI; ++p) cx_next[p] = gA[int64_t(kn) * a.Na + ic[p]];
 #pragma unroll
       for (int p = 0; p < PI; ++p) {
-        if (FORM == 1)
-          site_step_tracked<R>(v[p], cx[p], cy);
-        else
-          site_step<R>(v[p], cx[p], cy);
+        site_step<R>(v[p], cx[p], cy);
       }
       if (--countdown == 0) {
 #pragma unroll
@@ -372,7 +272,7 @@ __device__ __forceinline__ void butterfly_item(const SweepArgs& a, int64_t i0, i
   for (int p = 0; p < PI; ++p) {
     const int64_t i = i0 + p;
     if (pair_active(a, i, j)) {
-      const double s2 = comp[0] ? closure<R, FORM == 1>(v[0], gA[ic[0]], gy) : 1.0;
+      const double s2 = comp[0] ? closure<R>(v[0], gA[ic[0]], gy) : 1.0;
       // amp = closure * 2^(acc - R n)  =>  K = s2 * 2^(2 (acc - R n))
       store_entry(a, i, j, s2, 2 * (acc[0] - R * a.n));
     }

@@ -226,7 +226,7 @@ def qsvm_encode_mps(X, reps: int, out=None, stream=None) -> MPS:
     return MPS(out, N, n, reps)
 
 
-N_VARIANTS = 8
+N_VARIANTS = 4
 
 
 def qsvm_autotune(reps: int, n_qubits: int, N: int, stream=None):

@@ -126,7 +126,7 @@ def test_gram_rect_validation(lib, no_inject):
 
 @pytest.mark.parametrize(
     "field,value",
-    [("renorm_every", -1), ("renorm_every", 17), ("sweep", 3), ("sweep", -1), ("diag_mode", 2), ("variant", 9), ("variant", -1)],
+    [("renorm_every", -1), ("renorm_every", 17), ("sweep", 3), ("sweep", -1), ("diag_mode", 2), ("variant", 5), ("variant", -1)],
 )
 def test_gram_opts_validation(lib, no_inject, field, value):
     o = qsvm.GramOpts()
@@ -234,11 +234,11 @@ def test_batch_plan_injected_failure(lib, monkeypatch):
 
 
 def test_tuned_variant_table(lib, no_inject):
-    assert lib.qsvm_set_tuned_variant(2, 300, 8) == qsvm.QSVM_ERR_INVALID_ARG
+    assert lib.qsvm_set_tuned_variant(2, 300, 4) == qsvm.QSVM_ERR_INVALID_ARG
     assert lib.qsvm_set_tuned_variant(5, 300, 1) == qsvm.QSVM_ERR_UNSUPPORTED
-    assert lib.qsvm_set_tuned_variant(2, 300, 7) == qsvm.QSVM_OK
-    assert lib.qsvm_get_tuned_variant(2, 300) == 7
-    assert lib.qsvm_get_tuned_variant(2, 511) == 7  # same log2 bucket
+    assert lib.qsvm_set_tuned_variant(2, 300, 3) == qsvm.QSVM_OK
+    assert lib.qsvm_get_tuned_variant(2, 300) == 3
+    assert lib.qsvm_get_tuned_variant(2, 511) == 3  # same log2 bucket
     assert lib.qsvm_get_tuned_variant(2, 512) == 0  # untuned bucket -> default
     assert lib.qsvm_set_tuned_variant(2, 300, 0) == qsvm.QSVM_OK
 

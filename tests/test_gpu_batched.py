@@ -12,7 +12,7 @@ import oracle
 from oracle import mps, statevector
 from paper_2405_02630_amd import qsvm, synth
 
-from gpu_helpers import K_ABS_TOL, encode, log_close, require_gpu
+from gpu_helpers import K_ABS_TOL, encode, require_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -146,10 +146,7 @@ def test_uneven_jobs_workload_bitwise():
 
 
 @pytest.mark.parametrize("reps", [1, 2, 3])
-def test_every_variant_is_bitwise_identical_within_its_form(reps):
-    """Variants 1..4 (sign-folded butterflies) agree bitwise, so do 5..8
-    (sign-tracked); the two forms round differently and agree to the parity
-    bars."""
+def test_every_variant_is_bitwise_identical(reps):
     import torch
 
     X = synth.uniform_features(150, 40, seed=reps)
@@ -161,14 +158,8 @@ def test_every_variant_is_bitwise_identical_within_its_form(reps):
         qsvm.qsvm_gram_sym(m, K, log_k=L, variant=v)
         outs.append((K, L))
     torch.cuda.synchronize()
-    half = qsvm.N_VARIANTS // 2
-    for form in (outs[:half], outs[half:]):
-        for K, L in form[1:]:
-            assert torch.equal(K, form[0][0]) and torch.equal(L, form[0][1])
-    (K0, L0), (K1, L1) = outs[0], outs[half]
-    assert torch.max(torch.abs(K0 - K1)).item() <= K_ABS_TOL
-    off = ~torch.eye(150, dtype=torch.bool, device="cuda:0")
-    assert log_close(torch.abs(L0 - L1)[off].cpu().numpy())
+    for K, L in outs[1:]:
+        assert torch.equal(K, outs[0][0]) and torch.equal(L, outs[0][1])
 
 
 def test_autotune_records_a_variant():

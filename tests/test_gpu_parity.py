@@ -134,27 +134,16 @@ def test_rect_gram_vs_state_vector(sweep, reps):
 
 @pytest.mark.parametrize("reps", [1, 2, 3])
 @pytest.mark.parametrize("n,N", [(1, 5), (7, 130), (11, 67)])
-def test_sign_tracked_form_vs_state_vector(reps, n, N):
-    """The sign-tracked butterfly form (variants 5..8) against the oracle."""
+def test_every_variant_vs_state_vector(reps, n, N):
+    """Every forced kernel variant against the oracle (the default one is
+    covered by the tests above)."""
     X = synth.uniform_features(N, n, seed=2000 + 10 * n + reps)
     ref = statevector.sv_gram(X, reps)
-    for v in (5, 8):
+    pos = ref > 1e-200
+    for v in range(1, qsvm.N_VARIANTS + 1):
         K, L = gram_sym(X, reps, diag_mode=1, variant=v)
-        assert np.max(np.abs(K - ref)) <= K_ABS_TOL
-        pos = ref > 1e-200
-        assert log_close(_log_err(L[pos], np.log(ref[pos])))
-
-
-@pytest.mark.parametrize("reps", [2, 3])
-def test_sign_tracked_form_784_vs_mps(reps):
-    wl = synth.images784(seed=12, n_train=130, n_test=0, reps=reps)
-    pts = np.array([0, 3, 63, 64, 100, 129])
-    S = mps.mps_states(wl.X[pts], reps)
-    ia, jb = np.triu_indices(len(pts), 1)
-    lk_ref, k_ref = mps.mps_gram_pairs(S, S, ia, jb)
-    K, L = gram_sym(wl.X, reps, variant=6)
-    assert log_close(_log_err(L[pts[ia], pts[jb]], lk_ref))
-    assert np.max(np.abs(K[pts[ia], pts[jb]] - k_ref)) <= K_ABS_TOL
+        assert np.max(np.abs(K - ref)) <= K_ABS_TOL, v
+        assert log_close(_log_err(L[pos], np.log(ref[pos]))), v
 
 
 def test_single_point_and_single_qubit():
@@ -270,6 +259,24 @@ def test_renorm_interval_changes_rounding_only(sweep):
     off = ~np.eye(70, dtype=bool)
     assert log_close(_log_err(L1[off], L4[off]))
     assert log_close(_log_err(L1[off], L16[off]))
+
+
+@pytest.mark.parametrize("renorm_every", [0, 16])
+def test_near_orthogonal_stretch_stays_in_range(renorm_every):
+    """Pairs whose one-qubit states are nearly orthogonal on every odd site
+    (|overlap| = sin(delta) per site, delta = 1e-4) shrink the environment by
+    ~1e-4 per odd site, 1e-16 per 8 sites: far below FP32 range without the
+    renormalisation, inside it with the default interval and with 16."""
+    n = 240
+    rng = np.random.default_rng(70)
+    x = synth.pin_even_features(rng.uniform(0.0, 0.5 * math.pi, (1, n)))[0]
+    y = x.copy()
+    y[1::2] = x[1::2] + 0.5 * math.pi - 1e-4
+    X = np.stack([x, y])
+    _, L = gram_sym(X, 1, renorm_every=renorm_every)
+    ref = closed_forms.k_product_log(x, y, 1)
+    assert ref < -2000.0
+    assert abs(L[0, 1] - ref) <= LOG_TOL_MAX
 
 
 @pytest.mark.parametrize("sweep", SWEEPS, ids=SWEEP_IDS)
