@@ -333,7 +333,7 @@ def main():
 
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1 "
-                                   "(multi-GPU sharding is a design in DESIGN.md, not built)"}))
+                                   "(sharding across GPUs is designed, not built)"}))
         sys.exit(2)
 
     import numpy as np

@@ -86,6 +86,32 @@ def test_images784_32768_points_sampled():
     torch.cuda.empty_cache()
 
 
+def test_gram_beyond_2_pow_31_entries():
+    """65536 points (8 qubits, r = 2): K has 4.3e9 entries (34 GB), so entry
+    offsets i * ldk + j pass 2^31; sampled entries in the far corner against
+    the state vector, symmetry of a far off-diagonal block and the diagonal."""
+    import torch
+
+    N, n = 65536, 8
+    X = synth.uniform_features(N, n, seed=80)
+    m = encode(X, 2)
+    K = torch.empty((N, N), dtype=torch.float64, device="cuda:0")
+    qsvm.qsvm_gram_sym(m, K)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(81)
+    pts = np.unique(np.concatenate([[0, 1, 46340, 46341, 65471, 65472, 65534, 65535],
+                                    rng.choice(N, 16, replace=False)]))
+    p = torch.as_tensor(pts, device="cuda:0")
+    Kp = K[p][:, p].cpu().numpy()
+    assert np.max(np.abs(Kp - statevector.sv_gram(X[pts], 2))) <= K_ABS_TOL
+    far = K[N - 64:, N - 64:]
+    assert torch.equal(far, far.T)
+    assert torch.equal(K[N - 64:, :64], K[:64, N - 64:].T)
+    assert torch.all(torch.diagonal(K) == 1.0)
+    del K
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("reps", [1, 2])
 def test_maximum_qubits_closed_forms(reps):
     """n = 65535 qubits (the largest supported): entanglement-free inputs
