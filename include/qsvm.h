@@ -31,8 +31,11 @@
  *     call; they surface at the caller's next synchronisation.  Launch
  *     failures return QSVM_ERR_HIP.  qsvm_last_error() gives a message for
  *     the calling thread's most recent failure.
- *   - Supported: 1 <= n_qubits <= 65535, reps in {1, 2, 3} (chi = 2, 4, 8),
- *     1 <= N < 2^31.  Other reps return QSVM_ERR_UNSUPPORTED.
+ *   - Supported: 1 <= n_qubits <= 65535, reps in {1, 2, 3, 4} (chi = 2, 4,
+ *     8, 16), 1 <= N < 2^31.  Other reps return QSVM_ERR_UNSUPPORTED, as does
+ *     the dense sweep at reps = 4 and a batch plan with a reps = 4 job.  At
+ *     reps = 4 the butterfly sweep holds each pair's 128-entry environment in
+ *     two lanes (split on the shared physical bit).
  *   - No call throws across the ABI.  Results are bitwise reproducible for the
  *     same inputs, arguments and device (no floating-point atomics).
  */
@@ -49,7 +52,7 @@ extern "C" {
 typedef enum {
   QSVM_OK = 0,
   QSVM_ERR_INVALID_ARG = -1, /* null pointer, non-positive size, ldk too small, bad option */
-  QSVM_ERR_UNSUPPORTED = -2, /* valid request outside the supported range (e.g. reps > 3) */
+  QSVM_ERR_UNSUPPORTED = -2, /* valid request outside the supported range (e.g. reps > 4) */
   QSVM_ERR_HIP = -3,         /* a HIP runtime call or kernel launch failed */
   QSVM_ERR_SIZE = -4         /* a caller buffer is smaller than the call needs */
 } qsvm_status;
@@ -190,7 +193,8 @@ typedef struct {
   const void* mps;   /* device MPS buffer of the job (qsvm_encode_mps with N, n_qubits, reps) */
   int64_t N;         /* points */
   int32_t n_qubits;
-  int32_t reps;      /* 1..3; jobs may mix reps and sizes */
+  int32_t reps;      /* 1..3 (reps = 4 is QSVM_ERR_UNSUPPORTED here: use
+                        qsvm_gram / qsvm_gram_sym); jobs may mix reps and sizes */
   double* K;         /* device N x N output, row stride ldk >= N; written as by qsvm_gram_sym */
   int64_t ldk;
   double* log_k;     /* optional device N x N output (same stride), or NULL */

@@ -41,7 +41,8 @@ qsvm_status check_shape(int64_t N, int32_t n, int32_t reps, const char* what) {
   if (N < 1 || N > kMaxN) return fail(QSVM_ERR_INVALID_ARG, "%s: N = %lld outside [1, 2^31-1]", what, (long long)N);
   if (n < 1 || n > kMaxQubits) return fail(QSVM_ERR_INVALID_ARG, "%s: n_qubits = %d outside [1, 65535]", what, n);
   if (reps < 1) return fail(QSVM_ERR_INVALID_ARG, "%s: reps = %d must be >= 1", what, reps);
-  if (reps > 3) return fail(QSVM_ERR_UNSUPPORTED, "%s: reps = %d > 3 (bond dimension above 8) is not supported", what, reps);
+  if (reps > qsvm::kMaxReps)
+    return fail(QSVM_ERR_UNSUPPORTED, "%s: reps = %d > 4 (bond dimension above 16) is not supported", what, reps);
   return QSVM_OK;
 }
 
@@ -103,6 +104,8 @@ qsvm_status run_gram(const void* mps_a, int64_t Na, const void* mps_b, int64_t N
                      int32_t reps, double* K, int64_t ldk, const Opts& o, bool sym, void* stream,
                      const char* what) {
   using qsvm::kTile;
+  if (o.sweep == QSVM_SWEEP_DENSE && reps > 3)
+    return fail(QSVM_ERR_UNSUPPORTED, "%s: the dense sweep supports reps <= 3", what);
   if (o.row_end <= o.row_begin) return ok();  // empty row range: nothing to do
   qsvm::SweepArgs a{};
   a.gen_a = reinterpret_cast<const float4*>(static_cast<const char*>(mps_a) + qsvm::dense_bytes(Na, n, reps));
@@ -123,14 +126,14 @@ qsvm_status run_gram(const void* mps_a, int64_t Na, const void* mps_b, int64_t N
   a.tile_row0 = int32_t(o.row_begin / kTile);
   a.tile_rows = int32_t((o.row_end - 1) / kTile) - a.tile_row0 + 1;
   a.tiles_b = int32_t((Nb + kTile - 1) / kTile);
-  // launch-size limit: at most 16 blocks per tile, < 2^31 blocks
+  // launch-size limit: at most 32 blocks per tile, < 2^31 blocks
   const int64_t tiles = int64_t(a.tile_rows) * a.tiles_b;
-  if (tiles * 16 > (int64_t(1) << 31) - 8)
+  if (tiles * 32 > (int64_t(1) << 31) - 8)
     return fail(QSVM_ERR_UNSUPPORTED, "%s: %lld tiles exceed one launch", what, (long long)tiles);
   if (injected_launch_failure()) return fail(QSVM_ERR_HIP, "%s: injected launch failure (QSVM_FAULT_INJECT=launch)", what);
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = (o.sweep == QSVM_SWEEP_DENSE) ? qsvm::launch_sweep_dense_args(a, reps, s)
-                                                : qsvm::launch_sweep_butterfly_args(a, reps, pick_variant(o, reps, n), s);
+                                                : qsvm::launch_sweep_fast(a, reps, pick_variant(o, reps, n), s);
   return hip_status(e, what);
 }
 
@@ -147,7 +150,7 @@ bool api_injected_failure() { return injected_launch_failure(); }
 extern "C" {
 
 size_t qsvm_mps_bytes(int64_t N, int32_t n_qubits, int32_t reps) {
-  if (N < 1 || N > kMaxN || n_qubits < 1 || n_qubits > kMaxQubits || reps < 1 || reps > 3) return 0;
+  if (N < 1 || N > kMaxN || n_qubits < 1 || n_qubits > kMaxQubits || reps < 1 || reps > qsvm::kMaxReps) return 0;
   const int64_t chi = int64_t(1) << reps;
   return size_t(int64_t(n_qubits) * N * (chi * chi * 8 + 16));
 }
@@ -217,6 +220,8 @@ qsvm_status qsvm_gram_sym_tiles(const void* mps, int64_t N, int32_t n_qubits, in
   s = read_opts(opts, N, o, what);
   if (s != QSVM_OK) return s;
   if (o.row_begin != 0 || o.row_end != N) return fail(QSVM_ERR_INVALID_ARG, "%s: row ranges do not apply to tile lists", what);
+  if (o.sweep == QSVM_SWEEP_DENSE && reps > 3)
+    return fail(QSVM_ERR_UNSUPPORTED, "%s: the dense sweep supports reps <= 3", what);
   if (n_tiles == 0) return ok();
   if (injected_launch_failure()) return fail(QSVM_ERR_HIP, "%s: injected launch failure (QSVM_FAULT_INJECT=launch)", what);
   qsvm::SweepArgs a{};
@@ -238,7 +243,7 @@ qsvm_status qsvm_gram_sym_tiles(const void* mps, int64_t N, int32_t n_qubits, in
   a.tile_list = tiles;
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipError_t e = (o.sweep == QSVM_SWEEP_DENSE) ? qsvm::launch_sweep_dense_args(a, reps, st)
-                                                : qsvm::launch_sweep_butterfly_args(a, reps, pick_variant(o, reps, n_qubits), st);
+                                                : qsvm::launch_sweep_fast(a, reps, pick_variant(o, reps, n_qubits), st);
   return hip_status(e, what);
 }
 

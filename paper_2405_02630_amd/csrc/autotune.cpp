@@ -18,7 +18,7 @@ namespace {
 
 constexpr int kBuckets = 17;  // n-bucket = floor(log2 n), n <= 65535
 std::mutex g_table_mu;
-int8_t g_table[4][kBuckets];  // -1 = not tuned
+int8_t g_table[kMaxReps + 1][kBuckets];  // -1 = not tuned
 bool g_table_init = false;
 
 int bucket_of(int32_t n) {
@@ -50,7 +50,7 @@ __global__ void synth_features(double* X, int64_t count, uint64_t seed) {
 int32_t tuned_variant(int32_t reps, int32_t n) {
   std::lock_guard<std::mutex> lk(g_table_mu);
   ensure_init();
-  if (reps < 1 || reps > 3 || n < 1) return 0;
+  if (reps < 1 || reps > kMaxReps || n < 1) return 0;
   const int v = g_table[reps][bucket_of(n)];
   return v < 0 ? 0 : v;
 }
@@ -101,9 +101,9 @@ hipError_t autotune_run(int32_t reps, int32_t n, int64_t N, hipStream_t stream, 
     a.tile_row0 = 0;
     a.tiles_b = a.tile_rows = int32_t((N + kTile - 1) / kTile);
     for (int32_t v = 0; v < kButterflyVariants; ++v) {
-      QSVM_TRY(launch_sweep_butterfly_args(a, reps, v, stream));  // warm-up
+      QSVM_TRY(launch_sweep_fast(a, reps, v, stream));  // warm-up
       QSVM_TRY(hipEventRecord(e0, stream));
-      for (int r = 0; r < 3; ++r) QSVM_TRY(launch_sweep_butterfly_args(a, reps, v, stream));
+      for (int r = 0; r < 3; ++r) QSVM_TRY(launch_sweep_fast(a, reps, v, stream));
       QSVM_TRY(hipEventRecord(e1, stream));
       QSVM_TRY(hipEventSynchronize(e1));
       float ms = 0.f;

@@ -138,7 +138,8 @@ extern "C" qsvm_status qsvm_batch_plan_create(const qsvm_job* jobs, int32_t n_jo
   if (o.grid_blocks < 0) return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_batch_plan_create: grid_blocks < 0");
   for (int32_t q = 0; q < n_jobs; ++q) {
     if (jobs[q].reps > 3) {
-      snprintf(msg, sizeof msg, "qsvm_batch_plan_create: job %d: reps = %d > 3 is not supported", q, jobs[q].reps);
+      snprintf(msg, sizeof msg,
+               "qsvm_batch_plan_create: job %d: reps = %d > 3 is not supported in a batch plan", q, jobs[q].reps);
       return api_fail(QSVM_ERR_UNSUPPORTED, msg);
     }
   }

@@ -60,7 +60,10 @@ encode_kernel(const double* __restrict__ X, int64_t N, int32_t n,
     ti[m] = tr[m - 1] * st + ti[m - 1] * ct;
   }
   // 2^{-R/2}
-  const double scale = (R == 1) ? 0.70710678118654752440 : (R == 2) ? 0.5 : 0.35355339059327376220;
+  const double scale = (R == 1)   ? 0.70710678118654752440
+                       : (R == 2) ? 0.5
+                       : (R == 3) ? 0.35355339059327376220
+                                  : 0.25;
   float2* out = dense + (int64_t(k) * N + i) * (CHI * CHI);
 #pragma unroll
   for (int a = 0; a < CHI; ++a) {
@@ -111,6 +114,7 @@ hipError_t launch_encode(const double* X, int64_t N, int32_t n, int32_t reps, vo
     case 1: hipLaunchKernelGGL(encode_kernel<1>, grid, block, 0, stream, X, N, n, dense, gen); break;
     case 2: hipLaunchKernelGGL(encode_kernel<2>, grid, block, 0, stream, X, N, n, dense, gen); break;
     case 3: hipLaunchKernelGGL(encode_kernel<3>, grid, block, 0, stream, X, N, n, dense, gen); break;
+    case 4: hipLaunchKernelGGL(encode_kernel<4>, grid, block, 0, stream, X, N, n, dense, gen); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -26,7 +26,15 @@ constexpr int kButterflyVariants = 4;  // per reps, see launch_sweep_butterfly_a
 // over 8 sites.
 constexpr int32_t kDefaultRenorm = 8;
 constexpr int32_t kMaxRenorm = 16;
+constexpr int32_t kMaxReps = 4;        // chi = 16
 hipError_t launch_sweep_butterfly_args(const SweepArgs& a, int32_t reps, int32_t variant, hipStream_t stream);
+// reps = 4: the environment split across two lanes (sweep_split.hip).
+hipError_t launch_sweep_split_args(const SweepArgs& a, int32_t reps, int32_t variant, hipStream_t stream);
+// The fast (Section G) sweep for any supported reps.
+inline hipError_t launch_sweep_fast(const SweepArgs& a, int32_t reps, int32_t variant, hipStream_t stream) {
+  return reps <= 3 ? launch_sweep_butterfly_args(a, reps, variant, stream)
+                   : launch_sweep_split_args(a, reps, variant, stream);
+}
 // Autotuned variant table (autotune.cpp).
 int32_t tuned_variant(int32_t reps, int32_t n);
 void set_tuned_variant(int32_t reps, int32_t n, int32_t variant);

@@ -27,12 +27,7 @@ template <int R, int PI, int W>
 hipError_t launch_pi(const SweepArgs& a0, hipStream_t stream) {
   SweepArgs a = a0;
   a.blocks_per_tile = kTile / (4 * PI);
-  const int64_t tiles = a.tile_list ? int64_t(a.tile_rows)  // list length
-                        : a.sym ? (int64_t(a.tile_rows) * a.tiles_b -
-                                   (int64_t(a.tile_rows) * (a.tile_rows - 1)) / 2 -
-                                   int64_t(a.tile_rows) * a.tile_row0)
-                                : int64_t(a.tile_rows) * a.tiles_b;
-  const int64_t blocks = tiles * a.blocks_per_tile;
+  const int64_t blocks = launch_tiles(a) * a.blocks_per_tile;
   if (blocks <= 0) return hipSuccess;
   if (blocks > (int64_t(1) << 31) - 8) return hipErrorInvalidValue;
   a.num_blocks = uint32_t(blocks);

@@ -65,9 +65,9 @@ struct Layout {
   __host__ __device__ static constexpr int bra_bit(int l) { return R - 1 + l - 1; }  // l = 1..R-1
 };
 
-template <int R, int AXBIT, int SIGNBIT, int SIGNBIT2>
-__device__ __forceinline__ void axis(float2 (&v)[Layout<R>::M], float ar, float ai, float br, float bi) {
-  constexpr int M = Layout<R>::M;
+// One bit axis over an environment (or a lane's part of one) of M entries.
+template <int AXBIT, int SIGNBIT, int SIGNBIT2, int M>
+__device__ __forceinline__ void axis(float2 (&v)[M], float ar, float ai, float br, float bi) {
 #pragma unroll
   for (int i0 = 0; i0 < M; ++i0) {
     if (i0 & (1 << AXBIT)) continue;
@@ -82,18 +82,22 @@ __device__ __forceinline__ void axis(float2 (&v)[Layout<R>::M], float ar, float 
   }
 }
 
-// Ket axes and bra axes for l = 1..R-1 (compile-time recursion).
+// Ket axes and bra axes for l = 1..R-1 (compile-time recursion).  They act
+// on index bits below the shared bit only, so the same code serves the whole
+// environment (M = 2^(2R-1)) and a lane's half of it split on the shared bit.
 template <int R, int L>
 struct Axes {
-  __device__ __forceinline__ static void ket(float2 (&v)[Layout<R>::M], const float4& c) {
+  template <int M>
+  __device__ __forceinline__ static void ket(float2 (&v)[M], const float4& c) {
     if constexpr (L <= R - 1) {
-      axis<R, Layout<R>::ket_bit(L), (L >= 2 ? Layout<R>::ket_bit(L - 1) : -1), -1>(v, c.x, c.y, c.z, c.w);
+      axis<Layout<R>::ket_bit(L), (L >= 2 ? Layout<R>::ket_bit(L - 1) : -1), -1>(v, c.x, c.y, c.z, c.w);
       Axes<R, L + 1>::ket(v, c);
     }
   }
-  __device__ __forceinline__ static void bra(float2 (&v)[Layout<R>::M], const float4& c) {
+  template <int M>
+  __device__ __forceinline__ static void bra(float2 (&v)[M], const float4& c) {
     if constexpr (L <= R - 1) {
-      axis<R, Layout<R>::bra_bit(L), (L >= 2 ? Layout<R>::bra_bit(L - 1) : -1), -1>(v, c.x, -c.y, c.z, -c.w);
+      axis<Layout<R>::bra_bit(L), (L >= 2 ? Layout<R>::bra_bit(L - 1) : -1), -1>(v, c.x, -c.y, c.z, -c.w);
       Axes<R, L + 1>::bra(v, c);
     }
   }
@@ -110,7 +114,7 @@ __device__ __forceinline__ void site_step(float2 (&v)[Layout<R>::M], const float
   const float bsi = fmaf(cx.w, cy.z, -(cx.z * cy.w));
   constexpr int SB1 = (R >= 2) ? Layout<R>::ket_bit(R - 1) : -1;
   constexpr int SB2 = (R >= 2) ? Layout<R>::bra_bit(R - 1) : -1;
-  axis<R, Layout<R>::S, SB1, SB2>(v, asr, asi, bsr, bsi);
+  axis<Layout<R>::S, SB1, SB2>(v, asr, asi, bsr, bsi);
 }
 
 // max(|a|, |b|, |c|) in one instruction (source modifiers take the absolute
@@ -121,9 +125,9 @@ __device__ __forceinline__ float absmax3(float a, float b, float c) {
   return r;
 }
 
-template <int R>
-__device__ __forceinline__ int renorm(float2 (&v)[Layout<R>::M]) {
-  constexpr int M = Layout<R>::M;
+// Largest |component| of the M entries (a tree of three-input maxima).
+template <int M>
+__device__ __forceinline__ float absmax(const float2 (&v)[M]) {
   constexpr int F = 2 * M;  // real components
   float f[F];
 #pragma unroll
@@ -140,7 +144,14 @@ __device__ __forceinline__ int renorm(float2 (&v)[Layout<R>::M]) {
   float m = part[0];
 #pragma unroll
   for (int t = 1; t < P; t += 2) m = absmax3(m, part[t], part[t + 1 < P ? t + 1 : P - 1]);
-  const int e = __builtin_amdgcn_frexp_expf(m);  // m = f 2^e, f in [0.5, 1); 0 for m = 0
+  return m;
+}
+
+// Divide the entries by 2^e, e the exponent of m (m = f 2^e, f in [0.5, 1);
+// e = 0 for m = 0); returns e.
+template <int M>
+__device__ __forceinline__ int rescale(float2 (&v)[M], float m) {
+  const int e = __builtin_amdgcn_frexp_expf(m);
   // v * 2^-e, exact; ldexp per component stays correct even where 2^-e alone
   // would not be representable
 #pragma unroll
@@ -149,6 +160,11 @@ __device__ __forceinline__ int renorm(float2 (&v)[Layout<R>::M]) {
     v[q].y = __builtin_amdgcn_ldexpf(v[q].y, -e);
   }
   return e;
+}
+
+template <int R>
+__device__ __forceinline__ int renorm(float2 (&v)[Layout<R>::M]) {
+  return rescale(v, absmax(v));
 }
 
 // Sign of a bond column: (-1)^(sum_{l=1}^{r-1} c_l c_{l-1}) over the bits

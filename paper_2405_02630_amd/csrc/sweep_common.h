@@ -33,6 +33,16 @@ struct SweepArgs {
   const int32_t* tile_list;  // optional device list of (ti, tj) tiles (symmetric only)
 };
 
+// Tiles one launch covers: the list length, the upper triangle of the row
+// range (symmetric) or the full row range x column grid (rectangular).
+__host__ __device__ inline int64_t launch_tiles(const SweepArgs& a) {
+  if (a.tile_list) return a.tile_rows;
+  if (a.sym)
+    return int64_t(a.tile_rows) * a.tiles_b - (int64_t(a.tile_rows) * (a.tile_rows - 1)) / 2 -
+           int64_t(a.tile_rows) * a.tile_row0;
+  return int64_t(a.tile_rows) * a.tiles_b;
+}
+
 // Map the hardware block index to a logical block so that the blocks of one
 // tile run back to back on the same XCD (the dispatcher hands consecutive
 // block indices to the 8 XCDs round robin).  The grid is padded to a

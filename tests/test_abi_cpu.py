@@ -56,13 +56,13 @@ def test_opts_struct_layout():
     assert qsvm.GramOpts.log_k.offset == 32
 
 
-@pytest.mark.parametrize("N,n,reps", [(1, 1, 1), (32, 8, 2), (4096, 784, 2), (1024, 784, 3), (7, 3, 1)])
+@pytest.mark.parametrize("N,n,reps", [(1, 1, 1), (32, 8, 2), (4096, 784, 2), (1024, 784, 3), (7, 3, 1), (1024, 784, 4)])
 def test_mps_bytes_formula(N, n, reps):
     chi = 2**reps
     assert qsvm.qsvm_mps_bytes(N, n, reps) == n * N * (chi * chi * 8 + 16)
 
 
-@pytest.mark.parametrize("N,n,reps", [(0, 8, 2), (8, 0, 2), (8, 8, 0), (8, 8, 4), (-1, 8, 2), (8, 65536, 2), (2**31, 8, 2)])
+@pytest.mark.parametrize("N,n,reps", [(0, 8, 2), (8, 0, 2), (8, 8, 0), (8, 8, 5), (-1, 8, 2), (8, 65536, 2), (2**31, 8, 2)])
 def test_mps_bytes_rejects(N, n, reps):
     assert qsvm.qsvm_mps_bytes(N, n, reps) == 0
 
@@ -86,8 +86,8 @@ def test_encode_validation(lib, no_inject):
     assert _enc(lib, n=0) == qsvm.QSVM_ERR_INVALID_ARG
     assert _enc(lib, n=70000) == qsvm.QSVM_ERR_INVALID_ARG
     assert _enc(lib, reps=0) == qsvm.QSVM_ERR_INVALID_ARG
-    assert _enc(lib, reps=4) == qsvm.QSVM_ERR_UNSUPPORTED
-    assert b"reps = 4" in lib.qsvm_last_error()
+    assert _enc(lib, reps=5) == qsvm.QSVM_ERR_UNSUPPORTED
+    assert b"reps = 5" in lib.qsvm_last_error()
     assert _enc(lib, mps=ctypes.c_void_p(0x100008)) == qsvm.QSVM_ERR_INVALID_ARG  # misaligned
     assert _enc(lib, X=ctypes.c_void_p(0x100004)) == qsvm.QSVM_ERR_INVALID_ARG
     need = qsvm.qsvm_mps_bytes(8, 4, 2)
@@ -121,7 +121,15 @@ def test_gram_rect_validation(lib, no_inject):
     assert _rect(lib, Na=0) == qsvm.QSVM_ERR_INVALID_ARG
     assert _rect(lib, Nb=-3) == qsvm.QSVM_ERR_INVALID_ARG
     assert _rect(lib, ldk=69) == qsvm.QSVM_ERR_INVALID_ARG
-    assert _rect(lib, reps=4) == qsvm.QSVM_ERR_UNSUPPORTED
+    assert _rect(lib, reps=5) == qsvm.QSVM_ERR_UNSUPPORTED
+
+
+def test_dense_sweep_rejects_reps_4(lib, no_inject):
+    opts = qsvm.GramOpts()
+    opts.sweep = qsvm.SWEEP_DENSE
+    assert _sym(lib, reps=4, opts=opts) == qsvm.QSVM_ERR_UNSUPPORTED
+    assert b"dense sweep" in lib.qsvm_last_error()
+    assert _rect(lib, reps=4, opts=opts) == qsvm.QSVM_ERR_UNSUPPORTED
 
 
 @pytest.mark.parametrize(
@@ -245,6 +253,6 @@ def test_tuned_variant_table(lib, no_inject):
 
 def test_autotune_validation(lib, no_inject):
     ms = (ctypes.c_float * 2)()
-    assert lib.qsvm_autotune(4, 10, 100, None, None, None, 0) == qsvm.QSVM_ERR_UNSUPPORTED
+    assert lib.qsvm_autotune(5, 10, 100, None, None, None, 0) == qsvm.QSVM_ERR_UNSUPPORTED
     assert lib.qsvm_autotune(2, 10, 70000, None, None, None, 0) == qsvm.QSVM_ERR_INVALID_ARG
     assert lib.qsvm_autotune(2, 10, 100, None, None, ms, 2) == qsvm.QSVM_ERR_SIZE

@@ -54,7 +54,7 @@ def _oracle_pairs_log(Xa, Xb, reps, ia, jb):
 # --------------------------------------------------------------------------
 
 @pytest.mark.parametrize("n", [1, 2, 5, 10])
-@pytest.mark.parametrize("reps", [1, 2, 3])
+@pytest.mark.parametrize("reps", [1, 2, 3, 4])
 def test_encode_dense_section_is_the_state(n, reps):
     X = synth.uniform_features(3, n, seed=10 * n + reps)
     m = encode(X, reps)
@@ -66,7 +66,7 @@ def test_encode_dense_section_is_the_state(n, reps):
 
 
 @pytest.mark.parametrize("n", [1, 2, 5, 10])
-@pytest.mark.parametrize("reps", [1, 2, 3])
+@pytest.mark.parametrize("reps", [1, 2, 3, 4])
 def test_encode_gauge_section_is_the_state(n, reps):
     X = synth.uniform_features(3, n, seed=20 * n + reps)
     m = encode(X, reps)

@@ -107,7 +107,7 @@ def test_golden_closed_forms(case):
 # --------------------------------------------------------------------------
 
 @pytest.mark.parametrize("n", [1, 2, 3, 4, 5])
-@pytest.mark.parametrize("reps", [1, 2, 3])
+@pytest.mark.parametrize("reps", [1, 2, 3, 4])
 def test_state_vector_matches_kron(n, reps):
     rng = np.random.default_rng(100 * n + reps)
     x = rng.uniform(0, math.pi, n)
@@ -115,7 +115,7 @@ def test_state_vector_matches_kron(n, reps):
 
 
 @pytest.mark.parametrize("n", [2, 3, 6, 9, 12])
-@pytest.mark.parametrize("reps", [1, 2, 3])
+@pytest.mark.parametrize("reps", [1, 2, 3, 4])
 def test_mps_state_matches_state_vector(n, reps):
     rng = np.random.default_rng(7 * n + reps)
     x = rng.uniform(0, math.pi, n)
@@ -123,7 +123,7 @@ def test_mps_state_matches_state_vector(n, reps):
     assert np.max(np.abs(v - statevector.sv_state(x, reps))) < 1e-12
 
 
-@pytest.mark.parametrize("reps", [1, 2, 3])
+@pytest.mark.parametrize("reps", [1, 2, 3, 4])
 def test_mps_gram_matches_state_vector(reps):
     X = synth.uniform_features(10, 10, seed=reps)
     K1 = statevector.sv_gram(X, reps)
@@ -143,7 +143,7 @@ def test_mps_rect_gram_matches_state_vector():
     assert np.max(np.abs(K1 - K2.reshape(5, 7))) < 1e-12
 
 
-@pytest.mark.parametrize("reps", [1, 2, 3])
+@pytest.mark.parametrize("reps", [1, 2, 3, 4])
 def test_mps_bond_dimension_is_two_to_the_reps(reps):
     x = synth.uniform_features(1, 14, seed=3)[0]
     bonds = [t.shape[2] for t in mps.mps_state(x, reps)[:-1]]
@@ -186,7 +186,7 @@ def test_reps1_transfer_matches_mps_at_784():
 # Entanglement-free inputs
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("reps", [1, 2, 3])
+@pytest.mark.parametrize("reps", [1, 2, 3, 4])
 def test_product_form_matches_state_vector(reps):
     X = synth.pin_even_features(synth.uniform_features(2, 8, seed=30 + reps))
     K = statevector.sv_gram_rect(X[:1], X[1:], reps)[0, 0]
@@ -195,7 +195,7 @@ def test_product_form_matches_state_vector(reps):
         assert abs(np.prod(np.cos(X[0] - X[1]) ** 2) - K) < 1e-13
 
 
-@pytest.mark.parametrize("reps", [1, 2, 3])
+@pytest.mark.parametrize("reps", [1, 2, 3, 4])
 def test_product_form_matches_mps_at_784(reps):
     X = synth.pin_even_features(synth.images784(seed=1, n_train=2, n_test=0).X)
     la, _ = mps.mps_overlap_log(mps.mps_state(X[0], reps), mps.mps_state(X[1], reps))
