@@ -255,6 +255,51 @@ int32_t qsvm_get_tuned_variant(int32_t reps, int32_t n_qubits);
 qsvm_status qsvm_set_tuned_variant(int32_t reps, int32_t n_qubits, int32_t variant);
 
 /* ------------------------------------------------------------------------
+ * State-vector engine (the state-vector simulation method of §3.4.1 / Alg. 1,
+ * rebuilt for whole Grams): every point's full 2^n-amplitude state is formed
+ * once in FP64, and K = |Psi_a Psi_b^H|^2 is one dense complex product on the
+ * FP64 matrix cores.  A second exact engine beside the MPS path, for
+ * n_qubits <= 30 (memory 2^n * 16 B per point); its cost grows as 2^n where
+ * the MPS path grows as n.
+ * Layout: point i's state is 2^n complex128 values (re, im interleaved) at
+ * element offset i * 2^n; amplitude b is the basis state whose bit k is
+ * qubit k.
+ * ------------------------------------------------------------------------ */
+
+/* Bytes of the states of N points: N * 2^n * 16, or 0 when n_qubits is outside
+ * 1..30, N < 1 or the size overflows int64. */
+size_t qsvm_sv_bytes(int64_t N, int32_t n_qubits);
+
+/*
+ * Build psi(x_i) = U(x_i)|0^n> for the N rows of X (device N x n float64,
+ * row-major): `reps` repetitions of H on every qubit followed by the
+ * diagonal phase exp(i [sum_k 2 x_k b_k + sum_k theta_k (b_k XOR b_{k+1})]),
+ * theta_k = 2 (pi - x_k)(pi - x_{k+1}) (the circuit of §3.2 read as the ZZ
+ * map; the CNOT-P-CNOT block is that diagonal phase).  reps in 1..16.
+ *   sv        device output of at least qsvm_sv_bytes(N, n) bytes, 16-byte
+ *             aligned, caller-owned.
+ * QSVM_ERR_UNSUPPORTED for n_qubits outside 1..30; QSVM_ERR_SIZE for a short
+ * buffer; QSVM_ERR_INVALID_ARG for other bad arguments.
+ */
+qsvm_status qsvm_encode_sv(const double* X, int64_t N, int32_t n_qubits, int32_t reps, void* sv,
+                           size_t sv_bytes, void* stream);
+
+/*
+ * Rectangular Gram from states (Eq. 3 with the amplitudes of Alg. 1):
+ * K[i*ldk + j] = |<psi(b_j)|psi(a_i)>|^2 for i < Na, j < Nb.  opts: NULL or
+ * qsvm_gram_opts, of which log_k and row_begin/row_end are used (the MPS
+ * sweep settings are validated and ignored).  K is FP64 and computed from
+ * FP64 states with FP64 accumulation.
+ */
+qsvm_status qsvm_sv_gram(const void* sv_a, int64_t Na, const void* sv_b, int64_t Nb, int32_t n_qubits,
+                         double* K, int64_t ldk, const qsvm_gram_opts* opts, void* stream);
+
+/* Symmetric Gram from states: pairs i < j contracted and mirrored, the diagonal
+ * by diag_mode as in qsvm_gram_sym. */
+qsvm_status qsvm_sv_gram_sym(const void* sv, int64_t N, int32_t n_qubits, double* K, int64_t ldk,
+                             const qsvm_gram_opts* opts, void* stream);
+
+/* ------------------------------------------------------------------------
  * Learned surrogate: an MLP embedding f: R^n -> R^d_out (layers
  * d_in -> d_h1 -> d_h2 -> d_out, GELU after the two hidden layers, BF16
  * weights and activations, FP32 accumulation on the matrix cores) with

@@ -275,6 +275,84 @@ qsvm_status qsvm_set_tuned_variant(int32_t reps, int32_t n_qubits, int32_t varia
   return ok();
 }
 
+// ---- state-vector engine ----
+
+size_t qsvm_sv_bytes(int64_t N, int32_t n_qubits) {
+  if (n_qubits < 1 || n_qubits > qsvm::kMaxSvQubits || N < 1) return 0;
+  if (N > (INT64_MAX / 16) >> n_qubits) return 0;
+  return size_t(N << n_qubits) * 16;
+}
+
+qsvm_status qsvm_encode_sv(const double* X, int64_t N, int32_t n_qubits, int32_t reps, void* sv, size_t sv_bytes,
+                           void* stream) {
+  const char* what = "qsvm_encode_sv";
+  if (n_qubits < 1 || n_qubits > qsvm::kMaxSvQubits)
+    return fail(QSVM_ERR_UNSUPPORTED, "%s: n_qubits = %d outside [1, 30]", what, n_qubits);
+  if (reps < 1 || reps > qsvm::kMaxSvReps) return fail(QSVM_ERR_INVALID_ARG, "%s: reps = %d outside [1, 16]", what, reps);
+  const size_t need = qsvm_sv_bytes(N, n_qubits);
+  if (need == 0) return fail(QSVM_ERR_INVALID_ARG, "%s: N = %lld invalid or N * 2^n too large", what, (long long)N);
+  if (!X) return fail(QSVM_ERR_INVALID_ARG, "%s: X is NULL", what);
+  if (!sv) return fail(QSVM_ERR_INVALID_ARG, "%s: sv is NULL", what);
+  if (reinterpret_cast<uintptr_t>(sv) % 16 != 0) return fail(QSVM_ERR_INVALID_ARG, "%s: sv is not 16-byte aligned", what);
+  if (reinterpret_cast<uintptr_t>(X) % 8 != 0) return fail(QSVM_ERR_INVALID_ARG, "%s: X is not 8-byte aligned", what);
+  if (sv_bytes < need) return fail(QSVM_ERR_SIZE, "%s: sv_bytes = %zu < %zu needed", what, sv_bytes, need);
+  // one thread per 4 amplitudes (and per 2^(n-4) groups in the transform): < 2^31 blocks
+  if (int64_t(need / 16) / 4 / 256 >= (int64_t(1) << 31) - 1)
+    return fail(QSVM_ERR_UNSUPPORTED, "%s: N * 2^n too large for one launch", what);
+  if (injected_launch_failure()) return fail(QSVM_ERR_HIP, "%s: injected launch failure (QSVM_FAULT_INJECT=launch)", what);
+  return hip_status(qsvm::launch_encode_sv(X, N, n_qubits, reps, sv, static_cast<hipStream_t>(stream)), what);
+}
+
+namespace {
+
+qsvm_status run_sv_gram(const void* sv_a, int64_t Na, const void* sv_b, int64_t Nb, int32_t n, double* K,
+                        int64_t ldk, const qsvm_gram_opts* opts, bool sym, void* stream, const char* what) {
+  using qsvm::kTile;
+  if (!sv_a || !sv_b) return fail(QSVM_ERR_INVALID_ARG, "%s: state buffer is NULL", what);
+  if (!K) return fail(QSVM_ERR_INVALID_ARG, "%s: K is NULL", what);
+  if (n < 1 || n > qsvm::kMaxSvQubits) return fail(QSVM_ERR_UNSUPPORTED, "%s: n_qubits = %d outside [1, 30]", what, n);
+  if (qsvm_sv_bytes(Na, n) == 0 || qsvm_sv_bytes(Nb, n) == 0 || Na > kMaxN || Nb > kMaxN)
+    return fail(QSVM_ERR_INVALID_ARG, "%s: N invalid or N * 2^n too large", what);
+  if (ldk < Nb) return fail(QSVM_ERR_INVALID_ARG, "%s: ldk = %lld < %lld", what, (long long)ldk, (long long)Nb);
+  if ((reinterpret_cast<uintptr_t>(sv_a) | reinterpret_cast<uintptr_t>(sv_b)) % 16 != 0)
+    return fail(QSVM_ERR_INVALID_ARG, "%s: state buffer is not 16-byte aligned", what);
+  Opts o;
+  qsvm_status s = read_opts(opts, Na, o, what);
+  if (s != QSVM_OK) return s;
+  if (!sym) o.diag_mode = 0;
+  if (o.row_end <= o.row_begin) return ok();
+  qsvm::SweepArgs a{};
+  a.K = K;
+  a.log_k = o.log_k;
+  a.Na = Na;
+  a.Nb = Nb;
+  a.ldk = ldk;
+  a.row_begin = o.row_begin;
+  a.row_end = o.row_end;
+  a.n = n;
+  a.sym = sym ? 1 : 0;
+  a.diag_mode = o.diag_mode;
+  a.tile_row0 = int32_t(o.row_begin / kTile);
+  a.tile_rows = int32_t((o.row_end - 1) / kTile) - a.tile_row0 + 1;
+  a.tiles_b = int32_t((Nb + kTile - 1) / kTile);
+  if (int64_t(a.tile_rows) * a.tiles_b > (int64_t(1) << 31) - 8)
+    return fail(QSVM_ERR_UNSUPPORTED, "%s: too many tiles for one launch", what);
+  if (injected_launch_failure()) return fail(QSVM_ERR_HIP, "%s: injected launch failure (QSVM_FAULT_INJECT=launch)", what);
+  return hip_status(qsvm::launch_sv_gram(a, sv_a, sv_b, n, static_cast<hipStream_t>(stream)), what);
+}
+
+}  // namespace
+
+qsvm_status qsvm_sv_gram(const void* sv_a, int64_t Na, const void* sv_b, int64_t Nb, int32_t n_qubits, double* K,
+                         int64_t ldk, const qsvm_gram_opts* opts, void* stream) {
+  return run_sv_gram(sv_a, Na, sv_b, Nb, n_qubits, K, ldk, opts, false, stream, "qsvm_sv_gram");
+}
+
+qsvm_status qsvm_sv_gram_sym(const void* sv, int64_t N, int32_t n_qubits, double* K, int64_t ldk,
+                             const qsvm_gram_opts* opts, void* stream) {
+  return run_sv_gram(sv, N, sv, N, n_qubits, K, ldk, opts, true, stream, "qsvm_sv_gram_sym");
+}
+
 const char* qsvm_status_string(qsvm_status s) {
   switch (s) {
     case QSVM_OK: return "QSVM_OK";

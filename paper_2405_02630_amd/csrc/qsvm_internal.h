@@ -40,5 +40,10 @@ int32_t tuned_variant(int32_t reps, int32_t n);
 void set_tuned_variant(int32_t reps, int32_t n, int32_t variant);
 hipError_t autotune_run(int32_t reps, int32_t n, int64_t N, hipStream_t stream, int32_t* best, float* ms_out);
 hipError_t launch_sweep_dense_args(const SweepArgs& a, int32_t reps, hipStream_t stream);
+// State-vector engine (sv.hip).
+constexpr int32_t kMaxSvQubits = 30;
+constexpr int32_t kMaxSvReps = 16;
+hipError_t launch_encode_sv(const double* X, int64_t N, int32_t n, int32_t reps, void* sv, hipStream_t stream);
+hipError_t launch_sv_gram(const SweepArgs& a, const void* sv_a, const void* sv_b, int32_t n, hipStream_t stream);
 
 }  // namespace qsvm

@@ -158,6 +158,14 @@ def load_library(path: str = LIB_PATH):
     lib.qsvm_flag_tiles.argtypes = [vp, i32, f32, vp, vp, vp]
     lib.qsvm_flag_tiles.restype = i32
     lib.qsvm_autotune.argtypes = [i32, i32, i64, vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float), i32]
+    lib.qsvm_sv_bytes.argtypes = [i64, i32]
+    lib.qsvm_sv_bytes.restype = ctypes.c_size_t
+    lib.qsvm_encode_sv.argtypes = [vp, i64, i32, i32, vp, ctypes.c_size_t, vp]
+    lib.qsvm_encode_sv.restype = i32
+    lib.qsvm_sv_gram.argtypes = [vp, i64, vp, i64, i32, vp, i64, P(GramOpts), vp]
+    lib.qsvm_sv_gram.restype = i32
+    lib.qsvm_sv_gram_sym.argtypes = [vp, i64, i32, vp, i64, P(GramOpts), vp]
+    lib.qsvm_sv_gram_sym.restype = i32
     lib.qsvm_autotune.restype = i32
     lib.qsvm_get_tuned_variant.argtypes = [i32, i32]
     lib.qsvm_get_tuned_variant.restype = i32
@@ -301,6 +309,78 @@ def qsvm_gram_sym(mps: MPS, K=None, *, log_k=None, renorm_every: int = 0, sweep:
         ctypes.byref(o), _stream_ptr(stream),
     )
     _check(st)
+    return K
+
+
+@dataclass
+class SV:
+    """Device states written by qsvm_encode_sv (N x 2^n complex128)."""
+
+    buf: "object"  # torch.complex128 CUDA tensor, N x 2^n
+    N: int
+    n: int
+    reps: int
+
+
+def qsvm_sv_bytes(N: int, n_qubits: int) -> int:
+    return int(load_library().qsvm_sv_bytes(N, n_qubits))
+
+
+def qsvm_encode_sv(X, reps: int, out=None, stream=None) -> SV:
+    """Full state vectors of the rows of X (CUDA float64, N x n), n <= 30."""
+    import torch
+
+    lib = load_library()
+    if X.dim() != 2:
+        raise ValueError("X must be 2-D (N x n_qubits)")
+    N, n = int(X.shape[0]), int(X.shape[1])
+    need = lib.qsvm_sv_bytes(N, n)
+    if out is None:
+        if need == 0:
+            _check(lib.qsvm_encode_sv(_device_ptr(X, "X", torch.float64), N, n, reps, None, 0, _stream_ptr(stream)))
+        out = torch.empty((N, 1 << n), dtype=torch.complex128, device=X.device)
+    st = lib.qsvm_encode_sv(_device_ptr(X, "X", torch.float64), N, n, reps, _device_ptr(out, "out"),
+                            out.numel() * out.element_size(), _stream_ptr(stream))
+    _check(st)
+    return SV(out, N, n, reps)
+
+
+def _check_k(K, rows, log_k):
+    import torch
+
+    if K.dim() != 2 or K.shape[0] < rows or K.stride(1) != 1:
+        raise ValueError("K must be 2-D with unit column stride and enough rows")
+    if log_k is not None and (log_k.shape != K.shape or log_k.stride() != K.stride() or log_k.dtype != torch.float64):
+        raise ValueError("log_k must match K's shape, strides and dtype")
+
+
+def qsvm_sv_gram(sa: SV, sb: SV, K=None, *, log_k=None, rows=None, stream=None):
+    """K[i, j] = |<psi(b_j)|psi(a_i)>|^2 from full states.  Returns K."""
+    import torch
+
+    lib = load_library()
+    if sa.n != sb.n:
+        raise ValueError("both state sets need the same n_qubits")
+    if K is None:
+        K = torch.empty((sa.N, sb.N), dtype=torch.float64, device=sa.buf.device)
+    _check_k(K, sa.N, log_k)
+    o = _opts(0, SWEEP_AUTO, 0, rows, log_k)
+    _check(lib.qsvm_sv_gram(_device_ptr(sa.buf, "sv_a"), sa.N, _device_ptr(sb.buf, "sv_b"), sb.N, sa.n,
+                            ctypes.c_void_p(K.data_ptr()), K.stride(0), ctypes.byref(o), _stream_ptr(stream)))
+    return K
+
+
+def qsvm_sv_gram_sym(s: SV, K=None, *, log_k=None, diag_mode: int = 0, rows=None, stream=None):
+    """Symmetric Gram from full states (pairs i < j, mirrored).  Returns K."""
+    import torch
+
+    lib = load_library()
+    if K is None:
+        K = torch.empty((s.N, s.N), dtype=torch.float64, device=s.buf.device)
+    _check_k(K, s.N, log_k)
+    o = _opts(0, SWEEP_AUTO, diag_mode, rows, log_k)
+    _check(lib.qsvm_sv_gram_sym(_device_ptr(s.buf, "sv"), s.N, s.n, ctypes.c_void_p(K.data_ptr()), K.stride(0),
+                                ctypes.byref(o), _stream_ptr(stream)))
     return K
 
 

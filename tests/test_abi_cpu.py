@@ -256,3 +256,54 @@ def test_autotune_validation(lib, no_inject):
     assert lib.qsvm_autotune(5, 10, 100, None, None, None, 0) == qsvm.QSVM_ERR_UNSUPPORTED
     assert lib.qsvm_autotune(2, 10, 70000, None, None, None, 0) == qsvm.QSVM_ERR_INVALID_ARG
     assert lib.qsvm_autotune(2, 10, 100, None, None, ms, 2) == qsvm.QSVM_ERR_SIZE
+
+
+# --------------------------------------------------------------------------
+# State-vector engine
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("N,n", [(1, 1), (32, 8), (1024, 20), (3, 30)])
+def test_sv_bytes_formula(N, n):
+    assert qsvm.qsvm_sv_bytes(N, n) == N * 2**n * 16
+
+
+@pytest.mark.parametrize("N,n", [(0, 8), (-1, 8), (8, 0), (8, 31), (2**40, 30)])
+def test_sv_bytes_rejects(N, n):
+    assert qsvm.qsvm_sv_bytes(N, n) == 0
+
+
+def test_encode_sv_validation(lib, no_inject):
+    nb = qsvm.qsvm_sv_bytes(8, 4)
+    assert lib.qsvm_encode_sv(FAKE, 8, 31, 2, FAKE2, nb, None) == qsvm.QSVM_ERR_UNSUPPORTED
+    assert lib.qsvm_encode_sv(FAKE, 8, 4, 0, FAKE2, nb, None) == qsvm.QSVM_ERR_INVALID_ARG
+    assert lib.qsvm_encode_sv(FAKE, 8, 4, 17, FAKE2, nb, None) == qsvm.QSVM_ERR_INVALID_ARG
+    assert lib.qsvm_encode_sv(FAKE, 0, 4, 2, FAKE2, nb, None) == qsvm.QSVM_ERR_INVALID_ARG
+    assert lib.qsvm_encode_sv(None, 8, 4, 2, FAKE2, nb, None) == qsvm.QSVM_ERR_INVALID_ARG
+    assert lib.qsvm_encode_sv(FAKE, 8, 4, 2, None, nb, None) == qsvm.QSVM_ERR_INVALID_ARG
+    assert lib.qsvm_encode_sv(FAKE, 8, 4, 2, ctypes.c_void_p(0x200008), nb, None) == qsvm.QSVM_ERR_INVALID_ARG
+    assert lib.qsvm_encode_sv(FAKE, 8, 4, 2, FAKE2, nb - 1, None) == qsvm.QSVM_ERR_SIZE
+
+
+def test_sv_gram_validation(lib, no_inject):
+    o = qsvm.GramOpts()
+    assert lib.qsvm_sv_gram(None, 5, FAKE2, 7, 4, FAKE, 7, None, None) == qsvm.QSVM_ERR_INVALID_ARG
+    assert lib.qsvm_sv_gram(FAKE, 5, FAKE2, 7, 4, None, 7, None, None) == qsvm.QSVM_ERR_INVALID_ARG
+    assert lib.qsvm_sv_gram(FAKE, 5, FAKE2, 7, 31, FAKE, 7, None, None) == qsvm.QSVM_ERR_UNSUPPORTED
+    assert lib.qsvm_sv_gram(FAKE, 5, FAKE2, 7, 4, FAKE, 6, None, None) == qsvm.QSVM_ERR_INVALID_ARG
+    assert lib.qsvm_sv_gram(FAKE, 0, FAKE2, 7, 4, FAKE, 7, None, None) == qsvm.QSVM_ERR_INVALID_ARG
+    assert lib.qsvm_sv_gram(ctypes.c_void_p(0x100008), 5, FAKE2, 7, 4, FAKE, 7, None, None) == qsvm.QSVM_ERR_INVALID_ARG
+    o.row_begin, o.row_end = 3, 9
+    assert lib.qsvm_sv_gram_sym(FAKE, 5, 4, FAKE2, 5, ctypes.byref(o), None) == qsvm.QSVM_ERR_INVALID_ARG
+    o.row_begin, o.row_end = 2, 2  # empty range: nothing to do
+    assert lib.qsvm_sv_gram_sym(FAKE, 5, 4, FAKE2, 5, ctypes.byref(o), None) == qsvm.QSVM_OK
+    o = qsvm.GramOpts()
+    o.diag_mode = 2
+    assert lib.qsvm_sv_gram_sym(FAKE, 5, 4, FAKE2, 5, ctypes.byref(o), None) == qsvm.QSVM_ERR_INVALID_ARG
+
+
+def test_sv_injected_launch_failure(lib, monkeypatch):
+    monkeypatch.setenv("QSVM_FAULT_INJECT", "launch")
+    nb = qsvm.qsvm_sv_bytes(8, 4)
+    assert lib.qsvm_encode_sv(FAKE, 8, 4, 2, FAKE2, nb, None) == qsvm.QSVM_ERR_HIP
+    assert lib.qsvm_sv_gram_sym(FAKE, 8, 4, FAKE2, 8, None, None) == qsvm.QSVM_ERR_HIP
+    assert b"injected" in lib.qsvm_last_error()
