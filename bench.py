@@ -8,7 +8,7 @@ features already resident in HBM.  value = contracted pairs per second.
 Prints one JSON line with the timing, a roofline entry for the dominant
 kernel (the overlap sweep; launch durations from HIP events on the launch
 stream) and, on rank 0, a CPU baseline: the FP64 oracle timed on the host
-cores on a bounded sample of the same workload.  Two more legs add their own
+cores on a bounded sample of the same workload.  Three more legs add their own
 objects to the line:
   surrogate -- 32768 synthetic 784-pixel images, reps = 2: the MLP surrogate
                trained on 2 % of the exact entries (the complete Gram of a
@@ -18,10 +18,13 @@ objects to the line:
                one-vs-rest SVM accuracy on a 4096-point subset with the exact
                and the surrogate Gram;
   batched   -- 64 independent Gram jobs of uneven n, N and reps in one
-               persistent hipGraph launch, against one launch per job.
+               persistent hipGraph launch, against one launch per job;
+  sv        -- the state-vector engine against the MPS engine on 512 points
+               at 12, 16 and 20 qubits: times, agreement, and the FP64
+               matrix-core rate of the state-vector Gram.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--reps 2|3]
-                       [--sweep butterfly|dense] [--legs exact,surrogate,batched]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--reps 1|2|3|4]
+                       [--sweep butterfly|dense] [--legs exact,surrogate,batched,sv]
                        [--no-cpu-baseline] [--cpu-sample P] [--copy-calibration MiB]
 """
 
@@ -313,6 +316,67 @@ def batched_leg():
     return res
 
 
+PEAK_FP64_MATRIX_TFLOPS = 78.6  # MI355X dense FP64 MFMA
+
+
+def sv_leg(points: int = 512, qubits=(12, 16, 20), reps: int = 2):
+    """State-vector engine vs MPS engine on the same points (uniform features):
+    build + symmetric Gram time of each, their agreement, and the roofline of
+    the state-vector Gram (FP64 MFMA, 8 flops per complex multiply-add)."""
+    import numpy as np
+    import torch
+
+    from paper_2405_02630_amd import qsvm, synth
+
+    dev = torch.device("cuda:0")
+    rows = []
+    for n in qubits:
+        X = torch.as_tensor(synth.uniform_features(points, n, seed=6000 + n), device=dev)
+        Ks = torch.empty((points, points), dtype=torch.float64, device=dev)
+        Km = torch.empty_like(Ks)
+        sv = qsvm.qsvm_encode_sv(X, reps)
+        m = qsvm.qsvm_encode_mps(X, reps)
+        qsvm.qsvm_sv_gram_sym(sv, Ks)
+        qsvm.qsvm_gram_sym(m, Km)
+        torch.cuda.synchronize()
+        ev = _events(6)
+        ev[0].record()
+        qsvm.qsvm_encode_sv(X, reps, out=sv.buf)
+        ev[1].record()
+        qsvm.qsvm_sv_gram_sym(sv, Ks)
+        ev[2].record()
+        qsvm.qsvm_encode_mps(X, reps, out=m.buf)
+        ev[3].record()
+        qsvm.qsvm_gram_sym(m, Km)
+        ev[4].record()
+        torch.cuda.synchronize()
+        enc_s = ev[0].elapsed_time(ev[1]) / 1e3
+        gram_s = ev[1].elapsed_time(ev[2]) / 1e3
+        mps_s = ev[2].elapsed_time(ev[4]) / 1e3
+        pairs = points * (points - 1) // 2
+        T = (points + 63) // 64
+        # executed GEMM flops: the upper-triangular 64 x 64 tiles, 8 flops per complex MAC
+        flops = T * (T + 1) // 2 * 64 * 64 * (1 << n) * 8
+        rows.append({
+            "n_qubits": n,
+            "sv_encode_ms": enc_s * 1e3,
+            "sv_gram_ms": gram_s * 1e3,
+            "sv_entries_per_s": pairs / (enc_s + gram_s),
+            "mps_entries_per_s": pairs / mps_s,
+            "mps_over_sv": (enc_s + gram_s) / mps_s,
+            "max_abs_dK_sv_vs_mps": float((Ks - Km).abs().max().item()),
+            "sv_gram_fp64_tflops": flops / gram_s / 1e12,
+            "sv_gram_frac_of_fp64_matrix_peak": flops / gram_s / 1e12 / PEAK_FP64_MATRIX_TFLOPS,
+        })
+        log(f"sv n={n}: encode {enc_s*1e3:.2f} ms, gram {gram_s*1e3:.2f} ms "
+            f"({rows[-1]['sv_gram_fp64_tflops']:.1f} FP64 TFLOP/s); mps {mps_s*1e3:.2f} ms; "
+            f"max|dK| {rows[-1]['max_abs_dK_sv_vs_mps']:.1e}")
+        del sv, Ks, Km
+        torch.cuda.empty_cache()
+    return {"workload": f"{points} points, uniform features, reps={reps}, symmetric Gram", "points": points,
+            "unit": "entries/s", "peak_fp64_matrix_tflops": PEAK_FP64_MATRIX_TFLOPS, "by_qubits": rows}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -324,7 +388,7 @@ def main():
     ap.add_argument("--renorm-every", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=720)
-    ap.add_argument("--legs", default="exact,surrogate,batched")
+    ap.add_argument("--legs", default="exact,surrogate,batched,sv")
     ap.add_argument("--sur-points", type=int, default=32768)
     ap.add_argument("--sur-steps", type=int, default=300)
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -442,6 +506,8 @@ def main():
         K = None
     if "batched" in legs:
         out["batched"] = batched_leg()
+    if "sv" in legs:
+        out["state_vector"] = sv_leg()
 
     if not args.no_cpu_baseline:
         if K is None:

@@ -295,7 +295,11 @@ qsvm_status qsvm_sv_gram(const void* sv_a, int64_t Na, const void* sv_b, int64_t
                          double* K, int64_t ldk, const qsvm_gram_opts* opts, void* stream);
 
 /* Symmetric Gram from states: pairs i < j contracted and mirrored, the diagonal
- * by diag_mode as in qsvm_gram_sym. */
+ * by diag_mode as in qsvm_gram_sym.
+ * Both Gram calls split the 2^n inner dimension across blocks when there are
+ * fewer than about 1024 output tiles; the partial products (tiles x splits x
+ * 64 KB) live in a stream-ordered temporary (hipMallocAsync / hipFreeAsync on
+ * `stream`) and are added in a fixed order, so results are reproducible. */
 qsvm_status qsvm_sv_gram_sym(const void* sv, int64_t N, int32_t n_qubits, double* K, int64_t ldk,
                              const qsvm_gram_opts* opts, void* stream);
 

@@ -117,14 +117,20 @@ constexpr int kKB = 16;  // complex inner-dimension values per LDS stage
 // MFMA f64 16x16x4 operand layout (measured on gfx950): lane l supplies
 // A[l % 16][l / 16] and B[l / 16][l % 16]; result element v of lane l is
 // D[4 v + l / 16][l % 16].
+// With splits > 1 the inner dimension is cut into `splits` chunks of kchunk
+// values; block (tile, split) writes its partial product to W and
+// sv_reduce_kernel adds the partials in split order.
 __global__ void __launch_bounds__(256)
-sv_gram_kernel(SweepArgs a, const double2* __restrict__ A, const double2* __restrict__ B, int64_t D) {
+sv_gram_kernel(SweepArgs a, const double2* __restrict__ A, const double2* __restrict__ B, int64_t D,
+               int32_t splits, int64_t kchunk, double2* __restrict__ W) {
   __shared__ double2 sA[kKB][64];
   __shared__ double2 sB[kKB][64];
   const uint32_t L = xcd_logical_block();
   if (L >= a.num_blocks) return;
+  const uint32_t tile = L / uint32_t(splits);
+  const int32_t split = int32_t(L % uint32_t(splits));
   int32_t ti, tj;
-  if (!decode_tile(a, L, ti, tj)) return;
+  if (!decode_tile(a, tile, ti, tj)) return;
   const int64_t i0 = int64_t(ti) * kTile, j0 = int64_t(tj) * kTile;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -147,15 +153,29 @@ sv_gram_kernel(SweepArgs a, const double2* __restrict__ A, const double2* __rest
   const double2* pa = A + (va ? ga : 0) * D;
   const double2* pb = B + (vb ? gb : 0) * D;
 
-  for (int64_t k0 = 0; k0 < D; k0 += kKB) {
+  const int64_t kbeg = int64_t(split) * kchunk;
+  const int64_t kend = (kbeg + kchunk < D) ? kbeg + kchunk : D;
+  // the next stage's values are loaded into registers while the current
+  // stage's MFMAs run
+  double2 na[4], nb[4];
+  auto load_stage = [&](int64_t k0) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int64_t k = k0 + lk + e;
-      const bool kin = k < D;
-      sA[lk + e][lrow] = (va && kin) ? pa[k] : make_double2(0.0, 0.0);
-      sB[lk + e][lrow] = (vb && kin) ? pb[k] : make_double2(0.0, 0.0);
+      const bool kin = k < kend;
+      na[e] = (va && kin) ? pa[k] : make_double2(0.0, 0.0);
+      nb[e] = (vb && kin) ? pb[k] : make_double2(0.0, 0.0);
+    }
+  };
+  load_stage(kbeg);
+  for (int64_t k0 = kbeg; k0 < kend; k0 += kKB) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      sA[lk + e][lrow] = na[e];
+      sB[lk + e][lrow] = nb[e];
     }
     __syncthreads();
+    if (k0 + kKB < kend) load_stage(k0 + kKB);
 #pragma unroll
     for (int ks = 0; ks < kKB; ks += 4) {
       const int kk = ks + (lane >> 4);
@@ -164,18 +184,23 @@ sv_gram_kernel(SweepArgs a, const double2* __restrict__ A, const double2* __rest
       for (int mi = 0; mi < 2; ++mi) fa[mi] = sA[kk][wr + mi * 16 + (lane & 15)];
 #pragma unroll
       for (int nj = 0; nj < 2; ++nj) fb[nj] = sB[kk][wc + nj * 16 + (lane & 15)];
+      const double nar[2] = {-fa[0].x, -fa[1].x};
+      // re += ar br + ai bi ; im += ai br - ar bi.  The eight accumulators are
+      // visited in turn, so no MFMA waits on the one just issued.
 #pragma unroll
-      for (int mi = 0; mi < 2; ++mi) {
-        const double nar = -fa[mi].x;
+      for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
         for (int nj = 0; nj < 2; ++nj) {
-          // re += ar br + ai bi ; im += ai br - ar bi
           accr[mi][nj] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[mi].x, fb[nj].x, accr[mi][nj], 0, 0, 0);
-          accr[mi][nj] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[mi].y, fb[nj].y, accr[mi][nj], 0, 0, 0);
           acci[mi][nj] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[mi].y, fb[nj].x, acci[mi][nj], 0, 0, 0);
-          acci[mi][nj] = __builtin_amdgcn_mfma_f64_16x16x4f64(nar, fb[nj].y, acci[mi][nj], 0, 0, 0);
         }
-      }
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int nj = 0; nj < 2; ++nj) {
+          accr[mi][nj] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[mi].y, fb[nj].y, accr[mi][nj], 0, 0, 0);
+          acci[mi][nj] = __builtin_amdgcn_mfma_f64_16x16x4f64(nar[mi], fb[nj].y, acci[mi][nj], 0, 0, 0);
+        }
     }
     __syncthreads();
   }
@@ -186,12 +211,38 @@ sv_gram_kernel(SweepArgs a, const double2* __restrict__ A, const double2* __rest
     for (int nj = 0; nj < 2; ++nj)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t i = i0 + wr + mi * 16 + 4 * v + (lane >> 4);
-        const int64_t j = j0 + wc + nj * 16 + (lane & 15);
-        if (!pair_active(a, i, j)) continue;
+        const int r = wr + mi * 16 + 4 * v + (lane >> 4);
+        const int c = wc + nj * 16 + (lane & 15);
         const double gr = accr[mi][nj][v], gi = acci[mi][nj][v];
+        if (splits > 1) {
+          W[(int64_t(tile) * splits + split) * (kTile * kTile) + r * kTile + c] = make_double2(gr, gi);
+          continue;
+        }
+        const int64_t i = i0 + r, j = j0 + c;
+        if (!pair_active(a, i, j)) continue;
         store_entry(a, i, j, fma(gr, gr, gi * gi), 0);
       }
+}
+
+// Sum the split partials of every tile entry in split order, then finalize.
+__global__ void __launch_bounds__(256)
+sv_reduce_kernel(SweepArgs a, int32_t splits, const double2* __restrict__ W) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;  // (tile, entry)
+  const uint32_t tile = uint32_t(t / (kTile * kTile));
+  if (tile >= a.num_blocks) return;
+  const int e = int(t % (kTile * kTile));
+  int32_t ti, tj;
+  if (!decode_tile(a, tile, ti, tj)) return;
+  const int64_t i = int64_t(ti) * kTile + e / kTile, j = int64_t(tj) * kTile + e % kTile;
+  if (!pair_active(a, i, j)) return;
+  double gr = 0.0, gi = 0.0;
+  const double2* w = W + int64_t(tile) * splits * (kTile * kTile) + e;
+  for (int s = 0; s < splits; ++s) {
+    const double2 g = w[int64_t(s) * (kTile * kTile)];
+    gr += g.x;
+    gi += g.y;
+  }
+  store_entry(a, i, j, fma(gr, gr, gi * gi), 0);
 }
 
 }  // namespace
@@ -229,14 +280,42 @@ hipError_t launch_encode_sv(const double* X, int64_t N, int32_t n, int32_t reps,
 hipError_t launch_sv_gram(const SweepArgs& a0, const void* sv_a, const void* sv_b, int32_t n, hipStream_t stream) {
   SweepArgs a = a0;
   a.blocks_per_tile = 1;
-  const int64_t blocks = launch_tiles(a);
-  if (blocks <= 0) return hipSuccess;
+  const int64_t tiles = launch_tiles(a);
+  if (tiles <= 0) return hipSuccess;
+  const int64_t D = int64_t(1) << n;
+  // split the inner dimension until about 1024 blocks are in flight, keeping
+  // at least 256 values (16 LDS stages) per split
+  int64_t splits = (1024 + tiles - 1) / tiles;
+  if (splits > D / 256) splits = D / 256;
+  if (splits < 1) splits = 1;
+  const int64_t kchunk = ((D + splits - 1) / splits + kKB - 1) / kKB * kKB;
+  splits = (D + kchunk - 1) / kchunk;
+  const int64_t blocks = tiles * splits;
   if (blocks > (int64_t(1) << 31) - 8) return hipErrorInvalidValue;
   a.num_blocks = uint32_t(blocks);
+  double2* W = nullptr;
+  if (splits > 1) {
+    const hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&W), size_t(blocks) * kTile * kTile * sizeof(double2),
+                                        stream);
+    if (e != hipSuccess) return e;
+  }
   const uint32_t padded = uint32_t((blocks + 7) / 8 * 8);
   hipLaunchKernelGGL(sv_gram_kernel, dim3(padded), dim3(256), 0, stream, a, static_cast<const double2*>(sv_a),
-                     static_cast<const double2*>(sv_b), int64_t(1) << n);
-  return hipGetLastError();
+                     static_cast<const double2*>(sv_b), D, int32_t(splits), kchunk, W);
+  hipError_t e = hipGetLastError();
+  if (splits > 1) {
+    if (e == hipSuccess) {
+      SweepArgs r = a;
+      r.num_blocks = uint32_t(tiles);
+      const int64_t threads = tiles * kTile * kTile;
+      hipLaunchKernelGGL(sv_reduce_kernel, dim3(unsigned((threads + 255) / 256)), dim3(256), 0, stream, r,
+                         int32_t(splits), static_cast<const double2*>(W));
+      e = hipGetLastError();
+    }
+    const hipError_t f = hipFreeAsync(W, stream);
+    if (e == hipSuccess) e = f;
+  }
+  return e;
 }
 
 }  // namespace qsvm
