@@ -112,6 +112,36 @@ def cpu_baseline(X, reps, K_gpu, sample_points: int, cores: int):
     }
 
 
+def near_duplicate_check(reps: int, cores: int, n_base: int = 8):
+    """The bar where it bites: near-duplicate 784-pixel images (K up to ~1),
+    GPU rectangular Gram of n_base base images x their eps-perturbed copies
+    in the default launch configuration against the FP64 MPS oracle."""
+    import numpy as np
+    import torch
+
+    from oracle import mps as omps
+    from paper_2405_02630_amd import qsvm, synth
+
+    base, Xp, _, eps = synth.image_near_duplicates(seed=3, n_base=n_base)
+    dev = torch.device("cuda:0")
+    ma = qsvm.qsvm_encode_mps(torch.as_tensor(base, device=dev), reps)
+    mb = qsvm.qsvm_encode_mps(torch.as_tensor(Xp, device=dev), reps)
+    K = qsvm.qsvm_gram(ma, mb).cpu().numpy()
+    S = omps.mps_states(base, reps, processes=cores)
+    Sp = omps.mps_states(Xp, reps, processes=cores)
+    ii, jj = np.meshgrid(np.arange(base.shape[0]), np.arange(Xp.shape[0]), indexing="ij")
+    _, kk = omps.mps_gram_pairs(S, Sp, ii.ravel(), jj.ravel())
+    d = np.abs(K.ravel() - kk)
+    return {
+        "pairs": int(kk.size),
+        "eps": sorted(set(float(e) for e in eps)),
+        "K_oracle_max": float(kk.max()),
+        "pairs_with_K_above_1e-3": int(np.sum(kk > 1e-3)),
+        "max_abs_dK": float(d.max()),
+        "max_abs_dK_where_K_above_1e-3": float(d[kk > 1e-3].max()) if np.any(kk > 1e-3) else None,
+    }
+
+
 _BENCH_STATES = None
 
 
@@ -525,6 +555,9 @@ def main():
         qsvm.qsvm_gram_sym(m, K, log_k=L, sweep=sweep, renorm_every=args.renorm_every)
         Lh = L.cpu().numpy()
         cb["sample_max_log_err_vs_gpu"] = float(np.max(np.abs(Lh[ia, jb] - lk)))
+        cb["near_duplicates"] = near_duplicate_check(reps, cores)
+        log(f"near duplicates: max|dK| {cb['near_duplicates']['max_abs_dK']:.2e} over "
+            f"{cb['near_duplicates']['pairs']} pairs, K up to {cb['near_duplicates']['K_oracle_max']:.3f}")
         out["cpu_baseline"] = cb
     print(json.dumps(out))
 
