@@ -253,7 +253,9 @@ __device__ __forceinline__ void butterfly_item(const SweepArgs& a, int64_t i0, i
 
   const float4* __restrict__ gA = a.gen_a;
   const float4* __restrict__ gB = a.gen_b;
-  if (__builtin_amdgcn_ballot_w64(any_comp)) {
+  // sites 1 .. n-1 (none for one qubit: the generator plane then holds only
+  // site 0, so nothing is loaded beyond it)
+  if (a.n > 1 && __builtin_amdgcn_ballot_w64(any_comp)) {
     int countdown = a.renorm_every;
     float4 cy = gB[a.Nb + jc];  // site 1
     float4 cx[PI];
