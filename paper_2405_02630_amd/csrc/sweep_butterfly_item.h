@@ -257,30 +257,35 @@ __device__ __forceinline__ void butterfly_item(const SweepArgs& a, int64_t i0, i
   // site 0, so nothing is loaded beyond it)
   if (a.n > 1 && __builtin_amdgcn_ballot_w64(any_comp)) {
     int countdown = a.renorm_every;
-    float4 cy = gB[a.Nb + jc];  // site 1
-    float4 cx[PI];
+    // one site: apply it to every environment, renormalise on schedule
+    auto step = [&](const float4 (&cx)[PI], const float4& cy) {
 #pragma unroll
-    for (int p = 0; p < PI; ++p) cx[p] = gA[a.Na + ic[p]];
-    for (int k = 1; k < a.n; ++k) {
-      // prefetch the next site's generators (clamped to the last site)
-      const int kn = (k + 1 < a.n) ? k + 1 : k;
-      const float4 cy_next = gB[int64_t(kn) * a.Nb + jc];
-      float4 cx_next[PI];
-#pragma unroll
-      for (int p = 0; p < PI; ++p) cx_next[p] = gA[int64_t(kn) * a.Na + ic[p]];
-#pragma unroll
-      for (int p = 0; p < PI; ++p) {
-        site_step<R>(v[p], cx[p], cy);
-      }
+      for (int p = 0; p < PI; ++p) site_step<R>(v[p], cx[p], cy);
       if (--countdown == 0) {
 #pragma unroll
         for (int p = 0; p < PI; ++p) acc[p] += renorm<R>(v[p]);
         countdown = a.renorm_every;
       }
-      cy = cy_next;
+    };
+    // generators of one site (clamped to the last site)
+    auto load = [&](int k, float4 (&cx)[PI], float4& cy) {
+      const int kc = (k < a.n) ? k : a.n - 1;
+      cy = gB[int64_t(kc) * a.Nb + jc];
 #pragma unroll
-      for (int p = 0; p < PI; ++p) cx[p] = cx_next[p];
+      for (int p = 0; p < PI; ++p) cx[p] = gA[int64_t(kc) * a.Na + ic[p]];
+    };
+    // two sites per iteration with ping-pong registers, so the prefetched
+    // generators never have to be copied into the registers of the current site
+    float4 cxA[PI], cxB[PI], cyA, cyB;
+    load(1, cxA, cyA);
+    int k = 1;
+    for (; k + 1 < a.n; k += 2) {
+      load(k + 1, cxB, cyB);
+      step(cxA, cyA);
+      load(k + 2, cxA, cyA);
+      step(cxB, cyB);
     }
+    if (k < a.n) step(cxA, cyA);  // last site when n - 1 is odd
   }
 
   // Epilogue one pair at a time (rolled loop over the ket points, rotating
