@@ -328,6 +328,19 @@ def test_ldk_padding_untouched():
     assert np.max(np.abs(b[:, :70] - statevector.sv_gram(X, 2))) <= K_ABS_TOL
 
 
+def test_empty_row_range_leaves_k_untouched():
+    import torch
+
+    X = synth.uniform_features(70, 8, seed=17)
+    m = encode(X, 2)
+    K = torch.full((70, 70), -7.0, dtype=torch.float64, device="cuda:0")
+    qsvm.qsvm_gram_sym(m, K, rows=(33, 33))
+    Kr = torch.full((70, 70), -7.0, dtype=torch.float64, device="cuda:0")
+    qsvm.qsvm_gram(m, m, Kr, rows=(70, 70))
+    torch.cuda.synchronize()
+    assert torch.all(K == -7.0) and torch.all(Kr == -7.0)
+
+
 def test_unsupported_and_invalid_raise_before_launch():
     import torch
 

@@ -141,3 +141,16 @@ def test_dense_sweep_is_rejected():
     with pytest.raises(qsvm.QsvmError) as e:
         gram_sym(X, R, sweep=qsvm.SWEEP_DENSE)
     assert "dense sweep" in str(e.value)
+
+
+def test_maximum_qubits_closed_form():
+    """n = 65535 qubits (the largest supported) at reps = 4, entanglement-free
+    inputs, against the product closed form; the bar grows with the chain as
+    in the reps <= 2 maximum-size test (8 r u per site on ln K)."""
+    n = 65535
+    X = synth.pin_even_features(synth.uniform_features(3, n, seed=4600))
+    _, L = gram_sym(X, R)
+    bar = 8 * R * 2.0 ** -24 * n + LOG_TOL_MAX
+    for (i, j) in [(0, 1), (1, 2)]:
+        ref = closed_forms.k_product_log(X[i], X[j], R)
+        assert abs(L[i, j] - ref) <= bar, (i, j, L[i, j], ref)

@@ -108,3 +108,37 @@ def test_near_duplicates_reach_the_diagonal():
     ref = statevector.sv_gram(X, 3)
     assert np.max(np.abs(K - ref)) <= SV_TOL
     assert min(K[i, i + 4] for i in range(4)) > 0.99
+
+
+def test_maximum_qubits_entanglement_free():
+    """n = 30 (the largest supported): two points, 2 x 2^30 FP64 amplitudes
+    (34 GB), inner dimension 2^30 split across 1024 blocks; entanglement-free
+    inputs against the product closed form."""
+    import torch
+
+    from oracle import closed_forms
+
+    n = 30
+    X = synth.pin_even_features(synth.uniform_features(2, n, seed=5500))
+    s = _states(X, 2)
+    K = torch.empty((2, 2), dtype=torch.float64, device="cuda:0")
+    L = torch.empty_like(K)
+    qsvm.qsvm_sv_gram_sym(s, K, log_k=L, diag_mode=1)
+    torch.cuda.synchronize()
+    Kh, Lh = K.cpu().numpy(), L.cpu().numpy()
+    del s
+    torch.cuda.empty_cache()
+    ref = closed_forms.k_product_log(X[0], X[1], 2)
+    assert abs(Lh[0, 1] - ref) <= 1e-9 * max(1.0, abs(ref))
+    assert abs(Kh[0, 0] - 1.0) <= SV_TOL and abs(Kh[1, 1] - 1.0) <= SV_TOL
+
+
+def test_empty_row_range_leaves_k_untouched():
+    import torch
+
+    X = synth.uniform_features(10, 6, seed=5600)
+    s = _states(X, 2)
+    K = torch.full((10, 10), -7.0, dtype=torch.float64, device="cuda:0")
+    qsvm.qsvm_sv_gram_sym(s, K, rows=(4, 4))
+    torch.cuda.synchronize()
+    assert torch.all(K == -7.0)
