@@ -37,10 +37,16 @@ __global__ void __launch_bounds__(256)
 encode_kernel(const double* __restrict__ X, int64_t N, int32_t n,
               float2* __restrict__ dense, float4* __restrict__ gen) {
   constexpr int CHI = 1 << R;
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  constexpr int E = CHI * CHI;             // entries per site tensor
+  constexpr int CH = (E < 16) ? E : 16;    // entries staged per round
+  // Tensors go out through LDS so that consecutive lanes store consecutive
+  // addresses (each thread computes one point's whole tensor).
+  __shared__ float2 stage[256 * CH];
+  const int64_t i0 = int64_t(blockIdx.x) * blockDim.x;
+  const int64_t i = i0 + threadIdx.x;
   const int32_t k = blockIdx.y;
-  if (i >= N) return;
-  const double* x = X + i * n;
+  const bool valid = i < N;
+  const double* x = X + (valid ? i : N - 1) * n;  // idle threads compute a valid point, store nothing
 
   const double xk = x[k];
   const double th_prev = (k >= 1) ? zz_theta(x[k - 1], xk) : 0.0;  // theta_{k-1}
@@ -64,20 +70,30 @@ encode_kernel(const double* __restrict__ X, int64_t N, int32_t n,
                        : (R == 2) ? 0.5
                        : (R == 3) ? 0.35355339059327376220
                                   : 0.25;
-  float2* out = dense + (int64_t(k) * N + i) * (CHI * CHI);
+  const int64_t base = (int64_t(k) * N + i0) * E;  // the block's points are contiguous
+  const int64_t npts = (N - i0 < 256) ? N - i0 : 256;
 #pragma unroll
-  for (int a = 0; a < CHI; ++a) {
+  for (int c = 0; c < E / CH; ++c) {
 #pragma unroll
-    for (int b = 0; b < CHI; ++b) {
+    for (int e = 0; e < CH; ++e) {
+      const int ab = c * CH + e;
+      const int a = ab / CHI, b = ab % CHI;
       const int pb = __builtin_popcount(b);
       const int pab = __builtin_popcount(a ^ b);
       const int sgn_bits = __builtin_popcount(b & (b >> 1)) & 1;  // sum_l b_l b_{l-1} mod 2
-      double re = pr[pb] * tr[pab] - pi_[pb] * ti[pab];
-      double im = pr[pb] * ti[pab] + pi_[pb] * tr[pab];
-      const double s = sgn_bits ? -scale : scale;
-      out[a * CHI + b] = make_float2(float(re * s), float(im * s));
+      const double re = pr[pb] * tr[pab] - pi_[pb] * ti[pab];
+      const double im = pr[pb] * ti[pab] + pi_[pb] * tr[pab];
+      const double sg = sgn_bits ? -scale : scale;
+      stage[threadIdx.x * CH + e] = make_float2(float(re * sg), float(im * sg));
     }
+    __syncthreads();
+    for (int t = threadIdx.x; t < 256 * CH; t += 256) {
+      const int p = t / CH, e = t % CH;
+      if (p < npts) dense[base + int64_t(p) * E + c * CH + e] = stage[t];
+    }
+    __syncthreads();
   }
+  if (!valid) return;
 
   // ---- Section G: gauge generators ----
   float4 rec;
