@@ -36,6 +36,12 @@
  *     the dense sweep at reps = 4 and a batch plan with a reps = 4 job.  At
  *     reps = 4 the butterfly sweep holds each pair's 128-entry environment in
  *     two lanes (split on the shared physical bit).
+ *   - A Gram call issues its tiles as one or more kernel launches of whole
+ *     rows of 64 x 64 tiles (a dispatch holds at most 2^24 - 8 blocks of 256
+ *     threads), so one row of tiles must fit one launch: Nb <= 64 *
+ *     floor((2^24 - 8) / b) with b = 16 blocks per tile (32 for the reps = 4
+ *     sweep, 1 for the state-vector Gram), i.e. Nb below about 2^26 (2^25,
+ *     2^30).  Larger Nb is QSVM_ERR_UNSUPPORTED.
  *   - No call throws across the ABI.  Results are bitwise reproducible for the
  *     same inputs, arguments and device (no floating-point atomics).
  */
@@ -205,7 +211,8 @@ typedef struct {
   int32_t diag_mode;    /* as in qsvm_gram_opts, for every job */
   int32_t use_graph;    /* 1: capture the launch (counter reset + persistent kernel)
                            into a hipGraph at plan creation and replay it */
-  int32_t grid_blocks;  /* persistent blocks; 0 = compute units x resident blocks per unit */
+  int32_t grid_blocks;  /* persistent blocks, at most 2^24 - 8; 0 = compute units x resident blocks
+                           per unit */
 } qsvm_batch_opts;
 
 typedef struct qsvm_batch_plan qsvm_batch_plan; /* opaque */

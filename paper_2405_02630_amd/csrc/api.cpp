@@ -106,6 +106,12 @@ qsvm_status run_gram(const void* mps_a, int64_t Na, const void* mps_b, int64_t N
   using qsvm::kTile;
   if (o.sweep == QSVM_SWEEP_DENSE && reps > 3)
     return fail(QSVM_ERR_UNSUPPORTED, "%s: the dense sweep supports reps <= 3", what);
+  // the sweeps launch whole rows of tiles (at most 16 blocks per tile, 32 in
+  // the reps = 4 sweep), so one row must fit one launch
+  const int64_t tiles_b = (Nb + kTile - 1) / kTile;
+  if (tiles_b * (reps == 4 ? 32 : 16) > qsvm::kMaxGridBlocks)
+    return fail(QSVM_ERR_UNSUPPORTED, "%s: Nb = %lld: one row of %lld tiles exceeds one launch", what, (long long)Nb,
+                (long long)tiles_b);
   if (o.row_end <= o.row_begin) return ok();  // empty row range: nothing to do
   qsvm::SweepArgs a{};
   a.gen_a = reinterpret_cast<const float4*>(static_cast<const char*>(mps_a) + qsvm::dense_bytes(Na, n, reps));
@@ -125,11 +131,7 @@ qsvm_status run_gram(const void* mps_a, int64_t Na, const void* mps_b, int64_t N
   a.diag_mode = o.diag_mode;
   a.tile_row0 = int32_t(o.row_begin / kTile);
   a.tile_rows = int32_t((o.row_end - 1) / kTile) - a.tile_row0 + 1;
-  a.tiles_b = int32_t((Nb + kTile - 1) / kTile);
-  // launch-size limit: at most 32 blocks per tile, < 2^31 blocks
-  const int64_t tiles = int64_t(a.tile_rows) * a.tiles_b;
-  if (tiles * 32 > (int64_t(1) << 31) - 8)
-    return fail(QSVM_ERR_UNSUPPORTED, "%s: %lld tiles exceed one launch", what, (long long)tiles);
+  a.tiles_b = int32_t(tiles_b);
   if (injected_launch_failure()) return fail(QSVM_ERR_HIP, "%s: injected launch failure (QSVM_FAULT_INJECT=launch)", what);
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = (o.sweep == QSVM_SWEEP_DENSE) ? qsvm::launch_sweep_dense_args(a, reps, s)
@@ -296,9 +298,6 @@ qsvm_status qsvm_encode_sv(const double* X, int64_t N, int32_t n_qubits, int32_t
   if (reinterpret_cast<uintptr_t>(sv) % 16 != 0) return fail(QSVM_ERR_INVALID_ARG, "%s: sv is not 16-byte aligned", what);
   if (reinterpret_cast<uintptr_t>(X) % 8 != 0) return fail(QSVM_ERR_INVALID_ARG, "%s: X is not 8-byte aligned", what);
   if (sv_bytes < need) return fail(QSVM_ERR_SIZE, "%s: sv_bytes = %zu < %zu needed", what, sv_bytes, need);
-  // one thread per 4 amplitudes (and per 2^(n-4) groups in the transform): < 2^31 blocks
-  if (int64_t(need / 16) / 4 / 256 >= (int64_t(1) << 31) - 1)
-    return fail(QSVM_ERR_UNSUPPORTED, "%s: N * 2^n too large for one launch", what);
   if (injected_launch_failure()) return fail(QSVM_ERR_HIP, "%s: injected launch failure (QSVM_FAULT_INJECT=launch)", what);
   return hip_status(qsvm::launch_encode_sv(X, N, n_qubits, reps, sv, static_cast<hipStream_t>(stream)), what);
 }
@@ -320,6 +319,10 @@ qsvm_status run_sv_gram(const void* sv_a, int64_t Na, const void* sv_b, int64_t 
   qsvm_status s = read_opts(opts, Na, o, what);
   if (s != QSVM_OK) return s;
   if (!sym) o.diag_mode = 0;
+  const int64_t tiles_b = (Nb + kTile - 1) / kTile;
+  if (tiles_b > qsvm::kMaxGridBlocks)  // one block per tile; one row per launch at least
+    return fail(QSVM_ERR_UNSUPPORTED, "%s: Nb = %lld: one row of %lld tiles exceeds one launch", what, (long long)Nb,
+                (long long)tiles_b);
   if (o.row_end <= o.row_begin) return ok();
   qsvm::SweepArgs a{};
   a.K = K;
@@ -334,9 +337,7 @@ qsvm_status run_sv_gram(const void* sv_a, int64_t Na, const void* sv_b, int64_t 
   a.diag_mode = o.diag_mode;
   a.tile_row0 = int32_t(o.row_begin / kTile);
   a.tile_rows = int32_t((o.row_end - 1) / kTile) - a.tile_row0 + 1;
-  a.tiles_b = int32_t((Nb + kTile - 1) / kTile);
-  if (int64_t(a.tile_rows) * a.tiles_b > (int64_t(1) << 31) - 8)
-    return fail(QSVM_ERR_UNSUPPORTED, "%s: too many tiles for one launch", what);
+  a.tiles_b = int32_t(tiles_b);
   if (injected_launch_failure()) return fail(QSVM_ERR_HIP, "%s: injected launch failure (QSVM_FAULT_INJECT=launch)", what);
   return hip_status(qsvm::launch_sv_gram(a, sv_a, sv_b, n, static_cast<hipStream_t>(stream)), what);
 }

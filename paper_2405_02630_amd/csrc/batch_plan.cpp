@@ -135,7 +135,8 @@ extern "C" qsvm_status qsvm_batch_plan_create(const qsvm_job* jobs, int32_t n_jo
     return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_batch_plan_create: diag_mode must be 0 or 1");
   if (o.use_graph != 0 && o.use_graph != 1)
     return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_batch_plan_create: use_graph must be 0 or 1");
-  if (o.grid_blocks < 0) return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_batch_plan_create: grid_blocks < 0");
+  if (o.grid_blocks < 0 || o.grid_blocks > (1 << 24) - 8)
+    return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_batch_plan_create: grid_blocks outside [0, 2^24 - 8]");
   for (int32_t q = 0; q < n_jobs; ++q) {
     if (jobs[q].reps > 3) {
       snprintf(msg, sizeof msg,

@@ -31,81 +31,81 @@ namespace {
 
 constexpr double kPiD = 3.14159265358979323846;
 
-// psi(b) <- 2^(-n/2) exp(i Phi_x(b)) * (FIRST ? 1 : psi(b)); each thread
-// handles 4 consecutive entries of one point (chunks = ceil(D / 4) per point).
-template <bool FIRST>
-__global__ void __launch_bounds__(256)
-sv_phase_kernel(const double* __restrict__ X, int64_t N, int32_t n, int64_t D, double2* __restrict__ sv) {
-  const int64_t chunks = (D + 3) / 4;
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= N * chunks) return;
-  const int64_t p = t / chunks;
-  const int64_t b0 = (t - p * chunks) * 4;
-  const double* x = X + p * n;
-  double ph[4] = {0.0, 0.0, 0.0, 0.0};
+// 2^(-n/2) exp(i Phi_x(b)) for basis state b of the point with features x.
+__device__ __forceinline__ double2 phase_of(const double* __restrict__ x, int32_t n, int64_t b, double scale) {
+  double ph = 0.0;
   double xk = x[0];
   for (int k = 0; k < n; ++k) {
     const double xn = (k + 1 < n) ? x[k + 1] : 0.0;
-    const double al = 2.0 * xk;
-    const double th = 2.0 * (kPiD - xk) * (kPiD - xn);
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int64_t b = b0 + e;
-      const int bk = int((b >> k) & 1);
-      if (bk) ph[e] += al;
-      if (k + 1 < n && (bk ^ int((b >> (k + 1)) & 1))) ph[e] += th;
-    }
+    const int bk = int((b >> k) & 1);
+    if (bk) ph += 2.0 * xk;
+    if (k + 1 < n && (bk ^ int((b >> (k + 1)) & 1))) ph += 2.0 * (kPiD - xk) * (kPiD - xn);
     xk = xn;
   }
-  const double scale = exp2(-0.5 * double(n));
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const int64_t b = b0 + e;
-    if (b >= D) break;
-    double s, c;
-    sincos(ph[e], &s, &c);
-    c *= scale;
-    s *= scale;
-    double2* q = sv + p * D + b;
-    if (FIRST) {
-      *q = make_double2(c, s);
-    } else {
-      const double2 v = *q;
-      *q = make_double2(fma(c, v.x, -(s * v.y)), fma(c, v.y, s * v.x));
-    }
-  }
+  double sn, cs;
+  sincos(ph, &sn, &cs);
+  return make_double2(cs * scale, sn * scale);
 }
 
-// Unnormalised Walsh-Hadamard transform on bits [s, s + G) of every state:
-// each thread loads the 2^G entries that differ only in those bits.
-template <int G>
+constexpr int kTileAmps = 2048;  // amplitudes per LDS tile (32 KB)
+constexpr int kLogTileAmps = 11;
+
+// One pass over every state, in LDS tiles: the unnormalised Walsh-Hadamard
+// transform on bits [s, s + G), optionally preceded by GEN (the tile is the
+// first repetition's state 2^(-n/2) exp(i Phi(b)), computed instead of read)
+// and followed by FUSE (each amplitude multiplied by 2^(-n/2) exp(i Phi(b))).
+// `stages` is G, or 0 for a pass that only generates the first state.
+// A tile is 2^G rows (the bits of the pass) x 2^LC consecutive columns (the
+// indices below bit s, LC <= s), row u / column c at
+// b = h 2^(s+G) + u 2^s + cg 2^LC + c, so global accesses run over 2^LC
+// contiguous amplitudes.  Blocks stride over the N 2^n / 2^(G+LC) tiles.
+template <bool GEN, bool FUSE>
 __global__ void __launch_bounds__(256)
-sv_wht_kernel(int64_t N, int32_t n, int32_t s, double2* __restrict__ sv) {
-  constexpr int P = 1 << G;
-  const int64_t per_point = int64_t(1) << (n - G);
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= N * per_point) return;
-  const int64_t p = t / per_point;
-  const int64_t r = t - p * per_point;
-  const int64_t low = r & ((int64_t(1) << s) - 1);
-  const int64_t high = r >> s;
-  double2* base = sv + (p << n) + (high << (s + G)) + low;
-  const int64_t stride = int64_t(1) << s;
-  double2 v[P];
-#pragma unroll
-  for (int u = 0; u < P; ++u) v[u] = base[u * stride];
-#pragma unroll
-  for (int g = 0; g < G; ++g) {
-#pragma unroll
-    for (int u = 0; u < P; ++u) {
-      if (u & (1 << g)) continue;
-      const double2 a = v[u], c = v[u | (1 << g)];
-      v[u] = make_double2(a.x + c.x, a.y + c.y);
-      v[u | (1 << g)] = make_double2(a.x - c.x, a.y - c.y);
+sv_pass_kernel(const double* __restrict__ X, int64_t N, int32_t n, int32_t s, int32_t G, int32_t LC,
+               int32_t stages, double2* __restrict__ sv) {
+  __shared__ double2 t_[kTileAmps];
+  const int T = 1 << (G + LC);                       // amplitudes per tile (<= kTileAmps)
+  const int cmask = (1 << LC) - 1;
+  const int32_t log_tpp = n - G - LC;                // log2 tiles per point
+  const int32_t log_groups = s - LC;                 // log2 column groups below bit s
+  const int64_t total = N << log_tpp;
+  const double scale = exp2(-0.5 * double(n));
+  for (int64_t tl = blockIdx.x; tl < total; tl += gridDim.x) {  // block-uniform
+    const int64_t p = tl >> log_tpp;
+    const int64_t tile = tl & ((int64_t(1) << log_tpp) - 1);
+    const int64_t cg = tile & ((int64_t(1) << log_groups) - 1), h = tile >> log_groups;
+    const int64_t base = (h << (s + G)) + (cg << LC);
+    const double* x = X + p * n;
+    double2* psi = sv + (p << n);
+    auto amp_index = [&](int idx) { return base + (int64_t(idx >> LC) << s) + (idx & cmask); };
+
+    for (int idx = threadIdx.x; idx < T; idx += 256) {
+      const int64_t bi = amp_index(idx);
+      t_[idx] = GEN ? phase_of(x, n, bi, scale) : psi[bi];
     }
+    for (int g = 0; g < stages; ++g) {
+      __syncthreads();
+      for (int q = threadIdx.x; q < T / 2; q += 256) {
+        const int c = q & cmask, ur = q >> LC;
+        const int u0 = ((ur >> g) << (g + 1)) | (ur & ((1 << g) - 1));
+        const int i0 = (u0 << LC) + c, i1 = ((u0 | (1 << g)) << LC) + c;
+        const double2 a = t_[i0], d = t_[i1];
+        t_[i0] = make_double2(a.x + d.x, a.y + d.y);
+        t_[i1] = make_double2(a.x - d.x, a.y - d.y);
+      }
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < T; idx += 256) {
+      const int64_t bi = amp_index(idx);
+      double2 v = t_[idx];
+      if (FUSE) {
+        const double2 f = phase_of(x, n, bi, scale);
+        v = make_double2(fma(f.x, v.x, -(f.y * v.y)), fma(f.x, v.y, f.y * v.x));
+      }
+      psi[bi] = v;
+    }
+    __syncthreads();  // the tile buffer is reused by the next tile
   }
-#pragma unroll
-  for (int u = 0; u < P; ++u) base[u * stride] = v[u];
 }
 
 typedef double dvec4 __attribute__((ext_vector_type(4)));
@@ -248,38 +248,61 @@ sv_reduce_kernel(SweepArgs a, int32_t splits, const double2* __restrict__ W) {
 }  // namespace
 
 hipError_t launch_encode_sv(const double* X, int64_t N, int32_t n, int32_t reps, void* sv, hipStream_t stream) {
-  const int64_t D = int64_t(1) << n;
-  double2* s = static_cast<double2*>(sv);
-  const dim3 pgrid(unsigned((N * ((D + 3) / 4) + 255) / 256));
-  for (int l = 0; l < reps; ++l) {
-    if (l > 0) {
-      // unnormalised H on every qubit, up to 4 bits per pass
-      for (int s0 = 0; s0 < n; s0 += 4) {
-        const int g = (n - s0 < 4) ? n - s0 : 4;
-        const int64_t threads = N * (D >> g);
-        const dim3 grid(unsigned((threads + 255) / 256));
-        switch (g) {
-          case 1: hipLaunchKernelGGL(sv_wht_kernel<1>, grid, dim3(256), 0, stream, N, n, s0, s); break;
-          case 2: hipLaunchKernelGGL(sv_wht_kernel<2>, grid, dim3(256), 0, stream, N, n, s0, s); break;
-          case 3: hipLaunchKernelGGL(sv_wht_kernel<3>, grid, dim3(256), 0, stream, N, n, s0, s); break;
-          default: hipLaunchKernelGGL(sv_wht_kernel<4>, grid, dim3(256), 0, stream, N, n, s0, s); break;
-        }
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-      }
-      hipLaunchKernelGGL(sv_phase_kernel<false>, pgrid, dim3(256), 0, stream, X, N, n, D, s);
-    } else {
-      hipLaunchKernelGGL(sv_phase_kernel<true>, pgrid, dim3(256), 0, stream, X, N, n, D, s);
+  double2* st = static_cast<double2*>(sv);
+  // passes of one full transform: the low bits as whole contiguous tiles,
+  // then the remaining bits in the fewest groups of at most 9 bits, balanced
+  // in size, each over tiles of 2^11 amplitudes (2^(11-G) contiguous columns)
+  struct Pass { int s, G, LC; };
+  Pass passes[8];
+  int np = 0;
+  {
+    const int g0 = n < kLogTileAmps ? n : kLogTileAmps;
+    passes[np++] = {0, g0, 0};
+    const int rest = n - g0;
+    const int groups = (rest + 8) / 9;
+    for (int q = 0, s = g0; q < groups; ++q) {
+      const int g = (n - s + (groups - q) - 1) / (groups - q);
+      passes[np++] = {s, g, kLogTileAmps - g};  // kLogTileAmps - g <= s since s >= 11
+      s += g;
     }
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+  }
+  auto launch = [&](const Pass& pa, bool gen, bool fuse, int stages) {
+    const int64_t tiles = N << (n - pa.G - pa.LC);
+    const int64_t blocks = tiles < kMaxGridBlocks ? tiles : kMaxGridBlocks / 8 * 8;
+    const dim3 grid{unsigned(blocks)};
+    if (gen && fuse)
+      hipLaunchKernelGGL((sv_pass_kernel<true, true>), grid, dim3(256), 0, stream, X, N, n, pa.s, pa.G, pa.LC, stages,
+                         st);
+    else if (gen)
+      hipLaunchKernelGGL((sv_pass_kernel<true, false>), grid, dim3(256), 0, stream, X, N, n, pa.s, pa.G, pa.LC,
+                         stages, st);
+    else if (fuse)
+      hipLaunchKernelGGL((sv_pass_kernel<false, true>), grid, dim3(256), 0, stream, X, N, n, pa.s, pa.G, pa.LC,
+                         stages, st);
+    else
+      hipLaunchKernelGGL((sv_pass_kernel<false, false>), grid, dim3(256), 0, stream, X, N, n, pa.s, pa.G, pa.LC,
+                         stages, st);
+    return hipGetLastError();
+  };
+  if (reps == 1) {
+    // the first repetition alone: write the phase state (no transform)
+    return launch(passes[0], true, false, 0);
+  }
+  // repetitions 2..reps: transform then phase; the first repetition's state is
+  // generated inside the first pass instead of being written and read back
+  for (int l = 2; l <= reps; ++l) {
+    for (int q = 0; q < np; ++q) {
+      const hipError_t e = launch(passes[q], l == 2 && q == 0, q == np - 1, passes[q].G);
+      if (e != hipSuccess) return e;
+    }
   }
   return hipSuccess;
 }
 
-hipError_t launch_sv_gram(const SweepArgs& a0, const void* sv_a, const void* sv_b, int32_t n, hipStream_t stream) {
-  SweepArgs a = a0;
-  a.blocks_per_tile = 1;
+namespace {
+
+// One launch (plus its split-K reduction) over the tiles of `a`.
+hipError_t sv_gram_chunk(SweepArgs a, const void* sv_a, const void* sv_b, int32_t n, hipStream_t stream) {
   const int64_t tiles = launch_tiles(a);
   if (tiles <= 0) return hipSuccess;
   const int64_t D = int64_t(1) << n;
@@ -290,8 +313,7 @@ hipError_t launch_sv_gram(const SweepArgs& a0, const void* sv_a, const void* sv_
   if (splits < 1) splits = 1;
   const int64_t kchunk = ((D + splits - 1) / splits + kKB - 1) / kKB * kKB;
   splits = (D + kchunk - 1) / kchunk;
-  const int64_t blocks = tiles * splits;
-  if (blocks > (int64_t(1) << 31) - 8) return hipErrorInvalidValue;
+  const int64_t blocks = tiles * splits;  // splits > 1 only below 1024 tiles
   a.num_blocks = uint32_t(blocks);
   double2* W = nullptr;
   if (splits > 1) {
@@ -316,6 +338,14 @@ hipError_t launch_sv_gram(const SweepArgs& a0, const void* sv_a, const void* sv_
     if (e == hipSuccess) e = f;
   }
   return e;
+}
+
+}  // namespace
+
+hipError_t launch_sv_gram(const SweepArgs& a0, const void* sv_a, const void* sv_b, int32_t n, hipStream_t stream) {
+  SweepArgs a = a0;
+  a.blocks_per_tile = 1;
+  return launch_chunked(a, 1, [&](const SweepArgs& c) { return sv_gram_chunk(c, sv_a, sv_b, n, stream); });
 }
 
 }  // namespace qsvm

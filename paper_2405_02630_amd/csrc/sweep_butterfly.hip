@@ -27,13 +27,14 @@ template <int R, int PI, int W>
 hipError_t launch_pi(const SweepArgs& a0, hipStream_t stream) {
   SweepArgs a = a0;
   a.blocks_per_tile = kTile / (4 * PI);
-  const int64_t blocks = launch_tiles(a) * a.blocks_per_tile;
-  if (blocks <= 0) return hipSuccess;
-  if (blocks > (int64_t(1) << 31) - 8) return hipErrorInvalidValue;
-  a.num_blocks = uint32_t(blocks);
-  const uint32_t padded = uint32_t((blocks + 7) / 8 * 8);
-  hipLaunchKernelGGL((sweep_butterfly_kernel<R, PI, W>), dim3(padded), dim3(256), 0, stream, a);
-  return hipGetLastError();
+  return launch_chunked(a, a.blocks_per_tile, [&](SweepArgs c) {
+    const int64_t blocks = launch_tiles(c) * c.blocks_per_tile;
+    if (blocks <= 0) return hipSuccess;
+    c.num_blocks = uint32_t(blocks);
+    const uint32_t padded = uint32_t((blocks + 7) / 8 * 8);
+    hipLaunchKernelGGL((sweep_butterfly_kernel<R, PI, W>), dim3(padded), dim3(256), 0, stream, c);
+    return hipGetLastError();
+  });
 }
 
 }  // namespace

@@ -43,6 +43,46 @@ __host__ __device__ inline int64_t launch_tiles(const SweepArgs& a) {
   return int64_t(a.tile_rows) * a.tiles_b;
 }
 
+// A dispatch carries its grid size in work-items as a 32-bit number, so one
+// launch of 256-thread blocks holds fewer than 2^24 blocks.
+constexpr int64_t kMaxGridBlocks = (int64_t(1) << 24) - 8;
+
+// Issue the tiles of `a` as one or more launches of at most kMaxGridBlocks
+// blocks each: consecutive tile rows (the row range narrowed to them) or
+// consecutive stretches of the tile list.  `one(chunk)` launches one chunk.
+// A single tile row too wide for one launch is an error.
+template <class F>
+hipError_t launch_chunked(const SweepArgs& a, int64_t blocks_per_tile, F one) {
+  const int64_t cap = kMaxGridBlocks / blocks_per_tile;  // tiles per launch
+  if (a.tile_list) {
+    for (int64_t off = 0; off < a.tile_rows; off += cap) {
+      SweepArgs c = a;
+      c.tile_list = a.tile_list + 2 * off;
+      c.tile_rows = int32_t((a.tile_rows - off < cap) ? a.tile_rows - off : cap);
+      const hipError_t e = one(c);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  const int64_t t_end = int64_t(a.tile_row0) + a.tile_rows;
+  for (int64_t t = a.tile_row0; t < t_end;) {
+    // tiles of tile row u: the full grid, or the upper triangle from u on
+    auto row_tiles = [&](int64_t u) { return a.sym ? a.tiles_b - u : int64_t(a.tiles_b); };
+    if (row_tiles(t) > cap) return hipErrorInvalidConfiguration;
+    int64_t m = 0, tiles = 0;
+    while (t + m < t_end && tiles + row_tiles(t + m) <= cap) tiles += row_tiles(t + m++);
+    SweepArgs c = a;
+    c.tile_row0 = int32_t(t);
+    c.tile_rows = int32_t(m);
+    c.row_begin = (t * kTile > a.row_begin) ? t * kTile : a.row_begin;
+    c.row_end = ((t + m) * kTile < a.row_end) ? (t + m) * kTile : a.row_end;
+    const hipError_t e = one(c);
+    if (e != hipSuccess) return e;
+    t += m;
+  }
+  return hipSuccess;
+}
+
 // Map the hardware block index to a logical block so that the blocks of one
 // tile run back to back on the same XCD (the dispatcher hands consecutive
 // block indices to the 8 XCDs round robin).  The grid is padded to a

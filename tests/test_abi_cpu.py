@@ -124,6 +124,18 @@ def test_gram_rect_validation(lib, no_inject):
     assert _rect(lib, reps=5) == qsvm.QSVM_ERR_UNSUPPORTED
 
 
+# One row of 64 x 64 tiles must fit one launch of at most 2^24 - 8 blocks:
+# 16 blocks per tile (1048575 tiles, 67108800 points), 32 at reps = 4
+# (524287 tiles, 33554368 points).  Validation fails before any HIP call.
+@pytest.mark.parametrize("reps,nb_max", [(2, 64 * 1048575), (4, 64 * 524287)])
+def test_gram_rejects_a_tile_row_wider_than_one_launch(lib, no_inject, reps, nb_max):
+    opts = qsvm.GramOpts()
+    opts.row_begin, opts.row_end = 5, 5  # empty range: a valid Nb returns before launching
+    assert _rect(lib, Na=64, Nb=nb_max, n=4, reps=reps, opts=opts) == qsvm.QSVM_OK
+    assert _rect(lib, Na=64, Nb=nb_max + 1, n=4, reps=reps, opts=opts) == qsvm.QSVM_ERR_UNSUPPORTED
+    assert b"exceeds one launch" in lib.qsvm_last_error()
+
+
 def test_dense_sweep_rejects_reps_4(lib, no_inject):
     opts = qsvm.GramOpts()
     opts.sweep = qsvm.SWEEP_DENSE
@@ -218,7 +230,10 @@ def test_batch_plan_unsupported_reps(lib, no_inject):
     assert st == qsvm.QSVM_ERR_UNSUPPORTED and not h.value
 
 
-@pytest.mark.parametrize("field,value", [("renorm_every", 17), ("diag_mode", 3), ("use_graph", 2), ("grid_blocks", -1)])
+@pytest.mark.parametrize(
+    "field,value",
+    [("renorm_every", 17), ("diag_mode", 3), ("use_graph", 2), ("grid_blocks", -1), ("grid_blocks", 1 << 24)],
+)
 def test_batch_plan_rejects_bad_opts(lib, no_inject, field, value):
     o = qsvm.BatchOpts()
     setattr(o, field, value)
@@ -299,6 +314,16 @@ def test_sv_gram_validation(lib, no_inject):
     o = qsvm.GramOpts()
     o.diag_mode = 2
     assert lib.qsvm_sv_gram_sym(FAKE, 5, 4, FAKE2, 5, ctypes.byref(o), None) == qsvm.QSVM_ERR_INVALID_ARG
+
+
+def test_sv_gram_rejects_a_tile_row_wider_than_one_launch(lib, no_inject):
+    # one block per 64 x 64 tile: at most 2^24 - 8 tiles, 64 (2^24 - 8) points, in a row
+    o = qsvm.GramOpts()
+    o.row_begin, o.row_end = 2, 2
+    nb = 64 * ((1 << 24) - 8)
+    assert lib.qsvm_sv_gram(FAKE, 5, FAKE2, nb, 1, FAKE, nb, ctypes.byref(o), None) == qsvm.QSVM_OK
+    assert lib.qsvm_sv_gram(FAKE, 5, FAKE2, nb + 1, 1, FAKE, nb + 1, ctypes.byref(o), None) == qsvm.QSVM_ERR_UNSUPPORTED
+    assert b"exceeds one launch" in lib.qsvm_last_error()
 
 
 def test_sv_injected_launch_failure(lib, monkeypatch):
