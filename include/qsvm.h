@@ -285,8 +285,13 @@ size_t qsvm_sv_bytes(int64_t N, int32_t n_qubits);
  * map; the CNOT-P-CNOT block is that diagonal phase).  reps in 1..16.
  *   sv        device output of at least qsvm_sv_bytes(N, n) bytes, 16-byte
  *             aligned, caller-owned.
+ * The phase factors come from per-point tables of 2^L + 2^(n-L+1) complex128
+ * values, L = min(n, 11) (2^n + 2 values up to 11 qubits; beyond that
+ * 2^11 + 2^(n-10), about 2^-9 of the states from 20 qubits on), held in a
+ * stream-ordered temporary (hipMallocAsync / hipFreeAsync on `stream`).
  * QSVM_ERR_UNSUPPORTED for n_qubits outside 1..30; QSVM_ERR_SIZE for a short
- * buffer; QSVM_ERR_INVALID_ARG for other bad arguments.
+ * buffer; QSVM_ERR_INVALID_ARG for other bad arguments; QSVM_ERR_HIP if the
+ * temporary cannot be allocated.
  */
 qsvm_status qsvm_encode_sv(const double* X, int64_t N, int32_t n_qubits, int32_t reps, void* sv,
                            size_t sv_bytes, void* stream);

@@ -13,9 +13,9 @@
 //     Phi(b) = sum_k 2 x_k b_k + sum_{k<n-1} theta_k (b_k XOR b_{k+1}),
 // theta_k = 2 (pi - x_k)(pi - x_{k+1}), bit k of b being qubit k.  So
 // psi = (D H)^r |0>: the first H gives the uniform state, each later H is an
-// unnormalised Walsh-Hadamard transform (register-radix passes of up to 4
-// bits), and the phase pass applies 2^(-n/2) exp(i Phi(b)) (the H
-// normalisation folded in).
+// unnormalised Walsh-Hadamard transform (passes over LDS tiles), and each
+// repetition ends by multiplying with 2^(-n/2) exp(i Phi(b)) (the H
+// normalisation folded in), read from two small per-point tables.
 //
 // Gram: v_mfma_f64_16x16x4_f64 on 64 x 64 output tiles (4 waves of 32 x 32),
 // inner dimension staged through LDS 16 complex values at a time, complex
@@ -31,24 +31,65 @@ namespace {
 
 constexpr double kPiD = 3.14159265358979323846;
 
-// 2^(-n/2) exp(i Phi_x(b)) for basis state b of the point with features x.
-__device__ __forceinline__ double2 phase_of(const double* __restrict__ x, int32_t n, int64_t b, double scale) {
-  double ph = 0.0;
-  double xk = x[0];
-  for (int k = 0; k < n; ++k) {
-    const double xn = (k + 1 < n) ? x[k + 1] : 0.0;
-    const int bk = int((b >> k) & 1);
-    if (bk) ph += 2.0 * xk;
-    if (k + 1 < n && (bk ^ int((b >> (k + 1)) & 1))) ph += 2.0 * (kPiD - xk) * (kPiD - xn);
-    xk = xn;
-  }
-  double sn, cs;
-  sincos(ph, &sn, &cs);
-  return make_double2(cs * scale, sn * scale);
+constexpr int kLogTileAmps = 11;
+constexpr int kTileAmps = 1 << kLogTileAmps;  // amplitudes per LDS tile (32 KB)
+
+// The phase splits over the low L = min(n, 11) bits and the rest:
+//     Phi(b) = Phi_lo(b mod 2^L) + Phi_hi(b >> L) + theta_{L-1} (b_{L-1} XOR b_L),
+// Phi_lo holding the terms of qubits below L (and the pairs inside them),
+// Phi_hi those of qubits L and up.  Per point two tables hold
+//     lo[l]        = 2^(-n/2) exp(i Phi_lo(l)),                      l < 2^L,
+//     hi[2 h + t]  = exp(i (Phi_hi(h) + theta_{L-1} (t XOR h_0))),  h < 2^(n-L),
+// so that 2^(-n/2) exp(i Phi(b)) = lo[b mod 2^L] hi[b >> (L-1)]  (for n = L
+// the boundary term is absent and hi = {1, 1}).  Each entry is one FP64
+// angle sum and one sincos.
+__host__ __device__ inline int32_t low_bits(int32_t n) { return n < kLogTileAmps ? n : kLogTileAmps; }
+__host__ __device__ inline int64_t table_size(int32_t n) {
+  return (int64_t(1) << low_bits(n)) + (int64_t(2) << (n - low_bits(n)));
 }
 
-constexpr int kTileAmps = 2048;  // amplitudes per LDS tile (32 KB)
-constexpr int kLogTileAmps = 11;
+__device__ __forceinline__ double zz_theta(const double* __restrict__ x, int k) {
+  return 2.0 * (kPiD - x[k]) * (kPiD - x[k + 1]);
+}
+
+__global__ void __launch_bounds__(256)
+sv_table_kernel(const double* __restrict__ X, int64_t N, int32_t n, double2* __restrict__ tab) {
+  const int32_t L = low_bits(n);
+  const int64_t TS = table_size(n), lo_size = int64_t(1) << L;
+  const double scale = exp2(-0.5 * double(n));
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < N * TS; t += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t p = t / TS, e = t - p * TS;
+    const double* x = X + p * n;
+    double ph = 0.0, amp = 1.0;
+    if (e < lo_size) {
+      for (int k = 0; k < L; ++k) {
+        const int bk = int((e >> k) & 1);
+        if (bk) ph += 2.0 * x[k];
+        if (k + 1 < L && (bk ^ int((e >> (k + 1)) & 1))) ph += zz_theta(x, k);
+      }
+      amp = scale;
+    } else if (n > L) {
+      const int64_t u = e - lo_size, h = u >> 1;
+      const int tb = int(u & 1);  // bit L-1 of b
+      if (tb ^ int(h & 1)) ph += zz_theta(x, L - 1);
+      for (int k = L; k < n; ++k) {
+        const int bk = int((h >> (k - L)) & 1);
+        if (bk) ph += 2.0 * x[k];
+        if (k + 1 < n && (bk ^ int((h >> (k + 1 - L)) & 1))) ph += zz_theta(x, k);
+      }
+    }
+    double sn, cs;
+    sincos(ph, &sn, &cs);
+    tab[t] = make_double2(cs * amp, sn * amp);
+  }
+}
+
+// 2^(-n/2) exp(i Phi(b)) from the point's tables.
+__device__ __forceinline__ double2 phase_of(const double2* __restrict__ tab, int32_t L, int64_t b) {
+  const double2 l = tab[b & ((int64_t(1) << L) - 1)];
+  const double2 h = tab[(int64_t(1) << L) + (b >> (L - 1))];
+  return make_double2(fma(l.x, h.x, -(l.y * h.y)), fma(l.x, h.y, l.y * h.x));
+}
 
 // One pass over every state, in LDS tiles: the unnormalised Walsh-Hadamard
 // transform on bits [s, s + G), optionally preceded by GEN (the tile is the
@@ -61,7 +102,7 @@ constexpr int kLogTileAmps = 11;
 // contiguous amplitudes.  Blocks stride over the N 2^n / 2^(G+LC) tiles.
 template <bool GEN, bool FUSE>
 __global__ void __launch_bounds__(256)
-sv_pass_kernel(const double* __restrict__ X, int64_t N, int32_t n, int32_t s, int32_t G, int32_t LC,
+sv_pass_kernel(const double2* __restrict__ tab, int64_t N, int32_t n, int32_t s, int32_t G, int32_t LC,
                int32_t stages, double2* __restrict__ sv) {
   __shared__ double2 t_[kTileAmps];
   const int T = 1 << (G + LC);                       // amplitudes per tile (<= kTileAmps)
@@ -69,19 +110,20 @@ sv_pass_kernel(const double* __restrict__ X, int64_t N, int32_t n, int32_t s, in
   const int32_t log_tpp = n - G - LC;                // log2 tiles per point
   const int32_t log_groups = s - LC;                 // log2 column groups below bit s
   const int64_t total = N << log_tpp;
-  const double scale = exp2(-0.5 * double(n));
+  const int32_t L = low_bits(n);
+  const int64_t TS = table_size(n);
   for (int64_t tl = blockIdx.x; tl < total; tl += gridDim.x) {  // block-uniform
     const int64_t p = tl >> log_tpp;
     const int64_t tile = tl & ((int64_t(1) << log_tpp) - 1);
     const int64_t cg = tile & ((int64_t(1) << log_groups) - 1), h = tile >> log_groups;
     const int64_t base = (h << (s + G)) + (cg << LC);
-    const double* x = X + p * n;
+    const double2* tp = tab + p * TS;
     double2* psi = sv + (p << n);
     auto amp_index = [&](int idx) { return base + (int64_t(idx >> LC) << s) + (idx & cmask); };
 
     for (int idx = threadIdx.x; idx < T; idx += 256) {
       const int64_t bi = amp_index(idx);
-      t_[idx] = GEN ? phase_of(x, n, bi, scale) : psi[bi];
+      t_[idx] = GEN ? phase_of(tp, L, bi) : psi[bi];
     }
     for (int g = 0; g < stages; ++g) {
       __syncthreads();
@@ -99,7 +141,7 @@ sv_pass_kernel(const double* __restrict__ X, int64_t N, int32_t n, int32_t s, in
       const int64_t bi = amp_index(idx);
       double2 v = t_[idx];
       if (FUSE) {
-        const double2 f = phase_of(x, n, bi, scale);
+        const double2 f = phase_of(tp, L, bi);
         v = make_double2(fma(f.x, v.x, -(f.y * v.y)), fma(f.x, v.y, f.y * v.x));
       }
       psi[bi] = v;
@@ -256,7 +298,7 @@ hipError_t launch_encode_sv(const double* X, int64_t N, int32_t n, int32_t reps,
   Pass passes[8];
   int np = 0;
   {
-    const int g0 = n < kLogTileAmps ? n : kLogTileAmps;
+    const int g0 = low_bits(n);
     passes[np++] = {0, g0, 0};
     const int rest = n - g0;
     const int groups = (rest + 8) / 9;
@@ -266,37 +308,50 @@ hipError_t launch_encode_sv(const double* X, int64_t N, int32_t n, int32_t reps,
       s += g;
     }
   }
+  // the phase tables live in a stream-ordered temporary
+  const int64_t tab_entries = N * table_size(n);
+  double2* tab = nullptr;
+  hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&tab), size_t(tab_entries) * sizeof(double2), stream);
+  if (e != hipSuccess) return e;
+  {
+    const int64_t blocks = (tab_entries + 255) / 256;
+    hipLaunchKernelGGL(sv_table_kernel, dim3(unsigned(blocks < kMaxGridBlocks ? blocks : kMaxGridBlocks / 8 * 8)),
+                       dim3(256), 0, stream, X, N, n, tab);
+    e = hipGetLastError();
+  }
   auto launch = [&](const Pass& pa, bool gen, bool fuse, int stages) {
     const int64_t tiles = N << (n - pa.G - pa.LC);
     const int64_t blocks = tiles < kMaxGridBlocks ? tiles : kMaxGridBlocks / 8 * 8;
     const dim3 grid{unsigned(blocks)};
     if (gen && fuse)
-      hipLaunchKernelGGL((sv_pass_kernel<true, true>), grid, dim3(256), 0, stream, X, N, n, pa.s, pa.G, pa.LC, stages,
-                         st);
+      hipLaunchKernelGGL((sv_pass_kernel<true, true>), grid, dim3(256), 0, stream, tab, N, n, pa.s, pa.G, pa.LC,
+                         stages, st);
     else if (gen)
-      hipLaunchKernelGGL((sv_pass_kernel<true, false>), grid, dim3(256), 0, stream, X, N, n, pa.s, pa.G, pa.LC,
+      hipLaunchKernelGGL((sv_pass_kernel<true, false>), grid, dim3(256), 0, stream, tab, N, n, pa.s, pa.G, pa.LC,
                          stages, st);
     else if (fuse)
-      hipLaunchKernelGGL((sv_pass_kernel<false, true>), grid, dim3(256), 0, stream, X, N, n, pa.s, pa.G, pa.LC,
+      hipLaunchKernelGGL((sv_pass_kernel<false, true>), grid, dim3(256), 0, stream, tab, N, n, pa.s, pa.G, pa.LC,
                          stages, st);
     else
-      hipLaunchKernelGGL((sv_pass_kernel<false, false>), grid, dim3(256), 0, stream, X, N, n, pa.s, pa.G, pa.LC,
+      hipLaunchKernelGGL((sv_pass_kernel<false, false>), grid, dim3(256), 0, stream, tab, N, n, pa.s, pa.G, pa.LC,
                          stages, st);
     return hipGetLastError();
   };
-  if (reps == 1) {
-    // the first repetition alone: write the phase state (no transform)
-    return launch(passes[0], true, false, 0);
-  }
-  // repetitions 2..reps: transform then phase; the first repetition's state is
-  // generated inside the first pass instead of being written and read back
-  for (int l = 2; l <= reps; ++l) {
-    for (int q = 0; q < np; ++q) {
-      const hipError_t e = launch(passes[q], l == 2 && q == 0, q == np - 1, passes[q].G);
-      if (e != hipSuccess) return e;
+  if (e == hipSuccess) {
+    if (reps == 1) {
+      // the first repetition alone: write the phase state (no transform)
+      e = launch(passes[0], true, false, 0);
+    } else {
+      // repetitions 2..reps: transform then phase; the first repetition's
+      // state is generated inside the first pass instead of being written and
+      // read back
+      for (int l = 2; l <= reps && e == hipSuccess; ++l)
+        for (int q = 0; q < np && e == hipSuccess; ++q)
+          e = launch(passes[q], l == 2 && q == 0, q == np - 1, passes[q].G);
     }
   }
-  return hipSuccess;
+  const hipError_t f = hipFreeAsync(tab, stream);
+  return e != hipSuccess ? e : f;
 }
 
 namespace {
