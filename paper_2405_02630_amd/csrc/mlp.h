@@ -11,7 +11,6 @@ enum GemmEpilogue {
   EPI_BIAS_GELU = 1,     // C (float) = acc + bias (pre-activation); C2 (bf16) = gelu(C)
   EPI_BIAS = 2,          // C (float) = acc + bias; C2 (bf16) = C
   EPI_GELU_BWD = 3,      // C2 (bf16) = acc * gelu'(aux)
-  EPI_SIGMOID_GRAM = 4,  // C (double) = sigmoid(ab[0] acc + ab[1]), diagonal 1; tile_max per block
 };
 
 struct GemmArgs {
@@ -20,14 +19,11 @@ struct GemmArgs {
   int64_t lda;
   const void* B;      // bf16
   int64_t ldb;
-  void* C;            // float or double (see epilogue)
+  void* C;            // float
   void* C2;           // bf16 output of some epilogues
   int64_t ldc;        // row stride of C, C2 and aux
   const float* bias;  // [N]
   const float* aux;   // pre-activation for EPI_GELU_BWD
-  const float* ab;    // device (alpha, beta) for EPI_SIGMOID_GRAM
-  float* tile_max;    // [M/64][N/64] for EPI_SIGMOID_GRAM
-  int64_t valid;      // rows/cols < valid are real points (EPI_SIGMOID_GRAM)
   int32_t splits;     // split-K factor (>= 1; > 1 only with EPI_F32: C holds `splits` slabs of M x ldc)
 };
 
@@ -37,6 +33,9 @@ struct AdamArgs {
 };
 
 hipError_t launch_gemm(int ta, int tb, int epi, const GemmArgs& g, hipStream_t s);
+// K = sigmoid(ab[0] E E^T + ab[1]), diagonal 1, per-64x64-tile off-diagonal maxima.
+hipError_t launch_sigmoid_gram(const uint16_t* E, int64_t N_pad, int32_t d, const float* ab, double* K, int64_t ldk,
+                               int64_t valid, float* tile_max, hipStream_t s);
 hipError_t launch_gather(const double* X, int64_t N, int32_t n, const int32_t* idx, int64_t rows, int32_t d_pad,
                          uint16_t* out, hipStream_t s);
 int colsum_chunks(int64_t rows);

@@ -9,8 +9,10 @@
 //   LDS load.  Dimensions are multiples of the tile (the host pads), so no
 //   bounds checks are needed.  Fused epilogues: FP32 store; bias + GELU
 //   (keeps the pre-activation for the backward pass); bias + FP32/BF16 store;
-//   multiply by GELU'(pre-activation) (backward through the activation);
-//   sigmoid-scaled Gram with per-tile maxima of the off-diagonal entries.
+//   multiply by GELU'(pre-activation) (backward through the activation).
+// * sigmoid_gram_kernel: K_hat of all pairs, FP64, with per-tile maxima of
+//   the off-diagonal entries (write-bound; 128 x 64 blocks, non-temporal
+//   stores).
 // * gather_features: FP64 feature rows -> zero-padded BF16 rows.
 // * colsum_partial + sum_slabs: bias gradients (column sums in two fixed-order
 //   stages) and the reduction of split-K partial products.
@@ -62,7 +64,6 @@ template <int TA, int TB, int EPI>
 __global__ void __launch_bounds__(256) bf16_gemm(GemmArgs g) {
   __shared__ __attribute__((aligned(16))) uint16_t As[BM * LDS_STRIDE];  // [m][k]
   __shared__ __attribute__((aligned(16))) uint16_t Bs[BN * LDS_STRIDE];  // [n][k]
-  __shared__ float red[4];
   const int t = threadIdx.x;
   const int lane = t & 63;
   const int wave = t >> 6;
@@ -117,7 +118,6 @@ __global__ void __launch_bounds__(256) bf16_gemm(GemmArgs g) {
 
   // ---- epilogue: element v of the accumulator is row i, column j ----
   const int j = lane & 31;
-  float tmax = -INFINITY;
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
     const int i = (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
@@ -137,22 +137,87 @@ __global__ void __launch_bounds__(256) bf16_gemm(GemmArgs g) {
     } else if (EPI == EPI_GELU_BWD) {
       const float d = x * gelu_grad(g.aux[r * g.ldc + c]);
       static_cast<uint16_t*>(g.C2)[r * g.ldc + c] = f32_to_bf16(d);
-    } else if (EPI == EPI_SIGMOID_GRAM) {
-      if (r < g.valid && c < g.valid) {
-        const float s = sigmoidf(g.ab[0] * x + g.ab[1]);
-        static_cast<double*>(g.C)[r * g.ldc + c] = (r == c) ? 1.0 : double(s);
-        if (r != c) tmax = fmaxf(tmax, s);
-      }
     }
   }
-  if (EPI == EPI_SIGMOID_GRAM) {
-    for (int off = 32; off > 0; off >>= 1) tmax = fmaxf(tmax, __shfl_xor(tmax, off, 64));
-    if (lane == 0) red[wave] = tmax;
-    __syncthreads();
-    if (t == 0) {
-      const float mx = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
-      g.tile_max[int64_t(blockIdx.y) * gridDim.x + blockIdx.x] = mx;
+}
+
+// Sigmoid-scaled Gram of the embeddings, K = sigmoid(ab[0] E E^T + ab[1])
+// with K[i][i] = 1, on 128 x 64 output blocks (two 64 x 64 tiles of
+// tile_max), the inner dimension staged through LDS 32 at a time as in
+// bf16_gemm.  The kernel is bound by writing K (8 B per entry, the whole
+// square: recomputing the lower triangle keeps every store stream
+// row-sequential, which measured faster than mirroring the upper one); the
+// 128-row blocks halve the operand traffic per output byte of a 64 x 64
+// block, and the stores are non-temporal (K is not read back here).  Rows
+// past N_pad (an odd tile count) are clamped on load and never stored.
+__global__ void __launch_bounds__(256)
+sigmoid_gram_kernel(const uint16_t* __restrict__ E, int64_t N_pad, int32_t d, const float* __restrict__ ab,
+                    double* __restrict__ K, int64_t ldk, int64_t valid, float* __restrict__ tile_max) {
+  constexpr int GM = 128, GN = 64;
+  __shared__ __attribute__((aligned(16))) uint16_t As[GM * LDS_STRIDE];  // [m][k]
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[GN * LDS_STRIDE];  // [n][k]
+  __shared__ float red[2][4];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int64_t T = N_pad / 64;
+  const int64_t m0 = int64_t(blockIdx.y) * GM, n0 = int64_t(blockIdx.x) * GN;
+
+  f32x16_t acc[2];
+#pragma unroll
+  for (int w = 0; w < 2; ++w)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[w][v] = 0.0f;
+  for (int k0 = 0; k0 < d; k0 += BK) {
+    const int kk = (t & 3) * 8;
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+      const int m = w * 64 + (t >> 2);
+      const int64_t row = (m0 + m < N_pad) ? m0 + m : N_pad - 1;
+      *reinterpret_cast<uint4*>(&As[m * LDS_STRIDE + kk]) = *reinterpret_cast<const uint4*>(E + row * d + k0 + kk);
     }
+    {
+      const int n = t >> 2;
+      *reinterpret_cast<uint4*>(&Bs[n * LDS_STRIDE + kk]) = *reinterpret_cast<const uint4*>(E + (n0 + n) * d + k0 + kk);
+    }
+    __syncthreads();
+    const int i = lane & 31, kh = lane >> 5;
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 16) {
+      const bf16x8_t b = *reinterpret_cast<const bf16x8_t*>(&Bs[(wn * 32 + i) * LDS_STRIDE + ks + kh * 8]);
+#pragma unroll
+      for (int w = 0; w < 2; ++w) {
+        const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(&As[(w * 64 + wm * 32 + i) * LDS_STRIDE + ks + kh * 8]);
+        acc[w] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[w], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+
+  // element v of an accumulator is row (v / 4) * 8 + (lane / 32) * 4 + v % 4, column lane % 32
+  const float alpha = ab[0], beta = ab[1];
+  const int64_t c = n0 + wn * 32 + (lane & 31);
+  float tmax[2] = {-INFINITY, -INFINITY};
+#pragma unroll
+  for (int w = 0; w < 2; ++w)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int64_t r = m0 + w * 64 + wm * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+      if (r < valid && c < valid) {
+        const float sg = sigmoidf(alpha * acc[w][v] + beta);
+        __builtin_nontemporal_store((r == c) ? 1.0 : double(sg), &K[r * ldk + c]);
+        if (r != c) tmax[w] = fmaxf(tmax[w], sg);
+      }
+    }
+#pragma unroll
+  for (int w = 0; w < 2; ++w) {
+    for (int off = 32; off > 0; off >>= 1) tmax[w] = fmaxf(tmax[w], __shfl_xor(tmax[w], off, 64));
+    if (lane == 0) red[w][wave] = tmax[w];
+  }
+  __syncthreads();
+  if (t < 2) {
+    const int64_t ti = 2 * int64_t(blockIdx.y) + t;
+    if (ti < T)
+      tile_max[ti * T + blockIdx.x] = fmaxf(fmaxf(red[t][0], red[t][1]), fmaxf(red[t][2], red[t][3]));
   }
 }
 
@@ -309,9 +374,16 @@ hipError_t launch_gemm(int ta, int tb, int epi, const GemmArgs& g, hipStream_t s
     case 1 * 100 + 0 * 10 + EPI_F32: return launch_gemm_t<1, 0, EPI_F32>(g, s);
     case 0 * 100 + 1 * 10 + EPI_GELU_BWD: return launch_gemm_t<0, 1, EPI_GELU_BWD>(g, s);
     case 0 * 100 + 1 * 10 + EPI_F32: return launch_gemm_t<0, 1, EPI_F32>(g, s);
-    case 0 * 100 + 1 * 10 + EPI_SIGMOID_GRAM: return launch_gemm_t<0, 1, EPI_SIGMOID_GRAM>(g, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_sigmoid_gram(const uint16_t* E, int64_t N_pad, int32_t d, const float* ab, double* K, int64_t ldk,
+                               int64_t valid, float* tile_max, hipStream_t s) {
+  const int64_t T = N_pad / 64;
+  const dim3 grid(unsigned(T), unsigned((T + 1) / 2));
+  hipLaunchKernelGGL(sigmoid_gram_kernel, grid, dim3(256), 0, s, E, N_pad, d, ab, K, ldk, valid, tile_max);
+  return hipGetLastError();
 }
 
 hipError_t launch_gather(const double* X, int64_t N, int32_t n, const int32_t* idx, int64_t rows, int32_t d_pad,

@@ -232,12 +232,12 @@ qsvm_status qsvm_surrogate_gram(const void* E16, int64_t N, int64_t N_pad, int32
   if (N < 1 || N_pad < N || N_pad % 64 || N_pad - N >= 64 || d < 32 || d % 32 || ldk < N)
     return api_fail(QSVM_ERR_INVALID_ARG,
                     "qsvm_surrogate_gram: need 1 <= N <= N_pad < N + 64, N_pad % 64 == 0, d % 32 == 0, ldk >= N");
+  if (N_pad / 64 > 65535)  // launch grid: N_pad / 64 blocks across, half that down
+    return api_fail(QSVM_ERR_UNSUPPORTED, "qsvm_surrogate_gram: N_pad above 64 * 65535");
   if (qsvm::api_injected_failure()) return injected(what);
-  qsvm::GemmArgs g = gemm(N_pad, N_pad, d, E16, d, E16, d, K, nullptr, ldk);
-  g.ab = alpha_beta;
-  g.tile_max = tile_max;
-  g.valid = N;
-  return api_hip(qsvm::launch_gemm(0, 1, qsvm::EPI_SIGMOID_GRAM, g, static_cast<hipStream_t>(stream)), what);
+  return api_hip(qsvm::launch_sigmoid_gram(static_cast<const uint16_t*>(E16), N_pad, d, alpha_beta, K, ldk, N, tile_max,
+                                           static_cast<hipStream_t>(stream)),
+                 what);
 }
 
 qsvm_status qsvm_flag_tiles(const float* tile_max, int32_t T, float tau, int32_t* tile_list, int32_t* count,

@@ -180,12 +180,14 @@ def test_adamw_matches_reference():
     assert np.array_equal(_host(w16), ref.bf16_round(w.cpu().numpy()))
 
 
-def test_surrogate_gram_tile_max_and_flags():
+# Ragged N with an odd tile count (the last 128-row block half empty), an
+# exact tile multiple, and several embedding widths.
+@pytest.mark.parametrize("N,d", [(150, 64), (200, 128), (130, 256), (64, 256), (150, 96), (300, 32)])
+def test_surrogate_gram_tile_max_and_flags(N, d):
     import torch
 
-    rng = np.random.default_rng(4)
-    N, d = 150, 64
-    Np = 192
+    rng = np.random.default_rng(4 + d)
+    Np = (N + 63) // 64 * 64
     E = ref.bf16_round(rng.normal(0, 0.3, (Np, d)))
     E16 = _bf16_dev(E)
     ab = _f32_dev([0.5, -3.0])
@@ -197,6 +199,7 @@ def test_surrogate_gram_tile_max_and_flags():
     Kh = K.cpu().numpy()
     Kr = ref.surrogate_gram(E[:N], 0.5, -3.0)
     assert np.max(np.abs(Kh - Kr)) < 1e-6
+    assert np.array_equal(Kh, Kh.T)
     tm = tmax.cpu().numpy().reshape(T, T)
     for ti in range(T):
         for tj in range(T):
