@@ -308,10 +308,12 @@ qsvm_status qsvm_sv_gram(const void* sv_a, int64_t Na, const void* sv_b, int64_t
 
 /* Symmetric Gram from states: pairs i < j contracted and mirrored, the diagonal
  * by diag_mode as in qsvm_gram_sym.
- * Both Gram calls split the 2^n inner dimension across blocks when there are
- * fewer than about 1024 output tiles; the partial products (tiles x splits x
- * 64 KB) live in a stream-ordered temporary (hipMallocAsync / hipFreeAsync on
- * `stream`) and are added in a fixed order, so results are reproducible. */
+ * Both Gram calls split the 2^n inner dimension across blocks when that fills
+ * the device's resident blocks better (the split count depends on the tile
+ * count, n and the device's compute units; at most 4096 partial tiles); the
+ * partial products (tiles x splits x 64 KB, at most 256 MB) live in a
+ * stream-ordered temporary (hipMallocAsync / hipFreeAsync on `stream`) and
+ * are added in a fixed order, so results are reproducible on one device. */
 qsvm_status qsvm_sv_gram_sym(const void* sv, int64_t N, int32_t n_qubits, double* K, int64_t ldk,
                              const qsvm_gram_opts* opts, void* stream);
 
