@@ -23,6 +23,8 @@
 // the conjugate on the bra side), and |G|^2 written by the same finalize
 // (mirror, diagonal rule, optional log K) as the MPS sweeps.
 
+#include <atomic>
+
 #include "../../include/qsvm.h"
 #include "sweep_common.h"
 
@@ -361,20 +363,23 @@ namespace {
 // Blocks of sv_gram_kernel resident on the current device at once (compute
 // units x blocks per unit), cached per device.
 hipError_t resident_gram_blocks(int64_t* out) {
-  static int64_t cache[64] = {};
+  static std::atomic<int64_t> cache[64];  // zero-initialised (static storage)
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
-  if (dev >= 0 && dev < 64 && cache[dev] > 0) {
-    *out = cache[dev];
-    return hipSuccess;
+  if (dev >= 0 && dev < 64) {
+    const int64_t c = cache[dev].load(std::memory_order_relaxed);
+    if (c > 0) {
+      *out = c;
+      return hipSuccess;
+    }
   }
   int cus = 0, per_cu = 0;
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sv_gram_kernel, 256, 0);
   if (e != hipSuccess) return e;
   const int64_t r = int64_t(cus > 0 ? cus : 1) * (per_cu > 0 ? per_cu : 1);
-  if (dev >= 0 && dev < 64) cache[dev] = r;  // the same value from any thread
+  if (dev >= 0 && dev < 64) cache[dev].store(r, std::memory_order_relaxed);  // the same value from any thread
   *out = r;
   return hipSuccess;
 }
