@@ -8,8 +8,10 @@ features already resident in HBM.  value = contracted pairs per second.
 Prints one JSON line with the timing, a roofline entry for the dominant
 kernel (the overlap sweep; launch durations from HIP events on the launch
 stream) and, on rank 0, a CPU baseline: the FP64 oracle timed on the host
-cores on a bounded sample of the same workload.  Three more legs add their own
-objects to the line:
+cores on a bounded sample of the same workload.  The exact leg also times the
+workload's second Gram, 1024 test images x the 4096 training images
+(`test_by_train`: encode of the test MPS + rectangular Gram per step).  Three
+more legs add their own objects to the line:
   surrogate -- 32768 synthetic 784-pixel images, reps = 2: the MLP surrogate
                trained on 2 % of the exact entries (the complete Gram of a
                random 4634-point subset), judged on 1 % held out (the Gram of
@@ -156,6 +158,55 @@ def _events(n):
     import torch
 
     return [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+
+
+def test_by_train_leg(reps, n_train, train_buf, Xtrain, sweep, args):
+    """Rectangular Gram of 1024 test images against the training images (the
+    second Gram of the 784-pixel workload); encode + Gram timed per step."""
+    import numpy as np
+    import torch
+    from paper_2405_02630_amd import qsvm, synth
+
+    dev = torch.device("cuda:0")
+    n_test = 1024
+    wl = synth.images784(seed=0, n_train=n_train, n_test=n_test, reps=reps)
+    Xt = torch.as_tensor(wl.X_test, dtype=torch.float64, device=dev)
+    mb = qsvm.qsvm_encode_mps(Xtrain, reps, out=train_buf)
+    K = torch.empty((n_test, n_train), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        ma = qsvm.qsvm_encode_mps(Xt, reps)
+        if ev is not None:
+            ev[0].record(stream)
+        qsvm.qsvm_gram(ma, mb, K, sweep=sweep, renorm_every=args.renorm_every)
+        if ev is not None:
+            ev[1].record(stream)
+
+    for _ in range(max(1, args.warmup)):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step(evs[s])
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    sweep_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    pairs = n_test * n_train
+    flops = sweep_flops_per_pair(Xt.shape[1], reps, args.sweep) * pairs
+    log(f"test x train {n_test} x {n_train}: {ms:.3f} ms/step, sweep {sweep_ms:.3f} ms, "
+        f"{pairs / (ms / 1e3):.4e} entries/s")
+    return {
+        "workload": f"images-n{Xt.shape[1]}-r{reps}-test{n_test}-train{n_train}-rect",
+        "pairs_per_step": pairs,
+        "ms_per_step": ms,
+        "value": pairs / (ms / 1e3),
+        "unit": "entries/s",
+        "sweep_ms": round(sweep_ms, 4),
+        "sweep_frac_of_fp32_peak": round(flops / (sweep_ms / 1e3) / 1e12 / PEAK_FP32_VECTOR_TFLOPS, 4),
+        "step": "encode test MPS + rectangular Gram against the resident training MPS",
+    }
 
 
 def surrogate_leg(args, exact_rate):
@@ -418,7 +469,7 @@ def main():
     ap.add_argument("--renorm-every", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=720)
-    ap.add_argument("--legs", default="exact,surrogate,batched,sv")
+    ap.add_argument("--legs", default="exact,surrogate,batched,sv")  # "exact" adds the test x train Gram
     ap.add_argument("--sur-points", type=int, default=32768)
     ap.add_argument("--sur-steps", type=int, default=300)
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -529,6 +580,8 @@ def main():
     }
 
     legs = set(args.legs.split(","))
+    if "exact" in legs:
+        out["test_by_train"] = test_by_train_leg(reps, N, mps_buf, X, sweep, args)
     if "surrogate" in legs:
         del K  # release the exact leg's buffers first
         torch.cuda.empty_cache()
