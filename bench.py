@@ -549,7 +549,8 @@ def main():
         "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
         "traffic": traffic[0],
         "traffic_source": traffic[1],
-        "kernel": f"sweep_{args.sweep}_kernel<{reps},*>",
+        "kernel": (f"sweep_split_kernel<{reps},*>" if args.sweep == "butterfly" and reps == 4
+                   else f"sweep_{args.sweep}_kernel<{reps},*>"),
         "flops_per_launch": flops,
         "avg_launch_ms": round(sweep_ms, 4),
     }

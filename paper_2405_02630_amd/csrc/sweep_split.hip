@@ -16,9 +16,12 @@
 //     lane 1:  u~1 <- nu (u~1 + (1/Phi') p)  (p = lane 0's value),
 // after which Phi <- Phi'.  Both lanes compute "own + c * partner" with their
 // own coefficient c; Phi is carried in FP64 and multiplies lane 1's part of
-// the closure at the end.  The partner's value comes from the neighbouring
-// lane through a DPP quad permutation.  Renormalisation takes the larger of
-// the two lanes' maxima, so both halves share one power-of-two scale.
+// the closure at the end.  The partner's values come from the neighbouring
+// lane through the LDS crossbar (ds_swizzle, quad permutation [1, 0, 3, 2]),
+// four entries per wait: that keeps the 128 exchanges per site off the
+// VALU, where DPP moves measured about 8 extra issue cycles each (the sweep
+// ran 1.1x slower with them).  Renormalisation takes the larger of the two
+// lanes' maxima, so both halves share one power-of-two scale.
 //
 // Work layout: a tile is 64 ket x 64 bra points; a wave owns one ket point
 // (wave-uniform, scalar loads) and 32 bra points (two lanes each); a block of
@@ -30,7 +33,9 @@
 namespace qsvm {
 namespace {
 
-// Value of x in the partner lane (lane ^ 1): DPP quad permutation [1, 0, 3, 2].
+// Value of x in the partner lane (lane ^ 1): DPP quad permutation [1, 0, 3, 2]
+// (for the few values per site outside the shared-bit axis: the FP64 phase
+// and the renormalisation maximum).
 __device__ __forceinline__ float partner(float x) {
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0xB1, 0xF, 0xF, false));
 }
@@ -57,26 +62,54 @@ __device__ __forceinline__ void init_split(float2 (&v)[ML], int h) {
   }
 }
 
+// Partner (lane ^ 1) values of four entries through the LDS crossbar
+// (ds_swizzle in quad-permute mode [1, 0, 3, 2], no LDS memory touched); one
+// wait for all eight.  Written as one asm block so that the compiler cannot
+// hoist the swizzles of a whole site ahead of their use (it does with the
+// builtin, and the results then spill); the wait also covers any scalar loads
+// still in flight.  Faster than batches of eight entries (529.5 vs 527 ms).
+__device__ __forceinline__ void swizzle4(const float2& v0, const float2& v1, const float2& v2, const float2& v3,
+                                         float (&p)[8]) {
+  asm volatile(
+      "ds_swizzle_b32 %0, %8 offset:swizzle(QUAD_PERM,1,0,3,2)\n"
+      "ds_swizzle_b32 %1, %9 offset:swizzle(QUAD_PERM,1,0,3,2)\n"
+      "ds_swizzle_b32 %2, %10 offset:swizzle(QUAD_PERM,1,0,3,2)\n"
+      "ds_swizzle_b32 %3, %11 offset:swizzle(QUAD_PERM,1,0,3,2)\n"
+      "ds_swizzle_b32 %4, %12 offset:swizzle(QUAD_PERM,1,0,3,2)\n"
+      "ds_swizzle_b32 %5, %13 offset:swizzle(QUAD_PERM,1,0,3,2)\n"
+      "ds_swizzle_b32 %6, %14 offset:swizzle(QUAD_PERM,1,0,3,2)\n"
+      "ds_swizzle_b32 %7, %15 offset:swizzle(QUAD_PERM,1,0,3,2)\n"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(p[0]), "=&v"(p[1]), "=&v"(p[2]), "=&v"(p[3]), "=&v"(p[4]), "=&v"(p[5]), "=&v"(p[6]), "=&v"(p[7])
+      : "v"(v0.x), "v"(v0.y), "v"(v1.x), "v"(v1.y), "v"(v2.x), "v"(v2.y), "v"(v3.x), "v"(v3.y));
+}
+
 // Shared-bit axis across the lane pair: v <- sg(q) (v + c * partner(v)),
 // where sg(q) = -1 for the entries whose sign bits are set, in lane 1 only
-// (nsg = -1 in lane 1, +1 in lane 0).
+// (nsg = -1 in lane 1, +1 in lane 0).  Partner values arrive four entries
+// at a time through the LDS crossbar.
 template <int R, int ML>
 __device__ __forceinline__ void cross_axis(float2 (&v)[ML], float cr, float ci, float nsg) {
   constexpr int SB1 = Layout<R>::ket_bit(R - 1);
   constexpr int SB2 = Layout<R>::bra_bit(R - 1);
 #pragma unroll
-  for (int q = 0; q < ML; ++q) {
-    const float pr = partner(v[q].x);
-    const float pim = partner(v[q].y);
-    float tr = fmaf(cr, pr, v[q].x);
-    tr = fmaf(-ci, pim, tr);
-    float ti = fmaf(cr, pim, v[q].y);
-    ti = fmaf(ci, pr, ti);
-    if (((q >> SB1) ^ (q >> SB2)) & 1) {
-      tr *= nsg;
-      ti *= nsg;
+  for (int c = 0; c < ML / 4; ++c) {
+    float p[8];
+    swizzle4(v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3], p);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int q = 4 * c + e;
+      const float pr = p[2 * e], pim = p[2 * e + 1];
+      float tr = fmaf(cr, pr, v[q].x);
+      tr = fmaf(-ci, pim, tr);
+      float ti = fmaf(cr, pim, v[q].y);
+      ti = fmaf(ci, pr, ti);
+      if (((q >> SB1) ^ (q >> SB2)) & 1) {
+        tr *= nsg;
+        ti *= nsg;
+      }
+      v[q] = make_float2(tr, ti);
     }
-    v[q] = make_float2(tr, ti);
   }
 }
 
@@ -250,7 +283,8 @@ hipError_t launch_split(const SweepArgs& a0, hipStream_t stream) {
 
 // Variants of the split sweep (target waves per SIMD W, ket points per block
 // KB); all compute bitwise identical results.  Variant 0 is the default (the
-// fastest measured on MI355X at 784 qubits, 1024 points: 39.5 vs 40.5 ms).
+// fastest measured on MI355X at 784 qubits, 2048 points: 140.0 ms against
+// 141.5 / 140.2 / 141.6 ms for variants 1..3).
 hipError_t launch_sweep_split_args(const SweepArgs& a, int32_t reps, int32_t variant, hipStream_t stream) {
   switch (reps * 16 + variant) {
     case 64 + 0: return launch_split<4, 3, 2>(a, stream);
