@@ -377,6 +377,8 @@ def batched_leg():
     serial_s = ev_all[0].elapsed_time(ev_all[1]) / 1e3
     job_rates = [p / (e[0].elapsed_time(e[1]) / 1e3) for p, e in zip(pairs, per_job)]
     plan.close()
+    # executed sweep flops of all jobs (the same per-pair count as the roofline entry)
+    flops = sum(p * sweep_flops_per_pair(m.n, m.reps, "butterfly") for p, (m, _, _) in zip(pairs, jobs))
     res = {
         "workload": "64 jobs, n in {16,64,196,400,784}, N in [64,2048], reps in {2,3}, uniform features",
         "jobs": len(jobs),
@@ -389,11 +391,14 @@ def batched_leg():
         "one_launch_per_job_value": sum(pairs) / serial_s,
         "one_launch_per_job_seconds": serial_s,
         "speedup": serial_s / batched_s,
+        "sweep_flops": flops,
+        "frac_of_fp32_peak": flops / batched_s / 1e12 / PEAK_FP32_VECTOR_TFLOPS,
+        "one_launch_per_job_frac_of_fp32_peak": flops / serial_s / 1e12 / PEAK_FP32_VECTOR_TFLOPS,
         "per_job_entries_per_s": {"min": float(np.min(job_rates)), "median": float(np.median(job_rates)),
                                   "max": float(np.max(job_rates))},
     }
-    log(f"batched: {res['value']:.3e} entries/s ({batched_s*1e3:.1f} ms) vs one launch per job "
-        f"{res['one_launch_per_job_value']:.3e} ({serial_s*1e3:.1f} ms)")
+    log(f"batched: {res['value']:.3e} entries/s ({batched_s*1e3:.1f} ms, {res['frac_of_fp32_peak']:.3f} of peak) "
+        f"vs one launch per job {res['one_launch_per_job_value']:.3e} ({serial_s*1e3:.1f} ms)")
     return res
 
 
