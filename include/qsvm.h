@@ -99,11 +99,21 @@ typedef struct {
                            same shape and ldk as K (-inf for an exact zero).
                            K itself underflows to 0 below ~1e-308; log_k does
                            not.  NULL = not written. */
+  double refine_above;  /* FP64 refinement (reps <= 3): after the FP32 sweep,
+                           every 64 x 64 tile whose largest computed entry
+                           exceeds this value is recomputed with an FP64
+                           environment from FP64 generators (Sections G + L),
+                           so entries near 1 meet a 1e-5 bar at any n.
+                           0 = default (1e-3); negative = off.  Costs one read
+                           of the written K plus the FP64 sweep of the listed
+                           tiles; a 4-byte-per-tile list lives in a
+                           stream-ordered temporary.  reps = 4 and the
+                           state-vector Grams ignore it. */
 } qsvm_gram_opts;
 
 /*
  * Bytes of the MPS buffer that qsvm_encode_mps writes for N points of
- * n_qubits features: n*N*chi*chi*8 + n*N*16 with chi = 2^reps.  Returns 0 for
+ * n_qubits features: n*N*chi*chi*8 + n*N*32 with chi = 2^reps.  Returns 0 for
  * arguments outside the supported range.
  *
  * MPS buffer layout (site-major so that a sweep over site k reads the tensors
@@ -132,6 +142,11 @@ typedef struct {
  *    of Section D becomes 2^(-reps/2) * sgn(beta) * prod_l C_k[beta_l][alpha_l]
  *    with C_k = [[1, a_k], [1, b_k]] (row = new bit, column = old bit), the
  *    left boundary becomes sgn, and the right boundary becomes g_{n-1}^|beta|.
+ *
+ *  Section L, offset n*N*chi*chi*8 + n*N*16: the FP32 residuals of Section G,
+ *    same layout: each component is (float)(value - (double)G component), so
+ *    G + L is the FP64 generator to ~2^-48 relative.  Read only by the FP64
+ *    refinement (qsvm_gram_opts.refine_above).
  */
 size_t qsvm_mps_bytes(int64_t N, int32_t n_qubits, int32_t reps);
 
@@ -213,6 +228,10 @@ typedef struct {
                            into a hipGraph at plan creation and replay it */
   int32_t grid_blocks;  /* persistent blocks, at most 2^24 - 8; 0 = compute units x resident blocks
                            per unit */
+  double refine_above;  /* as in qsvm_gram_opts: after the persistent sweep, each
+                           job's tiles with an entry above it are recomputed in
+                           FP64 (0 = default 1e-3, negative = off); the plan
+                           holds the list buffer */
 } qsvm_batch_opts;
 
 typedef struct qsvm_batch_plan qsvm_batch_plan; /* opaque */

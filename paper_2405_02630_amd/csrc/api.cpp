@@ -7,10 +7,12 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <atomic>
 #include <string>
 
 #include "../../include/qsvm.h"
 #include "qsvm_internal.h"
+#include "refine.h"
 #include "sweep_common.h"
 
 namespace {
@@ -66,6 +68,7 @@ struct Opts {
   int32_t variant = 0;
   int64_t row_begin = 0, row_end = 0;
   double* log_k = nullptr;
+  double refine_above = qsvm::kDefaultRefineAbove;  // negative: no refinement
 };
 
 qsvm_status read_opts(const qsvm_gram_opts* o, int64_t rows, Opts& out, const char* what) {
@@ -92,7 +95,50 @@ qsvm_status read_opts(const qsvm_gram_opts* o, int64_t rows, Opts& out, const ch
     out.row_end = o->row_end;
   }
   out.log_k = o->log_k;
+  if (!(o->refine_above == o->refine_above))  // NaN
+    return fail(QSVM_ERR_INVALID_ARG, "%s: refine_above is NaN", what);
+  if (o->refine_above != 0.0) out.refine_above = o->refine_above;
   return QSVM_OK;
+}
+
+// Blocks of the refinement kernel resident on the current device, cached per
+// device and reps.
+hipError_t resident_refine_blocks(int32_t reps, int64_t* out) {
+  static std::atomic<int64_t> cache[64][4];  // zero-initialised (static storage)
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  const bool cacheable = dev >= 0 && dev < 64 && reps >= 1 && reps <= 3;
+  if (cacheable) {
+    const int64_t c = cache[dev][reps].load(std::memory_order_relaxed);
+    if (c > 0) {
+      *out = c;
+      return hipSuccess;
+    }
+  }
+  e = qsvm::refine_resident_blocks(reps, out);
+  if (e == hipSuccess && cacheable) cache[dev][reps].store(*out, std::memory_order_relaxed);
+  return e;
+}
+
+// FP64 refinement of the tiles of `a` (the tiles one Gram call swept) whose
+// largest entry exceeds the threshold, chunk by chunk like the sweeps.
+hipError_t refine_tiles(const qsvm::SweepArgs& a, int32_t reps, double thresh, hipStream_t stream) {
+  if (thresh < 0.0 || reps > 3) return hipSuccess;
+  const int64_t tiles = qsvm::launch_tiles(a);
+  if (tiles <= 0) return hipSuccess;
+  int64_t resident = 0;
+  hipError_t e = resident_refine_blocks(reps, &resident);
+  if (e != hipSuccess) return e;
+  const int64_t cap = tiles < qsvm::kMaxGridBlocks ? tiles : qsvm::kMaxGridBlocks;
+  uint32_t* ws = nullptr;  // [count, list...]
+  e = hipMallocAsync(reinterpret_cast<void**>(&ws), size_t(cap + 1) * sizeof(uint32_t), stream);
+  if (e != hipSuccess) return e;
+  e = qsvm::launch_chunked(a, 1, [&](const qsvm::SweepArgs& c) {
+    return qsvm::launch_refine(c, reps, thresh, ws + 1, ws, resident, stream);
+  });
+  const hipError_t f = hipFreeAsync(ws, stream);
+  return e != hipSuccess ? e : f;
 }
 
 // Variant for a launch: forced by opts, else the tuned table (default 0).
@@ -136,6 +182,7 @@ qsvm_status run_gram(const void* mps_a, int64_t Na, const void* mps_b, int64_t N
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = (o.sweep == QSVM_SWEEP_DENSE) ? qsvm::launch_sweep_dense_args(a, reps, s)
                                                 : qsvm::launch_sweep_fast(a, reps, pick_variant(o, reps, n), s);
+  if (e == hipSuccess) e = refine_tiles(a, reps, o.refine_above, s);
   return hip_status(e, what);
 }
 
@@ -153,8 +200,7 @@ extern "C" {
 
 size_t qsvm_mps_bytes(int64_t N, int32_t n_qubits, int32_t reps) {
   if (N < 1 || N > kMaxN || n_qubits < 1 || n_qubits > kMaxQubits || reps < 1 || reps > qsvm::kMaxReps) return 0;
-  const int64_t chi = int64_t(1) << reps;
-  return size_t(int64_t(n_qubits) * N * (chi * chi * 8 + 16));
+  return size_t(qsvm::mps_total_bytes(N, n_qubits, reps));
 }
 
 qsvm_status qsvm_encode_mps(const double* X, int64_t N, int32_t n_qubits, int32_t reps, void* mps,
@@ -246,6 +292,7 @@ qsvm_status qsvm_gram_sym_tiles(const void* mps, int64_t N, int32_t n_qubits, in
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipError_t e = (o.sweep == QSVM_SWEEP_DENSE) ? qsvm::launch_sweep_dense_args(a, reps, st)
                                                 : qsvm::launch_sweep_fast(a, reps, pick_variant(o, reps, n_qubits), st);
+  if (e == hipSuccess) e = refine_tiles(a, reps, o.refine_above, st);
   return hip_status(e, what);
 }
 

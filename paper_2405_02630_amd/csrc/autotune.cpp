@@ -63,8 +63,7 @@ void set_tuned_variant(int32_t reps, int32_t n, int32_t variant) {
 
 hipError_t autotune_run(int32_t reps, int32_t n, int64_t N, hipStream_t stream, int32_t* best,
                         float* ms_out) {
-  const int64_t chi = int64_t(1) << reps;
-  const int64_t mps_bytes = int64_t(n) * N * (chi * chi * 8 + 16);
+  const int64_t mps_bytes = mps_total_bytes(N, n, reps);
   double* X = nullptr;
   void* mps = nullptr;
   double* K = nullptr;

@@ -11,6 +11,7 @@
 #include "../../include/qsvm.h"
 #include "batched.h"
 #include "qsvm_internal.h"
+#include "refine.h"
 
 struct qsvm_batch_plan {
   int device = -1;
@@ -25,6 +26,11 @@ struct qsvm_batch_plan {
   hipGraphExec_t exec = nullptr;
   hipEvent_t last_launch = nullptr;
   bool launched = false;
+  // FP64 refinement after the persistent sweep, job by job
+  std::vector<qsvm::BatchJob> host_jobs;
+  double refine_above = 0.0;          // negative: off
+  uint32_t* d_refine = nullptr;       // [count, list of the largest job's tiles]
+  int64_t refine_resident[4] = {0, 0, 0, 0};
 };
 
 namespace qsvm {
@@ -38,7 +44,23 @@ void destroy_plan(qsvm_batch_plan* p) {
   if (p->last_launch) (void)hipEventDestroy(p->last_launch);
   if (p->d_jobs) (void)hipFree(p->d_jobs);
   if (p->d_counter) (void)hipFree(p->d_counter);
+  if (p->d_refine) (void)hipFree(p->d_refine);
   delete p;
+}
+
+// The persistent sweep of every job, then each job's FP64 refinement of its
+// tiles with an entry above the threshold (no allocation, no memset: the
+// sequence can be captured in a graph).
+hipError_t plan_enqueue(qsvm_batch_plan* p, hipStream_t s) {
+  hipError_t e = launch_batch(p->d_jobs, p->n_jobs, p->total_items, p->d_counter, p->grid, s);
+  if (e != hipSuccess || p->refine_above < 0.0) return e;
+  for (const BatchJob& j : p->host_jobs) {
+    e = launch_chunked(j.args, 1, [&](const SweepArgs& c) {
+      return launch_refine(c, j.reps, p->refine_above, p->d_refine + 1, p->d_refine, p->refine_resident[j.reps], s);
+    });
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // Build the host job table; returns false with a message on invalid input.
@@ -137,6 +159,8 @@ extern "C" qsvm_status qsvm_batch_plan_create(const qsvm_job* jobs, int32_t n_jo
     return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_batch_plan_create: use_graph must be 0 or 1");
   if (o.grid_blocks < 0 || o.grid_blocks > (1 << 24) - 8)
     return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_batch_plan_create: grid_blocks outside [0, 2^24 - 8]");
+  if (!(o.refine_above == o.refine_above))
+    return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_batch_plan_create: refine_above is NaN");
   for (int32_t q = 0; q < n_jobs; ++q) {
     if (jobs[q].reps > 3) {
       snprintf(msg, sizeof msg,
@@ -167,7 +191,15 @@ extern "C" qsvm_status qsvm_batch_plan_create(const qsvm_job* jobs, int32_t n_jo
   }
   p->n_jobs = n_jobs;
   p->total_items = total;
-  e = hipMalloc(&p->d_jobs, sizeof(BatchJob) * table.size());
+  p->host_jobs = table;
+  p->refine_above = o.refine_above == 0.0 ? kDefaultRefineAbove : o.refine_above;
+  int64_t max_tiles = 1;
+  for (const BatchJob& j : table) max_tiles = std::max(max_tiles, std::min(launch_tiles(j.args), kMaxGridBlocks));
+  if (p->refine_above >= 0.0) {
+    for (int r = 1; r <= 3 && e == hipSuccess; ++r) e = refine_resident_blocks(r, &p->refine_resident[r]);
+    if (e == hipSuccess) e = hipMalloc(&p->d_refine, sizeof(uint32_t) * size_t(max_tiles + 1));
+  }
+  if (e == hipSuccess) e = hipMalloc(&p->d_jobs, sizeof(BatchJob) * table.size());
   if (e == hipSuccess) e = hipMalloc(&p->d_counter, sizeof(unsigned int));
   if (e == hipSuccess) e = hipMemcpy(p->d_jobs, table.data(), sizeof(BatchJob) * table.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&p->last_launch, hipEventDisableTiming);
@@ -176,7 +208,7 @@ extern "C" qsvm_status qsvm_batch_plan_create(const qsvm_job* jobs, int32_t n_jo
     e = hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-      hipError_t le = launch_batch(p->d_jobs, p->n_jobs, p->total_items, p->d_counter, p->grid, p->capture_stream);
+      hipError_t le = plan_enqueue(p, p->capture_stream);
       e = hipStreamEndCapture(p->capture_stream, &p->graph);
       if (le != hipSuccess) e = le;
     }
@@ -195,8 +227,7 @@ extern "C" qsvm_status qsvm_batch_plan_launch(qsvm_batch_plan* p, void* stream) 
   if (!p) return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_batch_plan_launch: plan is NULL");
   if (api_injected_failure()) return api_fail(QSVM_ERR_HIP, "qsvm_batch_plan_launch: injected launch failure (QSVM_FAULT_INJECT=launch)");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e = p->use_graph ? hipGraphLaunch(p->exec, s)
-                              : launch_batch(p->d_jobs, p->n_jobs, p->total_items, p->d_counter, p->grid, s);
+  hipError_t e = p->use_graph ? hipGraphLaunch(p->exec, s) : plan_enqueue(p, s);
   if (e == hipSuccess) e = hipEventRecord(p->last_launch, s);
   if (e == hipSuccess) p->launched = true;
   return api_hip(e, "qsvm_batch_plan_launch");

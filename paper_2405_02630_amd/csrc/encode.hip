@@ -14,8 +14,10 @@
 // A_k[alpha][beta] = J_{k-1}(alpha, beta) w_k(beta).  Section D stores these
 // tensors; Section G stores the generators (a_k, b_k, g_{n-1}) of the same
 // MPS in the diagonal gauge D_k = diag(1, g_k) per bond bit, where
-// J_{k-1} w_k factorises into 2x2 blocks [[1, a_k], [1, b_k]] (layout and
-// formulas in include/qsvm.h).
+// J_{k-1} w_k factorises into 2x2 blocks [[1, a_k], [1, b_k]], and Section L
+// the FP32 residuals of those generators (FP32 value + residual = the FP64
+// value to ~2^-48), read only by the FP64 refinement (layout and formulas in
+// include/qsvm.h).
 //
 // One thread per (site k, point i).  All phases are formed in FP64 (the
 // largest angle is below 3 * (2 pi + 2 pi^2) ~ 78 rad) and each tensor entry
@@ -35,7 +37,7 @@ __device__ __forceinline__ double zz_theta(double a, double b) {
 template <int R>
 __global__ void __launch_bounds__(256)
 encode_kernel(const double* __restrict__ X, int64_t N, int32_t n,
-              float2* __restrict__ dense, float4* __restrict__ gen) {
+              float2* __restrict__ dense, float4* __restrict__ gen, float4* __restrict__ gen_lo) {
   constexpr int CHI = 1 << R;
   constexpr int E = CHI * CHI;             // entries per site tensor
   constexpr int CH = (E < 16) ? E : 16;    // entries staged per round
@@ -95,27 +97,27 @@ encode_kernel(const double* __restrict__ X, int64_t N, int32_t n,
   }
   if (!valid) return;
 
-  // ---- Section G: gauge generators ----
-  float4 rec;
+  // ---- Section G: gauge generators (FP32), Section L: their FP32 residuals ----
+  double g0, g1, g2, g3;
   if (k >= 1) {
     // G_{k-1} = 2 x_{k-1} + theta_{k-2};  a_k = e^{i(theta_{k-1} + G_{k-1})},
     // b_k = e^{i(G_{k-1} - theta_{k-1})}
     const double xm = x[k - 1];
     const double th_pp = (k >= 2) ? zz_theta(x[k - 2], xm) : 0.0;
     const double G = 2.0 * xm + th_pp;
-    double sa, ca, sb, cb;
-    sincos(G + th_prev, &sa, &ca);
-    sincos(G - th_prev, &sb, &cb);
-    rec = make_float4(float(ca), float(sa), float(cb), float(sb));
+    sincos(G + th_prev, &g1, &g0);
+    sincos(G - th_prev, &g3, &g2);
   } else {
     // closure phase g_{n-1} = e^{i(2 x_{n-1} + theta_{n-2})}
     const double xl = x[n - 1];
     const double th_l = (n >= 2) ? zz_theta(x[n - 2], xl) : 0.0;
-    double sg, cg;
-    sincos(2.0 * xl + th_l, &sg, &cg);
-    rec = make_float4(float(cg), float(sg), 0.0f, 0.0f);
+    sincos(2.0 * xl + th_l, &g1, &g0);
+    g2 = g3 = 0.0;
   }
-  gen[int64_t(k) * N + i] = rec;
+  const float4 hi = make_float4(float(g0), float(g1), float(g2), float(g3));
+  gen[int64_t(k) * N + i] = hi;
+  gen_lo[int64_t(k) * N + i] = make_float4(float(g0 - double(hi.x)), float(g1 - double(hi.y)), float(g2 - double(hi.z)),
+                                           float(g3 - double(hi.w)));
 }
 
 }  // namespace
@@ -126,11 +128,12 @@ hipError_t launch_encode(const double* X, int64_t N, int32_t n, int32_t reps, vo
   const dim3 grid(unsigned((N + 255) / 256), unsigned(n));
   float2* dense = static_cast<float2*>(mps);
   float4* gen = reinterpret_cast<float4*>(static_cast<char*>(mps) + dense_bytes(N, n, reps));
+  float4* gen_lo = gen + int64_t(n) * N;  // Section L follows Section G
   switch (reps) {
-    case 1: hipLaunchKernelGGL(encode_kernel<1>, grid, block, 0, stream, X, N, n, dense, gen); break;
-    case 2: hipLaunchKernelGGL(encode_kernel<2>, grid, block, 0, stream, X, N, n, dense, gen); break;
-    case 3: hipLaunchKernelGGL(encode_kernel<3>, grid, block, 0, stream, X, N, n, dense, gen); break;
-    case 4: hipLaunchKernelGGL(encode_kernel<4>, grid, block, 0, stream, X, N, n, dense, gen); break;
+    case 1: hipLaunchKernelGGL(encode_kernel<1>, grid, block, 0, stream, X, N, n, dense, gen, gen_lo); break;
+    case 2: hipLaunchKernelGGL(encode_kernel<2>, grid, block, 0, stream, X, N, n, dense, gen, gen_lo); break;
+    case 3: hipLaunchKernelGGL(encode_kernel<3>, grid, block, 0, stream, X, N, n, dense, gen, gen_lo); break;
+    case 4: hipLaunchKernelGGL(encode_kernel<4>, grid, block, 0, stream, X, N, n, dense, gen, gen_lo); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

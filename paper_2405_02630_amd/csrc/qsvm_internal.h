@@ -12,6 +12,11 @@ inline int64_t dense_bytes(int64_t N, int32_t n, int32_t reps) {
   const int64_t chi = int64_t(1) << reps;
   return int64_t(n) * N * chi * chi * 8;
 }
+// Bytes of the whole MPS buffer: Section D, then Section G (generators) and
+// Section L (their residuals), 16 B per site and point each.
+inline int64_t mps_total_bytes(int64_t N, int32_t n, int32_t reps) {
+  return dense_bytes(N, n, reps) + int64_t(n) * N * 32;
+}
 
 hipError_t launch_encode(const double* X, int64_t N, int32_t n, int32_t reps, void* mps,
                          hipStream_t stream);

@@ -1,0 +1,287 @@
+// FP64 refinement of the tiles whose largest entry is large.
+//
+// The sweep carries the environment in FP32.  Its rounding error in K is
+// relative and biased (an FP32 emulation of 784-qubit self-overlaps gives
+// K = 1 - 1.0e-5 ... 1.5e-5 from the arithmetic and < 3e-6 from the FP32
+// generators), so at 784 qubits an entry close to 1 can miss an absolute
+// bar of 1e-5 while every entry below 1e-3 is within 1e-8 of exact.  After a
+// sweep launch, refine_scan_kernel reads the K tiles the launch wrote and
+// lists those whose largest computed entry exceeds a threshold, and
+// refine_kernel recomputes every pair of the listed tiles with an FP64
+// environment from FP64 generators (Section G value + Section L residual),
+// overwriting K and log K.  The list length stays on the device: the
+// refinement kernel is launched with a fixed grid whose waves take (tile,
+// ket point) items until the list is exhausted (none when nothing was
+// listed), so no host synchronisation is needed and the three launches can
+// be captured in a graph.
+//
+// The FP64 sweep is the one-lane butterfly sweep of sweep_butterfly_item.h
+// (same recursion, gauge, sign pattern, renormalisation and closure) with
+// doubles: one pair per lane, one ket point per wave, reps <= 3.
+
+#include "../../include/qsvm.h"
+#include "refine.h"
+#include "sweep_common.h"
+
+namespace qsvm {
+namespace {
+
+template <int R>
+struct DLayout {
+  static constexpr int NB = 2 * R - 1;
+  static constexpr int M = 1 << NB;
+  static constexpr int S = NB - 1;
+  __host__ __device__ static constexpr int ket_bit(int l) { return l - 1; }
+  __host__ __device__ static constexpr int bra_bit(int l) { return R - 1 + l - 1; }
+};
+
+struct Gen64 {
+  double ar, ai, br, bi;
+};
+
+__device__ __forceinline__ Gen64 gen64(const float4* __restrict__ hi, const float4* __restrict__ lo, int64_t idx) {
+  const float4 h = hi[idx], l = lo[idx];
+  return {double(h.x) + double(l.x), double(h.y) + double(l.y), double(h.z) + double(l.z), double(h.w) + double(l.w)};
+}
+
+// (u0, u1) -> (u0 + (ar + i ai) u1, +-(u0 + (br + i bi) u1))
+template <bool NEG>
+__device__ __forceinline__ void dbfly(double2& u0, double2& u1, double ar, double ai, double br, double bi) {
+  const double x0 = u0.x, y0 = u0.y, x1 = u1.x, y1 = u1.y;
+  double t0r = fma(ar, x1, x0);
+  t0r = fma(-ai, y1, t0r);
+  double t0i = fma(ar, y1, y0);
+  t0i = fma(ai, x1, t0i);
+  double t1r = fma(br, x1, x0);
+  t1r = fma(-bi, y1, t1r);
+  double t1i = fma(br, y1, y0);
+  t1i = fma(bi, x1, t1i);
+  u0 = make_double2(t0r, t0i);
+  u1 = NEG ? make_double2(-t1r, -t1i) : make_double2(t1r, t1i);
+}
+
+template <int AXBIT, int SIGNBIT, int SIGNBIT2, int M>
+__device__ __forceinline__ void daxis(double2 (&v)[M], double ar, double ai, double br, double bi) {
+#pragma unroll
+  for (int i0 = 0; i0 < M; ++i0) {
+    if (i0 & (1 << AXBIT)) continue;
+    const int i1 = i0 | (1 << AXBIT);
+    bool neg = false;
+    if constexpr (SIGNBIT >= 0) neg ^= ((i0 >> SIGNBIT) & 1) != 0;
+    if constexpr (SIGNBIT2 >= 0) neg ^= ((i0 >> SIGNBIT2) & 1) != 0;
+    if (neg)
+      dbfly<true>(v[i0], v[i1], ar, ai, br, bi);
+    else
+      dbfly<false>(v[i0], v[i1], ar, ai, br, bi);
+  }
+}
+
+template <int R, int L>
+struct DAxes {
+  template <int M>
+  __device__ __forceinline__ static void ket(double2 (&v)[M], const Gen64& c) {
+    if constexpr (L <= R - 1) {
+      daxis<DLayout<R>::ket_bit(L), (L >= 2 ? DLayout<R>::ket_bit(L - 1) : -1), -1>(v, c.ar, c.ai, c.br, c.bi);
+      DAxes<R, L + 1>::ket(v, c);
+    }
+  }
+  template <int M>
+  __device__ __forceinline__ static void bra(double2 (&v)[M], const Gen64& c) {
+    if constexpr (L <= R - 1) {
+      daxis<DLayout<R>::bra_bit(L), (L >= 2 ? DLayout<R>::bra_bit(L - 1) : -1), -1>(v, c.ar, -c.ai, c.br, -c.bi);
+      DAxes<R, L + 1>::bra(v, c);
+    }
+  }
+};
+
+template <int R>
+__device__ __forceinline__ void dsite_step(double2 (&v)[DLayout<R>::M], const Gen64& cx, const Gen64& cy) {
+  DAxes<R, 1>::ket(v, cx);
+  DAxes<R, 1>::bra(v, cy);
+  // shared top bit: a_x conj(a_y), b_x conj(b_y)
+  const double asr = fma(cx.ar, cy.ar, cx.ai * cy.ai);
+  const double asi = fma(cx.ai, cy.ar, -(cx.ar * cy.ai));
+  const double bsr = fma(cx.br, cy.br, cx.bi * cy.bi);
+  const double bsi = fma(cx.bi, cy.br, -(cx.br * cy.bi));
+  constexpr int SB1 = (R >= 2) ? DLayout<R>::ket_bit(R - 1) : -1;
+  constexpr int SB2 = (R >= 2) ? DLayout<R>::bra_bit(R - 1) : -1;
+  daxis<DLayout<R>::S, SB1, SB2>(v, asr, asi, bsr, bsi);
+}
+
+// Divide by the power of two of the largest |component| (exact); returns it.
+template <int M>
+__device__ __forceinline__ int drenorm(double2 (&v)[M]) {
+  double m = 0.0;
+#pragma unroll
+  for (int q = 0; q < M; ++q) m = fmax(m, fmax(fabs(v[q].x), fabs(v[q].y)));
+  int e = 0;
+  (void)frexp(m, &e);
+#pragma unroll
+  for (int q = 0; q < M; ++q) v[q] = make_double2(ldexp(v[q].x, -e), ldexp(v[q].y, -e));
+  return e;
+}
+
+template <int R>
+__device__ __forceinline__ constexpr int dcol_sign_parity(int low, int s) {
+  const int c = low | (s << (R - 1));
+  return __builtin_popcount(c & (c >> 1)) & 1;
+}
+
+template <int R>
+__device__ __forceinline__ void dinit_env(double2 (&v)[DLayout<R>::M]) {
+  constexpr int LOWMASK = (1 << (R - 1)) - 1;
+#pragma unroll
+  for (int q = 0; q < DLayout<R>::M; ++q) {
+    const int s = (q >> DLayout<R>::S) & 1;
+    const int par = dcol_sign_parity<R>(q & LOWMASK, s) ^ dcol_sign_parity<R>((q >> (R - 1)) & LOWMASK, s);
+    v[q] = make_double2(par ? -1.0 : 1.0, 0.0);
+  }
+}
+
+// |sum_q g_x^|c| conj(g_y)^|c'| v[q]|^2 (right boundary of the gauge form).
+template <int R>
+__device__ __forceinline__ double dclosure(const double2 (&v)[DLayout<R>::M], double gxr, double gxi, double gyr,
+                                           double gyi) {
+  constexpr int LOWMASK = (1 << (R - 1)) - 1;
+  double pxr[R + 1], pxi[R + 1], pyr[R + 1], pyi[R + 1];
+  pxr[0] = 1.0; pxi[0] = 0.0; pyr[0] = 1.0; pyi[0] = 0.0;
+  gyi = -gyi;  // conj(g_y)
+#pragma unroll
+  for (int m = 1; m <= R; ++m) {
+    pxr[m] = fma(pxr[m - 1], gxr, -(pxi[m - 1] * gxi));
+    pxi[m] = fma(pxr[m - 1], gxi, pxi[m - 1] * gxr);
+    pyr[m] = fma(pyr[m - 1], gyr, -(pyi[m - 1] * gyi));
+    pyi[m] = fma(pyr[m - 1], gyi, pyi[m - 1] * gyr);
+  }
+  double sr = 0.0, si = 0.0;
+#pragma unroll
+  for (int q = 0; q < DLayout<R>::M; ++q) {
+    const int s = (q >> DLayout<R>::S) & 1;
+    const int hk = __builtin_popcount(q & LOWMASK) + s;
+    const int hb = __builtin_popcount((q >> (R - 1)) & LOWMASK) + s;
+    const double wr = fma(pxr[hk], pyr[hb], -(pxi[hk] * pyi[hb]));
+    const double wi = fma(pxr[hk], pyi[hb], pxi[hk] * pyr[hb]);
+    sr = fma(wr, v[q].x, fma(-wi, v[q].y, sr));
+    si = fma(wr, v[q].y, fma(wi, v[q].x, si));
+  }
+  return fma(sr, sr, si * si);
+}
+
+__global__ void refine_reset(uint32_t* count) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *count = 0u;
+}
+
+// One block per tile of the launch: the largest computed entry of the tile
+// (the assigned symmetric diagonal excluded); tiles above `thresh` are
+// appended to the list.
+__global__ void __launch_bounds__(256)
+refine_scan_kernel(SweepArgs a, double thresh, uint32_t* __restrict__ list, uint32_t* __restrict__ count) {
+  __shared__ double red[4];
+  const uint32_t tiles = uint32_t(launch_tiles(a));
+  for (uint32_t u = blockIdx.x; u < tiles; u += gridDim.x) {  // block-uniform
+    int32_t ti, tj;
+    const bool valid = decode_tile(a, u, ti, tj);
+    double m = 0.0;
+    if (valid) {
+      for (int e = threadIdx.x; e < kTile * kTile; e += 256) {
+        const int64_t i = int64_t(ti) * kTile + e / kTile, j = int64_t(tj) * kTile + e % kTile;
+        if (pair_computed(a, i, j)) m = fmax(m, a.K[i * a.ldk + j]);
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const double mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+      if (mx > thresh) list[atomicAdd(count, 1u)] = u;
+    }
+    __syncthreads();  // red is reused by the next tile
+  }
+}
+
+// Each wave takes items (listed tile, ket point of the tile) and recomputes
+// that ket point against the tile's 64 bra points in FP64.
+template <int R>
+__global__ void __launch_bounds__(256)
+refine_kernel(SweepArgs a, const uint32_t* __restrict__ list, const uint32_t* __restrict__ count) {
+  constexpr int M = DLayout<R>::M;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const float4* __restrict__ gA = a.gen_a;
+  const float4* __restrict__ gB = a.gen_b;
+  const float4* __restrict__ lA = a.gen_a + int64_t(a.n) * a.Na;  // Section L follows Section G
+  const float4* __restrict__ lB = a.gen_b + int64_t(a.n) * a.Nb;
+  const uint64_t items = uint64_t(*count) * kTile;
+  for (uint64_t it = uint64_t(blockIdx.x) * 4 + wave; it < items; it += uint64_t(gridDim.x) * 4) {  // wave-uniform
+    int32_t ti, tj;
+    if (!decode_tile(a, list[it / kTile], ti, tj)) continue;
+    const int64_t i = int64_t(ti) * kTile + int64_t(it % kTile);
+    const int64_t j = int64_t(tj) * kTile + lane;
+    const bool comp = pair_computed(a, i, j);
+    if (!__builtin_amdgcn_ballot_w64(comp)) continue;
+    const int64_t ic = (i < a.Na) ? i : a.Na - 1;  // loads of idle lanes stay in bounds
+    const int64_t jc = (j < a.Nb) ? j : a.Nb - 1;
+    double2 v[M];
+    dinit_env<R>(v);
+    int32_t acc = 0;
+    int countdown = a.renorm_every;
+    for (int k = 1; k < a.n; ++k) {
+      const Gen64 cx = gen64(gA, lA, int64_t(k) * a.Na + ic);
+      const Gen64 cy = gen64(gB, lB, int64_t(k) * a.Nb + jc);
+      dsite_step<R>(v, cx, cy);
+      if (--countdown == 0) {
+        acc += drenorm(v);
+        countdown = a.renorm_every;
+      }
+    }
+    if (comp) {
+      const Gen64 gx = gen64(gA, lA, ic), gy = gen64(gB, lB, jc);
+      const double s2 = dclosure<R>(v, gx.ar, gx.ai, gy.ar, gy.ai);
+      store_entry(a, i, j, s2, 2 * (acc - R * a.n));
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_refine(const SweepArgs& a, int32_t reps, double thresh, uint32_t* list, uint32_t* count,
+                         int64_t resident_blocks, hipStream_t stream) {
+  if (reps < 1 || reps > 3) return hipErrorInvalidValue;
+  const int64_t tiles = launch_tiles(a);
+  if (tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(refine_reset, dim3(1), dim3(64), 0, stream, count);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t scan_blocks = tiles < kMaxGridBlocks ? tiles : kMaxGridBlocks / 8 * 8;
+  hipLaunchKernelGGL(refine_scan_kernel, dim3(unsigned(scan_blocks)), dim3(256), 0, stream, a, thresh, list, count);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // enough waves for every listed ket point, at most the resident blocks
+  int64_t blocks = tiles * kTile / 4;
+  if (blocks > resident_blocks) blocks = resident_blocks;
+  if (blocks < 1) blocks = 1;
+  switch (reps) {
+    case 1: hipLaunchKernelGGL(refine_kernel<1>, dim3(unsigned(blocks)), dim3(256), 0, stream, a, list, count); break;
+    case 2: hipLaunchKernelGGL(refine_kernel<2>, dim3(unsigned(blocks)), dim3(256), 0, stream, a, list, count); break;
+    default: hipLaunchKernelGGL(refine_kernel<3>, dim3(unsigned(blocks)), dim3(256), 0, stream, a, list, count); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t refine_resident_blocks(int32_t reps, int64_t* out) {
+  int dev = 0, cus = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) {
+    switch (reps) {
+      case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, refine_kernel<1>, 256, 0); break;
+      case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, refine_kernel<2>, 256, 0); break;
+      default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, refine_kernel<3>, 256, 0); break;
+    }
+  }
+  if (e != hipSuccess) return e;
+  *out = int64_t(cus > 0 ? cus : 1) * (per_cu > 0 ? per_cu : 1);
+  return hipSuccess;
+}
+
+}  // namespace qsvm

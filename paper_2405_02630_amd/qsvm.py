@@ -39,6 +39,7 @@ class GramOpts(ctypes.Structure):
         ("row_begin", ctypes.c_int64),
         ("row_end", ctypes.c_int64),
         ("log_k", ctypes.c_void_p),
+        ("refine_above", ctypes.c_double),
     ]
 
 
@@ -64,6 +65,7 @@ class BatchOpts(ctypes.Structure):
         ("diag_mode", ctypes.c_int32),
         ("use_graph", ctypes.c_int32),
         ("grid_blocks", ctypes.c_int32),
+        ("refine_above", ctypes.c_double),
     ]
 
 
@@ -255,8 +257,9 @@ def qsvm_set_tuned_variant(reps: int, n_qubits: int, variant: int) -> None:
     _check(load_library().qsvm_set_tuned_variant(reps, n_qubits, variant))
 
 
-def _opts(renorm_every, sweep, diag_mode, rows, log_k, variant=0):
+def _opts(renorm_every, sweep, diag_mode, rows, log_k, variant=0, refine_above=0.0):
     o = GramOpts()
+    o.refine_above = refine_above
     o.variant = variant
     o.renorm_every = renorm_every
     o.sweep = sweep
@@ -268,8 +271,10 @@ def _opts(renorm_every, sweep, diag_mode, rows, log_k, variant=0):
 
 
 def qsvm_gram(mps_a: MPS, mps_b: MPS, K=None, *, log_k=None, renorm_every: int = 0,
-              sweep: int = SWEEP_AUTO, rows=None, variant: int = 0, stream=None):
-    """K[i, j] = |<psi(b_j)|psi(a_i)>|^2 (CUDA float64, Na x Nb).  Returns K."""
+              sweep: int = SWEEP_AUTO, rows=None, variant: int = 0, refine_above: float = 0.0, stream=None):
+    """K[i, j] = |<psi(b_j)|psi(a_i)>|^2 (CUDA float64, Na x Nb).  Returns K.
+    refine_above: tiles with an entry above it are recomputed in FP64 (0 =
+    default 1e-3, negative = off)."""
     import torch
 
     lib = load_library()
@@ -281,7 +286,7 @@ def qsvm_gram(mps_a: MPS, mps_b: MPS, K=None, *, log_k=None, renorm_every: int =
         raise ValueError("K must be 2-D with unit column stride and at least Na rows")
     if log_k is not None and (log_k.shape != K.shape or log_k.stride() != K.stride() or log_k.dtype != torch.float64):
         raise ValueError("log_k must match K's shape, strides and dtype")
-    o = _opts(renorm_every, sweep, 0, rows, log_k, variant)
+    o = _opts(renorm_every, sweep, 0, rows, log_k, variant, refine_above)
     st = lib.qsvm_gram(
         _device_ptr(mps_a.buf, "mps_a"), mps_a.N, _device_ptr(mps_b.buf, "mps_b"), mps_b.N, mps_a.n, mps_a.reps,
         ctypes.c_void_p(K.data_ptr()), K.stride(0), ctypes.byref(o), _stream_ptr(stream),
@@ -291,7 +296,7 @@ def qsvm_gram(mps_a: MPS, mps_b: MPS, K=None, *, log_k=None, renorm_every: int =
 
 
 def qsvm_gram_sym(mps: MPS, K=None, *, log_k=None, renorm_every: int = 0, sweep: int = SWEEP_AUTO,
-                  diag_mode: int = 0, rows=None, variant: int = 0, stream=None):
+                  diag_mode: int = 0, rows=None, variant: int = 0, refine_above: float = 0.0, stream=None):
     """Symmetric Gram of one set: pairs i < j contracted, mirrored, K[i, i] = 1
     (diag_mode 0) or computed (diag_mode 1).  Returns K."""
     import torch
@@ -303,7 +308,7 @@ def qsvm_gram_sym(mps: MPS, K=None, *, log_k=None, renorm_every: int = 0, sweep:
         raise ValueError("K must be 2-D with unit column stride and at least N rows")
     if log_k is not None and (log_k.shape != K.shape or log_k.stride() != K.stride() or log_k.dtype != torch.float64):
         raise ValueError("log_k must match K's shape, strides and dtype")
-    o = _opts(renorm_every, sweep, diag_mode, rows, log_k, variant)
+    o = _opts(renorm_every, sweep, diag_mode, rows, log_k, variant, refine_above)
     st = lib.qsvm_gram_sym(
         _device_ptr(mps.buf, "mps"), mps.N, mps.n, mps.reps, ctypes.c_void_p(K.data_ptr()), K.stride(0),
         ctypes.byref(o), _stream_ptr(stream),
@@ -391,7 +396,7 @@ class BatchPlan:
     one execution on the current PyTorch stream."""
 
     def __init__(self, jobs, *, renorm_every: int = 0, diag_mode: int = 0, use_graph: bool = True,
-                 grid_blocks: int = 0):
+                 grid_blocks: int = 0, refine_above: float = 0.0):
         lib = load_library()
         self._keep = list(jobs)
         arr = (Job * len(jobs))()
@@ -405,7 +410,7 @@ class BatchPlan:
             arr[q].K = K.data_ptr()
             arr[q].ldk = K.stride(0)
             arr[q].log_k = None if L is None else L.data_ptr()
-        o = BatchOpts(renorm_every, diag_mode, 1 if use_graph else 0, grid_blocks)
+        o = BatchOpts(renorm_every, diag_mode, 1 if use_graph else 0, grid_blocks, refine_above)
         h = ctypes.c_void_p()
         _check(lib.qsvm_batch_plan_create(arr, len(jobs), ctypes.byref(o), ctypes.byref(h)))
         self._h = h
@@ -441,9 +446,10 @@ def _p(t):
 
 
 def qsvm_gram_sym_tiles(mps: MPS, tiles, n_tiles: int, K, *, log_k=None, renorm_every: int = 0,
-                        sweep: int = SWEEP_AUTO, diag_mode: int = 0, variant: int = 0, stream=None):
+                        sweep: int = SWEEP_AUTO, diag_mode: int = 0, variant: int = 0, refine_above: float = 0.0,
+                        stream=None):
     """Exact symmetric Gram on a device list of (ti, tj) tiles (int32 tensor)."""
-    o = _opts(renorm_every, sweep, diag_mode, None, log_k, variant)
+    o = _opts(renorm_every, sweep, diag_mode, None, log_k, variant, refine_above)
     _check(load_library().qsvm_gram_sym_tiles(
         _device_ptr(mps.buf, "mps"), mps.N, mps.n, mps.reps, _p(tiles), n_tiles, _p(K), K.stride(0),
         ctypes.byref(o), _stream_ptr(stream)))

@@ -74,14 +74,18 @@ def gram_rect(Xa, Xb, reps, log=True, **kw):
     return K.cpu().numpy(), (L.cpu().numpy() if log else None)
 
 
-def mps_sections(m):
-    """Host copies of Section D (N, n, chi, chi complex) and Section G (n, N, 4 float)."""
+def mps_sections(m, residuals=False):
+    """Host copies of Section D (N, n, chi, chi complex) and Section G (n, N, 4 float),
+    and with residuals=True also Section L (n, N, 4 float)."""
     N, n, reps = m.N, m.n, m.reps
     chi = 1 << reps
     raw = m.buf.cpu().numpy()
     nd = n * N * chi * chi * 8
     dense = raw[:nd].view(np.complex64).reshape(n, N, chi, chi)
     gen = raw[nd : nd + n * N * 16].view(np.float32).reshape(n, N, 4)
+    if residuals:
+        lo = raw[nd + n * N * 16 : nd + n * N * 32].view(np.float32).reshape(n, N, 4)
+        return dense, gen, lo
     return dense, gen
 
 

@@ -51,15 +51,16 @@ def test_abi_version(lib):
 
 
 def test_opts_struct_layout():
-    # int32 x4, int64 x2, pointer: 40 bytes, log_k at offset 32
-    assert ctypes.sizeof(qsvm.GramOpts) == 40
+    # int32 x4, int64 x2, pointer, double: 48 bytes, log_k at 32, refine_above at 40
+    assert ctypes.sizeof(qsvm.GramOpts) == 48
     assert qsvm.GramOpts.log_k.offset == 32
+    assert qsvm.GramOpts.refine_above.offset == 40
 
 
 @pytest.mark.parametrize("N,n,reps", [(1, 1, 1), (32, 8, 2), (4096, 784, 2), (1024, 784, 3), (7, 3, 1), (1024, 784, 4)])
 def test_mps_bytes_formula(N, n, reps):
     chi = 2**reps
-    assert qsvm.qsvm_mps_bytes(N, n, reps) == n * N * (chi * chi * 8 + 16)
+    assert qsvm.qsvm_mps_bytes(N, n, reps) == n * N * (chi * chi * 8 + 32)
 
 
 @pytest.mark.parametrize("N,n,reps", [(0, 8, 2), (8, 0, 2), (8, 8, 0), (8, 8, 5), (-1, 8, 2), (8, 65536, 2), (2**31, 8, 2)])
@@ -134,6 +135,18 @@ def test_gram_rejects_a_tile_row_wider_than_one_launch(lib, no_inject, reps, nb_
     assert _rect(lib, Na=64, Nb=nb_max, n=4, reps=reps, opts=opts) == qsvm.QSVM_OK
     assert _rect(lib, Na=64, Nb=nb_max + 1, n=4, reps=reps, opts=opts) == qsvm.QSVM_ERR_UNSUPPORTED
     assert b"exceeds one launch" in lib.qsvm_last_error()
+
+
+def test_refine_above_nan_is_rejected(lib, no_inject):
+    o = qsvm.GramOpts()
+    o.refine_above = float("nan")
+    assert _sym(lib, opts=o) == qsvm.QSVM_ERR_INVALID_ARG
+    assert _rect(lib, opts=o) == qsvm.QSVM_ERR_INVALID_ARG
+    assert b"refine_above" in lib.qsvm_last_error()
+    b = qsvm.BatchOpts()
+    b.refine_above = float("nan")
+    st, h = _plan(lib, [_job()], b)
+    assert st == qsvm.QSVM_ERR_INVALID_ARG and not h.value
 
 
 def test_dense_sweep_rejects_reps_4(lib, no_inject):

@@ -1,0 +1,135 @@
+"""GPU tests of the FP64 refinement of large Gram entries.
+
+The FP32 sweep's error in K is relative and biased low: at 784 qubits an
+entry near 1 (a self-overlap, a near-duplicate pair) comes out 1e-5 or more
+below its exact value.  With refinement (the default, threshold 1e-3) every
+tile holding such an entry is recomputed with an FP64 environment from FP64
+generators.  Bars: refined entries within 1e-9 of the FP64 oracle (its own
+error is ~1e-12), every entry within the 1e-5 contract; untouched tiles are
+bitwise what the FP32 sweep wrote."""
+
+import numpy as np
+import pytest
+
+from oracle import mps as omps
+from paper_2405_02630_amd import qsvm, synth
+
+from gpu_helpers import K_ABS_TOL, encode, require_gpu, to_dev
+
+pytestmark = pytest.mark.gpu
+
+REFINED_TOL = 1e-9
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    return require_gpu()
+
+
+@pytest.mark.parametrize("reps", [1, 2, 3])
+def test_self_overlaps_784_qubits_are_exact(reps):
+    import torch
+
+    wl = synth.images784(seed=21, n_train=150, n_test=0, reps=reps)  # 3 tiles, ragged
+    m = encode(wl.X, reps)
+    K = qsvm.qsvm_gram_sym(m, diag_mode=1)
+    K32 = qsvm.qsvm_gram_sym(m, diag_mode=1, refine_above=-1.0)
+    torch.cuda.synchronize()
+    d = np.abs(np.diag(K.cpu().numpy()) - 1.0)
+    d32 = np.abs(np.diag(K32.cpu().numpy()) - 1.0)
+    assert d.max() <= REFINED_TOL
+    assert d32.max() > 1e-8  # the FP32 sweep's error that the refinement removes
+    # off-diagonal tiles hold only tiny entries: not refined, bitwise unchanged
+    Kh, K32h = K.cpu().numpy(), K32.cpu().numpy()
+    off = np.ones_like(Kh, dtype=bool)
+    for t in range(3):
+        off[t * 64:(t + 1) * 64, t * 64:(t + 1) * 64] = False
+    assert np.array_equal(Kh[off], K32h[off])
+
+
+@pytest.mark.parametrize("reps", [2, 3])
+def test_near_duplicates_784_qubits_vs_oracle(reps):
+    base, Xp, _, _ = synth.image_near_duplicates(seed=31, n_base=40)  # 40 x 200 pairs, K up to ~1
+    ma, mb = encode(base, reps), encode(Xp, reps)
+    K = qsvm.qsvm_gram(ma, mb).cpu().numpy()
+    Sa = omps.mps_states(base, reps, processes=5)
+    Sb = omps.mps_states(Xp, reps, processes=5)
+    ii, jj = np.meshgrid(np.arange(base.shape[0]), np.arange(Xp.shape[0]), indexing="ij")
+    _, kk = omps.mps_gram_pairs(Sa, Sb, ii.ravel(), jj.ravel())
+    d = np.abs(K.ravel() - kk)
+    big = kk > 1e-3
+    assert big.sum() >= 40
+    assert d[big].max() <= REFINED_TOL
+    assert d.max() <= K_ABS_TOL
+
+
+def test_every_variant_and_the_dense_sweep_agree_after_refinement():
+    import torch
+
+    base, Xp, _, _ = synth.image_near_duplicates(seed=33, n_base=30)
+    X = np.concatenate([base, Xp[:60]])  # 90 points, near-duplicate pairs inside
+    m = encode(X, 2)
+    Ks = [qsvm.qsvm_gram_sym(m, variant=v).cpu().numpy() for v in range(1, 5)]
+    torch.cuda.synchronize()
+    for K in Ks[1:]:
+        assert np.array_equal(K, Ks[0])
+    Kd = qsvm.qsvm_gram_sym(m, sweep=qsvm.SWEEP_DENSE).cpu().numpy()
+    big = Ks[0] > 1e-3
+    # refined tiles: both sweeps end in the same FP64 recomputation
+    assert np.max(np.abs(Kd[big] - Ks[0][big])) <= REFINED_TOL
+    assert np.max(np.abs(Kd - Ks[0])) <= K_ABS_TOL
+
+
+def test_tile_list_is_refined_like_the_full_gram():
+    import torch
+
+    base, Xp, _, _ = synth.image_near_duplicates(seed=35, n_base=50)
+    X = np.concatenate([base, Xp[:100]])  # 150 points, 3 tiles
+    m = encode(X, 2)
+    full = qsvm.qsvm_gram_sym(m, diag_mode=1).cpu().numpy()
+    T = 3
+    lst = [(i, j) for i in range(T) for j in range(i, T)]
+    tiles = torch.tensor(lst, dtype=torch.int32, device="cuda:0").reshape(-1)
+    K = torch.full((150, 150), -2.0, dtype=torch.float64, device="cuda:0")
+    qsvm.qsvm_gram_sym_tiles(m, tiles, len(lst), K, diag_mode=1)
+    torch.cuda.synchronize()
+    assert np.array_equal(K.cpu().numpy(), full)
+
+
+def test_row_range_refines_only_its_rows():
+    import torch
+
+    base, Xp, _, _ = synth.image_near_duplicates(seed=37, n_base=40)
+    ma, mb = encode(np.concatenate([base, base]), 2), encode(Xp, 2)  # 80 x 200
+    full = qsvm.qsvm_gram(ma, mb).cpu().numpy()
+    K = torch.full((80, 200), -3.0, dtype=torch.float64, device="cuda:0")
+    qsvm.qsvm_gram(ma, mb, K, rows=(64, 80))
+    torch.cuda.synchronize()
+    Kh = K.cpu().numpy()
+    assert np.all(Kh[:64] == -3.0)
+    assert np.array_equal(Kh[64:80], full[64:80])
+
+
+def test_batch_plan_is_refined_like_one_launch_per_job():
+    import torch
+
+    base, Xp, _, _ = synth.image_near_duplicates(seed=39, n_base=30)
+    sets = [np.concatenate([base, Xp[:40]]), synth.images784(seed=40, n_train=70, n_test=0, reps=3).X,
+            synth.uniform_features(100, 16, seed=41)]
+    reps = [2, 3, 2]
+    jobs, ref = [], []
+    for X, r in zip(sets, reps):
+        m = encode(X, r)
+        K = torch.empty((m.N, m.N), dtype=torch.float64, device="cuda:0")
+        jobs.append((m, K, None))
+        ref.append(qsvm.qsvm_gram_sym(m, diag_mode=1).cpu().numpy())
+    plan = qsvm.BatchPlan(jobs, diag_mode=1, use_graph=True)
+    for _ in range(2):  # graph replays
+        for _, K, _ in jobs:
+            K.fill_(-1.0)
+        plan.launch()
+        torch.cuda.synchronize()
+        for (_, K, _), R in zip(jobs, ref):
+            assert np.array_equal(K.cpu().numpy(), R)
+    plan.close()
+    assert np.max(np.abs(np.diag(ref[0]) - 1.0)) <= REFINED_TOL
