@@ -99,16 +99,17 @@ typedef struct {
                            same shape and ldk as K (-inf for an exact zero).
                            K itself underflows to 0 below ~1e-308; log_k does
                            not.  NULL = not written. */
-  double refine_above;  /* FP64 refinement (reps <= 3): after the FP32 sweep,
-                           every 64 x 64 tile whose largest computed entry
-                           exceeds this value is recomputed with an FP64
-                           environment from FP64 generators (Sections G + L),
-                           so entries near 1 meet a 1e-5 bar at any n.
-                           0 = default (1e-3); negative = off.  Costs one read
-                           of the written K plus the FP64 sweep of the listed
+  double refine_above;  /* FP64 refinement: after the FP32 sweep, every
+                           64 x 64 tile whose largest computed entry exceeds
+                           this value is recomputed with an FP64 environment
+                           from FP64 generators (Sections G + L), so entries
+                           near 1 meet a 1e-5 bar at any n (the FP32 sweep
+                           alone leaves up to ~1.3e-5 at 784 qubits).  0 =
+                           default (1e-3); negative = off.  Costs one read of
+                           the written K plus the FP64 sweep of the listed
                            tiles; a 4-byte-per-tile list lives in a
-                           stream-ordered temporary.  reps = 4 and the
-                           state-vector Grams ignore it. */
+                           stream-ordered temporary.  The state-vector Grams
+                           (FP64 throughout) ignore it. */
 } qsvm_gram_opts;
 
 /*

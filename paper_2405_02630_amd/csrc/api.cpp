@@ -104,11 +104,11 @@ qsvm_status read_opts(const qsvm_gram_opts* o, int64_t rows, Opts& out, const ch
 // Blocks of the refinement kernel resident on the current device, cached per
 // device and reps.
 hipError_t resident_refine_blocks(int32_t reps, int64_t* out) {
-  static std::atomic<int64_t> cache[64][4];  // zero-initialised (static storage)
+  static std::atomic<int64_t> cache[64][5];  // zero-initialised (static storage)
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
-  const bool cacheable = dev >= 0 && dev < 64 && reps >= 1 && reps <= 3;
+  const bool cacheable = dev >= 0 && dev < 64 && reps >= 1 && reps <= 4;
   if (cacheable) {
     const int64_t c = cache[dev][reps].load(std::memory_order_relaxed);
     if (c > 0) {
@@ -124,7 +124,7 @@ hipError_t resident_refine_blocks(int32_t reps, int64_t* out) {
 // FP64 refinement of the tiles of `a` (the tiles one Gram call swept) whose
 // largest entry exceeds the threshold, chunk by chunk like the sweeps.
 hipError_t refine_tiles(const qsvm::SweepArgs& a, int32_t reps, double thresh, hipStream_t stream) {
-  if (thresh < 0.0 || reps > 3) return hipSuccess;
+  if (thresh < 0.0) return hipSuccess;
   const int64_t tiles = qsvm::launch_tiles(a);
   if (tiles <= 0) return hipSuccess;
   int64_t resident = 0;

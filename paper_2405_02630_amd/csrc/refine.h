@@ -17,7 +17,7 @@ constexpr double kDefaultRefineAbove = 1e-3;
 // After a sweep launch over the tiles of `a` (at most kMaxGridBlocks tiles):
 // clear *count, list the tiles above `thresh` (list holds launch_tiles(a)
 // entries) and recompute their pairs in FP64 with a grid of at most
-// `resident_blocks` blocks.  reps 1..3.
+// `resident_blocks` blocks.  reps 1..4.
 hipError_t launch_refine(const SweepArgs& a, int32_t reps, double thresh, uint32_t* list, uint32_t* count,
                          int64_t resident_blocks, hipStream_t stream);
 // Blocks of the refinement kernel for `reps` resident on the current device.

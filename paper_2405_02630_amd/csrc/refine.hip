@@ -17,7 +17,8 @@
 //
 // The FP64 sweep is the one-lane butterfly sweep of sweep_butterfly_item.h
 // (same recursion, gauge, sign pattern, renormalisation and closure) with
-// doubles: one pair per lane, one ket point per wave, reps <= 3.
+// doubles: one pair per lane and one ket point per wave for reps <= 3; at
+// reps = 4 (128 environment entries) one pair per wave.
 
 #include "../../include/qsvm.h"
 #include "refine.h"
@@ -242,11 +243,131 @@ refine_kernel(SweepArgs a, const uint32_t* __restrict__ list, const uint32_t* __
   }
 }
 
+// reps = 4: one pair per wave.  The 2^7 environment entries q sit two per
+// lane: lane = bits 0..5 of q (ket bits 0-2, bra bits 3-5), register e = bit
+// 6 (the shared physical bit).  The shared-bit axis runs in registers; a ket
+// or bra axis on bit B pairs lane l with lane l ^ 2^B: the lane without the
+// bit computes u0 + a u1, the lane with it +-(u0 + b u1), each from its own
+// value and its partner's (__shfl_xor).  Sign rule, renormalisation and
+// closure as in the one-lane sweep, with wave-wide reductions.
+template <int B, int SIGNBIT>
+__device__ __forceinline__ void wave_axis(double2 (&v)[2], int lane, double ar, double ai, double br, double bi) {
+  const bool upper = (lane >> B) & 1;
+  double2 t[2];
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const double pr = __shfl_xor(v[e].x, 1 << B, 64), pim = __shfl_xor(v[e].y, 1 << B, 64);
+    const double2 u0 = upper ? make_double2(pr, pim) : v[e];
+    const double2 u1 = upper ? v[e] : make_double2(pr, pim);
+    const double cr = upper ? br : ar, ci = upper ? bi : ai;
+    double tr = fma(cr, u1.x, u0.x);
+    tr = fma(-ci, u1.y, tr);
+    double ti = fma(cr, u1.y, u0.y);
+    ti = fma(ci, u1.x, ti);
+    const int i0 = (lane | (e << 6)) & ~(1 << B);
+    const bool neg = upper && SIGNBIT >= 0 && ((i0 >> (SIGNBIT < 0 ? 0 : SIGNBIT)) & 1);
+    t[e] = neg ? make_double2(-tr, -ti) : make_double2(tr, ti);
+  }
+  v[0] = t[0];
+  v[1] = t[1];
+}
+
+__global__ void __launch_bounds__(256)
+refine_wave_kernel(SweepArgs a, const uint32_t* __restrict__ list, const uint32_t* __restrict__ count) {
+  constexpr int R = 4;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const float4* __restrict__ gA = a.gen_a;
+  const float4* __restrict__ gB = a.gen_b;
+  const float4* __restrict__ lA = a.gen_a + int64_t(a.n) * a.Na;  // Section L follows Section G
+  const float4* __restrict__ lB = a.gen_b + int64_t(a.n) * a.Nb;
+  const uint64_t items = uint64_t(*count) * (kTile * kTile);
+  for (uint64_t it = uint64_t(blockIdx.x) * 4 + wave; it < items; it += uint64_t(gridDim.x) * 4) {  // wave-uniform
+    int32_t ti, tj;
+    if (!decode_tile(a, list[it / (kTile * kTile)], ti, tj)) continue;
+    const int pr = int(it % (kTile * kTile));
+    const int64_t i = int64_t(ti) * kTile + pr / kTile, j = int64_t(tj) * kTile + pr % kTile;
+    if (!pair_computed(a, i, j)) continue;  // the same pair in every lane
+    double2 v[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int q = lane | (e << 6);
+      const int par = dcol_sign_parity<R>(q & 7, e) ^ dcol_sign_parity<R>((q >> 3) & 7, e);
+      v[e] = make_double2(par ? -1.0 : 1.0, 0.0);
+    }
+    int32_t acc = 0;
+    int countdown = a.renorm_every;
+    for (int k = 1; k < a.n; ++k) {
+      const Gen64 cx = gen64(gA, lA, int64_t(k) * a.Na + i);
+      const Gen64 cy = gen64(gB, lB, int64_t(k) * a.Nb + j);
+      // ket axes (bits 0, 1, 2; sign bit = the previous one), bra axes (bits 3, 4, 5)
+      wave_axis<0, -1>(v, lane, cx.ar, cx.ai, cx.br, cx.bi);
+      wave_axis<1, 0>(v, lane, cx.ar, cx.ai, cx.br, cx.bi);
+      wave_axis<2, 1>(v, lane, cx.ar, cx.ai, cx.br, cx.bi);
+      wave_axis<3, -1>(v, lane, cy.ar, -cy.ai, cy.br, -cy.bi);
+      wave_axis<4, 3>(v, lane, cy.ar, -cy.ai, cy.br, -cy.bi);
+      wave_axis<5, 4>(v, lane, cy.ar, -cy.ai, cy.br, -cy.bi);
+      // shared bit (register e): a_x conj(a_y), b_x conj(b_y); sign bits 2 and 5
+      const double asr = fma(cx.ar, cy.ar, cx.ai * cy.ai);
+      const double asi = fma(cx.ai, cy.ar, -(cx.ar * cy.ai));
+      const double bsr = fma(cx.br, cy.br, cx.bi * cy.bi);
+      const double bsi = fma(cx.bi, cy.br, -(cx.br * cy.bi));
+      const bool neg = ((lane >> 2) ^ (lane >> 5)) & 1;
+      dbfly<false>(v[0], v[1], asr, asi, bsr, bsi);
+      if (neg) v[1] = make_double2(-v[1].x, -v[1].y);
+      if (--countdown == 0) {
+        double m = fmax(fmax(fabs(v[0].x), fabs(v[0].y)), fmax(fabs(v[1].x), fabs(v[1].y)));
+        for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+        int e = 0;
+        (void)frexp(m, &e);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) v[q] = make_double2(ldexp(v[q].x, -e), ldexp(v[q].y, -e));
+        acc += e;
+        countdown = a.renorm_every;
+      }
+    }
+    // closure: sum over the wave of g_x^|c| conj(g_y)^|c'| v[q]
+    const Gen64 gx = gen64(gA, lA, i), gy = gen64(gB, lB, j);
+    double pxr[R + 1], pxi[R + 1], pyr[R + 1], pyi[R + 1];
+    pxr[0] = 1.0; pxi[0] = 0.0; pyr[0] = 1.0; pyi[0] = 0.0;
+    const double gyi = -gy.ai;  // conj(g_y)
+#pragma unroll
+    for (int m = 1; m <= R; ++m) {
+      pxr[m] = fma(pxr[m - 1], gx.ar, -(pxi[m - 1] * gx.ai));
+      pxi[m] = fma(pxr[m - 1], gx.ai, pxi[m - 1] * gx.ar);
+      pyr[m] = fma(pyr[m - 1], gy.ar, -(pyi[m - 1] * gyi));
+      pyi[m] = fma(pyr[m - 1], gyi, pyi[m - 1] * gy.ar);
+    }
+    double sr = 0.0, si = 0.0;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int hk = __builtin_popcount(lane & 7) + e;
+      const int hb = __builtin_popcount((lane >> 3) & 7) + e;
+      double wr = 0.0, wi = 0.0;
+#pragma unroll
+      for (int x = 0; x <= R; ++x)  // select the powers without dynamic register indexing
+#pragma unroll
+        for (int y = 0; y <= R; ++y)
+          if (x == hk && y == hb) {
+            wr = fma(pxr[x], pyr[y], -(pxi[x] * pyi[y]));
+            wi = fma(pxr[x], pyi[y], pxi[x] * pyr[y]);
+          }
+      sr = fma(wr, v[e].x, fma(-wi, v[e].y, sr));
+      si = fma(wr, v[e].y, fma(wi, v[e].x, si));
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      sr += __shfl_xor(sr, off, 64);
+      si += __shfl_xor(si, off, 64);
+    }
+    if (lane == 0) store_entry(a, i, j, fma(sr, sr, si * si), 2 * (acc - R * a.n));
+  }
+}
+
 }  // namespace
 
 hipError_t launch_refine(const SweepArgs& a, int32_t reps, double thresh, uint32_t* list, uint32_t* count,
                          int64_t resident_blocks, hipStream_t stream) {
-  if (reps < 1 || reps > 3) return hipErrorInvalidValue;
+  if (reps < 1 || reps > 4) return hipErrorInvalidValue;
   const int64_t tiles = launch_tiles(a);
   if (tiles <= 0) return hipSuccess;
   hipLaunchKernelGGL(refine_reset, dim3(1), dim3(64), 0, stream, count);
@@ -256,10 +377,15 @@ hipError_t launch_refine(const SweepArgs& a, int32_t reps, double thresh, uint32
   hipLaunchKernelGGL(refine_scan_kernel, dim3(unsigned(scan_blocks)), dim3(256), 0, stream, a, thresh, list, count);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  // enough waves for every listed ket point, at most the resident blocks
-  int64_t blocks = tiles * kTile / 4;
+  // enough waves for every listed ket point (pair at reps = 4), at most the
+  // resident blocks
+  int64_t blocks = tiles * (reps == 4 ? kTile * kTile : kTile) / 4;
   if (blocks > resident_blocks) blocks = resident_blocks;
   if (blocks < 1) blocks = 1;
+  if (reps == 4) {
+    hipLaunchKernelGGL(refine_wave_kernel, dim3(unsigned(blocks)), dim3(256), 0, stream, a, list, count);
+    return hipGetLastError();
+  }
   switch (reps) {
     case 1: hipLaunchKernelGGL(refine_kernel<1>, dim3(unsigned(blocks)), dim3(256), 0, stream, a, list, count); break;
     case 2: hipLaunchKernelGGL(refine_kernel<2>, dim3(unsigned(blocks)), dim3(256), 0, stream, a, list, count); break;
@@ -276,7 +402,8 @@ hipError_t refine_resident_blocks(int32_t reps, int64_t* out) {
     switch (reps) {
       case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, refine_kernel<1>, 256, 0); break;
       case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, refine_kernel<2>, 256, 0); break;
-      default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, refine_kernel<3>, 256, 0); break;
+      case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, refine_kernel<3>, 256, 0); break;
+      default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, refine_wave_kernel, 256, 0); break;
     }
   }
   if (e != hipSuccess) return e;

@@ -2,7 +2,7 @@
 
 The FP32 sweep's error in K is relative and biased low: at 784 qubits an
 entry near 1 (a self-overlap, a near-duplicate pair) comes out 1e-5 or more
-below its exact value.  With refinement (the default, threshold 1e-3) every
+below its exact value (reps 2 to 4).  With refinement (the default, threshold 1e-3) every
 tile holding such an entry is recomputed with an FP64 environment from FP64
 generators.  Bars: refined entries within 1e-9 of the FP64 oracle (its own
 error is ~1e-12), every entry within the 1e-5 contract; untouched tiles are
@@ -26,7 +26,7 @@ def gpu():
     return require_gpu()
 
 
-@pytest.mark.parametrize("reps", [1, 2, 3])
+@pytest.mark.parametrize("reps", [1, 2, 3, 4])
 def test_self_overlaps_784_qubits_are_exact(reps):
     import torch
 
@@ -47,9 +47,9 @@ def test_self_overlaps_784_qubits_are_exact(reps):
     assert np.array_equal(Kh[off], K32h[off])
 
 
-@pytest.mark.parametrize("reps", [2, 3])
-def test_near_duplicates_784_qubits_vs_oracle(reps):
-    base, Xp, _, _ = synth.image_near_duplicates(seed=31, n_base=40)  # 40 x 200 pairs, K up to ~1
+@pytest.mark.parametrize("reps,n_base", [(2, 40), (3, 40), (4, 8)])
+def test_near_duplicates_784_qubits_vs_oracle(reps, n_base):
+    base, Xp, _, _ = synth.image_near_duplicates(seed=31, n_base=n_base)  # n_base x 5 n_base pairs, K up to ~1
     ma, mb = encode(base, reps), encode(Xp, reps)
     K = qsvm.qsvm_gram(ma, mb).cpu().numpy()
     Sa = omps.mps_states(base, reps, processes=5)
@@ -58,7 +58,7 @@ def test_near_duplicates_784_qubits_vs_oracle(reps):
     _, kk = omps.mps_gram_pairs(Sa, Sb, ii.ravel(), jj.ravel())
     d = np.abs(K.ravel() - kk)
     big = kk > 1e-3
-    assert big.sum() >= 40
+    assert big.sum() >= n_base
     assert d[big].max() <= REFINED_TOL
     assert d.max() <= K_ABS_TOL
 
