@@ -102,14 +102,18 @@ typedef struct {
   double refine_above;  /* FP64 refinement: after the FP32 sweep, every
                            64 x 64 tile whose largest computed entry exceeds
                            this value is recomputed with an FP64 environment
-                           from FP64 generators (Sections G + L), so entries
-                           near 1 meet a 1e-5 bar at any n (the FP32 sweep
-                           alone leaves up to ~1.3e-5 at 784 qubits).  0 =
-                           default (1e-3); negative = off.  Costs one read of
-                           the written K plus the FP64 sweep of the listed
-                           tiles; a 4-byte-per-tile list lives in a
-                           stream-ordered temporary.  The state-vector Grams
-                           (FP64 throughout) ignore it. */
+                           from FP64 generators (Sections G + L).  The FP32
+                           sweep alone leaves up to ~1.3e-5 at 784 qubits for
+                           K near 1 (measured bound 4e-6 + 2e-8 n at K = 1,
+                           ~sqrt(K) times that below).  0 = automatic:
+                           (5e-6 / (4e-6 + 2e-8 n))^2, so every entry left in
+                           FP32 stays within 5e-6 (0.064 at 784 qubits; no
+                           refinement and no scan at n <= 50); > 0 = that
+                           threshold; negative = off.  Costs one read of the
+                           written K plus the FP64 sweep of the listed tiles;
+                           a 4-byte-per-tile list lives in a stream-ordered
+                           temporary.  The state-vector Grams (FP64
+                           throughout) ignore it. */
 } qsvm_gram_opts;
 
 /*
@@ -231,8 +235,8 @@ typedef struct {
                            per unit */
   double refine_above;  /* as in qsvm_gram_opts: after the persistent sweep, each
                            job's tiles with an entry above it are recomputed in
-                           FP64 (0 = default 1e-3, negative = off); the plan
-                           holds the list buffer */
+                           FP64 (0 = automatic per job from its n_qubits,
+                           negative = off); the plan holds the list buffer */
 } qsvm_batch_opts;
 
 typedef struct qsvm_batch_plan qsvm_batch_plan; /* opaque */

@@ -68,7 +68,7 @@ struct Opts {
   int32_t variant = 0;
   int64_t row_begin = 0, row_end = 0;
   double* log_k = nullptr;
-  double refine_above = qsvm::kDefaultRefineAbove;  // negative: no refinement
+  double refine_above = 0.0;  // 0: automatic (qsvm::auto_refine_threshold); negative: no refinement
 };
 
 qsvm_status read_opts(const qsvm_gram_opts* o, int64_t rows, Opts& out, const char* what) {
@@ -124,7 +124,8 @@ hipError_t resident_refine_blocks(int32_t reps, int64_t* out) {
 // FP64 refinement of the tiles of `a` (the tiles one Gram call swept) whose
 // largest entry exceeds the threshold, chunk by chunk like the sweeps.
 hipError_t refine_tiles(const qsvm::SweepArgs& a, int32_t reps, double thresh, hipStream_t stream) {
-  if (thresh < 0.0) return hipSuccess;
+  if (thresh == 0.0) thresh = qsvm::auto_refine_threshold(a.n);
+  if (thresh < 0.0 || thresh >= 1.0) return hipSuccess;  // off, or no entry can need it
   const int64_t tiles = qsvm::launch_tiles(a);
   if (tiles <= 0) return hipSuccess;
   int64_t resident = 0;

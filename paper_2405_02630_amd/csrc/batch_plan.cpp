@@ -28,7 +28,7 @@ struct qsvm_batch_plan {
   bool launched = false;
   // FP64 refinement after the persistent sweep, job by job
   std::vector<qsvm::BatchJob> host_jobs;
-  double refine_above = 0.0;          // negative: off
+  double refine_above = 0.0;          // 0: automatic per job; negative: off
   uint32_t* d_refine = nullptr;       // [count, list of the largest job's tiles]
   int64_t refine_resident[4] = {0, 0, 0, 0};
 };
@@ -55,8 +55,10 @@ hipError_t plan_enqueue(qsvm_batch_plan* p, hipStream_t s) {
   hipError_t e = launch_batch(p->d_jobs, p->n_jobs, p->total_items, p->d_counter, p->grid, s);
   if (e != hipSuccess || p->refine_above < 0.0) return e;
   for (const BatchJob& j : p->host_jobs) {
+    const double thresh = p->refine_above > 0.0 ? p->refine_above : auto_refine_threshold(j.args.n);
+    if (thresh >= 1.0) continue;  // no entry of this job can need it
     e = launch_chunked(j.args, 1, [&](const SweepArgs& c) {
-      return launch_refine(c, j.reps, p->refine_above, p->d_refine + 1, p->d_refine, p->refine_resident[j.reps], s);
+      return launch_refine(c, j.reps, thresh, p->d_refine + 1, p->d_refine, p->refine_resident[j.reps], s);
     });
     if (e != hipSuccess) return e;
   }
@@ -192,7 +194,7 @@ extern "C" qsvm_status qsvm_batch_plan_create(const qsvm_job* jobs, int32_t n_jo
   p->n_jobs = n_jobs;
   p->total_items = total;
   p->host_jobs = table;
-  p->refine_above = o.refine_above == 0.0 ? kDefaultRefineAbove : o.refine_above;
+  p->refine_above = o.refine_above;
   int64_t max_tiles = 1;
   for (const BatchJob& j : table) max_tiles = std::max(max_tiles, std::min(launch_tiles(j.args), kMaxGridBlocks));
   if (p->refine_above >= 0.0) {

@@ -8,11 +8,22 @@ namespace qsvm {
 
 struct SweepArgs;
 
-// Default threshold: tiles whose largest computed entry exceeds it are
-// recomputed in FP64.  Below it the FP32 sweep's relative error (< 1e-3 up
-// to the largest supported qubit count, ~1.5e-5 at 784 qubits) keeps every
-// entry within 1e-6 of exact.
-constexpr double kDefaultRefineAbove = 1e-3;
+// Automatic threshold for n qubits: tiles whose largest computed entry
+// exceeds it are recomputed in FP64.  The FP32 sweep's error at K = 1
+// (self-overlaps, the largest amplitude) was measured at up to 3e-6 (64
+// qubits), 8e-6 (400), 1.3e-5 (784) and 2.5e-5 (2000) over image, uniform
+// and mixture features and reps 1..4, inside err(n) = 4e-6 + 2e-8 n.  The
+// error of the amplitude is absolute (the environment stays O(1) after
+// renormalisation), so an entry K carries |dK| <~ sqrt(K) err(n); entries
+// left in FP32 stay within kRefineBudget (half the 1e-5 bar) when
+// K <= (kRefineBudget / err(n))^2.  At or above 1 (n <= 50) nothing needs
+// refining and the scan is skipped.
+constexpr double kRefineBudget = 5e-6;
+__host__ __device__ inline double auto_refine_threshold(int32_t n) {
+  const double err = 4e-6 + 2e-8 * double(n);
+  const double t = kRefineBudget / err;
+  return t * t;
+}
 
 // After a sweep launch over the tiles of `a` (at most kMaxGridBlocks tiles):
 // clear *count, list the tiles above `thresh` (list holds launch_tiles(a)

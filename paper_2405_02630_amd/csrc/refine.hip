@@ -1,12 +1,13 @@
 // FP64 refinement of the tiles whose largest entry is large.
 //
 // The sweep carries the environment in FP32.  Its rounding error in K is
-// relative and biased (an FP32 emulation of 784-qubit self-overlaps gives
-// K = 1 - 1.0e-5 ... 1.5e-5 from the arithmetic and < 3e-6 from the FP32
-// generators), so at 784 qubits an entry close to 1 can miss an absolute
-// bar of 1e-5 while every entry below 1e-3 is within 1e-8 of exact.  After a
-// sweep launch, refine_scan_kernel reads the K tiles the launch wrote and
-// lists those whose largest computed entry exceeds a threshold, and
+// biased (an FP32 emulation of 784-qubit self-overlaps gives K = 1 - 1.0e-5
+// ... 1.5e-5 from the arithmetic and < 3e-6 from the FP32 generators), so at
+// 784 qubits an entry close to 1 can miss an absolute bar of 1e-5 while small
+// entries stay far inside it (the threshold rule is auto_refine_threshold in
+// refine.h).  After a sweep launch, refine_scan_kernel reads the K tiles the
+// launch wrote and lists those whose largest computed entry exceeds a
+// threshold, and
 // refine_kernel recomputes every pair of the listed tiles with an FP64
 // environment from FP64 generators (Section G value + Section L residual),
 // overwriting K and log K.  The list length stays on the device: the

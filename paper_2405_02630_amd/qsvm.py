@@ -274,7 +274,7 @@ def qsvm_gram(mps_a: MPS, mps_b: MPS, K=None, *, log_k=None, renorm_every: int =
               sweep: int = SWEEP_AUTO, rows=None, variant: int = 0, refine_above: float = 0.0, stream=None):
     """K[i, j] = |<psi(b_j)|psi(a_i)>|^2 (CUDA float64, Na x Nb).  Returns K.
     refine_above: tiles with an entry above it are recomputed in FP64 (0 =
-    default 1e-3, negative = off)."""
+    automatic from n_qubits, negative = off)."""
     import torch
 
     lib = load_library()

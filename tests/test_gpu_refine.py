@@ -2,9 +2,9 @@
 
 The FP32 sweep's error in K is relative and biased low: at 784 qubits an
 entry near 1 (a self-overlap, a near-duplicate pair) comes out 1e-5 or more
-below its exact value (reps 2 to 4).  With refinement (the default, threshold 1e-3) every
-tile holding such an entry is recomputed with an FP64 environment from FP64
-generators.  Bars: refined entries within 1e-9 of the FP64 oracle (its own
+below its exact value (reps 2 to 4).  With refinement (the default: an
+automatic threshold from n, 0.064 at 784 qubits) every tile holding such an
+entry is recomputed with an FP64 environment from FP64 generators.  Bars: refined entries within 1e-9 of the FP64 oracle (its own
 error is ~1e-12), every entry within the 1e-5 contract; untouched tiles are
 bitwise what the FP32 sweep wrote."""
 
@@ -51,16 +51,33 @@ def test_self_overlaps_784_qubits_are_exact(reps):
 def test_near_duplicates_784_qubits_vs_oracle(reps, n_base):
     base, Xp, _, _ = synth.image_near_duplicates(seed=31, n_base=n_base)  # n_base x 5 n_base pairs, K up to ~1
     ma, mb = encode(base, reps), encode(Xp, reps)
-    K = qsvm.qsvm_gram(ma, mb).cpu().numpy()
+    K_auto = qsvm.qsvm_gram(ma, mb).cpu().numpy()  # automatic threshold: 0.064 at 784 qubits
+    K_1e3 = qsvm.qsvm_gram(ma, mb, refine_above=1e-3).cpu().numpy()
     Sa = omps.mps_states(base, reps, processes=5)
     Sb = omps.mps_states(Xp, reps, processes=5)
     ii, jj = np.meshgrid(np.arange(base.shape[0]), np.arange(Xp.shape[0]), indexing="ij")
     _, kk = omps.mps_gram_pairs(Sa, Sb, ii.ravel(), jj.ravel())
-    d = np.abs(K.ravel() - kk)
-    big = kk > 1e-3
-    assert big.sum() >= n_base
-    assert d[big].max() <= REFINED_TOL
-    assert d.max() <= K_ABS_TOL
+    assert (kk > 0.1).sum() >= n_base
+    d = np.abs(K_1e3.ravel() - kk)
+    assert d[kk > 1e-3].max() <= REFINED_TOL  # every entry above the threshold is refined
+    d = np.abs(K_auto.ravel() - kk)
+    assert d[kk > 0.1].max() <= REFINED_TOL
+    assert d.max() <= 5e-6  # the automatic threshold's budget for entries left in FP32
+
+
+def test_no_refinement_where_the_fp32_error_is_small():
+    # 16 qubits: the FP32 error (< 4.3e-6 at K = 1) needs no refinement, so
+    # the automatic threshold skips it and the result equals refine_above < 0
+    import torch
+
+    m = encode(synth.uniform_features(300, 16, seed=43), 2)
+    K = qsvm.qsvm_gram_sym(m, diag_mode=1).cpu().numpy()
+    K32 = qsvm.qsvm_gram_sym(m, diag_mode=1, refine_above=-1.0).cpu().numpy()
+    K64 = qsvm.qsvm_gram_sym(m, diag_mode=1, refine_above=1e-3).cpu().numpy()
+    torch.cuda.synchronize()
+    assert np.array_equal(K, K32)
+    assert np.max(np.abs(np.diag(K64) - 1.0)) <= REFINED_TOL
+    assert np.max(np.abs(K - K64)) <= 5e-6
 
 
 def test_every_variant_and_the_dense_sweep_agree_after_refinement():
@@ -74,7 +91,7 @@ def test_every_variant_and_the_dense_sweep_agree_after_refinement():
     for K in Ks[1:]:
         assert np.array_equal(K, Ks[0])
     Kd = qsvm.qsvm_gram_sym(m, sweep=qsvm.SWEEP_DENSE).cpu().numpy()
-    big = Ks[0] > 1e-3
+    big = Ks[0] > 0.1  # above the automatic threshold at 784 qubits (0.064): always refined
     # refined tiles: both sweeps end in the same FP64 recomputation
     assert np.max(np.abs(Kd[big] - Ks[0][big])) <= REFINED_TOL
     assert np.max(np.abs(Kd - Ks[0])) <= K_ABS_TOL
