@@ -227,14 +227,32 @@ refine_kernel(SweepArgs a, const uint32_t* __restrict__ list, const uint32_t* __
     dinit_env<R>(v);
     int32_t acc = 0;
     int countdown = a.renorm_every;
-    for (int k = 1; k < a.n; ++k) {
-      const Gen64 cx = gen64(gA, lA, int64_t(k) * a.Na + ic);
-      const Gen64 cy = gen64(gB, lB, int64_t(k) * a.Nb + jc);
+    auto step = [&](const Gen64& cx, const Gen64& cy) {
       dsite_step<R>(v, cx, cy);
       if (--countdown == 0) {
         acc += drenorm(v);
         countdown = a.renorm_every;
       }
+    };
+    // generators of site k (clamped to the last site, so a prefetch past the
+    // end stays in bounds); two sites per iteration with ping-pong registers
+    // so each site's loads are issued one site ahead
+    auto load = [&](int k, Gen64& cx, Gen64& cy) {
+      const int64_t kc = (k < a.n) ? k : a.n - 1;
+      cx = gen64(gA, lA, kc * a.Na + ic);
+      cy = gen64(gB, lB, kc * a.Nb + jc);
+    };
+    if (a.n > 1) {
+      Gen64 cxA, cyA, cxB, cyB;
+      load(1, cxA, cyA);
+      int k = 1;
+      for (; k + 1 < a.n; k += 2) {
+        load(k + 1, cxB, cyB);
+        step(cxA, cyA);
+        load(k + 2, cxA, cyA);
+        step(cxB, cyB);
+      }
+      if (k < a.n) step(cxA, cyA);  // last site when n - 1 is odd
     }
     if (comp) {
       const Gen64 gx = gen64(gA, lA, ic), gy = gen64(gB, lB, jc);
