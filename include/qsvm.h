@@ -42,8 +42,15 @@
  *     floor((2^24 - 8) / b) with b = 16 blocks per tile (32 for the reps = 4
  *     sweep, 1 for the state-vector Gram), i.e. Nb below about 2^26 (2^25,
  *     2^30).  Larger Nb is QSVM_ERR_UNSUPPORTED.
+ *   - Precision: the sweep carries the environment in FP32 with an exact
+ *     power-of-two log scale and forms |amp|^2 in FP64; every 64 x 64 tile
+ *     holding an entry above an n-dependent threshold is then recomputed
+ *     with an FP64 environment (qsvm_gram_opts.refine_above), so entries
+ *     left in FP32 stay within ~5e-6 of the exact kernel and refined ones
+ *     within ~1e-12.
  *   - No call throws across the ABI.  Results are bitwise reproducible for the
- *     same inputs, arguments and device (no floating-point atomics).
+ *     same inputs, arguments and device (no floating-point atomics; the
+ *     integer atomics that collect tile lists only order independent work).
  */
 #ifndef QSVM_H
 #define QSVM_H
@@ -164,7 +171,8 @@ size_t qsvm_mps_bytes(int64_t N, int32_t n_qubits, int32_t reps);
  *   mps        device output buffer of at least qsvm_mps_bytes(N, n, reps)
  *              bytes, 16-byte aligned; layout above.
  *   mps_bytes  size of that buffer; smaller than needed -> QSVM_ERR_SIZE.
- * Phases are formed and reduced in FP64 and rounded once to FP32.
+ * Phases are formed and reduced in FP64 and rounded once to FP32 (Sections D
+ * and G); Section L keeps the rounding residual of each generator.
  */
 qsvm_status qsvm_encode_mps(const double* X, int64_t N, int32_t n_qubits, int32_t reps,
                             void* mps, size_t mps_bytes, void* stream);
@@ -178,7 +186,8 @@ qsvm_status qsvm_encode_mps(const double* X, int64_t N, int32_t n_qubits, int32_
  *   K             device Na x Nb float64, row stride ldk >= Nb (elements).
  *   opts          NULL or settings above (diag_mode is ignored).
  * The environment is carried in FP32 with power-of-two renormalisation into
- * an integer log2 scale; the final modulus squared is formed in FP64.
+ * an integer log2 scale; the final modulus squared is formed in FP64, and
+ * tiles with large entries are recomputed in FP64 (opts->refine_above).
  */
 qsvm_status qsvm_gram(const void* mps_a, int64_t Na, const void* mps_b, int64_t Nb,
                       int32_t n_qubits, int32_t reps, double* K, int64_t ldk,
@@ -229,8 +238,9 @@ typedef struct {
 typedef struct {
   int32_t renorm_every; /* as in qsvm_gram_opts; 0 = default */
   int32_t diag_mode;    /* as in qsvm_gram_opts, for every job */
-  int32_t use_graph;    /* 1: capture the launch (counter reset + persistent kernel)
-                           into a hipGraph at plan creation and replay it */
+  int32_t use_graph;    /* 1: capture the launch (counter reset + persistent kernel
+                           + each job's refinement launches) into a hipGraph at
+                           plan creation and replay it */
   int32_t grid_blocks;  /* persistent blocks, at most 2^24 - 8; 0 = compute units x resident blocks
                            per unit */
   double refine_above;  /* as in qsvm_gram_opts: after the persistent sweep, each
@@ -244,16 +254,18 @@ typedef struct qsvm_batch_plan qsvm_batch_plan; /* opaque */
 /*
  * Build a plan for n_jobs jobs on the current device: validates every job
  * (errors name the job), orders the work queue, allocates and uploads the
- * job table and the queue counter (hipMalloc + a synchronous copy: call this
- * at set-up, not in a timed loop), and captures the graph if asked.  The
+ * job table, the queue counter and the refinement's tile list (hipMalloc + a
+ * synchronous copy: call this at set-up, not in a timed loop), and captures
+ * the graph if asked.  The
  * jobs' buffers must stay valid for every later launch.  *plan = NULL on error.
  */
 qsvm_status qsvm_batch_plan_create(const qsvm_job* jobs, int32_t n_jobs, const qsvm_batch_opts* opts,
                                    qsvm_batch_plan** plan);
 
-/* Enqueue one execution of the plan on `stream` (graph launch or the two
- * kernels).  Launches of one plan share its queue counter: keep them ordered
- * on one stream. */
+/* Enqueue one execution of the plan on `stream` (graph launch, or the
+ * counter reset, the persistent kernel and each job's refinement launches).
+ * Launches of one plan share its queue counter and tile list: keep them
+ * ordered on one stream. */
 qsvm_status qsvm_batch_plan_launch(qsvm_batch_plan* plan, void* stream);
 
 /* Wait for the plan's last launch, then free it (NULL is a no-op). */
