@@ -150,3 +150,22 @@ def test_batch_plan_is_refined_like_one_launch_per_job():
             assert np.array_equal(K.cpu().numpy(), R)
     plan.close()
     assert np.max(np.abs(np.diag(ref[0]) - 1.0)) <= REFINED_TOL
+
+
+def test_refined_entries_carry_log_k_and_respect_ldk_padding():
+    import torch
+
+    base, Xp, _, _ = synth.image_near_duplicates(seed=45, n_base=24)
+    ma, mb = encode(base, 2), encode(Xp[:70], 2)  # 24 x 70, rows padded to ldk = 96
+    Kp = torch.full((24, 96), -5.0, dtype=torch.float64, device="cuda:0")
+    Lp = torch.full((24, 96), -5.0, dtype=torch.float64, device="cuda:0")
+    K, L = Kp[:, :70], Lp[:, :70]
+    qsvm.qsvm_gram(ma, mb, K, log_k=L, refine_above=1e-3)
+    ref = qsvm.qsvm_gram(ma, mb, refine_above=1e-3).cpu().numpy()
+    torch.cuda.synchronize()
+    Kh, Lh = K.cpu().numpy(), L.cpu().numpy()
+    assert np.array_equal(Kh, ref)
+    assert np.all(Kp.cpu().numpy()[:, 70:] == -5.0) and np.all(Lp.cpu().numpy()[:, 70:] == -5.0)
+    big = Kh > 1e-3
+    assert big.sum() >= 24
+    assert np.max(np.abs(Lh[big] - np.log(Kh[big]))) <= 1e-12  # log K written by the FP64 pass too
