@@ -177,6 +177,12 @@ size_t qsvm_mps_bytes(int64_t N, int32_t n_qubits, int32_t reps);
 qsvm_status qsvm_encode_mps(const double* X, int64_t N, int32_t n_qubits, int32_t reps,
                             void* mps, size_t mps_bytes, void* stream);
 
+/* The threshold qsvm_gram_opts.refine_above = 0 selects for n_qubits:
+ * (5e-6 / (4e-6 + 2e-8 n))^2; a value >= 1 means no entry needs refining and
+ * the Gram calls skip the refinement (n <= 50).  0 for n_qubits < 1.  No HIP
+ * call. */
+double qsvm_auto_refine_threshold(int32_t n_qubits);
+
 /*
  * Rectangular Gram: K[i*ldk + j] = |<psi(b_j)|psi(a_i)>|^2 for i < Na, j < Nb
  * (Alg. 2 over the index set of all (i, j); no symmetrisation, since the

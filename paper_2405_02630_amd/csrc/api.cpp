@@ -220,6 +220,10 @@ qsvm_status qsvm_encode_mps(const double* X, int64_t N, int32_t n_qubits, int32_
   return hip_status(qsvm::launch_encode(X, N, n_qubits, reps, mps, static_cast<hipStream_t>(stream)), what);
 }
 
+double qsvm_auto_refine_threshold(int32_t n_qubits) {
+  return n_qubits < 1 ? 0.0 : qsvm::auto_refine_threshold(n_qubits);
+}
+
 qsvm_status qsvm_gram(const void* mps_a, int64_t Na, const void* mps_b, int64_t Nb, int32_t n_qubits,
                       int32_t reps, double* K, int64_t ldk, const qsvm_gram_opts* opts, void* stream) {
   const char* what = "qsvm_gram";

@@ -121,6 +121,8 @@ def load_library(path: str = LIB_PATH):
     lib.qsvm_mps_bytes.restype = sz
     lib.qsvm_encode_mps.argtypes = [vp, i64, i32, i32, vp, sz, vp]
     lib.qsvm_encode_mps.restype = i32
+    lib.qsvm_auto_refine_threshold.argtypes = [i32]
+    lib.qsvm_auto_refine_threshold.restype = ctypes.c_double
     lib.qsvm_gram.argtypes = [vp, i64, vp, i64, i32, i32, vp, i64, ctypes.POINTER(GramOpts), vp]
     lib.qsvm_gram.restype = i32
     lib.qsvm_gram_sym.argtypes = [vp, i64, i32, i32, vp, i64, ctypes.POINTER(GramOpts), vp]
@@ -268,6 +270,11 @@ def _opts(renorm_every, sweep, diag_mode, rows, log_k, variant=0, refine_above=0
         o.row_begin, o.row_end = int(rows[0]), int(rows[1])
     o.log_k = None if log_k is None else log_k.data_ptr()
     return o
+
+
+def qsvm_auto_refine_threshold(n_qubits: int) -> float:
+    """Threshold of the automatic FP64 refinement for n_qubits (>= 1: none)."""
+    return float(load_library().qsvm_auto_refine_threshold(n_qubits))
 
 
 def qsvm_gram(mps_a: MPS, mps_b: MPS, K=None, *, log_k=None, renorm_every: int = 0,

@@ -137,6 +137,17 @@ def test_gram_rejects_a_tile_row_wider_than_one_launch(lib, no_inject, reps, nb_
     assert b"exceeds one launch" in lib.qsvm_last_error()
 
 
+@pytest.mark.parametrize("n,expect", [(1, None), (50, None), (51, 0.992), (64, 0.897), (784, 0.0645), (65535, 1.4464e-5)])
+def test_auto_refine_threshold(n, expect):
+    # (5e-6 / (4e-6 + 2e-8 n))^2: >= 1 (no refinement) up to 50 qubits
+    t = qsvm.qsvm_auto_refine_threshold(n)
+    if expect is None:
+        assert t >= 1.0
+    else:
+        assert t == pytest.approx(expect, rel=2e-3)
+    assert qsvm.qsvm_auto_refine_threshold(0) == 0.0
+
+
 def test_refine_above_nan_is_rejected(lib, no_inject):
     o = qsvm.GramOpts()
     o.refine_above = float("nan")
