@@ -265,6 +265,7 @@ def surrogate_leg(args, exact_rate):
         _, flagged = sur.gram(X, mps_all, K=Kall)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
+    flagged = int(flagged.item())
     sur_s = float(np.median(times))
     T = (N + 63) // 64
     # judge on the held-out pairs against their exact Gram

@@ -222,6 +222,22 @@ qsvm_status qsvm_gram_sym(const void* mps, int64_t N, int32_t n_qubits, int32_t 
 qsvm_status qsvm_gram_sym_tiles(const void* mps, int64_t N, int32_t n_qubits, int32_t reps, const int32_t* tiles,
                                 int64_t n_tiles, double* K, int64_t ldk, const qsvm_gram_opts* opts, void* stream);
 
+/*
+ * qsvm_gram_sym_tiles with the list length in device memory: the number of
+ * listed tiles is *tile_count (device int32, e.g. written by qsvm_flag_tiles
+ * earlier on the same stream), read by the kernels when they run and clamped
+ * to [0, max_tiles]; `tiles` holds room for max_tiles pairs.  The host never
+ * reads the count, so a flag-then-recompute sequence (the surrogate's exact
+ * fallback) needs no synchronisation between its steps.  Results equal qsvm_gram_sym_tiles over the
+ * first *tile_count entries, bit for bit.  Butterfly sweep only (reps 1..3;
+ * otherwise QSVM_ERR_UNSUPPORTED), max_tiles <= 2^24 - 8 (QSVM_ERR_UNSUPPORTED
+ * above).  One persistent launch of the resident blocks strides over the
+ * listed tiles, followed by the refinement of opts->refine_above.
+ */
+qsvm_status qsvm_gram_sym_tiles_dev(const void* mps, int64_t N, int32_t n_qubits, int32_t reps, const int32_t* tiles,
+                                    const int32_t* tile_count, int64_t max_tiles, double* K, int64_t ldk,
+                                    const qsvm_gram_opts* opts, void* stream);
+
 /* ------------------------------------------------------------------------
  * Batched jobs: many independent symmetric Grams in one persistent launch.
  * Every job is cut into the work items of the single-Gram sweep, the items of

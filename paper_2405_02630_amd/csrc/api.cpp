@@ -187,6 +187,63 @@ qsvm_status run_gram(const void* mps_a, int64_t Na, const void* mps_b, int64_t N
   return hip_status(e, what);
 }
 
+// Symmetric Gram over a list of (ti, tj) tiles: n_tiles entries, or, with
+// tile_count, at most n_tiles entries, the count read on the device.
+qsvm_status gram_tile_list(const void* mps, int64_t N, int32_t n_qubits, int32_t reps, const int32_t* tiles,
+                           const int32_t* tile_count, int64_t n_tiles, double* K, int64_t ldk,
+                           const qsvm_gram_opts* opts, void* stream, const char* what) {
+  qsvm_status s = check_shape(N, n_qubits, reps, what);
+  if (s != QSVM_OK) return s;
+  if (!mps || !K || !tiles) return fail(QSVM_ERR_INVALID_ARG, "%s: mps, tiles or K is NULL", what);
+  if (ldk < N) return fail(QSVM_ERR_INVALID_ARG, "%s: ldk = %lld < N = %lld", what, (long long)ldk, (long long)N);
+  if (reinterpret_cast<uintptr_t>(mps) % 16 != 0) return fail(QSVM_ERR_INVALID_ARG, "%s: mps is not 16-byte aligned", what);
+  const int64_t T = (N + qsvm::kTile - 1) / qsvm::kTile;
+  if (n_tiles < 0 || n_tiles > T * (T + 1) / 2)
+    return fail(QSVM_ERR_INVALID_ARG, "%s: n_tiles = %lld outside [0, %lld]", what, (long long)n_tiles, (long long)(T * (T + 1) / 2));
+  if (n_tiles > INT32_MAX)
+    return fail(QSVM_ERR_UNSUPPORTED, "%s: n_tiles = %lld above 2^31-1", what, (long long)n_tiles);
+  Opts o;
+  s = read_opts(opts, N, o, what);
+  if (s != QSVM_OK) return s;
+  if (o.row_begin != 0 || o.row_end != N) return fail(QSVM_ERR_INVALID_ARG, "%s: row ranges do not apply to tile lists", what);
+  if (o.sweep == QSVM_SWEEP_DENSE && reps > 3)
+    return fail(QSVM_ERR_UNSUPPORTED, "%s: the dense sweep supports reps <= 3", what);
+  if (tile_count) {
+    if (o.sweep == QSVM_SWEEP_DENSE || reps > 3)
+      return fail(QSVM_ERR_UNSUPPORTED, "%s: a device-resident tile count needs the butterfly sweep (reps <= 3)", what);
+    if (n_tiles > qsvm::kMaxGridBlocks)
+      return fail(QSVM_ERR_UNSUPPORTED, "%s: max_tiles = %lld above %lld", what, (long long)n_tiles,
+                  (long long)qsvm::kMaxGridBlocks);
+  }
+  if (n_tiles == 0) return ok();
+  if (injected_launch_failure()) return fail(QSVM_ERR_HIP, "%s: injected launch failure (QSVM_FAULT_INJECT=launch)", what);
+  qsvm::SweepArgs a{};
+  a.gen_a = a.gen_b = reinterpret_cast<const float4*>(static_cast<const char*>(mps) + qsvm::dense_bytes(N, n_qubits, reps));
+  a.dense_a = a.dense_b = static_cast<const float2*>(mps);
+  a.K = K;
+  a.log_k = o.log_k;
+  a.Na = a.Nb = N;
+  a.ldk = ldk;
+  a.row_begin = 0;
+  a.row_end = N;
+  a.n = n_qubits;
+  a.renorm_every = o.renorm_every;
+  a.sym = 1;
+  a.diag_mode = o.diag_mode;
+  a.tile_row0 = 0;
+  a.tile_rows = int32_t(n_tiles);  // list length (capacity when the count is on the device)
+  a.tiles_b = int32_t(T);
+  a.tile_list = tiles;
+  a.tile_count = tile_count;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int32_t variant = pick_variant(o, reps, n_qubits);
+  hipError_t e = tile_count                      ? qsvm::launch_sweep_butterfly_counted(a, reps, variant, st)
+                 : (o.sweep == QSVM_SWEEP_DENSE) ? qsvm::launch_sweep_dense_args(a, reps, st)
+                                                 : qsvm::launch_sweep_fast(a, reps, variant, st);
+  if (e == hipSuccess) e = refine_tiles(a, reps, o.refine_above, st);
+  return hip_status(e, what);
+}
+
 }  // namespace
 
 namespace qsvm {
@@ -260,45 +317,15 @@ qsvm_status qsvm_gram_sym(const void* mps, int64_t N, int32_t n_qubits, int32_t 
 
 qsvm_status qsvm_gram_sym_tiles(const void* mps, int64_t N, int32_t n_qubits, int32_t reps, const int32_t* tiles,
                                 int64_t n_tiles, double* K, int64_t ldk, const qsvm_gram_opts* opts, void* stream) {
-  const char* what = "qsvm_gram_sym_tiles";
-  qsvm_status s = check_shape(N, n_qubits, reps, what);
-  if (s != QSVM_OK) return s;
-  if (!mps || !K || !tiles) return fail(QSVM_ERR_INVALID_ARG, "%s: mps, tiles or K is NULL", what);
-  if (ldk < N) return fail(QSVM_ERR_INVALID_ARG, "%s: ldk = %lld < N = %lld", what, (long long)ldk, (long long)N);
-  if (reinterpret_cast<uintptr_t>(mps) % 16 != 0) return fail(QSVM_ERR_INVALID_ARG, "%s: mps is not 16-byte aligned", what);
-  const int64_t T = (N + qsvm::kTile - 1) / qsvm::kTile;
-  if (n_tiles < 0 || n_tiles > T * (T + 1) / 2)
-    return fail(QSVM_ERR_INVALID_ARG, "%s: n_tiles = %lld outside [0, %lld]", what, (long long)n_tiles, (long long)(T * (T + 1) / 2));
-  Opts o;
-  s = read_opts(opts, N, o, what);
-  if (s != QSVM_OK) return s;
-  if (o.row_begin != 0 || o.row_end != N) return fail(QSVM_ERR_INVALID_ARG, "%s: row ranges do not apply to tile lists", what);
-  if (o.sweep == QSVM_SWEEP_DENSE && reps > 3)
-    return fail(QSVM_ERR_UNSUPPORTED, "%s: the dense sweep supports reps <= 3", what);
-  if (n_tiles == 0) return ok();
-  if (injected_launch_failure()) return fail(QSVM_ERR_HIP, "%s: injected launch failure (QSVM_FAULT_INJECT=launch)", what);
-  qsvm::SweepArgs a{};
-  a.gen_a = a.gen_b = reinterpret_cast<const float4*>(static_cast<const char*>(mps) + qsvm::dense_bytes(N, n_qubits, reps));
-  a.dense_a = a.dense_b = static_cast<const float2*>(mps);
-  a.K = K;
-  a.log_k = o.log_k;
-  a.Na = a.Nb = N;
-  a.ldk = ldk;
-  a.row_begin = 0;
-  a.row_end = N;
-  a.n = n_qubits;
-  a.renorm_every = o.renorm_every;
-  a.sym = 1;
-  a.diag_mode = o.diag_mode;
-  a.tile_row0 = 0;
-  a.tile_rows = int32_t(n_tiles);  // list length
-  a.tiles_b = int32_t(T);
-  a.tile_list = tiles;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  hipError_t e = (o.sweep == QSVM_SWEEP_DENSE) ? qsvm::launch_sweep_dense_args(a, reps, st)
-                                                : qsvm::launch_sweep_fast(a, reps, pick_variant(o, reps, n_qubits), st);
-  if (e == hipSuccess) e = refine_tiles(a, reps, o.refine_above, st);
-  return hip_status(e, what);
+  return gram_tile_list(mps, N, n_qubits, reps, tiles, nullptr, n_tiles, K, ldk, opts, stream, "qsvm_gram_sym_tiles");
+}
+
+qsvm_status qsvm_gram_sym_tiles_dev(const void* mps, int64_t N, int32_t n_qubits, int32_t reps, const int32_t* tiles,
+                                    const int32_t* tile_count, int64_t max_tiles, double* K, int64_t ldk,
+                                    const qsvm_gram_opts* opts, void* stream) {
+  const char* what = "qsvm_gram_sym_tiles_dev";
+  if (!tile_count) return fail(QSVM_ERR_INVALID_ARG, "%s: tile_count is NULL", what);
+  return gram_tile_list(mps, N, n_qubits, reps, tiles, tile_count, max_tiles, K, ldk, opts, stream, what);
 }
 
 qsvm_status qsvm_autotune(int32_t reps, int32_t n_qubits, int64_t N, void* stream, int32_t* best_variant,

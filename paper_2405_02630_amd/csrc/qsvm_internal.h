@@ -33,6 +33,9 @@ constexpr int32_t kDefaultRenorm = 8;
 constexpr int32_t kMaxRenorm = 16;
 constexpr int32_t kMaxReps = 4;        // chi = 16
 hipError_t launch_sweep_butterfly_args(const SweepArgs& a, int32_t reps, int32_t variant, hipStream_t stream);
+// Butterfly sweep (reps 1..3) over a tile list whose length a.tile_count
+// holds in device memory: one persistent launch, no host read of the count.
+hipError_t launch_sweep_butterfly_counted(const SweepArgs& a, int32_t reps, int32_t variant, hipStream_t stream);
 // reps = 4: the environment split across two lanes (sweep_split.hip).
 hipError_t launch_sweep_split_args(const SweepArgs& a, int32_t reps, int32_t variant, hipStream_t stream);
 // The fast (Section G) sweep for any supported reps.

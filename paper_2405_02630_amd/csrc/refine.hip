@@ -28,6 +28,8 @@
 namespace qsvm {
 namespace {
 
+constexpr int64_t kScanBlocksDeviceCount = 4096;  // scan grid when the list length is on the device
+
 template <int R>
 struct DLayout {
   static constexpr int NB = 2 * R - 1;
@@ -179,7 +181,7 @@ __global__ void refine_reset(uint32_t* count) {
 __global__ void __launch_bounds__(256)
 refine_scan_kernel(SweepArgs a, double thresh, uint32_t* __restrict__ list, uint32_t* __restrict__ count) {
   __shared__ double red[4];
-  const uint32_t tiles = uint32_t(launch_tiles(a));
+  const uint32_t tiles = uint32_t(device_tiles(a));
   for (uint32_t u = blockIdx.x; u < tiles; u += gridDim.x) {  // block-uniform
     int32_t ti, tj;
     const bool valid = decode_tile(a, u, ti, tj);
@@ -392,7 +394,10 @@ hipError_t launch_refine(const SweepArgs& a, int32_t reps, double thresh, uint32
   hipLaunchKernelGGL(refine_reset, dim3(1), dim3(64), 0, stream, count);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int64_t scan_blocks = tiles < kMaxGridBlocks ? tiles : kMaxGridBlocks / 8 * 8;
+  // a list whose length is read on the device may hold far fewer tiles than
+  // its capacity: a bounded grid strides over whatever it holds
+  const int64_t scan_cap = a.tile_count ? kScanBlocksDeviceCount : kMaxGridBlocks / 8 * 8;
+  const int64_t scan_blocks = tiles < scan_cap ? tiles : scan_cap;
   hipLaunchKernelGGL(refine_scan_kernel, dim3(unsigned(scan_blocks)), dim3(256), 0, stream, a, thresh, list, count);
   e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -2,6 +2,8 @@
 // sweep_butterfly_item.h): one grid over the tiles of one Gram, blocks mapped
 // XCD-aware, with the kernel variants the autotuner chooses among.
 
+#include <atomic>
+
 #include "sweep_butterfly_item.h"
 
 namespace qsvm {
@@ -37,6 +39,66 @@ hipError_t launch_pi(const SweepArgs& a0, hipStream_t stream) {
   });
 }
 
+// Persistent form for a tile list whose length is read on the device
+// (a.tile_count): every block strides over the (tile, block of the tile)
+// items in the XCD-aware order until the listed tiles are done.
+template <int R, int PI, int W>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8)))
+sweep_butterfly_list_kernel(SweepArgs a) {
+  const uint64_t bpt = uint64_t(a.blocks_per_tile);
+  const uint64_t items = uint64_t(device_tiles(a)) * bpt;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (uint64_t L = xcd_logical_block(); L < items; L += gridDim.x) {
+    const uint32_t tile = uint32_t(L / bpt);
+    const uint32_t sub = uint32_t(L % bpt);
+    int32_t ti, tj;
+    if (!decode_tile(a, tile, ti, tj)) continue;
+    const int64_t i0 = int64_t(ti) * kTile + (int64_t(sub) * 4 + wave) * PI;  // wave-uniform
+    butterfly_item<R, PI>(a, i0, int64_t(tj) * kTile);
+  }
+}
+
+// Blocks of the persistent form that fit the device at once (cached per
+// device and kernel variant), a multiple of 8 for the XCD-aware order.
+template <int R, int PI, int W>
+hipError_t list_grid(int64_t* out) {
+  static std::atomic<int64_t> cache[64];  // zero-initialised (static storage)
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev >= 0 && dev < 64) {
+    const int64_t v = cache[dev].load(std::memory_order_relaxed);
+    if (v > 0) {
+      *out = v;
+      return hipSuccess;
+    }
+  }
+  int cus = 0, per_cu = 0;
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sweep_butterfly_list_kernel<R, PI, W>, 256, 0);
+  if (e != hipSuccess) return e;
+  int64_t g = int64_t(cus > 0 ? cus : 1) * (per_cu > 0 ? per_cu : 1) / 8 * 8;
+  if (g < 8) g = 8;
+  if (dev >= 0 && dev < 64) cache[dev].store(g, std::memory_order_relaxed);
+  *out = g;
+  return hipSuccess;
+}
+
+template <int R, int PI, int W>
+hipError_t launch_list_pi(const SweepArgs& a0, hipStream_t stream) {
+  SweepArgs a = a0;
+  a.blocks_per_tile = kTile / (4 * PI);
+  int64_t grid = 0;
+  hipError_t e = list_grid<R, PI, W>(&grid);
+  if (e != hipSuccess) return e;
+  const int64_t most = launch_tiles(a) * a.blocks_per_tile;  // the list's capacity in blocks
+  if (most <= 0) return hipSuccess;
+  if (grid > most) grid = (most + 7) / 8 * 8;
+  a.num_blocks = uint32_t(grid);
+  hipLaunchKernelGGL((sweep_butterfly_list_kernel<R, PI, W>), dim3(unsigned(grid)), dim3(256), 0, stream, a);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 // Kernel variants (ket points per lane PI, target waves per SIMD W); all
@@ -56,6 +118,30 @@ hipError_t launch_sweep_butterfly_args(const SweepArgs& a, int32_t reps, int32_t
     case 48 + 1: return launch_pi<3, 2, 2>(a, stream);
     case 48 + 2: return launch_pi<3, 1, 3>(a, stream);
     case 48 + 3: return launch_pi<3, 1, 4>(a, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace qsvm
+
+namespace qsvm {
+
+// The same variants over a tile list of device-resident length.
+hipError_t launch_sweep_butterfly_counted(const SweepArgs& a, int32_t reps, int32_t variant, hipStream_t stream) {
+  if (!a.tile_list || !a.tile_count) return hipErrorInvalidValue;
+  switch (reps * 16 + variant) {
+    case 16 + 0: return launch_list_pi<1, 4, 8>(a, stream);
+    case 16 + 1: return launch_list_pi<1, 4, 4>(a, stream);
+    case 16 + 2: return launch_list_pi<1, 8, 4>(a, stream);
+    case 16 + 3: return launch_list_pi<1, 8, 2>(a, stream);
+    case 32 + 0: return launch_list_pi<2, 2, 4>(a, stream);
+    case 32 + 1: return launch_list_pi<2, 4, 4>(a, stream);
+    case 32 + 2: return launch_list_pi<2, 4, 2>(a, stream);
+    case 32 + 3: return launch_list_pi<2, 2, 8>(a, stream);
+    case 48 + 0: return launch_list_pi<3, 1, 2>(a, stream);
+    case 48 + 1: return launch_list_pi<3, 2, 2>(a, stream);
+    case 48 + 2: return launch_list_pi<3, 1, 3>(a, stream);
+    case 48 + 3: return launch_list_pi<3, 1, 4>(a, stream);
     default: return hipErrorInvalidValue;
   }
 }

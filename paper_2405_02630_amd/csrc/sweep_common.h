@@ -31,6 +31,8 @@ struct SweepArgs {
   int32_t blocks_per_tile;
   uint32_t num_blocks;   // logical blocks (before padding to a multiple of 8)
   const int32_t* tile_list;  // optional device list of (ti, tj) tiles (symmetric only)
+  const int32_t* tile_count; // optional: with tile_list, the list length is read here on the
+                             // device, clamped to [0, tile_rows] (tile_rows = the list capacity)
 };
 
 // Tiles one launch covers: the list length, the upper triangle of the row
@@ -41,6 +43,15 @@ __host__ __device__ inline int64_t launch_tiles(const SweepArgs& a) {
     return int64_t(a.tile_rows) * a.tiles_b - (int64_t(a.tile_rows) * (a.tile_rows - 1)) / 2 -
            int64_t(a.tile_rows) * a.tile_row0;
   return int64_t(a.tile_rows) * a.tiles_b;
+}
+
+// Tiles of the launch as the device sees them: launch_tiles, or the listed
+// count when the list length lives in device memory.
+__device__ __forceinline__ int64_t device_tiles(const SweepArgs& a) {
+  const int64_t t = launch_tiles(a);
+  if (!a.tile_count) return t;
+  const int64_t c = *a.tile_count;
+  return c < 0 ? 0 : (c < t ? c : t);
 }
 
 // A dispatch carries its grid size in work-items as a 32-bit number, so one

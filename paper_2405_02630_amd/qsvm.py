@@ -145,6 +145,8 @@ def load_library(path: str = LIB_PATH):
     f32 = ctypes.c_float
     lib.qsvm_gram_sym_tiles.argtypes = [vp, i64, i32, i32, vp, i64, vp, i64, P(GramOpts), vp]
     lib.qsvm_gram_sym_tiles.restype = i32
+    lib.qsvm_gram_sym_tiles_dev.argtypes = [vp, i64, i32, i32, vp, vp, i64, vp, i64, P(GramOpts), vp]
+    lib.qsvm_gram_sym_tiles_dev.restype = i32
     lib.qsvm_gather_features.argtypes = [vp, i64, i32, vp, i64, i32, vp, vp]
     lib.qsvm_gather_features.restype = i32
     lib.qsvm_mlp_forward.argtypes = [P(Mlp), vp, i64, P(MlpActs), vp]
@@ -460,6 +462,17 @@ def qsvm_gram_sym_tiles(mps: MPS, tiles, n_tiles: int, K, *, log_k=None, renorm_
     _check(load_library().qsvm_gram_sym_tiles(
         _device_ptr(mps.buf, "mps"), mps.N, mps.n, mps.reps, _p(tiles), n_tiles, _p(K), K.stride(0),
         ctypes.byref(o), _stream_ptr(stream)))
+    return K
+
+
+def qsvm_gram_sym_tiles_dev(mps: MPS, tiles, tile_count, max_tiles: int, K, *, log_k=None, renorm_every: int = 0,
+                            diag_mode: int = 0, variant: int = 0, refine_above: float = 0.0, stream=None):
+    """qsvm_gram_sym_tiles with the list length in device memory (tile_count:
+    1-element int32 tensor, read by the kernels, clamped to [0, max_tiles])."""
+    o = _opts(renorm_every, SWEEP_AUTO, diag_mode, None, log_k, variant, refine_above)
+    _check(load_library().qsvm_gram_sym_tiles_dev(
+        _device_ptr(mps.buf, "mps"), mps.N, mps.n, mps.reps, _p(tiles), _p(tile_count), max_tiles, _p(K),
+        K.stride(0), ctypes.byref(o), _stream_ptr(stream)))
     return K
 
 

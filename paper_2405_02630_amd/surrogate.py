@@ -213,8 +213,7 @@ class Surrogate:
         for r0 in range(0, Np, chunk):
             rows = min(chunk, Np - r0)
             b = self._buffers(rows)
-            idx = np.arange(r0, r0 + rows, dtype=np.int32)  # rows >= N are zero padding
-            b["idx"].copy_(torch.from_numpy(idx))
+            torch.arange(r0, r0 + rows, out=b["idx"])  # on the device; rows >= N are zero padding
             qsvm.qsvm_gather_features(X, b["idx"], self.d_in, b["X16"])
             qsvm.qsvm_mlp_forward(net, b["X16"], rows, self._acts(b))
             E16[r0:r0 + rows].copy_(b["E16"])
@@ -223,8 +222,10 @@ class Surrogate:
     def gram(self, X, mps: "qsvm.MPS | None", K=None, tau: float | None = None):
         """Surrogate Gram of the rows of X with exact fallback on flagged tiles.
 
-        Returns (K, flagged_tiles).  mps (the exact MPS of the same points) is
-        needed when a tile is flagged; pass None to skip the fallback."""
+        Returns (K, flagged): flagged is a 1-element device int32 tensor, the
+        number of flagged tiles.  mps (the exact MPS of the same points) feeds
+        the fallback; pass None to skip it.  Nothing here waits for the GPU:
+        the fallback reads the flagged count on the device."""
         import torch
 
         tau = self.cfg.tau if tau is None else tau
@@ -237,9 +238,8 @@ class Surrogate:
         tile_max = torch.empty(T * T, dtype=torch.float32, device=self.dev)
         qsvm.qsvm_surrogate_gram(E16, N, self.head.w, K, tile_max)
         tiles = torch.empty(T * (T + 1), dtype=torch.int32, device=self.dev)
-        count = torch.zeros(1, dtype=torch.int32, device=self.dev)
-        qsvm.qsvm_flag_tiles(tile_max, T, tau, tiles, count)
-        n_flag = int(count.item())
-        if n_flag and mps is not None:
-            qsvm.qsvm_gram_sym_tiles(mps, tiles, n_flag, K)
-        return K, n_flag
+        count = torch.empty(1, dtype=torch.int32, device=self.dev)
+        qsvm.qsvm_flag_tiles(tile_max, T, tau, tiles, count)  # clears count first
+        if mps is not None:
+            qsvm.qsvm_gram_sym_tiles_dev(mps, tiles, count, T * (T + 1) // 2, K)
+        return K, count

@@ -168,6 +168,46 @@ def test_dense_sweep_rejects_reps_4(lib, no_inject):
     assert _rect(lib, reps=4, opts=opts) == qsvm.QSVM_ERR_UNSUPPORTED
 
 
+def _tiles(lib, dev, mps=FAKE, N=150, n=8, reps=2, tiles=FAKE2, count=FAKE, n_tiles=3, K=FAKE2, ldk=None,
+           opts=None):
+    ldk = N if ldk is None else ldk
+    if dev:
+        return lib.qsvm_gram_sym_tiles_dev(mps, N, n, reps, tiles, count, n_tiles, K, ldk, opts, None)
+    return lib.qsvm_gram_sym_tiles(mps, N, n, reps, tiles, n_tiles, K, ldk, opts, None)
+
+
+@pytest.mark.parametrize("dev", [False, True])
+def test_tile_list_validation(lib, no_inject, dev):
+    bad = qsvm.QSVM_ERR_INVALID_ARG
+    assert _tiles(lib, dev, mps=None) == bad
+    assert _tiles(lib, dev, tiles=None) == bad
+    assert _tiles(lib, dev, K=None) == bad
+    assert _tiles(lib, dev, ldk=149) == bad
+    assert _tiles(lib, dev, mps=ctypes.c_void_p(0x100008)) == bad
+    assert _tiles(lib, dev, n_tiles=-1) == bad
+    assert _tiles(lib, dev, n_tiles=7) == bad  # 150 points: 3 tile rows, 6 upper-triangular tiles
+    o = qsvm.GramOpts()
+    o.row_begin, o.row_end = 0, 64
+    assert _tiles(lib, dev, opts=o) == bad
+    assert b"row ranges" in lib.qsvm_last_error()
+    assert _tiles(lib, dev, reps=5) == qsvm.QSVM_ERR_UNSUPPORTED
+    assert _tiles(lib, dev, n_tiles=0) == qsvm.QSVM_OK  # nothing to launch
+    assert _tiles(lib, dev, N=(1 << 31) - 1, n_tiles=1 << 31) == qsvm.QSVM_ERR_UNSUPPORTED
+
+
+def test_tile_list_with_device_count_validation(lib, no_inject):
+    assert _tiles(lib, True, count=None) == qsvm.QSVM_ERR_INVALID_ARG
+    assert b"tile_count" in lib.qsvm_last_error()
+    assert _tiles(lib, True, reps=4) == qsvm.QSVM_ERR_UNSUPPORTED
+    assert b"butterfly" in lib.qsvm_last_error()
+    o = qsvm.GramOpts()
+    o.sweep = qsvm.SWEEP_DENSE
+    assert _tiles(lib, True, opts=o) == qsvm.QSVM_ERR_UNSUPPORTED
+    # a list too long for the refinement's one-launch scan of a device count
+    assert _tiles(lib, True, N=370752, n_tiles=1 << 24) == qsvm.QSVM_ERR_UNSUPPORTED
+    assert _tiles(lib, True, N=370752, n_tiles=0) == qsvm.QSVM_OK
+
+
 @pytest.mark.parametrize(
     "field,value",
     [("renorm_every", -1), ("renorm_every", 17), ("sweep", 3), ("sweep", -1), ("diag_mode", 2), ("variant", 5), ("variant", -1)],
