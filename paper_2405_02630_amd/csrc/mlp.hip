@@ -4,7 +4,7 @@
 //
 // * bf16_gemm<TA, TB, EPI>: C = op(A) op(B) on v_mfma_f32_32x32x16_bf16.
 //   A 64 x 64 output tile per block of 4 waves (each wave one 32 x 32
-//   accumulator), K in steps of 32 staged through LDS with both operands
+//   accumulator), K in steps of 64 staged through LDS with both operands
 //   stored k-contiguous so every lane reads its 8 k-values as one 16-byte
 //   LDS load.  Dimensions are multiples of the tile (the host pads), so no
 //   bounds checks are needed.  Fused epilogues: FP32 store; bias + GELU
@@ -39,6 +39,8 @@ typedef float f32x16_t __attribute__((ext_vector_type(16)));
 
 constexpr int BM = 64, BN = 64, BK = 32;
 constexpr int LDS_STRIDE = BK + 8;  // bf16 elements per LDS row (16-byte pad)
+constexpr int GBK = 64;                   // K step of bf16_gemm
+constexpr int GEMM_LDS_STRIDE = GBK + 8;  // its LDS row, 16-byte pad
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
 
@@ -58,12 +60,44 @@ __device__ __forceinline__ float gelu_grad(float x) {
 
 __device__ __forceinline__ float sigmoidf(float z) { return 1.0f / (1.0f + __expf(-z)); }
 
+// Piece p (0..511) of a 64 x 64 step tile of an operand whose rows r0.. pair
+// with K values k0..: 8 consecutive bf16, 8 pieces per row.  KMAJ = 0: the
+// source is k-contiguous (M[r * ld + k]), piece p = row p / 8, k (p % 8) * 8;
+// KMAJ = 1: the source is r-contiguous (M[k * ld + r]), piece p = k p / 8,
+// rows (p % 8) * 8.  The LDS tile is [row][k] with row stride GEMM_LDS_STRIDE.
+template <int KMAJ>
+__device__ __forceinline__ uint4 load_piece(const uint16_t* __restrict__ M, int64_t ld, int64_t r0, int64_t k0, int p) {
+  if (KMAJ == 0) return *reinterpret_cast<const uint4*>(M + (r0 + (p >> 3)) * ld + k0 + (p & 7) * 8);
+  return *reinterpret_cast<const uint4*>(M + (k0 + (p >> 3)) * ld + r0 + (p & 7) * 8);
+}
+
+template <int KMAJ>
+__device__ __forceinline__ void stash_piece(uint16_t* S, uint4 v, int p) {
+  const int a = p >> 3, b = (p & 7) * 8;
+  if (KMAJ == 0) {
+    *reinterpret_cast<uint4*>(&S[a * GEMM_LDS_STRIDE + b]) = v;
+  } else {  // a = k, b = first row: transpose into [row][k]
+    S[(b + 0) * GEMM_LDS_STRIDE + a] = uint16_t(v.x);
+    S[(b + 1) * GEMM_LDS_STRIDE + a] = uint16_t(v.x >> 16);
+    S[(b + 2) * GEMM_LDS_STRIDE + a] = uint16_t(v.y);
+    S[(b + 3) * GEMM_LDS_STRIDE + a] = uint16_t(v.y >> 16);
+    S[(b + 4) * GEMM_LDS_STRIDE + a] = uint16_t(v.z);
+    S[(b + 5) * GEMM_LDS_STRIDE + a] = uint16_t(v.z >> 16);
+    S[(b + 6) * GEMM_LDS_STRIDE + a] = uint16_t(v.w);
+    S[(b + 7) * GEMM_LDS_STRIDE + a] = uint16_t(v.w >> 16);
+  }
+}
+
 // op(A)[m][k]: TA = 0 -> A[m*lda + k]; TA = 1 -> A[k*lda + m].
 // op(B)[k][n]: TB = 0 -> B[k*ldb + n]; TB = 1 -> B[n*ldb + k].
+// The K loop moves GBK = 64 values per step; the next step's operands are
+// loaded into registers while the current step's MFMAs run, so each block
+// keeps a step of loads in flight (the blocks are otherwise latency-bound:
+// 8 per compute unit, a few MFMAs per step).
 template <int TA, int TB, int EPI>
-__global__ void __launch_bounds__(256) bf16_gemm(GemmArgs g) {
-  __shared__ __attribute__((aligned(16))) uint16_t As[BM * LDS_STRIDE];  // [m][k]
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[BN * LDS_STRIDE];  // [n][k]
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) bf16_gemm(GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[BM * GEMM_LDS_STRIDE];  // [m][k]
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[BN * GEMM_LDS_STRIDE];  // [n][k]
   const int t = threadIdx.x;
   const int lane = t & 63;
   const int wave = t >> 6;
@@ -77,40 +111,34 @@ __global__ void __launch_bounds__(256) bf16_gemm(GemmArgs g) {
 #pragma unroll
   for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
 
+  // Each thread moves two 16-byte pieces of each operand per step (pieces
+  // t and t + 256 of the 64 x 64 step tile; see load_piece / stash_piece).
+  uint4 ra0, ra1, rb0, rb1;
   // split-K: block z covers K range [z K / splits, (z + 1) K / splits)
   const int64_t kspan = g.K / g.splits;
   const int64_t kbeg = int64_t(blockIdx.z) * kspan;
-  for (int64_t k0 = kbeg; k0 < kbeg + kspan; k0 += BK) {
-    // ---- global -> LDS (each thread moves 8 bf16 of A and 8 of B) ----
-    if (TA == 0) {
-      const int m = t >> 2, kk = (t & 3) * 8;
-      const uint4 val = *reinterpret_cast<const uint4*>(A + (m0 + m) * g.lda + k0 + kk);
-      *reinterpret_cast<uint4*>(&As[m * LDS_STRIDE + kk]) = val;
-    } else {
-      const int kk = t >> 3, m = (t & 7) * 8;
-      const uint4 val = *reinterpret_cast<const uint4*>(A + (k0 + kk) * g.lda + m0 + m);
-      const uint16_t* e = reinterpret_cast<const uint16_t*>(&val);
-#pragma unroll
-      for (int q = 0; q < 8; ++q) As[(m + q) * LDS_STRIDE + kk] = e[q];
-    }
-    if (TB == 1) {
-      const int n = t >> 2, kk = (t & 3) * 8;
-      const uint4 val = *reinterpret_cast<const uint4*>(B + (n0 + n) * g.ldb + k0 + kk);
-      *reinterpret_cast<uint4*>(&Bs[n * LDS_STRIDE + kk]) = val;
-    } else {
-      const int kk = t >> 3, n = (t & 7) * 8;
-      const uint4 val = *reinterpret_cast<const uint4*>(B + (k0 + kk) * g.ldb + n0 + n);
-      const uint16_t* e = reinterpret_cast<const uint16_t*>(&val);
-#pragma unroll
-      for (int q = 0; q < 8; ++q) Bs[(n + q) * LDS_STRIDE + kk] = e[q];
-    }
+  const int64_t kend = kbeg + kspan;
+  ra0 = load_piece<TA>(A, g.lda, m0, kbeg, t);
+  ra1 = load_piece<TA>(A, g.lda, m0, kbeg, t + 256);
+  rb0 = load_piece<1 - TB>(B, g.ldb, n0, kbeg, t);
+  rb1 = load_piece<1 - TB>(B, g.ldb, n0, kbeg, t + 256);
+  for (int64_t k0 = kbeg; k0 < kend; k0 += GBK) {
+    stash_piece<TA>(As, ra0, t);
+    stash_piece<TA>(As, ra1, t + 256);
+    stash_piece<1 - TB>(Bs, rb0, t);
+    stash_piece<1 - TB>(Bs, rb1, t + 256);
     __syncthreads();
-    // ---- two 32x32x16 MFMAs per wave ----
+    if (k0 + GBK < kend) {  // the next step's operands, in flight during this step's MFMAs
+      ra0 = load_piece<TA>(A, g.lda, m0, k0 + GBK, t);
+      ra1 = load_piece<TA>(A, g.lda, m0, k0 + GBK, t + 256);
+      rb0 = load_piece<1 - TB>(B, g.ldb, n0, k0 + GBK, t);
+      rb1 = load_piece<1 - TB>(B, g.ldb, n0, k0 + GBK, t + 256);
+    }
     const int i = lane & 31, kh = lane >> 5;
 #pragma unroll
-    for (int ks = 0; ks < BK; ks += 16) {
-      const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(&As[(wm * 32 + i) * LDS_STRIDE + ks + kh * 8]);
-      const bf16x8_t b = *reinterpret_cast<const bf16x8_t*>(&Bs[(wn * 32 + i) * LDS_STRIDE + ks + kh * 8]);
+    for (int ks = 0; ks < GBK; ks += 16) {
+      const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(&As[(wm * 32 + i) * GEMM_LDS_STRIDE + ks + kh * 8]);
+      const bf16x8_t b = *reinterpret_cast<const bf16x8_t*>(&Bs[(wn * 32 + i) * GEMM_LDS_STRIDE + ks + kh * 8]);
       acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
     }
     __syncthreads();
@@ -222,14 +250,29 @@ sigmoid_gram_kernel(const uint16_t* __restrict__ E, int64_t N_pad, int32_t d, co
 }
 
 // Indices outside [0, N) (padding rows) give zero rows.
-__global__ void gather_features(const double* __restrict__ X, int64_t N, int32_t n, const int32_t* __restrict__ idx,
-                                int64_t rows, int32_t d_pad, uint16_t* __restrict__ out) {
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= rows * d_pad) return;
-  const int64_t r = t / d_pad;
-  const int32_t c = int32_t(t % d_pad);
-  const int32_t p = idx[r];
-  out[t] = (c < n && p >= 0 && p < N) ? f32_to_bf16(float(X[int64_t(p) * n + c])) : uint16_t(0);
+// One block per output row at a time (grid-stride over rows): the row's
+// source index is read once, and with d_pad a multiple of 4 each thread
+// converts 4 consecutive features and writes them as one 8-byte store.
+__global__ void __launch_bounds__(256) gather_features(const double* __restrict__ X, int64_t N, int32_t n,
+                                                       const int32_t* __restrict__ idx, int64_t rows, int32_t d_pad,
+                                                       uint16_t* __restrict__ out) {
+  for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
+    const int32_t p = idx[r];
+    const int32_t m = (p >= 0 && p < N) ? n : 0;  // features copied (0: padding row)
+    const double* __restrict__ xr = X + int64_t(m ? p : 0) * n;
+    uint16_t* __restrict__ o = out + r * d_pad;
+    if ((d_pad & 3) == 0) {
+      for (int32_t c = 4 * int32_t(threadIdx.x); c < d_pad; c += 4 * 256) {
+        uint32_t h[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) h[q] = (c + q < m) ? f32_to_bf16(float(xr[c + q])) : 0u;
+        *reinterpret_cast<uint2*>(o + c) = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+      }
+    } else {
+      for (int32_t c = int32_t(threadIdx.x); c < d_pad; c += 256)
+        o[c] = (c < m) ? f32_to_bf16(float(xr[c])) : uint16_t(0);
+    }
+  }
 }
 
 // Column sums in two fixed-order stages: partial[chunk][c] over 256-row
@@ -388,8 +431,8 @@ hipError_t launch_sigmoid_gram(const uint16_t* E, int64_t N_pad, int32_t d, cons
 
 hipError_t launch_gather(const double* X, int64_t N, int32_t n, const int32_t* idx, int64_t rows, int32_t d_pad,
                          uint16_t* out, hipStream_t s) {
-  const int64_t total = rows * d_pad;
-  hipLaunchKernelGGL(gather_features, dim3(unsigned((total + 255) / 256)), dim3(256), 0, s, X, N, n, idx, rows, d_pad, out);
+  const int64_t blocks = rows < 65536 ? rows : 65536;
+  hipLaunchKernelGGL(gather_features, dim3(unsigned(blocks)), dim3(256), 0, s, X, N, n, idx, rows, d_pad, out);
   return hipGetLastError();
 }
 

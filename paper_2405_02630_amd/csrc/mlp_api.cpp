@@ -76,7 +76,7 @@ qsvm::GemmArgs gemm(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda,
 // Split-K factor of a weight-gradient GEMM with K = rows.
 int32_t grad_splits(int64_t rows) {
   for (int32_t s = 8; s > 1; s >>= 1)
-    if (rows % (int64_t(s) * 32) == 0 && rows / s >= 256) return s;
+    if (rows % (int64_t(s) * 64) == 0 && rows / s >= 256) return s;  // slabs of whole 64-deep K steps
   return 1;
 }
 

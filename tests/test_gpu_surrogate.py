@@ -325,3 +325,22 @@ def test_surrogate_gram_with_full_fallback_is_exact():
     torch.cuda.synchronize()
     assert int(flagged.item()) == 3 * 4 // 2
     assert torch.equal(K, exact)
+
+
+@pytest.mark.parametrize("N,n,d_pad", [(37, 13, 16), (37, 13, 18), (50, 784, 832), (5, 7, 7), (3, 1, 4)])
+def test_gather_features_matches_torch_conversion(N, n, d_pad):
+    """Rows idx[r] of X converted to bf16 (through float32, round to nearest
+    even) and zero-padded; rows with idx outside [0, N) are all zero."""
+    import torch
+
+    rng = np.random.default_rng(N * 1000 + d_pad)
+    Xh = rng.uniform(-4.0, 4.0, (N, n))
+    idx = np.concatenate([rng.integers(0, N, 60), [-1, N, N + 5, 0, N - 1]]).astype(np.int32)
+    X = torch.as_tensor(Xh, device="cuda:0")
+    out = torch.full((len(idx), d_pad), 7.0, dtype=torch.bfloat16, device="cuda:0")
+    qsvm.qsvm_gather_features(X, torch.as_tensor(idx, device="cuda:0"), d_pad, out)
+    torch.cuda.synchronize()
+    ref = torch.zeros((len(idx), d_pad), dtype=torch.bfloat16)
+    ok = (idx >= 0) & (idx < N)
+    ref[torch.as_tensor(ok), :n] = torch.as_tensor(Xh[idx[ok]]).to(torch.float32).to(torch.bfloat16)
+    assert torch.equal(out.cpu().view(torch.int16), ref.view(torch.int16))
