@@ -36,6 +36,15 @@ hipError_t launch_gemm(int ta, int tb, int epi, const GemmArgs& g, hipStream_t s
 // K = sigmoid(ab[0] E E^T + ab[1]), diagonal 1, per-64x64-tile off-diagonal maxima.
 hipError_t launch_sigmoid_gram(const uint16_t* E, int64_t N_pad, int32_t d, const float* ab, double* K, int64_t ldk,
                                int64_t valid, float* tile_max, hipStream_t s);
+// Up to three bf16 transposes (out_q = in_q^T, in_q R_q x C_q row-major) in
+// one launch; first_block is filled in by the launcher.
+struct TransposeJobs {
+  const uint16_t* in[3];
+  uint16_t* out[3];
+  int64_t R[3], C[3];
+  int32_t first_block[4];
+};
+hipError_t launch_transpose_bf16(TransposeJobs j, int32_t count, hipStream_t s);
 hipError_t launch_gather(const double* X, int64_t N, int32_t n, const int32_t* idx, int64_t rows, int32_t d_pad,
                          uint16_t* out, hipStream_t s);
 int colsum_chunks(int64_t rows);

@@ -14,6 +14,7 @@
 //   the off-diagonal entries (write-bound; 128 x 64 blocks, non-temporal
 //   stores).
 // * gather_features: FP64 feature rows -> zero-padded BF16 rows.
+// * transpose_bf16: the forward pass's k-contiguous copy of each weight.
 // * colsum_partial + sum_slabs: bias gradients (column sums in two fixed-order
 //   stages) and the reduction of split-K partial products.
 // * pair_head: per pair, K_hat, the loss (squared error or soft-target
@@ -102,8 +103,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))
   const int lane = t & 63;
   const int wave = t >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int64_t m0 = int64_t(blockIdx.y) * BM;
-  const int64_t n0 = int64_t(blockIdx.x) * BN;
+  // XCD-aware tile order: blocks are dealt to the 8 XCDs round-robin, so when
+  // the tile count allows, XCD x takes the x-th contiguous range of tiles and
+  // the column tiles of one row tile share that XCD's L2 copy of the A rows.
+  const uint32_t nx = gridDim.x, tiles = gridDim.x * gridDim.y;
+  uint32_t u = blockIdx.y * nx + blockIdx.x;
+  if ((tiles & 7u) == 0) u = (u & 7u) * (tiles >> 3) + (u >> 3);
+  const int64_t m0 = int64_t(u / nx) * BM;
+  const int64_t n0 = int64_t(u % nx) * BN;
   const uint16_t* __restrict__ A = static_cast<const uint16_t*>(g.A);
   const uint16_t* __restrict__ B = static_cast<const uint16_t*>(g.B);
 
@@ -250,6 +257,29 @@ sigmoid_gram_kernel(const uint16_t* __restrict__ E, int64_t N_pad, int32_t d, co
 }
 
 // Indices outside [0, N) (padding rows) give zero rows.
+// out_q (C_q x R_q) = in_q (R_q x C_q)^T for up to three bf16 matrices in one
+// launch: block b works on matrix q with first_block[q] <= b < first_block[q + 1],
+// one 32 x 32 tile through LDS (padded rows: the column reads hit distinct banks).
+__global__ void __launch_bounds__(256) transpose_bf16(TransposeJobs j) {
+  __shared__ uint16_t tile[32][34];
+  const int b = int(blockIdx.x);
+  const int q = (b >= j.first_block[2]) ? 2 : (b >= j.first_block[1]) ? 1 : 0;
+  const int64_t R = j.R[q], C = j.C[q];
+  const int64_t tiles_c = (C + 31) / 32;
+  const int64_t u = b - j.first_block[q];
+  const int64_t r0 = (u / tiles_c) * 32, c0 = (u % tiles_c) * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 8 rows of 32
+  const uint16_t* __restrict__ in = j.in[q];
+  uint16_t* __restrict__ out = j.out[q];
+#pragma unroll
+  for (int i = ty; i < 32; i += 8)
+    if (r0 + i < R && c0 + tx < C) tile[i][tx] = in[(r0 + i) * C + c0 + tx];
+  __syncthreads();
+#pragma unroll
+  for (int i = ty; i < 32; i += 8)
+    if (c0 + i < C && r0 + tx < R) out[(c0 + i) * R + r0 + tx] = tile[tx][i];
+}
+
 // One block per output row at a time (grid-stride over rows): the row's
 // source index is read once, and with d_pad a multiple of 4 each thread
 // converts 4 consecutive features and writes them as one 8-byte store.
@@ -415,6 +445,8 @@ hipError_t launch_gemm(int ta, int tb, int epi, const GemmArgs& g, hipStream_t s
     case 0 * 100 + 0 * 10 + EPI_BIAS: return launch_gemm_t<0, 0, EPI_BIAS>(g, s);
     case 0 * 100 + 0 * 10 + EPI_F32: return launch_gemm_t<0, 0, EPI_F32>(g, s);
     case 1 * 100 + 0 * 10 + EPI_F32: return launch_gemm_t<1, 0, EPI_F32>(g, s);
+    case 0 * 100 + 1 * 10 + EPI_BIAS_GELU: return launch_gemm_t<0, 1, EPI_BIAS_GELU>(g, s);
+    case 0 * 100 + 1 * 10 + EPI_BIAS: return launch_gemm_t<0, 1, EPI_BIAS>(g, s);
     case 0 * 100 + 1 * 10 + EPI_GELU_BWD: return launch_gemm_t<0, 1, EPI_GELU_BWD>(g, s);
     case 0 * 100 + 1 * 10 + EPI_F32: return launch_gemm_t<0, 1, EPI_F32>(g, s);
     default: return hipErrorInvalidValue;
@@ -426,6 +458,19 @@ hipError_t launch_sigmoid_gram(const uint16_t* E, int64_t N_pad, int32_t d, cons
   const int64_t T = N_pad / 64;
   const dim3 grid(unsigned(T), unsigned((T + 1) / 2));
   hipLaunchKernelGGL(sigmoid_gram_kernel, grid, dim3(256), 0, s, E, N_pad, d, ab, K, ldk, valid, tile_max);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose_bf16(TransposeJobs j, int32_t count, hipStream_t s) {
+  if (count < 1 || count > 3) return hipErrorInvalidValue;
+  int32_t blocks = 0;
+  for (int q = 0; q < 3; ++q) {
+    j.first_block[q] = blocks;
+    if (q < count) blocks += int32_t(((j.R[q] + 31) / 32) * ((j.C[q] + 31) / 32));
+  }
+  j.first_block[3] = blocks;
+  for (int q = count; q < 3; ++q) j.first_block[q] = blocks;  // unused slots own no block
+  hipLaunchKernelGGL(transpose_bf16, dim3(unsigned(blocks)), dim3(256), 0, s, j);
   return hipGetLastError();
 }
 

@@ -130,21 +130,44 @@ qsvm_status qsvm_mlp_forward(const qsvm_mlp* net, const void* X16, int64_t rows,
     return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_mlp_forward: input or an activation buffer is NULL");
   if (qsvm::api_injected_failure()) return injected(what);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  hipError_t e = qsvm::launch_gemm(0, 0, qsvm::EPI_BIAS_GELU,
-                                   gemm(rows, net->d_h1, net->d_in, X16, net->d_in, net->W1, net->d_h1, acts->H1,
-                                        acts->A1, net->d_h1, net->b1),
-                                   st);
+  // Each weight is first copied transposed (n x k, k contiguous: a
+  // stream-ordered temporary of ~1.6 MB at 784-512-512-256), so the GEMMs
+  // stage both operands into LDS with plain 16-byte stores instead of
+  // transposing a weight slab in every block.
+  const int64_t n1 = int64_t(net->d_in) * net->d_h1, n2 = int64_t(net->d_h1) * net->d_h2;
+  const int64_t n3 = int64_t(net->d_h2) * net->d_out;
+  uint16_t* wt = nullptr;
+  hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&wt), size_t(n1 + n2 + n3) * sizeof(uint16_t), st);
+  if (e != hipSuccess) return api_hip(e, what);
+  uint16_t *wt1 = wt, *wt2 = wt + n1, *wt3 = wt + n1 + n2;
+  qsvm::TransposeJobs tj{};
+  tj.in[0] = static_cast<const uint16_t*>(net->W1);
+  tj.in[1] = static_cast<const uint16_t*>(net->W2);
+  tj.in[2] = static_cast<const uint16_t*>(net->W3);
+  tj.out[0] = wt1;
+  tj.out[1] = wt2;
+  tj.out[2] = wt3;
+  tj.R[0] = net->d_in, tj.C[0] = net->d_h1;
+  tj.R[1] = net->d_h1, tj.C[1] = net->d_h2;
+  tj.R[2] = net->d_h2, tj.C[2] = net->d_out;
+  e = qsvm::launch_transpose_bf16(tj, 3, st);
   if (e == hipSuccess)
-    e = qsvm::launch_gemm(0, 0, qsvm::EPI_BIAS_GELU,
-                          gemm(rows, net->d_h2, net->d_h1, acts->A1, net->d_h1, net->W2, net->d_h2, acts->H2, acts->A2,
+    e = qsvm::launch_gemm(0, 1, qsvm::EPI_BIAS_GELU,
+                          gemm(rows, net->d_h1, net->d_in, X16, net->d_in, wt1, net->d_in, acts->H1, acts->A1,
+                               net->d_h1, net->b1),
+                          st);
+  if (e == hipSuccess)
+    e = qsvm::launch_gemm(0, 1, qsvm::EPI_BIAS_GELU,
+                          gemm(rows, net->d_h2, net->d_h1, acts->A1, net->d_h1, wt2, net->d_h1, acts->H2, acts->A2,
                                net->d_h2, net->b2),
                           st);
   if (e == hipSuccess)
-    e = qsvm::launch_gemm(0, 0, qsvm::EPI_BIAS,
-                          gemm(rows, net->d_out, net->d_h2, acts->A2, net->d_h2, net->W3, net->d_out, acts->E,
-                               acts->E16, net->d_out, net->b3),
+    e = qsvm::launch_gemm(0, 1, qsvm::EPI_BIAS,
+                          gemm(rows, net->d_out, net->d_h2, acts->A2, net->d_h2, wt3, net->d_h2, acts->E, acts->E16,
+                               net->d_out, net->b3),
                           st);
-  return api_hip(e, what);
+  const hipError_t f = hipFreeAsync(wt, st);
+  return api_hip(e != hipSuccess ? e : f, what);
 }
 
 qsvm_status qsvm_pair_head(const float* E, int64_t pairs, int32_t d, const float* target, const float* alpha_beta,
