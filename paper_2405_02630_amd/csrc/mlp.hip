@@ -256,7 +256,6 @@ sigmoid_gram_kernel(const uint16_t* __restrict__ E, int64_t N_pad, int32_t d, co
   }
 }
 
-// Indices outside [0, N) (padding rows) give zero rows.
 // out_q (C_q x R_q) = in_q (R_q x C_q)^T for up to three bf16 matrices in one
 // launch: block b works on matrix q with first_block[q] <= b < first_block[q + 1],
 // one 32 x 32 tile through LDS (padded rows: the column reads hit distinct banks).
@@ -280,7 +279,8 @@ __global__ void __launch_bounds__(256) transpose_bf16(TransposeJobs j) {
     if (c0 + i < C && r0 + tx < R) out[(c0 + i) * R + r0 + tx] = tile[tx][i];
 }
 
-// One block per output row at a time (grid-stride over rows): the row's
+// Indices outside [0, N) (padding rows) give zero rows.  One block per
+// output row at a time (grid-stride over rows): the row's
 // source index is read once, and with d_pad a multiple of 4 each thread
 // converts 4 consecutive features and writes them as one 8-byte store.
 __global__ void __launch_bounds__(256) gather_features(const double* __restrict__ X, int64_t N, int32_t n,
