@@ -417,7 +417,11 @@ int64_t qsvm_mlp_workspace_floats(const qsvm_mlp* net, int64_t rows);
 qsvm_status qsvm_gather_features(const double* X, int64_t N, int32_t n_qubits, const int32_t* idx, int64_t rows,
                                  int32_t d_pad, void* out, void* stream);
 
-/* Forward pass of `rows` inputs X16 (rows x d_in bf16) into acts. */
+/* Forward pass of `rows` inputs X16 (rows x d_in bf16) into acts.  The
+ * weights are first copied transposed into a stream-ordered temporary
+ * (hipMallocAsync / hipFreeAsync on `stream`, 2 (d_in d_h1 + d_h1 d_h2 +
+ * d_h2 d_out) bytes) that the GEMMs read k-contiguously; the result does not
+ * depend on it. */
 qsvm_status qsvm_mlp_forward(const qsvm_mlp* net, const void* X16, int64_t rows, const qsvm_mlp_acts* acts,
                              void* stream);
 
