@@ -232,7 +232,8 @@ qsvm_status qsvm_gram_sym_tiles(const void* mps, int64_t N, int32_t n_qubits, in
  * first *tile_count entries, bit for bit.  Butterfly sweep only (reps 1..3;
  * otherwise QSVM_ERR_UNSUPPORTED), max_tiles <= 2^24 - 8 (QSVM_ERR_UNSUPPORTED
  * above).  One persistent launch of the resident blocks strides over the
- * listed tiles, followed by the refinement of opts->refine_above.
+ * listed tiles (one fixed kernel variant per reps: opts->variant is
+ * accepted and ignored), followed by the refinement of opts->refine_above.
  */
 qsvm_status qsvm_gram_sym_tiles_dev(const void* mps, int64_t N, int32_t n_qubits, int32_t reps, const int32_t* tiles,
                                     const int32_t* tile_count, int64_t max_tiles, double* K, int64_t ldk,

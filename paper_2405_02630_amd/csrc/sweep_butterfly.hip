@@ -126,22 +126,16 @@ hipError_t launch_sweep_butterfly_args(const SweepArgs& a, int32_t reps, int32_t
 
 namespace qsvm {
 
-// The same variants over a tile list of device-resident length.
+// The persistent form over a tile list of device-resident length.  Inside
+// the persistent loop the compiler keeps more values live than in the
+// one-item kernel, so each reps uses one variant that compiles without
+// register spills (results are bitwise those of every variant).
 hipError_t launch_sweep_butterfly_counted(const SweepArgs& a, int32_t reps, int32_t variant, hipStream_t stream) {
-  if (!a.tile_list || !a.tile_count) return hipErrorInvalidValue;
-  switch (reps * 16 + variant) {
-    case 16 + 0: return launch_list_pi<1, 4, 8>(a, stream);
-    case 16 + 1: return launch_list_pi<1, 4, 4>(a, stream);
-    case 16 + 2: return launch_list_pi<1, 8, 4>(a, stream);
-    case 16 + 3: return launch_list_pi<1, 8, 2>(a, stream);
-    case 32 + 0: return launch_list_pi<2, 2, 4>(a, stream);
-    case 32 + 1: return launch_list_pi<2, 4, 4>(a, stream);
-    case 32 + 2: return launch_list_pi<2, 4, 2>(a, stream);
-    case 32 + 3: return launch_list_pi<2, 2, 8>(a, stream);
-    case 48 + 0: return launch_list_pi<3, 1, 2>(a, stream);
-    case 48 + 1: return launch_list_pi<3, 2, 2>(a, stream);
-    case 48 + 2: return launch_list_pi<3, 1, 3>(a, stream);
-    case 48 + 3: return launch_list_pi<3, 1, 4>(a, stream);
+  if (!a.tile_list || !a.tile_count || variant < 0 || variant >= kButterflyVariants) return hipErrorInvalidValue;
+  switch (reps) {
+    case 1: return launch_list_pi<1, 4, 4>(a, stream);
+    case 2: return launch_list_pi<2, 2, 4>(a, stream);
+    case 3: return launch_list_pi<3, 1, 2>(a, stream);
     default: return hipErrorInvalidValue;
   }
 }

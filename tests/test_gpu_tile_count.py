@@ -123,3 +123,13 @@ def test_flag_then_recompute_without_host_sync():
     cov = _covered(np.array(flagged), 200)
     assert np.array_equal(Kh[cov], exact[cov])
     assert np.all(Kh[~cov] == -7.0)
+
+
+@pytest.mark.parametrize("reps", [1, 2, 3])
+def test_device_count_ignores_the_variant_hint(reps):
+    X = synth.uniform_features(200, 9, seed=63 + reps)
+    m = encode(X, reps)
+    lst = _upper_tiles(4, seed=11)
+    ref = _run(m, lst, 7, dev=False)
+    for v in range(1, 5):
+        assert np.array_equal(_run(m, lst, 7, variant=v), ref)
