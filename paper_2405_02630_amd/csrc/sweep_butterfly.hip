@@ -106,8 +106,8 @@ hipError_t launch_list_pi(const SweepArgs& a0, hipStream_t stream) {
 // the fastest measured on MI355X for 784 qubits and 2048..4096 points.
 hipError_t launch_sweep_butterfly_args(const SweepArgs& a, int32_t reps, int32_t variant, hipStream_t stream) {
   switch (reps * 16 + variant) {
-    case 16 + 0: return launch_pi<1, 4, 8>(a, stream);
-    case 16 + 1: return launch_pi<1, 4, 4>(a, stream);
+    case 16 + 0: return launch_pi<1, 4, 4>(a, stream);
+    case 16 + 1: return launch_pi<1, 4, 8>(a, stream);
     case 16 + 2: return launch_pi<1, 8, 4>(a, stream);
     case 16 + 3: return launch_pi<1, 8, 2>(a, stream);
     case 32 + 0: return launch_pi<2, 2, 4>(a, stream);
