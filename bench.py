@@ -409,7 +409,7 @@ PEAK_FP64_MATRIX_TFLOPS = 78.6  # MI355X dense FP64 MFMA
 def sv_leg(points: int = 512, qubits=(12, 16, 20), reps: int = 2):
     """State-vector engine vs MPS engine on the same points (uniform features):
     build + symmetric Gram time of each, their agreement, and the roofline of
-    the state-vector Gram (FP64 MFMA, 8 flops per complex multiply-add)."""
+    the state-vector Gram (FP64 MFMA, 6 executed flops per complex multiply-add)."""
     import numpy as np
     import torch
 
@@ -442,8 +442,9 @@ def sv_leg(points: int = 512, qubits=(12, 16, 20), reps: int = 2):
         mps_s = ev[2].elapsed_time(ev[4]) / 1e3
         pairs = points * (points - 1) // 2
         T = (points + 63) // 64
-        # executed GEMM flops: the upper-triangular 64 x 64 tiles, 8 flops per complex MAC
-        flops = T * (T + 1) // 2 * 64 * 64 * (1 << n) * 8
+        # executed GEMM flops: the upper-triangular 64 x 64 tiles, 6 flops per complex
+        # MAC (the 3M form: three real multiply-adds)
+        flops = T * (T + 1) // 2 * 64 * 64 * (1 << n) * 6
         rows.append({
             "n_qubits": n,
             "sv_encode_ms": enc_s * 1e3,

@@ -164,9 +164,11 @@ constexpr int kKB = 16;  // complex inner-dimension values per LDS stage
 // With splits > 1 the inner dimension is cut into `splits` chunks of kchunk
 // values; block (tile, split) writes its partial product to W and
 // sv_reduce_kernel adds the partials in split order.
-// Three waves per SIMD (at most 168 registers, the accumulators in VGPRs):
-// measured 1.19x faster than the two that the unconstrained allocation gives.
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+// Two waves per SIMD: with the 3M product's three accumulator sets (170
+// VGPRs) this measured faster than three waves, where 2 registers spill
+// (at 20 qubits, 512 points: 20.4 vs 21.1 ms; the four-product form at three
+// waves, 130 VGPRs: 23.1 ms).
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 sv_gram_kernel(SweepArgs a, const double2* __restrict__ A, const double2* __restrict__ B, int64_t D,
                int32_t splits, int64_t kchunk, double2* __restrict__ W) {
   __shared__ double2 sA[kKB][64];
@@ -183,13 +185,17 @@ sv_gram_kernel(SweepArgs a, const double2* __restrict__ A, const double2* __rest
   const int wave = tid >> 6;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
 
-  dvec4 accr[2][2], acci[2][2];
+  // 3M form of the complex product A conj(B): P1 = Ar Br, P2 = Ai Bi and
+  // P3 = (Ar + Ai)(Br - Bi) give re = P1 + P2 and im = P3 - P1 + P2, three
+  // real MFMA products instead of four.
+  dvec4 p1[2][2], p2[2][2], p3[2][2];
 #pragma unroll
   for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
     for (int nj = 0; nj < 2; ++nj) {
-      accr[mi][nj] = dvec4{0.0, 0.0, 0.0, 0.0};
-      acci[mi][nj] = dvec4{0.0, 0.0, 0.0, 0.0};
+      p1[mi][nj] = dvec4{0.0, 0.0, 0.0, 0.0};
+      p2[mi][nj] = dvec4{0.0, 0.0, 0.0, 0.0};
+      p3[mi][nj] = dvec4{0.0, 0.0, 0.0, 0.0};
     }
 
   // loader: thread t stages row t / 4, inner values (t % 4) * 4 .. + 3
@@ -230,22 +236,17 @@ sv_gram_kernel(SweepArgs a, const double2* __restrict__ A, const double2* __rest
       for (int mi = 0; mi < 2; ++mi) fa[mi] = sA[kk][wr + mi * 16 + (lane & 15)];
 #pragma unroll
       for (int nj = 0; nj < 2; ++nj) fb[nj] = sB[kk][wc + nj * 16 + (lane & 15)];
-      const double nar[2] = {-fa[0].x, -fa[1].x};
-      // re += ar br + ai bi ; im += ai br - ar bi.  The eight accumulators are
-      // visited in turn, so no MFMA waits on the one just issued.
+      const double sa[2] = {fa[0].x + fa[0].y, fa[1].x + fa[1].y};
+      const double db[2] = {fb[0].x - fb[0].y, fb[1].x - fb[1].y};
+      // the twelve accumulators are visited in turn, so no MFMA waits on the
+      // one just issued
 #pragma unroll
       for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
         for (int nj = 0; nj < 2; ++nj) {
-          accr[mi][nj] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[mi].x, fb[nj].x, accr[mi][nj], 0, 0, 0);
-          acci[mi][nj] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[mi].y, fb[nj].x, acci[mi][nj], 0, 0, 0);
-        }
-#pragma unroll
-      for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-        for (int nj = 0; nj < 2; ++nj) {
-          accr[mi][nj] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[mi].y, fb[nj].y, accr[mi][nj], 0, 0, 0);
-          acci[mi][nj] = __builtin_amdgcn_mfma_f64_16x16x4f64(nar[mi], fb[nj].y, acci[mi][nj], 0, 0, 0);
+          p1[mi][nj] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[mi].x, fb[nj].x, p1[mi][nj], 0, 0, 0);
+          p2[mi][nj] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[mi].y, fb[nj].y, p2[mi][nj], 0, 0, 0);
+          p3[mi][nj] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[mi], db[nj], p3[mi][nj], 0, 0, 0);
         }
     }
     __syncthreads();
@@ -259,7 +260,8 @@ sv_gram_kernel(SweepArgs a, const double2* __restrict__ A, const double2* __rest
       for (int v = 0; v < 4; ++v) {
         const int r = wr + mi * 16 + 4 * v + (lane >> 4);
         const int c = wc + nj * 16 + (lane & 15);
-        const double gr = accr[mi][nj][v], gi = acci[mi][nj][v];
+        const double q1 = p1[mi][nj][v], q2 = p2[mi][nj][v];
+        const double gr = q1 + q2, gi = (p3[mi][nj][v] - q1) + q2;
         if (splits > 1) {
           W[(int64_t(tile) * splits + split) * (kTile * kTile) + r * kTile + c] = make_double2(gr, gi);
           continue;
