@@ -202,7 +202,7 @@ class Surrogate:
         return FitReport(steps, time.perf_counter() - t0, hist)
 
     # ------------------------------------------------------------------
-    def embed(self, X, chunk: int = 16384):
+    def embed(self, X, chunk: int = 32768):
         """BF16 embeddings of every row of X, padded to a multiple of 64 rows."""
         import torch
 
