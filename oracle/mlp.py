@@ -2,11 +2,19 @@
 
 The surrogate embeds a feature vector with a three-layer perceptron
 f(x) = ((gelu(gelu(x W1 + b1) W2 + b2)) W3 + b3) and predicts a kernel entry
-as K_hat(x, y) = sigmoid(alpha <f(x), f(y)> + beta); it is trained by mean
-squared error against exact kernel entries (the kernel of §2, Eq. 3) with
-AdamW.  This module writes those definitions out in float64 NumPy so the GPU
-kernels (BF16 operands, FP32 accumulation) can be compared with them.  GELU
-is the exact form x Phi(x).  Nothing here is shared with the GPU path.
+(the kernel of §2, Eq. 3) from the embeddings, with one of two heads:
+
+* log domain (the default):   ln K_hat(x, y) = -alpha ||f(x) - f(y)||^2,
+  trained by the mean squared error of ln K_hat against the exact ln K,
+  scaled by a fixed constant;
+* sigmoid:   K_hat(x, y) = sigmoid(alpha <f(x), f(y)> + beta), trained by
+  squared error or soft-target cross-entropy against K.
+
+Weights are updated with AdamW.  This module writes those definitions out in
+float64 NumPy so the GPU kernels (BF16 operands, FP32 accumulation) can be
+compared with them.  GELU is the exact form x Phi(x).  Nothing here is shared
+with the GPU path; only tests, the build's smoke check and the benchmark's CPU
+baseline use it.
 """
 
 from __future__ import annotations
@@ -107,3 +115,50 @@ def bf16_round(a):
     u = a32.view(np.uint32).astype(np.uint64)
     u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
     return (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def log_rbf_pair_loss(E, target, alpha, scale):
+    """Log-domain pair head.  Rows p and P + p of E are the two points of pair p.
+
+    ln K_hat_p = -alpha ||e_p - e_{P+p}||^2 and
+    loss = mean_p ((ln K_hat_p - t_p) / scale)^2 with t_p the exact ln K.
+    Returns (loss, dE, dalpha, ln_k_hat).
+    """
+    P = target.shape[0]
+    diff = E[:P] - E[P:]
+    d2 = np.sum(diff * diff, axis=1)
+    lh = -alpha * d2
+    r = (lh - target) / scale
+    loss = float(np.mean(r * r))
+    dl = 2.0 * r / (scale * P)  # d loss / d ln K_hat_p
+    gi = (dl * (-2.0 * alpha))[:, None] * diff
+    dE = np.concatenate([gi, -gi])
+    return loss, dE, float(np.sum(dl * (-d2))), lh
+
+
+def log_rbf_gram(E, alpha):
+    """ln K_hat[i][j] = -alpha ||e_i - e_j||^2 for all pairs, with the diagonal
+    rule ln K_hat[i][i] = 0 (K_hat = 1).  Returns (ln_k_hat, k_hat)."""
+    E = np.asarray(E, dtype=np.float64)
+    D2 = np.sum((E[:, None, :] - E[None, :, :]) ** 2, axis=2)
+    L = -alpha * D2
+    np.fill_diagonal(L, 0.0)
+    with np.errstate(under="ignore"):
+        K = np.exp(L)
+    return L, K
+
+
+def tile_max_offdiag(M, tile=64):
+    """Largest off-diagonal entry of every tile x tile block of the square M
+    (row-major over tiles, -inf for a block with none)."""
+    N = M.shape[0]
+    T = -(-N // tile)
+    out = np.full((T, T), -np.inf)
+    off = ~np.eye(N, dtype=bool)
+    for a in range(T):
+        for b in range(T):
+            blk = M[a * tile:(a + 1) * tile, b * tile:(b + 1) * tile]
+            msk = off[a * tile:(a + 1) * tile, b * tile:(b + 1) * tile]
+            if msk.any():
+                out[a, b] = blk[msk].max()
+    return out

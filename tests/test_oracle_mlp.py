@@ -125,10 +125,100 @@ def test_bf16_round_matches_torch():
     assert np.array_equal(mlp.bf16_round(x), ref)
 
 
-def test_surrogate_gram_definition():
+def test_surrogate_gram_matches_torch_sigmoid():
     rng = np.random.default_rng(4)
-    E = rng.normal(0, 1, (5, 3))
+    E = rng.normal(0, 1, (37, 9))
     K = mlp.surrogate_gram(E, 0.5, -1.0)
-    assert np.all(np.diag(K) == 1.0)
-    assert abs(K[1, 3] - 1 / (1 + np.exp(-(0.5 * E[1] @ E[3] - 1.0)))) < 1e-15
-    assert np.allclose(K, K.T)
+    tE = torch.tensor(E, dtype=torch.float64)
+    ref = torch.sigmoid(0.5 * (tE @ tE.T) - 1.0).numpy()
+    np.fill_diagonal(ref, 1.0)
+    assert np.max(np.abs(K - ref)) < 1e-15
+    assert np.array_equal(K, K.T)
+
+
+def _log_loss(params, X, target, alpha, scale):
+    acts = mlp.forward(params, X)
+    return mlp.log_rbf_pair_loss(acts["E"], target, alpha, scale)[0]
+
+
+def test_log_rbf_head_matches_torch_autograd():
+    # ln K_hat = -alpha * squared distance (torch.cdist, a library routine the
+    # reference does not use); loss and every gradient against autograd
+    rng = np.random.default_rng(6)
+    params = _params(rng, dims=(10, 8, 7, 5))
+    X = rng.normal(0, 1, (16, 10))
+    target = rng.uniform(-40.0, 0.0, 8)
+    alpha, scale = 0.8, 7.0
+    acts = mlp.forward(params, X)
+    loss, dE, da, lh = mlp.log_rbf_pair_loss(acts["E"], target, alpha, scale)
+    grads = mlp.backward(params, X, acts, dE)
+
+    tp = [torch.tensor(p, dtype=torch.float64, requires_grad=True) for p in params]
+    ta = torch.tensor(alpha, dtype=torch.float64, requires_grad=True)
+    g = torch.nn.functional.gelu
+    E = g(g(torch.tensor(X) @ tp[0] + tp[1]) @ tp[2] + tp[3]) @ tp[4] + tp[5]
+    P = 8
+    d2 = torch.cdist(E[:P].unsqueeze(0), E[P:].unsqueeze(0)).squeeze(0).diagonal() ** 2
+    tl = ((-ta * d2 - torch.tensor(target)) / scale).pow(2).mean()
+    tl.backward()
+    assert abs(tl.item() - loss) < 1e-13
+    assert np.max(np.abs((-alpha * d2).detach().numpy() - lh)) < 1e-12
+    for p, gr in zip(tp, grads):
+        assert np.max(np.abs(p.grad.numpy() - gr)) < 1e-13
+    assert abs(ta.grad.item() - da) < 1e-13
+
+
+def test_log_rbf_head_matches_finite_differences():
+    rng = np.random.default_rng(7)
+    params = list(_params(rng))
+    X = rng.normal(0, 1, (8, 6))
+    target = rng.uniform(-5, 0, 4)
+    alpha, scale = 0.6, 3.0
+    acts = mlp.forward(params, X)
+    _, dE, da, _ = mlp.log_rbf_pair_loss(acts["E"], target, alpha, scale)
+    grads = mlp.backward(params, X, acts, dE)
+    h = 1e-6
+    for p, g in zip(params, grads):
+        flat = p.reshape(-1)
+        for q in range(0, flat.size, max(1, flat.size // 5)):
+            old = flat[q]
+            flat[q] = old + h
+            lp = _log_loss(params, X, target, alpha, scale)
+            flat[q] = old - h
+            lm = _log_loss(params, X, target, alpha, scale)
+            flat[q] = old
+            assert abs((lp - lm) / (2 * h) - g.reshape(-1)[q]) < 1e-7
+    fa = (_log_loss(params, X, target, alpha + h, scale) - _log_loss(params, X, target, alpha - h, scale)) / (2 * h)
+    assert abs(fa - da) < 1e-7
+
+
+def test_log_rbf_head_special_cases():
+    # identical embeddings predict ln K_hat = 0 (K_hat = 1) whatever alpha is;
+    # orthogonal unit vectors are at squared distance 2
+    E = np.array([[1.0, 0.0], [0.0, 1.0], [1.0, 0.0], [1.0, 0.0]])  # pairs (0, 2) and (1, 3)
+    _, _, _, lh = mlp.log_rbf_pair_loss(E, np.zeros(2), 3.0, 1.0)
+    assert lh[0] == 0.0 and lh[1] == -6.0
+    L, K = mlp.log_rbf_gram(E, 3.0)
+    assert np.array_equal(np.diag(L), np.zeros(4)) and np.array_equal(np.diag(K), np.ones(4))
+    assert L[0, 1] == -6.0 and L[0, 2] == 0.0 and K[0, 2] == 1.0
+
+
+def test_log_rbf_gram_matches_torch_cdist():
+    rng = np.random.default_rng(8)
+    E = rng.normal(0, 0.3, (70, 12))
+    L, K = mlp.log_rbf_gram(E, 0.25)
+    tE = torch.tensor(E)
+    ref = -0.25 * torch.cdist(tE, tE).pow(2).numpy()
+    np.fill_diagonal(ref, 0.0)
+    assert np.max(np.abs(L - ref)) < 1e-12
+    assert np.max(np.abs(K - np.exp(ref))) < 1e-12
+
+
+def test_tile_max_offdiag():
+    M = np.arange(130 * 130, dtype=np.float64).reshape(130, 130)
+    tm = mlp.tile_max_offdiag(M)
+    assert tm.shape == (3, 3)
+    assert tm[0, 0] == M[63, 62]   # the diagonal entry M[63, 63] is excluded
+    assert tm[0, 2] == M[63, 129]
+    assert tm[2, 2] == M[129, 128]
+    assert tm[2, 0] == M[129, 63]
