@@ -211,6 +211,29 @@ qsvm_status qsvm_gram_sym(const void* mps, int64_t N, int32_t n_qubits, int32_t 
                           double* K, int64_t ldk, const qsvm_gram_opts* opts, void* stream);
 
 /*
+ * qsvm_gram_sym for callers that cannot allocate device memory: work recorded
+ * under stream capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, kernels and results (bit for bit) as qsvm_gram_sym; no
+ * hipMalloc, hipFree or other allocating call is made.  The FP64
+ * refinement's tile list, a stream-ordered temporary in qsvm_gram_sym, is
+ * kept instead in a static device array of QSVM_NOALLOC_SCRATCH_ENTRIES
+ * uint32 entries (4 MiB, one per device, held until the process ends): one
+ * entry for the count plus one per 64 x 64 tile of the call (at most 2^24 - 8
+ * per launch chunk).  Calls whose refinement would need more -- more than
+ * 1,048,575 tiles in the row range, e.g. N above about 92,600 for a full
+ * symmetric Gram -- return QSVM_ERR_SIZE before anything is enqueued; calls
+ * with the refinement off (opts->refine_above < 0, or n_qubits <= 50 with the
+ * automatic threshold) do not touch the array and have no such limit.  Every
+ * call on one device shares that device's array, and each call resets the
+ * count it uses on the device before listing tiles: calls that overlap on one
+ * device (different streams, or host threads) race and must be ordered by the
+ * caller.
+ */
+#define QSVM_NOALLOC_SCRATCH_ENTRIES (1 << 20)
+qsvm_status qsvm_gram_sym_noalloc(const void* mps, int64_t N, int32_t n_qubits, int32_t reps,
+                                  double* K, int64_t ldk, const qsvm_gram_opts* opts, void* stream);
+
+/*
  * Symmetric Gram restricted to a list of 64 x 64 tiles: for every (ti, tj) in
  * `tiles` (device int32 pairs, 0 <= ti <= tj < ceil(N/64)) the pairs
  * i < j with i in tile row ti and j in tile column tj are contracted and

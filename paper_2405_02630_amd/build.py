@@ -37,7 +37,7 @@ FLAGS = [
     "-I" + os.path.join(ROOT, "include"),
 ]
 
-SOURCES = ["api.cpp", "autotune.cpp", "batch_plan.cpp", "batched.hip", "encode.hip", "mlp.hip", "mlp_api.cpp", "refine.hip", "sweep_butterfly.hip", "sweep_dense.hip", "sweep_split.hip", "sv.hip"]
+SOURCES = ["api.cpp", "autotune.cpp", "batch_plan.cpp", "batched.hip", "encode.hip", "mlp.hip", "mlp_api.cpp", "noalloc.hip", "refine.hip", "sweep_butterfly.hip", "sweep_dense.hip", "sweep_split.hip", "sv.hip"]
 
 
 def _compile(src: str, verbose: bool) -> str:

@@ -121,24 +121,53 @@ hipError_t resident_refine_blocks(int32_t reps, int64_t* out) {
   return e;
 }
 
+// The refinement threshold a call uses: the automatic one for 0.  The
+// refinement runs only for thresholds in (0, 1) (negative: off; >= 1: no entry
+// can need it).
+double effective_refine_threshold(double refine_above, int32_t n) {
+  return refine_above == 0.0 ? qsvm::auto_refine_threshold(n) : refine_above;
+}
+bool refine_runs(double thresh) { return thresh > 0.0 && thresh < 1.0; }
+
+// uint32 entries of the refinement's workspace ([count, tile list...]) for the
+// tiles of `a`: launch_chunked issues at most kMaxGridBlocks tiles per chunk
+// and the chunks reuse the workspace in stream order.
+int64_t refine_workspace_entries(const qsvm::SweepArgs& a) {
+  const int64_t tiles = qsvm::launch_tiles(a);
+  if (tiles <= 0) return 0;
+  return (tiles < qsvm::kMaxGridBlocks ? tiles : qsvm::kMaxGridBlocks) + 1;
+}
+
+// Where the refinement's workspace comes from: a stream-ordered temporary
+// (get == nullptr) or memory the caller obtains without allocating.
+struct WorkspaceSource {
+  hipError_t (*get)(uint32_t** ptr) = nullptr;
+  int64_t entries = 0;  // capacity of what `get` returns
+};
+
 // FP64 refinement of the tiles of `a` (the tiles one Gram call swept) whose
 // largest entry exceeds the threshold, chunk by chunk like the sweeps.
-hipError_t refine_tiles(const qsvm::SweepArgs& a, int32_t reps, double thresh, hipStream_t stream) {
-  if (thresh == 0.0) thresh = qsvm::auto_refine_threshold(a.n);
-  if (thresh < 0.0 || thresh >= 1.0) return hipSuccess;  // off, or no entry can need it
-  const int64_t tiles = qsvm::launch_tiles(a);
-  if (tiles <= 0) return hipSuccess;
+hipError_t refine_tiles(const qsvm::SweepArgs& a, int32_t reps, double refine_above, hipStream_t stream,
+                        const WorkspaceSource& src) {
+  const double thresh = effective_refine_threshold(refine_above, a.n);
+  if (!refine_runs(thresh)) return hipSuccess;
+  const int64_t need = refine_workspace_entries(a);
+  if (need <= 0) return hipSuccess;
   int64_t resident = 0;
   hipError_t e = resident_refine_blocks(reps, &resident);
   if (e != hipSuccess) return e;
-  const int64_t cap = tiles < qsvm::kMaxGridBlocks ? tiles : qsvm::kMaxGridBlocks;
   uint32_t* ws = nullptr;  // [count, list...]
-  e = hipMallocAsync(reinterpret_cast<void**>(&ws), size_t(cap + 1) * sizeof(uint32_t), stream);
+  if (src.get) {
+    if (need > src.entries) return hipErrorInvalidValue;  // callers validate this first
+    e = src.get(&ws);
+  } else {
+    e = hipMallocAsync(reinterpret_cast<void**>(&ws), size_t(need) * sizeof(uint32_t), stream);
+  }
   if (e != hipSuccess) return e;
   e = qsvm::launch_chunked(a, 1, [&](const qsvm::SweepArgs& c) {
     return qsvm::launch_refine(c, reps, thresh, ws + 1, ws, resident, stream);
   });
-  const hipError_t f = hipFreeAsync(ws, stream);
+  const hipError_t f = src.get ? hipSuccess : hipFreeAsync(ws, stream);
   return e != hipSuccess ? e : f;
 }
 
@@ -149,7 +178,7 @@ int32_t pick_variant(const Opts& o, int32_t reps, int32_t n) {
 
 qsvm_status run_gram(const void* mps_a, int64_t Na, const void* mps_b, int64_t Nb, int32_t n,
                      int32_t reps, double* K, int64_t ldk, const Opts& o, bool sym, void* stream,
-                     const char* what) {
+                     const char* what, const WorkspaceSource& src = WorkspaceSource{}) {
   using qsvm::kTile;
   if (o.sweep == QSVM_SWEEP_DENSE && reps > 3)
     return fail(QSVM_ERR_UNSUPPORTED, "%s: the dense sweep supports reps <= 3", what);
@@ -179,11 +208,15 @@ qsvm_status run_gram(const void* mps_a, int64_t Na, const void* mps_b, int64_t N
   a.tile_row0 = int32_t(o.row_begin / kTile);
   a.tile_rows = int32_t((o.row_end - 1) / kTile) - a.tile_row0 + 1;
   a.tiles_b = int32_t(tiles_b);
+  if (src.get && refine_runs(effective_refine_threshold(o.refine_above, n)) &&
+      refine_workspace_entries(a) > src.entries)
+    return fail(QSVM_ERR_SIZE, "%s: the refinement needs a %lld-entry tile list, the static workspace holds %lld",
+                what, (long long)refine_workspace_entries(a), (long long)src.entries);
   if (injected_launch_failure()) return fail(QSVM_ERR_HIP, "%s: injected launch failure (QSVM_FAULT_INJECT=launch)", what);
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = (o.sweep == QSVM_SWEEP_DENSE) ? qsvm::launch_sweep_dense_args(a, reps, s)
                                                 : qsvm::launch_sweep_fast(a, reps, pick_variant(o, reps, n), s);
-  if (e == hipSuccess) e = refine_tiles(a, reps, o.refine_above, s);
+  if (e == hipSuccess) e = refine_tiles(a, reps, o.refine_above, s, src);
   return hip_status(e, what);
 }
 
@@ -240,8 +273,22 @@ qsvm_status gram_tile_list(const void* mps, int64_t N, int32_t n_qubits, int32_t
   hipError_t e = tile_count                      ? qsvm::launch_sweep_butterfly_counted(a, reps, variant, st)
                  : (o.sweep == QSVM_SWEEP_DENSE) ? qsvm::launch_sweep_dense_args(a, reps, st)
                                                  : qsvm::launch_sweep_fast(a, reps, variant, st);
-  if (e == hipSuccess) e = refine_tiles(a, reps, o.refine_above, st);
+  if (e == hipSuccess) e = refine_tiles(a, reps, o.refine_above, st, WorkspaceSource{});
   return hip_status(e, what);
+}
+
+qsvm_status gram_sym(const void* mps, int64_t N, int32_t n_qubits, int32_t reps, double* K, int64_t ldk,
+                     const qsvm_gram_opts* opts, void* stream, const char* what, const WorkspaceSource& src) {
+  if (!mps) return fail(QSVM_ERR_INVALID_ARG, "%s: mps is NULL", what);
+  if (!K) return fail(QSVM_ERR_INVALID_ARG, "%s: K is NULL", what);
+  qsvm_status s = check_shape(N, n_qubits, reps, what);
+  if (s != QSVM_OK) return s;
+  if (ldk < N) return fail(QSVM_ERR_INVALID_ARG, "%s: ldk = %lld < N = %lld", what, (long long)ldk, (long long)N);
+  if (reinterpret_cast<uintptr_t>(mps) % 16 != 0) return fail(QSVM_ERR_INVALID_ARG, "%s: mps is not 16-byte aligned", what);
+  Opts o;
+  s = read_opts(opts, N, o, what);
+  if (s != QSVM_OK) return s;
+  return run_gram(mps, N, mps, N, n_qubits, reps, K, ldk, o, true, stream, what, src);
 }
 
 }  // namespace
@@ -252,6 +299,19 @@ qsvm_status api_fail(qsvm_status s, const char* msg) { return fail(s, "%s", msg)
 qsvm_status api_ok() { return ok(); }
 qsvm_status api_hip(hipError_t e, const char* what) { return hip_status(e, what); }
 bool api_injected_failure() { return injected_launch_failure(); }
+
+// qsvm_gram_sym with the refinement's tile list taken from `get_ws` (at most
+// ws_entries uint32 entries) instead of a stream-ordered temporary; sizes that
+// need more are rejected with QSVM_ERR_SIZE before anything is enqueued, and
+// `get_ws` is called only when the refinement runs.
+qsvm_status gram_sym_static_workspace(const void* mps, int64_t N, int32_t n_qubits, int32_t reps, double* K,
+                                      int64_t ldk, const qsvm_gram_opts* opts, void* stream,
+                                      hipError_t (*get_ws)(uint32_t**), int64_t ws_entries, const char* what) {
+  WorkspaceSource src;
+  src.get = get_ws;
+  src.entries = ws_entries;
+  return gram_sym(mps, N, n_qubits, reps, K, ldk, opts, stream, what, src);
+}
 }  // namespace qsvm
 
 extern "C" {
@@ -302,17 +362,7 @@ qsvm_status qsvm_gram(const void* mps_a, int64_t Na, const void* mps_b, int64_t 
 
 qsvm_status qsvm_gram_sym(const void* mps, int64_t N, int32_t n_qubits, int32_t reps, double* K,
                           int64_t ldk, const qsvm_gram_opts* opts, void* stream) {
-  const char* what = "qsvm_gram_sym";
-  if (!mps) return fail(QSVM_ERR_INVALID_ARG, "%s: mps is NULL", what);
-  if (!K) return fail(QSVM_ERR_INVALID_ARG, "%s: K is NULL", what);
-  qsvm_status s = check_shape(N, n_qubits, reps, what);
-  if (s != QSVM_OK) return s;
-  if (ldk < N) return fail(QSVM_ERR_INVALID_ARG, "%s: ldk = %lld < N = %lld", what, (long long)ldk, (long long)N);
-  if (reinterpret_cast<uintptr_t>(mps) % 16 != 0) return fail(QSVM_ERR_INVALID_ARG, "%s: mps is not 16-byte aligned", what);
-  Opts o;
-  s = read_opts(opts, N, o, what);
-  if (s != QSVM_OK) return s;
-  return run_gram(mps, N, mps, N, n_qubits, reps, K, ldk, o, true, stream, what);
+  return gram_sym(mps, N, n_qubits, reps, K, ldk, opts, stream, "qsvm_gram_sym", WorkspaceSource{});
 }
 
 qsvm_status qsvm_gram_sym_tiles(const void* mps, int64_t N, int32_t n_qubits, int32_t reps, const int32_t* tiles,

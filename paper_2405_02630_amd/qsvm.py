@@ -127,6 +127,8 @@ def load_library(path: str = LIB_PATH):
     lib.qsvm_gram.restype = i32
     lib.qsvm_gram_sym.argtypes = [vp, i64, i32, i32, vp, i64, ctypes.POINTER(GramOpts), vp]
     lib.qsvm_gram_sym.restype = i32
+    lib.qsvm_gram_sym_noalloc.argtypes = [vp, i64, i32, i32, vp, i64, ctypes.POINTER(GramOpts), vp]
+    lib.qsvm_gram_sym_noalloc.restype = i32
     lib.qsvm_status_string.argtypes = [i32]
     lib.qsvm_status_string.restype = ctypes.c_char_p
     lib.qsvm_last_error.argtypes = []
@@ -319,6 +321,31 @@ def qsvm_gram_sym(mps: MPS, K=None, *, log_k=None, renorm_every: int = 0, sweep:
         raise ValueError("log_k must match K's shape, strides and dtype")
     o = _opts(renorm_every, sweep, diag_mode, rows, log_k, variant, refine_above)
     st = lib.qsvm_gram_sym(
+        _device_ptr(mps.buf, "mps"), mps.N, mps.n, mps.reps, ctypes.c_void_p(K.data_ptr()), K.stride(0),
+        ctypes.byref(o), _stream_ptr(stream),
+    )
+    _check(st)
+    return K
+
+
+NOALLOC_SCRATCH_ENTRIES = 1 << 20  # QSVM_NOALLOC_SCRATCH_ENTRIES
+
+
+def qsvm_gram_sym_noalloc(mps: MPS, K, *, log_k=None, renorm_every: int = 0, sweep: int = SWEEP_AUTO,
+                          diag_mode: int = 0, rows=None, variant: int = 0, refine_above: float = 0.0,
+                          stream=None):
+    """qsvm_gram_sym without any device allocation by the library: the
+    refinement's tile list lives in a static per-device array.  K (and log_k)
+    must be supplied by the caller.  Calls overlapping on one device race."""
+    import torch
+
+    lib = load_library()
+    if K is None or K.dim() != 2 or K.shape[0] < mps.N or K.stride(1) != 1 or K.dtype != torch.float64:
+        raise ValueError("K must be a float64 2-D tensor with unit column stride and at least N rows")
+    if log_k is not None and (log_k.shape != K.shape or log_k.stride() != K.stride() or log_k.dtype != torch.float64):
+        raise ValueError("log_k must match K's shape, strides and dtype")
+    o = _opts(renorm_every, sweep, diag_mode, rows, log_k, variant, refine_above)
+    st = lib.qsvm_gram_sym_noalloc(
         _device_ptr(mps.buf, "mps"), mps.N, mps.n, mps.reps, ctypes.c_void_p(K.data_ptr()), K.stride(0),
         ctypes.byref(o), _stream_ptr(stream),
     )

@@ -115,6 +115,47 @@ def test_gram_sym_validation(lib, no_inject):
     assert _sym(lib, mps=ctypes.c_void_p(0x100004)) == qsvm.QSVM_ERR_INVALID_ARG
 
 
+def _sym_noalloc(lib, N=100, n=784, reps=2, ldk=None, opts=None, mps=FAKE, K=FAKE2):
+    ldk = N if ldk is None else ldk
+    return lib.qsvm_gram_sym_noalloc(mps, N, n, reps, K, ldk, ctypes.byref(opts) if opts is not None else None, None)
+
+
+def _tiles_upper(N):
+    T = -(-N // 64)
+    return T * (T + 1) // 2
+
+
+def test_gram_sym_noalloc_validation(lib, no_inject):
+    assert _sym_noalloc(lib, mps=None) == qsvm.QSVM_ERR_INVALID_ARG
+    assert _sym_noalloc(lib, K=None) == qsvm.QSVM_ERR_INVALID_ARG
+    assert _sym_noalloc(lib, ldk=99) == qsvm.QSVM_ERR_INVALID_ARG
+    assert _sym_noalloc(lib, reps=5) == qsvm.QSVM_ERR_UNSUPPORTED
+    # the refinement's list needs one entry per tile plus the count: the
+    # largest N whose upper triangle fits the static array, and the next one
+    # that does not, are told apart before any HIP call
+    cap = qsvm.NOALLOC_SCRATCH_ENTRIES
+    N_ok = max(N for N in range(64, 200000, 64) if _tiles_upper(N) + 1 <= cap)
+    assert _tiles_upper(N_ok + 64) + 1 > cap
+    assert _sym_noalloc(lib, N=N_ok + 1) == qsvm.QSVM_ERR_SIZE
+    assert b"static workspace" in lib.qsvm_last_error()
+    # a row range narrows the tiles the call needs
+    o = qsvm.GramOpts()
+    o.row_begin, o.row_end = 0, 64
+    os.environ["QSVM_FAULT_INJECT"] = "launch"
+    try:
+        assert _sym_noalloc(lib, N=N_ok + 1, opts=o) == qsvm.QSVM_ERR_HIP
+        assert _sym_noalloc(lib, N=N_ok) == qsvm.QSVM_ERR_HIP  # passes validation
+        # refinement off: no workspace, no size limit
+        o2 = qsvm.GramOpts()
+        o2.refine_above = -1.0
+        assert _sym_noalloc(lib, N=4 * N_ok, opts=o2) == qsvm.QSVM_ERR_HIP
+        # at n <= 50 the automatic threshold switches the refinement off
+        assert _sym_noalloc(lib, N=4 * N_ok, n=50) == qsvm.QSVM_ERR_HIP
+    finally:
+        del os.environ["QSVM_FAULT_INJECT"]
+    assert _sym_noalloc(lib, N=4 * N_ok, n=51) == qsvm.QSVM_ERR_SIZE
+
+
 def test_gram_rect_validation(lib, no_inject):
     assert _rect(lib, a=None) == qsvm.QSVM_ERR_INVALID_ARG
     assert _rect(lib, b=None) == qsvm.QSVM_ERR_INVALID_ARG
