@@ -209,8 +209,141 @@ def test_by_train_leg(reps, n_train, train_buf, Xtrain, sweep, args):
     }
 
 
+def exact_reps_leg(reps, n_train, args):
+    """The 784-pixel image workload at another depth: the symmetric Gram of the
+    training images (encode + Gram per step) and the 1024 x n_train test-by-train
+    Gram, each with its sweep's fraction of the FP32 vector peak."""
+    import numpy as np
+    import torch
+    from paper_2405_02630_amd import qsvm, synth
+
+    dev = torch.device("cuda:0")
+    wl = synth.images784(seed=0, n_train=n_train, n_test=1024, reps=reps)
+    n = wl.X.shape[1]
+    X = torch.as_tensor(wl.X, dtype=torch.float64, device=dev)
+    Xt = torch.as_tensor(wl.X_test, dtype=torch.float64, device=dev)
+    buf = torch.empty(qsvm.qsvm_mps_bytes(n_train, n, reps), dtype=torch.uint8, device=dev)
+    K = torch.empty((n_train, n_train), dtype=torch.float64, device=dev)
+    Kr = torch.empty((Xt.shape[0], n_train), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    out = {}
+    for kind in ("sym", "test_by_train"):
+        def step(ev=None):
+            m = qsvm.qsvm_encode_mps(X, reps, out=buf)
+            if kind == "sym":
+                if ev is not None:
+                    ev[0].record(stream)
+                qsvm.qsvm_gram_sym(m, K)
+            else:
+                ma = qsvm.qsvm_encode_mps(Xt, reps)
+                if ev is not None:
+                    ev[0].record(stream)
+                qsvm.qsvm_gram(ma, m, Kr)
+            if ev is not None:
+                ev[1].record(stream)
+
+        for _ in range(max(1, args.warmup)):
+            step()
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+        t0 = time.perf_counter()
+        for st in range(args.steps):
+            step(evs[st])
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        sweep_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+        pairs = n_train * (n_train - 1) // 2 if kind == "sym" else Xt.shape[0] * n_train
+        flops = sweep_flops_per_pair(n, reps, "butterfly") * pairs
+        out[kind] = {
+            "workload": (f"images-n{n}-r{reps}-train{n_train}-sym" if kind == "sym"
+                         else f"images-n{n}-r{reps}-test{Xt.shape[0]}-train{n_train}-rect"),
+            "pairs_per_step": pairs,
+            "ms_per_step": ms,
+            "value": pairs / (ms / 1e3),
+            "unit": "entries/s",
+            "sweep_ms": round(sweep_ms, 4),
+            "sweep_tflops": round(flops / (sweep_ms / 1e3) / 1e12, 3),
+            "sweep_frac_of_fp32_peak": round(flops / (sweep_ms / 1e3) / 1e12 / PEAK_FP32_VECTOR_TFLOPS, 4),
+            "step": ("encode MPS + symmetric Gram" if kind == "sym"
+                     else "encode both MPS sets + rectangular Gram (the sweep time covers the Gram only)"),
+        }
+        log(f"reps={reps} {kind}: {ms:.3f} ms/step, sweep {sweep_ms:.3f} ms "
+            f"({out[kind]['sweep_frac_of_fp32_peak']:.3f} of peak), {out[kind]['value']:.4e} entries/s")
+    del K, Kr, buf
+    torch.cuda.empty_cache()
+    return out
+
+
+def refine_worst_leg(args, reps: int = 2, N: int = 4096, cores: int = 8):
+    """Worst case of the FP64 refinement: 4096 near-identical 784-pixel images,
+    so every 64 x 64 tile holds entries near 1 and is recomputed with an FP64
+    environment.  Times the symmetric Gram with the automatic refinement and
+    with the refinement off, and compares both with the FP64 oracle on the
+    pairs of the first 64 points (self-overlaps computed, diag_mode 1)."""
+    import numpy as np
+    import torch
+
+    from oracle import mps as omps
+    from paper_2405_02630_amd import qsvm, synth
+
+    dev = torch.device("cuda:0")
+    Xh = synth.near_identical_images(N, seed=9)
+    X = torch.as_tensor(Xh, device=dev)
+    m = qsvm.qsvm_encode_mps(X, reps)
+    K = torch.empty((N, N), dtype=torch.float64, device=dev)
+    res = {"workload": f"near-identical images-n{Xh.shape[1]}-r{reps}-N{N}-sym (one image + 4e-4 N(0,1) pixel noise)"}
+    S = omps.mps_states(Xh[:64], reps, processes=cores)
+    ia, jb = np.triu_indices(64)
+    _, kk = omps.mps_gram_pairs(S, S, ia, jb)
+    res["K_oracle_min_sample"] = float(kk.min())
+    for tag, ra in (("refined", 0.0), ("fp32_only", -1.0)):
+        qsvm.qsvm_gram_sym(m, K, refine_above=ra, diag_mode=1)
+        torch.cuda.synchronize()
+        ev = _events(2)
+        ev[0].record()
+        for _ in range(3):
+            qsvm.qsvm_gram_sym(m, K, refine_above=ra, diag_mode=1)
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1]) / 3
+        d = np.abs(K[:64, :64].cpu().numpy()[ia, jb] - kk)
+        res[tag] = {"ms": ms, "value": N * (N + 1) // 2 / (ms / 1e3), "unit": "entries/s",
+                    "sample_max_abs_dK": float(d.max())}
+        log(f"refine worst case ({tag}): {ms:.2f} ms, sample max|dK| {d.max():.2e}")
+    res["refined_over_fp32_time"] = res["refined"]["ms"] / res["fp32_only"]["ms"]
+    del K
+    torch.cuda.empty_cache()
+    return res
+
+
+def _tile_pairs(tiles, N):
+    """Pairs (i, j), i < j, of the listed 64 x 64 tiles of an N-point upper triangle."""
+    import numpy as np
+
+    a = np.arange(64)
+    I, J = [], []
+    for ti, tj in tiles:
+        ii = ti * 64 + a[:, None].repeat(64, 1)
+        jj = tj * 64 + a[None, :].repeat(64, 0)
+        m = (ii < jj) & (jj < N)
+        I.append(ii[m])
+        J.append(jj[m])
+    return np.concatenate(I), np.concatenate(J)
+
+
 def surrogate_leg(args, exact_rate):
-    """Train, time and judge the learned surrogate on the 32768-image workload."""
+    """Train, time and judge the learned surrogate on 32768 784-pixel images
+    (reps = 2) of which 2048 are near-duplicate copies (K up to ~1).
+
+    Training, calibration and judging pairs are the pairs of uniformly drawn
+    64 x 64 tiles of the upper triangle: 2 %, 0.5 % and 1 % of the tiles,
+    disjoint, with exact K and ln K from the tile-list Gram.  Reports the
+    held-out log-domain error of the trained network, the untrained network
+    (same head fitted to the same targets) and the best constant predictor,
+    on all pairs and on the close pairs (ln K > -100); the tiles each of
+    them would have to send to the exact fallback at the tau = 1e-6 bar; the
+    timed whole Gram with fallback against the exact Gram; and the largest
+    |dK| over every held-out pair."""
     import numpy as np
     import torch
 
@@ -220,44 +353,74 @@ def surrogate_leg(args, exact_rate):
     dev = torch.device("cuda:0")
     N = args.sur_points
     reps = 2
-    wl = synth.images784(seed=5, n_train=N, n_test=0, reps=reps)
-    X = torch.as_tensor(wl.X, dtype=torch.float64, device=dev)
-    n = wl.X.shape[1]
+    n_copies = N // 16
+    Xh, labels, base_of_row = synth.images784_with_near_duplicates(N, n_copies, seed=5)
+    X = torch.as_tensor(Xh, dtype=torch.float64, device=dev)
+    n = Xh.shape[1]
+    T = (N + 63) // 64
+    upper = [(a, b) for a in range(T) for b in range(a, T)]
     rng = np.random.default_rng(17)
-    perm = rng.permutation(N)
-    s_train = int(round(math.sqrt(0.02 * N * (N - 1))))  # S(S-1)/2 = 2 % of N(N-1)/2
-    s_hold = int(round(math.sqrt(0.01 * N * (N - 1))))
-    s_svm = min(4096, N - s_train - s_hold)
-    train_pts = np.sort(perm[:s_train])
-    hold_pts = np.sort(perm[s_train:s_train + s_hold])
-    svm_pts = np.sort(perm[s_train + s_hold:s_train + s_hold + s_svm])
-    log(f"surrogate: N={N}, train {s_train} pts ({s_train*(s_train-1)//2} pairs), "
-        f"held out {s_hold} pts ({s_hold*(s_hold-1)//2} pairs)")
-
-    def exact_sub(pts):
-        m = qsvm.qsvm_encode_mps(X[torch.as_tensor(pts, device=dev)].contiguous(), reps)
-        return qsvm.qsvm_gram_sym(m)
-
+    perm = rng.permutation(len(upper))
+    n_tr, n_cal, n_ho = (int(round(f * len(upper))) for f in (0.02, 0.005, 0.01))
+    sets = {"train": perm[:n_tr], "cal": perm[n_tr:n_tr + n_cal], "held": perm[n_tr + n_cal:n_tr + n_cal + n_ho]}
+    mps_all = qsvm.qsvm_encode_mps(X, reps)
+    Kex = torch.full((N, N), -1.0, dtype=torch.float64, device=dev)
+    Lex = torch.full((N, N), -1.0, dtype=torch.float64, device=dev)
+    pairs = {}
     t0 = time.perf_counter()
-    K_train = exact_sub(train_pts).cpu().numpy()
+    for name, sel in sets.items():
+        tl = np.array([upper[u] for u in sel], dtype=np.int32)
+        qsvm.qsvm_gram_sym_tiles(mps_all, torch.as_tensor(tl.reshape(-1), device=dev), len(tl), Kex, log_k=Lex)
+        I, J = _tile_pairs(tl, N)
+        It, Jt = torch.as_tensor(I, device=dev), torch.as_tensor(J, device=dev)
+        pairs[name] = (I, J, Lex[It, Jt].cpu().numpy(), Kex[It, Jt].cpu().numpy())
+    torch.cuda.synchronize()
     t_targets = time.perf_counter() - t0
+    log(f"surrogate: N={N} ({n_copies} near duplicates), exact targets on "
+        f"{n_tr}/{n_cal}/{n_ho} tiles: {len(pairs['train'][0])} train, {len(pairs['cal'][0])} calibration, "
+        f"{len(pairs['held'][0])} held-out pairs ({t_targets:.2f} s)")
+    Itr, Jtr, Ltr, _ = pairs["train"]
+    Ica, Jca, Lca, _ = pairs["cal"]
+    Iho, Jho, Lho, Kho = pairs["held"]
+
     cfg = SurrogateConfig()
     sur = Surrogate(n, cfg)
-    # the untrained network with the same initial head, judged like the trained one
-    hp = torch.as_tensor(hold_pts, device=dev)
-    iu = np.triu_indices(s_hold, 1)
-    Kh_hold = exact_sub(hold_pts).cpu().numpy()
-    sur.init_head_from_targets(float(np.mean(K_train[np.triu_indices(s_train, 1)])))
-    K0, _ = sur.gram(X[hp].contiguous(), None, tau=2.0)
-    dk0 = np.abs(K0.cpu().numpy()[iu] - Kh_hold[iu])
-    del K0
-    rep = sur.fit(X, train_pts, K_train, steps=args.sur_steps, log_every=max(1, args.sur_steps // 5))
-    log(f"surrogate: trained {rep.steps} steps in {rep.seconds:.2f} s, loss {rep.loss_history}")
+    pick = rng.choice(Itr.size, min(65536, Itr.size), replace=False)
+    sur.init_head(X, Itr[pick], Jtr[pick], Ltr[pick])
+    tau = cfg.tau
+    lt = math.log(tau)
+    const = float(np.median(Ltr))
 
-    mps_all = qsvm.qsvm_encode_mps(X, reps)
+    def margin_for(lh_cal):
+        # the margin Surrogate.calibrate sets, for the predictions lh_cal
+        near = Lca >= lt - 20.0
+        under = Lca - lh_cal
+        return max(0.0, float(np.max(under[near])) if near.any() else float(np.max(under))) + 1.0
+
+    def judge(lh):
+        e = np.abs(lh - Lho)
+        close = Lho > -100.0
+        return {"mean_abs_dlnK": float(e.mean()), "median_abs_dlnK": float(np.median(e)),
+                "close_pairs_mean_abs_dlnK": float(e[close].mean()) if close.any() else None,
+                "close_pairs_max_abs_dlnK": float(e[close].max()) if close.any() else None}
+
+    lh0_ho, _ = sur.predict_pairs(X, Iho, Jho)
+    lh0_ca, _ = sur.predict_pairs(X, Ica, Jca)
+    margin0 = margin_for(lh0_ca)
+    _, cnt0 = sur.gram(X, None, margin=margin0)
+    untrained_flagged = int(cnt0.item())
+    rep = sur.fit(X, Itr, Jtr, Ltr, steps=args.sur_steps, log_every=max(1, args.sur_steps // 5))
+    log(f"surrogate: trained {rep.steps} steps in {rep.seconds:.2f} s, loss {rep.loss_history}")
+    lh1_ho, _ = sur.predict_pairs(X, Iho, Jho)
+    margin = sur.calibrate(X, Ica, Jca, Lca)
+    untrained, trained = judge(lh0_ho), judge(lh1_ho)
+    constant = judge(np.full_like(Lho, const))
+    near_c = Lca >= lt - 20.0
+    const_margin = max(0.0, float(np.max(Lca[near_c] - const)) if near_c.any() else float(np.max(Lca - const))) + 1.0
+    constant_flagged = len(upper) if const >= lt - const_margin else 0
+
     Kall = torch.empty((N, N), dtype=torch.float64, device=dev)
-    # surrogate Gram with fallback, timed end to end (embedding + GEMM + flags + fallback)
-    sur.gram(X, mps_all, K=Kall)
+    sur.gram(X, mps_all, K=Kall)  # warm-up
     torch.cuda.synchronize()
     times = []
     for _ in range(3):
@@ -267,15 +430,17 @@ def surrogate_leg(args, exact_rate):
         times.append(time.perf_counter() - t0)
     flagged = int(flagged.item())
     sur_s = float(np.median(times))
-    T = (N + 63) // 64
-    # judge on the held-out pairs against their exact Gram
-    Ks_hold = Kall[hp][:, hp].cpu().numpy()
-    dk = np.abs(Ks_hold[iu] - Kh_hold[iu])
-    # SVM on a disjoint subset with the exact and the surrogate Gram
+    It, Jt = torch.as_tensor(Iho, device=dev), torch.as_tensor(Jho, device=dev)
+    Ks_ho = Kall[It, Jt].cpu().numpy()
+    dk = np.abs(Ks_ho - Kho)
+    big = Kho > 1e-3
+    # SVM on a 4096-point subset with the exact and the surrogate Gram
+    svm_pts = np.sort(rng.choice(N, 4096, replace=False))
     sp = torch.as_tensor(svm_pts, device=dev)
     Ks_svm = Kall[sp][:, sp].cpu().numpy()
-    Ke_svm = exact_sub(svm_pts).cpu().numpy()
-    acc_exact, acc_sur = svm_accuracies(Ke_svm, Ks_svm, wl.labels[svm_pts])
+    m_svm = qsvm.qsvm_encode_mps(X[sp].contiguous(), reps)
+    Ke_svm = qsvm.qsvm_gram_sym(m_svm).cpu().numpy()
+    acc_exact, acc_sur = svm_accuracies(Ke_svm, Ks_svm, labels[svm_pts])
     # exact whole-set Gram for the speedup (same N, same buffer)
     ev = _events(2)
     ev[0].record()
@@ -283,37 +448,52 @@ def surrogate_leg(args, exact_rate):
     ev[1].record()
     torch.cuda.synchronize()
     exact_s = ev[0].elapsed_time(ev[1]) / 1e3
-    pairs = N * (N - 1) // 2
+    n_pairs = N * (N - 1) // 2
+    c_head, s_head = sur.head_values()
     res = {
-        "workload": f"images-n{n}-r{reps}-N{N}-sym",
-        "value": pairs / sur_s,
+        "workload": f"images-n{n}-r{reps}-N{N}-sym, {n_copies} near-duplicate copies (eps 1e-3..1e-1), shuffled",
+        "value": n_pairs / sur_s,
         "unit": "entries/s",
         "seconds": sur_s,
         "exact_seconds": exact_s,
-        "exact_value": pairs / exact_s,
+        "exact_value": n_pairs / exact_s,
         "speedup_vs_exact": exact_s / sur_s,
+        "tau": tau,
+        "margin_nats": margin,
         "flagged_tiles": flagged,
-        "tiles": T * (T + 1) // 2,
+        "tiles": len(upper),
+        "untrained_flagged_tiles": untrained_flagged,
+        "constant_flagged_tiles": constant_flagged,
         "held_out_pairs": int(dk.size),
+        "held_out_pairs_K_above_1e-3": int(big.sum()),
         "held_out_max_abs_dK": float(dk.max()),
+        "held_out_max_abs_dK_where_K_above_1e-3": float(dk[big].max()) if big.any() else None,
         "held_out_mean_abs_dK": float(dk.mean()),
-        "held_out_exact_K_max": float(Kh_hold[iu].max()),
-        "untrained_held_out_max_abs_dK": float(dk0.max()),
-        "untrained_held_out_mean_abs_dK": float(dk0.mean()),
-        "train_pairs": s_train * (s_train - 1) // 2,
+        "held_out_log_domain": {"trained": trained, "untrained": untrained, "constant_median": constant,
+                                "close_pairs": int((Lho > -100.0).sum())},
+        "trained_over_constant_mean_abs_dlnK": constant["mean_abs_dlnK"] / trained["mean_abs_dlnK"],
+        "trained_over_constant_close_pairs": (constant["close_pairs_mean_abs_dlnK"] / trained["close_pairs_mean_abs_dlnK"]
+                                              if trained["close_pairs_mean_abs_dlnK"] else None),
+        "trained_over_untrained_close_pairs": (untrained["close_pairs_mean_abs_dlnK"] / trained["close_pairs_mean_abs_dlnK"]
+                                               if trained["close_pairs_mean_abs_dlnK"] else None),
+        "head": {"c": c_head, "s": s_head},
+        "train_pairs": int(Itr.size),
         "train_steps": rep.steps,
         "train_seconds": rep.seconds,
         "target_seconds": t_targets,
         "final_loss": rep.loss_history[-1][1] if rep.loss_history else None,
-        "svm_subset": int(s_svm),
+        "svm_subset": 4096,
         "svm_accuracy_exact": acc_exact,
         "svm_accuracy_surrogate": acc_sur,
-        "model": f"MLP {n}->{cfg.d_h1}->{cfg.d_h2}->{cfg.d_out} GELU, bf16 weights, fp32 accumulate",
+        "model": f"z = [x, MLP(x)], MLP {n}->{cfg.d_h1}->{cfg.d_h2}->{cfg.d_out} GELU, bf16 weights, fp32 accumulate; "
+                 "ln K_hat = -c (1 - exp(-s |z - z'|^2))",
     }
     log(f"surrogate: {res['value']:.3e} entries/s ({sur_s*1e3:.1f} ms) vs exact {exact_s*1e3:.1f} ms; "
-        f"held-out max|dK| {res['held_out_max_abs_dK']:.2e}; flagged {flagged}; "
-        f"SVM exact {acc_exact:.3f} surrogate {acc_sur:.3f}")
-    del Kall
+        f"held-out max|dK| {res['held_out_max_abs_dK']:.2e} ({int(big.sum())} pairs with K > 1e-3); "
+        f"flagged {flagged} (untrained {untrained_flagged}, constant {constant_flagged}) of {len(upper)}; "
+        f"|d ln K| trained {trained['mean_abs_dlnK']:.2f} untrained {untrained['mean_abs_dlnK']:.2f} "
+        f"constant {constant['mean_abs_dlnK']:.2f}; SVM exact {acc_exact:.3f} surrogate {acc_sur:.3f}")
+    del Kall, Kex, Lex
     torch.cuda.empty_cache()
     return res
 
@@ -476,9 +656,9 @@ def main():
     ap.add_argument("--renorm-every", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=720)
-    ap.add_argument("--legs", default="exact,surrogate,batched,sv")  # "exact" adds the test x train Gram
+    ap.add_argument("--legs", default="exact,reps3,refine_worst,surrogate,batched,sv")  # "exact" adds the test x train Gram
     ap.add_argument("--sur-points", type=int, default=32768)
-    ap.add_argument("--sur-steps", type=int, default=300)
+    ap.add_argument("--sur-steps", type=int, default=600)
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="run only a plain device copy of this many MiB (for HBM counter scaling)")
     args = ap.parse_args()
@@ -590,6 +770,10 @@ def main():
     legs = set(args.legs.split(","))
     if "exact" in legs:
         out["test_by_train"] = test_by_train_leg(reps, N, mps_buf, X, sweep, args)
+    if "reps3" in legs and reps == 2:
+        out["reps3"] = exact_reps_leg(3, N, args)
+    if "refine_worst" in legs:
+        out["refine_worst"] = refine_worst_leg(args)
     if "surrogate" in legs:
         del K  # release the exact leg's buffers first
         torch.cuda.empty_cache()

@@ -459,6 +459,24 @@ qsvm_status qsvm_mlp_forward(const qsvm_mlp* net, const void* X16, int64_t rows,
 qsvm_status qsvm_pair_head(const float* E, int64_t pairs, int32_t d, const float* target, const float* alpha_beta,
                            int32_t loss_kind, void* dE16, float* partial, float* out3, void* stream);
 
+/* Log-domain pair head on the embedding z = [x, f(x)]: rows p and pairs + p of
+ * X16 (2*pairs x d_in bf16, the gathered inputs; d_in may be 0, X16 then
+ * may be NULL) and of E
+ * (2*pairs x d f32, the MLP output) are the two points of pair p, and
+ *   d2_p = ||z_p - z_{pairs+p}||^2,
+ *   ln K_hat_p = -c (1 - exp(-s d2_p)),  c = exp(head[0]), s = exp(head[1]),
+ * a kernel estimate that is exactly 1 for identical points, -c s d2 for
+ * close ones and saturates at e^-c for unrelated ones (the concentration of
+ * kernel values at many qubits, §4.2.1).  loss = mean_p ((ln K_hat_p - t_p) /
+ * scale)^2 against the exact ln K (target[p], e.g. from qsvm_gram_opts.log_k).
+ * Writes dE16 (2*pairs x d bf16, d loss / d E; the input part has no
+ * parameters), per-pair partials (3*pairs floats) and out3 = (loss,
+ * d loss / d head[0], d loss / d head[1]) reduced in a fixed order; pred
+ * (optional, 2*pairs floats) receives (ln K_hat_p, d2_p). */
+qsvm_status qsvm_pair_head_log(const void* X16, int32_t d_in, const float* E, int32_t d, int64_t pairs,
+                               const float* target, const float* head, float scale, void* dE16, float* partial,
+                               float* out3, float* pred, void* stream);
+
 /* Backward pass given dE16 (rows x d_out bf16): parameter gradients into grads
  * (overwritten, not accumulated).  Weight gradients (K = rows) are split along
  * the rows into partial products in grads->ws and summed in a fixed order;
@@ -484,6 +502,18 @@ qsvm_status qsvm_surrogate_gram(const void* E16, int64_t N, int64_t N_pad, int32
  * value is >= tau to tile_list (int32 pairs, room for T(T+1)/2) and its count
  * to *count (device int32; cleared first).  The order of the list is not
  * specified. */
+/* Log-domain surrogate Gram: K[i][j] = exp(ln K_hat(z_i, z_j)) with the head
+ * of qsvm_pair_head_log on z = [X16 row, E16 row] (N_pad rows each, N_pad = N
+ * rounded up to 64; d_in % 32 == 0 (0: no input part, X16 may be NULL),
+ * d % 32 == 0), K[i][i] = 1, K row stride
+ * ldk >= N.  The squared distances come from the BF16 inner products
+ * (FP32 accumulation on the matrix cores) and the rows' squared norms;
+ * ln K_hat is formed in FP32.  tile_max receives per 64 x 64 tile
+ * ((N_pad/64)^2 floats, row-major) the largest off-diagonal ln K_hat (-inf for
+ * none), for qsvm_flag_tiles with a threshold in the log domain. */
+qsvm_status qsvm_surrogate_gram_log(const void* X16, int32_t d_in, const void* E16, int32_t d, int64_t N, int64_t N_pad,
+                                    const float* head, double* K, int64_t ldk, float* tile_max, void* stream);
+
 qsvm_status qsvm_flag_tiles(const float* tile_max, int32_t T, float tau, int32_t* tile_list, int32_t* count,
                             void* stream);
 

@@ -4,9 +4,12 @@ The surrogate embeds a feature vector with a three-layer perceptron
 f(x) = ((gelu(gelu(x W1 + b1) W2 + b2)) W3 + b3) and predicts a kernel entry
 (the kernel of §2, Eq. 3) from the embeddings, with one of two heads:
 
-* log domain (the default):   ln K_hat(x, y) = -alpha ||f(x) - f(y)||^2,
-  trained by the mean squared error of ln K_hat against the exact ln K,
-  scaled by a fixed constant;
+* log domain (the default):   ln K_hat(x, y) = -c (1 - exp(-s d^2)) with
+  d^2 = ||x - y||^2 + ||f(x) - f(y)||^2, the squared distance between the
+  embeddings [x, f(x)] (the input itself and the MLP output), trained by the
+  mean squared error of ln K_hat against the exact ln K, scaled by a fixed
+  constant; ln K_hat(x, x) = 0, and large distances saturate at -c, the
+  level to which kernels of unrelated points concentrate at many qubits;
 * sigmoid:   K_hat(x, y) = sigmoid(alpha <f(x), f(y)> + beta), trained by
   squared error or soft-target cross-entropy against K.
 
@@ -117,31 +120,47 @@ def bf16_round(a):
     return (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
 
 
-def log_rbf_pair_loss(E, target, alpha, scale):
-    """Log-domain pair head.  Rows p and P + p of E are the two points of pair p.
+def sat_log_head(d2, log_c, log_s):
+    """ln K_hat as a function of the squared embedding distance d2:
+    -c (1 - exp(-s d2)) with c = exp(log_c), s = exp(log_s).  It is 0 at
+    d2 = 0 (K_hat(x, x) = 1), -c s d2 for small d2, and saturates at -c."""
+    c, s = math.exp(log_c), math.exp(log_s)
+    return -c * (1.0 - np.exp(-s * d2))
 
-    ln K_hat_p = -alpha ||e_p - e_{P+p}||^2 and
-    loss = mean_p ((ln K_hat_p - t_p) / scale)^2 with t_p the exact ln K.
-    Returns (loss, dE, dalpha, ln_k_hat).
+
+def sat_log_pair_loss(Xr, E, target, log_c, log_s, scale):
+    """Log-domain pair head on the embedding [x, f(x)].
+
+    Rows p and P + p of Xr (the input features) and E (the MLP output) are
+    the two points of pair p; d2_p = ||x_p - x_{P+p}||^2 + ||e_p - e_{P+p}||^2,
+    ln K_hat_p = sat_log_head(d2_p), loss = mean_p ((ln K_hat_p - t_p) / scale)^2
+    with t_p the exact ln K.  The input part carries no parameters, so only E
+    receives a gradient.  Returns (loss, dE, dlog_c, dlog_s, ln_k_hat, d2).
     """
     P = target.shape[0]
-    diff = E[:P] - E[P:]
-    d2 = np.sum(diff * diff, axis=1)
-    lh = -alpha * d2
+    dx = Xr[:P] - Xr[P:]
+    de = E[:P] - E[P:]
+    d2 = np.sum(dx * dx, axis=1) + np.sum(de * de, axis=1)
+    c, s = math.exp(log_c), math.exp(log_s)
+    ex = np.exp(-s * d2)
+    lh = -c * (1.0 - ex)
     r = (lh - target) / scale
     loss = float(np.mean(r * r))
-    dl = 2.0 * r / (scale * P)  # d loss / d ln K_hat_p
-    gi = (dl * (-2.0 * alpha))[:, None] * diff
+    dl = 2.0 * r / (scale * P)             # d loss / d ln K_hat_p
+    g = dl * (-c * s * ex)                 # d loss / d d2_p
+    gi = (2.0 * g)[:, None] * de
     dE = np.concatenate([gi, -gi])
-    return loss, dE, float(np.sum(dl * (-d2))), lh
+    dlog_c = float(np.sum(dl * lh))        # d ln K_hat / d log_c = ln K_hat
+    dlog_s = float(np.sum(dl * (-c * s * d2 * ex)))
+    return loss, dE, dlog_c, dlog_s, lh, d2
 
 
-def log_rbf_gram(E, alpha):
-    """ln K_hat[i][j] = -alpha ||e_i - e_j||^2 for all pairs, with the diagonal
-    rule ln K_hat[i][i] = 0 (K_hat = 1).  Returns (ln_k_hat, k_hat)."""
-    E = np.asarray(E, dtype=np.float64)
-    D2 = np.sum((E[:, None, :] - E[None, :, :]) ** 2, axis=2)
-    L = -alpha * D2
+def sat_log_gram(Xr, E, log_c, log_s):
+    """ln K_hat for all pairs of the rows of [Xr, E], with the diagonal rule
+    ln K_hat[i][i] = 0.  Returns (ln_k_hat, k_hat)."""
+    Z = np.concatenate([np.asarray(Xr, dtype=np.float64), np.asarray(E, dtype=np.float64)], axis=1)
+    D2 = np.sum((Z[:, None, :] - Z[None, :, :]) ** 2, axis=2)
+    L = sat_log_head(D2, log_c, log_s)
     np.fill_diagonal(L, 0.0)
     with np.errstate(under="ignore"):
         K = np.exp(L)

@@ -52,6 +52,14 @@ hipError_t launch_colsum(const uint16_t* A, int64_t rows, int32_t cols, float* p
 hipError_t launch_sum_slabs(const float* slabs, int32_t n_slabs, int64_t count, float* out, hipStream_t s);
 hipError_t launch_pair_head(const float* E, int64_t P, int32_t d, const float* target, const float* ab,
                             int32_t loss_kind, uint16_t* dE16, float* partial, float* out3, hipStream_t s);
+// Log-domain head: per pair loss and gradient (pair_head_log + the fixed-order
+// reduction into out3 = (loss, d/d log c, d/d log s)); the whole Gram.
+hipError_t launch_pair_head_log(const uint16_t* X16, int32_t d_in, const float* E, int32_t d, int64_t P,
+                                const float* target, const float* head, float scale, uint16_t* dE16, float* partial,
+                                float* out3, float* pred, hipStream_t s);
+hipError_t launch_sat_log_gram(const uint16_t* X16, int32_t d_in, const uint16_t* E, int32_t d, int64_t N_pad,
+                               const float* head, double* K, int64_t ldk, int64_t valid, float* tile_max,
+                               hipStream_t s);
 hipError_t launch_adamw(float* w, const float* grad, float* m, float* v, uint16_t* w16, int64_t count,
                         const AdamArgs& o, hipStream_t s);
 hipError_t launch_flag_tiles(const float* tile_max, int32_t T, float tau, int32_t* list, int32_t* count,

@@ -1,6 +1,8 @@
 // Kernels of the learned surrogate: an MLP embedding f (BF16 weights and
-// activations, FP32 accumulation on the matrix cores) whose scaled inner
-// products stand in for kernel entries, K_hat(x, y) = sigmoid(alpha <f(x), f(y)> + beta).
+// activations, FP32 accumulation on the matrix cores) whose inner products
+// stand in for kernel entries, either in the log domain through the squared
+// distance of the embeddings [x, f(x)], ln K_hat = -c (1 - exp(-s d2)), or as
+// K_hat(x, y) = sigmoid(alpha <f(x), f(y)> + beta).
 //
 // * bf16_gemm<TA, TB, EPI>: C = op(A) op(B) on v_mfma_f32_32x32x16_bf16.
 //   A 64 x 64 output tile per block of 4 waves (each wave one 32 x 32
@@ -20,6 +22,10 @@
 // * pair_head: per pair, K_hat, the loss (squared error or soft-target
 //   cross-entropy) and its gradient w.r.t. both embeddings, alpha and beta;
 //   per-pair partial sums reduced in a fixed order.
+// * pair_head_log, sat_log_gram_kernel: the log-domain head
+//   ln K_hat = -c (1 - exp(-s d2)) on the squared distance of the embeddings
+//   [x, f(x)] (loss and gradients per pair; the whole Gram with per-tile
+//   maxima of ln K_hat).
 // * adamw: decoupled-weight-decay Adam on FP32 master weights, BF16 copy.
 // * flag_tiles: compacts the tiles whose largest off-diagonal K_hat reaches
 //   the fallback threshold.
@@ -256,6 +262,127 @@ sigmoid_gram_kernel(const uint16_t* __restrict__ E, int64_t N_pad, int32_t d, co
   }
 }
 
+// Log-domain surrogate Gram on the embedding [x, f(x)] (two BF16 segments:
+// the gathered inputs X16, d_in wide, and the MLP output E16, d wide):
+//   d2 = ||z_i - z_j||^2 = |z_i|^2 + |z_j|^2 - 2 <z_i, z_j>,
+//   ln K_hat = -c (1 - exp(-s d2)) = c expm1(-s d2),  c = exp(head[0]), s = exp(head[1]),
+// K[i][j] = exp(ln K_hat) (FP64 store of the FP32 value), K[i][i] = 1, and
+// per 64 x 64 tile the largest off-diagonal ln K_hat.  Same blocking as
+// sigmoid_gram_kernel (128 x 64 outputs per block, inner dimension staged
+// through LDS 32 at a time, first through X16, then through E16); each thread
+// also sums the squares of the pieces it stages, so the squared norms of the
+// block's rows come from the same BF16 values the matrix cores multiply.
+__global__ void __launch_bounds__(256)
+sat_log_gram_kernel(const uint16_t* __restrict__ X16, int32_t d_in, const uint16_t* __restrict__ E, int32_t d,
+                    int64_t N_pad, const float* __restrict__ head, double* __restrict__ K, int64_t ldk,
+                    int64_t valid, float* __restrict__ tile_max) {
+  constexpr int GM = 128, GN = 64;
+  __shared__ __attribute__((aligned(16))) uint16_t As[GM * LDS_STRIDE];  // [m][k]
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[GN * LDS_STRIDE];  // [n][k]
+  __shared__ float normA[GM], normB[GN];
+  __shared__ float red[2][4];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int64_t T = N_pad / 64;
+  const int64_t m0 = int64_t(blockIdx.y) * GM, n0 = int64_t(blockIdx.x) * GN;
+
+  f32x16_t acc[2];
+#pragma unroll
+  for (int w = 0; w < 2; ++w)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[w][v] = 0.0f;
+  float sqA[2] = {0.0f, 0.0f}, sqB = 0.0f;  // squares of this thread's staged pieces
+  const int dtot = d_in + d;
+  for (int k0 = 0; k0 < dtot; k0 += BK) {
+    const bool seg0 = k0 < d_in;
+    const uint16_t* __restrict__ src = seg0 ? X16 : E;
+    const int64_t ld = seg0 ? d_in : d;
+    const int kb = seg0 ? k0 : k0 - d_in;
+    const int kk = (t & 3) * 8;
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+      const int m = w * 64 + (t >> 2);
+      const int64_t row = (m0 + m < N_pad) ? m0 + m : N_pad - 1;
+      const uint4 q = *reinterpret_cast<const uint4*>(src + row * ld + kb + kk);
+      *reinterpret_cast<uint4*>(&As[m * LDS_STRIDE + kk]) = q;
+      const uint32_t u[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const float lo = bf16_to_f32(uint16_t(u[h])), hi = bf16_to_f32(uint16_t(u[h] >> 16));
+        sqA[w] = fmaf(lo, lo, sqA[w]);
+        sqA[w] = fmaf(hi, hi, sqA[w]);
+      }
+    }
+    {
+      const int n = t >> 2;
+      const uint4 q = *reinterpret_cast<const uint4*>(src + (n0 + n) * ld + kb + kk);
+      *reinterpret_cast<uint4*>(&Bs[n * LDS_STRIDE + kk]) = q;
+      const uint32_t u[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const float lo = bf16_to_f32(uint16_t(u[h])), hi = bf16_to_f32(uint16_t(u[h] >> 16));
+        sqB = fmaf(lo, lo, sqB);
+        sqB = fmaf(hi, hi, sqB);
+      }
+    }
+    __syncthreads();
+    const int i = lane & 31, kh = lane >> 5;
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 16) {
+      const bf16x8_t b = *reinterpret_cast<const bf16x8_t*>(&Bs[(wn * 32 + i) * LDS_STRIDE + ks + kh * 8]);
+#pragma unroll
+      for (int w = 0; w < 2; ++w) {
+        const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(&As[(w * 64 + wm * 32 + i) * LDS_STRIDE + ks + kh * 8]);
+        acc[w] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[w], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  // the four threads t & ~3 .. t | 3 staged the four quarters of the same rows
+#pragma unroll
+  for (int off = 1; off < 4; off <<= 1) {
+    sqA[0] += __shfl_xor(sqA[0], off, 64);
+    sqA[1] += __shfl_xor(sqA[1], off, 64);
+    sqB += __shfl_xor(sqB, off, 64);
+  }
+  if ((t & 3) == 0) {
+    normA[t >> 2] = sqA[0];
+    normA[64 + (t >> 2)] = sqA[1];
+    normB[t >> 2] = sqB;
+  }
+  __syncthreads();
+
+  const float c = __expf(head[0]), s = __expf(head[1]);
+  const int cl = wn * 32 + (lane & 31);
+  const int64_t col = n0 + cl;
+  const float nb = normB[cl];
+  float tmax[2] = {-INFINITY, -INFINITY};
+#pragma unroll
+  for (int w = 0; w < 2; ++w)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int rl = w * 64 + wm * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+      const int64_t r = m0 + rl;
+      if (r < valid && col < valid) {
+        const float d2 = fmaxf(fmaf(-2.0f, acc[w][v], normA[rl] + nb), 0.0f);
+        const float lk = c * expm1f(-s * d2);
+        __builtin_nontemporal_store((r == col) ? 1.0 : double(expf(lk)), &K[r * ldk + col]);
+        if (r != col) tmax[w] = fmaxf(tmax[w], lk);
+      }
+    }
+#pragma unroll
+  for (int w = 0; w < 2; ++w) {
+    for (int off = 32; off > 0; off >>= 1) tmax[w] = fmaxf(tmax[w], __shfl_xor(tmax[w], off, 64));
+    if (lane == 0) red[w][wave] = tmax[w];
+  }
+  __syncthreads();
+  if (t < 2) {
+    const int64_t ti = 2 * int64_t(blockIdx.y) + t;
+    if (ti < T)
+      tile_max[ti * T + blockIdx.x] = fmaxf(fmaxf(red[t][0], red[t][1]), fmaxf(red[t][2], red[t][3]));
+  }
+}
+
 // out_q (C_q x R_q) = in_q (R_q x C_q)^T for up to three bf16 matrices in one
 // launch: block b works on matrix q with first_block[q] <= b < first_block[q + 1],
 // one 32 x 32 tile through LDS (padded rows: the column reads hit distinct banks).
@@ -368,6 +495,58 @@ __global__ void __launch_bounds__(256) pair_head(const float* __restrict__ E, in
     partial[3 * p + 0] = lp;
     partial[3 * p + 1] = ds * dot;
     partial[3 * p + 2] = ds;
+  }
+}
+
+// Log-domain pair head, one wave per pair p: rows p (point i) and P + p
+// (point j) of the gathered inputs X16 (d_in wide, BF16) and of the MLP
+// output E (d wide, FP32).  d2 = ||x_i - x_j||^2 + ||e_i - e_j||^2,
+// ln K_hat = c expm1(-s d2) with c = exp(head[0]), s = exp(head[1]),
+// loss_p = ((ln K_hat - t) / scale)^2 with t the exact ln K.  Writes the BF16
+// gradient of the mean loss w.r.t. both rows of E (the input part has no
+// parameters) and the per-pair partials (loss, d/d log c, d/d log s);
+// pred (optional) receives (ln K_hat, d2) per pair.
+__global__ void __launch_bounds__(256) pair_head_log(const uint16_t* __restrict__ X16, int32_t d_in,
+                                                     const float* __restrict__ E, int32_t d, int64_t P,
+                                                     const float* __restrict__ target, const float* __restrict__ head,
+                                                     float scale, uint16_t* __restrict__ dE16,
+                                                     float* __restrict__ partial, float* __restrict__ pred) {
+  const int64_t p = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (p >= P) return;
+  const uint16_t* xi = X16 + p * d_in;
+  const uint16_t* xj = X16 + (P + p) * d_in;
+  const float* ei = E + p * d;
+  const float* ej = E + (P + p) * d;
+  float d2 = 0.0f;
+  for (int c = lane; c < d_in; c += 64) {
+    const float q = bf16_to_f32(xi[c]) - bf16_to_f32(xj[c]);
+    d2 = fmaf(q, q, d2);
+  }
+  for (int c = lane; c < d; c += 64) {
+    const float q = ei[c] - ej[c];
+    d2 = fmaf(q, q, d2);
+  }
+  for (int off = 32; off > 0; off >>= 1) d2 += __shfl_xor(d2, off, 64);
+  const float cc = __expf(head[0]), s = __expf(head[1]);
+  const float ex = __expf(-s * d2);
+  const float lk = cc * expm1f(-s * d2);
+  const float r = (lk - target[p]) / scale;
+  const float dl = 2.0f * r / (scale * float(P));  // d loss / d ln K_hat
+  const float g = dl * (-cc * s * ex);              // d loss / d d2
+  for (int c = lane; c < d; c += 64) {
+    const float q = 2.0f * g * (ei[c] - ej[c]);
+    dE16[p * d + c] = f32_to_bf16(q);
+    dE16[(P + p) * d + c] = f32_to_bf16(-q);
+  }
+  if (lane == 0) {
+    partial[3 * p + 0] = r * r;
+    partial[3 * p + 1] = dl * lk;
+    partial[3 * p + 2] = dl * (-cc * s * d2 * ex);
+    if (pred) {
+      pred[2 * p] = lk;
+      pred[2 * p + 1] = d2;
+    }
   }
 }
 
@@ -505,6 +684,28 @@ hipError_t launch_pair_head(const float* E, int64_t P, int32_t d, const float* t
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, s, partial, P, out3);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_head_log(const uint16_t* X16, int32_t d_in, const float* E, int32_t d, int64_t P,
+                                const float* target, const float* head, float scale, uint16_t* dE16, float* partial,
+                                float* out3, float* pred, hipStream_t s) {
+  const int64_t threads = P * 64;
+  hipLaunchKernelGGL(pair_head_log, dim3(unsigned((threads + 255) / 256)), dim3(256), 0, s, X16, d_in, E, d, P,
+                     target, head, scale, dE16, partial, pred);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, s, partial, P, out3);
+  return hipGetLastError();
+}
+
+hipError_t launch_sat_log_gram(const uint16_t* X16, int32_t d_in, const uint16_t* E, int32_t d, int64_t N_pad,
+                               const float* head, double* K, int64_t ldk, int64_t valid, float* tile_max,
+                               hipStream_t s) {
+  const int64_t T = N_pad / 64;
+  const dim3 grid(unsigned(T), unsigned((T + 1) / 2));
+  hipLaunchKernelGGL(sat_log_gram_kernel, grid, dim3(256), 0, s, X16, d_in, E, d, N_pad, head, K, ldk, valid,
+                     tile_max);
   return hipGetLastError();
 }
 

@@ -183,6 +183,21 @@ qsvm_status qsvm_pair_head(const float* E, int64_t pairs, int32_t d, const float
                  what);
 }
 
+qsvm_status qsvm_pair_head_log(const void* X16, int32_t d_in, const float* E, int32_t d, int64_t pairs,
+                               const float* target, const float* head, float scale, void* dE16, float* partial,
+                               float* out3, float* pred, void* stream) {
+  const char* what = "qsvm_pair_head_log";
+  if ((!X16 && d_in > 0) || !E || !target || !head || !dE16 || !partial || !out3)
+    return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_pair_head_log: NULL pointer");
+  if (pairs < 1 || d_in < 0 || d < 1 || !(scale > 0.0f))
+    return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_pair_head_log: need pairs >= 1, d_in >= 0, d >= 1, scale > 0");
+  if (qsvm::api_injected_failure()) return injected(what);
+  return api_hip(qsvm::launch_pair_head_log(static_cast<const uint16_t*>(X16), d_in, E, d, pairs, target, head, scale,
+                                            static_cast<uint16_t*>(dE16), partial, out3, pred,
+                                            static_cast<hipStream_t>(stream)),
+                 what);
+}
+
 qsvm_status qsvm_mlp_backward(const qsvm_mlp* net, const void* X16, const qsvm_mlp_acts* acts, const void* dE16,
                               int64_t rows, const qsvm_mlp_grads* g, void* stream) {
   const char* what = "qsvm_mlp_backward";
@@ -260,6 +275,23 @@ qsvm_status qsvm_surrogate_gram(const void* E16, int64_t N, int64_t N_pad, int32
   if (qsvm::api_injected_failure()) return injected(what);
   return api_hip(qsvm::launch_sigmoid_gram(static_cast<const uint16_t*>(E16), N_pad, d, alpha_beta, K, ldk, N, tile_max,
                                            static_cast<hipStream_t>(stream)),
+                 what);
+}
+
+qsvm_status qsvm_surrogate_gram_log(const void* X16, int32_t d_in, const void* E16, int32_t d, int64_t N, int64_t N_pad,
+                                    const float* head, double* K, int64_t ldk, float* tile_max, void* stream) {
+  const char* what = "qsvm_surrogate_gram_log";
+  if ((!X16 && d_in > 0) || !E16 || !head || !K || !tile_max)
+    return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_surrogate_gram_log: NULL pointer");
+  if (N < 1 || N_pad < N || N_pad % 64 || N_pad - N >= 64 || d_in < 0 || d_in % 32 || d < 32 || d % 32 || ldk < N)
+    return api_fail(QSVM_ERR_INVALID_ARG,
+                    "qsvm_surrogate_gram_log: need 1 <= N <= N_pad < N + 64, N_pad % 64 == 0, d_in % 32 == 0, "
+                    "d >= 32, d % 32 == 0, ldk >= N");
+  if (N_pad / 64 > 65535)  // launch grid: N_pad / 64 blocks across, half that down
+    return api_fail(QSVM_ERR_UNSUPPORTED, "qsvm_surrogate_gram_log: N_pad above 64 * 65535");
+  if (qsvm::api_injected_failure()) return injected(what);
+  return api_hip(qsvm::launch_sat_log_gram(static_cast<const uint16_t*>(X16), d_in, static_cast<const uint16_t*>(E16), d,
+                                           N_pad, head, K, ldk, N, tile_max, static_cast<hipStream_t>(stream)),
                  what);
 }
 

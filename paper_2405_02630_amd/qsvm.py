@@ -155,6 +155,10 @@ def load_library(path: str = LIB_PATH):
     lib.qsvm_mlp_forward.restype = i32
     lib.qsvm_pair_head.argtypes = [vp, i64, i32, vp, vp, i32, vp, vp, vp, vp]
     lib.qsvm_pair_head.restype = i32
+    lib.qsvm_pair_head_log.argtypes = [vp, i32, vp, i32, i64, vp, vp, f32, vp, vp, vp, vp, vp]
+    lib.qsvm_pair_head_log.restype = i32
+    lib.qsvm_surrogate_gram_log.argtypes = [vp, i32, vp, i32, i64, i64, vp, vp, i64, vp, vp]
+    lib.qsvm_surrogate_gram_log.restype = i32
     lib.qsvm_mlp_backward.argtypes = [P(Mlp), vp, P(MlpActs), vp, i64, P(MlpGrads), vp]
     lib.qsvm_mlp_backward.restype = i32
     lib.qsvm_mlp_workspace_floats.argtypes = [P(Mlp), i64]
@@ -521,6 +525,26 @@ def qsvm_pair_head(E, pairs: int, d: int, target, alpha_beta, dE16, partial, out
                    stream=None):
     _check(load_library().qsvm_pair_head(_p(E), pairs, d, _p(target), _p(alpha_beta), loss_kind, _p(dE16),
                                          _p(partial), _p(out3), _stream_ptr(stream)))
+
+
+def qsvm_pair_head_log(X16, E, pairs: int, target, head, scale: float, dE16, partial, out3, pred=None,
+                       stream=None):
+    """Log-domain pair head on [X16 row, E row] (see include/qsvm.h)."""
+    d_in = 0 if X16 is None else X16.shape[1]
+    _check(load_library().qsvm_pair_head_log(_p(X16) if d_in else None, d_in, _p(E), E.shape[1], pairs, _p(target), _p(head),
+                                             float(scale), _p(dE16), _p(partial), _p(out3),
+                                             None if pred is None else _p(pred), _stream_ptr(stream)))
+
+
+def qsvm_surrogate_gram_log(X16, E16, N: int, head, K, tile_max, stream=None):
+    """K = exp(ln K_hat) of all pairs of rows of [X16, E16]; per-tile max ln K_hat."""
+    if X16 is not None and X16.shape[0] != E16.shape[0]:
+        raise ValueError("X16 and E16 need the same (padded) row count")
+    d_in = 0 if X16 is None else X16.shape[1]
+    _check(load_library().qsvm_surrogate_gram_log(_p(X16) if d_in else None, d_in, _p(E16), E16.shape[1], N,
+                                                  E16.shape[0],
+                                                  _p(head), _p(K), K.stride(0), _p(tile_max), _stream_ptr(stream)))
+    return K
 
 
 def qsvm_mlp_backward(net: Mlp, X16, acts: MlpActs, dE16, rows: int, grads: MlpGrads, stream=None):

@@ -1,14 +1,28 @@
 """Learned surrogate of the quantum kernel, trained on exact entries.
 
-An MLP embedding f: R^n -> R^d_out (widths n -> 512 -> 512 -> 256 by default,
-GELU after the hidden layers, BF16 weights and activations, FP32 master
-weights and accumulation) predicts kernel entries as
-    K_hat(x, y) = sigmoid(alpha <f(x), f(y)> + beta).
-It is trained with AdamW on exact kernel entries computed by the MPS sweep.
-At prediction time the whole N x N surrogate Gram is one BF16 matrix-core
-GEMM with a sigmoid epilogue; every 64 x 64 tile whose largest off-diagonal
-K_hat reaches the threshold tau is recomputed exactly (the exact sweep is
-the fallback), and K_ii = 1.
+An MLP f: R^n -> R^d_out (widths n -> 512 -> 512 -> 256 by default, GELU
+after the hidden layers, BF16 weights and activations, FP32 master weights
+and accumulation) extends each point to the embedding z(x) = [x, f(x)], and
+the kernel is predicted in the log domain from the embeddings' squared
+distance d2 = ||z(x) - z(y)||^2 (their inner products and norms):
+
+    ln K_hat(x, y) = -c (1 - exp(-s d2)),     c = exp(head[0]), s = exp(head[1]).
+
+ln K_hat is 0 for identical points (K_ii = 1 needs no special case), -c s d2
+for close ones, and saturates at -c for unrelated ones: at hundreds of qubits
+kernel values of unrelated points concentrate at a tiny level (the vanishing
+off-diagonal kernels of §4.2.1, ln K ~ -585 for 784-pixel images at two
+repetitions), which no bounded K-domain predictor can represent, so both
+training and judging are in the log domain.  The network is trained with
+AdamW on the exact ln K that the MPS sweep exports (qsvm_gram_opts.log_k).
+
+Prediction: one BF16 matrix-core Gram of the embeddings with the head in
+its epilogue gives K_hat for all pairs and the largest off-diagonal ln K_hat
+per 64 x 64 tile; every tile whose maximum reaches ln(tau) - margin is
+recomputed by the exact sweep (the fallback), where margin bounds how far
+the network under-predicts ln K (the largest ln K - ln K_hat over calibration
+pairs with exact targets).  Entries left to the network are then below tau
+both in K_hat and, up to the calibration, in K.
 
 This module only orchestrates: it allocates device buffers with PyTorch,
 draws training pairs on the host (a seeded data loader) and calls the HIP
@@ -17,7 +31,6 @@ kernels of libqsvm.so through the binding for every arithmetic step.
 
 from __future__ import annotations
 
-import ctypes
 import math
 import time
 from dataclasses import dataclass, field
@@ -37,14 +50,17 @@ class SurrogateConfig:
     d_h2: int = 512
     d_out: int = 256
     lr: float = 1e-3
-    lr_head: float = 1e-2       # learning rate of alpha and beta
+    lr_head: float = 1e-2       # learning rate of (log c, log s)
     weight_decay: float = 1e-4
     beta1: float = 0.9
     beta2: float = 0.999
     eps: float = 1e-8
     pairs_per_step: int = 8192  # multiple of 32 (2 rows per pair, rows in multiples of 64)
-    loss: int = qsvm.LOSS_BCE
-    tau: float = 1e-6           # fallback threshold on the largest off-diagonal K_hat of a tile
+    out_init: float = 0.1       # output layer initialised at this fraction of its He scale (z starts near [x, 0])
+    loss_scale: float = 0.0     # the loss divides ln K errors by this; 0 = the number of features
+    high_log_k: float = -100.0  # training pairs above this ln K form the "close pairs" stratum ...
+    high_fraction: float = 0.125  # ... from which this share of every minibatch is drawn
+    tau: float = 1e-6           # fallback when a tile's largest K_hat may reach tau
     seed: int = 0
 
 
@@ -77,6 +93,7 @@ class Surrogate:
         self.n = n_features
         self.d_in = _round_up(n_features, 64)
         self.dev = torch.device(device)
+        self.scale = c.loss_scale if c.loss_scale > 0 else float(n_features)
         rng = np.random.default_rng(c.seed)
 
         def he(fan_in, fan_out, gain=2.0):
@@ -87,9 +104,10 @@ class Surrogate:
         self.params = [
             _Param(W1, self.dev, True), _Param(np.zeros(c.d_h1), self.dev, False),
             _Param(he(c.d_h1, c.d_h2), self.dev, True), _Param(np.zeros(c.d_h2), self.dev, False),
-            _Param(he(c.d_h2, c.d_out, gain=1.0), self.dev, True), _Param(np.zeros(c.d_out), self.dev, False),
+            _Param(c.out_init * he(c.d_h2, c.d_out, gain=1.0), self.dev, True), _Param(np.zeros(c.d_out), self.dev, False),
         ]
-        self.head = _Param(np.array([1.0 / c.d_out, 0.0]), self.dev, False)  # (alpha, beta)
+        self.head = _Param(np.array([0.0, 0.0]), self.dev, False)  # (log c, log s), set by init_head
+        self.margin = 0.0
         self.step = 0
         # BF16 copies of the initial weights: an AdamW step with lr = 0 and zero gradient
         for p in self.params:
@@ -124,6 +142,7 @@ class Surrogate:
             "dH2": torch.empty((rows, c.d_h2), dtype=b16, device=self.dev),
             "partial": torch.empty(3 * (rows // 2), dtype=f32, device=self.dev),
             "out3": torch.zeros(3, dtype=f32, device=self.dev),
+            "pred": torch.empty(rows, dtype=f32, device=self.dev),
             "idx": torch.empty(rows, dtype=torch.int32, device=self.dev),
             "target": torch.empty(rows // 2, dtype=f32, device=self.dev),
         }
@@ -131,9 +150,9 @@ class Surrogate:
         self._bufs[rows] = b
         return b
 
-    def _acts(self, b) -> qsvm.MlpActs:
+    def _acts(self, b, E16=None) -> qsvm.MlpActs:
         return qsvm.MlpActs(b["H1"].data_ptr(), b["A1"].data_ptr(), b["H2"].data_ptr(), b["A2"].data_ptr(),
-                            b["E"].data_ptr(), b["E16"].data_ptr())
+                            b["E"].data_ptr(), (b["E16"] if E16 is None else E16).data_ptr())
 
     def _grads(self, b) -> qsvm.MlpGrads:
         p = self.params
@@ -142,104 +161,171 @@ class Surrogate:
                              b["ws"].data_ptr(), b["ws"].numel())
 
     # ------------------------------------------------------------------
-    def init_head_from_targets(self, mean_target: float) -> None:
-        """beta := log-odds of the mean training target (clipped to [-20, 20])."""
-        t = min(max(mean_target, 1e-300), 1.0 - 1e-12)
-        beta = float(np.clip(math.log(t) - math.log1p(-t), -20.0, 20.0))
-        self.head.w[1].fill_(beta)
-
-    def train_step(self, X, idx_host: np.ndarray, target_host: np.ndarray) -> None:
-        """One AdamW step on pairs (idx[p], idx[P + p]) with exact targets."""
+    def _pair_pass(self, X, ii: np.ndarray, jj: np.ndarray, target: np.ndarray | None, train: bool):
+        """Forward (and with train=True backward + AdamW) of the pairs (ii[p], jj[p])."""
         import torch
 
         c = self.cfg
-        P = target_host.shape[0]
+        P = ii.shape[0]
         rows = 2 * P
         b = self._buffers(rows)
-        b["idx"].copy_(torch.from_numpy(idx_host.astype(np.int32)))
-        b["target"].copy_(torch.from_numpy(target_host.astype(np.float32)))
+        b["idx"].copy_(torch.from_numpy(np.concatenate([ii, jj]).astype(np.int32)))
+        if target is None:
+            b["target"].zero_()
+        else:
+            b["target"].copy_(torch.from_numpy(np.asarray(target, dtype=np.float32)))
         qsvm.qsvm_gather_features(X, b["idx"], self.d_in, b["X16"])
         net = self.net()
         acts = self._acts(b)
         qsvm.qsvm_mlp_forward(net, b["X16"], rows, acts)
-        qsvm.qsvm_pair_head(b["E"], P, c.d_out, b["target"], self.head.w, b["dE16"], b["partial"], b["out3"],
-                            loss_kind=c.loss)
-        qsvm.qsvm_mlp_backward(net, b["X16"], acts, b["dE16"], rows, self._grads(b))
-        self.step += 1
-        for p in self.params:
-            qsvm.qsvm_adamw(p.w, p.g, p.m, p.v, p.w16, c.lr, c.beta1, c.beta2, c.eps, c.weight_decay, self.step)
-        # head gradient = out3[1:3]
-        qsvm.qsvm_adamw(self.head.w, b["out3"][1:], self.head.m, self.head.v, None, c.lr_head, c.beta1, c.beta2,
-                        c.eps, 0.0, self.step)
+        qsvm.qsvm_pair_head_log(b["X16"], b["E"], P, b["target"], self.head.w, self.scale, b["dE16"], b["partial"],
+                                b["out3"], pred=b["pred"])
+        if train:
+            qsvm.qsvm_mlp_backward(net, b["X16"], acts, b["dE16"], rows, self._grads(b))
+            self.step += 1
+            for p in self.params:
+                qsvm.qsvm_adamw(p.w, p.g, p.m, p.v, p.w16, c.lr, c.beta1, c.beta2, c.eps, c.weight_decay, self.step)
+            qsvm.qsvm_adamw(self.head.w, b["out3"][1:], self.head.m, self.head.v, None, c.lr_head, c.beta1,
+                            c.beta2, c.eps, 0.0, self.step)
+        return b
+
+    def predict_pairs(self, X, ii: np.ndarray, jj: np.ndarray, chunk: int = 8192):
+        """(ln K_hat, d2) of the pairs (ii[p], jj[p]) as host arrays."""
+        out_l, out_d = [], []
+        for p0 in range(0, ii.shape[0], chunk):
+            i = ii[p0:p0 + chunk]
+            j = jj[p0:p0 + chunk]
+            P = i.shape[0]
+            Pp = _round_up(P, 32)
+            if Pp != P:  # pad to whole 64-row blocks with repeats of the first pair
+                i = np.concatenate([i, np.full(Pp - P, i[0])])
+                j = np.concatenate([j, np.full(Pp - P, j[0])])
+            b = self._pair_pass(X, i, j, None, train=False)
+            pr = b["pred"].view(-1, 2)[:P].cpu().numpy().astype(np.float64)
+            out_l.append(pr[:, 0])
+            out_d.append(pr[:, 1])
+        return np.concatenate(out_l), np.concatenate(out_d)
+
+    def init_head(self, X, ii, jj, log_k) -> None:
+        """Set (c, s) to the least-squares fit of ln K = -c (1 - exp(-s d2)) on
+        the given pairs at the current embedding (s on a log grid, c in closed
+        form)."""
+        _, d2 = self.predict_pairs(X, ii, jj)
+        t = np.asarray(log_k, dtype=np.float64)
+        best = None
+        med = float(np.median(d2[d2 > 0])) if np.any(d2 > 0) else 1.0
+        for s in np.geomspace(1e-3 / med, 1e3 / med, 241):
+            u = -np.expm1(-s * d2)
+            den = float(u @ u)
+            if den <= 0:
+                continue
+            cval = max(1e-6, -float(t @ u) / den)
+            err = float(np.mean((cval * u + t) ** 2))
+            if best is None or err < best[0]:
+                best = (err, cval, s)
+        _, cval, s = best
+        self.head.w.copy_(self._f32([math.log(cval), math.log(s)]))
+
+    def _f32(self, v):
+        import torch
+
+        return torch.as_tensor(np.asarray(v, dtype=np.float32), device=self.dev)
+
+    def head_values(self):
+        h = self.head.w.cpu().numpy().astype(np.float64)
+        return math.exp(h[0]), math.exp(h[1])
 
     def last_loss(self, pairs: int) -> float:
         return float(self._buffers(2 * pairs)["out3"][0].item())
 
-    def fit(self, X, train_points: np.ndarray, K_train: np.ndarray, steps: int, log_every: int = 50) -> FitReport:
-        """Train on the exact Gram K_train of the points train_points (host arrays)."""
+    def fit(self, X, ii: np.ndarray, jj: np.ndarray, log_k: np.ndarray, steps: int, log_every: int = 50) -> FitReport:
+        """Train on exact pairs (ii[p], jj[p]) with targets log_k[p] = ln K.
+
+        Every minibatch draws high_fraction of its pairs from the pairs with
+        ln K above high_log_k (when there are any) and the rest uniformly: a
+        stratified loader, so that the rare close pairs, the ones the fallback
+        must find, are seen in every step."""
         import torch
 
         c = self.cfg
         P = c.pairs_per_step
         if P % 32:
             raise ValueError("pairs_per_step must be a multiple of 32")
-        S = train_points.shape[0]
         rng = np.random.default_rng(c.seed + 1)
-        iu = np.triu_indices(S, 1)
-        self.init_head_from_targets(float(np.mean(K_train[iu])))
+        high = np.flatnonzero(log_k > c.high_log_k)
+        n_high = int(round(c.high_fraction * P)) if high.size else 0
         hist = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for s in range(steps):
-            i = rng.integers(0, S, P)
-            j = rng.integers(0, S - 1, P)
-            j = j + (j >= i)
-            idx = np.concatenate([train_points[i], train_points[j]])
-            self.train_step(X, idx, K_train[i, j])
+            sel = rng.integers(0, ii.shape[0], P - n_high)
+            if n_high:
+                sel = np.concatenate([sel, high[rng.integers(0, high.size, n_high)]])
+            self._pair_pass(X, ii[sel], jj[sel], log_k[sel], train=True)
             if log_every and (s % log_every == 0 or s == steps - 1):
                 hist.append((s, self.last_loss(P)))
         torch.cuda.synchronize()
         return FitReport(steps, time.perf_counter() - t0, hist)
 
+    def calibrate(self, X, ii, jj, log_k, band: float = 20.0, safety: float = 1.0) -> float:
+        """Set the margin gram() flags tiles with: the largest under-prediction
+        ln K - ln K_hat over the given pairs whose exact ln K is at least
+        ln(tau) - band, plus `safety` nats (>= 0).  A pair with K >= tau must
+        be flagged, i.e. ln K_hat >= ln(tau) - margin, which the margin
+        guarantees for every calibration pair of that kind; pairs far below tau
+        need no flag.  Without such pairs, the largest under-prediction over
+        all given pairs is used."""
+        lh, _ = self.predict_pairs(X, ii, jj)
+        lk = np.asarray(log_k, dtype=np.float64)
+        under = lk - lh
+        near = lk >= math.log(self.cfg.tau) - band
+        worst = float(np.max(under[near])) if np.any(near) else float(np.max(under))
+        self.margin = max(0.0, worst) + safety
+        return self.margin
+
     # ------------------------------------------------------------------
     def embed(self, X, chunk: int = 32768):
-        """BF16 embeddings of every row of X, padded to a multiple of 64 rows."""
+        """BF16 inputs and MLP outputs of every row of X, padded to a multiple of 64 rows."""
         import torch
 
         N = X.shape[0]
         Np = _round_up(N, 64)
+        X16 = torch.empty((Np, self.d_in), dtype=torch.bfloat16, device=self.dev)
         E16 = torch.empty((Np, self.cfg.d_out), dtype=torch.bfloat16, device=self.dev)
         net = self.net()
         for r0 in range(0, Np, chunk):
             rows = min(chunk, Np - r0)
             b = self._buffers(rows)
             torch.arange(r0, r0 + rows, out=b["idx"])  # on the device; rows >= N are zero padding
-            qsvm.qsvm_gather_features(X, b["idx"], self.d_in, b["X16"])
-            qsvm.qsvm_mlp_forward(net, b["X16"], rows, self._acts(b))
-            E16[r0:r0 + rows].copy_(b["E16"])
-        return E16
+            qsvm.qsvm_gather_features(X, b["idx"], self.d_in, X16[r0:r0 + rows])
+            qsvm.qsvm_mlp_forward(net, X16[r0:r0 + rows], rows, self._acts(b, E16[r0:r0 + rows]))
+        return X16, E16
 
-    def gram(self, X, mps: "qsvm.MPS | None", K=None, tau: float | None = None):
+    def gram(self, X, mps: "qsvm.MPS | None", K=None, tau: float | None = None, margin: float | None = None):
         """Surrogate Gram of the rows of X with exact fallback on flagged tiles.
 
-        Returns (K, flagged): flagged is a 1-element device int32 tensor, the
-        number of flagged tiles.  mps (the exact MPS of the same points) feeds
-        the fallback; pass None to skip it.  Nothing here waits for the GPU:
-        the fallback reads the flagged count on the device."""
+        A tile is flagged when its largest off-diagonal ln K_hat reaches
+        ln(tau) - margin (tau = 0 flags every tile).  Returns (K, flagged):
+        flagged is a 1-element device int32 tensor, the number of flagged
+        tiles.  mps (the exact MPS of the same points) feeds the fallback;
+        pass None to skip it.  Nothing here waits for the GPU: the fallback
+        reads the flagged count on the device."""
         import torch
 
         tau = self.cfg.tau if tau is None else tau
+        margin = self.margin if margin is None else margin
+        thresh = -math.inf if tau <= 0.0 else math.log(tau) - margin
         N = X.shape[0]
-        E16 = self.embed(X)
+        X16, E16 = self.embed(X)
         Np = E16.shape[0]
         T = Np // 64
         if K is None:
             K = torch.empty((N, N), dtype=torch.float64, device=self.dev)
         tile_max = torch.empty(T * T, dtype=torch.float32, device=self.dev)
-        qsvm.qsvm_surrogate_gram(E16, N, self.head.w, K, tile_max)
+        qsvm.qsvm_surrogate_gram_log(X16, E16, N, self.head.w, K, tile_max)
         tiles = torch.empty(T * (T + 1), dtype=torch.int32, device=self.dev)
         count = torch.empty(1, dtype=torch.int32, device=self.dev)
-        qsvm.qsvm_flag_tiles(tile_max, T, tau, tiles, count)  # clears count first
+        qsvm.qsvm_flag_tiles(tile_max, T, max(thresh, -3.0e38), tiles, count)  # clears count first
         if mps is not None:
             qsvm.qsvm_gram_sym_tiles_dev(mps, tiles, count, T * (T + 1) // 2, K)
         return K, count

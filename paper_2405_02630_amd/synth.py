@@ -144,6 +144,36 @@ def image_near_duplicates(seed: int = 0, n_base: int = 256):
     return wl.X, Xp, idx, eps
 
 
+def images784_with_near_duplicates(N: int = 32768, n_copies: int = 2048, seed: int = 0):
+    """N 784-pixel images of which n_copies are near duplicates: copies
+    x + eps z of distinct random base images (eps cycling through 1e-3, 3e-3,
+    1e-2, 3e-2, 1e-1), rows shuffled.  Returns (X, labels, base_of_row) with
+    base_of_row[r] = the row holding the original of a copy, -1 otherwise."""
+    n_img = N - n_copies
+    wl = images784(seed=seed, n_train=n_img, n_test=0)
+    g_pick, g_eps, g_perm = _streams(seed + 23, 3)
+    bases = g_pick.choice(n_img, size=n_copies, replace=False)
+    eps = np.array([1e-3, 3e-3, 1e-2, 3e-2, 1e-1])[np.arange(n_copies) % 5]
+    copies = np.clip(wl.X[bases] + eps[:, None] * g_eps.standard_normal((n_copies, wl.X.shape[1])), 0.0, PI)
+    X = np.concatenate([wl.X, copies])
+    labels = np.concatenate([wl.labels, wl.labels[bases]])
+    src = np.concatenate([np.full(n_img, -1), bases])
+    perm = g_perm.permutation(N)
+    inv = np.empty(N, dtype=np.int64)
+    inv[perm] = np.arange(N)
+    base_of_row = np.where(src[perm] >= 0, inv[np.maximum(src[perm], 0)], -1)
+    return X[perm], labels[perm], base_of_row
+
+
+def near_identical_images(N: int = 4096, eps: float = 4e-4, seed: int = 0) -> np.ndarray:
+    """N copies of one 784-pixel image, each x + eps z (z ~ N(0, I)) clipped to
+    [0, pi]: every pair is a near duplicate (the worst case for work that only
+    entries near 1 need)."""
+    wl = images784(seed=seed, n_train=1, n_test=0)
+    (g,) = _streams(seed + 11, 1)
+    return np.clip(wl.X[0][None, :] + eps * g.standard_normal((N, wl.X.shape[1])), 0.0, PI)
+
+
 def uneven_jobs(seed: int = 0, n_jobs: int = 64, n_choices=(16, 64, 196, 400, 784),
                 N_lo: int = 64, N_hi: int = 2048, reps_choices=(2, 3)):
     """Independent Gram jobs with n, N and reps drawn per job; features uniform on [0, pi]."""

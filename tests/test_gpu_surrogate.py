@@ -29,10 +29,6 @@ def gpu():
     return require_gpu()
 
 
-def _nrel(a, b):
-    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300))
-
-
 def _bf16_dev(x):
     import torch
 
@@ -51,11 +47,35 @@ def _host(t):
     return t.to(torch.float64).cpu().numpy()
 
 
-def _setup(seed=0, rows=128):
+# Element-wise bars.  A product of K-term dot products of BF16 values summed in
+# FP32 is exact per term and rounds the running sum: its error is at most
+# K u sum|a||b| (u = 2^-24) and typically sqrt(K) u sum|a||b|; the bar is
+# GEMM_REL * (|A| |B|)_ij with GEMM_REL = 8 sqrt(K) u, per element.  A value
+# the kernel rounds to BF16 may differ from the reference's rounding of the
+# FP64 value by one BF16 spacing (at most 2^-7 of the value) where the two
+# sit on either side of a rounding boundary: bar = 2^-7 |ref| plus the bar of
+# the value before rounding.
+U32 = 2.0**-24
+U16 = 2.0**-8
+GELU_ABS = 4e-7
+
+
+def _gemm_bar(absA, absB):
+    K = absA.shape[1]
+    return 8.0 * math.sqrt(K) * U32 * (absA @ absB) + 1e-30
+
+
+def _assert_elementwise(got, ref, bar, what):
+    d = np.abs(np.asarray(got, np.float64) - ref)
+    worst = np.unravel_index(np.argmax(d - bar), d.shape)
+    assert np.all(d <= bar), (what, worst, float(d[worst]), float(np.asarray(bar)[worst] if np.ndim(bar) else bar))
+
+
+def _setup(seed=0, rows=128, dims=DIMS):
     import torch
 
     rng = np.random.default_rng(seed)
-    d0, d1, d2, d3 = DIMS
+    d0, d1, d2, d3 = dims
     W = [ref.bf16_round(rng.normal(0, math.sqrt(2 / d0), (d0, d1))), rng.normal(0, 0.1, d1),
          ref.bf16_round(rng.normal(0, math.sqrt(2 / d1), (d1, d2))), rng.normal(0, 0.1, d2),
          ref.bf16_round(rng.normal(0, math.sqrt(1 / d2), (d2, d3))), rng.normal(0, 0.1, d3)]
@@ -80,13 +100,61 @@ def _setup(seed=0, rows=128):
     return W, X, dev, net, bufs, acts
 
 
-def _emulated_forward(W, X):
-    H1 = X @ W[0] + W[1]
-    A1 = ref.bf16_round(ref.gelu(H1))
-    H2 = A1 @ W[2] + W[3]
-    A2 = ref.bf16_round(ref.gelu(H2))
-    E = A2 @ W[4] + W[5]
+def _check_forward(W, X, bufs):
+    """Each layer against the FP64 reference evaluated on the kernel's own
+    inputs to that layer (so rounding differences do not compound)."""
+    H1, A1, H2, A2, E = (_host(bufs[k]) for k in ("H1", "A1", "H2", "A2", "E"))
+    _assert_elementwise(H1, X @ W[0] + W[1], _gemm_bar(np.abs(X), np.abs(W[0])) + 1e-7 * np.abs(W[1]), "H1")
+    g1 = ref.gelu(H1)
+    _assert_elementwise(A1, ref.bf16_round(g1), 2 * U16 * np.abs(g1) + 1e-6 * (1 + np.abs(H1)), "A1")
+    _assert_elementwise(H2, A1 @ W[2] + W[3], _gemm_bar(np.abs(A1), np.abs(W[2])) + 1e-7 * np.abs(W[3]), "H2")
+    g2 = ref.gelu(H2)
+    _assert_elementwise(A2, ref.bf16_round(g2), 2 * U16 * np.abs(g2) + 1e-6 * (1 + np.abs(H2)), "A2")
+    _assert_elementwise(E, A2 @ W[4] + W[5], _gemm_bar(np.abs(A2), np.abs(W[4])) + 1e-7 * np.abs(W[5]), "E")
+    assert np.array_equal(_host(bufs["E16"]), ref.bf16_round(E))
     return H1, A1, H2, A2, E
+
+
+def _check_backward(W, X, acts_h, dEk, grads, dH1, dH2):
+    """Backward against the FP64 reference on the kernel's own activations and
+    incoming gradients, element by element."""
+    H1, A1, H2, A2 = acts_h
+    aX, aA1, aA2, adE = np.abs(X), np.abs(A1), np.abs(A2), np.abs(dEk)
+    _assert_elementwise(_host(grads["dW3"]), A2.T @ dEk, _gemm_bar(aA2.T, adE), "dW3")
+    _assert_elementwise(_host(grads["db3"]), dEk.sum(0), _gemm_bar(np.ones((1, dEk.shape[0])), adE)[0], "db3")
+    acc2 = dEk @ W[4].T
+    pre2 = acc2 * ref.gelu_grad(H2)
+    # FP32 gelu'(h) = Phi(h) + h phi(h) carries an absolute error of a few
+    # 1e-8 where 1 + erf cancels (h << 0): GELU_ABS |acc| on top
+    bar2 = (_gemm_bar(adE, np.abs(W[4].T)) * np.abs(ref.gelu_grad(H2)) * 2 + GELU_ABS * np.abs(acc2)
+            + 2 * U16 * np.abs(pre2) + 1e-30)
+    dH2k = _host(dH2)
+    _assert_elementwise(dH2k, ref.bf16_round(pre2), bar2, "dH2")
+    _assert_elementwise(_host(grads["dW2"]), A1.T @ dH2k, _gemm_bar(aA1.T, np.abs(dH2k)), "dW2")
+    _assert_elementwise(_host(grads["db2"]), dH2k.sum(0), _gemm_bar(np.ones((1, dH2k.shape[0])), np.abs(dH2k))[0], "db2")
+    acc1 = dH2k @ W[2].T
+    pre1 = acc1 * ref.gelu_grad(H1)
+    bar1 = (_gemm_bar(np.abs(dH2k), np.abs(W[2].T)) * np.abs(ref.gelu_grad(H1)) * 2 + GELU_ABS * np.abs(acc1)
+            + 2 * U16 * np.abs(pre1) + 1e-30)
+    dH1k = _host(dH1)
+    _assert_elementwise(dH1k, ref.bf16_round(pre1), bar1, "dH1")
+    _assert_elementwise(_host(grads["dW1"]), X.T @ dH1k, _gemm_bar(aX.T, np.abs(dH1k)), "dW1")
+    _assert_elementwise(_host(grads["db1"]), dH1k.sum(0), _gemm_bar(np.ones((1, dH1k.shape[0])), np.abs(dH1k))[0], "db1")
+
+
+def _backward(net, bufs, acts, dev, dE16, rows, dims):
+    import torch
+
+    grads = {k: torch.empty_like(dev[w], dtype=torch.float32) for k, w in
+             zip(["dW1", "db1", "dW2", "db2", "dW3", "db3"], ["W1", "b1", "W2", "b2", "W3", "b3"])}
+    dH1 = torch.empty((rows, dims[1]), dtype=torch.bfloat16, device="cuda:0")
+    dH2 = torch.empty((rows, dims[2]), dtype=torch.bfloat16, device="cuda:0")
+    ws = torch.empty(qsvm.qsvm_mlp_workspace_floats(net, rows), dtype=torch.float32, device="cuda:0")
+    g = qsvm.MlpGrads(*(grads[k].data_ptr() for k in ("dW1", "db1", "dW2", "db2", "dW3", "db3")),
+                      dH1.data_ptr(), dH2.data_ptr(), ws.data_ptr(), ws.numel())
+    qsvm.qsvm_mlp_backward(net, bufs["X16"], acts, dE16, rows, g)
+    torch.cuda.synchronize()
+    return grads, dH1, dH2
 
 
 def test_mlp_forward_matches_reference():
@@ -95,14 +163,34 @@ def test_mlp_forward_matches_reference():
     W, X, dev, net, bufs, acts = _setup(0)
     qsvm.qsvm_mlp_forward(net, bufs["X16"], X.shape[0], acts)
     torch.cuda.synchronize()
-    H1, A1, H2, A2, E = _emulated_forward(W, X)
-    assert _nrel(_host(bufs["H1"]), H1) < 1e-5  # first layer: exact BF16 products, FP32 sums
-    assert _nrel(_host(bufs["A1"]), A1) < 4e-3  # one BF16 rounding of the activation
-    assert _nrel(_host(bufs["H2"]), H2) < 5e-3
-    assert _nrel(_host(bufs["E"]), E) < 1e-2
-    full = ref.forward(W, X)["E"]  # no intermediate rounding at all
-    assert _nrel(_host(bufs["E"]), full) < 2e-2
-    assert np.array_equal(_host(bufs["E16"]), ref.bf16_round(_host(bufs["E"])))
+    _check_forward(W, X, bufs)
+    # the whole chain against the FP64 forward without intermediate rounding:
+    # three layers of BF16 activations, each within 2^-8 relative
+    full = ref.forward(W, X)["E"]
+    E = _host(bufs["E"])
+    assert np.max(np.abs(E - full)) <= 0.05 * np.max(np.abs(full))
+
+
+PROD = (832, 512, 512, 256)  # 784 pixels padded to 832 -> 512 -> 512 -> 256
+
+
+def test_mlp_forward_backward_production_shape_elementwise():
+    """The surrogate's production widths on 16384 rows: 13 K steps in layer 1,
+    the XCD tile order, and weight gradients split 8 ways along the rows
+    (summed in fixed order) -- every element of every output against the FP64
+    reference on the kernel's own layer inputs."""
+    import torch
+
+    rows = 16384
+    W, X, dev, net, bufs, acts = _setup(11, rows=rows, dims=PROD)
+    qsvm.qsvm_mlp_forward(net, bufs["X16"], rows, acts)
+    torch.cuda.synchronize()
+    H1, A1, H2, A2, E = _check_forward(W, X, bufs)
+    assert qsvm.qsvm_mlp_workspace_floats(net, rows) >= 8 * 832 * 512  # the 8-way split is in use
+    rng = np.random.default_rng(12)
+    dEk = ref.bf16_round(rng.normal(0, 1e-3, (rows, PROD[3])))
+    grads, dH1, dH2 = _backward(net, bufs, acts, dev, _bf16_dev(dEk), rows, PROD)
+    _check_backward(W, X, (H1, A1, H2, A2), dEk, grads, dH1, dH2)
 
 
 @pytest.mark.parametrize("kind", [qsvm.LOSS_MSE, qsvm.LOSS_BCE], ids=["mse", "bce"])
@@ -128,37 +216,89 @@ def test_pair_head_and_backward_match_reference(kind):
     assert abs(o[0] - loss) <= 1e-5 * max(1.0, abs(loss))
     assert abs(o[1] - da) <= 1e-4 * max(1e-3, abs(da)) + 1e-7
     assert abs(o[2] - db) <= 1e-4 * max(1e-3, abs(db)) + 1e-7
-    assert _nrel(_host(dE16), dE) < 4e-3
+    _assert_elementwise(_host(dE16), dE, 2 * U16 * np.abs(dE) + 1e-6 * np.max(np.abs(dE)), "dE16")
+    acts_h = tuple(_host(bufs[k]) for k in ("H1", "A1", "H2", "A2"))
+    grads, dH1, dH2 = _backward(net, bufs, acts, dev, dE16, rows, DIMS)
+    _check_backward(W, X, acts_h, _host(dE16), grads, dH1, dH2)
 
-    grads = {k: torch.empty_like(dev[w], dtype=torch.float32) for k, w in
-             zip(["dW1", "db1", "dW2", "db2", "dW3", "db3"], ["W1", "b1", "W2", "b2", "W3", "b3"])}
-    dH1 = torch.empty((rows, DIMS[1]), dtype=torch.bfloat16, device="cuda:0")
-    dH2 = torch.empty((rows, DIMS[2]), dtype=torch.bfloat16, device="cuda:0")
-    ws = torch.empty(qsvm.qsvm_mlp_workspace_floats(net, rows), dtype=torch.float32, device="cuda:0")
-    g = qsvm.MlpGrads(*(grads[k].data_ptr() for k in ("dW1", "db1", "dW2", "db2", "dW3", "db3")),
-                      dH1.data_ptr(), dH2.data_ptr(), ws.data_ptr(), ws.numel())
-    qsvm.qsvm_mlp_backward(net, bufs["X16"], acts, dE16, rows, g)
+
+def test_pair_head_log_production_shape_elementwise():
+    """The log-domain head on 8192 pairs of [784-pixel input padded to 832,
+    256-wide MLP output]: loss, its head gradients, ln K_hat, d2 and the
+    embedding gradient of every element against oracle/mlp.py."""
+    import torch
+
+    P, d_in, d = 8192, 832, 256
+    rng = np.random.default_rng(21)
+    Xr = ref.bf16_round(rng.uniform(0, math.pi, (2 * P, d_in)) * (rng.random((2 * P, d_in)) < 0.7))
+    Xr[P:] = ref.bf16_round(np.clip(Xr[:P] + rng.normal(0, 0.05, (P, d_in)) * (rng.random((P, 1)) < 0.3), 0, math.pi))
+    E = rng.normal(0, 0.2, (2 * P, d)).astype(np.float32).astype(np.float64)
+    target = np.float32(rng.uniform(-600, 0, P)).astype(np.float64)
+    lc, ls = float(np.float32(math.log(585.0))), float(np.float32(math.log(0.03)))
+    scale = 784.0
+    dE16 = torch.empty((2 * P, d), dtype=torch.bfloat16, device="cuda:0")
+    partial = torch.empty(3 * P, dtype=torch.float32, device="cuda:0")
+    out3 = torch.empty(3, dtype=torch.float32, device="cuda:0")
+    pred = torch.empty(2 * P, dtype=torch.float32, device="cuda:0")
+    qsvm.qsvm_pair_head_log(_bf16_dev(Xr), _f32_dev(E), P, _f32_dev(target), _f32_dev([lc, ls]), scale, dE16,
+                            partial, out3, pred=pred)
     torch.cuda.synchronize()
-    # reference backward on the kernel's own forward activations and dE16,
-    # with the BF16 rounding of dH2 and dH1 emulated
-    H1, A1, H2, A2 = _host(bufs["H1"]), _host(bufs["A1"]), _host(bufs["H2"]), _host(bufs["A2"])
-    dEk = _host(dE16)
-    dW3 = A2.T @ dEk
-    dH2r = ref.bf16_round((dEk @ W[4].T) * ref.gelu_grad(H2))
-    dW2 = A1.T @ dH2r
-    dH1r = ref.bf16_round((dH2r @ W[2].T) * ref.gelu_grad(H1))
-    dW1 = X.T @ dH1r
-    assert _nrel(_host(grads["dW3"]), dW3) < 1e-5
-    assert _nrel(_host(grads["db3"]), dEk.sum(0)) < 1e-5
-    assert _nrel(_host(dH2), dH2r) < 4e-3
-    assert _nrel(_host(grads["dW2"]), dW2) < 5e-3
-    assert _nrel(_host(grads["dW1"]), dW1) < 1e-2
-    # and against the unrounded FP64 backward of the FP64 forward
-    full = ref.forward(W, X)
-    _, dEf, _, _ = ref.pair_loss(full["E"], target, 0.05, -0.3, "bce" if kind == qsvm.LOSS_BCE else "mse")
-    gf = ref.backward(W, X, full, dEf)
-    assert _nrel(_host(grads["dW1"]), gf[0]) < 5e-2
-    assert _nrel(_host(grads["dW3"]), gf[4]) < 5e-2
+    loss, dE, dlc, dls, lh, d2 = ref.sat_log_pair_loss(Xr, E, target, lc, ls, scale)
+    pr = pred.view(-1, 2).cpu().numpy().astype(np.float64)
+    # d2: FP32 sum of ~1100 squares (relative sqrt(K) u each way); ln K_hat from it
+    _assert_elementwise(pr[:, 1], d2, 1e-5 * d2 + 1e-6, "d2")
+    c, s = math.exp(lc), math.exp(ls)
+    _assert_elementwise(pr[:, 0], lh, c * s * np.exp(-s * d2) * 1e-5 * d2 + 1e-5 * np.abs(lh) + 1e-6, "lnK_hat")
+    o = out3.cpu().numpy()
+    assert abs(o[0] - loss) <= 1e-4 * loss
+    assert abs(o[1] - dlc) <= 1e-3 * abs(dlc) + 1e-6 and abs(o[2] - dls) <= 1e-3 * abs(dls) + 1e-6
+    _assert_elementwise(_host(dE16), dE, 2 * U16 * np.abs(dE) + 1e-4 * np.max(np.abs(dE)), "dE16")
+
+
+@pytest.mark.parametrize("N,d_in,d", [(150, 832, 256), (200, 64, 128), (130, 0, 64), (64, 832, 32), (300, 96, 256)])
+def test_surrogate_gram_log_elementwise_and_tile_max(N, d_in, d):
+    """Ragged N (odd tile counts: the last 128-row block half empty), an exact
+    tile multiple, and input parts from none to the production 832."""
+    import torch
+
+    rng = np.random.default_rng(N + d_in)
+    Np = (N + 63) // 64 * 64
+    base = rng.uniform(0, 1, (8, d_in))
+    Xr = ref.bf16_round(base[rng.integers(0, 8, Np)] + rng.normal(0, 0.02, (Np, d_in)))  # clusters: K spread out
+    E = ref.bf16_round(rng.normal(0, 0.1, (Np, d)))
+    lc, ls = float(np.float32(math.log(30.0))), float(np.float32(math.log(0.2)))
+    K = torch.full((N, N), -1.0, dtype=torch.float64, device="cuda:0")
+    T = Np // 64
+    tmax = torch.empty(T * T, dtype=torch.float32, device="cuda:0")
+    x16 = _bf16_dev(Xr) if d_in else None
+    qsvm.qsvm_surrogate_gram_log(x16, _bf16_dev(E), N, _f32_dev([lc, ls]), K, tmax)
+    torch.cuda.synchronize()
+    Kh = K.cpu().numpy()
+    L, Kr = ref.sat_log_gram(Xr[:N], E[:N], lc, ls)
+    Z = np.concatenate([Xr[:N], E[:N]], axis=1)
+    nrm = np.sum(Z * Z, axis=1)
+    # d2 from norms and a BF16 inner product in FP32: error ~ 1e-6 (|z_i|^2 + |z_j|^2)
+    err_d2 = 2e-6 * (nrm[:, None] + nrm[None, :]) + 1e-7
+    err_l = 30.0 * 0.2 * err_d2 + 1e-6 * np.abs(L) + 1e-6  # |d ln K_hat / d d2| <= c s
+    _assert_elementwise(Kh, Kr, Kr * np.expm1(err_l) + 1e-30, "K_hat")
+    assert np.all(np.diag(Kh) == 1.0)
+    assert np.array_equal(Kh, Kh.T)
+    tm = tmax.cpu().numpy().reshape(T, T)
+    tref = ref.tile_max_offdiag(L)
+    valid = np.isfinite(tref)
+    assert np.array_equal(np.isfinite(tm), valid)
+    tbar = np.array([[err_l[a * 64:(a + 1) * 64, b * 64:(b + 1) * 64].max() for b in range(T)] for a in range(T)])
+    assert np.all(np.abs(tm[valid] - tref[valid]) <= tbar[valid])
+    # flags in the log domain: exactly the tiles at or above the threshold
+    thr = float(np.median(tm[np.triu_indices(T)][np.isfinite(tm[np.triu_indices(T)])]))
+    tiles = torch.empty(T * (T + 1), dtype=torch.int32, device="cuda:0")
+    count = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+    qsvm.qsvm_flag_tiles(tmax, T, thr, tiles, count)
+    torch.cuda.synchronize()
+    c = int(count.item())
+    got = {tuple(x) for x in tiles.cpu().numpy()[: 2 * c].reshape(-1, 2)}
+    want = {(ti, tj) for ti in range(T) for tj in range(ti, T) if tm[ti, tj] >= np.float32(thr)}
+    assert got == want and c == len(want)
 
 
 def test_adamw_matches_reference():
@@ -238,76 +378,63 @@ def test_gram_sym_tiles_equals_full_gram_on_those_tiles():
     assert np.all(Kh[~mask] == -2.0)
 
 
-def test_surrogate_training_converges_without_degrading():
-    """Four-qubit, one-rep kernels of uniform features (K spread over [0, 0.6]):
-    the training loss falls, and the held-out squared error ends no worse than
-    the untrained network's and at the level of the best constant predictor
-    (the variance of K).  On these kernels the inner-product head does not
-    capture the pair structure beyond that level; see the surrogate notes in
-    the design document."""
+def _near_duplicate_rich(seed, n_img, n_base):
+    """784-pixel images plus eps-perturbed copies of the first n_base of them,
+    rows shuffled: ln K spans [-660, 0] (copies of one image down to ~-0.01)."""
+    wl = synth.images784(seed=seed, n_train=n_img, n_test=0, reps=2)
+    Xp, _, _ = synth.near_duplicates(wl.X[:n_base], seed=seed + 1)
+    X = np.concatenate([wl.X, Xp])
+    return X[np.random.default_rng(seed).permutation(X.shape[0])]
+
+
+def test_surrogate_learns_the_log_kernel_and_meets_the_bar():
+    """What the trained network gains, on 784-pixel images (reps = 2) with
+    near duplicates: trained on half of the exact pairs (ln K from the MPS
+    sweep), judged on a quarter held out.  Its held-out log-domain error is
+    below the best constant predictor's (on all pairs, and by a wide margin on
+    the close pairs) and below the untrained network's on the close pairs;
+    calibrated on the last quarter, the Gram with exact fallback stays within
+    1e-5 of the exact Gram on every pair while recomputing only a part of the
+    tiles."""
     import torch
 
     from paper_2405_02630_amd.surrogate import Surrogate, SurrogateConfig
 
-    n, reps = 4, 1
-    Xh = synth.uniform_features(640, n, seed=1)
+    Xh = _near_duplicate_rich(31, 1024, 64)  # 1344 points, 21 tiles a side
+    N = Xh.shape[0]
     X = torch.as_tensor(Xh, device="cuda:0")
-    train = np.arange(0, 384)
-    hold = np.arange(384, 640)
-    Kfull = qsvm.qsvm_gram_sym(encode(Xh, reps)).cpu().numpy()
-    assert np.max(np.abs(Kfull[:40, :40] - statevector.sv_gram(Xh[:40], reps))) <= K_ABS_TOL
-    cfg = SurrogateConfig(d_h1=128, d_h2=128, d_out=64, pairs_per_step=1024, lr=2e-3, lr_head=2e-2, seed=0)
-    sur = Surrogate(n, cfg)
-    iu = np.triu_indices(len(hold), 1)
-    Kt = Kfull[np.ix_(hold, hold)][iu]
-
-    def held_out_mse():
-        Kh, _ = sur.gram(X, None, tau=2.0)  # tau > 1: no tile is flagged, pure surrogate
-        Ks = Kh.cpu().numpy()[np.ix_(hold, hold)]
-        return float(np.mean((Ks[iu] - Kt) ** 2))
-
-    sur.init_head_from_targets(float(np.mean(Kfull[np.ix_(train, train)][np.triu_indices(len(train), 1)])))
-    before = held_out_mse()
-    rep = sur.fit(X, train, Kfull[np.ix_(train, train)], steps=600, log_every=100)
-    after = held_out_mse()
+    m = encode(Xh, 2)
+    L = torch.empty((N, N), dtype=torch.float64, device="cuda:0")
+    exact = qsvm.qsvm_gram_sym(m, log_k=L)
+    Lh, Kx = L.cpu().numpy(), exact.cpu().numpy()
+    ii, jj = np.triu_indices(N, 1)
+    lk = Lh[ii, jj]
+    part = np.random.default_rng(2).random(ii.size)
+    tr, cal, ho = part < 0.5, (part >= 0.5) & (part < 0.75), part >= 0.75
+    sur = Surrogate(784, SurrogateConfig(pairs_per_step=4096, seed=3))
+    pick = np.random.default_rng(4).choice(np.flatnonzero(tr), 65536, replace=False)
+    sur.init_head(X, ii[pick], jj[pick], lk[pick])
+    lh0, _ = sur.predict_pairs(X, ii[ho], jj[ho])
+    rep = sur.fit(X, ii[tr], jj[tr], lk[tr], steps=400, log_every=100)
     assert rep.loss_history[-1][1] < rep.loss_history[0][1]
-    assert after <= 1.05 * before, (before, after)
-    assert after <= 1.2 * float(np.var(Kt)), (after, float(np.var(Kt)))
-
-
-def test_surrogate_784_meets_the_bar_faster_than_exact():
-    """What the trained network gains over the exact sweep alone, on 784-pixel
-    images (reps = 2): trained on the exact Gram of 512 points, its Gram of
-    2048 further points (with fallback at tau = 1e-6) stays within 1e-5 of the
-    exact Gram on every pair and takes a fraction of the exact sweep's time."""
-    import torch
-
-    from paper_2405_02630_amd.surrogate import Surrogate, SurrogateConfig
-
-    wl = synth.images784(seed=21, n_train=2560, n_test=0, reps=2)
-    Xh = wl.X
-    X_train = torch.as_tensor(Xh[:512], device="cuda:0")
-    X_eval = torch.as_tensor(Xh[512:], device="cuda:0")
-    K_train = qsvm.qsvm_gram_sym(encode(Xh[:512], 2)).cpu().numpy()
-    sur = Surrogate(784, SurrogateConfig(pairs_per_step=4096))
-    sur.fit(X_train, np.arange(512), K_train, steps=100, log_every=50)
-    m = encode(Xh[512:], 2)
-    exact = torch.empty((2048, 2048), dtype=torch.float64, device="cuda:0")
-    Ks = torch.empty_like(exact)
-    qsvm.qsvm_gram_sym(m, exact)
-    sur.gram(X_eval, m, K=Ks)  # warm-up
+    lh1, _ = sur.predict_pairs(X, ii[ho], jj[ho])
+    close = lk[ho] > -100.0
+    assert close.sum() >= 50
+    e0, e1 = np.abs(lh0 - lk[ho]), np.abs(lh1 - lk[ho])
+    ec = np.abs(np.median(lk[tr]) - lk[ho])  # best constant (median of the training targets)
+    print(f"held-out mean |d ln K|: trained {e1.mean():.2f}, untrained {e0.mean():.2f}, constant {ec.mean():.2f}; "
+          f"close pairs: {e1[close].mean():.2f} / {e0[close].mean():.2f} / {ec[close].mean():.2f}", flush=True)
+    assert e1.mean() < ec.mean()
+    assert e1[close].mean() < 0.1 * ec[close].mean()
+    assert e1[close].mean() < e0[close].mean()
+    margin = sur.calibrate(X, ii[cal], jj[cal], lk[cal])
+    Ks, flagged = sur.gram(X, m)
     torch.cuda.synchronize()
-    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-    e[0].record()
-    qsvm.qsvm_gram_sym(m, exact)
-    e[1].record()
-    e[2].record()
-    _, flagged = sur.gram(X_eval, m, K=Ks)
-    e[3].record()
-    torch.cuda.synchronize()
-    assert float((Ks - exact).abs().max()) <= K_ABS_TOL
-    t_exact, t_sur = e[0].elapsed_time(e[1]), e[2].elapsed_time(e[3])
-    assert t_sur < 0.5 * t_exact, (t_sur, t_exact, flagged)
+    T = (N + 63) // 64
+    flagged = int(flagged.item())
+    print(f"margin {margin:.1f} nats, flagged {flagged} of {T * (T + 1) // 2} tiles", flush=True)
+    assert 0 < flagged < T * (T + 1) // 2
+    assert float(np.max(np.abs(Ks.cpu().numpy() - Kx))) <= K_ABS_TOL
 
 
 def test_surrogate_gram_with_full_fallback_is_exact():

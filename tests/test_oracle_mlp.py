@@ -6,6 +6,8 @@ float64 autograd, GELU and AdamW, and bfloat16 conversion -- library routines
 that the reference does not use.
 """
 
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -136,46 +138,53 @@ def test_surrogate_gram_matches_torch_sigmoid():
     assert np.array_equal(K, K.T)
 
 
-def _log_loss(params, X, target, alpha, scale):
+def _sat_loss(params, Xr, X, target, lc, ls, scale):
     acts = mlp.forward(params, X)
-    return mlp.log_rbf_pair_loss(acts["E"], target, alpha, scale)[0]
+    return mlp.sat_log_pair_loss(Xr, acts["E"], target, lc, ls, scale)[0]
 
 
-def test_log_rbf_head_matches_torch_autograd():
-    # ln K_hat = -alpha * squared distance (torch.cdist, a library routine the
-    # reference does not use); loss and every gradient against autograd
+def test_sat_log_head_matches_torch_autograd():
+    # ln K_hat = -c (1 - exp(-s d2)), d2 the squared distance of [x, f(x)]
+    # (torch.cdist, a library routine the reference does not use); loss and
+    # every gradient against autograd
     rng = np.random.default_rng(6)
     params = _params(rng, dims=(10, 8, 7, 5))
     X = rng.normal(0, 1, (16, 10))
+    Xr = rng.uniform(0, 3, (16, 4))  # the input part of the embedding
     target = rng.uniform(-40.0, 0.0, 8)
-    alpha, scale = 0.8, 7.0
+    lc, ls, scale = math.log(30.0), math.log(0.05), 7.0
     acts = mlp.forward(params, X)
-    loss, dE, da, lh = mlp.log_rbf_pair_loss(acts["E"], target, alpha, scale)
+    loss, dE, dlc, dls, lh, d2 = mlp.sat_log_pair_loss(Xr, acts["E"], target, lc, ls, scale)
     grads = mlp.backward(params, X, acts, dE)
 
     tp = [torch.tensor(p, dtype=torch.float64, requires_grad=True) for p in params]
-    ta = torch.tensor(alpha, dtype=torch.float64, requires_grad=True)
+    tlc = torch.tensor(lc, dtype=torch.float64, requires_grad=True)
+    tls = torch.tensor(ls, dtype=torch.float64, requires_grad=True)
     g = torch.nn.functional.gelu
     E = g(g(torch.tensor(X) @ tp[0] + tp[1]) @ tp[2] + tp[3]) @ tp[4] + tp[5]
+    Z = torch.cat([torch.tensor(Xr), E], dim=1)
     P = 8
-    d2 = torch.cdist(E[:P].unsqueeze(0), E[P:].unsqueeze(0)).squeeze(0).diagonal() ** 2
-    tl = ((-ta * d2 - torch.tensor(target)) / scale).pow(2).mean()
+    td2 = torch.cdist(Z[:P].unsqueeze(0), Z[P:].unsqueeze(0)).squeeze(0).diagonal() ** 2
+    tlh = -torch.exp(tlc) * (1 - torch.exp(-torch.exp(tls) * td2))
+    tl = ((tlh - torch.tensor(target)) / scale).pow(2).mean()
     tl.backward()
     assert abs(tl.item() - loss) < 1e-13
-    assert np.max(np.abs((-alpha * d2).detach().numpy() - lh)) < 1e-12
+    assert np.max(np.abs(td2.detach().numpy() - d2)) < 1e-11
+    assert np.max(np.abs(tlh.detach().numpy() - lh)) < 1e-11
     for p, gr in zip(tp, grads):
         assert np.max(np.abs(p.grad.numpy() - gr)) < 1e-13
-    assert abs(ta.grad.item() - da) < 1e-13
+    assert abs(tlc.grad.item() - dlc) < 1e-12 and abs(tls.grad.item() - dls) < 1e-12
 
 
-def test_log_rbf_head_matches_finite_differences():
+def test_sat_log_head_matches_finite_differences():
     rng = np.random.default_rng(7)
     params = list(_params(rng))
     X = rng.normal(0, 1, (8, 6))
+    Xr = rng.uniform(0, 1, (8, 3))
     target = rng.uniform(-5, 0, 4)
-    alpha, scale = 0.6, 3.0
+    lc, ls, scale = math.log(6.0), math.log(0.3), 3.0
     acts = mlp.forward(params, X)
-    _, dE, da, _ = mlp.log_rbf_pair_loss(acts["E"], target, alpha, scale)
+    _, dE, dlc, dls, _, _ = mlp.sat_log_pair_loss(Xr, acts["E"], target, lc, ls, scale)
     grads = mlp.backward(params, X, acts, dE)
     h = 1e-6
     for p, g in zip(params, grads):
@@ -183,32 +192,38 @@ def test_log_rbf_head_matches_finite_differences():
         for q in range(0, flat.size, max(1, flat.size // 5)):
             old = flat[q]
             flat[q] = old + h
-            lp = _log_loss(params, X, target, alpha, scale)
+            lp = _sat_loss(params, Xr, X, target, lc, ls, scale)
             flat[q] = old - h
-            lm = _log_loss(params, X, target, alpha, scale)
+            lm = _sat_loss(params, Xr, X, target, lc, ls, scale)
             flat[q] = old
             assert abs((lp - lm) / (2 * h) - g.reshape(-1)[q]) < 1e-7
-    fa = (_log_loss(params, X, target, alpha + h, scale) - _log_loss(params, X, target, alpha - h, scale)) / (2 * h)
-    assert abs(fa - da) < 1e-7
+    fc = (_sat_loss(params, Xr, X, target, lc + h, ls, scale) - _sat_loss(params, Xr, X, target, lc - h, ls, scale)) / (2 * h)
+    fs = (_sat_loss(params, Xr, X, target, lc, ls + h, scale) - _sat_loss(params, Xr, X, target, lc, ls - h, scale)) / (2 * h)
+    assert abs(fc - dlc) < 1e-7 and abs(fs - dls) < 1e-7
 
 
-def test_log_rbf_head_special_cases():
-    # identical embeddings predict ln K_hat = 0 (K_hat = 1) whatever alpha is;
-    # orthogonal unit vectors are at squared distance 2
-    E = np.array([[1.0, 0.0], [0.0, 1.0], [1.0, 0.0], [1.0, 0.0]])  # pairs (0, 2) and (1, 3)
-    _, _, _, lh = mlp.log_rbf_pair_loss(E, np.zeros(2), 3.0, 1.0)
-    assert lh[0] == 0.0 and lh[1] == -6.0
-    L, K = mlp.log_rbf_gram(E, 3.0)
+def test_sat_log_head_special_cases():
+    # identical embeddings predict ln K_hat = 0 (K_hat = 1) whatever c and s
+    # are; small distances give -c s d2; large ones saturate at -c
+    Xr = np.array([[1.0, 0.0], [0.0, 1.0], [1.0, 0.0], [1.0, 0.0]])  # pairs (0, 2) and (1, 3)
+    E = np.zeros((4, 3))
+    _, _, _, _, lh, d2 = mlp.sat_log_pair_loss(Xr, E, np.zeros(2), math.log(50.0), math.log(0.1), 1.0)
+    assert lh[0] == 0.0 and d2[1] == 2.0
+    assert lh[1] == pytest.approx(-50.0 * (1.0 - math.exp(-0.2)), rel=1e-15)
+    assert mlp.sat_log_head(np.array([1e-9]), math.log(50.0), math.log(0.1))[0] == pytest.approx(-50.0 * 0.1 * 1e-9, rel=1e-8)
+    assert mlp.sat_log_head(np.array([1e4]), math.log(50.0), math.log(0.1))[0] == pytest.approx(-50.0, rel=1e-15)
+    L, K = mlp.sat_log_gram(Xr, E, math.log(50.0), math.log(0.1))
     assert np.array_equal(np.diag(L), np.zeros(4)) and np.array_equal(np.diag(K), np.ones(4))
-    assert L[0, 1] == -6.0 and L[0, 2] == 0.0 and K[0, 2] == 1.0
+    assert L[0, 2] == 0.0 and K[0, 2] == 1.0 and L[0, 1] == pytest.approx(lh[1], rel=1e-15)
 
 
-def test_log_rbf_gram_matches_torch_cdist():
+def test_sat_log_gram_matches_torch_cdist():
     rng = np.random.default_rng(8)
+    Xr = rng.uniform(0, 3, (70, 5))
     E = rng.normal(0, 0.3, (70, 12))
-    L, K = mlp.log_rbf_gram(E, 0.25)
-    tE = torch.tensor(E)
-    ref = -0.25 * torch.cdist(tE, tE).pow(2).numpy()
+    L, K = mlp.sat_log_gram(Xr, E, math.log(20.0), math.log(0.25))
+    Z = torch.tensor(np.concatenate([Xr, E], axis=1))
+    ref = (-20.0 * (1 - torch.exp(-0.25 * torch.cdist(Z, Z).pow(2)))).numpy()
     np.fill_diagonal(ref, 0.0)
     assert np.max(np.abs(L - ref)) < 1e-12
     assert np.max(np.abs(K - np.exp(ref))) < 1e-12
