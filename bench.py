@@ -516,7 +516,10 @@ def svm_accuracies(K_exact, K_sur, labels, n_train_frac=0.75):
 
 
 def batched_leg():
-    """64 uneven jobs: one persistent hipGraph launch vs one launch per job."""
+    """64 uneven jobs: one persistent hipGraph launch vs one launch per job,
+    with the built-in work-item shape and after autotuning every (reps, n) of
+    the mix (the tuned table also sets the variant of the one-launch-per-job
+    calls)."""
     import numpy as np
     import torch
 
@@ -529,35 +532,62 @@ def batched_leg():
         m = qsvm.qsvm_encode_mps(torch.as_tensor(w.X, device=dev), w.reps)
         K = torch.empty((m.N, m.N), dtype=torch.float64, device=dev)
         jobs.append((m, K, None))
-    plan = qsvm.BatchPlan(jobs, use_graph=True)
-    total_items, grid, _ = plan.info()
     pairs = [m.N * (m.N - 1) // 2 for m, _, _ in jobs]
-    # warm-up both paths
-    plan.launch()
-    for m, K, _ in jobs:
-        qsvm.qsvm_gram_sym(m, K)
-    torch.cuda.synchronize()
-    ev = _events(2)
-    ev[0].record()
-    for _ in range(3):
+
+    def time_plan(plan):
         plan.launch()
-    ev[1].record()
-    torch.cuda.synchronize()
-    batched_s = ev[0].elapsed_time(ev[1]) / 3e3
-    per_job = []
-    ev_all = _events(2)
-    ev_all[0].record()
-    for m, K, _ in jobs:
-        e = _events(2)
-        e[0].record()
-        qsvm.qsvm_gram_sym(m, K)
-        e[1].record()
-        per_job.append(e)
-    ev_all[1].record()
-    torch.cuda.synchronize()
-    serial_s = ev_all[0].elapsed_time(ev_all[1]) / 1e3
-    job_rates = [p / (e[0].elapsed_time(e[1]) / 1e3) for p, e in zip(pairs, per_job)]
+        torch.cuda.synchronize()
+        ev = _events(2)
+        ev[0].record()
+        for _ in range(3):
+            plan.launch()
+        ev[1].record()
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / 3e3
+
+    def time_per_job():
+        for m, K, _ in jobs:
+            qsvm.qsvm_gram_sym(m, K)
+        torch.cuda.synchronize()
+        per_job = []
+        ev_all = _events(2)
+        ev_all[0].record()
+        for m, K, _ in jobs:
+            e = _events(2)
+            e[0].record()
+            qsvm.qsvm_gram_sym(m, K)
+            e[1].record()
+            per_job.append(e)
+        ev_all[1].record()
+        torch.cuda.synchronize()
+        return ev_all[0].elapsed_time(ev_all[1]) / 1e3, [p / (e[0].elapsed_time(e[1]) / 1e3) for p, e in zip(pairs, per_job)]
+
+    # built-in defaults: variant 0 everywhere, 2 / 1 ket points per lane in the plan
+    # one entry per (reps, n bucket, N bucket) of the mix, tuned at the bucket's
+    # largest N that occurs (so the tuning problem is the size of a real job)
+    shapes = {}
+    for m, _, _ in jobs:
+        key = (m.reps, m.n, m.N.bit_length() - 1)
+        shapes[key] = max(shapes.get(key, 0), m.N)
+    for (r, n, _), N in shapes.items():
+        qsvm.qsvm_set_tuned_variant(r, n, N, 0)
+    plan = qsvm.BatchPlan(jobs, use_graph=True, item_pi2=2, item_pi3=1)
+    total_items, grid, _ = plan.info()
+    default_s = time_plan(plan)
     plan.close()
+    default_serial_s, _ = time_per_job()
+    # autotune every (reps, n) of the mix on a 1024-point synthetic Gram
+    tuned = {}
+    t0 = time.perf_counter()
+    for (r, n, _), N in sorted(shapes.items()):
+        best, ms = qsvm.qsvm_autotune(r, n, N)
+        tuned[f"r{r}_n{n}_N{N}"] = {"variant": best, "ms_per_variant": [round(x, 4) for x in ms]}
+    tune_s = time.perf_counter() - t0
+    plan = qsvm.BatchPlan(jobs, use_graph=True)
+    shape = plan.shape()
+    batched_s = time_plan(plan)
+    plan.close()
+    serial_s, job_rates = time_per_job()
     # executed sweep flops of all jobs (the same per-pair count as the roofline entry)
     flops = sum(p * sweep_flops_per_pair(m.n, m.reps, "butterfly") for p, (m, _, _) in zip(pairs, jobs))
     res = {
@@ -577,9 +607,17 @@ def batched_leg():
         "one_launch_per_job_frac_of_fp32_peak": flops / serial_s / 1e12 / PEAK_FP32_VECTOR_TFLOPS,
         "per_job_entries_per_s": {"min": float(np.min(job_rates)), "median": float(np.median(job_rates)),
                                   "max": float(np.max(job_rates))},
+        "tuned_item_shape": {"pi2": shape[0], "pi3": shape[1]},
+        "default": {"seconds": default_s, "value": sum(pairs) / default_s,
+                    "one_launch_per_job_seconds": default_serial_s, "item_shape": {"pi2": 2, "pi3": 1}},
+        "tuned_over_default": default_s / batched_s,
+        "autotune_seconds": tune_s,
+        "autotune": tuned,
+        "autotune_cache": qsvm.qsvm_autotune_cache_path(),
     }
-    log(f"batched: {res['value']:.3e} entries/s ({batched_s*1e3:.1f} ms, {res['frac_of_fp32_peak']:.3f} of peak) "
-        f"vs one launch per job {res['one_launch_per_job_value']:.3e} ({serial_s*1e3:.1f} ms)")
+    log(f"batched: {res['value']:.3e} entries/s ({batched_s*1e3:.1f} ms, {res['frac_of_fp32_peak']:.3f} of peak, "
+        f"shape {shape}) vs default {default_s*1e3:.1f} ms vs one launch per job {serial_s*1e3:.1f} ms "
+        f"(default variants {default_serial_s*1e3:.1f} ms)")
     return res
 
 

@@ -293,6 +293,13 @@ typedef struct {
                            job's tiles with an entry above it are recomputed in
                            FP64 (0 = automatic per job from its n_qubits,
                            negative = off); the plan holds the list buffer */
+  int32_t item_pi2;     /* work-item shape: ket points per lane of the reps = 2
+                           items (2 or 4; 0 = from the tuned variant of the
+                           plan's costliest reps = 2 job, see qsvm_autotune) */
+  int32_t item_pi3;     /* the same for reps = 3 items (0 or 1: the persistent
+                           kernel's register budget holds one reps = 3
+                           environment per lane); reps = 1 items use 4.
+                           Results do not depend on the shape. */
 } qsvm_batch_opts;
 
 typedef struct qsvm_batch_plan qsvm_batch_plan; /* opaque */
@@ -321,12 +328,21 @@ qsvm_status qsvm_batch_plan_destroy(qsvm_batch_plan* plan);
 qsvm_status qsvm_batch_plan_info(const qsvm_batch_plan* plan, int64_t* total_items, int32_t* grid_blocks,
                                  int32_t* uses_graph);
 
+/* The plan's work-item shape: ket points per lane of its reps = 2 and reps = 3 items. */
+qsvm_status qsvm_batch_plan_shape(const qsvm_batch_plan* plan, int32_t* item_pi2, int32_t* item_pi3);
+
 /*
  * Autotune the butterfly sweep for (reps, n_qubits, N) on the current device:
  * every kernel variant (ket points per lane x register budget) is timed on a
  * synthetic symmetric Gram of that shape (features from a fixed hash, uniform
- * in [0, pi)), and the fastest is recorded in the per-process table that
- * launches with opts.variant == 0 consult, keyed by reps and floor(log2 n).
+ * in [0, pi)), and the fastest is recorded in the table that Gram calls with
+ * opts.variant == 0 and batch plans (their work-item shape) consult, keyed by
+ * (GPU architecture, reps, floor(log2 n), floor(log2 N)).  The table is persisted: entries
+ * are merged into a text cache file (qsvm_autotune_cache_path: the file named
+ * by $QSVM_TUNE_CACHE, an empty value meaning no file, else
+ * $XDG_CACHE_HOME/qsvm/autotune.txt or $HOME/.cache/qsvm/autotune.txt),
+ * which a process reads on its first lookup for an architecture; a cache
+ * that cannot be written leaves the in-process table in effect.
  * Allocates and frees its own device scratch (N x N doubles plus the MPS)
  * and synchronises `stream`; N <= 65536.
  *   best_variant  optional output: the chosen variant (0..3).
@@ -336,12 +352,25 @@ qsvm_status qsvm_batch_plan_info(const qsvm_batch_plan* plan, int64_t* total_ite
 qsvm_status qsvm_autotune(int32_t reps, int32_t n_qubits, int64_t N, void* stream, int32_t* best_variant,
                           float* variant_ms, int32_t n_variant_ms);
 
-/* The variant (0..3) a launch with opts.variant == 0 uses for (reps, n_qubits). */
-int32_t qsvm_get_tuned_variant(int32_t reps, int32_t n_qubits);
+/* The variant (0..3) a launch with opts.variant == 0 uses for (reps, n_qubits)
+ * on N points (a symmetric Gram of N points, or a rectangular Gram whose
+ * pair count Na Nb equals N^2 / 2): the entry of the bucket
+ * (floor(log2 n_qubits), floor(log2 N)), else that of the nearest N bucket
+ * tuned for the same n bucket, else 0. */
+int32_t qsvm_get_tuned_variant(int32_t reps, int32_t n_qubits, int64_t N);
 
-/* Record a variant for (reps, n_qubits) in the per-process table (e.g. from a
- * saved tuning cache).  No HIP call. */
-qsvm_status qsvm_set_tuned_variant(int32_t reps, int32_t n_qubits, int32_t variant);
+/* Record a variant for (reps, n_qubits, N) in the table of the current device's
+ * architecture (in this process; qsvm_autotune_save writes it to the cache).
+ * Queries the device's architecture; enqueues nothing. */
+qsvm_status qsvm_set_tuned_variant(int32_t reps, int32_t n_qubits, int64_t N, int32_t variant);
+
+/* Merge the table into the cache file now (the autotuner does so itself);
+ * QSVM_ERR_INVALID_ARG with a message when the file cannot be written. */
+qsvm_status qsvm_autotune_save(void);
+
+/* The cache file in use ("" = persistence off).  The pointer stays valid until
+ * the next call from the same thread. */
+const char* qsvm_autotune_cache_path(void);
 
 /* ------------------------------------------------------------------------
  * State-vector engine (the state-vector simulation method of §3.4.1 / Alg. 1,
@@ -523,7 +552,8 @@ const char* qsvm_status_string(qsvm_status s);
 /* Message describing the calling thread's most recent non-OK status ("" if none). */
 const char* qsvm_last_error(void);
 
-/* ABI version of this header: 1. */
+/* ABI version of this header: 2 (2: the tuned-variant calls take the point
+ * count N; batch options carry the work-item shape). */
 int32_t qsvm_abi_version(void);
 
 #ifdef __cplusplus

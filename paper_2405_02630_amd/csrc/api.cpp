@@ -2,6 +2,7 @@
 // HIP kernels.  Every check runs on the host before any HIP call, so a
 // rejected call enqueues nothing and touches no device state.
 
+#include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -171,9 +172,11 @@ hipError_t refine_tiles(const qsvm::SweepArgs& a, int32_t reps, double refine_ab
   return e != hipSuccess ? e : f;
 }
 
-// Variant for a launch: forced by opts, else the tuned table (default 0).
-int32_t pick_variant(const Opts& o, int32_t reps, int32_t n) {
-  return o.variant > 0 ? o.variant - 1 : qsvm::tuned_variant(reps, n);
+// Variant for a launch: forced by opts, else the tuned table (default 0) at
+// the symmetric point count with the launch's pair count.
+int32_t pick_variant(const Opts& o, int32_t reps, int32_t n, double pairs) {
+  if (o.variant > 0) return o.variant - 1;
+  return qsvm::tuned_variant(reps, n, int64_t(sqrt(2.0 * (pairs > 1.0 ? pairs : 1.0)) + 0.5));
 }
 
 qsvm_status run_gram(const void* mps_a, int64_t Na, const void* mps_b, int64_t Nb, int32_t n,
@@ -215,7 +218,10 @@ qsvm_status run_gram(const void* mps_a, int64_t Na, const void* mps_b, int64_t N
   if (injected_launch_failure()) return fail(QSVM_ERR_HIP, "%s: injected launch failure (QSVM_FAULT_INJECT=launch)", what);
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = (o.sweep == QSVM_SWEEP_DENSE) ? qsvm::launch_sweep_dense_args(a, reps, s)
-                                                : qsvm::launch_sweep_fast(a, reps, pick_variant(o, reps, n), s);
+                                                : qsvm::launch_sweep_fast(
+                                                      a, reps, pick_variant(o, reps, n, sym ? 0.5 * double(Na) * double(Na)
+                                                                                            : double(Na) * double(Nb)),
+                                                      s);
   if (e == hipSuccess) e = refine_tiles(a, reps, o.refine_above, s, src);
   return hip_status(e, what);
 }
@@ -269,7 +275,7 @@ qsvm_status gram_tile_list(const void* mps, int64_t N, int32_t n_qubits, int32_t
   a.tile_list = tiles;
   a.tile_count = tile_count;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const int32_t variant = pick_variant(o, reps, n_qubits);
+  const int32_t variant = pick_variant(o, reps, n_qubits, double(n_tiles) * qsvm::kTile * qsvm::kTile);
   hipError_t e = tile_count                      ? qsvm::launch_sweep_butterfly_counted(a, reps, variant, st)
                  : (o.sweep == QSVM_SWEEP_DENSE) ? qsvm::launch_sweep_dense_args(a, reps, st)
                                                  : qsvm::launch_sweep_fast(a, reps, variant, st);
@@ -394,15 +400,29 @@ qsvm_status qsvm_autotune(int32_t reps, int32_t n_qubits, int64_t N, void* strea
   return ok();
 }
 
-int32_t qsvm_get_tuned_variant(int32_t reps, int32_t n_qubits) { return qsvm::tuned_variant(reps, n_qubits); }
+int32_t qsvm_get_tuned_variant(int32_t reps, int32_t n_qubits, int64_t N) {
+  return qsvm::tuned_variant(reps, n_qubits, N);
+}
 
-qsvm_status qsvm_set_tuned_variant(int32_t reps, int32_t n_qubits, int32_t variant) {
+qsvm_status qsvm_autotune_save(void) {
+  if (!qsvm::save_tuned_table())
+    return fail(QSVM_ERR_INVALID_ARG, "qsvm_autotune_save: cannot write %s", qsvm::tune_cache_path().c_str());
+  return ok();
+}
+
+const char* qsvm_autotune_cache_path(void) {
+  static thread_local std::string path;
+  path = qsvm::tune_cache_path();
+  return path.c_str();
+}
+
+qsvm_status qsvm_set_tuned_variant(int32_t reps, int32_t n_qubits, int64_t N, int32_t variant) {
   const char* what = "qsvm_set_tuned_variant";
-  qsvm_status s = check_shape(1, n_qubits, reps, what);
+  qsvm_status s = check_shape(N, n_qubits, reps, what);
   if (s != QSVM_OK) return s;
   if (variant < 0 || variant >= qsvm::kButterflyVariants)
     return fail(QSVM_ERR_INVALID_ARG, "%s: variant = %d outside [0, %d)", what, variant, qsvm::kButterflyVariants);
-  qsvm::set_tuned_variant(reps, n_qubits, variant);
+  qsvm::set_tuned_variant(reps, n_qubits, N, variant);
   return ok();
 }
 
@@ -496,6 +516,6 @@ const char* qsvm_status_string(qsvm_status s) {
 
 const char* qsvm_last_error(void) { return g_last_error.c_str(); }
 
-int32_t qsvm_abi_version(void) { return 1; }
+int32_t qsvm_abi_version(void) { return 2; }
 
 }  // extern "C"

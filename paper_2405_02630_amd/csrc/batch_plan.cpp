@@ -20,6 +20,7 @@ struct qsvm_batch_plan {
   int32_t n_jobs = 0;
   int64_t total_items = 0;
   uint32_t grid = 0;
+  qsvm::BatchShape shape;
   bool use_graph = false;
   hipStream_t capture_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -52,7 +53,7 @@ void destroy_plan(qsvm_batch_plan* p) {
 // tiles with an entry above the threshold (no allocation, no memset: the
 // sequence can be captured in a graph).
 hipError_t plan_enqueue(qsvm_batch_plan* p, hipStream_t s) {
-  hipError_t e = launch_batch(p->d_jobs, p->n_jobs, p->total_items, p->d_counter, p->grid, s);
+  hipError_t e = launch_batch(p->shape, p->d_jobs, p->n_jobs, p->total_items, p->d_counter, p->grid, s);
   if (e != hipSuccess || p->refine_above < 0.0) return e;
   for (const BatchJob& j : p->host_jobs) {
     const double thresh = p->refine_above > 0.0 ? p->refine_above : auto_refine_threshold(j.args.n);
@@ -66,7 +67,7 @@ hipError_t plan_enqueue(qsvm_batch_plan* p, hipStream_t s) {
 }
 
 // Build the host job table; returns false with a message on invalid input.
-bool build_jobs(const qsvm_job* jobs, int32_t n_jobs, int32_t renorm_every, int32_t diag_mode,
+bool build_jobs(const qsvm_job* jobs, int32_t n_jobs, int32_t renorm_every, int32_t diag_mode, const BatchShape& shape,
                 std::vector<BatchJob>& out, int64_t& total, char* msg, size_t msg_len) {
   struct Entry {
     BatchJob job;
@@ -104,12 +105,12 @@ bool build_jobs(const qsvm_job* jobs, int32_t n_jobs, int32_t renorm_every, int3
     a.diag_mode = diag_mode;
     a.tile_row0 = 0;
     a.tiles_b = a.tile_rows = int32_t((J.N + kTile - 1) / kTile);
-    a.blocks_per_tile = batch_blocks_per_tile(J.reps);
+    a.blocks_per_tile = batch_blocks_per_tile(shape, J.reps);
     const int64_t T = a.tiles_b;
     e.items = (T * (T + 1) / 2) * a.blocks_per_tile;
     a.num_blocks = 0;  // unused by the persistent kernel
     e.job.reps = J.reps;
-    e.cost = batch_item_cost(J.reps, J.n_qubits);
+    e.cost = batch_item_cost(shape, J.reps, J.n_qubits);
     es.push_back(e);
   }
   // longest processing time first: most expensive items at the head of the queue
@@ -134,6 +135,7 @@ qsvm_status qsvm_batch_plan_launch(qsvm_batch_plan* plan, void* stream);
 qsvm_status qsvm_batch_plan_destroy(qsvm_batch_plan* plan);
 qsvm_status qsvm_batch_plan_info(const qsvm_batch_plan* plan, int64_t* total_items, int32_t* grid_blocks,
                                  int32_t* uses_graph);
+qsvm_status qsvm_batch_plan_shape(const qsvm_batch_plan* plan, int32_t* item_pi2, int32_t* item_pi3);
 
 }  // extern "C"
 
@@ -170,9 +172,41 @@ extern "C" qsvm_status qsvm_batch_plan_create(const qsvm_job* jobs, int32_t n_jo
       return api_fail(QSVM_ERR_UNSUPPORTED, msg);
     }
   }
+  // work-item shape: forced by opts, else the tuned single-Gram variant of the
+  // costliest job of each reps (its ket points per lane)
+  BatchShape shape;
+  if (o.item_pi2 != 0 || o.item_pi3 != 0) {
+    shape.pi2 = o.item_pi2 ? o.item_pi2 : shape.pi2;
+    shape.pi3 = o.item_pi3 ? o.item_pi3 : shape.pi3;
+    if (!batch_shape_supported(shape))
+      return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_batch_plan_create: item_pi2 must be 0, 2 or 4 and item_pi3 0 or 1");
+  } else {
+    for (int r = 2; r <= 3; ++r) {
+      double best = -1.0;
+      int32_t n_best = 0;
+      int64_t N_best = 0;
+      for (int32_t q = 0; q < n_jobs; ++q) {
+        if (jobs[q].reps != r || jobs[q].N < 1 || jobs[q].n_qubits < 1) continue;
+        const double cost = double(jobs[q].N) * double(jobs[q].N) * double(jobs[q].n_qubits);
+        if (cost > best) {
+          best = cost;
+          n_best = jobs[q].n_qubits;
+          N_best = jobs[q].N;
+        }
+      }
+      if (n_best == 0) continue;
+      // a tuned shape the persistent kernel cannot hold (two reps = 3 points
+      // per lane) keeps the default
+      const int32_t pi = butterfly_variant_pi(r, tuned_variant(r, n_best, N_best));
+      BatchShape t = shape;
+      (r == 2 ? t.pi2 : t.pi3) = pi;
+      if (batch_shape_supported(t)) shape = t;
+    }
+  }
   std::vector<BatchJob> table;
   int64_t total = 0;
-  if (!build_jobs(jobs, n_jobs, o.renorm_every ? o.renorm_every : kDefaultRenorm, o.diag_mode, table, total, msg, sizeof msg))
+  if (!build_jobs(jobs, n_jobs, o.renorm_every ? o.renorm_every : kDefaultRenorm, o.diag_mode, shape, table, total,
+                  msg, sizeof msg))
     return api_fail(QSVM_ERR_INVALID_ARG, msg);
   if (api_injected_failure()) return api_fail(QSVM_ERR_HIP, "qsvm_batch_plan_create: injected launch failure (QSVM_FAULT_INJECT=launch)");
 
@@ -181,7 +215,7 @@ extern "C" qsvm_status qsvm_batch_plan_create(const qsvm_job* jobs, int32_t n_jo
   hipError_t e = hipGetDevice(&p->device);
   int cus = 0, per_cu = 0;
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
-  if (e == hipSuccess) e = batch_kernel_occupancy(&per_cu);
+  if (e == hipSuccess) e = batch_kernel_occupancy(shape, &per_cu);
   if (e != hipSuccess) {
     destroy_plan(p);
     return api_hip(e, "qsvm_batch_plan_create");
@@ -192,6 +226,7 @@ extern "C" qsvm_status qsvm_batch_plan_create(const qsvm_job* jobs, int32_t n_jo
     return api_fail(QSVM_ERR_UNSUPPORTED, "qsvm_batch_plan_create: more than 2^31 work items");
   }
   p->n_jobs = n_jobs;
+  p->shape = shape;
   p->total_items = total;
   p->host_jobs = table;
   p->refine_above = o.refine_above;
@@ -238,6 +273,14 @@ extern "C" qsvm_status qsvm_batch_plan_launch(qsvm_batch_plan* p, void* stream) 
 extern "C" qsvm_status qsvm_batch_plan_destroy(qsvm_batch_plan* p) {
   qsvm::destroy_plan(p);
   return qsvm::api_ok();
+}
+
+extern "C" qsvm_status qsvm_batch_plan_shape(const qsvm_batch_plan* p, int32_t* item_pi2, int32_t* item_pi3) {
+  using namespace qsvm;
+  if (!p) return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_batch_plan_shape: plan is NULL");
+  if (item_pi2) *item_pi2 = p->shape.pi2;
+  if (item_pi3) *item_pi3 = p->shape.pi3;
+  return api_ok();
 }
 
 extern "C" qsvm_status qsvm_batch_plan_info(const qsvm_batch_plan* p, int64_t* total_items, int32_t* grid_blocks,

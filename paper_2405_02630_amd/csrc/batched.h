@@ -16,10 +16,19 @@ struct BatchJob {
   int64_t item_begin;  // first queue item of this job (jobs sorted by it)
 };
 
-int batch_blocks_per_tile(int reps);
-double batch_item_cost(int reps, int32_t n);
-hipError_t batch_kernel_occupancy(int* blocks_per_cu);
-hipError_t launch_batch(const BatchJob* d_jobs, int32_t n_jobs, int64_t total_items,
+// Work-item shape of a plan: ket points per lane of the reps = 2 and reps = 3
+// items (reps = 1 items use 4).  Supported: pi2 in {2, 4}, pi3 = 1.
+struct BatchShape {
+  int32_t pi2 = 2;
+  int32_t pi3 = 1;
+};
+
+bool batch_shape_supported(const BatchShape& s);
+int batch_pi(const BatchShape& s, int reps);
+int batch_blocks_per_tile(const BatchShape& s, int reps);
+double batch_item_cost(const BatchShape& s, int reps, int32_t n);
+hipError_t batch_kernel_occupancy(const BatchShape& s, int* blocks_per_cu);
+hipError_t launch_batch(const BatchShape& s, const BatchJob* d_jobs, int32_t n_jobs, int64_t total_items,
                         unsigned int* d_counter, uint32_t grid, hipStream_t stream);
 
 }  // namespace qsvm

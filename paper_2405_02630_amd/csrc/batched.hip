@@ -6,7 +6,8 @@
 // different sizes (n, N) and depths (reps) are drained by one persistent
 // kernel: every job is cut into the same work items the single-Gram sweep
 // uses (one block = 4 waves = 4 groups of PI ket points x 64 bra points of
-// one tile), the items of all jobs form one queue ordered by decreasing cost
+// one tile; PI per reps chosen by the plan from the tuned variants), the
+// items of all jobs form one queue ordered by decreasing cost
 // per item (longest-processing-time-first), and each resident block pops the
 // next item with an atomic counter until the queue is empty.  A job's reps
 // selects the code path per item (wave-uniform).  The counter is cleared by a
@@ -22,14 +23,13 @@ namespace {
 
 constexpr int kBatchWaves = 4;  // target waves per SIMD of the persistent kernel
 
-// Ket points per lane of each reps in the batched kernel (those of the default
-// single-launch variants).
-__host__ __device__ constexpr int batch_pi(int reps) { return reps == 1 ? 4 : (reps == 2 ? 2 : 1); }
-
 __global__ void reset_counter(unsigned int* counter) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
 }
 
+// PI2, PI3: ket points per lane of the reps = 2 and reps = 3 items (reps = 1
+// items use 4); the plan picks them from the tuned single-Gram variants.
+template <int PI2, int PI3>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kBatchWaves, 8)))
 batched_kernel(const BatchJob* __restrict__ jobs, int32_t n_jobs, int64_t total_items,
                unsigned int* __restrict__ counter) {
@@ -59,36 +59,52 @@ batched_kernel(const BatchJob* __restrict__ jobs, int32_t n_jobs, int64_t total_
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t j0 = int64_t(tj) * kTile;
     if (reps == 2) {
-      butterfly_item<2, batch_pi(2)>(a, int64_t(ti) * kTile + (int64_t(sub) * 4 + wave) * batch_pi(2), j0);
+      butterfly_item<2, PI2>(a, int64_t(ti) * kTile + (int64_t(sub) * 4 + wave) * PI2, j0);
     } else if (reps == 3) {
-      butterfly_item<3, batch_pi(3)>(a, int64_t(ti) * kTile + (int64_t(sub) * 4 + wave) * batch_pi(3), j0);
+      butterfly_item<3, PI3>(a, int64_t(ti) * kTile + (int64_t(sub) * 4 + wave) * PI3, j0);
     } else {
-      butterfly_item<1, batch_pi(1)>(a, int64_t(ti) * kTile + (int64_t(sub) * 4 + wave) * batch_pi(1), j0);
+      butterfly_item<1, 4>(a, int64_t(ti) * kTile + (int64_t(sub) * 4 + wave) * 4, j0);
     }
   }
 }
 
+// Kernel instance for a choice of ket points per lane: PI2 in {2, 4}; PI3 = 1
+// only (at the kernel's 4 waves per SIMD, 128 VGPRs, two reps = 3
+// environments per lane spill ~860 VGPRs).
+template <class F>
+hipError_t with_kernel(const BatchShape& s, F f) {
+  if (s.pi2 == 2 && s.pi3 == 1) return f(batched_kernel<2, 1>);
+  if (s.pi2 == 4 && s.pi3 == 1) return f(batched_kernel<4, 1>);
+  return hipErrorInvalidValue;
+}
+
 }  // namespace
 
-int batch_blocks_per_tile(int reps) { return kTile / (4 * batch_pi(reps)); }
+int batch_pi(const BatchShape& s, int reps) { return reps == 1 ? 4 : (reps == 2 ? s.pi2 : s.pi3); }
+
+int batch_blocks_per_tile(const BatchShape& s, int reps) { return kTile / (4 * batch_pi(s, reps)); }
 
 // Host-side cost model of one item: pairs x sites x operations per site.
-double batch_item_cost(int reps, int32_t n) {
+double batch_item_cost(const BatchShape& s, int reps, int32_t n) {
   const double per_site = double(2 * reps - 1) * double(1 << (2 * reps - 2)) * 16.0 + 12.0;
-  return double(4 * batch_pi(reps) * kTile) * double(n) * per_site;
+  return double(4 * batch_pi(s, reps) * kTile) * double(n) * per_site;
 }
 
-hipError_t batch_kernel_occupancy(int* blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batched_kernel, 256, 0);
+bool batch_shape_supported(const BatchShape& s) { return (s.pi2 == 2 || s.pi2 == 4) && s.pi3 == 1; }
+
+hipError_t batch_kernel_occupancy(const BatchShape& s, int* blocks_per_cu) {
+  return with_kernel(s, [&](auto k) { return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, 256, 0); });
 }
 
-hipError_t launch_batch(const BatchJob* d_jobs, int32_t n_jobs, int64_t total_items,
+hipError_t launch_batch(const BatchShape& s, const BatchJob* d_jobs, int32_t n_jobs, int64_t total_items,
                         unsigned int* d_counter, uint32_t grid, hipStream_t stream) {
   hipLaunchKernelGGL(reset_counter, dim3(1), dim3(64), 0, stream, d_counter);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(batched_kernel, dim3(grid), dim3(256), 0, stream, d_jobs, n_jobs, total_items, d_counter);
-  return hipGetLastError();
+  return with_kernel(s, [&](auto k) {
+    hipLaunchKernelGGL(k, dim3(grid), dim3(256), 0, stream, d_jobs, n_jobs, total_items, d_counter);
+    return hipGetLastError();
+  });
 }
 
 }  // namespace qsvm

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 namespace qsvm {
 
 // Bytes of section D (dense tensors) for N points.
@@ -33,6 +35,7 @@ constexpr int32_t kDefaultRenorm = 8;
 constexpr int32_t kMaxRenorm = 16;
 constexpr int32_t kMaxReps = 4;        // chi = 16
 hipError_t launch_sweep_butterfly_args(const SweepArgs& a, int32_t reps, int32_t variant, hipStream_t stream);
+int32_t butterfly_variant_pi(int32_t reps, int32_t variant);  // ket points per lane; 0 if invalid
 // Butterfly sweep (reps 1..3) over a tile list whose length a.tile_count
 // holds in device memory: one persistent launch, no host read of the count.
 hipError_t launch_sweep_butterfly_counted(const SweepArgs& a, int32_t reps, int32_t variant, hipStream_t stream);
@@ -44,8 +47,12 @@ inline hipError_t launch_sweep_fast(const SweepArgs& a, int32_t reps, int32_t va
                    : launch_sweep_split_args(a, reps, variant, stream);
 }
 // Autotuned variant table (autotune.cpp).
-int32_t tuned_variant(int32_t reps, int32_t n);
-void set_tuned_variant(int32_t reps, int32_t n, int32_t variant);
+// Tuned variant for (reps, n qubits, N points): N is the point count of a
+// symmetric Gram, sqrt(2 Na Nb) for a rectangular one (the same pair count).
+int32_t tuned_variant(int32_t reps, int32_t n, int64_t N);
+void set_tuned_variant(int32_t reps, int32_t n, int64_t N, int32_t variant);
+bool save_tuned_table();  // merge the table into the cache file; false on an I/O error
+std::string tune_cache_path();  // the cache file in use ("" = none)
 hipError_t autotune_run(int32_t reps, int32_t n, int64_t N, hipStream_t stream, int32_t* best, float* ms_out);
 hipError_t launch_sweep_dense_args(const SweepArgs& a, int32_t reps, hipStream_t stream);
 // State-vector engine (sv.hip).

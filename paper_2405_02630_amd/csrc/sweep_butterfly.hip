@@ -122,6 +122,13 @@ hipError_t launch_sweep_butterfly_args(const SweepArgs& a, int32_t reps, int32_t
   }
 }
 
+// Ket points per lane of a variant (the PI of the table above).
+int32_t butterfly_variant_pi(int32_t reps, int32_t variant) {
+  static constexpr int32_t kPi[3][4] = {{4, 4, 8, 8}, {2, 4, 4, 2}, {1, 2, 1, 1}};
+  if (reps < 1 || reps > 3 || variant < 0 || variant >= kButterflyVariants) return 0;
+  return kPi[reps - 1][variant];
+}
+
 }  // namespace qsvm
 
 namespace qsvm {

@@ -66,6 +66,8 @@ class BatchOpts(ctypes.Structure):
         ("use_graph", ctypes.c_int32),
         ("grid_blocks", ctypes.c_int32),
         ("refine_above", ctypes.c_double),
+        ("item_pi2", ctypes.c_int32),
+        ("item_pi3", ctypes.c_int32),
     ]
 
 
@@ -179,9 +181,15 @@ def load_library(path: str = LIB_PATH):
     lib.qsvm_sv_gram_sym.argtypes = [vp, i64, i32, vp, i64, P(GramOpts), vp]
     lib.qsvm_sv_gram_sym.restype = i32
     lib.qsvm_autotune.restype = i32
-    lib.qsvm_get_tuned_variant.argtypes = [i32, i32]
+    lib.qsvm_batch_plan_shape.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.qsvm_batch_plan_shape.restype = i32
+    lib.qsvm_autotune_save.argtypes = []
+    lib.qsvm_autotune_save.restype = i32
+    lib.qsvm_autotune_cache_path.argtypes = []
+    lib.qsvm_autotune_cache_path.restype = ctypes.c_char_p
+    lib.qsvm_get_tuned_variant.argtypes = [i32, i32, i64]
     lib.qsvm_get_tuned_variant.restype = i32
-    lib.qsvm_set_tuned_variant.argtypes = [i32, i32, i32]
+    lib.qsvm_set_tuned_variant.argtypes = [i32, i32, i64, i32]
     lib.qsvm_set_tuned_variant.restype = i32
     _lib = lib
     return lib
@@ -249,6 +257,14 @@ def qsvm_encode_mps(X, reps: int, out=None, stream=None) -> MPS:
 N_VARIANTS = 4
 
 
+def qsvm_autotune_cache_path() -> str:
+    return load_library().qsvm_autotune_cache_path().decode()
+
+
+def qsvm_autotune_save() -> None:
+    _check(load_library().qsvm_autotune_save())
+
+
 def qsvm_autotune(reps: int, n_qubits: int, N: int, stream=None):
     """Time every butterfly variant on a synthetic (N, n_qubits, reps) Gram and
     record the fastest for later launches.  Returns (best, [ms per variant])."""
@@ -259,12 +275,12 @@ def qsvm_autotune(reps: int, n_qubits: int, N: int, stream=None):
     return int(best.value), [float(x) for x in ms]
 
 
-def qsvm_get_tuned_variant(reps: int, n_qubits: int) -> int:
-    return int(load_library().qsvm_get_tuned_variant(reps, n_qubits))
+def qsvm_get_tuned_variant(reps: int, n_qubits: int, N: int) -> int:
+    return int(load_library().qsvm_get_tuned_variant(reps, n_qubits, N))
 
 
-def qsvm_set_tuned_variant(reps: int, n_qubits: int, variant: int) -> None:
-    _check(load_library().qsvm_set_tuned_variant(reps, n_qubits, variant))
+def qsvm_set_tuned_variant(reps: int, n_qubits: int, N: int, variant: int) -> None:
+    _check(load_library().qsvm_set_tuned_variant(reps, n_qubits, N, variant))
 
 
 def _opts(renorm_every, sweep, diag_mode, rows, log_k, variant=0, refine_above=0.0):
@@ -436,7 +452,7 @@ class BatchPlan:
     one execution on the current PyTorch stream."""
 
     def __init__(self, jobs, *, renorm_every: int = 0, diag_mode: int = 0, use_graph: bool = True,
-                 grid_blocks: int = 0, refine_above: float = 0.0):
+                 grid_blocks: int = 0, refine_above: float = 0.0, item_pi2: int = 0, item_pi3: int = 0):
         lib = load_library()
         self._keep = list(jobs)
         arr = (Job * len(jobs))()
@@ -450,7 +466,7 @@ class BatchPlan:
             arr[q].K = K.data_ptr()
             arr[q].ldk = K.stride(0)
             arr[q].log_k = None if L is None else L.data_ptr()
-        o = BatchOpts(renorm_every, diag_mode, 1 if use_graph else 0, grid_blocks, refine_above)
+        o = BatchOpts(renorm_every, diag_mode, 1 if use_graph else 0, grid_blocks, refine_above, item_pi2, item_pi3)
         h = ctypes.c_void_p()
         _check(lib.qsvm_batch_plan_create(arr, len(jobs), ctypes.byref(o), ctypes.byref(h)))
         self._h = h
@@ -464,6 +480,12 @@ class BatchPlan:
         u = ctypes.c_int32()
         _check(load_library().qsvm_batch_plan_info(self._h, ctypes.byref(t), ctypes.byref(g), ctypes.byref(u)))
         return int(t.value), int(g.value), bool(u.value)
+
+    def shape(self):
+        """(ket points per lane of the reps = 2 items, of the reps = 3 items)."""
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        _check(load_library().qsvm_batch_plan_shape(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return int(a.value), int(b.value)
 
     def close(self):
         if self._h:

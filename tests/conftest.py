@@ -1,9 +1,14 @@
 import os
 import sys
+import tempfile
 
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+# the autotuner's persistent cache goes to a per-session temporary file, not
+# the user's cache directory (set before the library's first table lookup)
+os.environ.setdefault("QSVM_TUNE_CACHE", os.path.join(tempfile.gettempdir(), f"qsvm_tune_tests_{os.getpid()}.txt"))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 

@@ -47,7 +47,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_abi_version(lib):
-    assert lib.qsvm_abi_version() == 1
+    assert lib.qsvm_abi_version() == 2
 
 
 def test_opts_struct_layout():
@@ -362,13 +362,65 @@ def test_batch_plan_injected_failure(lib, monkeypatch):
 
 
 def test_tuned_variant_table(lib, no_inject):
-    assert lib.qsvm_set_tuned_variant(2, 300, 4) == qsvm.QSVM_ERR_INVALID_ARG
-    assert lib.qsvm_set_tuned_variant(5, 300, 1) == qsvm.QSVM_ERR_UNSUPPORTED
-    assert lib.qsvm_set_tuned_variant(2, 300, 3) == qsvm.QSVM_OK
-    assert lib.qsvm_get_tuned_variant(2, 300) == 3
-    assert lib.qsvm_get_tuned_variant(2, 511) == 3  # same log2 bucket
-    assert lib.qsvm_get_tuned_variant(2, 512) == 0  # untuned bucket -> default
-    assert lib.qsvm_set_tuned_variant(2, 300, 0) == qsvm.QSVM_OK
+    assert lib.qsvm_set_tuned_variant(2, 300, 1000, 4) == qsvm.QSVM_ERR_INVALID_ARG
+    assert lib.qsvm_set_tuned_variant(5, 300, 1000, 1) == qsvm.QSVM_ERR_UNSUPPORTED
+    assert lib.qsvm_set_tuned_variant(2, 300, 0, 1) == qsvm.QSVM_ERR_INVALID_ARG
+    assert lib.qsvm_set_tuned_variant(2, 300, 1000, 3) == qsvm.QSVM_OK
+    assert lib.qsvm_get_tuned_variant(2, 300, 1000) == 3
+    assert lib.qsvm_get_tuned_variant(2, 511, 600) == 3  # same log2 buckets (n 8, N 9)
+    assert lib.qsvm_get_tuned_variant(2, 512, 1000) == 0  # untuned n bucket -> default
+    # another N bucket of the same n bucket: the nearest tuned N bucket
+    assert lib.qsvm_set_tuned_variant(2, 300, 8192, 1) == qsvm.QSVM_OK
+    assert lib.qsvm_get_tuned_variant(2, 300, 100) == 3      # bucket 6: nearest is 9
+    assert lib.qsvm_get_tuned_variant(2, 300, 5000) == 1     # bucket 12: nearest is 13
+    assert lib.qsvm_get_tuned_variant(2, 300, 1 << 20) == 1
+    assert lib.qsvm_get_tuned_variant(2, 300, 2900) == 1     # bucket 11: 9 and 13 equally near -> the larger
+    for N in (1000, 8192):
+        assert lib.qsvm_set_tuned_variant(2, 300, N, 0) == qsvm.QSVM_OK
+
+
+@pytest.mark.parametrize("field,value", [("item_pi2", 3), ("item_pi2", 1), ("item_pi3", 2), ("item_pi3", -1)])
+def test_batch_plan_rejects_bad_item_shape(lib, no_inject, field, value):
+    o = qsvm.BatchOpts()
+    setattr(o, field, value)
+    st, _ = _plan(lib, [_job()], o)
+    assert st == qsvm.QSVM_ERR_INVALID_ARG
+    assert b"item_pi" in lib.qsvm_last_error()
+
+
+def _run_py(code, env):
+    import subprocess
+    import sys
+
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 0, r.stderr
+    return r.stdout.strip()
+
+
+def test_tune_cache_persists_across_processes(tmp_path):
+    # without a GPU the architecture key is "unknown"; the file format and the
+    # merge of entries across processes are what is checked here
+    path = tmp_path / "sub" / "tune.txt"
+    env = dict(os.environ, QSVM_TUNE_CACHE=str(path))
+    env.pop("QSVM_FAULT_INJECT", None)
+    pre = "from paper_2405_02630_amd import qsvm; "
+    _run_py(pre + "qsvm.qsvm_set_tuned_variant(3, 784, 4096, 2); qsvm.qsvm_autotune_save(); "
+                  "print(qsvm.qsvm_autotune_cache_path())", env)
+    lines = [ln for ln in path.read_text().splitlines() if not ln.startswith("#")]
+    assert lines == ["unknown 3 9 12 2"]
+    out = _run_py(pre + "print(qsvm.qsvm_get_tuned_variant(3, 784, 4096), qsvm.qsvm_get_tuned_variant(3, 1100, 4096), "
+                        "qsvm.qsvm_get_tuned_variant(2, 784, 4096)); qsvm.qsvm_set_tuned_variant(2, 64, 100, 1); "
+                        "qsvm.qsvm_autotune_save()", env)
+    assert out == "2 0 0"  # 1100 qubits is in another log2 bucket
+    lines = sorted(ln for ln in path.read_text().splitlines() if not ln.startswith("#"))
+    assert lines == ["unknown 2 6 6 1", "unknown 3 9 12 2"]  # merged, not overwritten
+    # malformed lines are skipped
+    path.write_text(path.read_text() + "garbage line\nunknown 2 6\nunknown 9 1 1 1\n")
+    assert _run_py(pre + "print(qsvm.qsvm_get_tuned_variant(2, 64, 100))", env) == "1"
+    # an empty QSVM_TUNE_CACHE switches persistence off
+    env["QSVM_TUNE_CACHE"] = ""
+    assert _run_py(pre + "print(repr(qsvm.qsvm_autotune_cache_path()), qsvm.qsvm_get_tuned_variant(3, 784, 4096))",
+                   env) == "'' 0"
 
 
 def test_autotune_validation(lib, no_inject):

@@ -162,9 +162,66 @@ def test_every_variant_is_bitwise_identical(reps):
         assert torch.equal(K, outs[0][0]) and torch.equal(L, outs[0][1])
 
 
+@pytest.mark.parametrize("pi2", [2, 4])
+def test_batched_item_shapes_are_bitwise_identical(pi2):
+    import torch
+
+    jobs = _jobs(SPECS, seed=40)
+    refs = _reference(jobs)
+    plan = qsvm.BatchPlan([(m, K, L) for _, m, K, L in jobs], use_graph=True, item_pi2=pi2, item_pi3=1)
+    assert plan.shape() == (pi2, 1)
+    plan.launch()
+    torch.cuda.synchronize()
+    for (X, m, K, L), (Kr, Lr) in zip(jobs, refs):
+        assert torch.equal(K, Kr), (pi2, m.n, m.N, m.reps)
+        assert torch.equal(L, Lr)
+    plan.close()
+
+
+def test_plan_takes_its_item_shape_from_the_tuned_table():
+    # the costliest job (N^2 n) of each reps decides: 196 qubits for reps = 2,
+    # 64 qubits for reps = 3
+    n2, N2, _ = max((s for s in SPECS if s[2] == 2), key=lambda s: s[1] ** 2 * s[0])
+    n3, N3, _ = max((s for s in SPECS if s[2] == 3), key=lambda s: s[1] ** 2 * s[0])
+    assert (n2, n3) == (196, 64)
+    jobs = _jobs(SPECS, seed=41)
+    old2, old3 = qsvm.qsvm_get_tuned_variant(2, n2, N2), qsvm.qsvm_get_tuned_variant(3, n3, N3)
+    try:
+        qsvm.qsvm_set_tuned_variant(2, n2, N2, 1)  # 4 ket points per lane
+        qsvm.qsvm_set_tuned_variant(3, n3, N3, 1)  # 2 per lane: beyond the batched kernel's registers
+        plan = qsvm.BatchPlan([(m, K, L) for _, m, K, L in jobs], use_graph=False)
+        assert plan.shape() == (4, 1)
+        plan.close()
+        qsvm.qsvm_set_tuned_variant(2, n2, N2, 0)
+        plan = qsvm.BatchPlan([(m, K, L) for _, m, K, L in jobs], use_graph=False)
+        assert plan.shape() == (2, 1)
+        plan.close()
+    finally:
+        qsvm.qsvm_set_tuned_variant(2, n2, N2, old2)
+        qsvm.qsvm_set_tuned_variant(3, n3, N3, old3)
+
+
+def test_autotune_persists_for_this_architecture():
+    import os
+    import subprocess
+    import sys
+
+    best, _ = qsvm.qsvm_autotune(3, 40, 256)
+    path = qsvm.qsvm_autotune_cache_path()
+    assert path and os.path.exists(path)
+    rows = [ln.split() for ln in open(path) if not ln.startswith("#")]
+    assert ["gfx950", "3", "5", "8", str(best)] in rows
+    code = ("from paper_2405_02630_amd import qsvm; import torch; torch.zeros(1, device='cuda:0'); "
+            "print(qsvm.qsvm_get_tuned_variant(3, 40, 256))")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120,
+                       cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.strip().splitlines()[-1] == str(best)
+
+
 def test_autotune_records_a_variant():
     best, ms = qsvm.qsvm_autotune(2, 64, 512)
     assert 0 <= best < qsvm.N_VARIANTS
     assert all(t > 0 for t in ms) and ms[best] == min(ms)
-    assert qsvm.qsvm_get_tuned_variant(2, 64) == best
-    assert qsvm.qsvm_get_tuned_variant(2, 127) == best
+    assert qsvm.qsvm_get_tuned_variant(2, 64, 512) == best
+    assert qsvm.qsvm_get_tuned_variant(2, 127, 1000) == best
