@@ -735,8 +735,13 @@ def main():
     sweep = qsvm.SWEEP_BUTTERFLY if args.sweep == "butterfly" else qsvm.SWEEP_DENSE
     stream = torch.cuda.current_stream()
 
+    dense_buf = (torch.empty(qsvm.qsvm_dense_bytes(N, n, reps), dtype=torch.uint8, device=dev)
+                 if sweep == qsvm.SWEEP_DENSE else None)
+
     def step(ev_mid=None):
         m = qsvm.qsvm_encode_mps(X, reps, out=mps_buf)
+        if dense_buf is not None:  # the dense sweep reads the dense tensors
+            m.dense = qsvm.qsvm_encode_dense(X, reps, out=dense_buf)
         if ev_mid is not None:
             ev_mid[0].record(stream)
         qsvm.qsvm_gram_sym(m, K, sweep=sweep, renorm_every=args.renorm_every)
@@ -823,9 +828,12 @@ def main():
         out["state_vector"] = sv_leg()
 
     if not args.no_cpu_baseline:
+        dense_t = None if dense_buf is None else qsvm.qsvm_encode_dense(X, reps, out=dense_buf)
         if K is None:
             K = torch.empty((N, N), dtype=torch.float64, device=dev)
-            qsvm.qsvm_gram_sym(qsvm.qsvm_encode_mps(X, reps, out=mps_buf), K, sweep=sweep)
+            m = qsvm.qsvm_encode_mps(X, reps, out=mps_buf)
+            m.dense = dense_t
+            qsvm.qsvm_gram_sym(m, K, sweep=sweep)
         Kh = K.cpu().numpy()
         cores = max(1, min(16, os.cpu_count() or 1))
         log(f"cpu baseline: oracle on {args.cpu_sample} points with {cores} processes")
@@ -835,6 +843,7 @@ def main():
         lk = cb.pop("_lk")
         L = torch.empty_like(K)
         m = qsvm.qsvm_encode_mps(X, reps, out=mps_buf)
+        m.dense = dense_t
         qsvm.qsvm_gram_sym(m, K, log_k=L, sweep=sweep, renorm_every=args.renorm_every)
         Lh = L.cpu().numpy()
         cb["sample_max_log_err_vs_gpu"] = float(np.max(np.abs(Lh[ia, jb] - lk)))

@@ -121,44 +121,51 @@ typedef struct {
                            a 4-byte-per-tile list lives in a stream-ordered
                            temporary.  The state-vector Grams (FP64
                            throughout) ignore it. */
+  const void* dense_a;  /* QSVM_SWEEP_DENSE only (required there, ignored
+                           otherwise): the dense tensors (qsvm_encode_dense)
+                           of the first set (mps_a, or the set of a symmetric
+                           call) ... */
+  const void* dense_b;  /* ... and of the second set of qsvm_gram (NULL =
+                           dense_a, for mps_b == mps_a) */
 } qsvm_gram_opts;
 
 /*
  * Bytes of the MPS buffer that qsvm_encode_mps writes for N points of
- * n_qubits features: n*N*chi*chi*8 + n*N*32 with chi = 2^reps.  Returns 0 for
- * arguments outside the supported range.
+ * n_qubits features: n*N*32 (Sections G and L, 16 bytes each per site and
+ * point, whatever reps).  Returns 0 for arguments outside the supported range.
  *
- * MPS buffer layout (site-major so that a sweep over site k reads the tensors
- * of consecutive points contiguously):
- *
- *  Section D, offset 0: dense site tensors, complex64 (re, im float pairs).
- *    Tensor of site k of point i, element [alpha][beta] at complex index
- *        ((k*N + i)*chi + alpha)*chi + beta .
+ * MPS buffer layout (site-major so that a sweep over site k reads the data of
+ * consecutive points contiguously).  With chi = 2^reps, the MPS of a point is
+ *    psi(s_0..s_{n-1}) = e_0^T A_0^{s_0} A_1^{s_1} ... A_{n-1}^{s_{n-1}} 1 ,
  *    A_k[alpha][beta] = 2^(-reps/2) * sgn(beta)
  *                       * exp(i*(2 x_k |beta| + theta_{k-1} |alpha XOR beta|)),
- *    theta_{-1} = 0, |.| = number of set bits, and
- *    sgn(beta) = (-1)^(sum_{l=1}^{reps-1} beta_l beta_{l-1}) with beta_l the
- *    l-th bit of beta.  Bit l of a bond index is the value qubit k carries
- *    after repetition l+1; the physical index of A_k is s = bit (reps-1) of
- *    beta, so A_k^s[alpha][beta] = A_k[alpha][beta] if beta's top bit equals
- *    s and 0 otherwise.  The state is
- *        psi(s_0..s_{n-1}) = e_0^T A_0^{s_0} A_1^{s_1} ... A_{n-1}^{s_{n-1}} 1 ,
- *    with left boundary e_0 (row 0 of A_0) and right boundary all ones.
+ * theta_{-1} = 0, |.| = number of set bits, sgn(beta) =
+ * (-1)^(sum_{l=1}^{reps-1} beta_l beta_{l-1}) with beta_l the l-th bit of
+ * beta; bit l of a bond index is the value qubit k carries after repetition
+ * l+1, the physical index of A_k is s = bit (reps-1) of beta
+ * (A_k^s[alpha][beta] = A_k[alpha][beta] if beta's top bit equals s, else 0),
+ * the left boundary is e_0 (row 0 of A_0) and the right boundary all ones.
+ * The buffer holds this MPS in a diagonal gauge, compactly:
  *
- *  Section G, offset n*N*chi*chi*8: gauge generators, 4 floats per (k, i) at
- *    float4 index k*N + i.  With g_k = exp(i(2 x_k + theta_{k-1})):
+ *  Section G, offset 0: gauge generators, 4 floats per (k, i) at float4 index
+ *    k*N + i.  With g_k = exp(i(2 x_k + theta_{k-1})):
  *      k >= 1: (a_k.re, a_k.im, b_k.re, b_k.im),
  *              a_k = exp(i theta_{k-1}) g_{k-1},  b_k = exp(-i theta_{k-1}) g_{k-1};
  *      k == 0: (g_{n-1}.re, g_{n-1}.im, 0, 0).
  *    In the diagonal gauge D_k = diag(1, g_k) per bond bit, every site tensor
- *    of Section D becomes 2^(-reps/2) * sgn(beta) * prod_l C_k[beta_l][alpha_l]
+ *    A_k becomes 2^(-reps/2) * sgn(beta) * prod_l C_k[beta_l][alpha_l]
  *    with C_k = [[1, a_k], [1, b_k]] (row = new bit, column = old bit), the
  *    left boundary becomes sgn, and the right boundary becomes g_{n-1}^|beta|.
  *
- *  Section L, offset n*N*chi*chi*8 + n*N*16: the FP32 residuals of Section G,
- *    same layout: each component is (float)(value - (double)G component), so
- *    G + L is the FP64 generator to ~2^-48 relative.  Read only by the FP64
- *    refinement (qsvm_gram_opts.refine_above).
+ *  Section L, offset n*N*16: the FP32 residuals of Section G, same layout:
+ *    each component is (float)(value - (double)G component), so G + L is the
+ *    FP64 generator to ~2^-48 relative.  Read only by the FP64 refinement
+ *    (qsvm_gram_opts.refine_above).
+ *
+ * The dense tensors A_k themselves are not part of the MPS buffer: only the
+ * dense sweep (QSVM_SWEEP_DENSE, a cross-check that assumes nothing about
+ * the tensors) reads them, from a separate buffer written by
+ * qsvm_encode_dense and passed in qsvm_gram_opts.dense_a / dense_b.
  */
 size_t qsvm_mps_bytes(int64_t N, int32_t n_qubits, int32_t reps);
 
@@ -171,11 +178,29 @@ size_t qsvm_mps_bytes(int64_t N, int32_t n_qubits, int32_t reps);
  *   mps        device output buffer of at least qsvm_mps_bytes(N, n, reps)
  *              bytes, 16-byte aligned; layout above.
  *   mps_bytes  size of that buffer; smaller than needed -> QSVM_ERR_SIZE.
- * Phases are formed and reduced in FP64 and rounded once to FP32 (Sections D
- * and G); Section L keeps the rounding residual of each generator.
+ * Phases are formed and reduced in FP64 and rounded once to FP32 (Section G);
+ * Section L keeps the rounding residual of each generator.
  */
 qsvm_status qsvm_encode_mps(const double* X, int64_t N, int32_t n_qubits, int32_t reps,
                             void* mps, size_t mps_bytes, void* stream);
+
+/*
+ * Bytes of the dense site tensors of N points: n*N*chi*chi*8 (complex64).
+ * 0 for arguments outside the supported range.
+ */
+size_t qsvm_dense_bytes(int64_t N, int32_t n_qubits, int32_t reps);
+
+/*
+ * Write the dense site tensors A_k of the MPS above (complex64, re/im float
+ * pairs), tensor of site k of point i, element [alpha][beta] at complex index
+ * ((k*N + i)*chi + alpha)*chi + beta.  Only the dense sweep reads them.
+ *   dense        device output of at least qsvm_dense_bytes(N, n, reps) bytes,
+ *                16-byte aligned; dense_bytes its size (smaller -> QSVM_ERR_SIZE).
+ * Other arguments as qsvm_encode_mps; each entry's phase is formed in FP64 and
+ * rounded once to FP32.
+ */
+qsvm_status qsvm_encode_dense(const double* X, int64_t N, int32_t n_qubits, int32_t reps,
+                              void* dense, size_t dense_bytes, void* stream);
 
 /* The threshold qsvm_gram_opts.refine_above = 0 selects for n_qubits:
  * (5e-6 / (4e-6 + 2e-8 n))^2; a value >= 1 means no entry needs refining and

@@ -70,6 +70,8 @@ struct Opts {
   int64_t row_begin = 0, row_end = 0;
   double* log_k = nullptr;
   double refine_above = 0.0;  // 0: automatic (qsvm::auto_refine_threshold); negative: no refinement
+  const void* dense_a = nullptr;  // dense tensors of the sets (dense sweep only)
+  const void* dense_b = nullptr;
 };
 
 qsvm_status read_opts(const qsvm_gram_opts* o, int64_t rows, Opts& out, const char* what) {
@@ -99,6 +101,14 @@ qsvm_status read_opts(const qsvm_gram_opts* o, int64_t rows, Opts& out, const ch
   if (!(o->refine_above == o->refine_above))  // NaN
     return fail(QSVM_ERR_INVALID_ARG, "%s: refine_above is NaN", what);
   if (o->refine_above != 0.0) out.refine_above = o->refine_above;
+  out.dense_a = o->dense_a;
+  out.dense_b = o->dense_b ? o->dense_b : o->dense_a;
+  if (out.sweep == QSVM_SWEEP_DENSE) {
+    if (!out.dense_a)
+      return fail(QSVM_ERR_INVALID_ARG, "%s: the dense sweep needs opts.dense_a (tensors from qsvm_encode_dense)", what);
+    if ((reinterpret_cast<uintptr_t>(out.dense_a) | reinterpret_cast<uintptr_t>(out.dense_b)) % 16 != 0)
+      return fail(QSVM_ERR_INVALID_ARG, "%s: dense tensors are not 16-byte aligned", what);
+  }
   return QSVM_OK;
 }
 
@@ -193,10 +203,10 @@ qsvm_status run_gram(const void* mps_a, int64_t Na, const void* mps_b, int64_t N
                 (long long)tiles_b);
   if (o.row_end <= o.row_begin) return ok();  // empty row range: nothing to do
   qsvm::SweepArgs a{};
-  a.gen_a = reinterpret_cast<const float4*>(static_cast<const char*>(mps_a) + qsvm::dense_bytes(Na, n, reps));
-  a.gen_b = reinterpret_cast<const float4*>(static_cast<const char*>(mps_b) + qsvm::dense_bytes(Nb, n, reps));
-  a.dense_a = static_cast<const float2*>(mps_a);
-  a.dense_b = static_cast<const float2*>(mps_b);
+  a.gen_a = static_cast<const float4*>(mps_a);
+  a.gen_b = static_cast<const float4*>(mps_b);
+  a.dense_a = static_cast<const float2*>(o.dense_a);
+  a.dense_b = static_cast<const float2*>(o.dense_b);
   a.K = K;
   a.log_k = o.log_k;
   a.Na = Na;
@@ -257,8 +267,9 @@ qsvm_status gram_tile_list(const void* mps, int64_t N, int32_t n_qubits, int32_t
   if (n_tiles == 0) return ok();
   if (injected_launch_failure()) return fail(QSVM_ERR_HIP, "%s: injected launch failure (QSVM_FAULT_INJECT=launch)", what);
   qsvm::SweepArgs a{};
-  a.gen_a = a.gen_b = reinterpret_cast<const float4*>(static_cast<const char*>(mps) + qsvm::dense_bytes(N, n_qubits, reps));
-  a.dense_a = a.dense_b = static_cast<const float2*>(mps);
+  a.gen_a = a.gen_b = static_cast<const float4*>(mps);
+  a.dense_a = static_cast<const float2*>(o.dense_a);
+  a.dense_b = static_cast<const float2*>(o.dense_a);  // one set
   a.K = K;
   a.log_k = o.log_k;
   a.Na = a.Nb = N;
@@ -294,6 +305,7 @@ qsvm_status gram_sym(const void* mps, int64_t N, int32_t n_qubits, int32_t reps,
   Opts o;
   s = read_opts(opts, N, o, what);
   if (s != QSVM_OK) return s;
+  o.dense_b = o.dense_a;  // one set
   return run_gram(mps, N, mps, N, n_qubits, reps, K, ldk, o, true, stream, what, src);
 }
 
@@ -341,6 +353,26 @@ qsvm_status qsvm_encode_mps(const double* X, int64_t N, int32_t n_qubits, int32_
     return fail(QSVM_ERR_SIZE, "%s: mps_bytes = %zu < %zu needed", what, mps_bytes, need);
   if (injected_launch_failure()) return fail(QSVM_ERR_HIP, "%s: injected launch failure (QSVM_FAULT_INJECT=launch)", what);
   return hip_status(qsvm::launch_encode(X, N, n_qubits, reps, mps, static_cast<hipStream_t>(stream)), what);
+}
+
+size_t qsvm_dense_bytes(int64_t N, int32_t n_qubits, int32_t reps) {
+  if (N < 1 || N > kMaxN || n_qubits < 1 || n_qubits > kMaxQubits || reps < 1 || reps > qsvm::kMaxReps) return 0;
+  return size_t(qsvm::dense_bytes(N, n_qubits, reps));
+}
+
+qsvm_status qsvm_encode_dense(const double* X, int64_t N, int32_t n_qubits, int32_t reps, void* dense,
+                              size_t dense_bytes, void* stream) {
+  const char* what = "qsvm_encode_dense";
+  qsvm_status s = check_shape(N, n_qubits, reps, what);
+  if (s != QSVM_OK) return s;
+  if (!X) return fail(QSVM_ERR_INVALID_ARG, "%s: X is NULL", what);
+  if (!dense) return fail(QSVM_ERR_INVALID_ARG, "%s: dense is NULL", what);
+  if (reinterpret_cast<uintptr_t>(dense) % 16 != 0) return fail(QSVM_ERR_INVALID_ARG, "%s: dense is not 16-byte aligned", what);
+  if (reinterpret_cast<uintptr_t>(X) % 8 != 0) return fail(QSVM_ERR_INVALID_ARG, "%s: X is not 8-byte aligned", what);
+  const size_t need = qsvm_dense_bytes(N, n_qubits, reps);
+  if (dense_bytes < need) return fail(QSVM_ERR_SIZE, "%s: dense_bytes = %zu < %zu needed", what, dense_bytes, need);
+  if (injected_launch_failure()) return fail(QSVM_ERR_HIP, "%s: injected launch failure (QSVM_FAULT_INJECT=launch)", what);
+  return hip_status(qsvm::launch_encode_dense(X, N, n_qubits, reps, dense, static_cast<hipStream_t>(stream)), what);
 }
 
 double qsvm_auto_refine_threshold(int32_t n_qubits) {

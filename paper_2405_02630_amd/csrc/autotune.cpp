@@ -211,8 +211,7 @@ hipError_t autotune_run(int32_t reps, int32_t n, int64_t N, hipStream_t stream, 
   QSVM_TRY(launch_encode(X, N, n, reps, mps, stream));
   {
     SweepArgs a{};
-    a.gen_a = a.gen_b = reinterpret_cast<const float4*>(static_cast<char*>(mps) + dense_bytes(N, n, reps));
-    a.dense_a = a.dense_b = static_cast<const float2*>(mps);
+    a.gen_a = a.gen_b = static_cast<const float4*>(mps);  // butterfly sweep: no dense tensors
     a.K = K;
     a.Na = a.Nb = N;
     a.ldk = N;

@@ -90,9 +90,7 @@ bool build_jobs(const qsvm_job* jobs, int32_t n_jobs, int32_t renorm_every, int3
     }
     Entry e{};
     SweepArgs& a = e.job.args;
-    a.gen_a = a.gen_b =
-        reinterpret_cast<const float4*>(static_cast<const char*>(J.mps) + dense_bytes(J.N, J.n_qubits, J.reps));
-    a.dense_a = a.dense_b = static_cast<const float2*>(J.mps);
+    a.gen_a = a.gen_b = static_cast<const float4*>(J.mps);  // butterfly sweep: no dense tensors
     a.K = J.K;
     a.log_k = J.log_k;
     a.Na = a.Nb = J.N;

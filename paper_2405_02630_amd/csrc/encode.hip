@@ -11,17 +11,19 @@
 //     w_k(c) = 2^{-r/2} (-1)^{sum_l c_l c_{l-1}} exp(2 i x_k |c|),
 //     J_k(c, c') = exp(i theta_k |c XOR c'|),
 // i.e. an MPS with bond dimension exactly 2^r and site tensor
-// A_k[alpha][beta] = J_{k-1}(alpha, beta) w_k(beta).  Section D stores these
-// tensors; Section G stores the generators (a_k, b_k, g_{n-1}) of the same
+// A_k[alpha][beta] = J_{k-1}(alpha, beta) w_k(beta) (the dense tensors);
+// Section G stores the generators (a_k, b_k, g_{n-1}) of the same
 // MPS in the diagonal gauge D_k = diag(1, g_k) per bond bit, where
 // J_{k-1} w_k factorises into 2x2 blocks [[1, a_k], [1, b_k]], and Section L
 // the FP32 residuals of those generators (FP32 value + residual = the FP64
 // value to ~2^-48), read only by the FP64 refinement (layout and formulas in
-// include/qsvm.h).
+// include/qsvm.h).  The MPS buffer holds Sections G and L; the dense tensors
+// A_k are written on request into a buffer of their own (only the dense
+// sweep reads them).
 //
-// One thread per (site k, point i).  All phases are formed in FP64 (the
-// largest angle is below 3 * (2 pi + 2 pi^2) ~ 78 rad) and each tensor entry
-// is rounded to FP32 once.
+// One thread per (site k, point i) in both kernels.  All phases are formed in
+// FP64 (the largest angle is below 4 * (2 pi + 2 pi^2) ~ 104 rad) and each
+// value is rounded to FP32 once.
 
 #include "qsvm_internal.h"
 
@@ -34,15 +36,15 @@ __device__ __forceinline__ double zz_theta(double a, double b) {
   return 2.0 * (kPi - a) * (kPi - b);
 }
 
+// Dense site tensors (the opt-in buffer of qsvm_encode_dense): one thread per
+// (site k, point i) computes the point's chi x chi tensor; the tensors go out
+// through LDS so that consecutive lanes store consecutive addresses.
 template <int R>
 __global__ void __launch_bounds__(256)
-encode_kernel(const double* __restrict__ X, int64_t N, int32_t n,
-              float2* __restrict__ dense, float4* __restrict__ gen, float4* __restrict__ gen_lo) {
+encode_dense_kernel(const double* __restrict__ X, int64_t N, int32_t n, float2* __restrict__ dense) {
   constexpr int CHI = 1 << R;
   constexpr int E = CHI * CHI;             // entries per site tensor
   constexpr int CH = (E < 16) ? E : 16;    // entries staged per round
-  // Tensors go out through LDS so that consecutive lanes store consecutive
-  // addresses (each thread computes one point's whole tensor).
   __shared__ float2 stage[256 * CH];
   const int64_t i0 = int64_t(blockIdx.x) * blockDim.x;
   const int64_t i = i0 + threadIdx.x;
@@ -52,8 +54,6 @@ encode_kernel(const double* __restrict__ X, int64_t N, int32_t n,
 
   const double xk = x[k];
   const double th_prev = (k >= 1) ? zz_theta(x[k - 1], xk) : 0.0;  // theta_{k-1}
-
-  // ---- Section D: dense tensor A_k[alpha][beta] ----
   // powers p^m = exp(2 i x_k m) and t^m = exp(i theta_{k-1} m), m = 0..R, in FP64
   double pr[R + 1], pi_[R + 1], tr[R + 1], ti[R + 1];
   double sp, cp, st, ct;
@@ -95,14 +95,24 @@ encode_kernel(const double* __restrict__ X, int64_t N, int32_t n,
     }
     __syncthreads();
   }
-  if (!valid) return;
+}
 
-  // ---- Section G: gauge generators (FP32), Section L: their FP32 residuals ----
+// Sections G and L (the MPS buffer): one thread per (site k, point i) forms
+// the generator phases in FP64, rounds each component to FP32 once and keeps
+// the residual; consecutive threads write consecutive 16-byte entries.
+__global__ void __launch_bounds__(256)
+encode_gen_kernel(const double* __restrict__ X, int64_t N, int32_t n, float4* __restrict__ gen,
+                  float4* __restrict__ gen_lo) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int32_t k = blockIdx.y;
+  if (i >= N) return;
+  const double* x = X + i * n;
   double g0, g1, g2, g3;
   if (k >= 1) {
     // G_{k-1} = 2 x_{k-1} + theta_{k-2};  a_k = e^{i(theta_{k-1} + G_{k-1})},
     // b_k = e^{i(G_{k-1} - theta_{k-1})}
     const double xm = x[k - 1];
+    const double th_prev = zz_theta(xm, x[k]);
     const double th_pp = (k >= 2) ? zz_theta(x[k - 2], xm) : 0.0;
     const double G = 2.0 * xm + th_pp;
     sincos(G + th_prev, &g1, &g0);
@@ -124,16 +134,24 @@ encode_kernel(const double* __restrict__ X, int64_t N, int32_t n,
 
 hipError_t launch_encode(const double* X, int64_t N, int32_t n, int32_t reps, void* mps,
                          hipStream_t stream) {
+  if (reps < 1 || reps > kMaxReps) return hipErrorInvalidValue;
+  float4* gen = static_cast<float4*>(mps);
+  float4* gen_lo = gen + int64_t(n) * N;  // Section L follows Section G
+  hipLaunchKernelGGL(encode_gen_kernel, dim3(unsigned((N + 255) / 256), unsigned(n)), dim3(256), 0, stream, X, N, n,
+                     gen, gen_lo);
+  return hipGetLastError();
+}
+
+hipError_t launch_encode_dense(const double* X, int64_t N, int32_t n, int32_t reps, void* dense,
+                               hipStream_t stream) {
   const dim3 block(256);
   const dim3 grid(unsigned((N + 255) / 256), unsigned(n));
-  float2* dense = static_cast<float2*>(mps);
-  float4* gen = reinterpret_cast<float4*>(static_cast<char*>(mps) + dense_bytes(N, n, reps));
-  float4* gen_lo = gen + int64_t(n) * N;  // Section L follows Section G
+  float2* d = static_cast<float2*>(dense);
   switch (reps) {
-    case 1: hipLaunchKernelGGL(encode_kernel<1>, grid, block, 0, stream, X, N, n, dense, gen, gen_lo); break;
-    case 2: hipLaunchKernelGGL(encode_kernel<2>, grid, block, 0, stream, X, N, n, dense, gen, gen_lo); break;
-    case 3: hipLaunchKernelGGL(encode_kernel<3>, grid, block, 0, stream, X, N, n, dense, gen, gen_lo); break;
-    case 4: hipLaunchKernelGGL(encode_kernel<4>, grid, block, 0, stream, X, N, n, dense, gen, gen_lo); break;
+    case 1: hipLaunchKernelGGL(encode_dense_kernel<1>, grid, block, 0, stream, X, N, n, d); break;
+    case 2: hipLaunchKernelGGL(encode_dense_kernel<2>, grid, block, 0, stream, X, N, n, d); break;
+    case 3: hipLaunchKernelGGL(encode_dense_kernel<3>, grid, block, 0, stream, X, N, n, d); break;
+    case 4: hipLaunchKernelGGL(encode_dense_kernel<4>, grid, block, 0, stream, X, N, n, d); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

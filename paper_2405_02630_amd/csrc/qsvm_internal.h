@@ -9,19 +9,20 @@
 
 namespace qsvm {
 
-// Bytes of section D (dense tensors) for N points.
+// Bytes of the dense site tensors (the buffer of qsvm_encode_dense) for N points.
 inline int64_t dense_bytes(int64_t N, int32_t n, int32_t reps) {
   const int64_t chi = int64_t(1) << reps;
   return int64_t(n) * N * chi * chi * 8;
 }
-// Bytes of the whole MPS buffer: Section D, then Section G (generators) and
-// Section L (their residuals), 16 B per site and point each.
-inline int64_t mps_total_bytes(int64_t N, int32_t n, int32_t reps) {
-  return dense_bytes(N, n, reps) + int64_t(n) * N * 32;
-}
+// Bytes of the MPS buffer: Section G (generators), then Section L (their
+// residuals), 16 B per site and point each.
+inline int64_t mps_total_bytes(int64_t N, int32_t n, int32_t /*reps*/) { return int64_t(n) * N * 32; }
 
+// Sections G and L into mps; the dense tensors into their own buffer.
 hipError_t launch_encode(const double* X, int64_t N, int32_t n, int32_t reps, void* mps,
                          hipStream_t stream);
+hipError_t launch_encode_dense(const double* X, int64_t N, int32_t n, int32_t reps, void* dense,
+                               hipStream_t stream);
 struct SweepArgs;
 constexpr int kButterflyVariants = 4;  // per reps, see launch_sweep_butterfly_args
 // Sites between power-of-two renormalisations of the FP32 environment: the

@@ -40,6 +40,8 @@ class GramOpts(ctypes.Structure):
         ("row_end", ctypes.c_int64),
         ("log_k", ctypes.c_void_p),
         ("refine_above", ctypes.c_double),
+        ("dense_a", ctypes.c_void_p),
+        ("dense_b", ctypes.c_void_p),
     ]
 
 
@@ -123,6 +125,10 @@ def load_library(path: str = LIB_PATH):
     lib.qsvm_mps_bytes.restype = sz
     lib.qsvm_encode_mps.argtypes = [vp, i64, i32, i32, vp, sz, vp]
     lib.qsvm_encode_mps.restype = i32
+    lib.qsvm_dense_bytes.argtypes = [i64, i32, i32]
+    lib.qsvm_dense_bytes.restype = sz
+    lib.qsvm_encode_dense.argtypes = [vp, i64, i32, i32, vp, sz, vp]
+    lib.qsvm_encode_dense.restype = i32
     lib.qsvm_auto_refine_threshold.argtypes = [i32]
     lib.qsvm_auto_refine_threshold.restype = ctypes.c_double
     lib.qsvm_gram.argtypes = [vp, i64, vp, i64, i32, i32, vp, i64, ctypes.POINTER(GramOpts), vp]
@@ -221,20 +227,41 @@ def _device_ptr(t, name, dtype=None):
 
 @dataclass
 class MPS:
-    """Device MPS buffer written by qsvm_encode_mps (layout in include/qsvm.h)."""
+    """Device MPS buffer written by qsvm_encode_mps (layout in include/qsvm.h),
+    with the dense site tensors of qsvm_encode_dense when they were asked for
+    (only the dense sweep reads them)."""
 
     buf: "object"  # torch.uint8 CUDA tensor
     N: int
     n: int
     reps: int
+    dense: "object" = None  # torch.uint8 CUDA tensor or None
 
 
 def qsvm_mps_bytes(N: int, n_qubits: int, reps: int) -> int:
     return int(load_library().qsvm_mps_bytes(N, n_qubits, reps))
 
 
-def qsvm_encode_mps(X, reps: int, out=None, stream=None) -> MPS:
-    """Encode the rows of X (CUDA float64, N x n) as exact MPS."""
+def qsvm_dense_bytes(N: int, n_qubits: int, reps: int) -> int:
+    return int(load_library().qsvm_dense_bytes(N, n_qubits, reps))
+
+
+def qsvm_encode_dense(X, reps: int, out=None, stream=None):
+    """Dense site tensors of the rows of X (a uint8 CUDA tensor of qsvm_dense_bytes)."""
+    import torch
+
+    lib = load_library()
+    N, n = int(X.shape[0]), int(X.shape[1])
+    if out is None:
+        out = torch.empty(max(1, lib.qsvm_dense_bytes(N, n, reps)), dtype=torch.uint8, device=X.device)
+    _check(lib.qsvm_encode_dense(_device_ptr(X, "X", torch.float64), N, n, reps, _device_ptr(out, "out"), out.numel(),
+                                 _stream_ptr(stream)))
+    return out
+
+
+def qsvm_encode_mps(X, reps: int, out=None, stream=None, dense: bool = False) -> MPS:
+    """Encode the rows of X (CUDA float64, N x n) as exact MPS; with dense=True
+    also write the dense site tensors (for the dense sweep) into m.dense."""
     import torch
 
     lib = load_library()
@@ -251,7 +278,7 @@ def qsvm_encode_mps(X, reps: int, out=None, stream=None) -> MPS:
         _device_ptr(X, "X", torch.float64), N, n, reps, _device_ptr(out, "out"), out.numel(), _stream_ptr(stream)
     )
     _check(st)
-    return MPS(out, N, n, reps)
+    return MPS(out, N, n, reps, qsvm_encode_dense(X, reps, stream=stream) if dense else None)
 
 
 N_VARIANTS = 4
@@ -283,8 +310,10 @@ def qsvm_set_tuned_variant(reps: int, n_qubits: int, N: int, variant: int) -> No
     _check(load_library().qsvm_set_tuned_variant(reps, n_qubits, N, variant))
 
 
-def _opts(renorm_every, sweep, diag_mode, rows, log_k, variant=0, refine_above=0.0):
+def _opts(renorm_every, sweep, diag_mode, rows, log_k, variant=0, refine_above=0.0, dense_a=None, dense_b=None):
     o = GramOpts()
+    o.dense_a = None if dense_a is None else dense_a.data_ptr()
+    o.dense_b = None if dense_b is None else dense_b.data_ptr()
     o.refine_above = refine_above
     o.variant = variant
     o.renorm_every = renorm_every
@@ -317,7 +346,7 @@ def qsvm_gram(mps_a: MPS, mps_b: MPS, K=None, *, log_k=None, renorm_every: int =
         raise ValueError("K must be 2-D with unit column stride and at least Na rows")
     if log_k is not None and (log_k.shape != K.shape or log_k.stride() != K.stride() or log_k.dtype != torch.float64):
         raise ValueError("log_k must match K's shape, strides and dtype")
-    o = _opts(renorm_every, sweep, 0, rows, log_k, variant, refine_above)
+    o = _opts(renorm_every, sweep, 0, rows, log_k, variant, refine_above, mps_a.dense, mps_b.dense)
     st = lib.qsvm_gram(
         _device_ptr(mps_a.buf, "mps_a"), mps_a.N, _device_ptr(mps_b.buf, "mps_b"), mps_b.N, mps_a.n, mps_a.reps,
         ctypes.c_void_p(K.data_ptr()), K.stride(0), ctypes.byref(o), _stream_ptr(stream),
@@ -339,7 +368,7 @@ def qsvm_gram_sym(mps: MPS, K=None, *, log_k=None, renorm_every: int = 0, sweep:
         raise ValueError("K must be 2-D with unit column stride and at least N rows")
     if log_k is not None and (log_k.shape != K.shape or log_k.stride() != K.stride() or log_k.dtype != torch.float64):
         raise ValueError("log_k must match K's shape, strides and dtype")
-    o = _opts(renorm_every, sweep, diag_mode, rows, log_k, variant, refine_above)
+    o = _opts(renorm_every, sweep, diag_mode, rows, log_k, variant, refine_above, mps.dense)
     st = lib.qsvm_gram_sym(
         _device_ptr(mps.buf, "mps"), mps.N, mps.n, mps.reps, ctypes.c_void_p(K.data_ptr()), K.stride(0),
         ctypes.byref(o), _stream_ptr(stream),
@@ -364,7 +393,7 @@ def qsvm_gram_sym_noalloc(mps: MPS, K, *, log_k=None, renorm_every: int = 0, swe
         raise ValueError("K must be a float64 2-D tensor with unit column stride and at least N rows")
     if log_k is not None and (log_k.shape != K.shape or log_k.stride() != K.stride() or log_k.dtype != torch.float64):
         raise ValueError("log_k must match K's shape, strides and dtype")
-    o = _opts(renorm_every, sweep, diag_mode, rows, log_k, variant, refine_above)
+    o = _opts(renorm_every, sweep, diag_mode, rows, log_k, variant, refine_above, mps.dense)
     st = lib.qsvm_gram_sym_noalloc(
         _device_ptr(mps.buf, "mps"), mps.N, mps.n, mps.reps, ctypes.c_void_p(K.data_ptr()), K.stride(0),
         ctypes.byref(o), _stream_ptr(stream),
@@ -511,7 +540,7 @@ def qsvm_gram_sym_tiles(mps: MPS, tiles, n_tiles: int, K, *, log_k=None, renorm_
                         sweep: int = SWEEP_AUTO, diag_mode: int = 0, variant: int = 0, refine_above: float = 0.0,
                         stream=None):
     """Exact symmetric Gram on a device list of (ti, tj) tiles (int32 tensor)."""
-    o = _opts(renorm_every, sweep, diag_mode, None, log_k, variant, refine_above)
+    o = _opts(renorm_every, sweep, diag_mode, None, log_k, variant, refine_above, mps.dense)
     _check(load_library().qsvm_gram_sym_tiles(
         _device_ptr(mps.buf, "mps"), mps.N, mps.n, mps.reps, _p(tiles), n_tiles, _p(K), K.stride(0),
         ctypes.byref(o), _stream_ptr(stream)))

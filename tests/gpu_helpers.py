@@ -44,17 +44,17 @@ def to_dev(X):
     return torch.as_tensor(np.ascontiguousarray(X, dtype=np.float64), device="cuda:0")
 
 
-def encode(X, reps):
+def encode(X, reps, dense=False):
     from paper_2405_02630_amd import qsvm
 
-    return qsvm.qsvm_encode_mps(to_dev(X), reps)
+    return qsvm.qsvm_encode_mps(to_dev(X), reps, dense=dense)
 
 
 def gram_sym(X, reps, log=True, **kw):
     import torch
     from paper_2405_02630_amd import qsvm
 
-    m = encode(X, reps)
+    m = encode(X, reps, dense=kw.get("sweep") == qsvm.SWEEP_DENSE)
     K = torch.empty((m.N, m.N), dtype=torch.float64, device="cuda:0")
     L = torch.empty_like(K) if log else None
     qsvm.qsvm_gram_sym(m, K, log_k=L, **kw)
@@ -66,7 +66,8 @@ def gram_rect(Xa, Xb, reps, log=True, **kw):
     import torch
     from paper_2405_02630_amd import qsvm
 
-    ma, mb = encode(Xa, reps), encode(Xb, reps)
+    dense = kw.get("sweep") == qsvm.SWEEP_DENSE
+    ma, mb = encode(Xa, reps, dense), encode(Xb, reps, dense)
     K = torch.empty((ma.N, mb.N), dtype=torch.float64, device="cuda:0")
     L = torch.empty_like(K) if log else None
     qsvm.qsvm_gram(ma, mb, K, log_k=L, **kw)
@@ -75,16 +76,19 @@ def gram_rect(Xa, Xb, reps, log=True, **kw):
 
 
 def mps_sections(m, residuals=False):
-    """Host copies of Section D (N, n, chi, chi complex) and Section G (n, N, 4 float),
-    and with residuals=True also Section L (n, N, 4 float)."""
+    """Host copies of the dense tensors (n, N, chi, chi complex; None unless
+    encoded with dense=True) and of Section G (n, N, 4 float), and with
+    residuals=True also Section L (n, N, 4 float)."""
     N, n, reps = m.N, m.n, m.reps
     chi = 1 << reps
     raw = m.buf.cpu().numpy()
-    nd = n * N * chi * chi * 8
-    dense = raw[:nd].view(np.complex64).reshape(n, N, chi, chi)
-    gen = raw[nd : nd + n * N * 16].view(np.float32).reshape(n, N, 4)
+    assert raw.size == n * N * 32  # the MPS buffer: Sections G and L only
+    dense = None
+    if m.dense is not None:
+        dense = m.dense.cpu().numpy()[: n * N * chi * chi * 8].view(np.complex64).reshape(n, N, chi, chi)
+    gen = raw[: n * N * 16].view(np.float32).reshape(n, N, 4)
     if residuals:
-        lo = raw[nd + n * N * 16 : nd + n * N * 32].view(np.float32).reshape(n, N, 4)
+        lo = raw[n * N * 16 : n * N * 32].view(np.float32).reshape(n, N, 4)
         return dense, gen, lo
     return dense, gen
 

@@ -51,21 +51,61 @@ def test_abi_version(lib):
 
 
 def test_opts_struct_layout():
-    # int32 x4, int64 x2, pointer, double: 48 bytes, log_k at 32, refine_above at 40
-    assert ctypes.sizeof(qsvm.GramOpts) == 48
+    # int32 x4, int64 x2, pointer, double, pointer x2: 64 bytes
+    assert ctypes.sizeof(qsvm.GramOpts) == 64
     assert qsvm.GramOpts.log_k.offset == 32
     assert qsvm.GramOpts.refine_above.offset == 40
+    assert qsvm.GramOpts.dense_a.offset == 48 and qsvm.GramOpts.dense_b.offset == 56
 
 
 @pytest.mark.parametrize("N,n,reps", [(1, 1, 1), (32, 8, 2), (4096, 784, 2), (1024, 784, 3), (7, 3, 1), (1024, 784, 4)])
 def test_mps_bytes_formula(N, n, reps):
+    # Sections G and L only (16 bytes each per site and point); the dense
+    # tensors have their own buffer
     chi = 2**reps
-    assert qsvm.qsvm_mps_bytes(N, n, reps) == n * N * (chi * chi * 8 + 32)
+    assert qsvm.qsvm_mps_bytes(N, n, reps) == n * N * 32
+    assert qsvm.qsvm_dense_bytes(N, n, reps) == n * N * chi * chi * 8
 
 
 @pytest.mark.parametrize("N,n,reps", [(0, 8, 2), (8, 0, 2), (8, 8, 0), (8, 8, 5), (-1, 8, 2), (8, 65536, 2), (2**31, 8, 2)])
 def test_mps_bytes_rejects(N, n, reps):
     assert qsvm.qsvm_mps_bytes(N, n, reps) == 0
+    assert qsvm.qsvm_dense_bytes(N, n, reps) == 0
+
+
+def test_encode_dense_validation(lib, no_inject):
+    def enc(X=FAKE, N=8, n=4, reps=2, d=FAKE2, nbytes=None):
+        nbytes = max(qsvm.qsvm_dense_bytes(N, n, reps), 1) if nbytes is None else nbytes
+        return lib.qsvm_encode_dense(X, N, n, reps, d, nbytes, None)
+
+    assert enc(X=None) == qsvm.QSVM_ERR_INVALID_ARG
+    assert enc(d=None) == qsvm.QSVM_ERR_INVALID_ARG
+    assert enc(d=ctypes.c_void_p(0x100008)) == qsvm.QSVM_ERR_INVALID_ARG
+    assert enc(reps=5) == qsvm.QSVM_ERR_UNSUPPORTED
+    assert enc(nbytes=qsvm.qsvm_dense_bytes(8, 4, 2) - 1) == qsvm.QSVM_ERR_SIZE
+
+
+def test_dense_sweep_needs_dense_tensors(lib, no_inject):
+    o = qsvm.GramOpts()
+    o.sweep = qsvm.SWEEP_DENSE
+    assert _sym(lib, opts=o) == qsvm.QSVM_ERR_INVALID_ARG
+    assert b"dense_a" in lib.qsvm_last_error()
+    assert _rect(lib, opts=o) == qsvm.QSVM_ERR_INVALID_ARG
+    o.dense_a = 0x300008  # misaligned
+    assert _sym(lib, opts=o) == qsvm.QSVM_ERR_INVALID_ARG
+    o.dense_a = 0x300000
+    os.environ["QSVM_FAULT_INJECT"] = "launch"
+    try:
+        assert _sym(lib, opts=o) == qsvm.QSVM_ERR_HIP  # accepted: dense_b defaults to dense_a
+        assert _rect(lib, opts=o) == qsvm.QSVM_ERR_HIP
+    finally:
+        del os.environ["QSVM_FAULT_INJECT"]
+    # the butterfly sweep needs no dense tensors
+    os.environ["QSVM_FAULT_INJECT"] = "launch"
+    try:
+        assert _sym(lib, opts=qsvm.GramOpts()) == qsvm.QSVM_ERR_HIP
+    finally:
+        del os.environ["QSVM_FAULT_INJECT"]
 
 
 def test_status_strings(lib):
@@ -204,6 +244,7 @@ def test_refine_above_nan_is_rejected(lib, no_inject):
 def test_dense_sweep_rejects_reps_4(lib, no_inject):
     opts = qsvm.GramOpts()
     opts.sweep = qsvm.SWEEP_DENSE
+    opts.dense_a = 0x300000
     assert _sym(lib, reps=4, opts=opts) == qsvm.QSVM_ERR_UNSUPPORTED
     assert b"dense sweep" in lib.qsvm_last_error()
     assert _rect(lib, reps=4, opts=opts) == qsvm.QSVM_ERR_UNSUPPORTED
@@ -243,6 +284,7 @@ def test_tile_list_with_device_count_validation(lib, no_inject):
     assert b"butterfly" in lib.qsvm_last_error()
     o = qsvm.GramOpts()
     o.sweep = qsvm.SWEEP_DENSE
+    o.dense_a = 0x300000
     assert _tiles(lib, True, opts=o) == qsvm.QSVM_ERR_UNSUPPORTED
     # a list too long for the refinement's one-launch scan of a device count
     assert _tiles(lib, True, N=370752, n_tiles=1 << 24) == qsvm.QSVM_ERR_UNSUPPORTED

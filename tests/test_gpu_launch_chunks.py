@@ -37,7 +37,7 @@ def test_tile_list_longer_than_one_launch(reps, sweep, bpt, T):
     n = 2
     N = 64 * T - 9  # ragged last tile
     X = synth.uniform_features(N, n, seed=5100 + reps)
-    m = encode(X, reps)
+    m = encode(X, reps, dense=sweep == qsvm.SWEEP_DENSE)
     ti, tj = np.triu_indices(T)
     order = np.random.default_rng(5110 + reps).permutation(ti.size)
     lst = np.stack([ti[order], tj[order]], axis=1).astype(np.int32)

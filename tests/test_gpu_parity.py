@@ -50,14 +50,14 @@ def _oracle_pairs_log(Xa, Xb, reps, ia, jb):
 
 
 # --------------------------------------------------------------------------
-# Encode: the MPS the GPU writes is the state (both sections)
+# Encode: the MPS the GPU writes is the state (generators and dense tensors)
 # --------------------------------------------------------------------------
 
 @pytest.mark.parametrize("n", [1, 2, 5, 10])
 @pytest.mark.parametrize("reps", [1, 2, 3, 4])
-def test_encode_dense_section_is_the_state(n, reps):
+def test_encode_dense_tensors_are_the_state(n, reps):
     X = synth.uniform_features(3, n, seed=10 * n + reps)
-    m = encode(X, reps)
+    m = encode(X, reps, dense=True)
     dense, _ = mps_sections(m)
     for i in range(X.shape[0]):
         psi = contract_dense(dense[:, i], reps)
@@ -79,10 +79,10 @@ def test_encode_gauge_section_is_the_state(n, reps):
 
 
 def test_encode_dense_entries_closed_form():
-    # spot-check entries of Section D against the closed form of include/qsvm.h
+    # spot-check dense entries against the closed form of include/qsvm.h
     X = synth.uniform_features(5, 7, seed=3)
     reps = 3
-    m = encode(X, reps)
+    m = encode(X, reps, dense=True)
     dense, _ = mps_sections(m)
     for (k, i, a, b) in [(0, 0, 0, 5), (3, 2, 6, 1), (6, 4, 7, 7), (5, 1, 2, 4)]:
         th = 2 * (math.pi - X[i, k - 1]) * (math.pi - X[i, k]) if k else 0.0

@@ -85,7 +85,7 @@ def test_every_variant_and_the_dense_sweep_agree_after_refinement():
 
     base, Xp, _, _ = synth.image_near_duplicates(seed=33, n_base=30)
     X = np.concatenate([base, Xp[:60]])  # 90 points, near-duplicate pairs inside
-    m = encode(X, 2)
+    m = encode(X, 2, dense=True)
     Ks = [qsvm.qsvm_gram_sym(m, variant=v).cpu().numpy() for v in range(1, 5)]
     torch.cuda.synchronize()
     for K in Ks[1:]:
