@@ -498,6 +498,65 @@ def surrogate_leg(args, exact_rate):
     return res
 
 
+def mlp_leg(args, rows: int = 32768, reps_timed: int = 5):
+    """The surrogate's MLP kernels at the production widths 784 (padded to
+    832) -> 512 -> 512 -> 256: the forward pass of 32768 rows (the whole
+    surrogate workload's embedding) and one training step of 8192 pairs
+    (16384 rows: gather, forward, log-domain head, backward with split-K
+    weight gradients, AdamW), timed with HIP events; the GEMMs' BF16 flop rate
+    against the 2.5 PFLOP/s dense BF16 peak."""
+    import numpy as np
+    import torch
+
+    from paper_2405_02630_amd import qsvm, synth
+    from paper_2405_02630_amd.surrogate import Surrogate, SurrogateConfig
+
+    dev = torch.device("cuda:0")
+    wl = synth.images784(seed=8, n_train=rows, n_test=0, reps=2)
+    X = torch.as_tensor(wl.X, device=dev)
+    sur = Surrogate(784, SurrogateConfig())
+    sur.embed(X)  # warm-up, buffers
+    torch.cuda.synchronize()
+    ev = _events(2)
+    ev[0].record()
+    for _ in range(reps_timed):
+        sur.embed(X)
+    ev[1].record()
+    torch.cuda.synchronize()
+    fwd_s = ev[0].elapsed_time(ev[1]) / 1e3 / reps_timed
+    dims = (sur.d_in, sur.cfg.d_h1, sur.cfg.d_h2, sur.cfg.d_out)
+    fwd_flops = 2.0 * rows * (dims[0] * dims[1] + dims[1] * dims[2] + dims[2] * dims[3])
+    rng = np.random.default_rng(3)
+    P = sur.cfg.pairs_per_step
+    ii, jj = rng.integers(0, rows, P), rng.integers(0, rows, P)
+    tgt = np.full(P, -500.0)
+    sur._pair_pass(X, ii, jj, tgt, train=True)
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(reps_timed):
+        sur._pair_pass(X, ii, jj, tgt, train=True)
+    ev[1].record()
+    torch.cuda.synchronize()
+    step_s = ev[0].elapsed_time(ev[1]) / 1e3 / reps_timed
+    # forward + backward GEMM flops of one step: forward 1x, activation and weight gradients 2x
+    # (the first layer has no activation gradient)
+    r2 = 2 * P
+    step_flops = 2.0 * r2 * (3 * dims[0] * dims[1] - dims[0] * dims[1] + 3 * dims[1] * dims[2] + 3 * dims[2] * dims[3])
+    res = {
+        "widths": list(dims),
+        "forward_rows": rows,
+        "forward_ms": fwd_s * 1e3,
+        "forward_gemm_tflops": fwd_flops / fwd_s / 1e12,
+        "forward_frac_of_bf16_peak": fwd_flops / fwd_s / 1e12 / PEAK_BF16_MATRIX_TFLOPS,
+        "train_step_pairs": P,
+        "train_step_ms": step_s * 1e3,
+        "train_step_gemm_tflops": step_flops / step_s / 1e12,
+    }
+    log(f"mlp: forward {rows} rows {fwd_s*1e3:.3f} ms ({res['forward_gemm_tflops']:.0f} TFLOP/s of GEMMs, "
+        f"{res['forward_frac_of_bf16_peak']:.3f} of peak); train step {step_s*1e3:.3f} ms")
+    return res
+
+
 def svm_accuracies(K_exact, K_sur, labels, n_train_frac=0.75):
     """One-vs-rest SVM on a precomputed Gram: train on the first 75 %, test on the rest."""
     import numpy as np
@@ -622,6 +681,7 @@ def batched_leg():
 
 
 PEAK_FP64_MATRIX_TFLOPS = 78.6  # MI355X dense FP64 MFMA
+PEAK_BF16_MATRIX_TFLOPS = 2500.0  # MI355X dense BF16 MFMA
 
 
 def sv_leg(points: int = 512, qubits=(12, 16, 20), reps: int = 2):
@@ -694,7 +754,7 @@ def main():
     ap.add_argument("--renorm-every", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=720)
-    ap.add_argument("--legs", default="exact,reps3,refine_worst,surrogate,batched,sv")  # "exact" adds the test x train Gram
+    ap.add_argument("--legs", default="exact,reps3,refine_worst,mlp,surrogate,batched,sv")  # "exact" adds the test x train Gram
     ap.add_argument("--sur-points", type=int, default=32768)
     ap.add_argument("--sur-steps", type=int, default=600)
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -817,6 +877,8 @@ def main():
         out["reps3"] = exact_reps_leg(3, N, args)
     if "refine_worst" in legs:
         out["refine_worst"] = refine_worst_leg(args)
+    if "mlp" in legs:
+        out["mlp"] = mlp_leg(args)
     if "surrogate" in legs:
         del K  # release the exact leg's buffers first
         torch.cuda.empty_cache()

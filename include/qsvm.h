@@ -474,7 +474,9 @@ typedef struct {   /* activations of `rows` inputs */
   float* H1; void* A1; /* rows x d_h1: pre-activation (f32), GELU output (bf16) */
   float* H2; void* A2; /* rows x d_h2 */
   float* E;  void* E16; /* rows x d_out embedding, f32 and bf16 */
-} qsvm_mlp_acts;
+} qsvm_mlp_acts;      /* H1, H2 and E may be NULL together (inference: only the
+                         bf16 outputs are written, which the backward pass
+                         cannot use) */
 
 typedef struct {   /* gradients (f32, shaped like the parameters) and scratch */
   float* dW1; float* db1; float* dW2; float* db2; float* dW3; float* db3;

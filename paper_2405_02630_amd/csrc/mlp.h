@@ -11,6 +11,8 @@ enum GemmEpilogue {
   EPI_BIAS_GELU = 1,     // C (float) = acc + bias (pre-activation); C2 (bf16) = gelu(C)
   EPI_BIAS = 2,          // C (float) = acc + bias; C2 (bf16) = C
   EPI_GELU_BWD = 3,      // C2 (bf16) = acc * gelu'(aux)
+  EPI_BIAS_GELU_BF16 = 4, // C2 (bf16) = gelu(acc + bias) only (inference: no pre-activation kept)
+  EPI_BIAS_BF16 = 5,      // C2 (bf16) = acc + bias only
 };
 
 struct GemmArgs {

@@ -4,6 +4,9 @@
 // distance of the embeddings [x, f(x)], ln K_hat = -c (1 - exp(-s d2)), or as
 // K_hat(x, y) = sigmoid(alpha <f(x), f(y)> + beta).
 //
+// * bf16_gemm128<EPI>: the same product for k-contiguous operands on
+//   128 x 128 tiles (2 x 2 accumulators per wave), used whenever M and N are
+//   multiples of 128 (the forward layers and the activation gradients).
 // * bf16_gemm<TA, TB, EPI>: C = op(A) op(B) on v_mfma_f32_32x32x16_bf16.
 //   A 64 x 64 output tile per block of 4 waves (each wave one 32 x 32
 //   accumulator), K in steps of 64 staged through LDS with both operands
@@ -33,6 +36,8 @@
 // GELU is the exact form x Phi(x) = x (1 + erf(x / sqrt 2)) / 2.
 
 #include <hip/hip_runtime.h>
+
+#include <atomic>
 #include <math.h>
 #include <stdint.h>
 
@@ -178,8 +183,134 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))
     } else if (EPI == EPI_GELU_BWD) {
       const float d = x * gelu_grad(g.aux[r * g.ldc + c]);
       static_cast<uint16_t*>(g.C2)[r * g.ldc + c] = f32_to_bf16(d);
+    } else if (EPI == EPI_BIAS_GELU_BF16) {
+      static_cast<uint16_t*>(g.C2)[r * g.ldc + c] = f32_to_bf16(gelu(x + g.bias[c]));
+    } else if (EPI == EPI_BIAS_BF16) {
+      static_cast<uint16_t*>(g.C2)[r * g.ldc + c] = f32_to_bf16(x + g.bias[c]);
     }
   }
+}
+
+// C = A B^T-style GEMM with both operands k-contiguous (A[m*lda + k],
+// op(B)[k][n] = B[n*ldb + k]) on 128 x 128 output tiles: 4 waves in a 2 x 2
+// grid, each wave 64 x 64 = 2 x 2 accumulators of v_mfma_f32_32x32x16_bf16,
+// so one 64-deep K step is 16 MFMAs per wave against 4 LDS fragment loads per
+// 16-deep slice (twice the arithmetic per staged byte of bf16_gemm's 64 x 64
+// tiles, and four independent accumulation chains per wave).  The next step's
+// operands (4 x 16 B per thread and operand) are loaded into registers while
+// the current step's MFMAs run.  M and N must be multiples of 128; the
+// epilogues are those of bf16_gemm.
+constexpr int G2M = 128, G2N = 128;
+
+// Epilogue of one 32 x 32 accumulator whose top-left output is (r0, c0):
+// element v is row r0 + (v/4)*8 + (lane/32)*4 + v%4, column c0 + lane%32.
+template <int EPI>
+__device__ __forceinline__ void gemm_store32(const GemmArgs& g, const f32x16_t& acc, int64_t r0, int64_t c0, int lane) {
+  const int64_t c = c0 + (lane & 31);
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int64_t r = r0 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+    const float x = acc[v];
+    if (EPI == EPI_F32) {
+      static_cast<float*>(g.C)[int64_t(blockIdx.z) * g.M * g.ldc + r * g.ldc + c] = x;
+    } else if (EPI == EPI_BIAS_GELU) {
+      const float h = x + g.bias[c];
+      static_cast<float*>(g.C)[r * g.ldc + c] = h;
+      static_cast<uint16_t*>(g.C2)[r * g.ldc + c] = f32_to_bf16(gelu(h));
+    } else if (EPI == EPI_BIAS) {
+      const float h = x + g.bias[c];
+      static_cast<float*>(g.C)[r * g.ldc + c] = h;
+      static_cast<uint16_t*>(g.C2)[r * g.ldc + c] = f32_to_bf16(h);
+    } else if (EPI == EPI_GELU_BWD) {
+      const float d = x * gelu_grad(g.aux[r * g.ldc + c]);
+      static_cast<uint16_t*>(g.C2)[r * g.ldc + c] = f32_to_bf16(d);
+    } else if (EPI == EPI_BIAS_GELU_BF16) {
+      static_cast<uint16_t*>(g.C2)[r * g.ldc + c] = f32_to_bf16(gelu(x + g.bias[c]));
+    } else if (EPI == EPI_BIAS_BF16) {
+      static_cast<uint16_t*>(g.C2)[r * g.ldc + c] = f32_to_bf16(x + g.bias[c]);
+    }
+  }
+}
+
+template <int EPI>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) bf16_gemm128(GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[G2M * GEMM_LDS_STRIDE];  // [m][k]
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[G2N * GEMM_LDS_STRIDE];  // [n][k]
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int wave = t >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const uint32_t nx = gridDim.x, tiles = gridDim.x * gridDim.y;
+  uint32_t u = blockIdx.y * nx + blockIdx.x;
+  if ((tiles & 7u) == 0) u = (u & 7u) * (tiles >> 3) + (u >> 3);  // XCD-aware order, as in bf16_gemm
+  const int64_t m0 = int64_t(u / nx) * G2M;
+  const int64_t n0 = int64_t(u % nx) * G2N;
+  const uint16_t* __restrict__ A = static_cast<const uint16_t*>(g.A);
+  const uint16_t* __restrict__ B = static_cast<const uint16_t*>(g.B);
+
+  f32x16_t c00, c01, c10, c11;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) c00[v] = c01[v] = c10[v] = c11[v] = 0.0f;
+
+  // piece p (0..1023) of a 128 x 64 step tile: row p / 8, k (p % 8) * 8;
+  // thread t moves pieces t, t + 256, t + 512, t + 768 of each operand
+  const int64_t kspan = g.K / g.splits;
+  const int64_t kbeg = int64_t(blockIdx.z) * kspan;
+  const int64_t kend = kbeg + kspan;
+  const int pr = t >> 3, pk = (t & 7) * 8;  // row (within a 32-row quarter) and k of piece t
+  const uint16_t* pa = A + (m0 + pr) * g.lda + pk;
+  const uint16_t* pb = B + (n0 + pr) * g.ldb + pk;
+  const int64_t qa = 32 * g.lda, qb = 32 * g.ldb;  // the next quarter's pieces are 32 rows down
+  uint4 a0 = *reinterpret_cast<const uint4*>(pa + kbeg), a1 = *reinterpret_cast<const uint4*>(pa + qa + kbeg);
+  uint4 a2 = *reinterpret_cast<const uint4*>(pa + 2 * qa + kbeg), a3 = *reinterpret_cast<const uint4*>(pa + 3 * qa + kbeg);
+  uint4 b0 = *reinterpret_cast<const uint4*>(pb + kbeg), b1 = *reinterpret_cast<const uint4*>(pb + qb + kbeg);
+  uint4 b2 = *reinterpret_cast<const uint4*>(pb + 2 * qb + kbeg), b3 = *reinterpret_cast<const uint4*>(pb + 3 * qb + kbeg);
+  uint16_t* sa = &As[pr * GEMM_LDS_STRIDE + pk];
+  uint16_t* sb = &Bs[pr * GEMM_LDS_STRIDE + pk];
+  constexpr int SQ = 32 * GEMM_LDS_STRIDE;  // 32 LDS rows
+  for (int64_t k0 = kbeg; k0 < kend; k0 += GBK) {
+    *reinterpret_cast<uint4*>(sa) = a0;
+    *reinterpret_cast<uint4*>(sa + SQ) = a1;
+    *reinterpret_cast<uint4*>(sa + 2 * SQ) = a2;
+    *reinterpret_cast<uint4*>(sa + 3 * SQ) = a3;
+    *reinterpret_cast<uint4*>(sb) = b0;
+    *reinterpret_cast<uint4*>(sb + SQ) = b1;
+    *reinterpret_cast<uint4*>(sb + 2 * SQ) = b2;
+    *reinterpret_cast<uint4*>(sb + 3 * SQ) = b3;
+    __syncthreads();
+    if (k0 + GBK < kend) {  // the next step's operands, in flight during this step's MFMAs
+      const int64_t kn = k0 + GBK;
+      a0 = *reinterpret_cast<const uint4*>(pa + kn);
+      a1 = *reinterpret_cast<const uint4*>(pa + qa + kn);
+      a2 = *reinterpret_cast<const uint4*>(pa + 2 * qa + kn);
+      a3 = *reinterpret_cast<const uint4*>(pa + 3 * qa + kn);
+      b0 = *reinterpret_cast<const uint4*>(pb + kn);
+      b1 = *reinterpret_cast<const uint4*>(pb + qb + kn);
+      b2 = *reinterpret_cast<const uint4*>(pb + 2 * qb + kn);
+      b3 = *reinterpret_cast<const uint4*>(pb + 3 * qb + kn);
+    }
+    const int i = lane & 31, kh = lane >> 5;
+    const uint16_t* la = &As[(wm * 64 + i) * GEMM_LDS_STRIDE + kh * 8];
+    const uint16_t* lb = &Bs[(wn * 64 + i) * GEMM_LDS_STRIDE + kh * 8];
+#pragma unroll
+    for (int ks = 0; ks < GBK; ks += 16) {
+      const bf16x8_t fa0 = *reinterpret_cast<const bf16x8_t*>(la + ks);
+      const bf16x8_t fa1 = *reinterpret_cast<const bf16x8_t*>(la + SQ + ks);
+      const bf16x8_t fb0 = *reinterpret_cast<const bf16x8_t*>(lb + ks);
+      const bf16x8_t fb1 = *reinterpret_cast<const bf16x8_t*>(lb + SQ + ks);
+      c00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa0, fb0, c00, 0, 0, 0);
+      c01 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa0, fb1, c01, 0, 0, 0);
+      c10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa1, fb0, c10, 0, 0, 0);
+      c11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa1, fb1, c11, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+
+  const int64_t r0 = m0 + wm * 64, c0 = n0 + wn * 64;
+  gemm_store32<EPI>(g, c00, r0, c0, lane);
+  gemm_store32<EPI>(g, c01, r0, c0 + 32, lane);
+  gemm_store32<EPI>(g, c10, r0 + 32, c0, lane);
+  gemm_store32<EPI>(g, c11, r0 + 32, c0 + 32, lane);
 }
 
 // Sigmoid-scaled Gram of the embeddings, K = sigmoid(ab[0] E E^T + ab[1])
@@ -611,6 +742,12 @@ __global__ void zero_int(int32_t* p) {
 
 template <int TA, int TB, int EPI>
 hipError_t launch_gemm_t(const GemmArgs& g, hipStream_t s) {
+  // both operands k-contiguous and whole 128 x 128 tiles: the larger tile
+  if (TA == 0 && TB == 1 && g.M % G2M == 0 && g.N % G2N == 0) {
+    const dim3 grid(unsigned(g.N / G2N), unsigned(g.M / G2M), unsigned(g.splits));
+    hipLaunchKernelGGL((bf16_gemm128<EPI>), grid, dim3(256), 0, s, g);
+    return hipGetLastError();
+  }
   const dim3 grid(unsigned(g.N / BN), unsigned(g.M / BM), unsigned(g.splits));
   hipLaunchKernelGGL((bf16_gemm<TA, TB, EPI>), grid, dim3(256), 0, s, g);
   return hipGetLastError();
@@ -628,6 +765,8 @@ hipError_t launch_gemm(int ta, int tb, int epi, const GemmArgs& g, hipStream_t s
     case 0 * 100 + 1 * 10 + EPI_BIAS: return launch_gemm_t<0, 1, EPI_BIAS>(g, s);
     case 0 * 100 + 1 * 10 + EPI_GELU_BWD: return launch_gemm_t<0, 1, EPI_GELU_BWD>(g, s);
     case 0 * 100 + 1 * 10 + EPI_F32: return launch_gemm_t<0, 1, EPI_F32>(g, s);
+    case 0 * 100 + 1 * 10 + EPI_BIAS_GELU_BF16: return launch_gemm_t<0, 1, EPI_BIAS_GELU_BF16>(g, s);
+    case 0 * 100 + 1 * 10 + EPI_BIAS_BF16: return launch_gemm_t<0, 1, EPI_BIAS_BF16>(g, s);
     default: return hipErrorInvalidValue;
   }
 }

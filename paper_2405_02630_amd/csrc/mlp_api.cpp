@@ -126,8 +126,13 @@ qsvm_status qsvm_mlp_forward(const qsvm_mlp* net, const void* X16, int64_t rows,
   qsvm_status s = check_net(net, what);
   if (s != QSVM_OK) return s;
   if ((s = check_rows(rows, what)) != QSVM_OK) return s;
-  if (!X16 || !acts || !acts->H1 || !acts->A1 || !acts->H2 || !acts->A2 || !acts->E || !acts->E16)
-    return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_mlp_forward: input or an activation buffer is NULL");
+  if (!X16 || !acts || !acts->A1 || !acts->A2 || !acts->E16)
+    return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_mlp_forward: input or a BF16 activation buffer is NULL");
+  // inference: without the FP32 outputs (H1, H2, E all NULL) only the BF16
+  // activations are written; the FP32 ones are needed by the backward pass
+  const bool keep = acts->H1 || acts->H2 || acts->E;
+  if (keep && (!acts->H1 || !acts->H2 || !acts->E))
+    return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_mlp_forward: H1, H2 and E must be all given or all NULL");
   if (qsvm::api_injected_failure()) return injected(what);
   hipStream_t st = static_cast<hipStream_t>(stream);
   // Each weight is first copied transposed (n x k, k contiguous: a
@@ -151,18 +156,20 @@ qsvm_status qsvm_mlp_forward(const qsvm_mlp* net, const void* X16, int64_t rows,
   tj.R[1] = net->d_h1, tj.C[1] = net->d_h2;
   tj.R[2] = net->d_h2, tj.C[2] = net->d_out;
   e = qsvm::launch_transpose_bf16(tj, 3, st);
+  const int epi_gelu = keep ? qsvm::EPI_BIAS_GELU : qsvm::EPI_BIAS_GELU_BF16;
+  const int epi_out = keep ? qsvm::EPI_BIAS : qsvm::EPI_BIAS_BF16;
   if (e == hipSuccess)
-    e = qsvm::launch_gemm(0, 1, qsvm::EPI_BIAS_GELU,
+    e = qsvm::launch_gemm(0, 1, epi_gelu,
                           gemm(rows, net->d_h1, net->d_in, X16, net->d_in, wt1, net->d_in, acts->H1, acts->A1,
                                net->d_h1, net->b1),
                           st);
   if (e == hipSuccess)
-    e = qsvm::launch_gemm(0, 1, qsvm::EPI_BIAS_GELU,
+    e = qsvm::launch_gemm(0, 1, epi_gelu,
                           gemm(rows, net->d_h2, net->d_h1, acts->A1, net->d_h1, wt2, net->d_h1, acts->H2, acts->A2,
                                net->d_h2, net->b2),
                           st);
   if (e == hipSuccess)
-    e = qsvm::launch_gemm(0, 1, qsvm::EPI_BIAS,
+    e = qsvm::launch_gemm(0, 1, epi_out,
                           gemm(rows, net->d_out, net->d_h2, acts->A2, net->d_h2, wt3, net->d_h2, acts->E, acts->E16,
                                net->d_out, net->b3),
                           st);

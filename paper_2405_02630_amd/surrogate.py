@@ -150,7 +150,10 @@ class Surrogate:
         self._bufs[rows] = b
         return b
 
-    def _acts(self, b, E16=None) -> qsvm.MlpActs:
+    def _acts(self, b, E16=None, inference=False) -> qsvm.MlpActs:
+        if inference:  # BF16 outputs only: no FP32 pre-activations for a backward pass
+            return qsvm.MlpActs(None, b["A1"].data_ptr(), None, b["A2"].data_ptr(), None,
+                                (b["E16"] if E16 is None else E16).data_ptr())
         return qsvm.MlpActs(b["H1"].data_ptr(), b["A1"].data_ptr(), b["H2"].data_ptr(), b["A2"].data_ptr(),
                             b["E"].data_ptr(), (b["E16"] if E16 is None else E16).data_ptr())
 
@@ -298,7 +301,7 @@ class Surrogate:
             b = self._buffers(rows)
             torch.arange(r0, r0 + rows, out=b["idx"])  # on the device; rows >= N are zero padding
             qsvm.qsvm_gather_features(X, b["idx"], self.d_in, X16[r0:r0 + rows])
-            qsvm.qsvm_mlp_forward(net, X16[r0:r0 + rows], rows, self._acts(b, E16[r0:r0 + rows]))
+            qsvm.qsvm_mlp_forward(net, X16[r0:r0 + rows], rows, self._acts(b, E16[r0:r0 + rows], inference=True))
         return X16, E16
 
     def gram(self, X, mps: "qsvm.MPS | None", K=None, tau: float | None = None, margin: float | None = None):

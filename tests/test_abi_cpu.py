@@ -531,3 +531,27 @@ def test_sv_injected_launch_failure(lib, monkeypatch):
     assert lib.qsvm_encode_sv(FAKE, 8, 4, 2, FAKE2, nb, None) == qsvm.QSVM_ERR_HIP
     assert lib.qsvm_sv_gram_sym(FAKE, 8, 4, FAKE2, 8, None, None) == qsvm.QSVM_ERR_HIP
     assert b"injected" in lib.qsvm_last_error()
+
+
+def _net():
+    return qsvm.Mlp(832, 512, 512, 256, 0x100000, 0x110000, 0x120000, 0x130000, 0x140000, 0x150000)
+
+
+def test_mlp_forward_validation(lib, no_inject):
+    net = _net()
+    full = qsvm.MlpActs(0x200000, 0x210000, 0x220000, 0x230000, 0x240000, 0x250000)
+    part = qsvm.MlpActs(0x200000, 0x210000, None, 0x230000, 0x240000, 0x250000)  # H2 missing
+    infer = qsvm.MlpActs(None, 0x210000, None, 0x230000, None, 0x250000)
+    nobf16 = qsvm.MlpActs(0x200000, None, 0x220000, 0x230000, 0x240000, 0x250000)
+    f = lib.qsvm_mlp_forward
+    assert f(None, FAKE, 64, ctypes.byref(full), None) == qsvm.QSVM_ERR_INVALID_ARG
+    assert f(ctypes.byref(net), FAKE, 100, ctypes.byref(full), None) == qsvm.QSVM_ERR_INVALID_ARG  # rows % 64
+    assert f(ctypes.byref(net), FAKE, 64, ctypes.byref(part), None) == qsvm.QSVM_ERR_INVALID_ARG
+    assert b"all given or all NULL" in lib.qsvm_last_error()
+    assert f(ctypes.byref(net), FAKE, 64, ctypes.byref(nobf16), None) == qsvm.QSVM_ERR_INVALID_ARG
+    os.environ["QSVM_FAULT_INJECT"] = "launch"
+    try:  # both forms pass validation
+        assert f(ctypes.byref(net), FAKE, 64, ctypes.byref(full), None) == qsvm.QSVM_ERR_HIP
+        assert f(ctypes.byref(net), FAKE, 64, ctypes.byref(infer), None) == qsvm.QSVM_ERR_HIP
+    finally:
+        del os.environ["QSVM_FAULT_INJECT"]

@@ -174,6 +174,22 @@ def test_mlp_forward_matches_reference():
 PROD = (832, 512, 512, 256)  # 784 pixels padded to 832 -> 512 -> 512 -> 256
 
 
+@pytest.mark.parametrize("rows,dims", [(16384, PROD), (128, DIMS)])
+def test_mlp_forward_inference_mode_writes_the_same_bf16_outputs(rows, dims):
+    """H1, H2 and E omitted (inference): the BF16 activations and embedding are
+    bitwise those of the forward pass that keeps the FP32 values."""
+    import torch
+
+    W, X, dev, net, bufs, acts = _setup(13, rows=rows, dims=dims)
+    qsvm.qsvm_mlp_forward(net, bufs["X16"], rows, acts)
+    A1i, A2i, E16i = (torch.empty_like(bufs[k]) for k in ("A1", "A2", "E16"))
+    qsvm.qsvm_mlp_forward(net, bufs["X16"], rows, qsvm.MlpActs(None, A1i.data_ptr(), None, A2i.data_ptr(), None,
+                                                               E16i.data_ptr()))
+    torch.cuda.synchronize()
+    for a, b in ((A1i, bufs["A1"]), (A2i, bufs["A2"]), (E16i, bufs["E16"])):
+        assert torch.equal(a.view(torch.int16), b.view(torch.int16))
+
+
 def test_mlp_forward_backward_production_shape_elementwise():
     """The surrogate's production widths on 16384 rows: 13 K steps in layer 1,
     the XCD tile order, and weight gradients split 8 ways along the rows
