@@ -4,9 +4,10 @@
 // distance of the embeddings [x, f(x)], ln K_hat = -c (1 - exp(-s d2)), or as
 // K_hat(x, y) = sigmoid(alpha <f(x), f(y)> + beta).
 //
-// * bf16_gemm128<EPI>: the same product for k-contiguous operands on
-//   128 x 128 tiles (2 x 2 accumulators per wave), used whenever M and N are
-//   multiples of 128 (the forward layers and the activation gradients).
+// * bf16_gemm_dl<MT, EPI>: the same product for k-contiguous operands on
+//   256 x 128 or 128 x 128 tiles, operands moved global -> LDS by the DMA
+//   loads (global_load_lds_dwordx4), double-buffered; used whenever M and N
+//   are multiples of 128 (the forward layers and the activation gradients).
 // * bf16_gemm<TA, TB, EPI>: C = op(A) op(B) on v_mfma_f32_32x32x16_bf16.
 //   A 64 x 64 output tile per block of 4 waves (each wave one 32 x 32
 //   accumulator), K in steps of 64 staged through LDS with both operands
@@ -33,7 +34,8 @@
 // * flag_tiles: compacts the tiles whose largest off-diagonal K_hat reaches
 //   the fallback threshold.
 //
-// GELU is the exact form x Phi(x) = x (1 + erf(x / sqrt 2)) / 2.
+// GELU is the exact form x Phi(x) = x (1 + erf(x / sqrt 2)) / 2, with Phi
+// evaluated to a relative error near 1e-7 (normal_cdf).
 
 #include <hip/hip_runtime.h>
 
@@ -62,12 +64,34 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {  // round to nearest 
   return uint16_t(u >> 16);
 }
 
-__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+// Standard normal CDF Phi(x) without branches, through the complementary
+// error function of Numerical Recipes (Press et al., "erfcc": a Chebyshev
+// fit with fractional error below 1.2e-7 for every z >= 0):
+// Phi(x) = 1 - erfc(z)/2 for x >= 0 and erfc(z)/2 for x < 0, z = |x|/sqrt 2.
+// Every lane takes the same instructions, so a GEMM epilogue over mixed-sign
+// pre-activations does not run both sides of a branch.
+__device__ __forceinline__ float normal_cdf(float x) {
+  const float z = fabsf(x) * 0.70710678118654752f;
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.5f, z, 1.0f));  // 1 ulp
+  float p = 0.17087277f;
+  p = fmaf(p, t, -0.82215223f);
+  p = fmaf(p, t, 1.48851587f);
+  p = fmaf(p, t, -1.13520398f);
+  p = fmaf(p, t, 0.27886807f);
+  p = fmaf(p, t, -0.18628806f);
+  p = fmaf(p, t, 0.09678418f);
+  p = fmaf(p, t, 0.37409196f);
+  p = fmaf(p, t, 1.00002368f);
+  p = fmaf(p, t, -1.26551223f);
+  const float h = 0.5f * t * __expf(fmaf(-z, z, p));  // erfc(z) / 2
+  return (x >= 0.0f) ? 1.0f - h : h;
+}
+
+__device__ __forceinline__ float gelu(float x) { return x * normal_cdf(x); }
 
 __device__ __forceinline__ float gelu_grad(float x) {
-  const float cdf = 0.5f * (1.0f + erff(x * 0.70710678118654752f));
   const float pdf = 0.39894228040143268f * __expf(-0.5f * x * x);
-  return cdf + x * pdf;
+  return normal_cdf(x) + x * pdf;
 }
 
 __device__ __forceinline__ float sigmoidf(float z) { return 1.0f / (1.0f + __expf(-z)); }
@@ -192,15 +216,25 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))
 }
 
 // C = A B^T-style GEMM with both operands k-contiguous (A[m*lda + k],
-// op(B)[k][n] = B[n*ldb + k]) on 128 x 128 output tiles: 4 waves in a 2 x 2
-// grid, each wave 64 x 64 = 2 x 2 accumulators of v_mfma_f32_32x32x16_bf16,
-// so one 64-deep K step is 16 MFMAs per wave against 4 LDS fragment loads per
-// 16-deep slice (twice the arithmetic per staged byte of bf16_gemm's 64 x 64
-// tiles, and four independent accumulation chains per wave).  The next step's
-// operands (4 x 16 B per thread and operand) are loaded into registers while
-// the current step's MFMAs run.  M and N must be multiples of 128; the
+// op(B)[k][n] = B[n*ldb + k]) on (64 MT) x 128 output tiles: 4 waves in a
+// 2 x 2 grid, each wave (32 MT) x 64 = MT x 2 accumulators of
+// v_mfma_f32_32x32x16_bf16 (MT = 4 halves the LDS bytes per MFMA of MT = 2
+// and is used when the larger tiles still fill the device).  The operands
+// reach LDS without passing through registers: each wave issues
+// global_load_lds_dwordx4 for 1 KB chunks of the next 32-deep K step while
+// the current step's MFMAs run (two LDS buffers, one barrier per step).  A
+// DMA chunk is 64 consecutive 16-byte LDS slots; slot s of a tile holds row
+// s / 4, 16-byte piece (s % 4) ^ sw(row) of that row's 32 k-values, the XOR
+// swizzle sw(row) = ((row >> 1) ^ (row >> 3)) & 1 | (row >> 1) & 2 keeping
+// every 16-lane group of a fragment read on distinct LDS banks.  Waits are
+// explicit (vmcnt for this wave's DMA, then a plain barrier): a fenced
+// barrier would also wait for the step being prefetched.  M must be a
+// multiple of 64 MT, N of 128, K / splits of 32, lda and ldb of 8; the
 // epilogues are those of bf16_gemm.
-constexpr int G2M = 128, G2N = 128;
+constexpr int DL_BK = 32;      // K step
+constexpr int DL_PR = DL_BK / 8;  // 16-byte pieces per tile row and step
+
+__device__ __forceinline__ int dl_swizzle(int row) { return (((row >> 1) ^ (row >> 3)) & 1) | ((row >> 1) & 2); }
 
 // Epilogue of one 32 x 32 accumulator whose top-left output is (r0, c0):
 // element v is row r0 + (v/4)*8 + (lane/32)*4 + v%4, column c0 + lane%32.
@@ -232,85 +266,111 @@ __device__ __forceinline__ void gemm_store32(const GemmArgs& g, const f32x16_t& 
   }
 }
 
-template <int EPI>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) bf16_gemm128(GemmArgs g) {
-  __shared__ __attribute__((aligned(16))) uint16_t As[G2M * GEMM_LDS_STRIDE];  // [m][k]
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[G2N * GEMM_LDS_STRIDE];  // [n][k]
-  const int t = threadIdx.x;
-  const int lane = t & 63;
-  const int wave = t >> 6;
+template <int MT, int EPI>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) bf16_gemm_dl(GemmArgs g) {
+  constexpr int NT = 2;
+  constexpr int TM = 64 * MT, TN = 64 * NT;  // output tile
+  constexpr int SA = TM * DL_PR, SB = TN * DL_PR;  // 16-byte LDS slots per buffer and operand
+  constexpr int CA = SA / 256, CB = SB / 256;      // 64-slot DMA chunks per wave and step
+  extern __shared__ uint4 lds[];                   // 2 buffers x (SA + SB) slots, sized at launch
+  const int t = threadIdx.x, lane = t & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
   const int wm = wave >> 1, wn = wave & 1;
   const uint32_t nx = gridDim.x, tiles = gridDim.x * gridDim.y;
   uint32_t u = blockIdx.y * nx + blockIdx.x;
   if ((tiles & 7u) == 0) u = (u & 7u) * (tiles >> 3) + (u >> 3);  // XCD-aware order, as in bf16_gemm
-  const int64_t m0 = int64_t(u / nx) * G2M;
-  const int64_t n0 = int64_t(u % nx) * G2N;
-  const uint16_t* __restrict__ A = static_cast<const uint16_t*>(g.A);
-  const uint16_t* __restrict__ B = static_cast<const uint16_t*>(g.B);
-
-  f32x16_t c00, c01, c10, c11;
-#pragma unroll
-  for (int v = 0; v < 16; ++v) c00[v] = c01[v] = c10[v] = c11[v] = 0.0f;
-
-  // piece p (0..1023) of a 128 x 64 step tile: row p / 8, k (p % 8) * 8;
-  // thread t moves pieces t, t + 256, t + 512, t + 768 of each operand
+  const int64_t m0 = int64_t(u / nx) * TM;
+  const int64_t n0 = int64_t(u % nx) * TN;
   const int64_t kspan = g.K / g.splits;
   const int64_t kbeg = int64_t(blockIdx.z) * kspan;
-  const int64_t kend = kbeg + kspan;
-  const int pr = t >> 3, pk = (t & 7) * 8;  // row (within a 32-row quarter) and k of piece t
-  const uint16_t* pa = A + (m0 + pr) * g.lda + pk;
-  const uint16_t* pb = B + (n0 + pr) * g.ldb + pk;
-  const int64_t qa = 32 * g.lda, qb = 32 * g.ldb;  // the next quarter's pieces are 32 rows down
-  uint4 a0 = *reinterpret_cast<const uint4*>(pa + kbeg), a1 = *reinterpret_cast<const uint4*>(pa + qa + kbeg);
-  uint4 a2 = *reinterpret_cast<const uint4*>(pa + 2 * qa + kbeg), a3 = *reinterpret_cast<const uint4*>(pa + 3 * qa + kbeg);
-  uint4 b0 = *reinterpret_cast<const uint4*>(pb + kbeg), b1 = *reinterpret_cast<const uint4*>(pb + qb + kbeg);
-  uint4 b2 = *reinterpret_cast<const uint4*>(pb + 2 * qb + kbeg), b3 = *reinterpret_cast<const uint4*>(pb + 3 * qb + kbeg);
-  uint16_t* sa = &As[pr * GEMM_LDS_STRIDE + pk];
-  uint16_t* sb = &Bs[pr * GEMM_LDS_STRIDE + pk];
-  constexpr int SQ = 32 * GEMM_LDS_STRIDE;  // 32 LDS rows
-  for (int64_t k0 = kbeg; k0 < kend; k0 += GBK) {
-    *reinterpret_cast<uint4*>(sa) = a0;
-    *reinterpret_cast<uint4*>(sa + SQ) = a1;
-    *reinterpret_cast<uint4*>(sa + 2 * SQ) = a2;
-    *reinterpret_cast<uint4*>(sa + 3 * SQ) = a3;
-    *reinterpret_cast<uint4*>(sb) = b0;
-    *reinterpret_cast<uint4*>(sb + SQ) = b1;
-    *reinterpret_cast<uint4*>(sb + 2 * SQ) = b2;
-    *reinterpret_cast<uint4*>(sb + 3 * SQ) = b3;
-    __syncthreads();
-    if (k0 + GBK < kend) {  // the next step's operands, in flight during this step's MFMAs
-      const int64_t kn = k0 + GBK;
-      a0 = *reinterpret_cast<const uint4*>(pa + kn);
-      a1 = *reinterpret_cast<const uint4*>(pa + qa + kn);
-      a2 = *reinterpret_cast<const uint4*>(pa + 2 * qa + kn);
-      a3 = *reinterpret_cast<const uint4*>(pa + 3 * qa + kn);
-      b0 = *reinterpret_cast<const uint4*>(pb + kn);
-      b1 = *reinterpret_cast<const uint4*>(pb + qb + kn);
-      b2 = *reinterpret_cast<const uint4*>(pb + 2 * qb + kn);
-      b3 = *reinterpret_cast<const uint4*>(pb + 3 * qb + kn);
-    }
-    const int i = lane & 31, kh = lane >> 5;
-    const uint16_t* la = &As[(wm * 64 + i) * GEMM_LDS_STRIDE + kh * 8];
-    const uint16_t* lb = &Bs[(wn * 64 + i) * GEMM_LDS_STRIDE + kh * 8];
-#pragma unroll
-    for (int ks = 0; ks < GBK; ks += 16) {
-      const bf16x8_t fa0 = *reinterpret_cast<const bf16x8_t*>(la + ks);
-      const bf16x8_t fa1 = *reinterpret_cast<const bf16x8_t*>(la + SQ + ks);
-      const bf16x8_t fb0 = *reinterpret_cast<const bf16x8_t*>(lb + ks);
-      const bf16x8_t fb1 = *reinterpret_cast<const bf16x8_t*>(lb + SQ + ks);
-      c00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa0, fb0, c00, 0, 0, 0);
-      c01 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa0, fb1, c01, 0, 0, 0);
-      c10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa1, fb0, c10, 0, 0, 0);
-      c11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa1, fb1, c11, 0, 0, 0);
-    }
-    __syncthreads();
-  }
+  const int nsteps = int(kspan / DL_BK);
 
-  const int64_t r0 = m0 + wm * 64, c0 = n0 + wn * 64;
-  gemm_store32<EPI>(g, c00, r0, c0, lane);
-  gemm_store32<EPI>(g, c01, r0, c0 + 32, lane);
-  gemm_store32<EPI>(g, c10, r0 + 32, c0, lane);
-  gemm_store32<EPI>(g, c11, r0 + 32, c0 + 32, lane);
+  // source of the 16 bytes this lane moves in each of its chunks
+  const uint16_t* ga[CA];
+  const uint16_t* gb[CB];
+#pragma unroll
+  for (int c = 0; c < CA; ++c) {
+    const int s = (wave + 4 * c) * 64 + lane, row = s / DL_PR;
+    ga[c] = static_cast<const uint16_t*>(g.A) + (m0 + row) * g.lda + kbeg + ((s % DL_PR) ^ dl_swizzle(row)) * 8;
+  }
+#pragma unroll
+  for (int c = 0; c < CB; ++c) {
+    const int s = (wave + 4 * c) * 64 + lane, row = s / DL_PR;
+    gb[c] = static_cast<const uint16_t*>(g.B) + (n0 + row) * g.ldb + kbeg + ((s % DL_PR) ^ dl_swizzle(row)) * 8;
+  }
+  // The builtin's operands are taken through plain pointers and the shared
+  // array itself (operands of template-dependent type drop the kernel's host
+  // stub).
+#define QSVM_DL_ISSUE(buf, koff)                                                                      \
+  do {                                                                                               \
+    _Pragma("unroll") for (int c = 0; c < CA; ++c) {                                                 \
+      const uint16_t* src_ = ga[c];                                                                  \
+      __builtin_amdgcn_global_load_lds(src_ + (koff), lds + (buf) * (SA + SB) + (wave + 4 * c) * 64, 16, 0, 0); \
+    }                                                                                                \
+    _Pragma("unroll") for (int c = 0; c < CB; ++c) {                                                 \
+      const uint16_t* src_ = gb[c];                                                                  \
+      __builtin_amdgcn_global_load_lds(src_ + (koff), lds + (buf) * (SA + SB) + SA + (wave + 4 * c) * 64, 16, 0, 0); \
+    }                                                                                                \
+  } while (0)
+
+  // LDS slots of this lane's fragments: row i = lane % 32 of each 32-row
+  // block, 8 k-values at piece 2 * slice + lane / 32
+  const int i = lane & 31, kh = lane >> 5;
+  int oa[MT][2], ob[NT][2];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+      const int row = wm * MT * 32 + mt * 32 + i;
+      oa[mt][sl] = row * DL_PR + ((sl * 2 + kh) ^ dl_swizzle(row));
+    }
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+      const int row = wn * NT * 32 + nt * 32 + i;
+      ob[nt][sl] = SA + row * DL_PR + ((sl * 2 + kh) ^ dl_swizzle(row));
+    }
+
+  f32x16_t acc[MT][NT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[mt][nt][v] = 0.0f;
+
+  QSVM_DL_ISSUE(0, 0);
+  for (int kk = 0; kk < nsteps; ++kk) {
+    // this wave's DMA of step kk has landed (vmcnt(0)) and its LDS reads of
+    // step kk - 1 are done (lgkmcnt(0)); the barrier makes both block-wide
+    __builtin_amdgcn_s_waitcnt(0x0070);
+    __builtin_amdgcn_s_barrier();
+    if (kk + 1 < nsteps) QSVM_DL_ISSUE((kk + 1) & 1, int64_t(kk + 1) * DL_BK);
+    const uint4* base = lds + (kk & 1) * (SA + SB);
+    bf16x8_t fa[2][MT], fb[2][NT];
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) fa[sl][mt] = *reinterpret_cast<const bf16x8_t*>(base + oa[mt][sl]);
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) fb[sl][nt] = *reinterpret_cast<const bf16x8_t*>(base + ob[nt][sl]);
+    }
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+          acc[mt][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[sl][mt], fb[sl][nt], acc[mt][nt], 0, 0, 0);
+  }
+#undef QSVM_DL_ISSUE
+
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+      gemm_store32<EPI>(g, acc[mt][nt], m0 + wm * MT * 32 + mt * 32, n0 + wn * NT * 32 + nt * 32, lane);
 }
 
 // Sigmoid-scaled Gram of the embeddings, K = sigmoid(ab[0] E E^T + ab[1])
@@ -537,28 +597,33 @@ __global__ void __launch_bounds__(256) transpose_bf16(TransposeJobs j) {
     if (c0 + i < C && r0 + tx < R) out[(c0 + i) * R + r0 + tx] = tile[tx][i];
 }
 
-// Indices outside [0, N) (padding rows) give zero rows.  One block per
-// output row at a time (grid-stride over rows): the row's
-// source index is read once, and with d_pad a multiple of 4 each thread
-// converts 4 consecutive features and writes them as one 8-byte store.
+// Indices outside [0, N) (padding rows) give zero rows.  Consecutive threads
+// take consecutive feature pairs of a row (vec = 1: n and d_pad even, X
+// 16-byte and out 4-byte aligned; one 16-byte load and one 4-byte store per
+// thread, so a wave reads 1 KB of FP64 and writes 256 B of BF16, both
+// contiguous) or consecutive single features (vec = 0).
 __global__ void __launch_bounds__(256) gather_features(const double* __restrict__ X, int64_t N, int32_t n,
                                                        const int32_t* __restrict__ idx, int64_t rows, int32_t d_pad,
-                                                       uint16_t* __restrict__ out) {
-  for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
+                                                       uint16_t* __restrict__ out, int32_t vec) {
+  const int32_t per_row = vec ? d_pad / 2 : d_pad;  // work items per row
+  const int64_t total = rows * per_row;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < total; q += stride) {
+    const int64_t r = (total <= int64_t(0xffffffffu)) ? int64_t(uint32_t(q) / uint32_t(per_row)) : q / per_row;
+    const int32_t w = int32_t(q - r * per_row);
     const int32_t p = idx[r];
     const int32_t m = (p >= 0 && p < N) ? n : 0;  // features copied (0: padding row)
     const double* __restrict__ xr = X + int64_t(m ? p : 0) * n;
-    uint16_t* __restrict__ o = out + r * d_pad;
-    if ((d_pad & 3) == 0) {
-      for (int32_t c = 4 * int32_t(threadIdx.x); c < d_pad; c += 4 * 256) {
-        uint32_t h[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) h[q] = (c + q < m) ? f32_to_bf16(float(xr[c + q])) : 0u;
-        *reinterpret_cast<uint2*>(o + c) = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+    if (vec) {
+      const int32_t c = 2 * w;  // c < m implies c + 1 < m (m even)
+      uint32_t h = 0u;
+      if (c < m) {
+        const double2 v = *reinterpret_cast<const double2*>(xr + c);
+        h = uint32_t(f32_to_bf16(float(v.x))) | (uint32_t(f32_to_bf16(float(v.y))) << 16);
       }
+      *reinterpret_cast<uint32_t*>(out + r * d_pad + c) = h;
     } else {
-      for (int32_t c = int32_t(threadIdx.x); c < d_pad; c += 256)
-        o[c] = (c < m) ? f32_to_bf16(float(xr[c])) : uint16_t(0);
+      out[r * d_pad + w] = (w < m) ? f32_to_bf16(float(xr[w])) : uint16_t(0);
     }
   }
 }
@@ -742,10 +807,20 @@ __global__ void zero_int(int32_t* p) {
 
 template <int TA, int TB, int EPI>
 hipError_t launch_gemm_t(const GemmArgs& g, hipStream_t s) {
-  // both operands k-contiguous and whole 128 x 128 tiles: the larger tile
-  if (TA == 0 && TB == 1 && g.M % G2M == 0 && g.N % G2N == 0) {
-    const dim3 grid(unsigned(g.N / G2N), unsigned(g.M / G2M), unsigned(g.splits));
-    hipLaunchKernelGGL((bf16_gemm128<EPI>), grid, dim3(256), 0, s, g);
+  // both operands k-contiguous, whole 128 x 128 tiles, 16-byte rows and
+  // 32-deep steps: the direct-to-LDS kernel, on 256 x 128 tiles when there
+  // are at least 512 of them (two per compute unit), else 128 x 128
+  if (TA == 0 && TB == 1 && g.M % 128 == 0 && g.N % 128 == 0 && g.lda % 8 == 0 && g.ldb % 8 == 0 &&
+      g.K % g.splits == 0 && (g.K / g.splits) % DL_BK == 0) {
+    if (g.M % 256 == 0 && (g.M / 256) * (g.N / 128) >= 512) {
+      const dim3 grid(unsigned(g.N / 128), unsigned(g.M / 256), unsigned(g.splits));
+      const size_t lds = 2 * (256 + 128) * DL_PR * 16;
+      hipLaunchKernelGGL((bf16_gemm_dl<4, EPI>), grid, dim3(256), lds, s, g);
+    } else {
+      const dim3 grid(unsigned(g.N / 128), unsigned(g.M / 128), unsigned(g.splits));
+      const size_t lds = 2 * (128 + 128) * DL_PR * 16;
+      hipLaunchKernelGGL((bf16_gemm_dl<2, EPI>), grid, dim3(256), lds, s, g);
+    }
     return hipGetLastError();
   }
   const dim3 grid(unsigned(g.N / BN), unsigned(g.M / BM), unsigned(g.splits));
@@ -794,8 +869,11 @@ hipError_t launch_transpose_bf16(TransposeJobs j, int32_t count, hipStream_t s) 
 
 hipError_t launch_gather(const double* X, int64_t N, int32_t n, const int32_t* idx, int64_t rows, int32_t d_pad,
                          uint16_t* out, hipStream_t s) {
-  const int64_t blocks = rows < 65536 ? rows : 65536;
-  hipLaunchKernelGGL(gather_features, dim3(unsigned(blocks)), dim3(256), 0, s, X, N, n, idx, rows, d_pad, out);
+  const int32_t vec = (n % 2 == 0 && d_pad % 2 == 0 && (reinterpret_cast<uintptr_t>(X) & 15) == 0 &&
+                       (reinterpret_cast<uintptr_t>(out) & 3) == 0) ? 1 : 0;
+  const int64_t work = (rows * (vec ? d_pad / 2 : d_pad) + 255) / 256;
+  const int64_t blocks = work < 1 ? 1 : (work < 65536 ? work : 65536);  // grid-stride beyond
+  hipLaunchKernelGGL(gather_features, dim3(unsigned(blocks)), dim3(256), 0, s, X, N, n, idx, rows, d_pad, out, vec);
   return hipGetLastError();
 }
 
