@@ -50,7 +50,7 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3  # MI355X FP32 vector: 256 CU x 2.4 GHz x 256 fl
 # only for the kernel and configuration they were taken on (sweep, reps,
 # points, qubits) -- any other configuration reports null.
 MEASURED_TRAFFIC = {
-    ("butterfly", 2, 4096, 784): (2.4558e9, "profiles/sweep_butterfly_images784_r2_hbm_counters.md"),
+    ("butterfly", 2, 4096, 784): (3.4178e9, "profiles/sweep_butterfly_images784_r2_hbm_counters.md"),
 }
 
 

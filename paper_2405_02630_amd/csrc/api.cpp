@@ -45,7 +45,7 @@ qsvm_status check_shape(int64_t N, int32_t n, int32_t reps, const char* what) {
   if (n < 1 || n > kMaxQubits) return fail(QSVM_ERR_INVALID_ARG, "%s: n_qubits = %d outside [1, 65535]", what, n);
   if (reps < 1) return fail(QSVM_ERR_INVALID_ARG, "%s: reps = %d must be >= 1", what, reps);
   if (reps > qsvm::kMaxReps)
-    return fail(QSVM_ERR_UNSUPPORTED, "%s: reps = %d > 4 (bond dimension above 16) is not supported", what, reps);
+    return fail(QSVM_ERR_UNSUPPORTED, "%s: reps = %d > 6 (bond dimension above 64) is not supported", what, reps);
   return QSVM_OK;
 }
 
@@ -115,11 +115,11 @@ qsvm_status read_opts(const qsvm_gram_opts* o, int64_t rows, Opts& out, const ch
 // Blocks of the refinement kernel resident on the current device, cached per
 // device and reps.
 hipError_t resident_refine_blocks(int32_t reps, int64_t* out) {
-  static std::atomic<int64_t> cache[64][5];  // zero-initialised (static storage)
+  static std::atomic<int64_t> cache[64][qsvm::kMaxReps + 1];  // zero-initialised (static storage)
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
-  const bool cacheable = dev >= 0 && dev < 64 && reps >= 1 && reps <= 4;
+  const bool cacheable = dev >= 0 && dev < 64 && reps >= 1 && reps <= qsvm::kMaxReps;
   if (cacheable) {
     const int64_t c = cache[dev][reps].load(std::memory_order_relaxed);
     if (c > 0) {
@@ -195,10 +195,11 @@ qsvm_status run_gram(const void* mps_a, int64_t Na, const void* mps_b, int64_t N
   using qsvm::kTile;
   if (o.sweep == QSVM_SWEEP_DENSE && reps > 3)
     return fail(QSVM_ERR_UNSUPPORTED, "%s: the dense sweep supports reps <= 3", what);
-  // the sweeps launch whole rows of tiles (at most 16 blocks per tile, 32 in
-  // the reps = 4 sweep), so one row must fit one launch
+  // the sweeps launch whole rows of tiles (at most 16 blocks per tile, 32,
+  // 128 and 512 in the split sweep of reps 4, 5 and 6), so one row must fit
+  // one launch
   const int64_t tiles_b = (Nb + kTile - 1) / kTile;
-  if (tiles_b * (reps == 4 ? 32 : 16) > qsvm::kMaxGridBlocks)
+  if (tiles_b * (reps >= 4 ? qsvm::split_blocks_per_tile(reps) : 16) > qsvm::kMaxGridBlocks)
     return fail(QSVM_ERR_UNSUPPORTED, "%s: Nb = %lld: one row of %lld tiles exceeds one launch", what, (long long)Nb,
                 (long long)tiles_b);
   if (o.row_end <= o.row_begin) return ok();  // empty row range: nothing to do
@@ -356,7 +357,7 @@ qsvm_status qsvm_encode_mps(const double* X, int64_t N, int32_t n_qubits, int32_
 }
 
 size_t qsvm_dense_bytes(int64_t N, int32_t n_qubits, int32_t reps) {
-  if (N < 1 || N > kMaxN || n_qubits < 1 || n_qubits > kMaxQubits || reps < 1 || reps > qsvm::kMaxReps) return 0;
+  if (N < 1 || N > kMaxN || n_qubits < 1 || n_qubits > kMaxQubits || reps < 1 || reps > qsvm::kMaxDenseReps) return 0;
   return size_t(qsvm::dense_bytes(N, n_qubits, reps));
 }
 
@@ -365,6 +366,8 @@ qsvm_status qsvm_encode_dense(const double* X, int64_t N, int32_t n_qubits, int3
   const char* what = "qsvm_encode_dense";
   qsvm_status s = check_shape(N, n_qubits, reps, what);
   if (s != QSVM_OK) return s;
+  if (reps > qsvm::kMaxDenseReps)
+    return fail(QSVM_ERR_UNSUPPORTED, "%s: dense tensors are written for reps <= %d", what, qsvm::kMaxDenseReps);
   if (!X) return fail(QSVM_ERR_INVALID_ARG, "%s: X is NULL", what);
   if (!dense) return fail(QSVM_ERR_INVALID_ARG, "%s: dense is NULL", what);
   if (reinterpret_cast<uintptr_t>(dense) % 16 != 0) return fail(QSVM_ERR_INVALID_ARG, "%s: dense is not 16-byte aligned", what);

@@ -34,14 +34,16 @@ constexpr int kButterflyVariants = 4;  // per reps, see launch_sweep_butterfly_a
 // over 8 sites.
 constexpr int32_t kDefaultRenorm = 8;
 constexpr int32_t kMaxRenorm = 16;
-constexpr int32_t kMaxReps = 4;        // chi = 16
+constexpr int32_t kMaxReps = 6;        // chi = 64
+constexpr int32_t kMaxDenseReps = 4;   // dense site tensors (chi <= 16) are written up to here
 hipError_t launch_sweep_butterfly_args(const SweepArgs& a, int32_t reps, int32_t variant, hipStream_t stream);
 int32_t butterfly_variant_pi(int32_t reps, int32_t variant);  // ket points per lane; 0 if invalid
 // Butterfly sweep (reps 1..3) over a tile list whose length a.tile_count
 // holds in device memory: one persistent launch, no host read of the count.
 hipError_t launch_sweep_butterfly_counted(const SweepArgs& a, int32_t reps, int32_t variant, hipStream_t stream);
-// reps = 4: the environment split across two lanes (sweep_split.hip).
+// reps = 4..6: the environment split across 2, 8 or 32 lanes (sweep_split.hip).
 hipError_t launch_sweep_split_args(const SweepArgs& a, int32_t reps, int32_t variant, hipStream_t stream);
+int32_t split_blocks_per_tile(int32_t reps);  // blocks per 64 x 64 tile of the split sweep
 // The fast (Section G) sweep for any supported reps.
 inline hipError_t launch_sweep_fast(const SweepArgs& a, int32_t reps, int32_t variant, hipStream_t stream) {
   return reps <= 3 ? launch_sweep_butterfly_args(a, reps, variant, stream)

@@ -19,7 +19,7 @@
 // The FP64 sweep is the one-lane butterfly sweep of sweep_butterfly_item.h
 // (same recursion, gauge, sign pattern, renormalisation and closure) with
 // doubles: one pair per lane and one ket point per wave for reps <= 3; at
-// reps = 4 (128 environment entries) one pair per wave.
+// reps >= 4 (128 to 2048 environment entries) one pair per wave.
 
 #include "../../include/qsvm.h"
 #include "refine.h"
@@ -264,38 +264,83 @@ refine_kernel(SweepArgs a, const uint32_t* __restrict__ list, const uint32_t* __
   }
 }
 
-// reps = 4: one pair per wave.  The 2^7 environment entries q sit two per
-// lane: lane = bits 0..5 of q (ket bits 0-2, bra bits 3-5), register e = bit
-// 6 (the shared physical bit).  The shared-bit axis runs in registers; a ket
-// or bra axis on bit B pairs lane l with lane l ^ 2^B: the lane without the
-// bit computes u0 + a u1, the lane with it +-(u0 + b u1), each from its own
-// value and its partner's (__shfl_xor).  Sign rule, renormalisation and
-// closure as in the one-lane sweep, with wave-wide reductions.
-template <int B, int SIGNBIT>
-__device__ __forceinline__ void wave_axis(double2 (&v)[2], int lane, double ar, double ai, double br, double bi) {
-  const bool upper = (lane >> B) & 1;
-  double2 t[2];
+// reps >= 4: one pair per wave.  The 2^(2r-1) environment entries q sit
+// E = 2^(2r-7) per lane: lane = bits 0..5 of q, register e = the bits above
+// (ket bits 0..r-2, bra bits r-1..2r-3, shared bit 2r-2, as in the one-lane
+// sweep).  An axis on a register bit runs as register butterflies; an axis
+// on bit B < 6 pairs lane l with lane l ^ 2^B: the lane without the bit
+// computes u0 + a u1, the lane with it +-(u0 + b u1), each from its own value
+// and its partner's (__shfl_xor).  Sign rule, renormalisation and closure as
+// in the one-lane sweep, with wave-wide reductions.
+template <int R>
+struct WLayout {
+  static constexpr int E = 1 << (2 * R - 7);  // entries per lane
+  static constexpr int ket_bit(int l) { return l - 1; }
+  static constexpr int bra_bit(int l) { return R + l - 2; }
+  static constexpr int S = 2 * R - 2;
+};
+
+template <int R, int B, int SB1, int SB2>
+__device__ __forceinline__ void wave_axis(double2 (&v)[WLayout<R>::E], int lane, double ar, double ai, double br,
+                                          double bi) {
+  constexpr int E = WLayout<R>::E;
+  if constexpr (B >= 6) {  // register bit
 #pragma unroll
-  for (int e = 0; e < 2; ++e) {
-    const double pr = __shfl_xor(v[e].x, 1 << B, 64), pim = __shfl_xor(v[e].y, 1 << B, 64);
-    const double2 u0 = upper ? make_double2(pr, pim) : v[e];
-    const double2 u1 = upper ? v[e] : make_double2(pr, pim);
+    for (int e0 = 0; e0 < E; ++e0) {
+      if (e0 & (1 << (B - 6))) continue;
+      const int e1 = e0 | (1 << (B - 6));
+      const int i0 = lane | (e0 << 6);
+      bool neg = false;
+      if constexpr (SB1 >= 0) neg ^= ((i0 >> SB1) & 1) != 0;
+      if constexpr (SB2 >= 0) neg ^= ((i0 >> SB2) & 1) != 0;
+      dbfly<false>(v[e0], v[e1], ar, ai, br, bi);
+      if (neg) v[e1] = make_double2(-v[e1].x, -v[e1].y);
+    }
+  } else {  // lane bit
+    const bool upper = (lane >> B) & 1;
     const double cr = upper ? br : ar, ci = upper ? bi : ai;
-    double tr = fma(cr, u1.x, u0.x);
-    tr = fma(-ci, u1.y, tr);
-    double ti = fma(cr, u1.y, u0.y);
-    ti = fma(ci, u1.x, ti);
-    const int i0 = (lane | (e << 6)) & ~(1 << B);
-    const bool neg = upper && SIGNBIT >= 0 && ((i0 >> (SIGNBIT < 0 ? 0 : SIGNBIT)) & 1);
-    t[e] = neg ? make_double2(-tr, -ti) : make_double2(tr, ti);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const double pr = __shfl_xor(v[e].x, 1 << B, 64), pim = __shfl_xor(v[e].y, 1 << B, 64);
+      const double2 u0 = upper ? make_double2(pr, pim) : v[e];
+      const double2 u1 = upper ? v[e] : make_double2(pr, pim);
+      double tr = fma(cr, u1.x, u0.x);
+      tr = fma(-ci, u1.y, tr);
+      double ti = fma(cr, u1.y, u0.y);
+      ti = fma(ci, u1.x, ti);
+      const int i0 = (lane | (e << 6)) & ~(1 << B);
+      bool neg = false;
+      if constexpr (SB1 >= 0) neg ^= ((i0 >> SB1) & 1) != 0;
+      if constexpr (SB2 >= 0) neg ^= ((i0 >> SB2) & 1) != 0;
+      v[e] = (upper && neg) ? make_double2(-tr, -ti) : make_double2(tr, ti);
+    }
   }
-  v[0] = t[0];
-  v[1] = t[1];
 }
 
+template <int R, int L>
+struct WAxes {
+  __device__ __forceinline__ static void ket(double2 (&v)[WLayout<R>::E], int lane, const Gen64& c) {
+    if constexpr (L <= R - 1) {
+      wave_axis<R, WLayout<R>::ket_bit(L), (L >= 2 ? WLayout<R>::ket_bit(L - 1) : -1), -1>(v, lane, c.ar, c.ai, c.br,
+                                                                                             c.bi);
+      WAxes<R, L + 1>::ket(v, lane, c);
+    }
+  }
+  __device__ __forceinline__ static void bra(double2 (&v)[WLayout<R>::E], int lane, const Gen64& c) {
+    if constexpr (L <= R - 1) {
+      wave_axis<R, WLayout<R>::bra_bit(L), (L >= 2 ? WLayout<R>::bra_bit(L - 1) : -1), -1>(v, lane, c.ar, -c.ai,
+                                                                                             c.br, -c.bi);
+      WAxes<R, L + 1>::bra(v, lane, c);
+    }
+  }
+};
+
+template <int R>
 __global__ void __launch_bounds__(256)
 refine_wave_kernel(SweepArgs a, const uint32_t* __restrict__ list, const uint32_t* __restrict__ count) {
-  constexpr int R = 4;
+  using W = WLayout<R>;
+  constexpr int E = W::E;
+  constexpr int LOWMASK = (1 << (R - 1)) - 1;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const float4* __restrict__ gA = a.gen_a;
@@ -309,11 +354,12 @@ refine_wave_kernel(SweepArgs a, const uint32_t* __restrict__ list, const uint32_
     const int pr = int(it % (kTile * kTile));
     const int64_t i = int64_t(ti) * kTile + pr / kTile, j = int64_t(tj) * kTile + pr % kTile;
     if (!pair_computed(a, i, j)) continue;  // the same pair in every lane
-    double2 v[2];
+    double2 v[E];
 #pragma unroll
-    for (int e = 0; e < 2; ++e) {
+    for (int e = 0; e < E; ++e) {
       const int q = lane | (e << 6);
-      const int par = dcol_sign_parity<R>(q & 7, e) ^ dcol_sign_parity<R>((q >> 3) & 7, e);
+      const int s = (q >> W::S) & 1;
+      const int par = dcol_sign_parity<R>(q & LOWMASK, s) ^ dcol_sign_parity<R>((q >> (R - 1)) & LOWMASK, s);
       v[e] = make_double2(par ? -1.0 : 1.0, 0.0);
     }
     int32_t acc = 0;
@@ -321,29 +367,24 @@ refine_wave_kernel(SweepArgs a, const uint32_t* __restrict__ list, const uint32_
     for (int k = 1; k < a.n; ++k) {
       const Gen64 cx = gen64(gA, lA, int64_t(k) * a.Na + i);
       const Gen64 cy = gen64(gB, lB, int64_t(k) * a.Nb + j);
-      // ket axes (bits 0, 1, 2; sign bit = the previous one), bra axes (bits 3, 4, 5)
-      wave_axis<0, -1>(v, lane, cx.ar, cx.ai, cx.br, cx.bi);
-      wave_axis<1, 0>(v, lane, cx.ar, cx.ai, cx.br, cx.bi);
-      wave_axis<2, 1>(v, lane, cx.ar, cx.ai, cx.br, cx.bi);
-      wave_axis<3, -1>(v, lane, cy.ar, -cy.ai, cy.br, -cy.bi);
-      wave_axis<4, 3>(v, lane, cy.ar, -cy.ai, cy.br, -cy.bi);
-      wave_axis<5, 4>(v, lane, cy.ar, -cy.ai, cy.br, -cy.bi);
-      // shared bit (register e): a_x conj(a_y), b_x conj(b_y); sign bits 2 and 5
+      WAxes<R, 1>::ket(v, lane, cx);
+      WAxes<R, 1>::bra(v, lane, cy);
+      // shared bit: a_x conj(a_y), b_x conj(b_y); sign bits ket and bra l = R-1
       const double asr = fma(cx.ar, cy.ar, cx.ai * cy.ai);
       const double asi = fma(cx.ai, cy.ar, -(cx.ar * cy.ai));
       const double bsr = fma(cx.br, cy.br, cx.bi * cy.bi);
       const double bsi = fma(cx.bi, cy.br, -(cx.br * cy.bi));
-      const bool neg = ((lane >> 2) ^ (lane >> 5)) & 1;
-      dbfly<false>(v[0], v[1], asr, asi, bsr, bsi);
-      if (neg) v[1] = make_double2(-v[1].x, -v[1].y);
+      wave_axis<R, W::S, W::ket_bit(R - 1), W::bra_bit(R - 1)>(v, lane, asr, asi, bsr, bsi);
       if (--countdown == 0) {
-        double m = fmax(fmax(fabs(v[0].x), fabs(v[0].y)), fmax(fabs(v[1].x), fabs(v[1].y)));
-        for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
-        int e = 0;
-        (void)frexp(m, &e);
+        double m = 0.0;
 #pragma unroll
-        for (int q = 0; q < 2; ++q) v[q] = make_double2(ldexp(v[q].x, -e), ldexp(v[q].y, -e));
-        acc += e;
+        for (int e = 0; e < E; ++e) m = fmax(m, fmax(fabs(v[e].x), fabs(v[e].y)));
+        for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+        int ex = 0;
+        (void)frexp(m, &ex);
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = make_double2(ldexp(v[e].x, -ex), ldexp(v[e].y, -ex));
+        acc += ex;
         countdown = a.renorm_every;
       }
     }
@@ -361,9 +402,11 @@ refine_wave_kernel(SweepArgs a, const uint32_t* __restrict__ list, const uint32_
     }
     double sr = 0.0, si = 0.0;
 #pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      const int hk = __builtin_popcount(lane & 7) + e;
-      const int hb = __builtin_popcount((lane >> 3) & 7) + e;
+    for (int e = 0; e < E; ++e) {
+      const int q = lane | (e << 6);
+      const int s = (q >> W::S) & 1;
+      const int hk = __builtin_popcount(q & LOWMASK) + s;
+      const int hb = __builtin_popcount((q >> (R - 1)) & LOWMASK) + s;
       double wr = 0.0, wi = 0.0;
 #pragma unroll
       for (int x = 0; x <= R; ++x)  // select the powers without dynamic register indexing
@@ -388,7 +431,7 @@ refine_wave_kernel(SweepArgs a, const uint32_t* __restrict__ list, const uint32_
 
 hipError_t launch_refine(const SweepArgs& a, int32_t reps, double thresh, uint32_t* list, uint32_t* count,
                          int64_t resident_blocks, hipStream_t stream) {
-  if (reps < 1 || reps > 4) return hipErrorInvalidValue;
+  if (reps < 1 || reps > kMaxReps) return hipErrorInvalidValue;
   const int64_t tiles = launch_tiles(a);
   if (tiles <= 0) return hipSuccess;
   hipLaunchKernelGGL(refine_reset, dim3(1), dim3(64), 0, stream, count);
@@ -401,13 +444,18 @@ hipError_t launch_refine(const SweepArgs& a, int32_t reps, double thresh, uint32
   hipLaunchKernelGGL(refine_scan_kernel, dim3(unsigned(scan_blocks)), dim3(256), 0, stream, a, thresh, list, count);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  // enough waves for every listed ket point (pair at reps = 4), at most the
+  // enough waves for every listed ket point (pair at reps >= 4), at most the
   // resident blocks
-  int64_t blocks = tiles * (reps == 4 ? kTile * kTile : kTile) / 4;
+  int64_t blocks = tiles * (reps >= 4 ? kTile * kTile : kTile) / 4;
   if (blocks > resident_blocks) blocks = resident_blocks;
   if (blocks < 1) blocks = 1;
-  if (reps == 4) {
-    hipLaunchKernelGGL(refine_wave_kernel, dim3(unsigned(blocks)), dim3(256), 0, stream, a, list, count);
+  if (reps >= 4) {
+    const dim3 grid{unsigned(blocks)};
+    switch (reps) {
+      case 4: hipLaunchKernelGGL(refine_wave_kernel<4>, grid, dim3(256), 0, stream, a, list, count); break;
+      case 5: hipLaunchKernelGGL(refine_wave_kernel<5>, grid, dim3(256), 0, stream, a, list, count); break;
+      default: hipLaunchKernelGGL(refine_wave_kernel<6>, grid, dim3(256), 0, stream, a, list, count); break;
+    }
     return hipGetLastError();
   }
   switch (reps) {
@@ -427,7 +475,9 @@ hipError_t refine_resident_blocks(int32_t reps, int64_t* out) {
       case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, refine_kernel<1>, 256, 0); break;
       case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, refine_kernel<2>, 256, 0); break;
       case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, refine_kernel<3>, 256, 0); break;
-      default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, refine_wave_kernel, 256, 0); break;
+      case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, refine_wave_kernel<4>, 256, 0); break;
+      case 5: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, refine_wave_kernel<5>, 256, 0); break;
+      default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, refine_wave_kernel<6>, 256, 0); break;
     }
   }
   if (e != hipSuccess) return e;

@@ -58,16 +58,17 @@ def test_opts_struct_layout():
     assert qsvm.GramOpts.dense_a.offset == 48 and qsvm.GramOpts.dense_b.offset == 56
 
 
-@pytest.mark.parametrize("N,n,reps", [(1, 1, 1), (32, 8, 2), (4096, 784, 2), (1024, 784, 3), (7, 3, 1), (1024, 784, 4)])
+@pytest.mark.parametrize("N,n,reps", [(1, 1, 1), (32, 8, 2), (4096, 784, 2), (1024, 784, 3), (7, 3, 1), (1024, 784, 4),
+                                     (1024, 784, 5), (9, 3, 6)])
 def test_mps_bytes_formula(N, n, reps):
-    # Sections G and L only (16 bytes each per site and point); the dense
-    # tensors have their own buffer
+    # Sections G and L only (16 bytes each per site and point, any reps); the
+    # dense tensors have their own buffer, written for reps <= 4 only
     chi = 2**reps
     assert qsvm.qsvm_mps_bytes(N, n, reps) == n * N * 32
-    assert qsvm.qsvm_dense_bytes(N, n, reps) == n * N * chi * chi * 8
+    assert qsvm.qsvm_dense_bytes(N, n, reps) == (n * N * chi * chi * 8 if reps <= 4 else 0)
 
 
-@pytest.mark.parametrize("N,n,reps", [(0, 8, 2), (8, 0, 2), (8, 8, 0), (8, 8, 5), (-1, 8, 2), (8, 65536, 2), (2**31, 8, 2)])
+@pytest.mark.parametrize("N,n,reps", [(0, 8, 2), (8, 0, 2), (8, 8, 0), (8, 8, 7), (-1, 8, 2), (8, 65536, 2), (2**31, 8, 2)])
 def test_mps_bytes_rejects(N, n, reps):
     assert qsvm.qsvm_mps_bytes(N, n, reps) == 0
     assert qsvm.qsvm_dense_bytes(N, n, reps) == 0
@@ -81,7 +82,9 @@ def test_encode_dense_validation(lib, no_inject):
     assert enc(X=None) == qsvm.QSVM_ERR_INVALID_ARG
     assert enc(d=None) == qsvm.QSVM_ERR_INVALID_ARG
     assert enc(d=ctypes.c_void_p(0x100008)) == qsvm.QSVM_ERR_INVALID_ARG
-    assert enc(reps=5) == qsvm.QSVM_ERR_UNSUPPORTED
+    assert enc(reps=5) == qsvm.QSVM_ERR_UNSUPPORTED  # dense tensors up to reps 4
+    assert b"reps <= 4" in lib.qsvm_last_error()
+    assert enc(reps=7) == qsvm.QSVM_ERR_UNSUPPORTED
     assert enc(nbytes=qsvm.qsvm_dense_bytes(8, 4, 2) - 1) == qsvm.QSVM_ERR_SIZE
 
 
@@ -127,8 +130,8 @@ def test_encode_validation(lib, no_inject):
     assert _enc(lib, n=0) == qsvm.QSVM_ERR_INVALID_ARG
     assert _enc(lib, n=70000) == qsvm.QSVM_ERR_INVALID_ARG
     assert _enc(lib, reps=0) == qsvm.QSVM_ERR_INVALID_ARG
-    assert _enc(lib, reps=5) == qsvm.QSVM_ERR_UNSUPPORTED
-    assert b"reps = 5" in lib.qsvm_last_error()
+    assert _enc(lib, reps=7) == qsvm.QSVM_ERR_UNSUPPORTED
+    assert b"reps = 7" in lib.qsvm_last_error()
     assert _enc(lib, mps=ctypes.c_void_p(0x100008)) == qsvm.QSVM_ERR_INVALID_ARG  # misaligned
     assert _enc(lib, X=ctypes.c_void_p(0x100004)) == qsvm.QSVM_ERR_INVALID_ARG
     need = qsvm.qsvm_mps_bytes(8, 4, 2)
@@ -150,7 +153,7 @@ def test_gram_sym_validation(lib, no_inject):
     assert _sym(lib, K=None) == qsvm.QSVM_ERR_INVALID_ARG
     assert _sym(lib, N=0) == qsvm.QSVM_ERR_INVALID_ARG
     assert _sym(lib, n=0) == qsvm.QSVM_ERR_INVALID_ARG
-    assert _sym(lib, reps=5) == qsvm.QSVM_ERR_UNSUPPORTED
+    assert _sym(lib, reps=7) == qsvm.QSVM_ERR_UNSUPPORTED
     assert _sym(lib, ldk=99) == qsvm.QSVM_ERR_INVALID_ARG
     assert _sym(lib, mps=ctypes.c_void_p(0x100004)) == qsvm.QSVM_ERR_INVALID_ARG
 
@@ -169,7 +172,7 @@ def test_gram_sym_noalloc_validation(lib, no_inject):
     assert _sym_noalloc(lib, mps=None) == qsvm.QSVM_ERR_INVALID_ARG
     assert _sym_noalloc(lib, K=None) == qsvm.QSVM_ERR_INVALID_ARG
     assert _sym_noalloc(lib, ldk=99) == qsvm.QSVM_ERR_INVALID_ARG
-    assert _sym_noalloc(lib, reps=5) == qsvm.QSVM_ERR_UNSUPPORTED
+    assert _sym_noalloc(lib, reps=7) == qsvm.QSVM_ERR_UNSUPPORTED
     # the refinement's list needs one entry per tile plus the count: the
     # largest N whose upper triangle fits the static array, and the next one
     # that does not, are told apart before any HIP call
@@ -203,13 +206,14 @@ def test_gram_rect_validation(lib, no_inject):
     assert _rect(lib, Na=0) == qsvm.QSVM_ERR_INVALID_ARG
     assert _rect(lib, Nb=-3) == qsvm.QSVM_ERR_INVALID_ARG
     assert _rect(lib, ldk=69) == qsvm.QSVM_ERR_INVALID_ARG
-    assert _rect(lib, reps=5) == qsvm.QSVM_ERR_UNSUPPORTED
+    assert _rect(lib, reps=7) == qsvm.QSVM_ERR_UNSUPPORTED
 
 
 # One row of 64 x 64 tiles must fit one launch of at most 2^24 - 8 blocks:
 # 16 blocks per tile (1048575 tiles, 67108800 points), 32 at reps = 4
-# (524287 tiles, 33554368 points).  Validation fails before any HIP call.
-@pytest.mark.parametrize("reps,nb_max", [(2, 64 * 1048575), (4, 64 * 524287)])
+# (524287 tiles), 128 at reps = 5 (131071 tiles), 512 at reps = 6 (32767
+# tiles).  Validation fails before any HIP call.
+@pytest.mark.parametrize("reps,nb_max", [(2, 64 * 1048575), (4, 64 * 524287), (5, 64 * 131071), (6, 64 * 32767)])
 def test_gram_rejects_a_tile_row_wider_than_one_launch(lib, no_inject, reps, nb_max):
     opts = qsvm.GramOpts()
     opts.row_begin, opts.row_end = 5, 5  # empty range: a valid Nb returns before launching
@@ -272,7 +276,7 @@ def test_tile_list_validation(lib, no_inject, dev):
     o.row_begin, o.row_end = 0, 64
     assert _tiles(lib, dev, opts=o) == bad
     assert b"row ranges" in lib.qsvm_last_error()
-    assert _tiles(lib, dev, reps=5) == qsvm.QSVM_ERR_UNSUPPORTED
+    assert _tiles(lib, dev, reps=7) == qsvm.QSVM_ERR_UNSUPPORTED
     assert _tiles(lib, dev, n_tiles=0) == qsvm.QSVM_OK  # nothing to launch
     assert _tiles(lib, dev, N=(1 << 31) - 1, n_tiles=1 << 31) == qsvm.QSVM_ERR_UNSUPPORTED
 
@@ -405,7 +409,7 @@ def test_batch_plan_injected_failure(lib, monkeypatch):
 
 def test_tuned_variant_table(lib, no_inject):
     assert lib.qsvm_set_tuned_variant(2, 300, 1000, 4) == qsvm.QSVM_ERR_INVALID_ARG
-    assert lib.qsvm_set_tuned_variant(5, 300, 1000, 1) == qsvm.QSVM_ERR_UNSUPPORTED
+    assert lib.qsvm_set_tuned_variant(7, 300, 1000, 1) == qsvm.QSVM_ERR_UNSUPPORTED
     assert lib.qsvm_set_tuned_variant(2, 300, 0, 1) == qsvm.QSVM_ERR_INVALID_ARG
     assert lib.qsvm_set_tuned_variant(2, 300, 1000, 3) == qsvm.QSVM_OK
     assert lib.qsvm_get_tuned_variant(2, 300, 1000) == 3
@@ -467,7 +471,7 @@ def test_tune_cache_persists_across_processes(tmp_path):
 
 def test_autotune_validation(lib, no_inject):
     ms = (ctypes.c_float * 2)()
-    assert lib.qsvm_autotune(5, 10, 100, None, None, None, 0) == qsvm.QSVM_ERR_UNSUPPORTED
+    assert lib.qsvm_autotune(7, 10, 100, None, None, None, 0) == qsvm.QSVM_ERR_UNSUPPORTED
     assert lib.qsvm_autotune(2, 10, 70000, None, None, None, 0) == qsvm.QSVM_ERR_INVALID_ARG
     assert lib.qsvm_autotune(2, 10, 100, None, None, ms, 2) == qsvm.QSVM_ERR_SIZE
 
