@@ -8,25 +8,34 @@ features already resident in HBM.  value = contracted pairs per second.
 Prints one JSON line with the timing, a roofline entry for the dominant
 kernel (the overlap sweep; launch durations from HIP events on the launch
 stream) and, on rank 0, a CPU baseline: the FP64 oracle timed on the host
-cores on a bounded sample of the same workload.  The exact leg also times the
-workload's second Gram, 1024 test images x the 4096 training images
-(`test_by_train`: encode of the test MPS + rectangular Gram per step).  Three
-more legs add their own objects to the line:
-  surrogate -- 32768 synthetic 784-pixel images, reps = 2: the MLP surrogate
-               trained on 2 % of the exact entries (the complete Gram of a
-               random 4634-point subset), judged on 1 % held out (the Gram of
-               a disjoint 3277-point subset), its whole-set Gram with exact
-               fallback timed against the exact whole-set Gram, and
-               one-vs-rest SVM accuracy on a 4096-point subset with the exact
-               and the surrogate Gram;
-  batched   -- 64 independent Gram jobs of uneven n, N and reps in one
-               persistent hipGraph launch, against one launch per job;
-  sv        -- the state-vector engine against the MPS engine on 512 points
-               at 12, 16 and 20 qubits: times, agreement, and the FP64
-               matrix-core rate of the state-vector Gram.
+cores on a bounded sample of the same workload.  Legs (--legs, all by
+default) add their own objects to the line:
+  exact        -- the workload's second Gram, 1024 test images x the 4096
+                  training images (`test_by_train`: encode of the test MPS +
+                  rectangular Gram per step);
+  reps3        -- both Grams again at reps = 3 (bond dimension 8);
+  deep         -- the split sweep at reps 4, 5 and 6 (bond dimensions 16, 32,
+                  64): symmetric Grams of 2048, 1024 and 512 images;
+  refine_worst -- 4096 near-identical images, every tile refined in FP64,
+                  against the FP32 sweep alone;
+  mlp          -- the surrogate's MLP at 784 (832) -> 512 -> 512 -> 256: the
+                  forward pass of 32768 rows and one 8192-pair training step;
+  surrogate    -- 32768 synthetic 784-pixel images with 2048 near-duplicate
+                  copies, reps = 2: the log-domain surrogate trained on exact
+                  entries of ~2 % of the tiles, calibrated on ~0.5 %, judged
+                  on ~1 % held out (trained, untrained and constant
+                  predictors), its whole-set Gram with exact fallback for the
+                  flagged tiles timed against the exact whole-set Gram, and
+                  one-vs-rest SVM accuracy on a 4096-point subset;
+  batched      -- 64 independent Gram jobs of uneven n, N and reps in one
+                  persistent hipGraph launch (default and tuned work-item
+                  shape) against one launch per job;
+  sv           -- the state-vector engine against the MPS engine on 512
+                  points at 12, 16 and 20 qubits: times, agreement, and the
+                  FP64 matrix-core rate of the state-vector Gram.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--reps 1|2|3|4]
-                       [--sweep butterfly|dense] [--legs exact,surrogate,batched,sv]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--reps 1..6]
+                       [--sweep butterfly|dense] [--legs exact,reps3,deep,...]
                        [--no-cpu-baseline] [--cpu-sample P] [--copy-calibration MiB]
 """
 
@@ -209,10 +218,11 @@ def test_by_train_leg(reps, n_train, train_buf, Xtrain, sweep, args):
     }
 
 
-def exact_reps_leg(reps, n_train, args):
+def exact_reps_leg(reps, n_train, args, kinds=("sym", "test_by_train"), steps=None):
     """The 784-pixel image workload at another depth: the symmetric Gram of the
     training images (encode + Gram per step) and the 1024 x n_train test-by-train
     Gram, each with its sweep's fraction of the FP32 vector peak."""
+    steps = args.steps if steps is None else steps
     import numpy as np
     import torch
     from paper_2405_02630_amd import qsvm, synth
@@ -227,7 +237,7 @@ def exact_reps_leg(reps, n_train, args):
     Kr = torch.empty((Xt.shape[0], n_train), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
     out = {}
-    for kind in ("sym", "test_by_train"):
+    for kind in kinds:
         def step(ev=None):
             m = qsvm.qsvm_encode_mps(X, reps, out=buf)
             if kind == "sym":
@@ -245,12 +255,12 @@ def exact_reps_leg(reps, n_train, args):
         for _ in range(max(1, args.warmup)):
             step()
         torch.cuda.synchronize()
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
         t0 = time.perf_counter()
-        for st in range(args.steps):
+        for st in range(steps):
             step(evs[st])
         torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        ms = (time.perf_counter() - t0) * 1e3 / steps
         sweep_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
         pairs = n_train * (n_train - 1) // 2 if kind == "sym" else Xt.shape[0] * n_train
         flops = sweep_flops_per_pair(n, reps, "butterfly") * pairs
@@ -754,7 +764,7 @@ def main():
     ap.add_argument("--renorm-every", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=720)
-    ap.add_argument("--legs", default="exact,reps3,refine_worst,mlp,surrogate,batched,sv")  # "exact" adds the test x train Gram
+    ap.add_argument("--legs", default="exact,reps3,deep,refine_worst,mlp,surrogate,batched,sv")  # "exact" adds the test x train Gram
     ap.add_argument("--sur-points", type=int, default=32768)
     ap.add_argument("--sur-steps", type=int, default=600)
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -839,7 +849,7 @@ def main():
         "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
         "traffic": traffic[0],
         "traffic_source": traffic[1],
-        "kernel": (f"sweep_split_kernel<{reps},*>" if args.sweep == "butterfly" and reps == 4
+        "kernel": (f"sweep_split_kernel<{reps},*>" if args.sweep == "butterfly" and reps >= 4
                    else f"sweep_{args.sweep}_kernel<{reps},*>"),
         "flops_per_launch": flops,
         "avg_launch_ms": round(sweep_ms, 4),
@@ -875,6 +885,11 @@ def main():
         out["test_by_train"] = test_by_train_leg(reps, N, mps_buf, X, sweep, args)
     if "reps3" in legs and reps == 2:
         out["reps3"] = exact_reps_leg(3, N, args)
+    if "deep" in legs:
+        # the split sweep at bond dimensions 16, 32 and 64 (symmetric Grams of
+        # 2048, 1024 and 512 images; at most 3 timed steps each)
+        out["deep_reps"] = {f"reps{r}": exact_reps_leg(r, pts, args, kinds=("sym",), steps=min(args.steps, 3))["sym"]
+                            for r, pts in ((4, 2048), (5, 1024), (6, 512))}
     if "refine_worst" in legs:
         out["refine_worst"] = refine_worst_leg(args)
     if "mlp" in legs:

@@ -31,17 +31,18 @@
  *     call; they surface at the caller's next synchronisation.  Launch
  *     failures return QSVM_ERR_HIP.  qsvm_last_error() gives a message for
  *     the calling thread's most recent failure.
- *   - Supported: 1 <= n_qubits <= 65535, reps in {1, 2, 3, 4} (chi = 2, 4,
- *     8, 16), 1 <= N < 2^31.  Other reps return QSVM_ERR_UNSUPPORTED, as does
- *     the dense sweep at reps = 4 and a batch plan with a reps = 4 job.  At
- *     reps = 4 the butterfly sweep holds each pair's 128-entry environment in
- *     two lanes (split on the shared physical bit).
+ *   - Supported: 1 <= n_qubits <= 65535, reps in {1, ..., 6} (chi = 2 ..
+ *     64), 1 <= N < 2^31.  Other reps return QSVM_ERR_UNSUPPORTED, as do the
+ *     dense sweep at reps >= 4, dense tensors at reps >= 5, a device-resident
+ *     tile count at reps >= 4 and a batch plan with a reps >= 4 job.  At
+ *     reps >= 4 the butterfly sweep holds each pair's environment (128, 512
+ *     or 2048 entries) in 2, 8 or 32 lanes, 64 entries per lane.
  *   - A Gram call issues its tiles as one or more kernel launches of whole
  *     rows of 64 x 64 tiles (a dispatch holds at most 2^24 - 8 blocks of 256
  *     threads), so one row of tiles must fit one launch: Nb <= 64 *
- *     floor((2^24 - 8) / b) with b = 16 blocks per tile (32 for the reps = 4
- *     sweep, 1 for the state-vector Gram), i.e. Nb below about 2^26 (2^25,
- *     2^30).  Larger Nb is QSVM_ERR_UNSUPPORTED.
+ *     floor((2^24 - 8) / b) with b = 16 blocks per tile (32, 128 and 512 for
+ *     reps 4, 5 and 6, 1 for the state-vector Gram), i.e. Nb below about
+ *     2^26 (2^25, 2^23, 2^21; 2^30).  Larger Nb is QSVM_ERR_UNSUPPORTED.
  *   - Precision: the sweep carries the environment in FP32 with an exact
  *     power-of-two log scale and forms |amp|^2 in FP64; every 64 x 64 tile
  *     holding an entry above an n-dependent threshold is then recomputed
@@ -65,7 +66,7 @@ extern "C" {
 typedef enum {
   QSVM_OK = 0,
   QSVM_ERR_INVALID_ARG = -1, /* null pointer, non-positive size, ldk too small, bad option */
-  QSVM_ERR_UNSUPPORTED = -2, /* valid request outside the supported range (e.g. reps > 4) */
+  QSVM_ERR_UNSUPPORTED = -2, /* valid request outside the supported range (e.g. reps > 6) */
   QSVM_ERR_HIP = -3,         /* a HIP runtime call or kernel launch failed */
   QSVM_ERR_SIZE = -4         /* a caller buffer is smaller than the call needs */
 } qsvm_status;
@@ -186,7 +187,7 @@ qsvm_status qsvm_encode_mps(const double* X, int64_t N, int32_t n_qubits, int32_
 
 /*
  * Bytes of the dense site tensors of N points: n*N*chi*chi*8 (complex64).
- * 0 for arguments outside the supported range.
+ * 0 for arguments outside the supported range (dense tensors: reps <= 4).
  */
 size_t qsvm_dense_bytes(int64_t N, int32_t n_qubits, int32_t reps);
 
@@ -299,7 +300,7 @@ typedef struct {
   const void* mps;   /* device MPS buffer of the job (qsvm_encode_mps with N, n_qubits, reps) */
   int64_t N;         /* points */
   int32_t n_qubits;
-  int32_t reps;      /* 1..3 (reps = 4 is QSVM_ERR_UNSUPPORTED here: use
+  int32_t reps;      /* 1..3 (reps >= 4 is QSVM_ERR_UNSUPPORTED here: use
                         qsvm_gram / qsvm_gram_sym); jobs may mix reps and sizes */
   double* K;         /* device N x N output, row stride ldk >= N; written as by qsvm_gram_sym */
   int64_t ldk;
