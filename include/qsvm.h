@@ -43,6 +43,10 @@
  *     floor((2^24 - 8) / b) with b = 16 blocks per tile (32, 128 and 512 for
  *     reps 4, 5 and 6, 1 for the state-vector Gram), i.e. Nb below about
  *     2^26 (2^25, 2^23, 2^21; 2^30).  Larger Nb is QSVM_ERR_UNSUPPORTED.
+ *   - Tracing: with QSVM_ROCTX=1 in the environment, every entry point that
+ *     enqueues work pushes a roctx range named after itself for the host side
+ *     of the call (`rocprofv3 --marker-trace`); the marker library is opened
+ *     at run time, so nothing links against it.
  *   - Precision: the sweep carries the environment in FP32 with an exact
  *     power-of-two log scale and forms |amp|^2 in FP64; every 64 x 64 tile
  *     holding an entry above an n-dependent threshold is then recomputed

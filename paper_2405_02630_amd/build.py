@@ -37,7 +37,7 @@ FLAGS = [
     "-I" + os.path.join(ROOT, "include"),
 ]
 
-SOURCES = ["api.cpp", "autotune.cpp", "batch_plan.cpp", "batched.hip", "encode.hip", "mlp.hip", "mlp_api.cpp", "noalloc.hip", "refine.hip", "sweep_butterfly.hip", "sweep_dense.hip", "sweep_split.hip", "sv.hip"]
+SOURCES = ["api.cpp", "autotune.cpp", "batch_plan.cpp", "batched.hip", "encode.hip", "mlp.hip", "mlp_api.cpp", "noalloc.hip", "refine.hip", "sweep_butterfly.hip", "sweep_dense.hip", "sweep_split.hip", "sv.hip", "trace.cpp"]
 
 
 def _compile(src: str, verbose: bool) -> str:
@@ -59,7 +59,7 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-ldl"]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

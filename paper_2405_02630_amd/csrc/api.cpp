@@ -13,6 +13,7 @@
 
 #include "../../include/qsvm.h"
 #include "qsvm_internal.h"
+#include "trace.h"
 #include "refine.h"
 #include "sweep_common.h"
 
@@ -342,6 +343,7 @@ size_t qsvm_mps_bytes(int64_t N, int32_t n_qubits, int32_t reps) {
 
 qsvm_status qsvm_encode_mps(const double* X, int64_t N, int32_t n_qubits, int32_t reps, void* mps,
                             size_t mps_bytes, void* stream) {
+  QSVM_TRACE_RANGE("qsvm_encode_mps");
   const char* what = "qsvm_encode_mps";
   qsvm_status s = check_shape(N, n_qubits, reps, what);
   if (s != QSVM_OK) return s;
@@ -363,6 +365,7 @@ size_t qsvm_dense_bytes(int64_t N, int32_t n_qubits, int32_t reps) {
 
 qsvm_status qsvm_encode_dense(const double* X, int64_t N, int32_t n_qubits, int32_t reps, void* dense,
                               size_t dense_bytes, void* stream) {
+  QSVM_TRACE_RANGE("qsvm_encode_dense");
   const char* what = "qsvm_encode_dense";
   qsvm_status s = check_shape(N, n_qubits, reps, what);
   if (s != QSVM_OK) return s;
@@ -384,6 +387,7 @@ double qsvm_auto_refine_threshold(int32_t n_qubits) {
 
 qsvm_status qsvm_gram(const void* mps_a, int64_t Na, const void* mps_b, int64_t Nb, int32_t n_qubits,
                       int32_t reps, double* K, int64_t ldk, const qsvm_gram_opts* opts, void* stream) {
+  QSVM_TRACE_RANGE("qsvm_gram");
   const char* what = "qsvm_gram";
   if (!mps_a || !mps_b) return fail(QSVM_ERR_INVALID_ARG, "%s: MPS buffer is NULL", what);
   if (!K) return fail(QSVM_ERR_INVALID_ARG, "%s: K is NULL", what);
@@ -403,17 +407,20 @@ qsvm_status qsvm_gram(const void* mps_a, int64_t Na, const void* mps_b, int64_t 
 
 qsvm_status qsvm_gram_sym(const void* mps, int64_t N, int32_t n_qubits, int32_t reps, double* K,
                           int64_t ldk, const qsvm_gram_opts* opts, void* stream) {
+  QSVM_TRACE_RANGE("qsvm_gram_sym");
   return gram_sym(mps, N, n_qubits, reps, K, ldk, opts, stream, "qsvm_gram_sym", WorkspaceSource{});
 }
 
 qsvm_status qsvm_gram_sym_tiles(const void* mps, int64_t N, int32_t n_qubits, int32_t reps, const int32_t* tiles,
                                 int64_t n_tiles, double* K, int64_t ldk, const qsvm_gram_opts* opts, void* stream) {
+  QSVM_TRACE_RANGE("qsvm_gram_sym_tiles");
   return gram_tile_list(mps, N, n_qubits, reps, tiles, nullptr, n_tiles, K, ldk, opts, stream, "qsvm_gram_sym_tiles");
 }
 
 qsvm_status qsvm_gram_sym_tiles_dev(const void* mps, int64_t N, int32_t n_qubits, int32_t reps, const int32_t* tiles,
                                     const int32_t* tile_count, int64_t max_tiles, double* K, int64_t ldk,
                                     const qsvm_gram_opts* opts, void* stream) {
+  QSVM_TRACE_RANGE("qsvm_gram_sym_tiles_dev");
   const char* what = "qsvm_gram_sym_tiles_dev";
   if (!tile_count) return fail(QSVM_ERR_INVALID_ARG, "%s: tile_count is NULL", what);
   return gram_tile_list(mps, N, n_qubits, reps, tiles, tile_count, max_tiles, K, ldk, opts, stream, what);
@@ -421,6 +428,7 @@ qsvm_status qsvm_gram_sym_tiles_dev(const void* mps, int64_t N, int32_t n_qubits
 
 qsvm_status qsvm_autotune(int32_t reps, int32_t n_qubits, int64_t N, void* stream, int32_t* best_variant,
                           float* variant_ms, int32_t n_variant_ms) {
+  QSVM_TRACE_RANGE("qsvm_autotune");
   const char* what = "qsvm_autotune";
   qsvm_status s = check_shape(N, n_qubits, reps, what);
   if (s != QSVM_OK) return s;
@@ -471,6 +479,7 @@ size_t qsvm_sv_bytes(int64_t N, int32_t n_qubits) {
 
 qsvm_status qsvm_encode_sv(const double* X, int64_t N, int32_t n_qubits, int32_t reps, void* sv, size_t sv_bytes,
                            void* stream) {
+  QSVM_TRACE_RANGE("qsvm_encode_sv");
   const char* what = "qsvm_encode_sv";
   if (n_qubits < 1 || n_qubits > qsvm::kMaxSvQubits)
     return fail(QSVM_ERR_UNSUPPORTED, "%s: n_qubits = %d outside [1, 30]", what, n_qubits);
@@ -530,11 +539,13 @@ qsvm_status run_sv_gram(const void* sv_a, int64_t Na, const void* sv_b, int64_t 
 
 qsvm_status qsvm_sv_gram(const void* sv_a, int64_t Na, const void* sv_b, int64_t Nb, int32_t n_qubits, double* K,
                          int64_t ldk, const qsvm_gram_opts* opts, void* stream) {
+  QSVM_TRACE_RANGE("qsvm_sv_gram");
   return run_sv_gram(sv_a, Na, sv_b, Nb, n_qubits, K, ldk, opts, false, stream, "qsvm_sv_gram");
 }
 
 qsvm_status qsvm_sv_gram_sym(const void* sv, int64_t N, int32_t n_qubits, double* K, int64_t ldk,
                              const qsvm_gram_opts* opts, void* stream) {
+  QSVM_TRACE_RANGE("qsvm_sv_gram_sym");
   return run_sv_gram(sv, N, sv, N, n_qubits, K, ldk, opts, true, stream, "qsvm_sv_gram_sym");
 }
 

@@ -11,6 +11,7 @@
 #include "../../include/qsvm.h"
 #include "batched.h"
 #include "qsvm_internal.h"
+#include "trace.h"
 #include "refine.h"
 
 struct qsvm_batch_plan {
@@ -146,6 +147,7 @@ bool api_injected_failure();
 
 extern "C" qsvm_status qsvm_batch_plan_create(const qsvm_job* jobs, int32_t n_jobs, const qsvm_batch_opts* opts,
                                               qsvm_batch_plan** plan_out) {
+  QSVM_TRACE_RANGE("qsvm_batch_plan_create");
   using namespace qsvm;
   char msg[256];
   if (!plan_out) return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_batch_plan_create: plan is NULL");
@@ -258,6 +260,7 @@ extern "C" qsvm_status qsvm_batch_plan_create(const qsvm_job* jobs, int32_t n_jo
 }
 
 extern "C" qsvm_status qsvm_batch_plan_launch(qsvm_batch_plan* p, void* stream) {
+  QSVM_TRACE_RANGE("qsvm_batch_plan_launch");
   using namespace qsvm;
   if (!p) return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_batch_plan_launch: plan is NULL");
   if (api_injected_failure()) return api_fail(QSVM_ERR_HIP, "qsvm_batch_plan_launch: injected launch failure (QSVM_FAULT_INJECT=launch)");

@@ -9,6 +9,7 @@
 #include "../../include/qsvm.h"
 #include "mlp.h"
 #include "qsvm_internal.h"
+#include "trace.h"
 #include "sweep_common.h"
 
 namespace qsvm {
@@ -110,6 +111,7 @@ extern "C" {
 
 qsvm_status qsvm_gather_features(const double* X, int64_t N, int32_t n_qubits, const int32_t* idx, int64_t rows,
                                  int32_t d_pad, void* out, void* stream) {
+  QSVM_TRACE_RANGE("qsvm_gather_features");
   const char* what = "qsvm_gather_features";
   if (!X || !idx || !out) return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_gather_features: NULL pointer");
   if (N < 1 || n_qubits < 1 || rows < 1 || d_pad < n_qubits)
@@ -122,6 +124,7 @@ qsvm_status qsvm_gather_features(const double* X, int64_t N, int32_t n_qubits, c
 
 qsvm_status qsvm_mlp_forward(const qsvm_mlp* net, const void* X16, int64_t rows, const qsvm_mlp_acts* acts,
                              void* stream) {
+  QSVM_TRACE_RANGE("qsvm_mlp_forward");
   const char* what = "qsvm_mlp_forward";
   qsvm_status s = check_net(net, what);
   if (s != QSVM_OK) return s;
@@ -193,6 +196,7 @@ qsvm_status qsvm_pair_head(const float* E, int64_t pairs, int32_t d, const float
 qsvm_status qsvm_pair_head_log(const void* X16, int32_t d_in, const float* E, int32_t d, int64_t pairs,
                                const float* target, const float* head, float scale, void* dE16, float* partial,
                                float* out3, float* pred, void* stream) {
+  QSVM_TRACE_RANGE("qsvm_pair_head_log");
   const char* what = "qsvm_pair_head_log";
   if ((!X16 && d_in > 0) || !E || !target || !head || !dE16 || !partial || !out3)
     return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_pair_head_log: NULL pointer");
@@ -207,6 +211,7 @@ qsvm_status qsvm_pair_head_log(const void* X16, int32_t d_in, const float* E, in
 
 qsvm_status qsvm_mlp_backward(const qsvm_mlp* net, const void* X16, const qsvm_mlp_acts* acts, const void* dE16,
                               int64_t rows, const qsvm_mlp_grads* g, void* stream) {
+  QSVM_TRACE_RANGE("qsvm_mlp_backward");
   const char* what = "qsvm_mlp_backward";
   qsvm_status s = check_net(net, what);
   if (s != QSVM_OK) return s;
@@ -252,6 +257,7 @@ int64_t qsvm_mlp_workspace_floats(const qsvm_mlp* net, int64_t rows) {
 
 qsvm_status qsvm_adamw(float* w, const float* grad, float* m, float* v, void* w16, int64_t count, float lr,
                        float beta1, float beta2, float eps, float weight_decay, int32_t step, void* stream) {
+  QSVM_TRACE_RANGE("qsvm_adamw");
   const char* what = "qsvm_adamw";
   if (!w || !grad || !m || !v) return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_adamw: NULL pointer");
   if (count < 1 || step < 1 || !(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) ||
@@ -287,6 +293,7 @@ qsvm_status qsvm_surrogate_gram(const void* E16, int64_t N, int64_t N_pad, int32
 
 qsvm_status qsvm_surrogate_gram_log(const void* X16, int32_t d_in, const void* E16, int32_t d, int64_t N, int64_t N_pad,
                                     const float* head, double* K, int64_t ldk, float* tile_max, void* stream) {
+  QSVM_TRACE_RANGE("qsvm_surrogate_gram_log");
   const char* what = "qsvm_surrogate_gram_log";
   if ((!X16 && d_in > 0) || !E16 || !head || !K || !tile_max)
     return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_surrogate_gram_log: NULL pointer");
@@ -304,6 +311,7 @@ qsvm_status qsvm_surrogate_gram_log(const void* X16, int32_t d_in, const void* E
 
 qsvm_status qsvm_flag_tiles(const float* tile_max, int32_t T, float tau, int32_t* tile_list, int32_t* count,
                             void* stream) {
+  QSVM_TRACE_RANGE("qsvm_flag_tiles");
   const char* what = "qsvm_flag_tiles";
   if (!tile_max || !tile_list || !count) return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_flag_tiles: NULL pointer");
   if (T < 1 || T > 65536) return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_flag_tiles: T outside [1, 65536]");

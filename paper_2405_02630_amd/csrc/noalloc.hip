@@ -13,6 +13,7 @@
 
 #include "../../include/qsvm.h"
 #include "qsvm_internal.h"
+#include "trace.h"
 
 namespace qsvm {
 qsvm_status gram_sym_static_workspace(const void* mps, int64_t N, int32_t n_qubits, int32_t reps, double* K,
@@ -56,6 +57,7 @@ hipError_t scratch_address(uint32_t** out) {
 
 extern "C" qsvm_status qsvm_gram_sym_noalloc(const void* mps, int64_t N, int32_t n_qubits, int32_t reps, double* K,
                                              int64_t ldk, const qsvm_gram_opts* opts, void* stream) {
+  QSVM_TRACE_RANGE("qsvm_gram_sym_noalloc");
   return qsvm::gram_sym_static_workspace(mps, N, n_qubits, reps, K, ldk, opts, stream, scratch_address,
                                          kScratchEntries, "qsvm_gram_sym_noalloc");
 }

@@ -559,3 +559,37 @@ def test_mlp_forward_validation(lib, no_inject):
         assert f(ctypes.byref(net), FAKE, 64, ctypes.byref(infer), None) == qsvm.QSVM_ERR_HIP
     finally:
         del os.environ["QSVM_FAULT_INJECT"]
+
+
+def _roctx_probe(env_value):
+    """In a fresh process: one entry-point call that fails validation, then
+    whether the marker library is mapped."""
+    import subprocess
+    import sys
+
+    code = (
+        "import ctypes\n"
+        "from paper_2405_02630_amd import qsvm\n"
+        "lib = qsvm.load_library()\n"
+        "st = lib.qsvm_gram_sym(None, 100, 8, 2, ctypes.c_void_p(0x200000), 100, None, None)\n"
+        "maps = open('/proc/self/maps').read()\n"
+        "print(st, 'rocprofiler-sdk-roctx' in maps)\n"
+    )
+    env = dict(os.environ)
+    env.pop("QSVM_ROCTX", None)
+    if env_value is not None:
+        env["QSVM_ROCTX"] = env_value
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 0, r.stderr
+    return r.stdout.split()
+
+
+def test_roctx_ranges_are_opt_in():
+    # QSVM_ROCTX=1: the marker library is opened on the first entry-point call
+    # (the call itself behaves as without it); otherwise it is never loaded
+    st, mapped = _roctx_probe("1")
+    assert int(st) == qsvm.QSVM_ERR_INVALID_ARG and mapped == "True"
+    st, mapped = _roctx_probe(None)
+    assert int(st) == qsvm.QSVM_ERR_INVALID_ARG and mapped == "False"
+    st, mapped = _roctx_probe("0")
+    assert mapped == "False"
