@@ -385,8 +385,8 @@ qsvm_status qsvm_autotune(int32_t reps, int32_t n_qubits, int64_t N, void* strea
 /* The variant (0..3) a launch with opts.variant == 0 uses for (reps, n_qubits)
  * on N points (a symmetric Gram of N points, or a rectangular Gram whose
  * pair count Na Nb equals N^2 / 2): the entry of the bucket
- * (floor(log2 n_qubits), floor(log2 N)), else that of the nearest N bucket
- * tuned for the same n bucket, else 0. */
+ * (floor(log2 n_qubits), floor(log2 N)), else 0 (the built-in default; a
+ * variant tuned for another point count is not carried over). */
 int32_t qsvm_get_tuned_variant(int32_t reps, int32_t n_qubits, int64_t N);
 
 /* Record a variant for (reps, n_qubits, N) in the table of the current device's

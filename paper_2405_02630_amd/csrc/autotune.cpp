@@ -156,19 +156,12 @@ int32_t tuned_variant(int32_t reps, int32_t n, int64_t N) {
   std::lock_guard<std::mutex> lk(g_mu);
   const std::string arch = current_arch_locked();
   load_arch_locked(arch);
-  const int nb = bucket_of(n, kBuckets), Nb = bucket_of(N, kNBuckets);
-  // the entry of this (n, N) bucket, else the one of the nearest N bucket
-  // tuned for this n bucket (the larger on a tie), else the default 0
-  int best = -1, best_d = 1 << 30;
-  for (auto it = g_table.lower_bound(Key(arch, reps, nb, 0)); it != g_table.end(); ++it) {
-    if (std::get<0>(it->first) != arch || std::get<1>(it->first) != reps || std::get<2>(it->first) != nb) break;
-    const int d = std::abs(std::get<3>(it->first) - Nb);
-    if (d <= best_d) {
-      best_d = d;
-      best = it->second;
-    }
-  }
-  return best < 0 ? 0 : best;
+  // the entry of this (n, N) bucket, else the built-in default 0: a variant
+  // tuned for another point count is not carried over (the best one changes
+  // with the number of tiles: 8 waves per SIMD win below ~2048 points at
+  // r = 2 and lose 8 % at 4096)
+  const auto it = g_table.find(Key(arch, reps, bucket_of(n, kBuckets), bucket_of(N, kNBuckets)));
+  return it == g_table.end() ? 0 : it->second;
 }
 
 void set_tuned_variant(int32_t reps, int32_t n, int64_t N, int32_t variant) {

@@ -629,17 +629,25 @@ __global__ void __launch_bounds__(256) gather_features(const double* __restrict_
 }
 
 // Column sums in two fixed-order stages: partial[chunk][c] over 256-row
-// chunks (consecutive threads read consecutive columns), then the chunks.
+// chunks, then the chunks (sum_slabs).  A block covers 64 columns (one per
+// lane) of one chunk; wave w sums the rows w, w + 4, ... of the chunk, and
+// the four wave sums are added in wave order.
 constexpr int kColChunk = 256;
 
-__global__ void colsum_partial(const uint16_t* __restrict__ A, int64_t rows, int32_t cols, float* __restrict__ partial) {
-  const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= cols) return;
+__global__ void __launch_bounds__(256) colsum_partial(const uint16_t* __restrict__ A, int64_t rows, int32_t cols,
+                                                      float* __restrict__ partial) {
+  __shared__ float part[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int32_t c = int32_t(blockIdx.x) * 64 + lane;
   const int64_t r0 = int64_t(blockIdx.y) * kColChunk;
   const int64_t r1 = (r0 + kColChunk < rows) ? r0 + kColChunk : rows;
   float s = 0.0f;
-  for (int64_t r = r0; r < r1; ++r) s += bf16_to_f32(A[r * cols + c]);
-  partial[int64_t(blockIdx.y) * cols + c] = s;
+  if (c < cols)
+    for (int64_t r = r0 + wave; r < r1; r += 4) s += bf16_to_f32(A[r * cols + c]);
+  part[wave][lane] = s;
+  __syncthreads();
+  if (wave == 0 && c < cols)
+    partial[int64_t(blockIdx.y) * cols + c] = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
 }
 
 __global__ void sum_slabs(const float* __restrict__ slabs, int32_t n_slabs, int64_t count, float* __restrict__ out) {
@@ -881,7 +889,7 @@ int colsum_chunks(int64_t rows) { return int((rows + kColChunk - 1) / kColChunk)
 
 hipError_t launch_colsum(const uint16_t* A, int64_t rows, int32_t cols, float* partial, float* out, hipStream_t s) {
   const int chunks = colsum_chunks(rows);
-  hipLaunchKernelGGL(colsum_partial, dim3(unsigned((cols + 255) / 256), unsigned(chunks)), dim3(256), 0, s, A, rows,
+  hipLaunchKernelGGL(colsum_partial, dim3(unsigned((cols + 63) / 64), unsigned(chunks)), dim3(256), 0, s, A, rows,
                      cols, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -84,6 +84,42 @@ __device__ __forceinline__ void swizzle4(const float2& v0, const float2& v1, con
 }
 #undef QSVM_SWZ4
 
+// The same for eight complex entries (sixteen swizzles, one wait).
+#define QSVM_SWZ8(OFF)                                                                               \
+  asm volatile("ds_swizzle_b32 %0, %16 offset:" OFF "\n"                                            \
+               "ds_swizzle_b32 %1, %17 offset:" OFF "\n"                                            \
+               "ds_swizzle_b32 %2, %18 offset:" OFF "\n"                                            \
+               "ds_swizzle_b32 %3, %19 offset:" OFF "\n"                                            \
+               "ds_swizzle_b32 %4, %20 offset:" OFF "\n"                                            \
+               "ds_swizzle_b32 %5, %21 offset:" OFF "\n"                                            \
+               "ds_swizzle_b32 %6, %22 offset:" OFF "\n"                                            \
+               "ds_swizzle_b32 %7, %23 offset:" OFF "\n"                                            \
+               "ds_swizzle_b32 %8, %24 offset:" OFF "\n"                                            \
+               "ds_swizzle_b32 %9, %25 offset:" OFF "\n"                                            \
+               "ds_swizzle_b32 %10, %26 offset:" OFF "\n"                                           \
+               "ds_swizzle_b32 %11, %27 offset:" OFF "\n"                                           \
+               "ds_swizzle_b32 %12, %28 offset:" OFF "\n"                                           \
+               "ds_swizzle_b32 %13, %29 offset:" OFF "\n"                                           \
+               "ds_swizzle_b32 %14, %30 offset:" OFF "\n"                                           \
+               "ds_swizzle_b32 %15, %31 offset:" OFF "\n"                                           \
+               "s_waitcnt lgkmcnt(0)"                                                                \
+               : "=&v"(p[0]), "=&v"(p[1]), "=&v"(p[2]), "=&v"(p[3]), "=&v"(p[4]), "=&v"(p[5]),      \
+                 "=&v"(p[6]), "=&v"(p[7]), "=&v"(p[8]), "=&v"(p[9]), "=&v"(p[10]), "=&v"(p[11]),    \
+                 "=&v"(p[12]), "=&v"(p[13]), "=&v"(p[14]), "=&v"(p[15])                            \
+               : "v"(v[0].x), "v"(v[0].y), "v"(v[1].x), "v"(v[1].y), "v"(v[2].x), "v"(v[2].y),      \
+                 "v"(v[3].x), "v"(v[3].y), "v"(v[4].x), "v"(v[4].y), "v"(v[5].x), "v"(v[5].y),      \
+                 "v"(v[6].x), "v"(v[6].y), "v"(v[7].x), "v"(v[7].y))
+
+template <int XM>
+__device__ __forceinline__ void swizzle8(const float2* v, float (&p)[16]) {
+  if constexpr (XM == 1) QSVM_SWZ8("1055");
+  else if constexpr (XM == 2) QSVM_SWZ8("2079");
+  else if constexpr (XM == 4) QSVM_SWZ8("4127");
+  else if constexpr (XM == 8) QSVM_SWZ8("8223");
+  else QSVM_SWZ8("16415");
+}
+#undef QSVM_SWZ8
+
 // The value of x in lane ^ XM (a few values per site or per pair: the
 // renormalisation maximum and the closure's partial sums).
 template <int XM>
@@ -105,15 +141,18 @@ __device__ __forceinline__ double swz_xor(double x) {
 // passes f0 = f1 = 1; the lane with it passes its sign pattern (f0 = the
 // lane-bit part of the sign, f1 = -f0).  LANE_SIGN = false: f0 is 1 in every
 // lane, so the even entries are not multiplied.
-template <int XM, int IB1, int IB2, bool LANE_SIGN, int ML>
+template <int XM, int IB1, int IB2, bool LANE_SIGN, int ML, int B = 4>
 __device__ __forceinline__ void cross_axis(float2 (&v)[ML], float cr, float ci, float f0, float f1) {
 #pragma unroll
-  for (int c = 0; c < ML / 4; ++c) {
-    float p[8];
-    swizzle4<XM>(v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3], p);
+  for (int c = 0; c < ML / B; ++c) {
+    float p[2 * B];
+    if constexpr (B == 8)
+      swizzle8<XM>(&v[8 * c], p);
+    else
+      swizzle4<XM>(v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3], p);
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int q = 4 * c + e;
+    for (int e = 0; e < B; ++e) {
+      const int q = B * c + e;
       const float pr = p[2 * e], pim = p[2 * e + 1];
       float tr = fmaf(cr, pr, v[q].x);
       tr = fmaf(-ci, pim, tr);
@@ -231,10 +270,10 @@ struct CrossKet {
       float cr, ci;
       axis_coeff(upper, a[0], a[1], a[2], a[3], phr[B], phi[B], cr, ci);
       if constexpr (L0 == 4) {
-        cross_axis<1 << B, 2, -1, false>(v, cr, ci, 1.0f, upper ? -1.0f : 1.0f);
+        cross_axis<1 << B, 2, -1, false, 64, 8>(v, cr, ci, 1.0f, upper ? -1.0f : 1.0f);
       } else {
         const float f0 = (upper && ((g >> Split<R>::kbit(L0 - 1)) & 1)) ? -1.0f : 1.0f;
-        cross_axis<1 << B, -1, -1, true>(v, cr, ci, f0, f0);
+        cross_axis<1 << B, -1, -1, true, 64, 8>(v, cr, ci, f0, f0);
       }
       CrossKet<R, L0 + 1>::run(v, g, a, phr, phi);
     }
@@ -251,10 +290,10 @@ struct CrossBra {
       float cr, ci;
       axis_coeff(upper, a[0], a[1], a[2], a[3], phr[B], phi[B], cr, ci);
       if constexpr (L0 == 4) {
-        cross_axis<1 << B, 5, -1, false>(v, cr, ci, 1.0f, upper ? -1.0f : 1.0f);
+        cross_axis<1 << B, 5, -1, false, 64, 8>(v, cr, ci, 1.0f, upper ? -1.0f : 1.0f);
       } else {
         const float f0 = (upper && ((g >> Split<R>::bbit(L0 - 1)) & 1)) ? -1.0f : 1.0f;
-        cross_axis<1 << B, -1, -1, true>(v, cr, ci, f0, f0);
+        cross_axis<1 << B, -1, -1, true, 64, 8>(v, cr, ci, f0, f0);
       }
       CrossBra<R, L0 + 1>::run(v, g, a, phr, phi);
     }
@@ -345,7 +384,7 @@ __device__ __forceinline__ void split_item(const SweepArgs& a, int64_t i, int64_
         if constexpr (R == 4)
           cross_axis<1, 2, 5, false>(v, cr, ci, 1.0f, up_s ? -1.0f : 1.0f);
         else
-          cross_axis<1, -1, -1, true>(v, cr, ci, fs, fs);
+          cross_axis<1, -1, -1, true, 64, 8>(v, cr, ci, fs, fs);
       }
       if (--countdown == 0) {
         acc += rescale(v, group_max<C>(absmax(v)));

@@ -415,12 +415,12 @@ def test_tuned_variant_table(lib, no_inject):
     assert lib.qsvm_get_tuned_variant(2, 300, 1000) == 3
     assert lib.qsvm_get_tuned_variant(2, 511, 600) == 3  # same log2 buckets (n 8, N 9)
     assert lib.qsvm_get_tuned_variant(2, 512, 1000) == 0  # untuned n bucket -> default
-    # another N bucket of the same n bucket: the nearest tuned N bucket
+    # other N buckets of the same n bucket: only the tuned buckets answer
     assert lib.qsvm_set_tuned_variant(2, 300, 8192, 1) == qsvm.QSVM_OK
-    assert lib.qsvm_get_tuned_variant(2, 300, 100) == 3      # bucket 6: nearest is 9
-    assert lib.qsvm_get_tuned_variant(2, 300, 5000) == 1     # bucket 12: nearest is 13
-    assert lib.qsvm_get_tuned_variant(2, 300, 1 << 20) == 1
-    assert lib.qsvm_get_tuned_variant(2, 300, 2900) == 1     # bucket 11: 9 and 13 equally near -> the larger
+    assert lib.qsvm_get_tuned_variant(2, 300, 9000) == 1     # bucket 13
+    assert lib.qsvm_get_tuned_variant(2, 300, 100) == 0      # bucket 6: untuned -> default
+    assert lib.qsvm_get_tuned_variant(2, 300, 5000) == 0     # bucket 12: untuned -> default
+    assert lib.qsvm_get_tuned_variant(2, 300, 1 << 20) == 0
     for N in (1000, 8192):
         assert lib.qsvm_set_tuned_variant(2, 300, N, 0) == qsvm.QSVM_OK
 

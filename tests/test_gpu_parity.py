@@ -346,7 +346,7 @@ def test_unsupported_and_invalid_raise_before_launch():
 
     X = torch.zeros((4, 5), dtype=torch.float64, device="cuda:0")
     with pytest.raises(qsvm.QsvmError) as ei:
-        qsvm.qsvm_encode_mps(X, 5)
+        qsvm.qsvm_encode_mps(X, 7)
     assert ei.value.status == qsvm.QSVM_ERR_UNSUPPORTED
     m = qsvm.qsvm_encode_mps(X, 2)
     K = torch.empty((4, 3), dtype=torch.float64, device="cuda:0")
