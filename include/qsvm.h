@@ -48,11 +48,10 @@
  *     of the call (`rocprofv3 --marker-trace`); the marker library is opened
  *     at run time, so nothing links against it.
  *   - Precision: the sweep carries the environment in FP32 with an exact
- *     power-of-two log scale and forms |amp|^2 in FP64; every 64 x 64 tile
- *     holding an entry above an n-dependent threshold is then recomputed
- *     with an FP64 environment (qsvm_gram_opts.refine_above), so entries
- *     left in FP32 stay within ~5e-6 of the exact kernel and refined ones
- *     within ~1e-12.
+ *     power-of-two log scale and forms |amp|^2 in FP64; every entry above
+ *     an n-dependent threshold is then recomputed with an FP64 environment
+ *     (qsvm_gram_opts.refine_above), so entries left in FP32 stay within
+ *     ~5e-6 of the exact kernel and refined ones within ~1e-12.
  *   - No call throws across the ABI.  Results are bitwise reproducible for the
  *     same inputs, arguments and device (no floating-point atomics; the
  *     integer atomics that collect tile lists only order independent work).
@@ -112,9 +111,11 @@ typedef struct {
                            K itself underflows to 0 below ~1e-308; log_k does
                            not.  NULL = not written. */
   double refine_above;  /* FP64 refinement: after the FP32 sweep, every
-                           64 x 64 tile whose largest computed entry exceeds
-                           this value is recomputed with an FP64 environment
-                           from FP64 generators (Sections G + L).  The FP32
+                           computed entry above this value is recomputed with
+                           an FP64 environment from FP64 generators (Sections
+                           G + L): the 64 x 64 tiles whose largest entry
+                           exceeds it are listed, and within them the waves
+                           holding such an entry recompute it.  The FP32
                            sweep alone leaves up to ~1.3e-5 at 784 qubits for
                            K near 1 (measured bound 4e-6 + 2e-8 n at K = 1,
                            ~sqrt(K) times that below).  0 = automatic:
@@ -223,7 +224,7 @@ double qsvm_auto_refine_threshold(int32_t n_qubits);
  *   opts          NULL or settings above (diag_mode is ignored).
  * The environment is carried in FP32 with power-of-two renormalisation into
  * an integer log2 scale; the final modulus squared is formed in FP64, and
- * tiles with large entries are recomputed in FP64 (opts->refine_above).
+ * large entries are recomputed in FP64 (opts->refine_above).
  */
 qsvm_status qsvm_gram(const void* mps_a, int64_t Na, const void* mps_b, int64_t Nb,
                       int32_t n_qubits, int32_t reps, double* K, int64_t ldk,

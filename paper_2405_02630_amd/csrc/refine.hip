@@ -8,9 +8,11 @@
 // refine.h).  After a sweep launch, refine_scan_kernel reads the K tiles the
 // launch wrote and lists those whose largest computed entry exceeds a
 // threshold, and
-// refine_kernel recomputes every pair of the listed tiles with an FP64
-// environment from FP64 generators (Section G value + Section L residual),
-// overwriting K and log K.  The list length stays on the device: the
+// refine_kernel recomputes the pairs of the listed tiles whose entry exceeds
+// the threshold with an FP64 environment from FP64 generators (Section G
+// value + Section L residual), overwriting K and log K; a wave whose pairs
+// are all below it skips its item (a tile listed for one near-duplicate
+// pair costs one wave, not 64).  The list length stays on the device: the
 // refinement kernel is launched with a fixed grid whose waves take (tile,
 // ket point) items until the list is exhausted (none when nothing was
 // listed), so no host synchronisation is needed and the three launches can
@@ -207,7 +209,7 @@ refine_scan_kernel(SweepArgs a, double thresh, uint32_t* __restrict__ list, uint
 // that ket point against the tile's 64 bra points in FP64.
 template <int R>
 __global__ void __launch_bounds__(256)
-refine_kernel(SweepArgs a, const uint32_t* __restrict__ list, const uint32_t* __restrict__ count) {
+refine_kernel(SweepArgs a, double thresh, const uint32_t* __restrict__ list, const uint32_t* __restrict__ count) {
   constexpr int M = DLayout<R>::M;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -221,7 +223,10 @@ refine_kernel(SweepArgs a, const uint32_t* __restrict__ list, const uint32_t* __
     if (!decode_tile(a, list[it / kTile], ti, tj)) continue;
     const int64_t i = int64_t(ti) * kTile + int64_t(it % kTile);
     const int64_t j = int64_t(tj) * kTile + lane;
-    const bool comp = pair_computed(a, i, j);
+    // only the pairs whose FP32 entry exceeds the threshold (entries at or
+    // below it are within the FP32 sweep's error budget); a wave with none
+    // of them skips the item
+    const bool comp = pair_computed(a, i, j) && a.K[i * a.ldk + j] > thresh;
     if (!__builtin_amdgcn_ballot_w64(comp)) continue;
     const int64_t ic = (i < a.Na) ? i : a.Na - 1;  // loads of idle lanes stay in bounds
     const int64_t jc = (j < a.Nb) ? j : a.Nb - 1;
@@ -337,7 +342,7 @@ struct WAxes {
 
 template <int R>
 __global__ void __launch_bounds__(256)
-refine_wave_kernel(SweepArgs a, const uint32_t* __restrict__ list, const uint32_t* __restrict__ count) {
+refine_wave_kernel(SweepArgs a, double thresh, const uint32_t* __restrict__ list, const uint32_t* __restrict__ count) {
   using W = WLayout<R>;
   constexpr int E = W::E;
   constexpr int LOWMASK = (1 << (R - 1)) - 1;
@@ -353,7 +358,8 @@ refine_wave_kernel(SweepArgs a, const uint32_t* __restrict__ list, const uint32_
     if (!decode_tile(a, list[it / (kTile * kTile)], ti, tj)) continue;
     const int pr = int(it % (kTile * kTile));
     const int64_t i = int64_t(ti) * kTile + pr / kTile, j = int64_t(tj) * kTile + pr % kTile;
-    if (!pair_computed(a, i, j)) continue;  // the same pair in every lane
+    // the same pair in every lane; only entries above the threshold
+    if (!pair_computed(a, i, j) || !(a.K[i * a.ldk + j] > thresh)) continue;
     double2 v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -452,16 +458,16 @@ hipError_t launch_refine(const SweepArgs& a, int32_t reps, double thresh, uint32
   if (reps >= 4) {
     const dim3 grid{unsigned(blocks)};
     switch (reps) {
-      case 4: hipLaunchKernelGGL(refine_wave_kernel<4>, grid, dim3(256), 0, stream, a, list, count); break;
-      case 5: hipLaunchKernelGGL(refine_wave_kernel<5>, grid, dim3(256), 0, stream, a, list, count); break;
-      default: hipLaunchKernelGGL(refine_wave_kernel<6>, grid, dim3(256), 0, stream, a, list, count); break;
+      case 4: hipLaunchKernelGGL(refine_wave_kernel<4>, grid, dim3(256), 0, stream, a, thresh, list, count); break;
+      case 5: hipLaunchKernelGGL(refine_wave_kernel<5>, grid, dim3(256), 0, stream, a, thresh, list, count); break;
+      default: hipLaunchKernelGGL(refine_wave_kernel<6>, grid, dim3(256), 0, stream, a, thresh, list, count); break;
     }
     return hipGetLastError();
   }
   switch (reps) {
-    case 1: hipLaunchKernelGGL(refine_kernel<1>, dim3(unsigned(blocks)), dim3(256), 0, stream, a, list, count); break;
-    case 2: hipLaunchKernelGGL(refine_kernel<2>, dim3(unsigned(blocks)), dim3(256), 0, stream, a, list, count); break;
-    default: hipLaunchKernelGGL(refine_kernel<3>, dim3(unsigned(blocks)), dim3(256), 0, stream, a, list, count); break;
+    case 1: hipLaunchKernelGGL(refine_kernel<1>, dim3(unsigned(blocks)), dim3(256), 0, stream, a, thresh, list, count); break;
+    case 2: hipLaunchKernelGGL(refine_kernel<2>, dim3(unsigned(blocks)), dim3(256), 0, stream, a, thresh, list, count); break;
+    default: hipLaunchKernelGGL(refine_kernel<3>, dim3(unsigned(blocks)), dim3(256), 0, stream, a, thresh, list, count); break;
   }
   return hipGetLastError();
 }

@@ -3,9 +3,11 @@
 The FP32 sweep's error in K is relative and biased low: at 784 qubits an
 entry near 1 (a self-overlap, a near-duplicate pair) comes out 1e-5 or more
 below its exact value (reps 2 to 4).  With refinement (the default: an
-automatic threshold from n, 0.064 at 784 qubits) every tile holding such an
-entry is recomputed with an FP64 environment from FP64 generators.  Bars: refined entries within 1e-9 of the FP64 oracle (its own
-error is ~1e-12), every entry within the 1e-5 contract; untouched tiles are
+automatic threshold from n, 0.064 at 784 qubits) every entry above it is
+recomputed with an FP64 environment from FP64 generators (the tiles holding
+such entries are listed, and within them only those entries are
+recomputed).  Bars: refined entries within 1e-9 of the FP64 oracle (its own
+error is ~1e-12), every entry within the 1e-5 contract; untouched entries are
 bitwise what the FP32 sweep wrote."""
 
 import numpy as np
