@@ -439,6 +439,7 @@ def surrogate_leg(args, exact_rate):
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
     flagged = int(flagged.item())
+    fb = [int(v) for v in sur.fallback.cpu()] if sur.fallback is not None else [None, None]
     sur_s = float(np.median(times))
     It, Jt = torch.as_tensor(Iho, device=dev), torch.as_tensor(Jho, device=dev)
     Ks_ho = Kall[It, Jt].cpu().numpy()
@@ -468,6 +469,8 @@ def surrogate_leg(args, exact_rate):
         "exact_seconds": exact_s,
         "exact_value": n_pairs / exact_s,
         "speedup_vs_exact": exact_s / sur_s,
+        "fallback_pairs": fb[0],
+        "fallback_whole_tiles": fb[1],
         "tau": tau,
         "margin_nats": margin,
         "flagged_tiles": flagged,
@@ -498,6 +501,7 @@ def surrogate_leg(args, exact_rate):
         "model": f"z = [x, MLP(x)], MLP {n}->{cfg.d_h1}->{cfg.d_h2}->{cfg.d_out} GELU, bf16 weights, fp32 accumulate; "
                  "ln K_hat = -c (1 - exp(-s |z - z'|^2))",
     }
+    log(f"surrogate: fallback {fb[0]} pairs one by one, {fb[1]} whole tiles")
     log(f"surrogate: {res['value']:.3e} entries/s ({sur_s*1e3:.1f} ms) vs exact {exact_s*1e3:.1f} ms; "
         f"held-out max|dK| {res['held_out_max_abs_dK']:.2e} ({int(big.sum())} pairs with K > 1e-3); "
         f"flagged {flagged} (untrained {untrained_flagged}, constant {constant_flagged}) of {len(upper)}; "

@@ -293,6 +293,23 @@ qsvm_status qsvm_gram_sym_tiles_dev(const void* mps, int64_t N, int32_t n_qubits
                                     const int32_t* tile_count, int64_t max_tiles, double* K, int64_t ldk,
                                     const qsvm_gram_opts* opts, void* stream);
 
+/*
+ * Exact entries of a symmetric Gram for a list of pairs: for each of the
+ * first *pair_count (device int32, clamped to [0, max_pairs]) entries (i, j)
+ * of `pairs` (device int32 pairs; (j, i) is taken as (i, j); entries with an
+ * index outside [0, N) are skipped) K[i][j] and K[j][i] (and log K with
+ * opts->log_k) are written with an FP64 environment from FP64 generators
+ * (Sections G + L): the value the refinement (opts.refine_above) writes for
+ * that entry, bit for bit.  i == j follows opts->diag_mode.  One pair per
+ * lane (reps <= 3) or per wave (reps >= 4), waves striding over the list;
+ * the host never reads the count.  The exact fallback of the surrogate for
+ * flagged pairs (qsvm_flag_pairs).  opts row ranges must be 0,0; sweep,
+ * variant and refine_above are ignored.
+ */
+qsvm_status qsvm_gram_sym_pairs_dev(const void* mps, int64_t N, int32_t n_qubits, int32_t reps, const int32_t* pairs,
+                                    const int32_t* pair_count, int64_t max_pairs, double* K, int64_t ldk,
+                                    const qsvm_gram_opts* opts, void* stream);
+
 /* ------------------------------------------------------------------------
  * Batched jobs: many independent symmetric Grams in one persistent launch.
  * Every job is cut into the work items of the single-Gram sweep, the items of
@@ -560,10 +577,6 @@ qsvm_status qsvm_adamw(float* w, const float* grad, float* m, float* v, void* w1
 qsvm_status qsvm_surrogate_gram(const void* E16, int64_t N, int64_t N_pad, int32_t d, const float* alpha_beta,
                                 double* K, int64_t ldk, float* tile_max, void* stream);
 
-/* Append every upper-triangular tile (ti <= tj) of a T x T tile_max array whose
- * value is >= tau to tile_list (int32 pairs, room for T(T+1)/2) and its count
- * to *count (device int32; cleared first).  The order of the list is not
- * specified. */
 /* Log-domain surrogate Gram: K[i][j] = exp(ln K_hat(z_i, z_j)) with the head
  * of qsvm_pair_head_log on z = [X16 row, E16 row] (N_pad rows each, N_pad = N
  * rounded up to 64; d_in % 32 == 0 (0: no input part, X16 may be NULL),
@@ -576,8 +589,29 @@ qsvm_status qsvm_surrogate_gram(const void* E16, int64_t N, int64_t N_pad, int32
 qsvm_status qsvm_surrogate_gram_log(const void* X16, int32_t d_in, const void* E16, int32_t d, int64_t N, int64_t N_pad,
                                     const float* head, double* K, int64_t ldk, float* tile_max, void* stream);
 
+/* Append every upper-triangular tile (ti <= tj) of a T x T tile_max array whose
+ * value is >= tau to tile_list (int32 pairs, room for T(T+1)/2) and its count
+ * to *count (device int32; cleared first).  The order of the list is not
+ * specified. */
 qsvm_status qsvm_flag_tiles(const float* tile_max, int32_t T, float tau, int32_t* tile_list, int32_t* count,
                             void* stream);
+
+/* The pairs of flagged tiles that need the exact fallback (the surrogate's
+ * fallback per pair; every buffer is the caller's).  For each of the first *tile_count (device int32,
+ * clamped to [0, max_tiles]) entries (ti, tj) of `tiles` (as from
+ * qsvm_flag_tiles), the pairs i < j of that tile with K[i][j] >= cut (K: the
+ * N x N surrogate Gram, row stride ldk) are appended to `pairs` (int32
+ * (i, j), room for max_pairs) when there are at most cap_per_tile of them
+ * (0..4096); a tile with more, or whose pairs do not fit in max_pairs, is
+ * appended to dense_tiles (int32 (ti, tj), room for max_tiles) instead.
+ * *pair_count and *dense_count (device int32, cleared first) receive the
+ * counts; *pair_count may exceed max_pairs, and list slots a tile reserved
+ * but could not use hold (-1, -1) (qsvm_gram_sym_pairs_dev skips them).
+ * max_tiles * cap_per_tile < 2^31.  The order of both lists is not
+ * specified. */
+qsvm_status qsvm_flag_pairs(const double* K, int64_t N, int64_t ldk, const int32_t* tiles, const int32_t* tile_count,
+                            int64_t max_tiles, double cut, int32_t cap_per_tile, int32_t* pairs, int32_t* pair_count,
+                            int64_t max_pairs, int32_t* dense_tiles, int32_t* dense_count, void* stream);
 
 /* Static description of a status code (never NULL). */
 const char* qsvm_status_string(qsvm_status s);

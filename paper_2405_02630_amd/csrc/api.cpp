@@ -426,6 +426,44 @@ qsvm_status qsvm_gram_sym_tiles_dev(const void* mps, int64_t N, int32_t n_qubits
   return gram_tile_list(mps, N, n_qubits, reps, tiles, tile_count, max_tiles, K, ldk, opts, stream, what);
 }
 
+qsvm_status qsvm_gram_sym_pairs_dev(const void* mps, int64_t N, int32_t n_qubits, int32_t reps, const int32_t* pairs,
+                                    const int32_t* pair_count, int64_t max_pairs, double* K, int64_t ldk,
+                                    const qsvm_gram_opts* opts, void* stream) {
+  QSVM_TRACE_RANGE("qsvm_gram_sym_pairs_dev");
+  const char* what = "qsvm_gram_sym_pairs_dev";
+  qsvm_status s = check_shape(N, n_qubits, reps, what);
+  if (s != QSVM_OK) return s;
+  if (!mps || !K || !pairs || !pair_count)
+    return fail(QSVM_ERR_INVALID_ARG, "%s: mps, pairs, pair_count or K is NULL", what);
+  if (ldk < N) return fail(QSVM_ERR_INVALID_ARG, "%s: ldk = %lld < N = %lld", what, (long long)ldk, (long long)N);
+  if (reinterpret_cast<uintptr_t>(mps) % 16 != 0) return fail(QSVM_ERR_INVALID_ARG, "%s: mps is not 16-byte aligned", what);
+  if (max_pairs < 0 || max_pairs > (int64_t(1) << 40))
+    return fail(QSVM_ERR_INVALID_ARG, "%s: max_pairs = %lld outside [0, 2^40]", what, (long long)max_pairs);
+  Opts o;
+  s = read_opts(opts, N, o, what);
+  if (s != QSVM_OK) return s;
+  if (o.row_begin != 0 || o.row_end != N) return fail(QSVM_ERR_INVALID_ARG, "%s: row ranges do not apply to pair lists", what);
+  if (max_pairs == 0) return ok();
+  if (injected_launch_failure()) return fail(QSVM_ERR_HIP, "%s: injected launch failure (QSVM_FAULT_INJECT=launch)", what);
+  qsvm::SweepArgs a{};
+  a.gen_a = a.gen_b = static_cast<const float4*>(mps);
+  a.K = K;
+  a.log_k = o.log_k;
+  a.Na = a.Nb = N;
+  a.ldk = ldk;
+  a.row_begin = 0;
+  a.row_end = N;
+  a.n = n_qubits;
+  a.renorm_every = o.renorm_every;
+  a.sym = 1;
+  a.diag_mode = o.diag_mode;
+  int64_t resident = 0;
+  hipError_t e = resident_refine_blocks(reps, &resident);
+  if (e == hipSuccess)
+    e = qsvm::launch_pairs_fp64(a, reps, pairs, pair_count, max_pairs, resident, static_cast<hipStream_t>(stream));
+  return hip_status(e, what);
+}
+
 qsvm_status qsvm_autotune(int32_t reps, int32_t n_qubits, int64_t N, void* stream, int32_t* best_variant,
                           float* variant_ms, int32_t n_variant_ms) {
   QSVM_TRACE_RANGE("qsvm_autotune");

@@ -64,6 +64,12 @@ hipError_t launch_sat_log_gram(const uint16_t* X16, int32_t d_in, const uint16_t
                                hipStream_t s);
 hipError_t launch_adamw(float* w, const float* grad, float* m, float* v, uint16_t* w16, int64_t count,
                         const AdamArgs& o, hipStream_t s);
+// Pairs (i < j) of the listed tiles with K[i][j] >= cut: at most cap per tile
+// into the pair list, the other tiles into the dense list (counts cleared
+// here first).
+hipError_t launch_flag_pairs(const double* K, int64_t N, int64_t ldk, const int32_t* tiles, const int32_t* tile_count,
+                             int64_t max_tiles, double cut, int32_t cap, int32_t* pairs, int32_t* pair_count,
+                             int64_t max_pairs, int32_t* dense, int32_t* dense_count, hipStream_t s);
 hipError_t launch_flag_tiles(const float* tile_max, int32_t T, float tau, int32_t* list, int32_t* count,
                              hipStream_t s);
 

@@ -31,6 +31,8 @@
 //   [x, f(x)] (loss and gradients per pair; the whole Gram with per-tile
 //   maxima of ln K_hat).
 // * adamw: decoupled-weight-decay Adam on FP32 master weights, BF16 copy.
+// * flag_pairs_kernel: lists the pairs of flagged tiles whose K_hat reaches
+//   the fallback threshold (tiles with many go to a dense tile list).
 // * flag_tiles: compacts the tiles whose largest off-diagonal K_hat reaches
 //   the fallback threshold.
 //
@@ -809,6 +811,76 @@ __global__ void flag_tiles(const float* __restrict__ tile_max, int32_t T, float 
   }
 }
 
+// Pairs of the listed tiles (a symmetric Gram's upper triangle: i < j) whose
+// K_hat reaches `cut`.  One block per listed tile (grid-stride over the
+// device count): a tile with at most `cap` such pairs appends them to the
+// pair list (one reservation per tile), a tile with more goes to the dense
+// tile list.  A tile whose reservation would pass max_pairs goes dense too,
+// and fills the slots it reserved below max_pairs with (-1, -1), which the
+// consumer skips.  Both counts must be zero before the launch.
+__global__ void __launch_bounds__(256)
+flag_pairs_kernel(const double* __restrict__ K, int64_t N, int64_t ldk, const int32_t* __restrict__ tiles,
+                  const int32_t* __restrict__ tile_count, int64_t max_tiles, double cut, int32_t cap,
+                  int32_t* __restrict__ pairs, int32_t* __restrict__ pair_count, int64_t max_pairs,
+                  int32_t* __restrict__ dense, int32_t* __restrict__ dense_count) {
+  __shared__ int32_t pre[256];
+  __shared__ int64_t base_s;
+  const int t = threadIdx.x;
+  int64_t nt = *tile_count;
+  nt = nt < 0 ? 0 : (nt < max_tiles ? nt : max_tiles);
+  for (int64_t u = blockIdx.x; u < nt; u += gridDim.x) {  // block-uniform
+    const int32_t ti = tiles[2 * u], tj = tiles[2 * u + 1];
+    // this thread's 16 entries: e = t + 256 q, row e / 64, column e % 64
+    uint32_t hits = 0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = t + 256 * q, r = e >> 6, c = e & 63;
+      const int64_t i = int64_t(ti) * 64 + r, j = int64_t(tj) * 64 + c;
+      const bool ok = ti >= 0 && tj >= ti && i < N && j < N && (ti < tj || c > r) && K[i * ldk + j] >= cut;
+      hits |= uint32_t(ok) << q;
+    }
+    // block prefix sum of the hit counts (Hillis-Steele in LDS)
+    pre[t] = __builtin_popcount(hits);
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+      const int32_t v = (t >= off) ? pre[t - off] : 0;
+      __syncthreads();
+      pre[t] += v;
+      __syncthreads();
+    }
+    const int32_t total = pre[255];
+    const int32_t mine = pre[t] - __builtin_popcount(hits);  // exclusive prefix
+    if (t == 0) base_s = (total > 0 && total <= cap) ? int64_t(atomicAdd(pair_count, total)) : -1;
+    __syncthreads();
+    const int64_t base = base_s;
+    const bool listed = base >= 0 && base + total <= max_pairs;
+    if (t == 0 && total > 0 && !listed) {
+      const int32_t slot = atomicAdd(dense_count, 1);
+      dense[2 * slot] = ti;
+      dense[2 * slot + 1] = tj;
+    }
+    int64_t w = base + mine;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      if (!((hits >> q) & 1u)) continue;
+      if (base >= 0 && w < max_pairs) {
+        const int e = t + 256 * q;
+        pairs[2 * w] = listed ? ti * 64 + (e >> 6) : -1;
+        pairs[2 * w + 1] = listed ? tj * 64 + (e & 63) : -1;
+      }
+      ++w;
+    }
+    __syncthreads();  // pre[] and base_s are rewritten for the next tile
+  }
+}
+
+__global__ void zero_two(int32_t* a, int32_t* b) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    *a = 0;
+    *b = 0;
+  }
+}
+
 __global__ void zero_int(int32_t* p) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
 }
@@ -937,6 +1009,18 @@ hipError_t launch_sat_log_gram(const uint16_t* X16, int32_t d_in, const uint16_t
 hipError_t launch_adamw(float* w, const float* grad, float* m, float* v, uint16_t* w16, int64_t count,
                         const AdamArgs& o, hipStream_t s) {
   hipLaunchKernelGGL(adamw, dim3(unsigned((count + 255) / 256)), dim3(256), 0, s, w, grad, m, v, w16, count, o);
+  return hipGetLastError();
+}
+
+hipError_t launch_flag_pairs(const double* K, int64_t N, int64_t ldk, const int32_t* tiles, const int32_t* tile_count,
+                             int64_t max_tiles, double cut, int32_t cap, int32_t* pairs, int32_t* pair_count,
+                             int64_t max_pairs, int32_t* dense, int32_t* dense_count, hipStream_t s) {
+  hipLaunchKernelGGL(zero_two, dim3(1), dim3(64), 0, s, pair_count, dense_count);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || max_tiles <= 0) return e;
+  const int64_t blocks = max_tiles < 8192 ? max_tiles : 8192;  // grid-stride over the listed tiles
+  hipLaunchKernelGGL(flag_pairs_kernel, dim3(unsigned(blocks)), dim3(256), 0, s, K, N, ldk, tiles, tile_count,
+                     max_tiles, cut, cap, pairs, pair_count, max_pairs, dense, dense_count);
   return hipGetLastError();
 }
 

@@ -309,6 +309,27 @@ qsvm_status qsvm_surrogate_gram_log(const void* X16, int32_t d_in, const void* E
                  what);
 }
 
+qsvm_status qsvm_flag_pairs(const double* K, int64_t N, int64_t ldk, const int32_t* tiles, const int32_t* tile_count,
+                            int64_t max_tiles, double cut, int32_t cap_per_tile, int32_t* pairs, int32_t* pair_count,
+                            int64_t max_pairs, int32_t* dense_tiles, int32_t* dense_count, void* stream) {
+  QSVM_TRACE_RANGE("qsvm_flag_pairs");
+  const char* what = "qsvm_flag_pairs";
+  if (!K || !tiles || !tile_count || !pairs || !pair_count || !dense_tiles || !dense_count)
+    return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_flag_pairs: NULL pointer");
+  if (N < 1 || N > INT32_MAX || ldk < N)
+    return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_flag_pairs: need 1 <= N < 2^31 and ldk >= N");
+  if (max_tiles < 0 || max_tiles > INT32_MAX || max_pairs < 0 || max_pairs > INT32_MAX)
+    return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_flag_pairs: max_tiles and max_pairs must lie in [0, 2^31)");
+  if (cap_per_tile < 0 || cap_per_tile > 4096)
+    return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_flag_pairs: cap_per_tile outside [0, 4096]");
+  if (max_tiles * int64_t(cap_per_tile) > INT32_MAX)
+    return api_fail(QSVM_ERR_INVALID_ARG, "qsvm_flag_pairs: max_tiles * cap_per_tile must stay below 2^31");
+  if (qsvm::api_injected_failure()) return injected(what);
+  return api_hip(qsvm::launch_flag_pairs(K, N, ldk, tiles, tile_count, max_tiles, cut, cap_per_tile, pairs, pair_count,
+                                         max_pairs, dense_tiles, dense_count, static_cast<hipStream_t>(stream)),
+                 what);
+}
+
 qsvm_status qsvm_flag_tiles(const float* tile_max, int32_t T, float tau, int32_t* tile_list, int32_t* count,
                             void* stream) {
   QSVM_TRACE_RANGE("qsvm_flag_tiles");

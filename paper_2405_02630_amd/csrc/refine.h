@@ -28,9 +28,14 @@ __host__ __device__ inline double auto_refine_threshold(int32_t n) {
 // After a sweep launch over the tiles of `a` (at most kMaxGridBlocks tiles):
 // clear *count, list the tiles above `thresh` (list holds launch_tiles(a)
 // entries) and recompute their pairs in FP64 with a grid of at most
-// `resident_blocks` blocks.  reps 1..4.
+// `resident_blocks` blocks.  reps 1..6.
 hipError_t launch_refine(const SweepArgs& a, int32_t reps, double thresh, uint32_t* list, uint32_t* count,
                          int64_t resident_blocks, hipStream_t stream);
+// FP64 entries of the pairs of a device-resident list (int32 (i, j) pairs,
+// *count of them, clamped to [0, max_pairs]; invalid entries skipped) of the
+// symmetric Gram described by `a`, with a grid of at most resident_blocks.
+hipError_t launch_pairs_fp64(const SweepArgs& a, int32_t reps, const int32_t* pairs, const int32_t* count,
+                             int64_t max_pairs, int64_t resident_blocks, hipStream_t stream);
 // Blocks of the refinement kernel for `reps` resident on the current device.
 hipError_t refine_resident_blocks(int32_t reps, int64_t* out);
 

@@ -205,18 +205,63 @@ refine_scan_kernel(SweepArgs a, double thresh, uint32_t* __restrict__ list, uint
   }
 }
 
+// FP64 sweep of one pair per lane, (i, j) per lane; every lane of the wave
+// takes part (lanes with comp = false compute a clamped pair and store
+// nothing), so the caller keeps the whole wave in the call.
+template <int R>
+__device__ __forceinline__ void fp64_pair_lanes(const SweepArgs& a, int64_t i, int64_t j, bool comp) {
+  constexpr int M = DLayout<R>::M;
+  const float4* __restrict__ gA = a.gen_a;
+  const float4* __restrict__ gB = a.gen_b;
+  const float4* __restrict__ lA = a.gen_a + int64_t(a.n) * a.Na;  // Section L follows Section G
+  const float4* __restrict__ lB = a.gen_b + int64_t(a.n) * a.Nb;
+  const int64_t ic = (i >= 0 && i < a.Na) ? i : a.Na - 1;  // loads of idle lanes stay in bounds
+  const int64_t jc = (j >= 0 && j < a.Nb) ? j : a.Nb - 1;
+  double2 v[M];
+  dinit_env<R>(v);
+  int32_t acc = 0;
+  int countdown = a.renorm_every;
+  auto step = [&](const Gen64& cx, const Gen64& cy) {
+    dsite_step<R>(v, cx, cy);
+    if (--countdown == 0) {
+      acc += drenorm(v);
+      countdown = a.renorm_every;
+    }
+  };
+  // generators of site k (clamped to the last site, so a prefetch past the
+  // end stays in bounds); two sites per iteration with ping-pong registers
+  // so each site's loads are issued one site ahead
+  auto load = [&](int k, Gen64& cx, Gen64& cy) {
+    const int64_t kc = (k < a.n) ? k : a.n - 1;
+    cx = gen64(gA, lA, kc * a.Na + ic);
+    cy = gen64(gB, lB, kc * a.Nb + jc);
+  };
+  if (a.n > 1) {
+    Gen64 cxA, cyA, cxB, cyB;
+    load(1, cxA, cyA);
+    int k = 1;
+    for (; k + 1 < a.n; k += 2) {
+      load(k + 1, cxB, cyB);
+      step(cxA, cyA);
+      load(k + 2, cxA, cyA);
+      step(cxB, cyB);
+    }
+    if (k < a.n) step(cxA, cyA);  // last site when n - 1 is odd
+  }
+  if (comp) {
+    const Gen64 gx = gen64(gA, lA, ic), gy = gen64(gB, lB, jc);
+    const double s2 = dclosure<R>(v, gx.ar, gx.ai, gy.ar, gy.ai);
+    store_entry(a, i, j, s2, 2 * (acc - R * a.n));
+  }
+}
+
 // Each wave takes items (listed tile, ket point of the tile) and recomputes
 // that ket point against the tile's 64 bra points in FP64.
 template <int R>
 __global__ void __launch_bounds__(256)
 refine_kernel(SweepArgs a, double thresh, const uint32_t* __restrict__ list, const uint32_t* __restrict__ count) {
-  constexpr int M = DLayout<R>::M;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const float4* __restrict__ gA = a.gen_a;
-  const float4* __restrict__ gB = a.gen_b;
-  const float4* __restrict__ lA = a.gen_a + int64_t(a.n) * a.Na;  // Section L follows Section G
-  const float4* __restrict__ lB = a.gen_b + int64_t(a.n) * a.Nb;
   const uint64_t items = uint64_t(*count) * kTile;
   for (uint64_t it = uint64_t(blockIdx.x) * 4 + wave; it < items; it += uint64_t(gridDim.x) * 4) {  // wave-uniform
     int32_t ti, tj;
@@ -228,44 +273,50 @@ refine_kernel(SweepArgs a, double thresh, const uint32_t* __restrict__ list, con
     // of them skips the item
     const bool comp = pair_computed(a, i, j) && a.K[i * a.ldk + j] > thresh;
     if (!__builtin_amdgcn_ballot_w64(comp)) continue;
-    const int64_t ic = (i < a.Na) ? i : a.Na - 1;  // loads of idle lanes stay in bounds
-    const int64_t jc = (j < a.Nb) ? j : a.Nb - 1;
-    double2 v[M];
-    dinit_env<R>(v);
-    int32_t acc = 0;
-    int countdown = a.renorm_every;
-    auto step = [&](const Gen64& cx, const Gen64& cy) {
-      dsite_step<R>(v, cx, cy);
-      if (--countdown == 0) {
-        acc += drenorm(v);
-        countdown = a.renorm_every;
-      }
-    };
-    // generators of site k (clamped to the last site, so a prefetch past the
-    // end stays in bounds); two sites per iteration with ping-pong registers
-    // so each site's loads are issued one site ahead
-    auto load = [&](int k, Gen64& cx, Gen64& cy) {
-      const int64_t kc = (k < a.n) ? k : a.n - 1;
-      cx = gen64(gA, lA, kc * a.Na + ic);
-      cy = gen64(gB, lB, kc * a.Nb + jc);
-    };
-    if (a.n > 1) {
-      Gen64 cxA, cyA, cxB, cyB;
-      load(1, cxA, cyA);
-      int k = 1;
-      for (; k + 1 < a.n; k += 2) {
-        load(k + 1, cxB, cyB);
-        step(cxA, cyA);
-        load(k + 2, cxA, cyA);
-        step(cxB, cyB);
-      }
-      if (k < a.n) step(cxA, cyA);  // last site when n - 1 is odd
-    }
-    if (comp) {
-      const Gen64 gx = gen64(gA, lA, ic), gy = gen64(gB, lB, jc);
-      const double s2 = dclosure<R>(v, gx.ar, gx.ai, gy.ar, gy.ai);
-      store_entry(a, i, j, s2, 2 * (acc - R * a.n));
-    }
+    fp64_pair_lanes<R>(a, i, j, comp);
+  }
+}
+
+// Pair i <= j of list entry p (a symmetric Gram's upper triangle; the pair
+// is swapped if given the other way round); false for entries past the
+// count, invalid indices (e.g. -1 placeholders) and pairs the Gram does not
+// compute (the assigned diagonal).
+__device__ __forceinline__ bool listed_pair(const SweepArgs& a, const int32_t* __restrict__ pairs, int64_t count,
+                                            int64_t p, int64_t& i, int64_t& j) {
+  i = 0;
+  j = 0;
+  if (p >= count) return false;
+  int64_t x = pairs[2 * p], y = pairs[2 * p + 1];
+  if (x < 0 || y < 0 || x >= a.Na || y >= a.Nb) return false;
+  if (x > y) {
+    const int64_t t = x;
+    x = y;
+    y = t;
+  }
+  i = x;
+  j = y;
+  return pair_computed(a, i, j);
+}
+
+__device__ __forceinline__ int64_t listed_count(const int32_t* __restrict__ count, int64_t max_pairs) {
+  const int64_t c = *count;
+  return c < 0 ? 0 : (c < max_pairs ? c : max_pairs);
+}
+
+// FP64 entries of a device-resident pair list (reps <= 3): one pair per lane,
+// waves striding over the list.
+template <int R>
+__global__ void __launch_bounds__(256)
+pairs_fp64_kernel(SweepArgs a, const int32_t* __restrict__ pairs, const int32_t* __restrict__ count,
+                  int64_t max_pairs) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t n = listed_count(count, max_pairs);
+  for (int64_t base = (int64_t(blockIdx.x) * 4 + wave) * 64; base < n; base += int64_t(gridDim.x) * 256) {
+    int64_t i, j;
+    const bool comp = listed_pair(a, pairs, n, base + lane, i, j);
+    if (!__builtin_amdgcn_ballot_w64(comp)) continue;
+    fp64_pair_lanes<R>(a, i, j, comp);
   }
 }
 
@@ -340,18 +391,93 @@ struct WAxes {
   }
 };
 
+// FP64 sweep of one pair per wave (reps >= 4), the pair wave-uniform.
 template <int R>
-__global__ void __launch_bounds__(256)
-refine_wave_kernel(SweepArgs a, double thresh, const uint32_t* __restrict__ list, const uint32_t* __restrict__ count) {
+__device__ __forceinline__ void fp64_pair_wave(const SweepArgs& a, int64_t i, int64_t j) {
   using W = WLayout<R>;
   constexpr int E = W::E;
   constexpr int LOWMASK = (1 << (R - 1)) - 1;
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
   const float4* __restrict__ gA = a.gen_a;
   const float4* __restrict__ gB = a.gen_b;
   const float4* __restrict__ lA = a.gen_a + int64_t(a.n) * a.Na;  // Section L follows Section G
   const float4* __restrict__ lB = a.gen_b + int64_t(a.n) * a.Nb;
+  double2 v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int q = lane | (e << 6);
+    const int s = (q >> W::S) & 1;
+    const int par = dcol_sign_parity<R>(q & LOWMASK, s) ^ dcol_sign_parity<R>((q >> (R - 1)) & LOWMASK, s);
+    v[e] = make_double2(par ? -1.0 : 1.0, 0.0);
+  }
+  int32_t acc = 0;
+  int countdown = a.renorm_every;
+  for (int k = 1; k < a.n; ++k) {
+    const Gen64 cx = gen64(gA, lA, int64_t(k) * a.Na + i);
+    const Gen64 cy = gen64(gB, lB, int64_t(k) * a.Nb + j);
+    WAxes<R, 1>::ket(v, lane, cx);
+    WAxes<R, 1>::bra(v, lane, cy);
+    // shared bit: a_x conj(a_y), b_x conj(b_y); sign bits ket and bra l = R-1
+    const double asr = fma(cx.ar, cy.ar, cx.ai * cy.ai);
+    const double asi = fma(cx.ai, cy.ar, -(cx.ar * cy.ai));
+    const double bsr = fma(cx.br, cy.br, cx.bi * cy.bi);
+    const double bsi = fma(cx.bi, cy.br, -(cx.br * cy.bi));
+    wave_axis<R, W::S, W::ket_bit(R - 1), W::bra_bit(R - 1)>(v, lane, asr, asi, bsr, bsi);
+    if (--countdown == 0) {
+      double m = 0.0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) m = fmax(m, fmax(fabs(v[e].x), fabs(v[e].y)));
+      for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+      int ex = 0;
+      (void)frexp(m, &ex);
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = make_double2(ldexp(v[e].x, -ex), ldexp(v[e].y, -ex));
+      acc += ex;
+      countdown = a.renorm_every;
+    }
+  }
+  // closure: sum over the wave of g_x^|c| conj(g_y)^|c'| v[q]
+  const Gen64 gx = gen64(gA, lA, i), gy = gen64(gB, lB, j);
+  double pxr[R + 1], pxi[R + 1], pyr[R + 1], pyi[R + 1];
+  pxr[0] = 1.0; pxi[0] = 0.0; pyr[0] = 1.0; pyi[0] = 0.0;
+  const double gyi = -gy.ai;  // conj(g_y)
+#pragma unroll
+  for (int m = 1; m <= R; ++m) {
+    pxr[m] = fma(pxr[m - 1], gx.ar, -(pxi[m - 1] * gx.ai));
+    pxi[m] = fma(pxr[m - 1], gx.ai, pxi[m - 1] * gx.ar);
+    pyr[m] = fma(pyr[m - 1], gy.ar, -(pyi[m - 1] * gyi));
+    pyi[m] = fma(pyr[m - 1], gyi, pyi[m - 1] * gy.ar);
+  }
+  double sr = 0.0, si = 0.0;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int q = lane | (e << 6);
+    const int s = (q >> W::S) & 1;
+    const int hk = __builtin_popcount(q & LOWMASK) + s;
+    const int hb = __builtin_popcount((q >> (R - 1)) & LOWMASK) + s;
+    double wr = 0.0, wi = 0.0;
+#pragma unroll
+    for (int x = 0; x <= R; ++x)  // select the powers without dynamic register indexing
+#pragma unroll
+      for (int y = 0; y <= R; ++y)
+        if (x == hk && y == hb) {
+          wr = fma(pxr[x], pyr[y], -(pxi[x] * pyi[y]));
+          wi = fma(pxr[x], pyi[y], pxi[x] * pyr[y]);
+        }
+    sr = fma(wr, v[e].x, fma(-wi, v[e].y, sr));
+    si = fma(wr, v[e].y, fma(wi, v[e].x, si));
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    sr += __shfl_xor(sr, off, 64);
+    si += __shfl_xor(si, off, 64);
+  }
+  if (lane == 0) store_entry(a, i, j, fma(sr, sr, si * si), 2 * (acc - R * a.n));
+}
+
+template <int R>
+__global__ void __launch_bounds__(256)
+refine_wave_kernel(SweepArgs a, double thresh, const uint32_t* __restrict__ list, const uint32_t* __restrict__ count) {
+  const int wave = threadIdx.x >> 6;
   const uint64_t items = uint64_t(*count) * (kTile * kTile);
   for (uint64_t it = uint64_t(blockIdx.x) * 4 + wave; it < items; it += uint64_t(gridDim.x) * 4) {  // wave-uniform
     int32_t ti, tj;
@@ -360,80 +486,45 @@ refine_wave_kernel(SweepArgs a, double thresh, const uint32_t* __restrict__ list
     const int64_t i = int64_t(ti) * kTile + pr / kTile, j = int64_t(tj) * kTile + pr % kTile;
     // the same pair in every lane; only entries above the threshold
     if (!pair_computed(a, i, j) || !(a.K[i * a.ldk + j] > thresh)) continue;
-    double2 v[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int q = lane | (e << 6);
-      const int s = (q >> W::S) & 1;
-      const int par = dcol_sign_parity<R>(q & LOWMASK, s) ^ dcol_sign_parity<R>((q >> (R - 1)) & LOWMASK, s);
-      v[e] = make_double2(par ? -1.0 : 1.0, 0.0);
-    }
-    int32_t acc = 0;
-    int countdown = a.renorm_every;
-    for (int k = 1; k < a.n; ++k) {
-      const Gen64 cx = gen64(gA, lA, int64_t(k) * a.Na + i);
-      const Gen64 cy = gen64(gB, lB, int64_t(k) * a.Nb + j);
-      WAxes<R, 1>::ket(v, lane, cx);
-      WAxes<R, 1>::bra(v, lane, cy);
-      // shared bit: a_x conj(a_y), b_x conj(b_y); sign bits ket and bra l = R-1
-      const double asr = fma(cx.ar, cy.ar, cx.ai * cy.ai);
-      const double asi = fma(cx.ai, cy.ar, -(cx.ar * cy.ai));
-      const double bsr = fma(cx.br, cy.br, cx.bi * cy.bi);
-      const double bsi = fma(cx.bi, cy.br, -(cx.br * cy.bi));
-      wave_axis<R, W::S, W::ket_bit(R - 1), W::bra_bit(R - 1)>(v, lane, asr, asi, bsr, bsi);
-      if (--countdown == 0) {
-        double m = 0.0;
-#pragma unroll
-        for (int e = 0; e < E; ++e) m = fmax(m, fmax(fabs(v[e].x), fabs(v[e].y)));
-        for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
-        int ex = 0;
-        (void)frexp(m, &ex);
-#pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = make_double2(ldexp(v[e].x, -ex), ldexp(v[e].y, -ex));
-        acc += ex;
-        countdown = a.renorm_every;
-      }
-    }
-    // closure: sum over the wave of g_x^|c| conj(g_y)^|c'| v[q]
-    const Gen64 gx = gen64(gA, lA, i), gy = gen64(gB, lB, j);
-    double pxr[R + 1], pxi[R + 1], pyr[R + 1], pyi[R + 1];
-    pxr[0] = 1.0; pxi[0] = 0.0; pyr[0] = 1.0; pyi[0] = 0.0;
-    const double gyi = -gy.ai;  // conj(g_y)
-#pragma unroll
-    for (int m = 1; m <= R; ++m) {
-      pxr[m] = fma(pxr[m - 1], gx.ar, -(pxi[m - 1] * gx.ai));
-      pxi[m] = fma(pxr[m - 1], gx.ai, pxi[m - 1] * gx.ar);
-      pyr[m] = fma(pyr[m - 1], gy.ar, -(pyi[m - 1] * gyi));
-      pyi[m] = fma(pyr[m - 1], gyi, pyi[m - 1] * gy.ar);
-    }
-    double sr = 0.0, si = 0.0;
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int q = lane | (e << 6);
-      const int s = (q >> W::S) & 1;
-      const int hk = __builtin_popcount(q & LOWMASK) + s;
-      const int hb = __builtin_popcount((q >> (R - 1)) & LOWMASK) + s;
-      double wr = 0.0, wi = 0.0;
-#pragma unroll
-      for (int x = 0; x <= R; ++x)  // select the powers without dynamic register indexing
-#pragma unroll
-        for (int y = 0; y <= R; ++y)
-          if (x == hk && y == hb) {
-            wr = fma(pxr[x], pyr[y], -(pxi[x] * pyi[y]));
-            wi = fma(pxr[x], pyi[y], pxi[x] * pyr[y]);
-          }
-      sr = fma(wr, v[e].x, fma(-wi, v[e].y, sr));
-      si = fma(wr, v[e].y, fma(wi, v[e].x, si));
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-      sr += __shfl_xor(sr, off, 64);
-      si += __shfl_xor(si, off, 64);
-    }
-    if (lane == 0) store_entry(a, i, j, fma(sr, sr, si * si), 2 * (acc - R * a.n));
+    fp64_pair_wave<R>(a, i, j);
+  }
+}
+
+// FP64 entries of a device-resident pair list (reps >= 4): one pair per wave.
+template <int R>
+__global__ void __launch_bounds__(256)
+pairs_fp64_wave_kernel(SweepArgs a, const int32_t* __restrict__ pairs, const int32_t* __restrict__ count,
+                       int64_t max_pairs) {
+  const int wave = threadIdx.x >> 6;
+  const int64_t n = listed_count(count, max_pairs);
+  for (int64_t p = int64_t(blockIdx.x) * 4 + wave; p < n; p += int64_t(gridDim.x) * 4) {  // wave-uniform
+    int64_t i, j;
+    if (!listed_pair(a, pairs, n, p, i, j)) continue;
+    fp64_pair_wave<R>(a, i, j);
   }
 }
 
 }  // namespace
+
+hipError_t launch_pairs_fp64(const SweepArgs& a, int32_t reps, const int32_t* pairs, const int32_t* count,
+                             int64_t max_pairs, int64_t resident_blocks, hipStream_t stream) {
+  if (reps < 1 || reps > kMaxReps) return hipErrorInvalidValue;
+  if (max_pairs <= 0) return hipSuccess;
+  // one pair per lane (reps <= 3) or per wave, at most the resident blocks
+  int64_t blocks = (reps >= 4) ? (max_pairs + 3) / 4 : (max_pairs + 255) / 256;
+  if (blocks > resident_blocks) blocks = resident_blocks;
+  if (blocks < 1) blocks = 1;
+  const dim3 grid{unsigned(blocks)};
+  switch (reps) {
+    case 1: hipLaunchKernelGGL(pairs_fp64_kernel<1>, grid, dim3(256), 0, stream, a, pairs, count, max_pairs); break;
+    case 2: hipLaunchKernelGGL(pairs_fp64_kernel<2>, grid, dim3(256), 0, stream, a, pairs, count, max_pairs); break;
+    case 3: hipLaunchKernelGGL(pairs_fp64_kernel<3>, grid, dim3(256), 0, stream, a, pairs, count, max_pairs); break;
+    case 4: hipLaunchKernelGGL(pairs_fp64_wave_kernel<4>, grid, dim3(256), 0, stream, a, pairs, count, max_pairs); break;
+    case 5: hipLaunchKernelGGL(pairs_fp64_wave_kernel<5>, grid, dim3(256), 0, stream, a, pairs, count, max_pairs); break;
+    default: hipLaunchKernelGGL(pairs_fp64_wave_kernel<6>, grid, dim3(256), 0, stream, a, pairs, count, max_pairs); break;
+  }
+  return hipGetLastError();
+}
 
 hipError_t launch_refine(const SweepArgs& a, int32_t reps, double thresh, uint32_t* list, uint32_t* count,
                          int64_t resident_blocks, hipStream_t stream) {

@@ -157,6 +157,8 @@ def load_library(path: str = LIB_PATH):
     lib.qsvm_gram_sym_tiles.restype = i32
     lib.qsvm_gram_sym_tiles_dev.argtypes = [vp, i64, i32, i32, vp, vp, i64, vp, i64, P(GramOpts), vp]
     lib.qsvm_gram_sym_tiles_dev.restype = i32
+    lib.qsvm_gram_sym_pairs_dev.argtypes = [vp, i64, i32, i32, vp, vp, i64, vp, i64, P(GramOpts), vp]
+    lib.qsvm_gram_sym_pairs_dev.restype = i32
     lib.qsvm_gather_features.argtypes = [vp, i64, i32, vp, i64, i32, vp, vp]
     lib.qsvm_gather_features.restype = i32
     lib.qsvm_mlp_forward.argtypes = [P(Mlp), vp, i64, P(MlpActs), vp]
@@ -177,6 +179,8 @@ def load_library(path: str = LIB_PATH):
     lib.qsvm_surrogate_gram.restype = i32
     lib.qsvm_flag_tiles.argtypes = [vp, i32, f32, vp, vp, vp]
     lib.qsvm_flag_tiles.restype = i32
+    lib.qsvm_flag_pairs.argtypes = [vp, i64, i64, vp, vp, i64, ctypes.c_double, i32, vp, vp, i64, vp, vp, vp]
+    lib.qsvm_flag_pairs.restype = i32
     lib.qsvm_autotune.argtypes = [i32, i32, i64, vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float), i32]
     lib.qsvm_sv_bytes.argtypes = [i64, i32]
     lib.qsvm_sv_bytes.restype = ctypes.c_size_t
@@ -558,6 +562,17 @@ def qsvm_gram_sym_tiles_dev(mps: MPS, tiles, tile_count, max_tiles: int, K, *, l
     return K
 
 
+def qsvm_gram_sym_pairs_dev(mps: MPS, pairs, pair_count, max_pairs: int, K, *, log_k=None, renorm_every: int = 0,
+                            diag_mode: int = 0, stream=None):
+    """FP64 entries of the listed pairs (pairs: int32 (i, j) rows; pair_count:
+    1-element int32 tensor read by the kernels, clamped to [0, max_pairs])."""
+    o = _opts(renorm_every, SWEEP_AUTO, diag_mode, None, log_k)
+    _check(load_library().qsvm_gram_sym_pairs_dev(
+        _device_ptr(mps.buf, "mps"), mps.N, mps.n, mps.reps, _p(pairs), _p(pair_count), max_pairs, _p(K),
+        K.stride(0), ctypes.byref(o), _stream_ptr(stream)))
+    return K
+
+
 def qsvm_gather_features(X, idx, d_pad: int, out, stream=None):
     _check(load_library().qsvm_gather_features(
         _p(X), X.shape[0], X.shape[1], _p(idx), idx.shape[0], d_pad, _p(out), _stream_ptr(stream)))
@@ -620,3 +635,13 @@ def qsvm_surrogate_gram(E16, N: int, alpha_beta, K, tile_max, stream=None):
 
 def qsvm_flag_tiles(tile_max, T: int, tau: float, tile_list, count, stream=None):
     _check(load_library().qsvm_flag_tiles(_p(tile_max), T, tau, _p(tile_list), _p(count), _stream_ptr(stream)))
+
+
+def qsvm_flag_pairs(K, N: int, tiles, tile_count, max_tiles: int, cut: float, cap_per_tile: int, pairs, pair_count,
+                    max_pairs: int, dense_tiles, dense_count, stream=None):
+    """Pairs of the listed tiles with K >= cut (at most cap_per_tile per tile,
+    else the tile goes to dense_tiles); counts written to the 1-element int32
+    tensors pair_count and dense_count."""
+    _check(load_library().qsvm_flag_pairs(_p(K), N, K.stride(0), _p(tiles), _p(tile_count), max_tiles, cut,
+                                          cap_per_tile, _p(pairs), _p(pair_count), max_pairs, _p(dense_tiles),
+                                          _p(dense_count), _stream_ptr(stream)))

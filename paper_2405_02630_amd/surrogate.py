@@ -61,6 +61,9 @@ class SurrogateConfig:
     high_log_k: float = -100.0  # training pairs above this ln K form the "close pairs" stratum ...
     high_fraction: float = 0.125  # ... from which this share of every minibatch is drawn
     tau: float = 1e-6           # fallback when a tile's largest K_hat may reach tau
+    pair_cap: int = 256         # exact fallback per pair for tiles with at most this many flagged pairs
+                                # (0: whole flagged tiles only)
+    max_fallback_pairs: int = 1 << 20  # room of the pair list (tiles whose pairs do not fit fall back whole)
     seed: int = 0
 
 
@@ -90,6 +93,7 @@ class Surrogate:
 
         self.cfg = cfg or SurrogateConfig()
         c = self.cfg
+        self.fallback = None  # device counts (pairs, whole tiles) of the last gram() fallback
         self.n = n_features
         self.d_in = _round_up(n_features, 64)
         self.dev = torch.device(device)
@@ -305,14 +309,19 @@ class Surrogate:
         return X16, E16
 
     def gram(self, X, mps: "qsvm.MPS | None", K=None, tau: float | None = None, margin: float | None = None):
-        """Surrogate Gram of the rows of X with exact fallback on flagged tiles.
+        """Surrogate Gram of the rows of X with exact fallback.
 
         A tile is flagged when its largest off-diagonal ln K_hat reaches
-        ln(tau) - margin (tau = 0 flags every tile).  Returns (K, flagged):
+        ln(tau) - margin (tau = 0 flags every tile, which are then recomputed
+        whole); within a flagged tile the pairs with K_hat >= tau exp(-margin)
+        are recomputed exactly, one by one when there are at most
+        cfg.pair_cap of them (FP64), else the whole tile (the exact sweep with
+        its refinement).  Returns (K, flagged):
         flagged is a 1-element device int32 tensor, the number of flagged
-        tiles.  mps (the exact MPS of the same points) feeds the fallback;
-        pass None to skip it.  Nothing here waits for the GPU: the fallback
-        reads the flagged count on the device."""
+        tiles; self.fallback holds the device counts (pairs, whole tiles) of
+        the last call with an MPS.  mps (the exact MPS of the same points)
+        feeds the fallback; pass None to skip it.  Nothing here waits for the
+        GPU: the fallback reads the counts on the device."""
         import torch
 
         tau = self.cfg.tau if tau is None else tau
@@ -326,9 +335,23 @@ class Surrogate:
             K = torch.empty((N, N), dtype=torch.float64, device=self.dev)
         tile_max = torch.empty(T * T, dtype=torch.float32, device=self.dev)
         qsvm.qsvm_surrogate_gram_log(X16, E16, N, self.head.w, K, tile_max)
-        tiles = torch.empty(T * (T + 1), dtype=torch.int32, device=self.dev)
+        n_tiles = T * (T + 1) // 2
+        tiles = torch.empty(2 * n_tiles, dtype=torch.int32, device=self.dev)
         count = torch.empty(1, dtype=torch.int32, device=self.dev)
         qsvm.qsvm_flag_tiles(tile_max, T, max(thresh, -3.0e38), tiles, count)  # clears count first
         if mps is not None:
-            qsvm.qsvm_gram_sym_tiles_dev(mps, tiles, count, T * (T + 1) // 2, K)
+            if self.cfg.pair_cap > 0 and thresh > -math.inf:  # tau <= 0 (every tile) falls back whole
+                cut = 0.0 if thresh == -math.inf else math.exp(thresh)
+                maxp = self.cfg.max_fallback_pairs
+                pairs = torch.empty(2 * maxp, dtype=torch.int32, device=self.dev)
+                dense = torch.empty(2 * n_tiles, dtype=torch.int32, device=self.dev)
+                counts = torch.empty(2, dtype=torch.int32, device=self.dev)  # pairs, dense tiles
+                qsvm.qsvm_flag_pairs(K, N, tiles, count, n_tiles, cut, self.cfg.pair_cap, pairs, counts[0:1], maxp,
+                                     dense, counts[1:2])
+                qsvm.qsvm_gram_sym_tiles_dev(mps, dense, counts[1:2], n_tiles, K)
+                qsvm.qsvm_gram_sym_pairs_dev(mps, pairs, counts[0:1], maxp, K)
+                self.fallback = counts
+            else:
+                qsvm.qsvm_gram_sym_tiles_dev(mps, tiles, count, n_tiles, K)
+                self.fallback = None
         return K, count

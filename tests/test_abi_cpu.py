@@ -593,3 +593,34 @@ def test_roctx_ranges_are_opt_in():
     assert int(st) == qsvm.QSVM_ERR_INVALID_ARG and mapped == "False"
     st, mapped = _roctx_probe("0")
     assert mapped == "False"
+
+
+def test_pair_fallback_validation(lib, no_inject):
+    o = qsvm.GramOpts()
+
+    def pairs_dev(mps=FAKE, N=100, n=8, reps=2, pairs=FAKE2, count=FAKE2, maxp=10, K=FAKE2, ldk=100, opts=None):
+        return lib.qsvm_gram_sym_pairs_dev(mps, N, n, reps, pairs, count, maxp, K, ldk,
+                                           ctypes.byref(opts) if opts is not None else None, None)
+
+    assert pairs_dev(mps=None) == qsvm.QSVM_ERR_INVALID_ARG
+    assert pairs_dev(pairs=None) == qsvm.QSVM_ERR_INVALID_ARG
+    assert pairs_dev(count=None) == qsvm.QSVM_ERR_INVALID_ARG
+    assert pairs_dev(ldk=99) == qsvm.QSVM_ERR_INVALID_ARG
+    assert pairs_dev(maxp=-1) == qsvm.QSVM_ERR_INVALID_ARG
+    assert pairs_dev(reps=7) == qsvm.QSVM_ERR_UNSUPPORTED
+    assert pairs_dev(mps=ctypes.c_void_p(0x100008)) == qsvm.QSVM_ERR_INVALID_ARG
+    o.row_begin, o.row_end = 0, 50
+    assert pairs_dev(opts=o) == qsvm.QSVM_ERR_INVALID_ARG
+    assert pairs_dev(maxp=0) == qsvm.QSVM_OK  # nothing to do, nothing launched
+
+    def flag(K=FAKE, N=100, ldk=100, tiles=FAKE2, tcount=FAKE2, maxt=10, cut=1e-6, cap=64, pairs=FAKE2,
+             pcount=FAKE2, maxp=100, dense=FAKE2, dcount=FAKE2):
+        return lib.qsvm_flag_pairs(K, N, ldk, tiles, tcount, maxt, cut, cap, pairs, pcount, maxp, dense, dcount, None)
+
+    assert flag(K=None) == qsvm.QSVM_ERR_INVALID_ARG
+    assert flag(dense=None) == qsvm.QSVM_ERR_INVALID_ARG
+    assert flag(N=0) == qsvm.QSVM_ERR_INVALID_ARG
+    assert flag(ldk=50) == qsvm.QSVM_ERR_INVALID_ARG
+    assert flag(cap=4097) == qsvm.QSVM_ERR_INVALID_ARG
+    assert flag(maxt=1 << 20, cap=4096) == qsvm.QSVM_ERR_INVALID_ARG  # reservations could pass 2^31
+    assert flag(maxp=-1) == qsvm.QSVM_ERR_INVALID_ARG

@@ -487,3 +487,84 @@ def test_gather_features_matches_torch_conversion(N, n, d_pad):
     ok = (idx >= 0) & (idx < N)
     ref[torch.as_tensor(ok), :n] = torch.as_tensor(Xh[idx[ok]]).to(torch.float32).to(torch.bfloat16)
     assert torch.equal(out.cpu().view(torch.int16), ref.view(torch.int16))
+
+
+@pytest.mark.parametrize("reps", [2, 4])
+def test_gram_sym_pairs_dev_writes_the_fp64_entries(reps):
+    """Listed pairs (either order, duplicates, the diagonal, invalid indices
+    and entries past the count among them) get exactly the FP64 value the
+    refinement writes for that entry; nothing else is touched."""
+    import torch
+
+    N = 150
+    Xh = synth.uniform_features(N, 64, seed=70 + reps)
+    m = encode(Xh, reps)
+    Lref = torch.empty((N, N), dtype=torch.float64, device="cuda:0")
+    Kref = qsvm.qsvm_gram_sym(m, log_k=Lref, refine_above=1e-300)  # every entry refined in FP64
+    rng = np.random.default_rng(5)
+    P = 600
+    pr = rng.integers(0, N, size=(P, 2))
+    pr[:5] = [[3, 3], [7, 2], [2, 7], [149, 0], [0, 149]]  # diagonal, both orders
+    pr[5:8] = [[-1, -1], [4, 150], [-3, 9]]               # skipped on the device
+    pairs = torch.as_tensor(pr.astype(np.int32).ravel(), device="cuda:0")
+    count = torch.tensor([P - 50], dtype=torch.int32, device="cuda:0")  # the last 50 are past the count
+    K = torch.full((N, N), -1.0, dtype=torch.float64, device="cuda:0")
+    L = torch.full((N, N), -1.0, dtype=torch.float64, device="cuda:0")
+    qsvm.qsvm_gram_sym_pairs_dev(m, pairs, count, P, K, log_k=L)
+    torch.cuda.synchronize()
+    Kh, Lh, Kr, Lr = K.cpu().numpy(), L.cpu().numpy(), Kref.cpu().numpy(), Lref.cpu().numpy()
+    want = np.zeros((N, N), dtype=bool)
+    for i, j in pr[:P - 50]:
+        if 0 <= i < N and 0 <= j < N and i != j:
+            want[i, j] = want[j, i] = True
+    assert want.sum() > 900
+    assert np.array_equal(Kh[want], Kr[want]) and np.array_equal(Lh[want], Lr[want])
+    assert np.all(Kh[~want] == -1.0) and np.all(Lh[~want] == -1.0)  # incl. the diagonal (diag_mode 0)
+
+
+def test_flag_pairs_matches_a_host_listing():
+    import torch
+
+    N, T = 200, 4
+    rng = np.random.default_rng(9)
+    Kh = np.exp(-rng.exponential(30.0, size=(N, N)))  # most entries tiny, a few near 1
+    K = torch.as_tensor(Kh, device="cuda:0")
+    cut = 1e-6
+    tl = [(0, 0), (0, 2), (1, 3), (3, 3), (2, 2), (0, 1)]
+    tiles = torch.as_tensor(np.array(tl, dtype=np.int32).ravel(), device="cuda:0")
+    tcount = torch.tensor([len(tl) - 1], dtype=torch.int32, device="cuda:0")  # (0, 1) is past the count
+
+    def host(tmax):
+        pairs, dense = set(), set()
+        for ti, tj in tl[:tmax]:
+            hits = [(i, j) for i in range(64 * ti, min(N, 64 * ti + 64)) for j in range(64 * tj, min(N, 64 * tj + 64))
+                    if j > i and Kh[i, j] >= cut]
+            if len(hits) > cap:
+                dense.add((ti, tj))
+            elif hits:
+                pairs.update(hits)
+        return pairs, dense
+
+    for cap, maxp in [(64, 4096), (4096, 4096), (64, 30)]:
+        pairs = torch.full((2 * maxp,), -7, dtype=torch.int32, device="cuda:0")
+        dense = torch.full((2 * len(tl),), -7, dtype=torch.int32, device="cuda:0")
+        counts = torch.full((2,), 99, dtype=torch.int32, device="cuda:0")
+        qsvm.qsvm_flag_pairs(K, N, tiles, tcount, len(tl), cut, cap, pairs, counts[0:1], maxp, dense, counts[1:2])
+        torch.cuda.synchronize()
+        npair, ndense = (int(v) for v in counts.cpu())
+        P = pairs.cpu().numpy().reshape(-1, 2)[:min(npair, maxp)]
+        D = dense.cpu().numpy().reshape(-1, 2)[:ndense]
+        got_pairs = {(int(i), int(j)) for i, j in P if i >= 0}
+        got_dense = {(int(a), int(b)) for a, b in D}
+        want_pairs, want_dense = host(len(tl) - 1)
+        if maxp >= 4096:
+            assert got_pairs == want_pairs and got_dense == want_dense
+            assert npair == len(want_pairs) and all(i >= 0 for i, _ in P)
+        else:
+            # the pair list overflows: tiles that did not fit fall back whole,
+            # their reserved slots hold (-1, -1); every flagged pair is covered
+            assert got_pairs <= want_pairs and want_dense <= got_dense
+            covered = got_pairs | {(i, j) for (ti, tj) in got_dense for (i, j) in want_pairs
+                                   if i // 64 == ti and j // 64 == tj}
+            assert covered == want_pairs
+            assert all((i >= 0) == (j >= 0) for i, j in P)
