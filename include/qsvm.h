@@ -583,9 +583,11 @@ qsvm_status qsvm_surrogate_gram(const void* E16, int64_t N, int64_t N_pad, int32
  * d % 32 == 0), K[i][i] = 1, K row stride
  * ldk >= N.  The squared distances come from the BF16 inner products
  * (FP32 accumulation on the matrix cores) and the rows' squared norms;
- * ln K_hat is formed in FP32.  tile_max receives per 64 x 64 tile
- * ((N_pad/64)^2 floats, row-major) the largest off-diagonal ln K_hat (-inf for
- * none), for qsvm_flag_tiles with a threshold in the log domain. */
+ * ln K_hat is formed in FP32 once per pair (K is exactly symmetric).
+ * tile_max receives per 64 x 64 tile ((N_pad/64)^2 floats, row-major) the
+ * largest off-diagonal ln K_hat (-inf for none), for qsvm_flag_tiles with a
+ * threshold in the log domain.  N_pad <= 2^19; N_pad floats of workspace are
+ * taken stream-ordered (hipMallocAsync / hipFreeAsync on `stream`). */
 qsvm_status qsvm_surrogate_gram_log(const void* X16, int32_t d_in, const void* E16, int32_t d, int64_t N, int64_t N_pad,
                                     const float* head, double* K, int64_t ldk, float* tile_max, void* stream);
 

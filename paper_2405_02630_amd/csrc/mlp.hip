@@ -455,124 +455,268 @@ sigmoid_gram_kernel(const uint16_t* __restrict__ E, int64_t N_pad, int32_t d, co
   }
 }
 
-// Log-domain surrogate Gram on the embedding [x, f(x)] (two BF16 segments:
-// the gathered inputs X16, d_in wide, and the MLP output E16, d wide):
+// Squared norms of the rows of z = [X16 row, E row] (FP32 sums of the squares
+// of the BF16 values), one wave per row.
+__global__ void __launch_bounds__(256) sat_row_norms(const uint16_t* __restrict__ X16, int32_t d_in,
+                                                     const uint16_t* __restrict__ E, int32_t d, int64_t N_pad,
+                                                     float* __restrict__ norms) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (row >= N_pad) return;
+  float acc = 0.0f;
+  for (int p = lane; p < (d_in + d) / 8; p += 64) {
+    const bool x = p * 8 < d_in;
+    const uint4 q = x ? *reinterpret_cast<const uint4*>(X16 + row * d_in + p * 8)
+                      : *reinterpret_cast<const uint4*>(E + row * d + (p * 8 - d_in));
+    const uint32_t u[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const float lo = bf16_to_f32(uint16_t(u[h])), hi = bf16_to_f32(uint16_t(u[h] >> 16));
+      acc = fmaf(lo, lo, acc);
+      acc = fmaf(hi, hi, acc);
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0) norms[row] = acc;
+}
+
+// expm1(x) for x <= 0 in FP32: the Taylor polynomial to degree 7 above
+// -1/4 (truncation below 2e-9 relative), exp(x) - 1 below (|expm1| >= 0.22
+// there, so the rounding of exp and of the subtraction stays below 1e-6
+// relative).
+__device__ __forceinline__ float expm1_neg(float x) {
+  float p = fmaf(x, 1.0f / 5040.0f, 1.0f / 720.0f);
+  p = fmaf(x, p, 1.0f / 120.0f);
+  p = fmaf(x, p, 1.0f / 24.0f);
+  p = fmaf(x, p, 1.0f / 6.0f);
+  p = fmaf(x, p, 0.5f);
+  p = fmaf(x, p, 1.0f);
+  p *= x;
+  return x > -0.25f ? p : __expf(x) - 1.0f;
+}
+
+// Upper-triangular super-tile `st` (row-major over Is <= Js < S) -> (Is, Js).
+__device__ __forceinline__ void upper_index(int64_t st, int64_t S, int64_t* is, int64_t* js) {
+  const double b = double(2 * S + 1);
+  int64_t i = int64_t((b - sqrt(b * b - 8.0 * double(st))) * 0.5);
+  auto first = [S](int64_t r) { return r * S - r * (r - 1) / 2; };  // index of (r, r)
+  if (i < 0) i = 0;
+  if (i > S - 1) i = S - 1;
+  while (i > 0 && first(i) > st) --i;
+  while (i + 1 < S && first(i + 1) <= st) ++i;
+  *is = i;
+  *js = i + (st - first(i));
+}
+
+// Log-domain surrogate Gram on the embedding z = [x, f(x)] (two BF16
+// segments: the gathered inputs X16, d_in wide, and the MLP output E, d wide):
 //   d2 = ||z_i - z_j||^2 = |z_i|^2 + |z_j|^2 - 2 <z_i, z_j>,
 //   ln K_hat = -c (1 - exp(-s d2)) = c expm1(-s d2),  c = exp(head[0]), s = exp(head[1]),
 // K[i][j] = exp(ln K_hat) (FP64 store of the FP32 value), K[i][i] = 1, and
-// per 64 x 64 tile the largest off-diagonal ln K_hat.  Same blocking as
-// sigmoid_gram_kernel (128 x 64 outputs per block, inner dimension staged
-// through LDS 32 at a time, first through X16, then through E16); each thread
-// also sums the squares of the pieces it stages, so the squared norms of the
-// block's rows come from the same BF16 values the matrix cores multiply.
-__global__ void __launch_bounds__(256)
-sat_log_gram_kernel(const uint16_t* __restrict__ X16, int32_t d_in, const uint16_t* __restrict__ E, int32_t d,
-                    int64_t N_pad, const float* __restrict__ head, double* __restrict__ K, int64_t ldk,
-                    int64_t valid, float* __restrict__ tile_max) {
-  constexpr int GM = 128, GN = 64;
-  __shared__ __attribute__((aligned(16))) uint16_t As[GM * LDS_STRIDE];  // [m][k]
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[GN * LDS_STRIDE];  // [n][k]
-  __shared__ float normA[GM], normB[GN];
-  __shared__ float red[2][4];
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  const int64_t T = N_pad / 64;
-  const int64_t m0 = int64_t(blockIdx.y) * GM, n0 = int64_t(blockIdx.x) * GN;
+// per 64 x 64 tile the largest off-diagonal ln K_hat.
+//
+// Only blocks on or above the diagonal run: 128 x 128 outputs per block, the
+// inner products on the direct-to-LDS pipeline of bf16_gemm_dl (both segments
+// in turn, 32 values per step, double-buffered).  Each value is formed once;
+// a block off the diagonal stores its entries row by row and also their
+// mirror image, each wave passing its 32 x 32 accumulators through LDS so the
+// mirror rows leave as contiguous 256-byte row pieces too.  Blocks are
+// grouped in 8 x 8 super-tiles that each run on one XCD (the 16 operand
+// panels of a super-tile are read from its L2 once instead of once per
+// block).  The row norms come precomputed (sat_row_norms).  Rows past N_pad
+// (an odd tile count) are clamped on load and never stored.
+constexpr int SG_G = 8;       // super-tile side, in 128-row blocks
+constexpr int SG_P = 34;      // doubles per row of a wave's transpose tile (16-byte aligned rows)
+constexpr int SG_LDS = 4 * 32 * SG_P * 8;  // the four waves' transpose tiles, bytes (>= the operand buffers)
+static_assert(SG_LDS >= 2 * 2 * 128 * DL_PR * 16, "transpose tiles reuse the operand buffers");
 
-  f32x16_t acc[2];
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8)))
+sat_log_gram_kernel(const uint16_t* __restrict__ X16, int32_t d_in, const uint16_t* __restrict__ E, int32_t d,
+                    int64_t N_pad, const float* __restrict__ norms, const float* __restrict__ head,
+                    double* __restrict__ K, int64_t ldk, int64_t valid, float* __restrict__ tile_max) {
+  constexpr int MT = 2, NT = 2;
+  constexpr int SA = 128 * DL_PR, SB = SA;  // 16-byte LDS slots per buffer and operand
+  constexpr int CA = SA / 256;              // 64-slot DMA chunks per wave and step, per operand
+  extern __shared__ uint4 lds[];
+  const int t = threadIdx.x, lane = t & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int wm = wave >> 1, wn = wave & 1;
+  const int64_t T2 = (N_pad + 127) / 128, S = (T2 + SG_G - 1) / SG_G;
+  // consecutive blocks of one XCD (hardware ids b, b + 8, ...) take consecutive u
+  const uint32_t nb = gridDim.x;  // 64 per super-tile
+  const uint32_t u = (blockIdx.x & 7u) * (nb >> 3) + (blockIdx.x >> 3);
+  int64_t is, js;
+  upper_index(int64_t(u >> 6), S, &is, &js);
+  const int64_t I = is * SG_G + ((u >> 3) & 7), J = js * SG_G + (u & 7);
+  if (I > J || J >= T2) return;  // the lower half of a diagonal super-tile, or past the last block
+  const int64_t m0 = I * 128, n0 = J * 128;
+
+  // source of the 16 bytes this lane moves in each chunk, per segment
+  const uint16_t* ax[CA];
+  const uint16_t* ae[CA];
+  const uint16_t* bx[CA];
+  const uint16_t* be[CA];
 #pragma unroll
-  for (int w = 0; w < 2; ++w)
-#pragma unroll
-    for (int v = 0; v < 16; ++v) acc[w][v] = 0.0f;
-  float sqA[2] = {0.0f, 0.0f}, sqB = 0.0f;  // squares of this thread's staged pieces
-  const int dtot = d_in + d;
-  for (int k0 = 0; k0 < dtot; k0 += BK) {
-    const bool seg0 = k0 < d_in;
-    const uint16_t* __restrict__ src = seg0 ? X16 : E;
-    const int64_t ld = seg0 ? d_in : d;
-    const int kb = seg0 ? k0 : k0 - d_in;
-    const int kk = (t & 3) * 8;
-#pragma unroll
-    for (int w = 0; w < 2; ++w) {
-      const int m = w * 64 + (t >> 2);
-      const int64_t row = (m0 + m < N_pad) ? m0 + m : N_pad - 1;
-      const uint4 q = *reinterpret_cast<const uint4*>(src + row * ld + kb + kk);
-      *reinterpret_cast<uint4*>(&As[m * LDS_STRIDE + kk]) = q;
-      const uint32_t u[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-      for (int h = 0; h < 4; ++h) {
-        const float lo = bf16_to_f32(uint16_t(u[h])), hi = bf16_to_f32(uint16_t(u[h] >> 16));
-        sqA[w] = fmaf(lo, lo, sqA[w]);
-        sqA[w] = fmaf(hi, hi, sqA[w]);
-      }
-    }
-    {
-      const int n = t >> 2;
-      const uint4 q = *reinterpret_cast<const uint4*>(src + (n0 + n) * ld + kb + kk);
-      *reinterpret_cast<uint4*>(&Bs[n * LDS_STRIDE + kk]) = q;
-      const uint32_t u[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-      for (int h = 0; h < 4; ++h) {
-        const float lo = bf16_to_f32(uint16_t(u[h])), hi = bf16_to_f32(uint16_t(u[h] >> 16));
-        sqB = fmaf(lo, lo, sqB);
-        sqB = fmaf(hi, hi, sqB);
-      }
-    }
-    __syncthreads();
-    const int i = lane & 31, kh = lane >> 5;
-#pragma unroll
-    for (int ks = 0; ks < BK; ks += 16) {
-      const bf16x8_t b = *reinterpret_cast<const bf16x8_t*>(&Bs[(wn * 32 + i) * LDS_STRIDE + ks + kh * 8]);
-#pragma unroll
-      for (int w = 0; w < 2; ++w) {
-        const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(&As[(w * 64 + wm * 32 + i) * LDS_STRIDE + ks + kh * 8]);
-        acc[w] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[w], 0, 0, 0);
-      }
-    }
-    __syncthreads();
+  for (int c = 0; c < CA; ++c) {
+    const int s = (wave + 4 * c) * 64 + lane, row = s / DL_PR;
+    const int piece = ((s % DL_PR) ^ dl_swizzle(row)) * 8;
+    const int64_t ra = (m0 + row < N_pad) ? m0 + row : N_pad - 1;
+    const int64_t rb = (n0 + row < N_pad) ? n0 + row : N_pad - 1;
+    ax[c] = d_in ? X16 + ra * d_in + piece : E;
+    bx[c] = d_in ? X16 + rb * d_in + piece : E;
+    ae[c] = E + ra * d + piece;
+    be[c] = E + rb * d + piece;
   }
-  // the four threads t & ~3 .. t | 3 staged the four quarters of the same rows
+#define QSVM_SAT_ISSUE(buf, k0)                                                                        \
+  do {                                                                                                \
+    const int k_ = (k0);                                                                              \
+    const bool x_ = k_ < d_in;                                                                        \
+    const int ko_ = x_ ? k_ : k_ - d_in;                                                              \
+    _Pragma("unroll") for (int c = 0; c < CA; ++c) {                                                  \
+      const uint16_t* src_ = (x_ ? ax[c] : ae[c]) + ko_;                                              \
+      __builtin_amdgcn_global_load_lds(src_, lds + (buf) * (SA + SB) + (wave + 4 * c) * 64, 16, 0, 0); \
+    }                                                                                                 \
+    _Pragma("unroll") for (int c = 0; c < CA; ++c) {                                                  \
+      const uint16_t* src_ = (x_ ? bx[c] : be[c]) + ko_;                                              \
+      __builtin_amdgcn_global_load_lds(src_, lds + (buf) * (SA + SB) + SA + (wave + 4 * c) * 64, 16, 0, 0); \
+    }                                                                                                 \
+  } while (0)
+
+  const int i = lane & 31, kh = lane >> 5;
+  int oa[MT][2], ob[NT][2];
 #pragma unroll
-  for (int off = 1; off < 4; off <<= 1) {
-    sqA[0] += __shfl_xor(sqA[0], off, 64);
-    sqA[1] += __shfl_xor(sqA[1], off, 64);
-    sqB += __shfl_xor(sqB, off, 64);
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+      const int row = wm * MT * 32 + mt * 32 + i;
+      oa[mt][sl] = row * DL_PR + ((sl * 2 + kh) ^ dl_swizzle(row));
+    }
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+      const int row = wn * NT * 32 + nt * 32 + i;
+      ob[nt][sl] = SA + row * DL_PR + ((sl * 2 + kh) ^ dl_swizzle(row));
+    }
+
+  f32x16_t acc[MT][NT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[mt][nt][v] = 0.0f;
+
+  const int nsteps = (d_in + d) / DL_BK;
+  QSVM_SAT_ISSUE(0, 0);
+  for (int kk = 0; kk < nsteps; ++kk) {
+    __builtin_amdgcn_s_waitcnt(0x0070);  // as in bf16_gemm_dl
+    __builtin_amdgcn_s_barrier();
+    if (kk + 1 < nsteps) QSVM_SAT_ISSUE((kk + 1) & 1, (kk + 1) * DL_BK);
+    const uint4* base = lds + (kk & 1) * (SA + SB);
+    bf16x8_t fa[2][MT], fb[2][NT];
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) fa[sl][mt] = *reinterpret_cast<const bf16x8_t*>(base + oa[mt][sl]);
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) fb[sl][nt] = *reinterpret_cast<const bf16x8_t*>(base + ob[nt][sl]);
+    }
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+          acc[mt][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[sl][mt], fb[sl][nt], acc[mt][nt], 0, 0, 0);
   }
-  if ((t & 3) == 0) {
-    normA[t >> 2] = sqA[0];
-    normA[64 + (t >> 2)] = sqA[1];
-    normB[t >> 2] = sqB;
-  }
-  __syncthreads();
+#undef QSVM_SAT_ISSUE
+  __syncthreads();  // every wave is past its last operand read: the LDS becomes the transpose tiles
 
   const float c = __expf(head[0]), s = __expf(head[1]);
-  const int cl = wn * 32 + (lane & 31);
-  const int64_t col = n0 + cl;
-  const float nb = normB[cl];
-  float tmax[2] = {-INFINITY, -INFINITY};
+  const bool mirror = I != J;
+  double* tw = reinterpret_cast<double*>(lds) + wave * 32 * SG_P;  // this wave's [column][row] tile
+  const int h = lane >> 5;
+  float tmax = -INFINITY;
 #pragma unroll
-  for (int w = 0; w < 2; ++w)
+  for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int rl = w * 64 + wm * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
-      const int64_t r = m0 + rl;
-      if (r < valid && col < valid) {
-        const float d2 = fmaxf(fmaf(-2.0f, acc[w][v], normA[rl] + nb), 0.0f);
-        const float lk = c * expm1f(-s * d2);
-        __builtin_nontemporal_store((r == col) ? 1.0 : double(expf(lk)), &K[r * ldk + col]);
-        if (r != col) tmax[w] = fmaxf(tmax[w], lk);
+    for (int nt = 0; nt < NT; ++nt) {
+      // element v: row r0 + (v / 4) * 8 + h * 4 + v % 4, column c0 + i
+      const int64_t r0 = m0 + wm * 64 + mt * 32, c0 = n0 + wn * 64 + nt * 32;
+      if (r0 >= valid || c0 >= valid) continue;  // wave-uniform; r0, c0 < valid <= N_pad keep the norm reads in range
+      const bool whole = r0 + 32 <= valid && c0 + 32 <= valid;  // no entry past N (wave-uniform)
+      const bool diag = r0 == c0;  // the accumulator holds (r, r) at v with (v / 4) * 8 + h * 4 + v % 4 == i
+      const int64_t col = c0 + i;
+      const float nb = norms[col];
+      float kf[16];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float4 na = *reinterpret_cast<const float4*>(norms + r0 + q * 8 + h * 4);
+        const float nav[4] = {na.x, na.y, na.z, na.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int v = q * 4 + e, rl = q * 8 + h * 4 + e;
+          const float d2 = fmaxf(fmaf(-2.0f, acc[mt][nt][v], nav[e] + nb), 0.0f);
+          const float lk = c * expm1_neg(-s * d2);
+          const bool self = diag && rl == i;
+          const bool ok = whole || (r0 + rl < valid && col < valid);
+          if (ok && !self) tmax = fmaxf(tmax, lk);
+          kf[v] = self ? 1.0f : __expf(lk);
+        }
+      }
+      // rows r0 + h * 4 + e + 8 q, column col
+      double* row = K + (r0 + h * 4) * ldk + col;
+      const int64_t ld8 = 8 * ldk;
+      if (whole) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) __builtin_nontemporal_store(double(kf[q * 4 + e]), row + q * ld8 + e * ldk);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (r0 + q * 8 + h * 4 + e < valid && col < valid)
+              __builtin_nontemporal_store(double(kf[q * 4 + e]), row + q * ld8 + e * ldk);
+      }
+      if (mirror) {
+        // tw[column - c0][row - r0], then rows c0 + j of K from row j of tw
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int e = 0; e < 4; e += 2) {
+            double2 pr;
+            pr.x = double(kf[q * 4 + e]);
+            pr.y = double(kf[q * 4 + e + 1]);
+            *reinterpret_cast<double2*>(&tw[i * SG_P + q * 8 + h * 4 + e]) = pr;
+          }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // row c0 + 2 q + h, column r0 + i
+        double* mrow = K + (c0 + h) * ldk + r0 + i;
+        const int64_t ld2 = 2 * ldk;
+        if (whole) {
+#pragma unroll
+          for (int q = 0; q < 16; ++q) __builtin_nontemporal_store(tw[(q * 2 + h) * SG_P + i], mrow + q * ld2);
+        } else {
+#pragma unroll
+          for (int q = 0; q < 16; ++q)
+            if (c0 + q * 2 + h < valid && r0 + i < valid)
+              __builtin_nontemporal_store(tw[(q * 2 + h) * SG_P + i], mrow + q * ld2);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
     }
-#pragma unroll
-  for (int w = 0; w < 2; ++w) {
-    for (int off = 32; off > 0; off >>= 1) tmax[w] = fmaxf(tmax[w], __shfl_xor(tmax[w], off, 64));
-    if (lane == 0) red[w][wave] = tmax[w];
-  }
-  __syncthreads();
-  if (t < 2) {
-    const int64_t ti = 2 * int64_t(blockIdx.y) + t;
-    if (ti < T)
-      tile_max[ti * T + blockIdx.x] = fmaxf(fmaxf(red[t][0], red[t][1]), fmaxf(red[t][2], red[t][3]));
+  for (int off = 32; off > 0; off >>= 1) tmax = fmaxf(tmax, __shfl_xor(tmax, off, 64));
+  const int64_t T = N_pad / 64, ti = 2 * I + wm, tj = 2 * J + wn;
+  if (lane == 0 && ti < T && tj < T) {
+    tile_max[ti * T + tj] = tmax;
+    if (mirror) tile_max[tj * T + ti] = tmax;
   }
 }
 
@@ -998,11 +1142,13 @@ hipError_t launch_pair_head_log(const uint16_t* X16, int32_t d_in, const float* 
 
 hipError_t launch_sat_log_gram(const uint16_t* X16, int32_t d_in, const uint16_t* E, int32_t d, int64_t N_pad,
                                const float* head, double* K, int64_t ldk, int64_t valid, float* tile_max,
-                               hipStream_t s) {
-  const int64_t T = N_pad / 64;
-  const dim3 grid(unsigned(T), unsigned((T + 1) / 2));
-  hipLaunchKernelGGL(sat_log_gram_kernel, grid, dim3(256), 0, s, X16, d_in, E, d, N_pad, head, K, ldk, valid,
-                     tile_max);
+                               float* norms, hipStream_t s) {
+  const int64_t T2 = (N_pad + 127) / 128, S = (T2 + SG_G - 1) / SG_G;
+  const int64_t blocks = S * (S + 1) / 2 * SG_G * SG_G;
+  if (blocks * 256 >= (int64_t(1) << 32)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(sat_row_norms, dim3(unsigned((N_pad + 3) / 4)), dim3(256), 0, s, X16, d_in, E, d, N_pad, norms);
+  hipLaunchKernelGGL(sat_log_gram_kernel, dim3(unsigned(blocks)), dim3(256), SG_LDS, s, X16, d_in, E, d, N_pad, norms,
+                     head, K, ldk, valid, tile_max);
   return hipGetLastError();
 }
 

@@ -301,12 +301,17 @@ qsvm_status qsvm_surrogate_gram_log(const void* X16, int32_t d_in, const void* E
     return api_fail(QSVM_ERR_INVALID_ARG,
                     "qsvm_surrogate_gram_log: need 1 <= N <= N_pad < N + 64, N_pad % 64 == 0, d_in % 32 == 0, "
                     "d >= 32, d % 32 == 0, ldk >= N");
-  if (N_pad / 64 > 65535)  // launch grid: N_pad / 64 blocks across, half that down
-    return api_fail(QSVM_ERR_UNSUPPORTED, "qsvm_surrogate_gram_log: N_pad above 64 * 65535");
+  if (N_pad > (int64_t(1) << 19))  // one block per 128 x 128 piece of the upper triangle, a 1-D grid
+    return api_fail(QSVM_ERR_UNSUPPORTED, "qsvm_surrogate_gram_log: N_pad above 2^19");
   if (qsvm::api_injected_failure()) return injected(what);
-  return api_hip(qsvm::launch_sat_log_gram(static_cast<const uint16_t*>(X16), d_in, static_cast<const uint16_t*>(E16), d,
-                                           N_pad, head, K, ldk, N, tile_max, static_cast<hipStream_t>(stream)),
-                 what);
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  float* norms = nullptr;  // the rows' squared norms, stream-ordered workspace
+  hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&norms), size_t(N_pad) * sizeof(float), st);
+  if (e != hipSuccess) return api_hip(e, what);
+  e = qsvm::launch_sat_log_gram(static_cast<const uint16_t*>(X16), d_in, static_cast<const uint16_t*>(E16), d, N_pad,
+                                head, K, ldk, N, tile_max, norms, st);
+  const hipError_t f = hipFreeAsync(norms, st);
+  return api_hip(e != hipSuccess ? e : f, what);
 }
 
 qsvm_status qsvm_flag_pairs(const double* K, int64_t N, int64_t ldk, const int32_t* tiles, const int32_t* tile_count,

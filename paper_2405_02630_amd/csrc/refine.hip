@@ -207,8 +207,9 @@ refine_scan_kernel(SweepArgs a, double thresh, uint32_t* __restrict__ list, uint
 
 // FP64 sweep of one pair per lane, (i, j) per lane; every lane of the wave
 // takes part (lanes with comp = false compute a clamped pair and store
-// nothing), so the caller keeps the whole wave in the call.
-template <int R>
+// nothing), so the caller keeps the whole wave in the call.  PF sites per
+// load group (below).
+template <int R, int PF>
 __device__ __forceinline__ void fp64_pair_lanes(const SweepArgs& a, int64_t i, int64_t j, bool comp) {
   constexpr int M = DLayout<R>::M;
   const float4* __restrict__ gA = a.gen_a;
@@ -228,25 +229,46 @@ __device__ __forceinline__ void fp64_pair_lanes(const SweepArgs& a, int64_t i, i
       countdown = a.renorm_every;
     }
   };
-  // generators of site k (clamped to the last site, so a prefetch past the
-  // end stays in bounds); two sites per iteration with ping-pong registers
-  // so each site's loads are issued one site ahead
-  auto load = [&](int k, Gen64& cx, Gen64& cy) {
-    const int64_t kc = (k < a.n) ? k : a.n - 1;
-    cx = gen64(gA, lA, kc * a.Na + ic);
-    cy = gen64(gB, lB, kc * a.Nb + jc);
+  // generators of sites k .. k + PF - 1 as loaded (clamped to the last
+  // site, so a prefetch past the end stays in bounds); two groups of PF sites
+  // alternate, the loads of one group in flight while the other's sites are
+  // swept.  Scattered points (a pair list) miss the caches at every site and
+  // take PF = 4; the bra points of a tile are consecutive and PF = 1 keeps
+  // the registers (and occupancy) of the refinement kernel.
+  struct Raw {
+    float4 xh, xl, yh, yl;
+  };
+  Raw buf[2][PF];
+  auto load = [&](int k0, Raw(&g)[PF]) {
+#pragma unroll
+    for (int d = 0; d < PF; ++d) {
+      const int64_t kc = (k0 + d < a.n) ? k0 + d : a.n - 1;
+      g[d].xh = gA[kc * a.Na + ic];
+      g[d].xl = lA[kc * a.Na + ic];
+      g[d].yh = gB[kc * a.Nb + jc];
+      g[d].yl = lB[kc * a.Nb + jc];
+    }
+  };
+  auto sweep = [&](int k0, const Raw(&g)[PF]) {
+#pragma unroll
+    for (int d = 0; d < PF; ++d) {
+      if (k0 + d >= a.n) break;  // uniform
+      const Gen64 cx = {double(g[d].xh.x) + double(g[d].xl.x), double(g[d].xh.y) + double(g[d].xl.y),
+                        double(g[d].xh.z) + double(g[d].xl.z), double(g[d].xh.w) + double(g[d].xl.w)};
+      const Gen64 cy = {double(g[d].yh.x) + double(g[d].yl.x), double(g[d].yh.y) + double(g[d].yl.y),
+                        double(g[d].yh.z) + double(g[d].yl.z), double(g[d].yh.w) + double(g[d].yl.w)};
+      step(cx, cy);
+    }
   };
   if (a.n > 1) {
-    Gen64 cxA, cyA, cxB, cyB;
-    load(1, cxA, cyA);
-    int k = 1;
-    for (; k + 1 < a.n; k += 2) {
-      load(k + 1, cxB, cyB);
-      step(cxA, cyA);
-      load(k + 2, cxA, cyA);
-      step(cxB, cyB);
+    load(1, buf[0]);
+    for (int k = 1; k < a.n; k += 2 * PF) {
+      load(k + PF, buf[1]);
+      sweep(k, buf[0]);
+      if (k + PF >= a.n) break;
+      load(k + 2 * PF, buf[0]);
+      sweep(k + PF, buf[1]);
     }
-    if (k < a.n) step(cxA, cyA);  // last site when n - 1 is odd
   }
   if (comp) {
     const Gen64 gx = gen64(gA, lA, ic), gy = gen64(gB, lB, jc);
@@ -273,7 +295,7 @@ refine_kernel(SweepArgs a, double thresh, const uint32_t* __restrict__ list, con
     // of them skips the item
     const bool comp = pair_computed(a, i, j) && a.K[i * a.ldk + j] > thresh;
     if (!__builtin_amdgcn_ballot_w64(comp)) continue;
-    fp64_pair_lanes<R>(a, i, j, comp);
+    fp64_pair_lanes<R, 1>(a, i, j, comp);
   }
 }
 
@@ -304,7 +326,11 @@ __device__ __forceinline__ int64_t listed_count(const int32_t* __restrict__ coun
 }
 
 // FP64 entries of a device-resident pair list (reps <= 3): one pair per lane,
-// waves striding over the list.
+// waves striding over the list.  Chunks of 64 pairs go to the blocks in turn
+// (chunk c to block c % gridDim.x, wave c / gridDim.x) so a short list is
+// spread over as many compute units as it has chunks: the generator loads of
+// scattered points are gathers that miss the caches, and the number a
+// compute unit keeps in flight bounds the sweep.
 template <int R>
 __global__ void __launch_bounds__(256)
 pairs_fp64_kernel(SweepArgs a, const int32_t* __restrict__ pairs, const int32_t* __restrict__ count,
@@ -312,11 +338,11 @@ pairs_fp64_kernel(SweepArgs a, const int32_t* __restrict__ pairs, const int32_t*
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int64_t n = listed_count(count, max_pairs);
-  for (int64_t base = (int64_t(blockIdx.x) * 4 + wave) * 64; base < n; base += int64_t(gridDim.x) * 256) {
+  for (int64_t base = (int64_t(wave) * gridDim.x + blockIdx.x) * 64; base < n; base += int64_t(gridDim.x) * 256) {
     int64_t i, j;
     const bool comp = listed_pair(a, pairs, n, base + lane, i, j);
     if (!__builtin_amdgcn_ballot_w64(comp)) continue;
-    fp64_pair_lanes<R>(a, i, j, comp);
+    fp64_pair_lanes<R, 4>(a, i, j, comp);
   }
 }
 
@@ -497,7 +523,8 @@ pairs_fp64_wave_kernel(SweepArgs a, const int32_t* __restrict__ pairs, const int
                        int64_t max_pairs) {
   const int wave = threadIdx.x >> 6;
   const int64_t n = listed_count(count, max_pairs);
-  for (int64_t p = int64_t(blockIdx.x) * 4 + wave; p < n; p += int64_t(gridDim.x) * 4) {  // wave-uniform
+  // pair p to block p % gridDim.x (a short list spread over the compute units)
+  for (int64_t p = int64_t(wave) * gridDim.x + blockIdx.x; p < n; p += int64_t(gridDim.x) * 4) {  // wave-uniform
     int64_t i, j;
     if (!listed_pair(a, pairs, n, p, i, j)) continue;
     fp64_pair_wave<R>(a, i, j);
