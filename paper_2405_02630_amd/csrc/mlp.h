@@ -59,7 +59,7 @@ hipError_t launch_pair_head(const float* E, int64_t P, int32_t d, const float* t
 hipError_t launch_pair_head_log(const uint16_t* X16, int32_t d_in, const float* E, int32_t d, int64_t P,
                                 const float* target, const float* head, float scale, uint16_t* dE16, float* partial,
                                 float* out3, float* pred, hipStream_t s);
-// (norms: N_pad floats of workspace, the rows' squared norms)
+// (norms: N_pad floats of workspace, the rows' squared norms times -s log2(e))
 hipError_t launch_sat_log_gram(const uint16_t* X16, int32_t d_in, const uint16_t* E, int32_t d, int64_t N_pad,
                                const float* head, double* K, int64_t ldk, int64_t valid, float* tile_max,
                                float* norms, hipStream_t s);

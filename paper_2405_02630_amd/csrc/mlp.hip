@@ -456,10 +456,12 @@ sigmoid_gram_kernel(const uint16_t* __restrict__ E, int64_t N_pad, int32_t d, co
 }
 
 // Squared norms of the rows of z = [X16 row, E row] (FP32 sums of the squares
-// of the BF16 values), one wave per row.
+// of the BF16 values), one wave per row, stored as -s log2(e) |z|^2
+// (s = exp(head[1])): the Gram's exponent then adds a row's and a column's
+// value, which is symmetric in the two.
 __global__ void __launch_bounds__(256) sat_row_norms(const uint16_t* __restrict__ X16, int32_t d_in,
                                                      const uint16_t* __restrict__ E, int32_t d, int64_t N_pad,
-                                                     float* __restrict__ norms) {
+                                                     const float* __restrict__ head, float* __restrict__ norms) {
   const int lane = threadIdx.x & 63;
   const int64_t row = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
   if (row >= N_pad) return;
@@ -477,22 +479,22 @@ __global__ void __launch_bounds__(256) sat_row_norms(const uint16_t* __restrict_
     }
   }
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-  if (lane == 0) norms[row] = acc;
+  if (lane == 0) norms[row] = -(__expf(head[1]) * 1.44269504f) * acc;
 }
 
-// expm1(x) for x <= 0 in FP32: the Taylor polynomial to degree 7 above
-// -1/4 (truncation below 2e-9 relative), exp(x) - 1 below (|expm1| >= 0.22
-// there, so the rounding of exp and of the subtraction stays below 1e-6
-// relative).
-__device__ __forceinline__ float expm1_neg(float x) {
-  float p = fmaf(x, 1.0f / 5040.0f, 1.0f / 720.0f);
-  p = fmaf(x, p, 1.0f / 120.0f);
-  p = fmaf(x, p, 1.0f / 24.0f);
-  p = fmaf(x, p, 1.0f / 6.0f);
-  p = fmaf(x, p, 0.5f);
-  p = fmaf(x, p, 1.0f);
-  p *= x;
-  return x > -0.25f ? p : __expf(x) - 1.0f;
+// expm1(t ln 2) for t <= 0 in FP32 (t = x log2 e): the Taylor polynomial of
+// expm1(x) to degree 6, written in t, above x = -1/4 (truncation below 6e-8
+// relative), 2^t - 1 below (|expm1| >= 0.22 there, so the rounding of
+// v_exp_f32 and of the subtraction stays below 4e-7 relative).
+__device__ __forceinline__ float expm1_neg_base2(float t) {
+  // ln2^k / k!, k = 6 .. 1
+  float p = fmaf(t, 1.5403530e-4f, 1.3333558e-3f);
+  p = fmaf(t, p, 9.6181291e-3f);
+  p = fmaf(t, p, 5.5504109e-2f);
+  p = fmaf(t, p, 2.4022651e-1f);
+  p = fmaf(t, p, 6.9314718e-1f);
+  p *= t;
+  return t > -0.36067376f ? p : __builtin_amdgcn_exp2f(t) - 1.0f;
 }
 
 // Upper-triangular super-tile `st` (row-major over Is <= Js < S) -> (Is, Js).
@@ -517,7 +519,11 @@ __device__ __forceinline__ void upper_index(int64_t st, int64_t S, int64_t* is, 
 //
 // Only blocks on or above the diagonal run: 128 x 128 outputs per block, the
 // inner products on the direct-to-LDS pipeline of bf16_gemm_dl (both segments
-// in turn, 32 values per step, double-buffered).  Each value is formed once;
+// in turn, double-buffered, SG_KS 32-deep slices per step).  Alone, this loop
+// runs at 0.37 of the BF16 peak with 32-deep steps and 0.48 with 64-deep ones,
+// but the 64 KB of LDS the latter takes leaves two blocks per compute unit
+// instead of four, too few to overlap one block's stores with another's
+// inner products: the whole kernel measured 5 % slower.  Each value is formed once;
 // a block off the diagonal stores its entries row by row and also their
 // mirror image, each wave passing its 32 x 32 accumulators through LDS so the
 // mirror rows leave as contiguous 256-byte row pieces too.  Blocks are
@@ -527,16 +533,20 @@ __device__ __forceinline__ void upper_index(int64_t st, int64_t S, int64_t* is, 
 // (an odd tile count) are clamped on load and never stored.
 constexpr int SG_G = 8;       // super-tile side, in 128-row blocks
 constexpr int SG_P = 34;      // doubles per row of a wave's transpose tile (16-byte aligned rows)
-constexpr int SG_LDS = 4 * 32 * SG_P * 8;  // the four waves' transpose tiles, bytes (>= the operand buffers)
-static_assert(SG_LDS >= 2 * 2 * 128 * DL_PR * 16, "transpose tiles reuse the operand buffers");
+constexpr int SG_KS = 1;  // 32-deep slices per K step
+constexpr int SG_OPER = 2 * SG_KS * 2 * 128 * DL_PR * 16;  // two buffers of both operands, bytes
+constexpr int SG_TRAN = 4 * 32 * SG_P * 8;  // the four waves' transpose tiles, bytes (reusing the operand buffers)
+constexpr int SG_LDS = SG_OPER > SG_TRAN ? SG_OPER : SG_TRAN;
 
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8)))
 sat_log_gram_kernel(const uint16_t* __restrict__ X16, int32_t d_in, const uint16_t* __restrict__ E, int32_t d,
                     int64_t N_pad, const float* __restrict__ norms, const float* __restrict__ head,
                     double* __restrict__ K, int64_t ldk, int64_t valid, float* __restrict__ tile_max) {
   constexpr int MT = 2, NT = 2;
-  constexpr int SA = 128 * DL_PR, SB = SA;  // 16-byte LDS slots per buffer and operand
-  constexpr int CA = SA / 256;              // 64-slot DMA chunks per wave and step, per operand
+  constexpr int SL = 128 * DL_PR;      // 16-byte LDS slots of one operand's 32-deep slice
+  constexpr int SA = SG_KS * SL;       // of one operand in a buffer
+  constexpr int CA = SA / 256;         // 64-slot DMA chunks per wave and step, per operand (chunk c: slice c / 2)
+  static_assert(CA == 2 * SG_KS, "chunk c of a wave holds slice c / 2");  // (wave + 4 c) / 8 = c / 2
   extern __shared__ uint4 lds[];
   const int t = threadIdx.x, lane = t & 63;
   const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
@@ -550,16 +560,18 @@ sat_log_gram_kernel(const uint16_t* __restrict__ X16, int32_t d_in, const uint16
   const int64_t I = is * SG_G + ((u >> 3) & 7), J = js * SG_G + (u & 7);
   if (I > J || J >= T2) return;  // the lower half of a diagonal super-tile, or past the last block
   const int64_t m0 = I * 128, n0 = J * 128;
+  const int dtot = d_in + d;
 
-  // source of the 16 bytes this lane moves in each chunk, per segment
+  // source of the 16 bytes this lane moves in each chunk, per segment (the
+  // chunk's slice offset is added at issue)
   const uint16_t* ax[CA];
   const uint16_t* ae[CA];
   const uint16_t* bx[CA];
   const uint16_t* be[CA];
 #pragma unroll
   for (int c = 0; c < CA; ++c) {
-    const int s = (wave + 4 * c) * 64 + lane, row = s / DL_PR;
-    const int piece = ((s % DL_PR) ^ dl_swizzle(row)) * 8;
+    const int r = ((wave + 4 * c) * 64 + lane) % SL, row = r / DL_PR;
+    const int piece = ((r % DL_PR) ^ dl_swizzle(row)) * 8;
     const int64_t ra = (m0 + row < N_pad) ? m0 + row : N_pad - 1;
     const int64_t rb = (n0 + row < N_pad) ? n0 + row : N_pad - 1;
     ax[c] = d_in ? X16 + ra * d_in + piece : E;
@@ -567,23 +579,25 @@ sat_log_gram_kernel(const uint16_t* __restrict__ X16, int32_t d_in, const uint16
     ae[c] = E + ra * d + piece;
     be[c] = E + rb * d + piece;
   }
-#define QSVM_SAT_ISSUE(buf, k0)                                                                        \
-  do {                                                                                                \
-    const int k_ = (k0);                                                                              \
-    const bool x_ = k_ < d_in;                                                                        \
-    const int ko_ = x_ ? k_ : k_ - d_in;                                                              \
-    _Pragma("unroll") for (int c = 0; c < CA; ++c) {                                                  \
-      const uint16_t* src_ = (x_ ? ax[c] : ae[c]) + ko_;                                              \
-      __builtin_amdgcn_global_load_lds(src_, lds + (buf) * (SA + SB) + (wave + 4 * c) * 64, 16, 0, 0); \
-    }                                                                                                 \
-    _Pragma("unroll") for (int c = 0; c < CA; ++c) {                                                  \
-      const uint16_t* src_ = (x_ ? bx[c] : be[c]) + ko_;                                              \
-      __builtin_amdgcn_global_load_lds(src_, lds + (buf) * (SA + SB) + SA + (wave + 4 * c) * 64, 16, 0, 0); \
-    }                                                                                                 \
+  // step `st` (inner values 64 st ..) into buffer `buf`; each slice from the
+  // segment holding it (d_in % 32 == 0), a slice past the end not at all
+#define QSVM_SAT_ISSUE(buf, st)                                                                          \
+  do {                                                                                                  \
+    _Pragma("unroll") for (int c = 0; c < CA; ++c) {                                                    \
+      const int k_ = (st) * (SG_KS * DL_BK) + (c >> 1) * DL_BK;                                         \
+      if (k_ < dtot) {                                                                                  \
+        const bool x_ = k_ < d_in;                                                                      \
+        const int ko_ = x_ ? k_ : k_ - d_in;                                                            \
+        const uint16_t* sa_ = (x_ ? ax[c] : ae[c]) + ko_;                                               \
+        __builtin_amdgcn_global_load_lds(sa_, lds + (buf) * (2 * SA) + (wave + 4 * c) * 64, 16, 0, 0);   \
+        const uint16_t* sb_ = (x_ ? bx[c] : be[c]) + ko_;                                               \
+        __builtin_amdgcn_global_load_lds(sb_, lds + (buf) * (2 * SA) + SA + (wave + 4 * c) * 64, 16, 0, 0); \
+      }                                                                                                 \
+    }                                                                                                   \
   } while (0)
 
   const int i = lane & 31, kh = lane >> 5;
-  int oa[MT][2], ob[NT][2];
+  int oa[MT][2], ob[NT][2];  // within a slice
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -607,37 +621,44 @@ sat_log_gram_kernel(const uint16_t* __restrict__ X16, int32_t d_in, const uint16
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[mt][nt][v] = 0.0f;
 
-  const int nsteps = (d_in + d) / DL_BK;
+  const int nsteps = (dtot + SG_KS * DL_BK - 1) / (SG_KS * DL_BK);
   QSVM_SAT_ISSUE(0, 0);
   for (int kk = 0; kk < nsteps; ++kk) {
     __builtin_amdgcn_s_waitcnt(0x0070);  // as in bf16_gemm_dl
     __builtin_amdgcn_s_barrier();
-    if (kk + 1 < nsteps) QSVM_SAT_ISSUE((kk + 1) & 1, (kk + 1) * DL_BK);
-    const uint4* base = lds + (kk & 1) * (SA + SB);
-    bf16x8_t fa[2][MT], fb[2][NT];
+    if (kk + 1 < nsteps) QSVM_SAT_ISSUE((kk + 1) & 1, kk + 1);
+    const uint4* base = lds + (kk & 1) * (2 * SA);
 #pragma unroll
-    for (int sl = 0; sl < 2; ++sl) {
+    for (int ks = 0; ks < SG_KS; ++ks) {
+      if (kk * (SG_KS * DL_BK) + ks * DL_BK >= dtot) break;  // uniform: the last step's missing slice
+      bf16x8_t fa[2][MT], fb[2][NT];
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) fa[sl][mt] = *reinterpret_cast<const bf16x8_t*>(base + oa[mt][sl]);
+      for (int sl = 0; sl < 2; ++sl) {
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) fb[sl][nt] = *reinterpret_cast<const bf16x8_t*>(base + ob[nt][sl]);
+        for (int mt = 0; mt < MT; ++mt) fa[sl][mt] = *reinterpret_cast<const bf16x8_t*>(base + ks * SL + oa[mt][sl]);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) fb[sl][nt] = *reinterpret_cast<const bf16x8_t*>(base + ks * SL + ob[nt][sl]);
+      }
+#pragma unroll
+      for (int sl = 0; sl < 2; ++sl)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt)
+            acc[mt][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[sl][mt], fb[sl][nt], acc[mt][nt], 0, 0, 0);
     }
-#pragma unroll
-    for (int sl = 0; sl < 2; ++sl)
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt)
-          acc[mt][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[sl][mt], fb[sl][nt], acc[mt][nt], 0, 0, 0);
   }
 #undef QSVM_SAT_ISSUE
   __syncthreads();  // every wave is past its last operand read: the LDS becomes the transpose tiles
 
+  // in base 2: t = -s d2 log2(e) = fma(2 s log2(e), acc, n_r + n_c) with the
+  // scaled norms n = -s log2(e) |z|^2, log2 K_hat = c log2(e) expm1(t ln 2)
   const float c = __expf(head[0]), s = __expf(head[1]);
+  const float sl = s * 1.44269504f, cl = c * 1.44269504f, a2 = 2.0f * sl;
   const bool mirror = I != J;
   double* tw = reinterpret_cast<double*>(lds) + wave * 32 * SG_P;  // this wave's [column][row] tile
   const int h = lane >> 5;
-  float tmax = -INFINITY;
+  float tmax = -INFINITY;  // largest off-diagonal log2 K_hat of this wave's 64 x 64 tile
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -648,27 +669,26 @@ sat_log_gram_kernel(const uint16_t* __restrict__ X16, int32_t d_in, const uint16
       const bool whole = r0 + 32 <= valid && c0 + 32 <= valid;  // no entry past N (wave-uniform)
       const bool diag = r0 == c0;  // the accumulator holds (r, r) at v with (v / 4) * 8 + h * 4 + v % 4 == i
       const int64_t col = c0 + i;
-      const float nb = norms[col];
-      float kf[16];
+      const float bn = norms[col];
+      float kf[16], l2[16];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const float4 na = *reinterpret_cast<const float4*>(norms + r0 + q * 8 + h * 4);
         const float nav[4] = {na.x, na.y, na.z, na.w};
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int v = q * 4 + e, rl = q * 8 + h * 4 + e;
-          const float d2 = fmaxf(fmaf(-2.0f, acc[mt][nt][v], nav[e] + nb), 0.0f);
-          const float lk = c * expm1_neg(-s * d2);
-          const bool self = diag && rl == i;
-          const bool ok = whole || (r0 + rl < valid && col < valid);
-          if (ok && !self) tmax = fmaxf(tmax, lk);
-          kf[v] = self ? 1.0f : __expf(lk);
+          const int v = q * 4 + e;
+          const float t = fminf(fmaf(a2, acc[mt][nt][v], nav[e] + bn), 0.0f);
+          l2[v] = cl * expm1_neg_base2(t);
+          kf[v] = __builtin_amdgcn_exp2f(l2[v]);
         }
       }
       // rows r0 + h * 4 + e + 8 q, column col
       double* row = K + (r0 + h * 4) * ldk + col;
       const int64_t ld8 = 8 * ldk;
-      if (whole) {
+      if (whole && !diag) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) tmax = fmaxf(tmax, l2[v]);
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -677,9 +697,15 @@ sat_log_gram_kernel(const uint16_t* __restrict__ X16, int32_t d_in, const uint16
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
-          for (int e = 0; e < 4; ++e)
-            if (r0 + q * 8 + h * 4 + e < valid && col < valid)
-              __builtin_nontemporal_store(double(kf[q * 4 + e]), row + q * ld8 + e * ldk);
+          for (int e = 0; e < 4; ++e) {
+            const int v = q * 4 + e, rl = q * 8 + h * 4 + e;
+            const bool self = diag && rl == i;
+            if (self) kf[v] = 1.0f;
+            if (r0 + rl < valid && col < valid) {
+              if (!self) tmax = fmaxf(tmax, l2[v]);
+              __builtin_nontemporal_store(double(kf[v]), row + q * ld8 + e * ldk);
+            }
+          }
       }
       if (mirror) {
         // tw[column - c0][row - r0], then rows c0 + j of K from row j of tw
@@ -713,6 +739,7 @@ sat_log_gram_kernel(const uint16_t* __restrict__ X16, int32_t d_in, const uint16
       }
     }
   for (int off = 32; off > 0; off >>= 1) tmax = fmaxf(tmax, __shfl_xor(tmax, off, 64));
+  tmax *= 0.693147181f;  // natural log
   const int64_t T = N_pad / 64, ti = 2 * I + wm, tj = 2 * J + wn;
   if (lane == 0 && ti < T && tj < T) {
     tile_max[ti * T + tj] = tmax;
@@ -1146,7 +1173,8 @@ hipError_t launch_sat_log_gram(const uint16_t* X16, int32_t d_in, const uint16_t
   const int64_t T2 = (N_pad + 127) / 128, S = (T2 + SG_G - 1) / SG_G;
   const int64_t blocks = S * (S + 1) / 2 * SG_G * SG_G;
   if (blocks * 256 >= (int64_t(1) << 32)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(sat_row_norms, dim3(unsigned((N_pad + 3) / 4)), dim3(256), 0, s, X16, d_in, E, d, N_pad, norms);
+  hipLaunchKernelGGL(sat_row_norms, dim3(unsigned((N_pad + 3) / 4)), dim3(256), 0, s, X16, d_in, E, d, N_pad, head,
+                     norms);
   hipLaunchKernelGGL(sat_log_gram_kernel, dim3(unsigned(blocks)), dim3(256), SG_LDS, s, X16, d_in, E, d, N_pad, norms,
                      head, K, ldk, valid, tile_max);
   return hipGetLastError();
