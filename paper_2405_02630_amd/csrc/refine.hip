@@ -21,7 +21,9 @@
 // The FP64 sweep is the one-lane butterfly sweep of sweep_butterfly_item.h
 // (same recursion, gauge, sign pattern, renormalisation and closure) with
 // doubles: one pair per lane and one ket point per wave for reps <= 3; at
-// reps >= 4 (128 to 2048 environment entries) one pair per wave.
+// reps >= 4 (128 to 2048 environment entries) one pair per wave.  A pair
+// list (pairs_fp64_group_kernel, reps <= 3) takes one pair per group of 2,
+// 4 or 8 lanes and writes bitwise the one-lane values.
 
 #include "../../include/qsvm.h"
 #include "refine.h"
@@ -325,27 +327,6 @@ __device__ __forceinline__ int64_t listed_count(const int32_t* __restrict__ coun
   return c < 0 ? 0 : (c < max_pairs ? c : max_pairs);
 }
 
-// FP64 entries of a device-resident pair list (reps <= 3): one pair per lane,
-// waves striding over the list.  Chunks of 64 pairs go to the blocks in turn
-// (chunk c to block c % gridDim.x, wave c / gridDim.x) so a short list is
-// spread over as many compute units as it has chunks: the generator loads of
-// scattered points are gathers that miss the caches, and the number a
-// compute unit keeps in flight bounds the sweep.
-template <int R>
-__global__ void __launch_bounds__(256)
-pairs_fp64_kernel(SweepArgs a, const int32_t* __restrict__ pairs, const int32_t* __restrict__ count,
-                  int64_t max_pairs) {
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int64_t n = listed_count(count, max_pairs);
-  for (int64_t base = (int64_t(wave) * gridDim.x + blockIdx.x) * 64; base < n; base += int64_t(gridDim.x) * 256) {
-    int64_t i, j;
-    const bool comp = listed_pair(a, pairs, n, base + lane, i, j);
-    if (!__builtin_amdgcn_ballot_w64(comp)) continue;
-    fp64_pair_lanes<R, 4>(a, i, j, comp);
-  }
-}
-
 // reps >= 4: one pair per wave.  The 2^(2r-1) environment entries q sit
 // E = 2^(2r-7) per lane: lane = bits 0..5 of q, register e = the bits above
 // (ket bits 0..r-2, bra bits r-1..2r-3, shared bit 2r-2, as in the one-lane
@@ -362,16 +343,21 @@ struct WLayout {
   static constexpr int S = 2 * R - 2;
 };
 
-template <int R, int B, int SB1, int SB2>
-__device__ __forceinline__ void wave_axis(double2 (&v)[WLayout<R>::E], int lane, double ar, double ai, double br,
-                                          double bi) {
-  constexpr int E = WLayout<R>::E;
-  if constexpr (B >= 6) {  // register bit
+// Axis on entry bit B of an environment whose entries q sit E per lane:
+// lane bits 0 .. LB - 1 of q are bits of the lane, the bits above index the
+// registers (q = lane % 2^LB + e 2^LB).  A register bit runs as register
+// butterflies; a lane bit B pairs lane l with lane l ^ 2^B: the lane without
+// the bit computes u0 + a u1, the lane with it +-(u0 + b u1), each from its
+// own value and its partner's (__shfl_xor), the same operations as dbfly.
+template <int E, int LB, int B, int SB1, int SB2>
+__device__ __forceinline__ void group_axis(double2 (&v)[E], int lane, double ar, double ai, double br, double bi) {
+  constexpr int LM = (1 << LB) - 1;
+  if constexpr (B >= LB) {  // register bit
 #pragma unroll
     for (int e0 = 0; e0 < E; ++e0) {
-      if (e0 & (1 << (B - 6))) continue;
-      const int e1 = e0 | (1 << (B - 6));
-      const int i0 = lane | (e0 << 6);
+      if (e0 & (1 << (B - LB))) continue;
+      const int e1 = e0 | (1 << (B - LB));
+      const int i0 = (lane & LM) | (e0 << LB);
       bool neg = false;
       if constexpr (SB1 >= 0) neg ^= ((i0 >> SB1) & 1) != 0;
       if constexpr (SB2 >= 0) neg ^= ((i0 >> SB2) & 1) != 0;
@@ -390,13 +376,19 @@ __device__ __forceinline__ void wave_axis(double2 (&v)[WLayout<R>::E], int lane,
       tr = fma(-ci, u1.y, tr);
       double ti = fma(cr, u1.y, u0.y);
       ti = fma(ci, u1.x, ti);
-      const int i0 = (lane | (e << 6)) & ~(1 << B);
+      const int i0 = ((lane & LM) | (e << LB)) & ~(1 << B);
       bool neg = false;
       if constexpr (SB1 >= 0) neg ^= ((i0 >> SB1) & 1) != 0;
       if constexpr (SB2 >= 0) neg ^= ((i0 >> SB2) & 1) != 0;
       v[e] = (upper && neg) ? make_double2(-tr, -ti) : make_double2(tr, ti);
     }
   }
+}
+
+template <int R, int B, int SB1, int SB2>
+__device__ __forceinline__ void wave_axis(double2 (&v)[WLayout<R>::E], int lane, double ar, double ai, double br,
+                                          double bi) {
+  group_axis<WLayout<R>::E, 6, B, SB1, SB2>(v, lane, ar, ai, br, bi);
 }
 
 template <int R, int L>
@@ -413,6 +405,24 @@ struct WAxes {
       wave_axis<R, WLayout<R>::bra_bit(L), (L >= 2 ? WLayout<R>::bra_bit(L - 1) : -1), -1>(v, lane, c.ar, -c.ai,
                                                                                              c.br, -c.bi);
       WAxes<R, L + 1>::bra(v, lane, c);
+    }
+  }
+};
+
+template <int R, int LB, int E, int L>
+struct GAxes {
+  __device__ __forceinline__ static void ket(double2 (&v)[E], int lane, const Gen64& c) {
+    if constexpr (L <= R - 1) {
+      group_axis<E, LB, DLayout<R>::ket_bit(L), (L >= 2 ? DLayout<R>::ket_bit(L - 1) : -1), -1>(v, lane, c.ar, c.ai,
+                                                                                                c.br, c.bi);
+      GAxes<R, LB, E, L + 1>::ket(v, lane, c);
+    }
+  }
+  __device__ __forceinline__ static void bra(double2 (&v)[E], int lane, const Gen64& c) {
+    if constexpr (L <= R - 1) {
+      group_axis<E, LB, DLayout<R>::bra_bit(L), (L >= 2 ? DLayout<R>::bra_bit(L - 1) : -1), -1>(v, lane, c.ar, -c.ai,
+                                                                                                c.br, -c.bi);
+      GAxes<R, LB, E, L + 1>::bra(v, lane, c);
     }
   }
 };
@@ -500,6 +510,133 @@ __device__ __forceinline__ void fp64_pair_wave(const SweepArgs& a, int64_t i, in
   if (lane == 0) store_entry(a, i, j, fma(sr, sr, si * si), 2 * (acc - R * a.n));
 }
 
+// FP64 sweep of one pair per group of G = 2^LB lanes (reps <= 3, the pair
+// uniform over the group): the M = 2^(2r-1) entries sit M / G per lane as
+// in group_axis, every butterfly the one-lane sweep's operations and the
+// renormalisation its power of two (the group's largest component), so the
+// environment is bitwise the one-lane sweep's; for the closure the group's
+// first lane gathers the M entries and sums them in the one-lane order, so
+// the stored entry is bitwise the refinement's.  Generators of the next
+// 2 PF sites in flight (the points of a pair list are scattered: each
+// site's loads miss the caches).
+template <int R, int LB, int PF>
+__device__ __forceinline__ void fp64_pair_group(const SweepArgs& a, int64_t i, int64_t j, bool comp) {
+  using D = DLayout<R>;
+  constexpr int M = D::M, G = 1 << LB, E = M / G;
+  static_assert(E >= 1, "a group holds at most M lanes");
+  constexpr int LOWMASK = (1 << (R - 1)) - 1;
+  const int lane = threadIdx.x & 63, gl = lane & (G - 1);
+  const float4* __restrict__ gA = a.gen_a;
+  const float4* __restrict__ gB = a.gen_b;
+  const float4* __restrict__ lA = a.gen_a + int64_t(a.n) * a.Na;  // Section L follows Section G
+  const float4* __restrict__ lB = a.gen_b + int64_t(a.n) * a.Nb;
+  const int64_t ic = (i >= 0 && i < a.Na) ? i : a.Na - 1;  // loads of idle groups stay in bounds
+  const int64_t jc = (j >= 0 && j < a.Nb) ? j : a.Nb - 1;
+  double2 v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int q = gl | (e << LB);
+    const int s = (q >> D::S) & 1;
+    const int par = dcol_sign_parity<R>(q & LOWMASK, s) ^ dcol_sign_parity<R>((q >> (R - 1)) & LOWMASK, s);
+    v[e] = make_double2(par ? -1.0 : 1.0, 0.0);
+  }
+  int32_t acc = 0;
+  int countdown = a.renorm_every;
+  auto step = [&](const Gen64& cx, const Gen64& cy) {
+    GAxes<R, LB, E, 1>::ket(v, lane, cx);
+    GAxes<R, LB, E, 1>::bra(v, lane, cy);
+    const double asr = fma(cx.ar, cy.ar, cx.ai * cy.ai);
+    const double asi = fma(cx.ai, cy.ar, -(cx.ar * cy.ai));
+    const double bsr = fma(cx.br, cy.br, cx.bi * cy.bi);
+    const double bsi = fma(cx.bi, cy.br, -(cx.br * cy.bi));
+    constexpr int SB1 = (R >= 2) ? D::ket_bit(R - 1) : -1;
+    constexpr int SB2 = (R >= 2) ? D::bra_bit(R - 1) : -1;
+    group_axis<E, LB, D::S, SB1, SB2>(v, lane, asr, asi, bsr, bsi);
+    if (--countdown == 0) {
+      double m = 0.0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) m = fmax(m, fmax(fabs(v[e].x), fabs(v[e].y)));
+#pragma unroll
+      for (int off = 1; off < G; off <<= 1) m = fmax(m, __shfl_xor(m, off, 64));
+      int ex = 0;
+      (void)frexp(m, &ex);
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = make_double2(ldexp(v[e].x, -ex), ldexp(v[e].y, -ex));
+      acc += ex;
+      countdown = a.renorm_every;
+    }
+  };
+  struct Raw {
+    float4 xh, xl, yh, yl;
+  };
+  Raw buf[2][PF];
+  auto load = [&](int k0, Raw(&g)[PF]) {
+#pragma unroll
+    for (int d = 0; d < PF; ++d) {
+      const int64_t kc = (k0 + d < a.n) ? k0 + d : a.n - 1;
+      g[d].xh = gA[kc * a.Na + ic];
+      g[d].xl = lA[kc * a.Na + ic];
+      g[d].yh = gB[kc * a.Nb + jc];
+      g[d].yl = lB[kc * a.Nb + jc];
+    }
+  };
+  auto sweep = [&](int k0, const Raw(&g)[PF]) {
+#pragma unroll
+    for (int d = 0; d < PF; ++d) {
+      if (k0 + d >= a.n) break;  // uniform
+      const Gen64 cx = {double(g[d].xh.x) + double(g[d].xl.x), double(g[d].xh.y) + double(g[d].xl.y),
+                        double(g[d].xh.z) + double(g[d].xl.z), double(g[d].xh.w) + double(g[d].xl.w)};
+      const Gen64 cy = {double(g[d].yh.x) + double(g[d].yl.x), double(g[d].yh.y) + double(g[d].yl.y),
+                        double(g[d].yh.z) + double(g[d].yl.z), double(g[d].yh.w) + double(g[d].yl.w)};
+      step(cx, cy);
+    }
+  };
+  if (a.n > 1) {
+    load(1, buf[0]);
+    for (int k = 1; k < a.n; k += 2 * PF) {
+      load(k + PF, buf[1]);
+      sweep(k, buf[0]);
+      if (k + PF >= a.n) break;
+      load(k + 2 * PF, buf[0]);
+      sweep(k + PF, buf[1]);
+    }
+  }
+  // the M entries in q order, in every lane of the group
+  double2 all[M];
+  const int base = lane & ~(G - 1);
+#pragma unroll
+  for (int q = 0; q < M; ++q) {
+    const int src = base | (q & (G - 1));
+    all[q] = make_double2(__shfl(v[q >> LB].x, src, 64), __shfl(v[q >> LB].y, src, 64));
+  }
+  if (comp && gl == 0) {
+    const Gen64 gx = gen64(gA, lA, ic), gy = gen64(gB, lB, jc);
+    const double s2 = dclosure<R>(all, gx.ar, gx.ai, gy.ar, gy.ai);
+    store_entry(a, i, j, s2, 2 * (acc - R * a.n));
+  }
+}
+
+// FP64 entries of a device-resident pair list (reps <= 3): one pair per
+// group of 2^LB lanes, 64 / 2^LB pairs per wave.  Chunks of a wave's pairs
+// go to the blocks in turn (chunk c to block c % gridDim.x, wave
+// c / gridDim.x) so a short list is spread over as many compute units as it
+// has chunks.
+template <int R, int LB>
+__global__ void __launch_bounds__(256)
+pairs_fp64_group_kernel(SweepArgs a, const int32_t* __restrict__ pairs, const int32_t* __restrict__ count,
+                        int64_t max_pairs) {
+  constexpr int P = 64 >> LB;  // pairs per wave
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t n = listed_count(count, max_pairs);
+  for (int64_t c = int64_t(wave) * gridDim.x + blockIdx.x; c * P < n; c += int64_t(gridDim.x) * 4) {  // wave-uniform
+    int64_t i, j;
+    const bool comp = listed_pair(a, pairs, n, c * P + (lane >> LB), i, j);
+    if (!__builtin_amdgcn_ballot_w64(comp)) continue;
+    fp64_pair_group<R, LB, 4>(a, i, j, comp);
+  }
+}
+
 template <int R>
 __global__ void __launch_bounds__(256)
 refine_wave_kernel(SweepArgs a, double thresh, const uint32_t* __restrict__ list, const uint32_t* __restrict__ count) {
@@ -537,15 +674,17 @@ hipError_t launch_pairs_fp64(const SweepArgs& a, int32_t reps, const int32_t* pa
                              int64_t max_pairs, int64_t resident_blocks, hipStream_t stream) {
   if (reps < 1 || reps > kMaxReps) return hipErrorInvalidValue;
   if (max_pairs <= 0) return hipSuccess;
-  // one pair per lane (reps <= 3) or per wave, at most the resident blocks
-  int64_t blocks = (reps >= 4) ? (max_pairs + 3) / 4 : (max_pairs + 255) / 256;
+  // one pair per group of 2, 4 or 8 lanes (reps 1, 2, 3) or per wave, at
+  // most the resident blocks
+  const int64_t per_block = (reps >= 4) ? 4 : 4 * (64 >> (reps == 3 ? 3 : reps == 2 ? 2 : 1));
+  int64_t blocks = (max_pairs + per_block - 1) / per_block;
   if (blocks > resident_blocks) blocks = resident_blocks;
   if (blocks < 1) blocks = 1;
   const dim3 grid{unsigned(blocks)};
   switch (reps) {
-    case 1: hipLaunchKernelGGL(pairs_fp64_kernel<1>, grid, dim3(256), 0, stream, a, pairs, count, max_pairs); break;
-    case 2: hipLaunchKernelGGL(pairs_fp64_kernel<2>, grid, dim3(256), 0, stream, a, pairs, count, max_pairs); break;
-    case 3: hipLaunchKernelGGL(pairs_fp64_kernel<3>, grid, dim3(256), 0, stream, a, pairs, count, max_pairs); break;
+    case 1: hipLaunchKernelGGL((pairs_fp64_group_kernel<1, 1>), grid, dim3(256), 0, stream, a, pairs, count, max_pairs); break;
+    case 2: hipLaunchKernelGGL((pairs_fp64_group_kernel<2, 2>), grid, dim3(256), 0, stream, a, pairs, count, max_pairs); break;
+    case 3: hipLaunchKernelGGL((pairs_fp64_group_kernel<3, 3>), grid, dim3(256), 0, stream, a, pairs, count, max_pairs); break;
     case 4: hipLaunchKernelGGL(pairs_fp64_wave_kernel<4>, grid, dim3(256), 0, stream, a, pairs, count, max_pairs); break;
     case 5: hipLaunchKernelGGL(pairs_fp64_wave_kernel<5>, grid, dim3(256), 0, stream, a, pairs, count, max_pairs); break;
     default: hipLaunchKernelGGL(pairs_fp64_wave_kernel<6>, grid, dim3(256), 0, stream, a, pairs, count, max_pairs); break;
