@@ -22,8 +22,8 @@
 // (same recursion, gauge, sign pattern, renormalisation and closure) with
 // doubles: one pair per lane and one ket point per wave for reps <= 3; at
 // reps >= 4 (128 to 2048 environment entries) one pair per wave.  A pair
-// list (pairs_fp64_group_kernel, reps <= 3) takes one pair per group of 2,
-// 4 or 8 lanes and writes bitwise the one-lane values.
+// list (pairs_fp64_group_kernel, reps <= 3) takes one pair per group of 2
+// or 4 lanes and writes bitwise the one-lane values.
 
 #include "../../include/qsvm.h"
 #include "refine.h"
@@ -348,7 +348,21 @@ struct WLayout {
 // registers (q = lane % 2^LB + e 2^LB).  A register bit runs as register
 // butterflies; a lane bit B pairs lane l with lane l ^ 2^B: the lane without
 // the bit computes u0 + a u1, the lane with it +-(u0 + b u1), each from its
-// own value and its partner's (__shfl_xor), the same operations as dbfly.
+// own value and its partner's (xor_lane), the same operations as dbfly.
+// x of lane l ^ 2^B: a DPP quad permutation for B = 0, 1 (no trip through
+// the LDS crossbar), __shfl_xor above.
+template <int B>
+__device__ __forceinline__ double xor_lane(double x) {
+  if constexpr (B <= 1) {
+    constexpr int ctrl = (B == 0) ? 0xB1 : 0x4E;  // quad_perm [1,0,3,2] / [2,3,0,1]
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), ctrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), ctrl, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+  } else {
+    return __shfl_xor(x, 1 << B, 64);
+  }
+}
+
 template <int E, int LB, int B, int SB1, int SB2>
 __device__ __forceinline__ void group_axis(double2 (&v)[E], int lane, double ar, double ai, double br, double bi) {
   constexpr int LM = (1 << LB) - 1;
@@ -369,7 +383,7 @@ __device__ __forceinline__ void group_axis(double2 (&v)[E], int lane, double ar,
     const double cr = upper ? br : ar, ci = upper ? bi : ai;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const double pr = __shfl_xor(v[e].x, 1 << B, 64), pim = __shfl_xor(v[e].y, 1 << B, 64);
+      const double pr = xor_lane<B>(v[e].x), pim = xor_lane<B>(v[e].y);
       const double2 u0 = upper ? make_double2(pr, pim) : v[e];
       const double2 u1 = upper ? v[e] : make_double2(pr, pim);
       double tr = fma(cr, u1.x, u0.x);
@@ -556,8 +570,10 @@ __device__ __forceinline__ void fp64_pair_group(const SweepArgs& a, int64_t i, i
       double m = 0.0;
 #pragma unroll
       for (int e = 0; e < E; ++e) m = fmax(m, fmax(fabs(v[e].x), fabs(v[e].y)));
+      if constexpr (G > 1) m = fmax(m, xor_lane<0>(m));
+      if constexpr (G > 2) m = fmax(m, xor_lane<1>(m));
 #pragma unroll
-      for (int off = 1; off < G; off <<= 1) m = fmax(m, __shfl_xor(m, off, 64));
+      for (int off = 4; off < G; off <<= 1) m = fmax(m, __shfl_xor(m, off, 64));
       int ex = 0;
       (void)frexp(m, &ex);
 #pragma unroll
@@ -674,9 +690,9 @@ hipError_t launch_pairs_fp64(const SweepArgs& a, int32_t reps, const int32_t* pa
                              int64_t max_pairs, int64_t resident_blocks, hipStream_t stream) {
   if (reps < 1 || reps > kMaxReps) return hipErrorInvalidValue;
   if (max_pairs <= 0) return hipSuccess;
-  // one pair per group of 2, 4 or 8 lanes (reps 1, 2, 3) or per wave, at
+  // one pair per group of 2 or 4 lanes (reps 1; 2 and 3) or per wave, at
   // most the resident blocks
-  const int64_t per_block = (reps >= 4) ? 4 : 4 * (64 >> (reps == 3 ? 3 : reps == 2 ? 2 : 1));
+  const int64_t per_block = (reps >= 4) ? 4 : 4 * (64 >> (reps == 1 ? 1 : 2));
   int64_t blocks = (max_pairs + per_block - 1) / per_block;
   if (blocks > resident_blocks) blocks = resident_blocks;
   if (blocks < 1) blocks = 1;
@@ -684,7 +700,7 @@ hipError_t launch_pairs_fp64(const SweepArgs& a, int32_t reps, const int32_t* pa
   switch (reps) {
     case 1: hipLaunchKernelGGL((pairs_fp64_group_kernel<1, 1>), grid, dim3(256), 0, stream, a, pairs, count, max_pairs); break;
     case 2: hipLaunchKernelGGL((pairs_fp64_group_kernel<2, 2>), grid, dim3(256), 0, stream, a, pairs, count, max_pairs); break;
-    case 3: hipLaunchKernelGGL((pairs_fp64_group_kernel<3, 3>), grid, dim3(256), 0, stream, a, pairs, count, max_pairs); break;
+    case 3: hipLaunchKernelGGL((pairs_fp64_group_kernel<3, 2>), grid, dim3(256), 0, stream, a, pairs, count, max_pairs); break;
     case 4: hipLaunchKernelGGL(pairs_fp64_wave_kernel<4>, grid, dim3(256), 0, stream, a, pairs, count, max_pairs); break;
     case 5: hipLaunchKernelGGL(pairs_fp64_wave_kernel<5>, grid, dim3(256), 0, stream, a, pairs, count, max_pairs); break;
     default: hipLaunchKernelGGL(pairs_fp64_wave_kernel<6>, grid, dim3(256), 0, stream, a, pairs, count, max_pairs); break;
