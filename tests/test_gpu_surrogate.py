@@ -317,6 +317,57 @@ def test_surrogate_gram_log_elementwise_and_tile_max(N, d_in, d):
     assert got == want and c == len(want)
 
 
+def test_surrogate_gram_log_many_super_tiles_every_entry_written():
+    """N = 4160 at the production widths (832 + 256): 33 block rows of 128 in
+    5 super-rows of 8 (the last partial, its last block half past N_pad).
+    Every entry of K and every tile maximum is written (NaN before the call),
+    K is exactly symmetric with a unit diagonal, and sampled rows around the
+    block and super-tile boundaries, and whole tiles on and off the diagonal,
+    match the FP64 reference."""
+    import torch
+
+    N, d_in, d = 4160, 832, 256
+    rng = np.random.default_rng(4160)
+    base = rng.uniform(0, 1, (16, d_in))
+    Xr = ref.bf16_round(base[rng.integers(0, 16, N)] + rng.normal(0, 0.02, (N, d_in)))
+    E = ref.bf16_round(rng.normal(0, 0.1, (N, d)))
+    lc, ls = float(np.float32(math.log(30.0))), float(np.float32(math.log(0.2)))
+    T = N // 64
+    K = torch.full((N, N), float("nan"), dtype=torch.float64, device="cuda:0")
+    tmax = torch.full((T * T,), float("nan"), dtype=torch.float32, device="cuda:0")
+    qsvm.qsvm_surrogate_gram_log(_bf16_dev(Xr), _bf16_dev(E), N, _f32_dev([lc, ls]), K, tmax)
+    torch.cuda.synchronize()
+    assert not torch.isnan(K).any().item()
+    assert torch.equal(K, K.T)
+    assert torch.all(torch.diagonal(K) == 1.0).item()
+    tm = tmax.cpu().numpy().reshape(T, T)
+    assert not np.isnan(tm).any() and np.array_equal(tm, tm.T)
+
+    def bars(rows):
+        Z = np.concatenate([Xr[rows], E[rows]], axis=1)
+        nrm = np.sum(Z * Z, axis=1)
+        err_d2 = 2e-6 * (nrm[:, None] + nrm[None, :]) + 1e-7
+        return err_d2
+
+    idx = np.unique(np.concatenate([[0, 1, 127, 128, 129, 1023, 1024, 1025, 2047, 2048, 4095, 4096, 4159],
+                                    rng.integers(0, N, 150)]))
+    L, Kr = ref.sat_log_gram(Xr[idx], E[idx], lc, ls)
+    err_l = 30.0 * 0.2 * bars(idx) + 1e-6 * np.abs(L) + 1e-6
+    Kh = K.cpu().numpy()
+    _assert_elementwise(Kh[np.ix_(idx, idx)], Kr, Kr * np.expm1(err_l) + 1e-30, "K_hat sampled")
+    for ta, tb in [(0, 0), (0, 1), (15, 16), (16, 16), (31, 64), (64, 64), (2, 60)]:
+        rows = np.concatenate([np.arange(ta * 64, ta * 64 + 64), np.arange(tb * 64, tb * 64 + 64)])
+        L, Kr = ref.sat_log_gram(Xr[rows], E[rows], lc, ls)
+        err_l = 30.0 * 0.2 * bars(rows) + 1e-6 * np.abs(L) + 1e-6
+        blk = (slice(0, 64), slice(64, 128)) if ta != tb else (slice(0, 64), slice(0, 64))
+        got = Kh[ta * 64:ta * 64 + 64, tb * 64:tb * 64 + 64]
+        _assert_elementwise(got, Kr[blk], Kr[blk] * np.expm1(err_l[blk]) + 1e-30, f"tile ({ta},{tb})")
+        lref = L[blk].copy()
+        if ta == tb:
+            np.fill_diagonal(lref, -np.inf)
+        assert abs(tm[ta, tb] - lref.max()) <= err_l[blk].max(), (ta, tb, tm[ta, tb], lref.max())
+
+
 def test_adamw_matches_reference():
     import torch
 
