@@ -26,8 +26,11 @@
 // their own coefficient c; the phases are carried in FP64 and multiply each
 // lane's part of the closure at the end.  The partner's values come through
 // the LDS crossbar (ds_swizzle, bit-mask mode with the xor mask of the lane
-// bit), four entries per wait: that keeps the exchanges off the VALU, where
-// DPP moves measured about 8 extra issue cycles each.  Renormalisation takes
+// bit), four or eight entries per wait, or by DPP moves: at reps 4 (two
+// waves per SIMD, VALU-bound) the swizzles keep the exchange off the VALU,
+// where DPP moves measured about 8 extra issue cycles each; at reps 5 and 6
+// (one wave per SIMD, the exchange latency exposed) xor 1, 2 and 8 go by DPP
+// (7-8 % faster; xor 4 as two row rotations and a select measured slower).  Renormalisation takes
 // the largest of the group's maxima, so the group shares one power-of-two
 // scale.  The closure reduces the group's FP64 partial sums over the lane
 // bits in a fixed order, identical in every lane.
@@ -141,15 +144,35 @@ __device__ __forceinline__ double swz_xor(double x) {
 // passes f0 = f1 = 1; the lane with it passes its sign pattern (f0 = the
 // lane-bit part of the sign, f1 = -f0).  LANE_SIGN = false: f0 is 1 in every
 // lane, so the even entries are not multiplied.
-template <int XM, int IB1, int IB2, bool LANE_SIGN, int ML, int B = 4>
+// x of lane l ^ XM for XM = 1, 2 (quad permutations) and 8 (rotation of a
+// row of 16 by 8), a VALU move.
+template <int XM>
+__device__ __forceinline__ float dpp_xor(float x) {
+  static_assert(XM == 1 || XM == 2 || XM == 8, "DPP covers xor 1, 2 and 8");
+  constexpr int ctrl = XM == 1 ? 0xB1 : XM == 2 ? 0x4E : 0x128;  // quad_perm [1,0,3,2], [2,3,0,1]; row_ror:8
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), ctrl, 0xF, 0xF, false));
+}
+
+// DP: the partner values of xor 1, 2 and 8 come by DPP (reps >= 5, one wave
+// per SIMD: the exchange latency is exposed and the VALU has room), the
+// others through ds_swizzle.
+template <int XM, int IB1, int IB2, bool LANE_SIGN, int ML, int B = 4, bool DP = false>
 __device__ __forceinline__ void cross_axis(float2 (&v)[ML], float cr, float ci, float f0, float f1) {
+  constexpr bool dpp = DP && (XM == 1 || XM == 2 || XM == 8);
 #pragma unroll
   for (int c = 0; c < ML / B; ++c) {
     float p[2 * B];
-    if constexpr (B == 8)
+    if constexpr (dpp) {
+#pragma unroll
+      for (int e = 0; e < B; ++e) {
+        p[2 * e] = dpp_xor<dpp ? XM : 1>(v[B * c + e].x);
+        p[2 * e + 1] = dpp_xor<dpp ? XM : 1>(v[B * c + e].y);
+      }
+    } else if constexpr (B == 8) {
       swizzle8<XM>(&v[8 * c], p);
-    else
+    } else {
       swizzle4<XM>(v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3], p);
+    }
 #pragma unroll
     for (int e = 0; e < B; ++e) {
       const int q = B * c + e;
@@ -270,10 +293,10 @@ struct CrossKet {
       float cr, ci;
       axis_coeff(upper, a[0], a[1], a[2], a[3], phr[B], phi[B], cr, ci);
       if constexpr (L0 == 4) {
-        cross_axis<1 << B, 2, -1, false, 64, 8>(v, cr, ci, 1.0f, upper ? -1.0f : 1.0f);
+        cross_axis<1 << B, 2, -1, false, 64, 8, true>(v, cr, ci, 1.0f, upper ? -1.0f : 1.0f);
       } else {
         const float f0 = (upper && ((g >> Split<R>::kbit(L0 - 1)) & 1)) ? -1.0f : 1.0f;
-        cross_axis<1 << B, -1, -1, true, 64, 8>(v, cr, ci, f0, f0);
+        cross_axis<1 << B, -1, -1, true, 64, 8, true>(v, cr, ci, f0, f0);
       }
       CrossKet<R, L0 + 1>::run(v, g, a, phr, phi);
     }
@@ -290,10 +313,10 @@ struct CrossBra {
       float cr, ci;
       axis_coeff(upper, a[0], a[1], a[2], a[3], phr[B], phi[B], cr, ci);
       if constexpr (L0 == 4) {
-        cross_axis<1 << B, 5, -1, false, 64, 8>(v, cr, ci, 1.0f, upper ? -1.0f : 1.0f);
+        cross_axis<1 << B, 5, -1, false, 64, 8, true>(v, cr, ci, 1.0f, upper ? -1.0f : 1.0f);
       } else {
         const float f0 = (upper && ((g >> Split<R>::bbit(L0 - 1)) & 1)) ? -1.0f : 1.0f;
-        cross_axis<1 << B, -1, -1, true, 64, 8>(v, cr, ci, f0, f0);
+        cross_axis<1 << B, -1, -1, true, 64, 8, true>(v, cr, ci, f0, f0);
       }
       CrossBra<R, L0 + 1>::run(v, g, a, phr, phi);
     }
@@ -384,7 +407,7 @@ __device__ __forceinline__ void split_item(const SweepArgs& a, int64_t i, int64_
         if constexpr (R == 4)
           cross_axis<1, 2, 5, false>(v, cr, ci, 1.0f, up_s ? -1.0f : 1.0f);
         else
-          cross_axis<1, -1, -1, true, 64, 8>(v, cr, ci, fs, fs);
+          cross_axis<1, -1, -1, true, 64, 8, true>(v, cr, ci, fs, fs);
       }
       if (--countdown == 0) {
         acc += rescale(v, group_max<C>(absmax(v)));
