@@ -505,8 +505,9 @@ typedef struct {   /* gradients (f32, shaped like the parameters) and scratch */
   float* dW1; float* db1; float* dW2; float* db2; float* dW3; float* db3;
   void* dH1; void* dH2; /* bf16, rows x d_h1 and rows x d_h2 */
   float* ws;            /* f32 workspace of ws_floats >= qsvm_mlp_workspace_floats(net, rows):
-                           split-K partial products of the weight gradients and
-                           partial column sums, reduced in a fixed order */
+                           k-contiguous copies of each weight gradient's operands
+                           and its split-K partial products (weights and biases
+                           in one product), reduced in a fixed order */
   int64_t ws_floats;
 } qsvm_mlp_grads;
 
@@ -557,9 +558,10 @@ qsvm_status qsvm_pair_head_log(const void* X16, int32_t d_in, const float* E, in
                                float* out3, float* pred, void* stream);
 
 /* Backward pass given dE16 (rows x d_out bf16): parameter gradients into grads
- * (overwritten, not accumulated).  Weight gradients (K = rows) are split along
- * the rows into partial products in grads->ws and summed in a fixed order;
- * a too-small workspace returns QSVM_ERR_SIZE. */
+ * (overwritten, not accumulated).  Each layer's weight and bias gradients are
+ * one product [A, 1]^T dH (K = rows) on k-contiguous copies of the operands in
+ * grads->ws, split along the rows into partial products summed in a fixed
+ * order; a too-small workspace returns QSVM_ERR_SIZE. */
 qsvm_status qsvm_mlp_backward(const qsvm_mlp* net, const void* X16, const qsvm_mlp_acts* acts, const void* dE16,
                               int64_t rows, const qsvm_mlp_grads* grads, void* stream);
 

@@ -21,8 +21,10 @@
 //   stores).
 // * gather_features: FP64 feature rows -> zero-padded BF16 rows.
 // * transpose_bf16: the forward pass's k-contiguous copy of each weight.
-// * colsum_partial + sum_slabs: bias gradients (column sums in two fixed-order
-//   stages) and the reduction of split-K partial products.
+// * transpose64_bf16, ones_row_bf16, sum_slabs: the weight gradients' operands
+//   copied k-contiguous (the activations with a row of ones appended, whose
+//   product row is the bias gradient) and the fixed-order reduction of their
+//   split-K partial products.
 // * pair_head: per pair, K_hat, the loss (squared error or soft-target
 //   cross-entropy) and its gradient w.r.t. both embeddings, alpha and beta;
 //   per-pair partial sums reduced in a fixed order.
@@ -747,6 +749,36 @@ sat_log_gram_kernel(const uint16_t* __restrict__ X16, int32_t d_in, const uint16
   }
 }
 
+// out (C x R, row stride R) = in (R x C, row stride C)^T for one large bf16
+// matrix, R and C multiples of 8: 64 x 64 tiles, 16-byte loads and stores
+// (each thread two pieces of 8 values each way) through a padded LDS tile.
+__global__ void __launch_bounds__(256) transpose64_bf16(const uint16_t* __restrict__ in, int64_t R, int64_t C,
+                                                       uint16_t* __restrict__ out) {
+  constexpr int TP = 64 + 8;  // LDS row (bf16): 144 bytes, 16-byte aligned
+  __shared__ __attribute__((aligned(16))) uint16_t tile[64 * TP];
+  const int t = threadIdx.x;
+  const int64_t r0 = int64_t(blockIdx.x) * 64, c0 = int64_t(blockIdx.y) * 64;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int p = t + 256 * h, row = p >> 3, pc = (p & 7) * 8;
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (r0 + row < R && c0 + pc < C) v = *reinterpret_cast<const uint4*>(in + (r0 + row) * C + c0 + pc);
+    *reinterpret_cast<uint4*>(&tile[row * TP + pc]) = v;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int p = t + 256 * h, oc = p >> 3, pr = (p & 7) * 8;  // output row c0 + oc, its values r0 + pr ..
+    if (c0 + oc < C && r0 + pr < R) {
+      uint32_t w[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        w[e] = uint32_t(tile[(pr + 2 * e) * TP + oc]) | (uint32_t(tile[(pr + 2 * e + 1) * TP + oc]) << 16);
+      *reinterpret_cast<uint4*>(out + (c0 + oc) * R + r0 + pr) = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+  }
+}
+
 // out_q (C_q x R_q) = in_q (R_q x C_q)^T for up to three bf16 matrices in one
 // launch: block b works on matrix q with first_block[q] <= b < first_block[q + 1],
 // one 32 x 32 tile through LDS (padded rows: the column reads hit distinct banks).
@@ -801,34 +833,26 @@ __global__ void __launch_bounds__(256) gather_features(const double* __restrict_
   }
 }
 
-// Column sums in two fixed-order stages: partial[chunk][c] over 256-row
-// chunks, then the chunks (sum_slabs).  A block covers 64 columns (one per
-// lane) of one chunk; wave w sums the rows w, w + 4, ... of the chunk, and
-// the four wave sums are added in wave order.
-constexpr int kColChunk = 256;
-
-__global__ void __launch_bounds__(256) colsum_partial(const uint16_t* __restrict__ A, int64_t rows, int32_t cols,
-                                                      float* __restrict__ partial) {
-  __shared__ float part[4][64];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int32_t c = int32_t(blockIdx.x) * 64 + lane;
-  const int64_t r0 = int64_t(blockIdx.y) * kColChunk;
-  const int64_t r1 = (r0 + kColChunk < rows) ? r0 + kColChunk : rows;
-  float s = 0.0f;
-  if (c < cols)
-    for (int64_t r = r0 + wave; r < r1; r += 4) s += bf16_to_f32(A[r * cols + c]);
-  part[wave][lane] = s;
-  __syncthreads();
-  if (wave == 0 && c < cols)
-    partial[int64_t(blockIdx.y) * cols + c] = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
-}
-
-__global__ void sum_slabs(const float* __restrict__ slabs, int32_t n_slabs, int64_t count, float* __restrict__ out) {
+// sum over z (in order) of slabs[z stride + t], t < count, into out[t] for
+// t < split and out2[t - split] above.
+__global__ void sum_slabs(const float* __restrict__ slabs, int32_t n_slabs, int64_t count, int64_t stride,
+                          float* __restrict__ out, int64_t split, float* __restrict__ out2) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= count) return;
   float s = 0.0f;
-  for (int32_t z = 0; z < n_slabs; ++z) s += slabs[int64_t(z) * count + t];
-  out[t] = s;
+  for (int32_t z = 0; z < n_slabs; ++z) s += slabs[int64_t(z) * stride + t];
+  if (t < split)
+    out[t] = s;
+  else
+    out2[t - split] = s;
+}
+
+// rows x cols bf16 (cols % 8 == 0): row 0 ones, the others zeros.
+__global__ void __launch_bounds__(256) ones_row_bf16(uint16_t* __restrict__ out, int64_t rows, int64_t cols) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x, per_row = cols / 8;
+  if (p >= rows * per_row) return;
+  const uint32_t w = (p < per_row) ? 0x3F803F80u : 0u;  // bf16 1.0 twice
+  *reinterpret_cast<uint4*>(out + p * 8) = make_uint4(w, w, w, w);
 }
 
 __device__ __forceinline__ float softplusf(float z) {  // log(1 + e^z), no overflow
@@ -1105,6 +1129,13 @@ hipError_t launch_sigmoid_gram(const uint16_t* E, int64_t N_pad, int32_t d, cons
   return hipGetLastError();
 }
 
+hipError_t launch_transpose64_bf16(const uint16_t* in, int64_t R, int64_t C, uint16_t* out, hipStream_t s) {
+  if (R < 1 || C < 1 || R % 8 || C % 8 || (R + 63) / 64 > INT32_MAX || (C + 63) / 64 > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(transpose64_bf16, dim3(unsigned((R + 63) / 64), unsigned((C + 63) / 64)), dim3(256), 0, s, in, R,
+                     C, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_transpose_bf16(TransposeJobs j, int32_t count, hipStream_t s) {
   if (count < 1 || count > 3) return hipErrorInvalidValue;
   int32_t blocks = 0;
@@ -1128,19 +1159,17 @@ hipError_t launch_gather(const double* X, int64_t N, int32_t n, const int32_t* i
   return hipGetLastError();
 }
 
-int colsum_chunks(int64_t rows) { return int((rows + kColChunk - 1) / kColChunk); }
-
-hipError_t launch_colsum(const uint16_t* A, int64_t rows, int32_t cols, float* partial, float* out, hipStream_t s) {
-  const int chunks = colsum_chunks(rows);
-  hipLaunchKernelGGL(colsum_partial, dim3(unsigned((cols + 63) / 64), unsigned(chunks)), dim3(256), 0, s, A, rows,
-                     cols, partial);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  return launch_sum_slabs(partial, chunks, cols, out, s);
+hipError_t launch_sum_slabs(const float* slabs, int32_t n_slabs, int64_t count, int64_t stride, float* out,
+                            int64_t split, float* out2, hipStream_t s) {
+  hipLaunchKernelGGL(sum_slabs, dim3(unsigned((count + 255) / 256)), dim3(256), 0, s, slabs, n_slabs, count, stride,
+                     out, split, out2);
+  return hipGetLastError();
 }
 
-hipError_t launch_sum_slabs(const float* slabs, int32_t n_slabs, int64_t count, float* out, hipStream_t s) {
-  hipLaunchKernelGGL(sum_slabs, dim3(unsigned((count + 255) / 256)), dim3(256), 0, s, slabs, n_slabs, count, out);
+hipError_t launch_ones_row_bf16(uint16_t* out, int64_t rows, int64_t cols, hipStream_t s) {
+  if (rows < 1 || cols < 8 || cols % 8) return hipErrorInvalidValue;
+  const int64_t pieces = rows * (cols / 8);
+  hipLaunchKernelGGL(ones_row_bf16, dim3(unsigned((pieces + 255) / 256)), dim3(256), 0, s, out, rows, cols);
   return hipGetLastError();
 }
 

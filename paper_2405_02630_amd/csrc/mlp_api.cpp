@@ -75,33 +75,61 @@ qsvm::GemmArgs gemm(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda,
 }
 
 // Split-K factor of a weight-gradient GEMM with K = rows.
-int32_t grad_splits(int64_t rows) {
-  for (int32_t s = 8; s > 1; s >>= 1)
-    if (rows % (int64_t(s) * 64) == 0 && rows / s >= 256) return s;  // slabs of whole 64-deep K steps
-  return 1;
+// Rows of the k-contiguous copy of a weight gradient's first operand (M
+// activations x rows): M, one row of ones (its product row is the bias
+// gradient, 1^T dH) and zeros up to a multiple of 128 where N allows the
+// direct-to-LDS GEMM, else of 64.
+int64_t padded_m(int64_t M, int64_t N) {
+  const int64_t q = (N % 128 == 0) ? 128 : 64;
+  return (M / q + 1) * q;
+}
+
+// Split-K of a weight gradient (Mp x N over K = rows): the smallest power of
+// two that gives the GEMM at least 384 blocks, at most 32, each slab whole
+// 64-deep steps and at least 256 rows.
+int32_t grad_splits(int64_t Mp, int64_t N, int64_t rows) {
+  const int64_t tiles = (Mp % 128 == 0 && N % 128 == 0) ? (Mp / 128) * (N / 128) : (Mp / 64) * (N / 64);
+  int32_t s = 1;
+  while (s < 32 && tiles * s < 384 && rows % (int64_t(2 * s) * 64) == 0 && rows / (2 * s) >= 256) s *= 2;
+  return s;
+}
+
+// Floats of a weight gradient's scratch: its split-K slabs (Mp x N each),
+// then the k-contiguous copies of its operands (Mp x rows and N x rows bf16).
+int64_t grad_floats(int64_t M, int64_t N, int64_t rows) {
+  const int64_t Mp = padded_m(M, N);
+  return int64_t(grad_splits(Mp, N, rows)) * Mp * N + (Mp + N) * rows / 2;
 }
 
 int64_t workspace_floats(const qsvm_mlp* net, int64_t rows) {
   const int64_t din = net->d_in, h1 = net->d_h1, h2 = net->d_h2, dout = net->d_out;
-  int64_t mn = din * h1;
-  if (h1 * h2 > mn) mn = h1 * h2;
-  if (h2 * dout > mn) mn = h2 * dout;
-  int64_t cols = h1 > h2 ? h1 : h2;
-  if (dout > cols) cols = dout;
-  const int64_t a = int64_t(grad_splits(rows)) * mn;
-  const int64_t b = int64_t(qsvm::colsum_chunks(rows)) * cols;
-  return a > b ? a : b;
+  int64_t a = grad_floats(din, h1, rows);
+  const int64_t b = grad_floats(h1, h2, rows), c = grad_floats(h2, dout, rows);
+  if (b > a) a = b;
+  if (c > a) a = c;
+  return a;
 }
 
-// dW (M x N) = op(A)^T B over K = rows, split along K into workspace slabs
-// that are then summed in a fixed order.
-hipError_t grad_gemm(int64_t M, int64_t N, int64_t rows, const void* A, int64_t lda, const void* B, int64_t ldb,
-                     float* dW, float* ws, hipStream_t st) {
-  qsvm::GemmArgs g = gemm(M, N, rows, A, lda, B, ldb, ws, nullptr, N);
-  g.splits = grad_splits(rows);
-  if (g.splits == 1) g.C = dW;
-  hipError_t e = qsvm::launch_gemm(1, 0, qsvm::EPI_F32, g, st);
-  if (e == hipSuccess && g.splits > 1) e = qsvm::launch_sum_slabs(ws, g.splits, M * N, dW, st);
+// dW (M x N) = A^T dH and db (N) = 1^T dH over K = rows (A: rows x M,
+// dH: rows x N, bf16, row-major).  Both operands are first copied
+// k-contiguous, A's copy followed by a row of ones and zero rows (padded_m),
+// so one product on the k-contiguous GEMMs (the direct-to-LDS kernel where
+// the padded sizes are multiples of 128) gives dW in its first M rows and db
+// in row M; it is split along K into slabs summed in a fixed order.
+hipError_t grad_gemm(int64_t M, int64_t N, int64_t rows, const void* A, const void* B, float* dW, float* db,
+                     float* ws, hipStream_t st) {
+  const int64_t Mp = padded_m(M, N);
+  const int32_t splits = grad_splits(Mp, N, rows);
+  uint16_t* at = reinterpret_cast<uint16_t*>(ws + int64_t(splits) * Mp * N);  // 16-byte aligned: Mp, N % 64 == 0
+  uint16_t* bt = at + Mp * rows;
+  hipError_t e = qsvm::launch_transpose64_bf16(static_cast<const uint16_t*>(A), rows, M, at, st);
+  if (e == hipSuccess) e = qsvm::launch_ones_row_bf16(at + M * rows, Mp - M, rows, st);
+  if (e == hipSuccess) e = qsvm::launch_transpose64_bf16(static_cast<const uint16_t*>(B), rows, N, bt, st);
+  if (e != hipSuccess) return e;
+  qsvm::GemmArgs g = gemm(Mp, N, rows, at, rows, bt, rows, ws, nullptr, N);
+  g.splits = splits;
+  e = qsvm::launch_gemm(0, 1, qsvm::EPI_F32, g, st);
+  if (e == hipSuccess) e = qsvm::launch_sum_slabs(ws, splits, (M + 1) * N, Mp * N, dW, M * N, db, st);
   return e;
 }
 
@@ -229,23 +257,20 @@ qsvm_status qsvm_mlp_backward(const qsvm_mlp* net, const void* X16, const qsvm_m
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int64_t din = net->d_in, h1 = net->d_h1, h2 = net->d_h2, dout = net->d_out;
   float* ws = g->ws;
-  // dW3 = A2^T dE ; db3 = colsum(dE)
-  hipError_t e = grad_gemm(h2, dout, rows, acts->A2, h2, dE16, dout, g->dW3, ws, st);
-  if (e == hipSuccess) e = qsvm::launch_colsum(static_cast<const uint16_t*>(dE16), rows, int32_t(dout), ws, g->db3, st);
+  // dW3 = A2^T dE ; db3 = 1^T dE
+  hipError_t e = grad_gemm(h2, dout, rows, acts->A2, dE16, g->dW3, g->db3, ws, st);
   // dH2 = (dE W3^T) * gelu'(H2)
   if (e == hipSuccess)
     e = qsvm::launch_gemm(0, 1, qsvm::EPI_GELU_BWD,
                           gemm(rows, h2, dout, dE16, dout, net->W3, dout, nullptr, g->dH2, h2, nullptr, acts->H2), st);
-  // dW2 = A1^T dH2 ; db2 = colsum(dH2)
-  if (e == hipSuccess) e = grad_gemm(h1, h2, rows, acts->A1, h1, g->dH2, h2, g->dW2, ws, st);
-  if (e == hipSuccess) e = qsvm::launch_colsum(static_cast<const uint16_t*>(g->dH2), rows, int32_t(h2), ws, g->db2, st);
+  // dW2 = A1^T dH2 ; db2 = 1^T dH2
+  if (e == hipSuccess) e = grad_gemm(h1, h2, rows, acts->A1, g->dH2, g->dW2, g->db2, ws, st);
   // dH1 = (dH2 W2^T) * gelu'(H1)
   if (e == hipSuccess)
     e = qsvm::launch_gemm(0, 1, qsvm::EPI_GELU_BWD,
                           gemm(rows, h1, h2, g->dH2, h2, net->W2, h2, nullptr, g->dH1, h1, nullptr, acts->H1), st);
-  // dW1 = X^T dH1 ; db1 = colsum(dH1)
-  if (e == hipSuccess) e = grad_gemm(din, h1, rows, X16, din, g->dH1, h1, g->dW1, ws, st);
-  if (e == hipSuccess) e = qsvm::launch_colsum(static_cast<const uint16_t*>(g->dH1), rows, int32_t(h1), ws, g->db1, st);
+  // dW1 = X^T dH1 ; db1 = 1^T dH1
+  if (e == hipSuccess) e = grad_gemm(din, h1, rows, X16, g->dH1, g->dW1, g->db1, ws, st);
   return api_hip(e, what);
 }
 

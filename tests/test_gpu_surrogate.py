@@ -192,9 +192,11 @@ def test_mlp_forward_inference_mode_writes_the_same_bf16_outputs(rows, dims):
 
 def test_mlp_forward_backward_production_shape_elementwise():
     """The surrogate's production widths on 16384 rows: 13 K steps in layer 1,
-    the XCD tile order, and weight gradients split 8 ways along the rows
-    (summed in fixed order) -- every element of every output against the FP64
-    reference on the kernel's own layer inputs."""
+    the XCD tile order, and each layer's weight and bias gradients as one
+    product on k-contiguous copies (the activations with a row of ones),
+    split 16 or 32 ways along the rows and summed in fixed order -- every
+    element of every output against the FP64 reference on the kernel's own
+    layer inputs."""
     import torch
 
     rows = 16384
@@ -202,7 +204,7 @@ def test_mlp_forward_backward_production_shape_elementwise():
     qsvm.qsvm_mlp_forward(net, bufs["X16"], rows, acts)
     torch.cuda.synchronize()
     H1, A1, H2, A2, E = _check_forward(W, X, bufs)
-    assert qsvm.qsvm_mlp_workspace_floats(net, rows) >= 8 * 832 * 512  # the 8-way split is in use
+    assert qsvm.qsvm_mlp_workspace_floats(net, rows) >= 16 * 896 * 512  # layer 1: 16 slabs of 896 x 512
     rng = np.random.default_rng(12)
     dEk = ref.bf16_round(rng.normal(0, 1e-3, (rows, PROD[3])))
     grads, dH1, dH2 = _backward(net, bufs, acts, dev, _bf16_dev(dEk), rows, PROD)
