@@ -47,16 +47,22 @@ struct TransposeJobs {
   int32_t first_block[4];
 };
 hipError_t launch_transpose_bf16(TransposeJobs j, int32_t count, hipStream_t s);
-// out (C x R) = in (R x C)^T, bf16, R and C multiples of 8, C / 64 <= 65535.
-hipError_t launch_transpose64_bf16(const uint16_t* in, int64_t R, int64_t C, uint16_t* out, hipStream_t s);
+// out (Cp x R) = in (R x C)^T for two bf16 matrices with R rows (R % 8 ==
+// 0, C and Cp multiples of 64, Cp >= C); output rows C .. Cp - 1: a row of
+// ones, then zeros.
+struct T64Job {
+  const uint16_t* in;
+  uint16_t* out;
+  int64_t C, Cp;
+};
+hipError_t launch_transpose64_bf16(T64Job j0, T64Job j1, int64_t R, hipStream_t s);
 hipError_t launch_gather(const double* X, int64_t N, int32_t n, const int32_t* idx, int64_t rows, int32_t d_pad,
                          uint16_t* out, hipStream_t s);
 // sum over z < n_slabs, in order, of slabs[z * stride + t], t < count, into
 // out[t] for t < split and out2[t - split] above.
 hipError_t launch_sum_slabs(const float* slabs, int32_t n_slabs, int64_t count, int64_t stride, float* out,
                             int64_t split, float* out2, hipStream_t s);
-// rows x cols bf16 (cols % 8 == 0): row 0 all ones, the other rows zeros.
-hipError_t launch_ones_row_bf16(uint16_t* out, int64_t rows, int64_t cols, hipStream_t s);
+
 hipError_t launch_pair_head(const float* E, int64_t P, int32_t d, const float* target, const float* ab,
                             int32_t loss_kind, uint16_t* dE16, float* partial, float* out3, hipStream_t s);
 // Log-domain head: per pair loss and gradient (pair_head_log + the fixed-order

@@ -21,7 +21,7 @@
 //   stores).
 // * gather_features: FP64 feature rows -> zero-padded BF16 rows.
 // * transpose_bf16: the forward pass's k-contiguous copy of each weight.
-// * transpose64_bf16, ones_row_bf16, sum_slabs: the weight gradients' operands
+// * transpose64_bf16, sum_slabs: the weight gradients' operands
 //   copied k-contiguous (the activations with a row of ones appended, whose
 //   product row is the bias gradient) and the fixed-order reduction of their
 //   split-K partial products.
@@ -749,32 +749,46 @@ sat_log_gram_kernel(const uint16_t* __restrict__ X16, int32_t d_in, const uint16
   }
 }
 
-// out (C x R, row stride R) = in (R x C, row stride C)^T for one large bf16
-// matrix, R and C multiples of 8: 64 x 64 tiles, 16-byte loads and stores
-// (each thread two pieces of 8 values each way) through a padded LDS tile.
-__global__ void __launch_bounds__(256) transpose64_bf16(const uint16_t* __restrict__ in, int64_t R, int64_t C,
-                                                       uint16_t* __restrict__ out) {
+// out (Cp x R, row stride R) = in (R x C, row stride C)^T for two large bf16
+// matrices with the same R (R, C multiples of 8; C and Cp multiples of 64):
+// output rows C .. Cp - 1 hold a row of ones, then zeros.  Block row
+// blockIdx.y < y0 belongs to job 0, the others to job 1.  64 x 64 tiles,
+// 16-byte loads and stores (each thread two pieces of 8 values each way)
+// through a padded LDS tile.
+__global__ void __launch_bounds__(256) transpose64_bf16(T64Job j0, T64Job j1, int64_t R, int32_t y0) {
   constexpr int TP = 64 + 8;  // LDS row (bf16): 144 bytes, 16-byte aligned
   __shared__ __attribute__((aligned(16))) uint16_t tile[64 * TP];
   const int t = threadIdx.x;
-  const int64_t r0 = int64_t(blockIdx.x) * 64, c0 = int64_t(blockIdx.y) * 64;
+  const bool second = int32_t(blockIdx.y) >= y0;
+  const T64Job& j = second ? j1 : j0;
+  const int64_t r0 = int64_t(blockIdx.x) * 64, c0 = int64_t(second ? blockIdx.y - y0 : blockIdx.y) * 64;
+  if (c0 >= j.C) {  // padding rows of the output (uniform per block)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int p = t + 256 * h, oc = p >> 3, pr = (p & 7) * 8;
+      const uint32_t w = (c0 + oc == j.C) ? 0x3F803F80u : 0u;  // bf16 1.0 twice
+      if (c0 + oc < j.Cp && r0 + pr < R)
+        *reinterpret_cast<uint4*>(j.out + (c0 + oc) * R + r0 + pr) = make_uint4(w, w, w, w);
+    }
+    return;
+  }
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int p = t + 256 * h, row = p >> 3, pc = (p & 7) * 8;
     uint4 v = make_uint4(0u, 0u, 0u, 0u);
-    if (r0 + row < R && c0 + pc < C) v = *reinterpret_cast<const uint4*>(in + (r0 + row) * C + c0 + pc);
+    if (r0 + row < R && c0 + pc < j.C) v = *reinterpret_cast<const uint4*>(j.in + (r0 + row) * j.C + c0 + pc);
     *reinterpret_cast<uint4*>(&tile[row * TP + pc]) = v;
   }
   __syncthreads();
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int p = t + 256 * h, oc = p >> 3, pr = (p & 7) * 8;  // output row c0 + oc, its values r0 + pr ..
-    if (c0 + oc < C && r0 + pr < R) {
+    if (c0 + oc < j.C && r0 + pr < R) {
       uint32_t w[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e)
         w[e] = uint32_t(tile[(pr + 2 * e) * TP + oc]) | (uint32_t(tile[(pr + 2 * e + 1) * TP + oc]) << 16);
-      *reinterpret_cast<uint4*>(out + (c0 + oc) * R + r0 + pr) = make_uint4(w[0], w[1], w[2], w[3]);
+      *reinterpret_cast<uint4*>(j.out + (c0 + oc) * R + r0 + pr) = make_uint4(w[0], w[1], w[2], w[3]);
     }
   }
 }
@@ -845,14 +859,6 @@ __global__ void sum_slabs(const float* __restrict__ slabs, int32_t n_slabs, int6
     out[t] = s;
   else
     out2[t - split] = s;
-}
-
-// rows x cols bf16 (cols % 8 == 0): row 0 ones, the others zeros.
-__global__ void __launch_bounds__(256) ones_row_bf16(uint16_t* __restrict__ out, int64_t rows, int64_t cols) {
-  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x, per_row = cols / 8;
-  if (p >= rows * per_row) return;
-  const uint32_t w = (p < per_row) ? 0x3F803F80u : 0u;  // bf16 1.0 twice
-  *reinterpret_cast<uint4*>(out + p * 8) = make_uint4(w, w, w, w);
 }
 
 __device__ __forceinline__ float softplusf(float z) {  // log(1 + e^z), no overflow
@@ -952,9 +958,11 @@ __global__ void __launch_bounds__(256) pair_head_log(const uint16_t* __restrict_
 }
 
 // out[0] = mean per-pair loss, out[1] = d loss / d alpha, out[2] = d loss / d beta.
-__global__ void __launch_bounds__(256) reduce_partials(const float* __restrict__ partial, int64_t P, float* __restrict__ out) {
-  __shared__ double s[3][256];
+__global__ void __launch_bounds__(1024) reduce_partials(const float* __restrict__ partial, int64_t P,
+                                                        float* __restrict__ out) {
+  __shared__ double s[3][1024];
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll 4
   for (int64_t p = threadIdx.x; p < P; p += blockDim.x) {
     a0 += partial[3 * p];
     a1 += partial[3 * p + 1];
@@ -964,7 +972,7 @@ __global__ void __launch_bounds__(256) reduce_partials(const float* __restrict__
   s[1][threadIdx.x] = a1;
   s[2][threadIdx.x] = a2;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
+  for (int w = 512; w > 0; w >>= 1) {
     if (int(threadIdx.x) < w)
       for (int q = 0; q < 3; ++q) s[q][threadIdx.x] += s[q][threadIdx.x + w];
     __syncthreads();
@@ -1129,10 +1137,13 @@ hipError_t launch_sigmoid_gram(const uint16_t* E, int64_t N_pad, int32_t d, cons
   return hipGetLastError();
 }
 
-hipError_t launch_transpose64_bf16(const uint16_t* in, int64_t R, int64_t C, uint16_t* out, hipStream_t s) {
-  if (R < 1 || C < 1 || R % 8 || C % 8 || (R + 63) / 64 > INT32_MAX || (C + 63) / 64 > 65535) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(transpose64_bf16, dim3(unsigned((R + 63) / 64), unsigned((C + 63) / 64)), dim3(256), 0, s, in, R,
-                     C, out);
+hipError_t launch_transpose64_bf16(T64Job j0, T64Job j1, int64_t R, hipStream_t s) {
+  auto bad = [](const T64Job& j) { return j.C < 64 || j.C % 64 || j.Cp < j.C || j.Cp % 64; };
+  if (R < 1 || R % 8 || bad(j0) || bad(j1) || (R + 63) / 64 > INT32_MAX || (j0.Cp + j1.Cp) / 64 > 65535)
+    return hipErrorInvalidValue;
+  const int32_t y0 = int32_t(j0.Cp / 64);
+  hipLaunchKernelGGL(transpose64_bf16, dim3(unsigned((R + 63) / 64), unsigned(y0 + j1.Cp / 64)), dim3(256), 0, s, j0,
+                     j1, R, y0);
   return hipGetLastError();
 }
 
@@ -1166,13 +1177,6 @@ hipError_t launch_sum_slabs(const float* slabs, int32_t n_slabs, int64_t count, 
   return hipGetLastError();
 }
 
-hipError_t launch_ones_row_bf16(uint16_t* out, int64_t rows, int64_t cols, hipStream_t s) {
-  if (rows < 1 || cols < 8 || cols % 8) return hipErrorInvalidValue;
-  const int64_t pieces = rows * (cols / 8);
-  hipLaunchKernelGGL(ones_row_bf16, dim3(unsigned((pieces + 255) / 256)), dim3(256), 0, s, out, rows, cols);
-  return hipGetLastError();
-}
-
 hipError_t launch_pair_head(const float* E, int64_t P, int32_t d, const float* target, const float* ab,
                             int32_t loss_kind, uint16_t* dE16, float* partial, float* out3, hipStream_t s) {
   const int64_t threads = P * 64;
@@ -1180,7 +1184,7 @@ hipError_t launch_pair_head(const float* E, int64_t P, int32_t d, const float* t
                      loss_kind, dE16, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, s, partial, P, out3);
+  hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(1024), 0, s, partial, P, out3);
   return hipGetLastError();
 }
 
@@ -1192,7 +1196,7 @@ hipError_t launch_pair_head_log(const uint16_t* X16, int32_t d_in, const float* 
                      target, head, scale, dE16, partial, pred);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, s, partial, P, out3);
+  hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(1024), 0, s, partial, P, out3);
   return hipGetLastError();
 }
 

@@ -122,9 +122,8 @@ hipError_t grad_gemm(int64_t M, int64_t N, int64_t rows, const void* A, const vo
   const int32_t splits = grad_splits(Mp, N, rows);
   uint16_t* at = reinterpret_cast<uint16_t*>(ws + int64_t(splits) * Mp * N);  // 16-byte aligned: Mp, N % 64 == 0
   uint16_t* bt = at + Mp * rows;
-  hipError_t e = qsvm::launch_transpose64_bf16(static_cast<const uint16_t*>(A), rows, M, at, st);
-  if (e == hipSuccess) e = qsvm::launch_ones_row_bf16(at + M * rows, Mp - M, rows, st);
-  if (e == hipSuccess) e = qsvm::launch_transpose64_bf16(static_cast<const uint16_t*>(B), rows, N, bt, st);
+  hipError_t e = qsvm::launch_transpose64_bf16({static_cast<const uint16_t*>(A), at, M, Mp},
+                                                {static_cast<const uint16_t*>(B), bt, N, N}, rows, st);
   if (e != hipSuccess) return e;
   qsvm::GemmArgs g = gemm(Mp, N, rows, at, rows, bt, rows, ws, nullptr, N);
   g.splits = splits;

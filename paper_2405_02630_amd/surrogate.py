@@ -87,6 +87,36 @@ class _Param:
         self.w16 = torch.empty(self.w.shape, dtype=torch.bfloat16, device=dev) if bf16 else None
 
 
+class _ParamSet:
+    """Several parameters in one flat FP32 buffer (each a view), with flat
+    AdamW moments, gradients and BF16 copies: one AdamW launch updates them
+    all (the same hyper-parameters apply to every tensor)."""
+
+    def __init__(self, hosts, dev):
+        import torch
+
+        sizes = [int(np.asarray(h).size) for h in hosts]
+        total = sum(sizes)
+        self.w = torch.empty(total, dtype=torch.float32, device=dev)
+        self.m = torch.zeros_like(self.w)
+        self.v = torch.zeros_like(self.w)
+        self.g = torch.zeros_like(self.w)
+        self.w16 = torch.empty(total, dtype=torch.bfloat16, device=dev)
+        self.views = []
+        off = 0
+        for h, n in zip(hosts, sizes):  # offsets stay multiples of 8 (the widths are multiples of 64)
+            h = np.asarray(h, dtype=np.float32)
+            self.w[off:off + n].copy_(torch.from_numpy(np.ascontiguousarray(h).ravel()))
+            view = _Param.__new__(_Param)
+            view.w = self.w[off:off + n].view(h.shape)
+            view.m = self.m[off:off + n].view(h.shape)
+            view.v = self.v[off:off + n].view(h.shape)
+            view.g = self.g[off:off + n].view(h.shape)
+            view.w16 = self.w16[off:off + n].view(h.shape)
+            self.views.append(view)
+            off += n
+
+
 class Surrogate:
     def __init__(self, n_features: int, cfg: SurrogateConfig | None = None, device="cuda:0"):
         import torch
@@ -105,18 +135,15 @@ class Surrogate:
 
         W1 = he(self.d_in, c.d_h1)
         W1[n_features:] = 0.0  # padded input columns carry no weight
-        self.params = [
-            _Param(W1, self.dev, True), _Param(np.zeros(c.d_h1), self.dev, False),
-            _Param(he(c.d_h1, c.d_h2), self.dev, True), _Param(np.zeros(c.d_h2), self.dev, False),
-            _Param(c.out_init * he(c.d_h2, c.d_out, gain=1.0), self.dev, True), _Param(np.zeros(c.d_out), self.dev, False),
-        ]
+        self.pset = _ParamSet([W1, np.zeros(c.d_h1), he(c.d_h1, c.d_h2), np.zeros(c.d_h2),
+                               c.out_init * he(c.d_h2, c.d_out, gain=1.0), np.zeros(c.d_out)], self.dev)
+        self.params = self.pset.views  # W1, b1, W2, b2, W3, b3
         self.head = _Param(np.array([0.0, 0.0]), self.dev, False)  # (log c, log s), set by init_head
         self.margin = 0.0
         self.step = 0
         # BF16 copies of the initial weights: an AdamW step with lr = 0 and zero gradient
-        for p in self.params:
-            if p.w16 is not None:
-                qsvm.qsvm_adamw(p.w, p.g, p.m, p.v, p.w16, 0.0, c.beta1, c.beta2, c.eps, 0.0, 1)
+        ps = self.pset
+        qsvm.qsvm_adamw(ps.w, ps.g, ps.m, ps.v, ps.w16, 0.0, c.beta1, c.beta2, c.eps, 0.0, 1)
         self._bufs = {}
 
     # ------------------------------------------------------------------
@@ -190,8 +217,8 @@ class Surrogate:
         if train:
             qsvm.qsvm_mlp_backward(net, b["X16"], acts, b["dE16"], rows, self._grads(b))
             self.step += 1
-            for p in self.params:
-                qsvm.qsvm_adamw(p.w, p.g, p.m, p.v, p.w16, c.lr, c.beta1, c.beta2, c.eps, c.weight_decay, self.step)
+            ps = self.pset  # every weight and bias in one launch
+            qsvm.qsvm_adamw(ps.w, ps.g, ps.m, ps.v, ps.w16, c.lr, c.beta1, c.beta2, c.eps, c.weight_decay, self.step)
             qsvm.qsvm_adamw(self.head.w, b["out3"][1:], self.head.m, self.head.v, None, c.lr_head, c.beta1,
                             c.beta2, c.eps, 0.0, self.step)
         return b
