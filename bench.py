@@ -37,6 +37,7 @@ default) add their own objects to the line:
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--reps 1..6]
                        [--sweep butterfly|dense] [--legs exact,reps3,deep,...]
                        [--no-cpu-baseline] [--cpu-sample P] [--copy-calibration MiB]
+                       [--surrogate-gram-only N]
 """
 
 from __future__ import annotations
@@ -571,6 +572,47 @@ def mlp_leg(args, rows: int = 32768, reps_timed: int = 5):
     return res
 
 
+def surrogate_gram_only(N: int):
+    """The prediction Gram alone: N synthetic embeddings z = [x (832 wide, uniform
+    pixels in [0, 1]), e (256 wide, N(0, 0.01))] in BF16, head (c, s) = (30, 0.2);
+    two warm-up and five timed calls of qsvm_surrogate_gram_log, then three
+    timed plain fills of the same FP64 K (its write bound)."""
+    import torch
+
+    from paper_2405_02630_amd import qsvm
+
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev)
+    g.manual_seed(0)
+    Np = (N + 63) // 64 * 64
+    X16 = torch.rand((Np, 832), device=dev, generator=g).to(torch.bfloat16)
+    E16 = (torch.randn((Np, 256), device=dev, generator=g) * 0.1).to(torch.bfloat16)
+    head = torch.tensor([math.log(30.0), math.log(0.2)], dtype=torch.float32, device=dev)
+    K = torch.empty((N, N), dtype=torch.float64, device=dev)
+    T = Np // 64
+    tile_max = torch.empty(T * T, dtype=torch.float32, device=dev)
+    for _ in range(2):
+        qsvm.qsvm_surrogate_gram_log(X16, E16, N, head, K, tile_max)
+    torch.cuda.synchronize()
+    ev = _events(2)
+    gram_ms = []
+    for _ in range(5):
+        ev[0].record()
+        qsvm.qsvm_surrogate_gram_log(X16, E16, N, head, K, tile_max)
+        ev[1].record()
+        torch.cuda.synchronize()
+        gram_ms.append(ev[0].elapsed_time(ev[1]))
+    fill_ms = []
+    for _ in range(3):
+        ev[0].record()
+        K.fill_(0.5)
+        ev[1].record()
+        torch.cuda.synchronize()
+        fill_ms.append(ev[0].elapsed_time(ev[1]))
+    return {"surrogate_gram_only": N, "K_bytes": N * N * 8, "gram_ms": [round(x, 4) for x in gram_ms],
+            "fill_ms": [round(x, 4) for x in fill_ms]}
+
+
 def svm_accuracies(K_exact, K_sur, labels, n_train_frac=0.75):
     """One-vs-rest SVM on a precomputed Gram: train on the first 75 %, test on the rest."""
     import numpy as np
@@ -773,6 +815,10 @@ def main():
     ap.add_argument("--sur-steps", type=int, default=600)
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="run only a plain device copy of this many MiB (for HBM counter scaling)")
+    ap.add_argument("--surrogate-gram-only", type=int, default=0, metavar="N",
+                    help="run only the surrogate's prediction Gram (qsvm_surrogate_gram_log) on N synthetic "
+                         "embeddings of the production widths, 5 timed calls, and a plain fill of the same K "
+                         "(for its kernel's counters and write bound)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -797,6 +843,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": nbytes, "launches": 3}))
+        return
+    if args.surrogate_gram_only:
+        print(json.dumps(surrogate_gram_only(args.surrogate_gram_only)))
         return
 
     reps = args.reps

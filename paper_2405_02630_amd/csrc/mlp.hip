@@ -533,7 +533,7 @@ __device__ __forceinline__ void upper_index(int64_t st, int64_t S, int64_t* is, 
 // panels of a super-tile are read from its L2 once instead of once per
 // block).  The row norms come precomputed (sat_row_norms).  Rows past N_pad
 // (an odd tile count) are clamped on load and never stored.
-constexpr int SG_G = 8;       // super-tile side, in 128-row blocks
+constexpr int SG_G = 8;  // super-tile side, in 128-row blocks (4 and 16 measured the same)
 constexpr int SG_P = 34;      // doubles per row of a wave's transpose tile (16-byte aligned rows)
 constexpr int SG_KS = 1;  // 32-deep slices per K step
 constexpr int SG_OPER = 2 * SG_KS * 2 * 128 * DL_PR * 16;  // two buffers of both operands, bytes
@@ -555,11 +555,11 @@ sat_log_gram_kernel(const uint16_t* __restrict__ X16, int32_t d_in, const uint16
   const int wm = wave >> 1, wn = wave & 1;
   const int64_t T2 = (N_pad + 127) / 128, S = (T2 + SG_G - 1) / SG_G;
   // consecutive blocks of one XCD (hardware ids b, b + 8, ...) take consecutive u
-  const uint32_t nb = gridDim.x;  // 64 per super-tile
+  const uint32_t nb = gridDim.x;  // SG_G^2 per super-tile, a multiple of 8
   const uint32_t u = (blockIdx.x & 7u) * (nb >> 3) + (blockIdx.x >> 3);
   int64_t is, js;
-  upper_index(int64_t(u >> 6), S, &is, &js);
-  const int64_t I = is * SG_G + ((u >> 3) & 7), J = js * SG_G + (u & 7);
+  upper_index(int64_t(u / (SG_G * SG_G)), S, &is, &js);
+  const int64_t I = is * SG_G + (u % (SG_G * SG_G)) / SG_G, J = js * SG_G + u % SG_G;
   if (I > J || J >= T2) return;  // the lower half of a diagonal super-tile, or past the last block
   const int64_t m0 = I * 128, n0 = J * 128;
   const int dtot = d_in + d;
