@@ -349,6 +349,19 @@ struct WLayout {
 // butterflies; a lane bit B pairs lane l with lane l ^ 2^B: the lane without
 // the bit computes u0 + a u1, the lane with it +-(u0 + b u1), each from its
 // own value and its partner's (xor_lane), the same operations as dbfly.
+// x of the lane of l's pair (l, l ^ 2^B) without bit B (HI = false) or with
+// it (HI = true), B = 0, 1: a DPP quad permutation that hands both lanes the
+// same value, so neither has to select between its own and its partner's.
+template <int B, bool HI>
+__device__ __forceinline__ double pair_lane(double x) {
+  static_assert(B <= 1, "quad permutations cover lane bits 0 and 1");
+  // quad_perm [0,0,2,2] / [1,1,3,3] (bit 0), [0,1,0,1] / [2,3,2,3] (bit 1)
+  constexpr int ctrl = (B == 0) ? (HI ? 0xF5 : 0xA0) : (HI ? 0xEE : 0x44);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), ctrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), ctrl, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
 // x of lane l ^ 2^B: a DPP quad permutation for B = 0, 1 (no trip through
 // the LDS crossbar), __shfl_xor above.
 template <int B>
@@ -383,9 +396,15 @@ __device__ __forceinline__ void group_axis(double2 (&v)[E], int lane, double ar,
     const double cr = upper ? br : ar, ci = upper ? bi : ai;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const double pr = xor_lane<B>(v[e].x), pim = xor_lane<B>(v[e].y);
-      const double2 u0 = upper ? make_double2(pr, pim) : v[e];
-      const double2 u1 = upper ? v[e] : make_double2(pr, pim);
+      double2 u0, u1;  // the entries of the lanes without and with bit B
+      if constexpr (B <= 1) {
+        u0 = make_double2(pair_lane<B, false>(v[e].x), pair_lane<B, false>(v[e].y));
+        u1 = make_double2(pair_lane<B, true>(v[e].x), pair_lane<B, true>(v[e].y));
+      } else {
+        const double pr = xor_lane<B>(v[e].x), pim = xor_lane<B>(v[e].y);
+        u0 = upper ? make_double2(pr, pim) : v[e];
+        u1 = upper ? v[e] : make_double2(pr, pim);
+      }
       double tr = fma(cr, u1.x, u0.x);
       tr = fma(-ci, u1.y, tr);
       double ti = fma(cr, u1.y, u0.y);
