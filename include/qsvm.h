@@ -301,8 +301,8 @@ qsvm_status qsvm_gram_sym_tiles_dev(const void* mps, int64_t N, int32_t n_qubits
  * opts->log_k) are written with an FP64 environment from FP64 generators
  * (Sections G + L): the value the refinement (opts.refine_above) writes for
  * that entry, bit for bit.  i == j follows opts->diag_mode.  One pair per
- * lane (reps <= 3) or per wave (reps >= 4), waves striding over the list;
- * the host never reads the count.  The exact fallback of the surrogate for
+ * group of 2 lanes (reps 1), 4 lanes (reps 2, 3) or per wave (reps >= 4),
+ * the list's chunks spread over the blocks; the host never reads the count.  The exact fallback of the surrogate for
  * flagged pairs (qsvm_flag_pairs).  opts row ranges must be 0,0; sweep,
  * variant and refine_above are ignored.
  */
