@@ -14,6 +14,9 @@ default) add their own objects to the line:
                   training images (`test_by_train`: encode of the test MPS +
                   rectangular Gram per step);
   reps3        -- both Grams again at reps = 3 (bond dimension 8);
+  mixture64    -- 1024 points of a 10-class Gaussian mixture in R^64, reps = 2:
+                  encode + symmetric Gram (the refinement recomputes the
+                  entries above the 64-qubit threshold);
   deep         -- the split sweep at reps 4, 5 and 6 (bond dimensions 16, 32,
                   64): symmetric Grams of 2048, 1024 and 512 images;
   refine_worst -- 4096 near-identical images, every tile refined in FP64,
@@ -283,6 +286,73 @@ def exact_reps_leg(reps, n_train, args, kinds=("sym", "test_by_train"), steps=No
     del K, Kr, buf
     torch.cuda.empty_cache()
     return out
+
+
+def mixture64_leg(args, steps=None):
+    """The 64-qubit workload: 1024 points of the 10-class Gaussian mixture in
+    R^64 (reps = 2), encode + symmetric Gram per step, the sweep's fraction of
+    the FP32 vector peak, the entries the refinement recomputed (K above the
+    64-qubit threshold), and, outside the timed region, max|dK| against the
+    same Gram with every entry recomputed in FP64 (refine_above = 1e-300;
+    the parity tests check this workload against the oracle)."""
+    steps = args.steps if steps is None else steps
+    import numpy as np
+    import torch
+
+    from paper_2405_02630_amd import qsvm, synth
+
+    dev = torch.device("cuda:0")
+    wl = synth.mixture64(seed=0)
+    N, n = wl.X.shape
+    X = torch.as_tensor(wl.X, dtype=torch.float64, device=dev)
+    buf = torch.empty(qsvm.qsvm_mps_bytes(N, n, wl.reps), dtype=torch.uint8, device=dev)
+    K = torch.empty((N, N), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        m = qsvm.qsvm_encode_mps(X, wl.reps, out=buf)
+        if ev is not None:
+            ev[0].record(stream)
+        qsvm.qsvm_gram_sym(m, K)
+        if ev is not None:
+            ev[1].record(stream)
+
+    for _ in range(max(1, args.warmup)):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for st in range(steps):
+        step(evs[st])
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    gram_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    pairs = N * (N - 1) // 2
+    flops = sweep_flops_per_pair(n, wl.reps, "butterfly") * pairs
+    Kh = K.cpu().numpy()
+    thresh = qsvm.qsvm_auto_refine_threshold(n)
+    iu = np.triu_indices(N, 1)
+    K64 = qsvm.qsvm_gram_sym(qsvm.qsvm_encode_mps(X, wl.reps), refine_above=1e-300).cpu().numpy()
+    res = {
+        "workload": f"mixture-n{n}-r{wl.reps}-N{N}-sym (10-class Gaussian mixture in R^64)",
+        "pairs_per_step": pairs,
+        "ms_per_step": ms,
+        "value": pairs / (ms / 1e3),
+        "unit": "entries/s",
+        "gram_ms": round(gram_ms, 4),
+        "gram_frac_of_fp32_peak": round(flops / (gram_ms / 1e3) / 1e12 / PEAK_FP32_VECTOR_TFLOPS, 4),
+        "K_max_offdiag": float(np.max(Kh[iu])),
+        "entries_above_refine_threshold": int(np.count_nonzero(Kh[iu] > thresh)),
+        "refine_threshold": thresh,
+        "max_abs_dK_vs_fp64_sweep": float(np.max(np.abs(Kh[iu] - K64[iu]))),
+        "step": "encode MPS + symmetric Gram (sweep, tile scan and FP64 refinement of the entries above the threshold)",
+    }
+    log(f"mixture64: {ms:.3f} ms/step, Gram {gram_ms:.3f} ms ({res['gram_frac_of_fp32_peak']:.3f} of peak in "
+        f"sweep flops), {res['value']:.4e} entries/s; {res['entries_above_refine_threshold']} entries above "
+        f"{thresh:.3f} refined; max|dK| vs the FP64 sweep {res['max_abs_dK_vs_fp64_sweep']:.2e}")
+    del K, buf
+    torch.cuda.empty_cache()
+    return res
 
 
 def refine_worst_leg(args, reps: int = 2, N: int = 4096, cores: int = 8):
@@ -810,7 +880,7 @@ def main():
     ap.add_argument("--renorm-every", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=720)
-    ap.add_argument("--legs", default="exact,reps3,deep,refine_worst,mlp,surrogate,batched,sv")  # "exact" adds the test x train Gram
+    ap.add_argument("--legs", default="exact,reps3,mixture64,deep,refine_worst,mlp,surrogate,batched,sv")  # "exact" adds the test x train Gram
     ap.add_argument("--sur-points", type=int, default=32768)
     ap.add_argument("--sur-steps", type=int, default=600)
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -943,6 +1013,8 @@ def main():
         # 2048, 1024 and 512 images; at most 3 timed steps each)
         out["deep_reps"] = {f"reps{r}": exact_reps_leg(r, pts, args, kinds=("sym",), steps=min(args.steps, 3))["sym"]
                             for r, pts in ((4, 2048), (5, 1024), (6, 512))}
+    if "mixture64" in legs:
+        out["mixture64"] = mixture64_leg(args)
     if "refine_worst" in legs:
         out["refine_worst"] = refine_worst_leg(args)
     if "mlp" in legs:
