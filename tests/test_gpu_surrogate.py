@@ -542,7 +542,7 @@ def test_gather_features_matches_torch_conversion(N, n, d_pad):
     assert torch.equal(out.cpu().view(torch.int16), ref.view(torch.int16))
 
 
-@pytest.mark.parametrize("reps", [1, 2, 3, 4])
+@pytest.mark.parametrize("reps", [1, 2, 3, 4, 5, 6])
 def test_gram_sym_pairs_dev_writes_the_fp64_entries(reps):
     """Listed pairs (either order, duplicates, the diagonal, invalid indices
     and entries past the count among them) get exactly the FP64 value the
