@@ -624,3 +624,28 @@ def test_pair_fallback_validation(lib, no_inject):
     assert flag(cap=4097) == qsvm.QSVM_ERR_INVALID_ARG
     assert flag(maxt=1 << 20, cap=4096) == qsvm.QSVM_ERR_INVALID_ARG  # reservations could pass 2^31
     assert flag(maxp=-1) == qsvm.QSVM_ERR_INVALID_ARG
+
+
+def test_surrogate_gram_log_validation(lib, no_inject):
+    head = FAKE2
+
+    def gram(X16=FAKE, d_in=832, E16=FAKE, d=256, N=100, N_pad=128, K=FAKE2, ldk=100, tmax=FAKE2):
+        return lib.qsvm_surrogate_gram_log(X16, d_in, E16, d, N, N_pad, head, K, ldk, tmax, None)
+
+    assert gram(E16=None) == qsvm.QSVM_ERR_INVALID_ARG
+    assert gram(K=None) == qsvm.QSVM_ERR_INVALID_ARG
+    assert gram(X16=None) == qsvm.QSVM_ERR_INVALID_ARG  # an input part needs its rows
+    assert gram(N_pad=96) == qsvm.QSVM_ERR_INVALID_ARG  # N_pad % 64
+    assert gram(N_pad=192) == qsvm.QSVM_ERR_INVALID_ARG  # N_pad >= N + 64
+    assert gram(d_in=48) == qsvm.QSVM_ERR_INVALID_ARG
+    assert gram(d=16) == qsvm.QSVM_ERR_INVALID_ARG
+    assert gram(ldk=99) == qsvm.QSVM_ERR_INVALID_ARG
+    big = (1 << 19) + 64  # one block per 128 x 128 piece of the upper triangle: N_pad <= 2^19
+    assert gram(N=big, N_pad=big, ldk=big) == qsvm.QSVM_ERR_UNSUPPORTED
+    os.environ["QSVM_FAULT_INJECT"] = "launch"
+    try:  # valid arguments, without and with the input part, reach the launch
+        assert gram() == qsvm.QSVM_ERR_HIP
+        assert gram(X16=None, d_in=0) == qsvm.QSVM_ERR_HIP
+        assert gram(N=1 << 19, N_pad=1 << 19, ldk=1 << 19) == qsvm.QSVM_ERR_HIP
+    finally:
+        del os.environ["QSVM_FAULT_INJECT"]
