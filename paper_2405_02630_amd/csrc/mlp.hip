@@ -62,10 +62,15 @@ constexpr int GEMM_LDS_STRIDE = GBK + 8;  // its LDS row, 16-byte pad
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
 
-__device__ __forceinline__ uint16_t f32_to_bf16(float f) {  // round to nearest even
-  uint32_t u = __float_as_uint(f);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return uint16_t(u >> 16);
+// Round to nearest even through the hardware conversion (v_cvt_pk_bf16_f32,
+// two values per instruction in bf16_pair).
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) { return __builtin_bit_cast(uint16_t, static_cast<__bf16>(f)); }
+
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t bf16_pair(float lo, float hi) {
+  const f32x2_t v = {lo, hi};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
 }
 
 // Standard normal CDF Phi(x) without branches, through the complementary
@@ -91,7 +96,28 @@ __device__ __forceinline__ float normal_cdf(float x) {
   return (x >= 0.0f) ? 1.0f - h : h;
 }
 
-__device__ __forceinline__ float gelu(float x) { return x * normal_cdf(x); }
+// GELU x Phi(x) written as max(x, 0) - |x| Q(|x|) with the normal tail
+// Q(u) = Phi(-u) = exp2(R(min(u, 5)) - k u): R(v) = log2 Q(v) + k v is a
+// degree-8 polynomial (Chebyshev least-squares fit on [0, 5], refitted to the
+// power basis) and k = 7.4825435 is the slope of -log2 Q at u = 5, so the
+// tail beyond 5 continues as the tangent of log2 Q there (relative error of Q
+// below 2e-6 on [0, 5] once the argument of exp2 is rounded to FP32; beyond
+// 5, |x| Q is below 1.5e-8 absolute).  One transcendental and no reciprocal
+// or select: the forward epilogues are bound by these instructions.
+__device__ __forceinline__ float gelu(float x) {
+  const float u = fabsf(x), v = fminf(u, 5.0f);
+  float p = -2.5299283e-07f;
+  p = fmaf(p, v, 3.276253e-06f);
+  p = fmaf(p, v, 1.9859166e-05f);
+  p = fmaf(p, v, -0.0007542323f);
+  p = fmaf(p, v, 0.008099142f);
+  p = fmaf(p, v, -0.053451717f);
+  p = fmaf(p, v, -0.45876977f);
+  p = fmaf(p, v, 6.331361f);
+  p = fmaf(p, v, -0.99999774f);
+  const float q = __builtin_amdgcn_exp2f(fmaf(u, -7.4825435f, p));
+  return fmaf(-u, q, fmaxf(x, 0.0f));
+}
 
 __device__ __forceinline__ float gelu_grad(float x) {
   const float pdf = 0.39894228040143268f * __expf(-0.5f * x * x);
@@ -242,31 +268,46 @@ __device__ __forceinline__ int dl_swizzle(int row) { return (((row >> 1) ^ (row 
 
 // Epilogue of one 32 x 32 accumulator whose top-left output is (r0, c0):
 // element v is row r0 + (v/4)*8 + (lane/32)*4 + v%4, column c0 + lane%32.
+// Elements v and v + 1 (rows r and r + 1) share one BF16 conversion.
 template <int EPI>
 __device__ __forceinline__ void gemm_store32(const GemmArgs& g, const f32x16_t& acc, int64_t r0, int64_t c0, int lane) {
   const int64_t c = c0 + (lane & 31);
+  float* const Cf = static_cast<float*>(g.C);
+  uint16_t* const C2 = static_cast<uint16_t*>(g.C2);
+  const bool has_bias = EPI == EPI_BIAS_GELU || EPI == EPI_BIAS || EPI == EPI_BIAS_GELU_BF16 || EPI == EPI_BIAS_BF16;
+  const float bc = has_bias ? g.bias[c] : 0.0f;
 #pragma unroll
-  for (int v = 0; v < 16; ++v) {
+  for (int v = 0; v < 16; v += 2) {
     const int64_t r = r0 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
-    const float x = acc[v];
+    const int64_t o0 = r * g.ldc + c, o1 = o0 + g.ldc;
+    const float x0 = acc[v], x1 = acc[v + 1];
+    uint32_t q = 0;
     if (EPI == EPI_F32) {
-      static_cast<float*>(g.C)[int64_t(blockIdx.z) * g.M * g.ldc + r * g.ldc + c] = x;
-    } else if (EPI == EPI_BIAS_GELU) {
-      const float h = x + g.bias[c];
-      static_cast<float*>(g.C)[r * g.ldc + c] = h;
-      static_cast<uint16_t*>(g.C2)[r * g.ldc + c] = f32_to_bf16(gelu(h));
+      const int64_t z = int64_t(blockIdx.z) * g.M * g.ldc;
+      Cf[z + o0] = x0;
+      Cf[z + o1] = x1;
+      continue;
     } else if (EPI == EPI_BIAS) {
-      const float h = x + g.bias[c];
-      static_cast<float*>(g.C)[r * g.ldc + c] = h;
-      static_cast<uint16_t*>(g.C2)[r * g.ldc + c] = f32_to_bf16(h);
+      const float h0 = x0 + bc, h1 = x1 + bc;
+      Cf[o0] = h0;
+      C2[o0] = f32_to_bf16(h0);
+      Cf[o1] = h1;
+      C2[o1] = f32_to_bf16(h1);
+      continue;
+    } else if (EPI == EPI_BIAS_GELU) {
+      const float h0 = x0 + bc, h1 = x1 + bc;
+      q = bf16_pair(gelu(h0), gelu(h1));
+      Cf[o0] = h0;
+      Cf[o1] = h1;
     } else if (EPI == EPI_GELU_BWD) {
-      const float d = x * gelu_grad(g.aux[r * g.ldc + c]);
-      static_cast<uint16_t*>(g.C2)[r * g.ldc + c] = f32_to_bf16(d);
+      q = bf16_pair(x0 * gelu_grad(g.aux[o0]), x1 * gelu_grad(g.aux[o1]));
     } else if (EPI == EPI_BIAS_GELU_BF16) {
-      static_cast<uint16_t*>(g.C2)[r * g.ldc + c] = f32_to_bf16(gelu(x + g.bias[c]));
+      q = bf16_pair(gelu(x0 + bc), gelu(x1 + bc));
     } else if (EPI == EPI_BIAS_BF16) {
-      static_cast<uint16_t*>(g.C2)[r * g.ldc + c] = f32_to_bf16(x + g.bias[c]);
+      q = bf16_pair(x0 + bc, x1 + bc);
     }
+    C2[o0] = uint16_t(q);
+    C2[o1] = uint16_t(q >> 16);
   }
 }
 
