@@ -4,10 +4,11 @@
 // distance of the embeddings [x, f(x)], ln K_hat = -c (1 - exp(-s d2)), or as
 // K_hat(x, y) = sigmoid(alpha <f(x), f(y)> + beta).
 //
-// * bf16_gemm_dl<MT, EPI>: the same product for k-contiguous operands on
-//   256 x 128 or 128 x 128 tiles, operands moved global -> LDS by the DMA
-//   loads (global_load_lds_dwordx4), double-buffered; used whenever M and N
-//   are multiples of 128 (the forward layers and the activation gradients).
+// * bf16_gemm_dl<MT, WN, BK, EPI>: the same product for k-contiguous
+//   operands on 256 x 256 (8 waves, 64-deep K steps), 256 x 128 or 128 x 128
+//   tiles, operands moved global -> LDS by the DMA loads
+//   (global_load_lds_dwordx4), double-buffered; used whenever M and N are
+//   multiples of 128 (the forward layers and the activation gradients).
 // * bf16_gemm<TA, TB, EPI>: C = op(A) op(B) on v_mfma_f32_32x32x16_bf16.
 //   A 64 x 64 output tile per block of 4 waves (each wave one 32 x 32
 //   accumulator), K in steps of 64 staged through LDS with both operands
@@ -246,25 +247,35 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))
 }
 
 // C = A B^T-style GEMM with both operands k-contiguous (A[m*lda + k],
-// op(B)[k][n] = B[n*ldb + k]) on (64 MT) x 128 output tiles: 4 waves in a
-// 2 x 2 grid, each wave (32 MT) x 64 = MT x 2 accumulators of
-// v_mfma_f32_32x32x16_bf16 (MT = 4 halves the LDS bytes per MFMA of MT = 2
-// and is used when the larger tiles still fill the device).  The operands
-// reach LDS without passing through registers: each wave issues
-// global_load_lds_dwordx4 for 1 KB chunks of the next 32-deep K step while
-// the current step's MFMAs run (two LDS buffers, one barrier per step).  A
-// DMA chunk is 64 consecutive 16-byte LDS slots; slot s of a tile holds row
-// s / 4, 16-byte piece (s % 4) ^ sw(row) of that row's 32 k-values, the XOR
-// swizzle sw(row) = ((row >> 1) ^ (row >> 3)) & 1 | (row >> 1) & 2 keeping
-// every 16-lane group of a fragment read on distinct LDS banks.  Waits are
-// explicit (vmcnt for this wave's DMA, then a plain barrier): a fenced
-// barrier would also wait for the step being prefetched.  M must be a
-// multiple of 64 MT, N of 128, K / splits of 32, lda and ldb of 8; the
-// epilogues are those of bf16_gemm.
+// op(B)[k][n] = B[n*ldb + k]) on (64 MT) x (64 WN) output tiles: 2 WN waves
+// in a 2 x WN grid, each wave (32 MT) x 64 = MT x 2 accumulators of
+// v_mfma_f32_32x32x16_bf16.  Three shapes are launched: MT = 2, WN = 2
+// (128 x 128, 4 waves), MT = 4, WN = 2 (256 x 128: half the LDS bytes per
+// MFMA) and MT = 4, WN = 4 (256 x 256, 8 waves, one block per compute unit,
+// 64-deep K steps in 128 KB of LDS: a third less DMA into LDS per MFMA and
+// half the barriers).  The operands reach LDS without passing through
+// registers: each wave issues global_load_lds_dwordx4 for 1 KB chunks of the
+// next BK-deep K step while the current step's MFMAs run (two LDS buffers,
+// one barrier per step).  A DMA chunk is 64 consecutive 16-byte LDS slots;
+// slot s of a tile holds row s / PR, 16-byte piece (s % PR) ^ sw(row) of that
+// row's BK k-values (PR = BK / 8), the XOR swizzle keeping every 16-lane
+// group of a fragment read on distinct LDS banks: for PR = 4
+// sw(row) = ((row >> 1) ^ (row >> 3)) & 1 | (row >> 1) & 2, for PR = 8
+// sw(row) = (row ^ (row >> 3)) & 7.  Waits are explicit (vmcnt for this
+// wave's DMA, then a plain barrier): a fenced barrier would also wait for
+// the step being prefetched.  M must be a multiple of 64 MT, N of 64 WN,
+// K / splits of BK, lda and ldb of 8; the epilogues are those of bf16_gemm.
 constexpr int DL_BK = 32;      // K step
 constexpr int DL_PR = DL_BK / 8;  // 16-byte pieces per tile row and step
 
 __device__ __forceinline__ int dl_swizzle(int row) { return (((row >> 1) ^ (row >> 3)) & 1) | ((row >> 1) & 2); }
+
+template <int PR>
+__device__ __forceinline__ int dl_swz(int row) {
+  static_assert(PR == 4 || PR == 8, "16-byte pieces per row: 4 or 8");
+  if constexpr (PR == 4) return dl_swizzle(row);
+  else return (row ^ (row >> 3)) & 7;
+}
 
 // Epilogue of one 32 x 32 accumulator whose top-left output is (r0, c0):
 // element v is row r0 + (v/4)*8 + (lane/32)*4 + v%4, column c0 + lane%32.
@@ -311,16 +322,17 @@ __device__ __forceinline__ void gemm_store32(const GemmArgs& g, const f32x16_t& 
   }
 }
 
-template <int MT, int EPI>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) bf16_gemm_dl(GemmArgs g) {
-  constexpr int NT = 2;
-  constexpr int TM = 64 * MT, TN = 64 * NT;  // output tile
-  constexpr int SA = TM * DL_PR, SB = TN * DL_PR;  // 16-byte LDS slots per buffer and operand
-  constexpr int CA = SA / 256, CB = SB / 256;      // 64-slot DMA chunks per wave and step
+template <int MT, int WN, int BK, int EPI>
+__global__ void __launch_bounds__(128 * WN) __attribute__((amdgpu_waves_per_eu(2, 8))) bf16_gemm_dl(GemmArgs g) {
+  constexpr int NT = 2, NW = 2 * WN, PR = BK / 8;
+  constexpr int TM = 64 * MT, TN = 32 * NT * WN;   // output tile
+  constexpr int SA = TM * PR, SB = TN * PR;        // 16-byte LDS slots per buffer and operand
+  constexpr int CA = SA / (64 * NW), CB = SB / (64 * NW);  // 64-slot DMA chunks per wave and step
+  static_assert(CA * 64 * NW == SA && CB * 64 * NW == SB, "whole DMA chunks per wave");
   extern __shared__ uint4 lds[];                   // 2 buffers x (SA + SB) slots, sized at launch
   const int t = threadIdx.x, lane = t & 63;
   const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / WN, wn = wave % WN;
   const uint32_t nx = gridDim.x, tiles = gridDim.x * gridDim.y;
   uint32_t u = blockIdx.y * nx + blockIdx.x;
   if ((tiles & 7u) == 0) u = (u & 7u) * (tiles >> 3) + (u >> 3);  // XCD-aware order, as in bf16_gemm
@@ -328,20 +340,20 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
   const int64_t n0 = int64_t(u % nx) * TN;
   const int64_t kspan = g.K / g.splits;
   const int64_t kbeg = int64_t(blockIdx.z) * kspan;
-  const int nsteps = int(kspan / DL_BK);
+  const int nsteps = int(kspan / BK);
 
   // source of the 16 bytes this lane moves in each of its chunks
   const uint16_t* ga[CA];
   const uint16_t* gb[CB];
 #pragma unroll
   for (int c = 0; c < CA; ++c) {
-    const int s = (wave + 4 * c) * 64 + lane, row = s / DL_PR;
-    ga[c] = static_cast<const uint16_t*>(g.A) + (m0 + row) * g.lda + kbeg + ((s % DL_PR) ^ dl_swizzle(row)) * 8;
+    const int s = (wave + NW * c) * 64 + lane, row = s / PR;
+    ga[c] = static_cast<const uint16_t*>(g.A) + (m0 + row) * g.lda + kbeg + ((s % PR) ^ dl_swz<PR>(row)) * 8;
   }
 #pragma unroll
   for (int c = 0; c < CB; ++c) {
-    const int s = (wave + 4 * c) * 64 + lane, row = s / DL_PR;
-    gb[c] = static_cast<const uint16_t*>(g.B) + (n0 + row) * g.ldb + kbeg + ((s % DL_PR) ^ dl_swizzle(row)) * 8;
+    const int s = (wave + NW * c) * 64 + lane, row = s / PR;
+    gb[c] = static_cast<const uint16_t*>(g.B) + (n0 + row) * g.ldb + kbeg + ((s % PR) ^ dl_swz<PR>(row)) * 8;
   }
   // The builtin's operands are taken through plain pointers and the shared
   // array itself (operands of template-dependent type drop the kernel's host
@@ -350,31 +362,32 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
   do {                                                                                               \
     _Pragma("unroll") for (int c = 0; c < CA; ++c) {                                                 \
       const uint16_t* src_ = ga[c];                                                                  \
-      __builtin_amdgcn_global_load_lds(src_ + (koff), lds + (buf) * (SA + SB) + (wave + 4 * c) * 64, 16, 0, 0); \
+      __builtin_amdgcn_global_load_lds(src_ + (koff), lds + (buf) * (SA + SB) + (wave + NW * c) * 64, 16, 0, 0); \
     }                                                                                                \
     _Pragma("unroll") for (int c = 0; c < CB; ++c) {                                                 \
       const uint16_t* src_ = gb[c];                                                                  \
-      __builtin_amdgcn_global_load_lds(src_ + (koff), lds + (buf) * (SA + SB) + SA + (wave + 4 * c) * 64, 16, 0, 0); \
+      __builtin_amdgcn_global_load_lds(src_ + (koff), lds + (buf) * (SA + SB) + SA + (wave + NW * c) * 64, 16, 0, 0); \
     }                                                                                                \
   } while (0)
 
   // LDS slots of this lane's fragments: row i = lane % 32 of each 32-row
   // block, 8 k-values at piece 2 * slice + lane / 32
   const int i = lane & 31, kh = lane >> 5;
-  int oa[MT][2], ob[NT][2];
+  constexpr int NS = BK / 16;  // 16-deep MFMA slices per K step
+  int oa[MT][NS], ob[NT][NS];
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-    for (int sl = 0; sl < 2; ++sl) {
+    for (int sl = 0; sl < NS; ++sl) {
       const int row = wm * MT * 32 + mt * 32 + i;
-      oa[mt][sl] = row * DL_PR + ((sl * 2 + kh) ^ dl_swizzle(row));
+      oa[mt][sl] = row * PR + ((sl * 2 + kh) ^ dl_swz<PR>(row));
     }
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
-    for (int sl = 0; sl < 2; ++sl) {
+    for (int sl = 0; sl < NS; ++sl) {
       const int row = wn * NT * 32 + nt * 32 + i;
-      ob[nt][sl] = SA + row * DL_PR + ((sl * 2 + kh) ^ dl_swizzle(row));
+      ob[nt][sl] = SA + row * PR + ((sl * 2 + kh) ^ dl_swz<PR>(row));
     }
 
   f32x16_t acc[MT][NT];
@@ -391,18 +404,18 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
     // step kk - 1 are done (lgkmcnt(0)); the barrier makes both block-wide
     __builtin_amdgcn_s_waitcnt(0x0070);
     __builtin_amdgcn_s_barrier();
-    if (kk + 1 < nsteps) QSVM_DL_ISSUE((kk + 1) & 1, int64_t(kk + 1) * DL_BK);
+    if (kk + 1 < nsteps) QSVM_DL_ISSUE((kk + 1) & 1, int64_t(kk + 1) * BK);
     const uint4* base = lds + (kk & 1) * (SA + SB);
-    bf16x8_t fa[2][MT], fb[2][NT];
+    bf16x8_t fa[NS][MT], fb[NS][NT];
 #pragma unroll
-    for (int sl = 0; sl < 2; ++sl) {
+    for (int sl = 0; sl < NS; ++sl) {
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) fa[sl][mt] = *reinterpret_cast<const bf16x8_t*>(base + oa[mt][sl]);
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) fb[sl][nt] = *reinterpret_cast<const bf16x8_t*>(base + ob[nt][sl]);
     }
 #pragma unroll
-    for (int sl = 0; sl < 2; ++sl)
+    for (int sl = 0; sl < NS; ++sl)
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -1131,19 +1144,40 @@ __global__ void zero_int(int32_t* p) {
 
 template <int TA, int TB, int EPI>
 hipError_t launch_gemm_t(const GemmArgs& g, hipStream_t s) {
-  // both operands k-contiguous, whole 128 x 128 tiles, 16-byte rows and
-  // 32-deep steps: the direct-to-LDS kernel, on 256 x 128 tiles when there
-  // are at least 512 of them (two per compute unit), else 128 x 128
-  if (TA == 0 && TB == 1 && g.M % 128 == 0 && g.N % 128 == 0 && g.lda % 8 == 0 && g.ldb % 8 == 0 &&
-      g.K % g.splits == 0 && (g.K / g.splits) % DL_BK == 0) {
+  // both operands k-contiguous, 16-byte rows: the direct-to-LDS kernel, on
+  // 256 x 256 tiles with 64-deep K steps when they fill every compute unit
+  // (one 8-wave block each, 128 KB of LDS), else on 256 x 128 tiles when
+  // there are at least 512 of them (two per compute unit), else 128 x 128
+  const bool dl = TA == 0 && TB == 1 && g.M % 128 == 0 && g.N % 128 == 0 && g.lda % 8 == 0 && g.ldb % 8 == 0 &&
+                  g.K % g.splits == 0;
+  if (dl && g.M % 256 == 0 && g.N % 256 == 0 && (g.K / g.splits) % 64 == 0 &&
+      (g.M / 256) * (g.N / 256) * g.splits >= 256) {
+    constexpr int lds = 2 * (256 + 256) * 8 * 16;
+    // more than the default 64 KB of dynamic LDS: raised once per device
+    static std::atomic<uint64_t> lds_raised{0};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const uint64_t bit = dev < 64 ? uint64_t(1) << dev : 0;
+    if (!(lds_raised.load() & bit)) {
+      e = hipFuncSetAttribute(reinterpret_cast<const void*>(&bf16_gemm_dl<4, 4, 64, EPI>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+      if (e != hipSuccess) return e;
+      lds_raised.fetch_or(bit);
+    }
+    const dim3 grid(unsigned(g.N / 256), unsigned(g.M / 256), unsigned(g.splits));
+    hipLaunchKernelGGL((bf16_gemm_dl<4, 4, 64, EPI>), grid, dim3(512), lds, s, g);
+    return hipGetLastError();
+  }
+  if (dl && (g.K / g.splits) % DL_BK == 0) {
     if (g.M % 256 == 0 && (g.M / 256) * (g.N / 128) >= 512) {
       const dim3 grid(unsigned(g.N / 128), unsigned(g.M / 256), unsigned(g.splits));
       const size_t lds = 2 * (256 + 128) * DL_PR * 16;
-      hipLaunchKernelGGL((bf16_gemm_dl<4, EPI>), grid, dim3(256), lds, s, g);
+      hipLaunchKernelGGL((bf16_gemm_dl<4, 2, DL_BK, EPI>), grid, dim3(256), lds, s, g);
     } else {
       const dim3 grid(unsigned(g.N / 128), unsigned(g.M / 128), unsigned(g.splits));
       const size_t lds = 2 * (128 + 128) * DL_PR * 16;
-      hipLaunchKernelGGL((bf16_gemm_dl<2, EPI>), grid, dim3(256), lds, s, g);
+      hipLaunchKernelGGL((bf16_gemm_dl<2, 2, DL_BK, EPI>), grid, dim3(256), lds, s, g);
     }
     return hipGetLastError();
   }

@@ -174,7 +174,7 @@ def test_mlp_forward_matches_reference():
 PROD = (832, 512, 512, 256)  # 784 pixels padded to 832 -> 512 -> 512 -> 256
 
 
-@pytest.mark.parametrize("rows,dims", [(16384, PROD), (128, DIMS)])
+@pytest.mark.parametrize("rows,dims", [(32768, PROD), (16384, PROD), (128, DIMS)])
 def test_mlp_forward_inference_mode_writes_the_same_bf16_outputs(rows, dims):
     """H1, H2 and E omitted (inference): the BF16 activations and embedding are
     bitwise those of the forward pass that keeps the FP32 values."""
@@ -209,6 +209,20 @@ def test_mlp_forward_backward_production_shape_elementwise():
     dEk = ref.bf16_round(rng.normal(0, 1e-3, (rows, PROD[3])))
     grads, dH1, dH2 = _backward(net, bufs, acts, dev, _bf16_dev(dEk), rows, PROD)
     _check_backward(W, X, (H1, A1, H2, A2), dEk, grads, dH1, dH2)
+
+
+def test_mlp_forward_256x256_tiles_elementwise():
+    """At 32768 rows layers 1 and 2 (512 outputs wide) fill every compute unit
+    with 256 x 256 tiles: one 8-wave block each, 64-deep K steps (13 in layer
+    1, K = 832), 128 KB of LDS.  Every element of every layer's output
+    against the FP64 reference on the kernel's own layer inputs."""
+    import torch
+
+    rows = 32768
+    W, X, dev, net, bufs, acts = _setup(21, rows=rows, dims=PROD)
+    qsvm.qsvm_mlp_forward(net, bufs["X16"], rows, acts)
+    torch.cuda.synchronize()
+    _check_forward(W, X, bufs)
 
 
 @pytest.mark.parametrize("kind", [qsvm.LOSS_MSE, qsvm.LOSS_BCE], ids=["mse", "bce"])
