@@ -251,10 +251,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))
 // op(B)[k][n] = B[n*ldb + k]) on (64 MT) x (64 WN) output tiles: 2 WN waves
 // in a 2 x WN grid, each wave (32 MT) x 64 = MT x 2 accumulators of
 // v_mfma_f32_32x32x16_bf16.  Three shapes are launched: MT = 2, WN = 2
-// (128 x 128, 4 waves), MT = 4, WN = 2 (256 x 128: half the LDS bytes per
-// MFMA) and MT = 4, WN = 4 (256 x 256, 8 waves, one block per compute unit,
-// 64-deep K steps in 128 KB of LDS: a third less DMA into LDS per MFMA and
-// half the barriers).  The operands reach LDS without passing through
+// (128 x 128, 4 waves; 64-deep K steps in 64 KB of LDS when the grid puts at
+// most two blocks on a compute unit), MT = 4, WN = 2 (256 x 128: half the
+// LDS bytes per MFMA) and MT = 4, WN = 4 (256 x 256, 8 waves, one block per
+// compute unit, 64-deep K steps in 128 KB of LDS: a third less DMA into LDS
+// per MFMA and half the barriers).  The operands reach LDS without passing through
 // registers: each wave issues global_load_lds_dwordx4 for 1 KB chunks of the
 // next BK-deep K step while the current step's MFMAs run (two LDS buffers,
 // one barrier per step).  A DMA chunk is 64 consecutive 16-byte LDS slots;
@@ -1148,7 +1149,8 @@ hipError_t launch_gemm_t(const GemmArgs& g, hipStream_t s) {
   // both operands k-contiguous, 16-byte rows: the direct-to-LDS kernel, on
   // 256 x 256 tiles with 64-deep K steps when they fill every compute unit
   // (one 8-wave block each, 128 KB of LDS), else on 256 x 128 tiles when
-  // there are at least 512 of them (two per compute unit), else 128 x 128
+  // there are at least 512 of them (two per compute unit), else 128 x 128,
+  // with 64-deep steps when at most two blocks share a compute unit
   const bool dl = TA == 0 && TB == 1 && g.M % 128 == 0 && g.N % 128 == 0 && g.lda % 8 == 0 && g.ldb % 8 == 0 &&
                   g.K % g.splits == 0;
   if (dl && g.M % 256 == 0 && g.N % 256 == 0 && (g.K / g.splits) % 64 == 0 &&
@@ -1175,6 +1177,11 @@ hipError_t launch_gemm_t(const GemmArgs& g, hipStream_t s) {
       const dim3 grid(unsigned(g.N / 128), unsigned(g.M / 256), unsigned(g.splits));
       const size_t lds = 2 * (256 + 128) * DL_PR * 16;
       hipLaunchKernelGGL((bf16_gemm_dl<4, 2, DL_BK, EPI>), grid, dim3(256), lds, s, g);
+    } else if ((g.K / g.splits) % 64 == 0 && (g.M / 128) * (g.N / 128) * g.splits <= 512) {
+      // at most two blocks per compute unit: 64-deep steps in 64 KB of LDS
+      const dim3 grid(unsigned(g.N / 128), unsigned(g.M / 128), unsigned(g.splits));
+      const size_t lds = 2 * (128 + 128) * 8 * 16;
+      hipLaunchKernelGGL((bf16_gemm_dl<2, 2, 64, EPI>), grid, dim3(256), lds, s, g);
     } else {
       const dim3 grid(unsigned(g.N / 128), unsigned(g.M / 128), unsigned(g.splits));
       const size_t lds = 2 * (128 + 128) * DL_PR * 16;
