@@ -100,10 +100,14 @@ def _setup(seed=0, rows=128, dims=DIMS):
     return W, X, dev, net, bufs, acts
 
 
-def _check_forward(W, X, bufs):
+def _check_forward(W, X, bufs, idx=None):
     """Each layer against the FP64 reference evaluated on the kernel's own
-    inputs to that layer (so rounding differences do not compound)."""
+    inputs to that layer (so rounding differences do not compound); on the
+    rows `idx` only when given (every row's check stands on its own)."""
     H1, A1, H2, A2, E = (_host(bufs[k]) for k in ("H1", "A1", "H2", "A2", "E"))
+    E16 = _host(bufs["E16"])
+    if idx is not None:
+        X, H1, A1, H2, A2, E, E16 = (a[idx] for a in (X, H1, A1, H2, A2, E, E16))
     _assert_elementwise(H1, X @ W[0] + W[1], _gemm_bar(np.abs(X), np.abs(W[0])) + 1e-7 * np.abs(W[1]), "H1")
     g1 = ref.gelu(H1)
     _assert_elementwise(A1, ref.bf16_round(g1), 2 * U16 * np.abs(g1) + 1e-6 * (1 + np.abs(H1)), "A1")
@@ -111,7 +115,7 @@ def _check_forward(W, X, bufs):
     g2 = ref.gelu(H2)
     _assert_elementwise(A2, ref.bf16_round(g2), 2 * U16 * np.abs(g2) + 1e-6 * (1 + np.abs(H2)), "A2")
     _assert_elementwise(E, A2 @ W[4] + W[5], _gemm_bar(np.abs(A2), np.abs(W[4])) + 1e-7 * np.abs(W[5]), "E")
-    assert np.array_equal(_host(bufs["E16"]), ref.bf16_round(E))
+    assert np.array_equal(E16, ref.bf16_round(E))
     return H1, A1, H2, A2, E
 
 
@@ -223,6 +227,22 @@ def test_mlp_forward_256x256_tiles_elementwise():
     qsvm.qsvm_mlp_forward(net, bufs["X16"], rows, acts)
     torch.cuda.synchronize()
     _check_forward(W, X, bufs)
+
+
+def test_mlp_forward_256x128_tiles_on_rows_sampled_from_every_tile():
+    """Hidden widths of 384 (a multiple of 128, not of 256) on 44032 rows:
+    layers 1 and 2 take 256 x 128 tiles of 4 waves (172 x 3 = 516 tiles, at
+    least two per compute unit) and layer 3 128 x 128 tiles with 32-deep
+    steps (688 blocks).  Every third row plus the last 256 against the FP64
+    reference on the kernel's own layer inputs."""
+    import torch
+
+    rows, dims = 44032, (832, 384, 384, 256)
+    W, X, dev, net, bufs, acts = _setup(23, rows=rows, dims=dims)
+    qsvm.qsvm_mlp_forward(net, bufs["X16"], rows, acts)
+    torch.cuda.synchronize()
+    idx = np.union1d(np.arange(0, rows, 3), np.arange(rows - 256, rows))
+    _check_forward(W, X, bufs, idx)
 
 
 @pytest.mark.parametrize("kind", [qsvm.LOSS_MSE, qsvm.LOSS_BCE], ids=["mse", "bce"])
