@@ -525,7 +525,12 @@ qsvm_status qsvm_gather_features(const double* X, int64_t N, int32_t n_qubits, c
  * weights are first copied transposed into a stream-ordered temporary
  * (hipMallocAsync / hipFreeAsync on `stream`, 2 (d_in d_h1 + d_h1 d_h2 +
  * d_h2 d_out) bytes) that the GEMMs read k-contiguously; the result does not
- * depend on it. */
+ * depend on it.  A layer with at least 256 output tiles of 256 x 256 runs on
+ * a kernel that takes 128 KB of LDS per block: the first such launch on a
+ * device raises that kernel's dynamic LDS limit (hipFuncSetAttribute, a
+ * host call made once per device and epilogue), so under stream capture
+ * make one uncaptured call of the same shape first; a failure of that call
+ * is returned as QSVM_ERR_HIP. */
 qsvm_status qsvm_mlp_forward(const qsvm_mlp* net, const void* X16, int64_t rows, const qsvm_mlp_acts* acts,
                              void* stream);
 
